@@ -1,0 +1,407 @@
+"""Pins of the CPU oracle against facts fixed by the paper or by mathematics.
+
+Each test checks the oracle against something other than itself: a
+hand-derived example, a textbook graph algorithm from scipy, a closed form,
+brute force over possible worlds, or an independent fixpoint algorithm.
+"""
+import heapq
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.sparse import csr_matrix
+from scipy.sparse.csgraph import dijkstra, shortest_path
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def run(oracle, program, semiring, facts, k=3, batched=False):
+    o = oracle.Oracle(program, semiring, k=k, batched=batched)
+    for rel, args in facts.items():
+        o.add_facts(rel, *args)
+    return o.run()
+
+
+def tc(oracle, synth, src, dst, p, semiring, k=3):
+    return run(oracle, synth.TC_PROGRAM, semiring, {"edge": ([src, dst], p)}, k=k)
+
+
+def as_dict(r):
+    return {(int(a), int(b)): i for i, (a, b) in enumerate(r["cols"])}
+
+
+# --------------------------------------------------------------- golden file
+def load_golden():
+    rows, edges, rounds = [], None, {}
+    with open(os.path.join(GOLDEN, "tiny_tc.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            if line.startswith("edges"):
+                edges = [tuple(e.split(":")) for e in line.split()[1:]]
+            elif line.startswith("rounds"):
+                rounds = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in line.split()[1:]}
+            else:
+                rows.append(line.split())
+    src = np.array([int(e[0]) for e in edges], np.uint32)
+    dst = np.array([int(e[1]) for e in edges], np.uint32)
+    p = np.array([float(e[2]) for e in edges], np.float32)
+    return src, dst, p, rows, rounds
+
+
+def test_golden_tiny_tc(oracle, synth):
+    src, dst, p, rows, rounds = load_golden()
+    col = {"bool": 2, "maxmin": 3, "minplus": 4, "addmult": 5}
+    for sr, c in col.items():
+        o = tc(oracle, synth, src, dst, p, sr)
+        r = o.read("path")
+        got = as_dict(r)
+        assert sorted(got) == sorted((int(x[0]), int(x[1])) for x in rows), sr
+        for x in rows:
+            i = got[(int(x[0]), int(x[1]))]
+            assert r["value"][i] == pytest.approx(float(x[c]), rel=1e-6), (sr, x)
+        assert o.rounds() == rounds[sr], sr
+    o = tc(oracle, synth, src, dst, p, "topk")
+    r = o.read("path")
+    got = as_dict(r)
+    for x in rows:
+        i = got[(int(x[0]), int(x[1]))]
+        want = [int(h, 16) for h in x[6].split("|")]
+        assert r["cnt"][i] == len(want)
+        assert list(r["bits"][i][: len(want)]) == want, x
+        assert r["prob"][i] == pytest.approx(float(x[7]), rel=1e-6), x
+    assert o.rounds() == rounds["topk"]
+
+
+# ------------------------------------------------------------ graph closures
+def hop_matrix(n, src, dst):
+    A = csr_matrix((np.ones(src.size), (src, dst)), shape=(n, n))
+    d = shortest_path(A, unweighted=True)  # d[z, z] = 0
+    # shortest walk with at least one edge: first edge, then any walk
+    d1 = np.full((n, n), np.inf)
+    for e in range(src.size):
+        d1[src[e]] = np.minimum(d1[src[e]], 1 + d[dst[e]])
+    return d1
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_bool_closure_and_rounds_vs_bfs(oracle, synth, seed):
+    """Bool TC set = BFS closure with >= 1 edge; discovery round = hop distance."""
+    n = 256
+    src, dst, _ = synth.er_graph(seed, n, 1024)
+    r = tc(oracle, synth, src, dst, None, "bool")
+    res = r.read("path")
+    d1 = hop_matrix(n, src, dst)
+    want = np.argwhere(np.isfinite(d1))
+    assert np.array_equal(res["cols"], want.astype(np.uint32))
+    assert np.array_equal(res["round"], d1[want[:, 0], want[:, 1]].astype(np.int32))
+    assert r.rounds() == int(d1[np.isfinite(d1)].max()) + 1
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_maxmin_vs_widest_path(oracle, synth, seed):
+    n = 256
+    src, dst, p = synth.er_graph(seed, n, 1024, weights=True)
+    W = np.zeros((n, n))
+    W[src, dst] = p.astype(np.float64)
+    for k in range(n):  # Floyd-Warshall for the bottleneck (>= 1 edge) closure
+        W = np.maximum(W, np.minimum(W[:, k : k + 1], W[k : k + 1, :]))
+    res = tc(oracle, synth, src, dst, p, "maxmin").read("path")
+    want = np.argwhere(W > 0)
+    assert np.array_equal(res["cols"], want.astype(np.uint32))
+    assert np.array_equal(res["value"], W[want[:, 0], want[:, 1]])
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_minplus_vs_dijkstra(oracle, synth, seed):
+    n = 256
+    src, dst, p = synth.er_graph(seed, n, 1024, weights=True)
+    A = csr_matrix((p.astype(np.float64), (src, dst)), shape=(n, n))
+    d = dijkstra(A)
+    d1 = np.full((n, n), np.inf)
+    for e in range(src.size):
+        d1[src[e]] = np.minimum(d1[src[e]], float(p[e]) + d[dst[e]])
+    res = tc(oracle, synth, src, dst, p, "minplus").read("path")
+    want = np.argwhere(np.isfinite(d1))
+    assert np.array_equal(res["cols"], want.astype(np.uint32))
+    np.testing.assert_allclose(res["value"], d1[want[:, 0], want[:, 1]], rtol=1e-12)
+
+
+def grid_closed_form(k, src, dst, p):
+    """Frozen add-mult TC on a bidirectional grid, by Manhattan distance:
+    f_t(x) = min(1, sum over neighbours y one step closer to t of
+    p(x, y) f_t(y)), with f_t(t) := 1 as the base of the recursion, and
+    path(t, t) = min(1, sum_y p(t, y) p(y, t))."""
+    w = {(int(a), int(b)): float(q) for a, b, q in zip(src, dst, p)}
+    nb = {}
+    for a, b in w:
+        nb.setdefault(a, []).append(b)
+    n = k * k
+    dist = lambda a, b: abs(a // k - b // k) + abs(a % k - b % k)
+    out = {}
+    for t in range(n):
+        f = {t: 1.0}
+        for x in sorted(range(n), key=lambda x: dist(x, t)):
+            if x == t:
+                continue
+            s = sum(w[(x, y)] * f[y] for y in nb[x] if dist(y, t) == dist(x, t) - 1)
+            f[x] = min(1.0, s)
+            out[(x, t)] = f[x]
+        out[(t, t)] = min(1.0, sum(w[(t, y)] * w[(y, t)] for y in nb[t]))
+    return out
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_addmult_grid_closed_form(oracle, synth, k):
+    rng = np.random.default_rng(k)
+    src, dst = synth.grid_edges(k)
+    p = synth.unit_prob(rng, src.size)
+    res = tc(oracle, synth, src, dst, p, "addmult").read("path")
+    want = grid_closed_form(k, src, dst, p)
+    got = {(int(a), int(b)): v for (a, b), v in zip(res["cols"], res["value"])}
+    assert sorted(got) == sorted(want)
+    for key, v in want.items():
+        assert got[key] == pytest.approx(v, rel=1e-12), key
+
+
+def test_addmult_out_tree_products(oracle, synth):
+    """On an out-tree every pair has one walk: the tag is its edge product."""
+    rng = np.random.default_rng(7)
+    n = 60
+    parent = np.array([rng.integers(0, i) for i in range(1, n)], np.uint32)
+    child = np.arange(1, n, dtype=np.uint32)
+    p = synth.unit_prob(rng, n - 1)
+    res = tc(oracle, synth, parent, child, p, "addmult").read("path")
+    pw = {int(c): float(q) for c, q in zip(child, p)}
+    par = {int(c): int(a) for a, c in zip(parent, child)}
+    want = {}
+    for z in range(1, n):
+        prod, y = 1.0, z
+        while y != 0:
+            prod *= pw[y]
+            y = par[y]
+            want[(y, z)] = prod
+    got = {(int(a), int(b)): v for (a, b), v in zip(res["cols"], res["value"])}
+    assert sorted(got) == sorted(want)
+    for key, v in want.items():
+        assert got[key] == pytest.approx(v, rel=1e-12)
+
+
+@pytest.mark.parametrize("sr", ["bool", "maxmin", "minplus", "addmult"])
+def test_column_solver_matches_generic(oracle, synth, sr):
+    n = 256
+    src, dst, p = synth.er_graph(1, n, 1024, weights=True)
+    o = tc(oracle, synth, src, dst, p, sr)
+    res = o.read("path")
+    rounds = 0
+    for z in range(0, n, 17):
+        c = oracle.tc_column(n, src, dst, p, sr, z)
+        m = res["cols"][:, 1] == z
+        xs = res["cols"][m, 0]
+        assert np.array_equal(np.nonzero(c["present"])[0], xs)
+        assert np.array_equal(c["tag"][xs], res["value"][m])  # same +-order: identical
+        assert np.array_equal(c["found"][xs], res["round"][m])
+        rounds = max(rounds, c["rounds"])
+    assert rounds <= o.rounds()
+
+
+def test_tuple_set_is_semiring_independent(oracle, synth):
+    src, dst, p = synth.er_graph(3, 200, 700, weights=True)
+    ref = tc(oracle, synth, src, dst, p, "bool").read("path")["cols"]
+    for sr in ["maxmin", "minplus", "addmult"]:
+        assert np.array_equal(tc(oracle, synth, src, dst, p, sr).read("path")["cols"], ref), sr
+    src, dst, p = synth.er_graph(3, 30, 64, weights=True)  # top-k: <= 64 facts
+    ref = tc(oracle, synth, src, dst, p, "bool").read("path")["cols"]
+    assert np.array_equal(tc(oracle, synth, src, dst, p, "topk").read("path")["cols"], ref)
+
+
+# ------------------------------------------------------------------- top-k
+def brute_force_reach(n, src, dst, p):
+    """Exact P(z reachable from x by >= 1 edge) over all 2^m edge worlds."""
+    m = src.size
+    P = np.zeros((n, n))
+    for world in range(1 << m):
+        on = [(world >> e) & 1 for e in range(m)]
+        pr = 1.0
+        A = np.zeros((n, n), bool)
+        for e in range(m):
+            pr *= float(p[e]) if on[e] else 1.0 - float(p[e])
+            if on[e]:
+                A[src[e], dst[e]] = True
+        R = A.copy()
+        for _ in range(n):
+            R2 = R | ((R.astype(np.int32) @ A.astype(np.int32)) > 0)
+            if (R2 == R).all():
+                break
+            R = R2
+        P += pr * R
+    return P
+
+
+def random_dag(rng, n, m):
+    pairs = [(a, b) for a in range(n) for b in range(a + 1, n)]
+    idx = rng.choice(len(pairs), size=m, replace=False)
+    src = np.array([pairs[i][0] for i in idx], np.uint32)
+    dst = np.array([pairs[i][1] for i in idx], np.uint32)
+    return src, dst
+
+
+def count_paths(n, src, dst):
+    C = np.zeros((n, n), np.int64)
+    for a, b in zip(src, dst):
+        C[a, b] += 1
+    total = C.copy()
+    step = C.copy()
+    for _ in range(n):
+        step = step @ C
+        total += step
+    return total
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13, 14])
+def test_topk_vs_possible_worlds(oracle, synth, seed):
+    rng = np.random.default_rng(seed)
+    n, m = 7, 11
+    src, dst = random_dag(rng, n, m)
+    p = synth.unit_prob(rng, m)
+    res = tc(oracle, synth, src, dst, p, "topk").read("path")
+    exact = brute_force_reach(n, src, dst, p)
+    npaths = count_paths(n, src, dst)
+    for (x, z), cnt, bits, prob in zip(res["cols"], res["cnt"], res["bits"], res["prob"]):
+        for b in bits[:cnt]:  # (i) every kept proof derives the tuple on its own
+            keep = np.array([(int(b) >> e) & 1 for e in range(m)], bool)
+            sub = brute_force_reach(n, src[keep], dst[keep], np.ones(keep.sum()))
+            assert sub[x, z] == 1.0
+        if npaths[x, z] <= 3:  # (iii) all proofs kept: exact probability
+            assert cnt == npaths[x, z]
+            assert prob == pytest.approx(exact[x, z], rel=1e-9)
+        assert prob <= exact[x, z] + 1e-12  # (iv) a lower bound in general
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_top1_is_max_product_path(oracle, synth, seed):
+    """Top-1 proof of path(x, z) = edge set of the most likely path (Dijkstra
+    on -log p); its canonical probability is that path's product."""
+    rng = np.random.default_rng(seed)
+    n = 24
+    src, dst, p = synth.er_graph(seed, n, 60, weights=True)
+    res = tc(oracle, synth, src, dst, p, "topk", k=1).read("path")
+    eid = {(int(a), int(b)): e for e, (a, b) in enumerate(zip(src, dst))}
+    adj = {}
+    for e, (a, b) in enumerate(zip(src, dst)):
+        adj.setdefault(int(a), []).append((int(b), -math.log(float(p[e]))))
+    for (x, z), bits, pr in zip(res["cols"], res["bits"], res["p"]):
+        # Dijkstra from x over >= 1 edge; track predecessor edges
+        best = {}
+        heap = [(c, y, (eid[(int(x), y)],)) for y, c in adj.get(int(x), [])]
+        heapq.heapify(heap)
+        while heap:
+            c, y, path = heapq.heappop(heap)
+            if y in best:
+                continue
+            best[y] = (c, path)
+            for w2, c2 in adj.get(y, []):
+                if w2 not in best:
+                    heapq.heappush(heap, (c + c2, w2, path + (eid[(y, w2)],)))
+        c, path = best[int(z)]
+        assert pr[0] == pytest.approx(math.exp(-c), rel=1e-5)
+        want = sum(1 << e for e in set(path))
+        assert int(bits[0]) == want, (x, z)
+
+
+def test_topk_gradient_vs_finite_differences(oracle, synth):
+    rng = np.random.default_rng(5)
+    n, m = 7, 11
+    src, dst = random_dag(rng, n, m)
+    p = synth.unit_prob(rng, m).astype(np.float64)
+
+    def forward(q):
+        r = tc(oracle, synth, src, dst, q.astype(np.float32), "diff_topk")
+        return r, r.read("path")
+
+    r, res = forward(p)
+    g_out = synth.normal_grads(9, res["cols"].shape[0]).astype(np.float64)
+    r.backward("path", g_out)
+    g = r.grad("edge", m)
+    h = 1e-3
+    for e in range(m):
+        qp, qm = p.copy(), p.copy()
+        qp[e] += h
+        qm[e] -= h
+        _, rp = forward(qp)
+        _, rm = forward(qm)
+        if not (np.array_equal(rp["bits"], res["bits"]) and np.array_equal(rm["bits"], res["bits"])):
+            continue  # a ranking tie moved: the closed form holds selection fixed
+        dq = float(np.float32(qp[e])) - float(np.float32(qm[e]))
+        fd = float(g_out @ (rp["prob"] - rm["prob"])) / dq
+        assert g[e] == pytest.approx(fd, rel=1e-3, abs=1e-6), e
+
+
+# ------------------------------------------------------- diff add-mult grads
+def test_diff_addmult_gradient_vs_finite_differences(oracle, synth):
+    rng = np.random.default_rng(3)
+    src, dst, p = synth.er_graph(4, 20, 45, weights=True)
+    p = (p * 0.5).astype(np.float32)  # keep sums below the clamp
+    r = tc(oracle, synth, src, dst, p, "diff_addmult")
+    res = r.read("path")
+    g_out = rng.standard_normal(res["cols"].shape[0])
+    r.backward("path", g_out)
+    g = r.grad("edge", src.size)
+    for e in range(src.size):
+        h = 1e-3
+        qp, qm = p.copy(), p.copy()
+        qp[e] += np.float32(h)
+        qm[e] -= np.float32(h)
+        vp = tc(oracle, synth, src, dst, qp, "diff_addmult").read("path")["value"]
+        vm = tc(oracle, synth, src, dst, qm, "diff_addmult").read("path")["value"]
+        if (vp >= 1).any() or (vm >= 1).any() or (res["value"] >= 1).any():
+            pytest.skip("clamp reached")
+        fd = float(g_out @ (vp - vm)) / (float(qp[e]) - float(qm[e]))
+        assert g[e] == pytest.approx(fd, rel=1e-3, abs=1e-8), e
+
+
+def test_column_gradient_matches_generic(oracle, synth):
+    k = 6
+    rng = np.random.default_rng(8)
+    src, dst = synth.grid_edges(k)
+    p = synth.unit_prob(rng, src.size)
+    r = tc(oracle, synth, src, dst, p, "diff_addmult")
+    res = r.read("path")
+    z = k * k - 1
+    g_out = np.zeros(res["cols"].shape[0])
+    g_out[(res["cols"][:, 0] == 0) & (res["cols"][:, 1] == z)] = 1.0
+    r.backward("path", g_out)
+    g_generic = r.grad("edge", src.size)
+    gc = np.zeros(k * k)
+    gc[0] = 1.0
+    col = oracle.tc_column(k * k, src, dst, p, "diff_addmult", z, grad_col=gc)
+    np.testing.assert_allclose(col["grad_edge"], g_generic, rtol=1e-12, atol=1e-15)
+
+
+# --------------------------------------------------------------- points-to
+def test_andersen_worklist_matches_naive(oracle, synth):
+    rels = synth.andersen(1, v=600, n_addr=300, n_assign=1800, n_load=240, n_store=240)
+    v, o = oracle.andersen(600, rels)
+    r = run(oracle, synth.ANDERSEN_PROGRAM, "bool",
+            {name: ([a, b], None) for name, (a, b) in rels.items()})
+    res = r.read("pt")
+    assert np.array_equal(res["cols"][:, 0], v)
+    assert np.array_equal(res["cols"][:, 1], o)
+    assert v.size > 1000
+
+
+# ---------------------------------------------------------------- batching
+def test_batched_equals_separate_runs(oracle, synth):
+    g = synth.grid_batch(4, samples=5, kmin=2, kmax=4)
+    r = run(oracle, synth.TC_PROGRAM, "addmult",
+            {"edge": ([g["src"], g["dst"]], g["p"], g["sample"])}, batched=True)
+    res = r.read("path")
+    for s in range(5):
+        m = g["sample"] == s
+        one = tc(oracle, synth, g["src"][m], g["dst"][m], g["p"][m], "addmult").read("path")
+        sel = res["sample"] == s
+        assert np.array_equal(res["cols"][sel], one["cols"])
+        assert np.array_equal(res["value"][sel], one["value"])
