@@ -1,0 +1,168 @@
+/* dlfix -- semiring Datalog fixpoint engine for AMD MI355X (gfx950).
+ *
+ * C ABI of the shared library libdlfix.so.  Every call returns a dl_status
+ * (DL_OK = 0); no C++ exception crosses this boundary.  The text of the last
+ * error of an engine is available from dl_last_error().
+ *
+ * The library evaluates positive Datalog programs bottom-up to their least
+ * fixpoint, semi-naively (Sec. 3.4: rules fire only on the facts that changed
+ * in the previous iteration; Appendix A: the stable / recent / delta split of
+ * the database and of every join).  Relations are columnar: an arity-n
+ * relation is n integer columns plus one tag column (Sec. 3.3), held in HBM
+ * as a sorted array of packed integer keys plus a tag array.  Every fact
+ * carries a provenance tag from a semiring (T, 0, 1, +, x) (Sec. 3.1,
+ * Sec. 3.5); a derived fact's tag is the +-sum over its derivations of the
+ * x-product of the body tags.
+ *
+ * Threading: one engine per host thread; calls on one engine must not
+ * overlap.  All device work of an engine runs on the stream given in
+ * dl_options (or on a stream the engine creates).
+ */
+#ifndef DLFIX_H
+#define DLFIX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dl_engine dl_engine; /* opaque; created by dl_load_program, freed by dl_free */
+
+typedef enum {
+  DL_OK = 0,
+  DL_ERR_ARG = 1,             /* bad argument (NULL pointer, unknown relation, size mismatch) */
+  DL_ERR_PARSE = 2,           /* program text does not parse */
+  DL_ERR_UNSUPPORTED = 3,     /* construct outside the supported fragment (see dl_load_program) */
+  DL_ERR_STATE = 4,           /* call out of order (e.g. read before run) */
+  DL_ERR_NOMEM = 5,           /* device allocation failed; engine and facts stay valid */
+  DL_ERR_CAPACITY = 6,        /* a size exceeds an index width (e.g. > 2^32 join outputs in one round) */
+  DL_ERR_PROOF_OVERFLOW = 7,  /* top-k: more than 64 probabilistic facts in one sample */
+  DL_ERR_HIP = 8              /* a HIP runtime call failed */
+} dl_status;
+
+/* Provenance semirings (Sec. 3.1, Sec. 3.5).  Tags are binary32.
+ *  BOOL          {false, true}, +: or, x: and.  No tag is stored.
+ *  MAXMIN        [0,1], +: max, x: min.
+ *  MINPLUS       [0, inf], +: min, x: + (tropical; weights as tags).
+ *  ADDMULT       [0,1], +: min(1, a+b), x: a*b.
+ *  DIFF_ADDMULT  ADDMULT with reverse-mode gradients (dl_backward).
+ *  TOPK          up to k <= 3 proofs per fact; a proof is a set of input facts
+ *                (bitset over the <= 64 probabilistic facts of its sample),
+ *                its probability the binary32 product of those facts'
+ *                probabilities in ascending fact order.  x: pairwise unions,
+ *                + : union of the lists; both keep the k most likely distinct
+ *                proofs (ties: smaller bitset first).
+ *  DIFF_TOPK     TOPK with the gradient of the inclusion-exclusion
+ *                probability of the kept proofs.
+ * BOOL, MAXMIN, MINPLUS and the TOPK forms have an idempotent + and are
+ * iterated until no tag changes; the ADDMULT forms fix a fact's tag in the
+ * iteration that first derives it (later derivations do not change it). */
+typedef enum {
+  DL_BOOL = 0,
+  DL_MAXMIN = 1,
+  DL_MINPLUS = 2,
+  DL_ADDMULT = 3,
+  DL_DIFF_ADDMULT = 4,
+  DL_TOPK = 5,
+  DL_DIFF_TOPK = 6
+} dl_semiring;
+
+typedef struct {
+  int semiring;       /* dl_semiring */
+  int k;              /* top-k proof count, 1..3 (ignored otherwise; 0 = 3) */
+  int batched;        /* 1: every fact carries a sample id; samples never join each other (Sec. 4.3) */
+  void* stream;       /* hipStream_t to run on; NULL: the engine creates its own stream */
+} dl_options;
+
+/* Result columns of dl_read_relation.  Any pointer may be NULL (not written).
+ * Rows come in canonical lexicographic order (sample, col0, col1, ...). */
+typedef struct {
+  uint32_t* sample_ids;   /* [n] (batched engines) */
+  uint32_t* columns[4];   /* columns[c][n] for c < arity */
+  float* tags;            /* [n]: the tag (f32 semirings), 1.0 (BOOL), or the
+                             inclusion-exclusion probability of the kept proofs (TOPK) */
+  uint8_t* topk_count;    /* [n]   number of kept proofs (TOPK) */
+  uint64_t* topk_bits;    /* [k*n] proof j of row i at [j*n + i]; bit f = fact f of the row's sample */
+  float* topk_prob;       /* [k*n] binary32 proof probabilities, same layout */
+} dl_relation_out;
+
+typedef struct {
+  int strata;             /* strata evaluated in the last run */
+  int rounds;             /* iterations over all strata (each stratum counts its final, empty one) */
+  int max_rounds;         /* largest iteration count of a single stratum */
+  uint64_t candidates;    /* join outputs (derivations) produced, all rounds */
+  uint64_t unique;        /* distinct candidate keys after the per-round +-reduction */
+  uint64_t derived;       /* tuples in derived relations at the fixpoint */
+  uint64_t lineage;       /* derivations recorded for the backward pass (DIFF_ADDMULT) */
+  double run_ms;          /* host wall time of the last dl_run_fixpoint */
+  uint64_t device_bytes;  /* device memory currently held by the engine */
+  uint32_t key_bits;      /* width of the packed keys (32 or 64) */
+  uint32_t id_bits;       /* bits per column value */
+  uint32_t sample_bits;   /* bits of the sample id */
+} dl_stats;
+
+/* Parse and plan a program.
+ * Text: one statement per '.'-terminated clause; '#' or '//' start comments.
+ *   .input name/arity           declares an input (extensional) relation
+ *   .output name/arity          optional; any derived relation can be read
+ *   head(x, y) :- a(x, z), b(z, y).
+ * Supported fragment: positive rules; 1 to 3 body atoms; arity 1..4;
+ * variables only (no constants), pairwise distinct inside an atom; every
+ * head variable occurs in the body; every body atom after the first shares a
+ * variable with the atoms before it.  Strata are the strongly connected
+ * components of the predicate graph, evaluated in dependency order
+ * (Algorithm 1).  Under the ADDMULT forms a rule may contain at most one atom
+ * of its own stratum, and DIFF_ADDMULT rules have at most 2 body atoms.
+ * Anything else returns DL_ERR_UNSUPPORTED.  On success *out owns a new
+ * engine (free with dl_free). */
+dl_status dl_load_program(const char* program_text, const dl_options* opts, dl_engine** out);
+
+/* Drop all facts and results, keep the program. */
+dl_status dl_clear_facts(dl_engine* e);
+
+/* Append n facts to input relation `relation`.
+ * columns: `arity` pointers to n uint32 values each (SoA).
+ * sample_ids: n values (batched engines; ignored otherwise, may be NULL).
+ * tags: n binary32 values (probability / weight); NULL allowed for BOOL.
+ * on_device: 1 if every pointer is device memory, 0 if host memory.  The data
+ * is copied before the call returns.  Duplicate facts are +-merged. */
+dl_status dl_add_facts(dl_engine* e, const char* relation, size_t n,
+                       const uint32_t* sample_ids, const uint32_t* const* columns,
+                       const float* tags, int on_device);
+
+/* Evaluate every stratum to its fixpoint.  Blocks until the result is on the
+ * device (one small device-to-host read per join step and per iteration). */
+dl_status dl_run_fixpoint(dl_engine* e);
+
+/* Number of tuples of a relation (after dl_run_fixpoint for derived ones). */
+dl_status dl_relation_size(dl_engine* e, const char* relation, size_t* n);
+
+/* Copy a relation out (see dl_relation_out).  `capacity` rows are available
+ * in every given buffer; fewer than the relation size gives DL_ERR_ARG.
+ * on_device selects device (1) or host (0) pointers for all buffers. */
+dl_status dl_read_relation(dl_engine* e, const char* relation, size_t capacity,
+                           const dl_relation_out* out, int on_device, size_t* n_written);
+
+/* Reverse mode for DIFF_ADDMULT and DIFF_TOPK: grad_out[i] is d(loss)/d(tag)
+ * of row i of out_relation in canonical order.  Gradients with respect to the
+ * input facts' tags are accumulated (+=) into the engine until dl_zero_grad. */
+dl_status dl_backward(dl_engine* e, const char* out_relation, const float* grad_out, int on_device);
+
+/* Accumulated input gradients of an input relation, in dl_add_facts order. */
+dl_status dl_read_grad(dl_engine* e, const char* in_relation, float* grad_in, int on_device);
+
+dl_status dl_zero_grad(dl_engine* e);
+
+dl_status dl_get_stats(const dl_engine* e, dl_stats* out);
+
+/* Owned by the engine; valid until the next call on it.  Never NULL. */
+const char* dl_last_error(const dl_engine* e);
+
+void dl_free(dl_engine* e);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DLFIX_H */

@@ -1,0 +1,161 @@
+// Device-side building blocks for gfx950 (CDNA4, wave64): wave ballots,
+// mbcnt ranks, wave/block scans, packed-key helpers and the provenance tag
+// algebra.  Included by the .hip kernel sources only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dlfix {
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;  // 4 waves per workgroup
+constexpr int NWAVES = BLOCK / WAVE;
+
+__device__ __forceinline__ int lane_id() { return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// Number of set bits of `mask` below the calling lane.
+__device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Inclusive scan across the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    T t = __shfl_up(v, d, WAVE);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+  return v;
+}
+
+// Exclusive scan over a 256-thread block; returns the block total in *total.
+// `tmp` is __shared__ storage of NWAVES elements.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* tmp, T* total) {
+  const int lane = lane_id();
+  const int w = threadIdx.x / WAVE;
+  T inc = wave_inclusive_scan(v);
+  if (lane == WAVE - 1) tmp[w] = inc;
+  __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < NWAVES; ++i) {
+    T t = tmp[i];
+    if (i < w) before += t;
+    all += t;
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - v;
+}
+
+// ---------------------------------------------------------------- tag types
+// Bool: presence is the tag (nothing stored).
+struct NoTag {};
+
+// Top-k proofs, k <= 3: bitsets over the sample's probabilistic facts with
+// their binary32 probabilities, best first.
+struct TopK {
+  uint64_t b[3];
+  float p[3];
+  uint32_t cnt;
+};
+
+enum SemiringKind : int { SR_BOOL = 0, SR_MAXMIN = 1, SR_MINPLUS = 2, SR_ADDMULT = 3, SR_DIFF_ADDMULT = 4, SR_TOPK = 5, SR_DIFF_TOPK = 6 };
+
+// x for binary32 semirings (`sr` is uniform across the launch).
+__device__ __forceinline__ float f_otimes(int sr, float a, float b) {
+  switch (sr) {
+    case SR_MAXMIN: return fminf(a, b);
+    case SR_MINPLUS: return __fadd_rn(a, b);
+    default: return __fmul_rn(a, b);
+  }
+}
+// + for binary32 semirings; add-mult clamps at 1.
+__device__ __forceinline__ float f_oplus(int sr, float a, float b) {
+  switch (sr) {
+    case SR_MAXMIN: return fmaxf(a, b);
+    case SR_MINPLUS: return fminf(a, b);
+    default: return fminf(1.0f, __fadd_rn(a, b));
+  }
+}
+
+// Probability of a proof: product of its facts' probabilities in binary32,
+// ascending fact id, starting from 1 (multiplications only: no contraction).
+__device__ __forceinline__ float proof_prob(uint64_t bits, const float* __restrict__ q) {
+  float acc = 1.0f;
+  while (bits) {
+    int i = __builtin_ctzll(bits);
+    acc = __fmul_rn(acc, q[i]);
+    bits &= bits - 1;
+  }
+  return acc;
+}
+
+// Ranking of proofs: higher probability first, then smaller bitset.
+__device__ __forceinline__ bool proof_before(float pa, uint64_t ba, float pb, uint64_t bb) {
+  return pa > pb || (pa == pb && ba < bb);
+}
+
+// Offer one proof to a best-k list (kept sorted, distinct bitsets).
+__device__ __forceinline__ void topk_offer(TopK& t, int k, uint64_t b, float p) {
+  for (uint32_t i = 0; i < t.cnt; ++i)
+    if (t.b[i] == b) return;
+  int pos = (int)t.cnt;
+  while (pos > 0 && proof_before(p, b, t.p[pos - 1], t.b[pos - 1])) --pos;
+  if (pos >= k) return;
+  int last = (int)t.cnt < k ? (int)t.cnt : k - 1;
+  for (int i = last; i > pos; --i) {
+    t.b[i] = t.b[i - 1];
+    t.p[i] = t.p[i - 1];
+  }
+  t.b[pos] = b;
+  t.p[pos] = p;
+  if ((int)t.cnt < k) ++t.cnt;
+}
+
+__device__ __forceinline__ TopK topk_empty() {
+  TopK t;
+  t.cnt = 0;
+  t.b[0] = t.b[1] = t.b[2] = 0;
+  t.p[0] = t.p[1] = t.p[2] = 0.0f;
+  return t;
+}
+
+// a x b: the k best distinct unions of one proof of a with one of b.
+__device__ __forceinline__ TopK topk_otimes(const TopK& a, const TopK& b, int k, const float* __restrict__ q) {
+  TopK t = topk_empty();
+  for (uint32_t i = 0; i < a.cnt; ++i)
+    for (uint32_t j = 0; j < b.cnt; ++j) {
+      uint64_t u = a.b[i] | b.b[j];
+      topk_offer(t, k, u, proof_prob(u, q));
+    }
+  return t;
+}
+
+// a + b: the k best distinct proofs of the two lists.
+__device__ __forceinline__ TopK topk_oplus(const TopK& a, const TopK& b, int k) {
+  TopK t = a;
+  for (uint32_t j = 0; j < b.cnt; ++j) topk_offer(t, k, b.b[j], b.p[j]);
+  return t;
+}
+
+__device__ __forceinline__ bool topk_same(const TopK& a, const TopK& b) {
+  if (a.cnt != b.cnt) return false;
+  for (uint32_t i = 0; i < a.cnt; ++i)
+    if (a.b[i] != b.b[i]) return false;
+  return true;
+}
+
+}  // namespace dlfix

@@ -1,0 +1,151 @@
+// Host side of the fixpoint engine: device buffers, relation store, plans.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dlfix.h"
+#include "kernels.h"
+#include "program.h"
+
+namespace dlfix {
+
+// Raised inside the library, turned into a dl_status at the C boundary.
+struct Error {
+  dl_status code;
+  std::string msg;
+};
+
+#define DL_HIP(call)                                                                                 \
+  do {                                                                                               \
+    hipError_t err_ = (call);                                                                        \
+    if (err_ != hipSuccess)                                                                          \
+      throw ::dlfix::Error{err_ == hipErrorOutOfMemory ? DL_ERR_NOMEM : DL_ERR_HIP,                   \
+                           std::string(#call) + ": " + hipGetErrorString(err_)};                     \
+  } while (0)
+
+// A device buffer that only grows (buffer reuse across iterations, Sec. 4.1).
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+struct Table {
+  DevBuf keys, tags, ids;
+  size_t n = 0;
+};
+
+struct RelState {
+  // input relations: facts staged as they arrive, packed at the next run
+  std::vector<DevBuf> raw_cols;
+  DevBuf raw_sample, raw_tags, raw_local;  // raw_local: top-k fact id inside its sample
+  size_t nraw = 0;
+  Table full, full_alt, recent;
+  DevBuf cand_keys, cand_tags, cand_l, cand_r;  // this round's derivations (head rows)
+  size_t ncand = 0;
+  uint64_t version = 0;  // bumped whenever `full` changes (keys or tags)
+  DevBuf fact_entry;  // input facts -> entry id
+  DevBuf grad;        // accumulated input gradients (per fact)
+  std::vector<uint32_t> fact_slot;  // top-k: sample*64 + local id per fact (host)
+  DevBuf fact_slot_d;
+  uint32_t id_base = 0;  // input relations: id of entry 0
+};
+
+struct IndexState {
+  Table t;           // keys permuted, tags, ids
+  DevBuf off;        // CSR over the prefix
+  bool built = false;
+  bool borrowed = false;  // identity permutation: t aliases the relation
+  uint64_t version = ~0ull;  // relation version it was built from
+};
+
+struct LineageSeg {
+  size_t off, n;
+};
+
+struct Engine {
+  Program prog;
+  dl_options opts{};
+  int sr = 0;
+  int k = 3;
+  bool batched = false;
+  bool converge = true;   // idempotent +
+  bool lineage = false;   // diff add-mult
+  int tag_kind = 0;       // TagKind
+  size_t tag_bytes = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  // data-dependent layout, fixed at ingest
+  bool ingested = false;
+  bool ran = false;
+  bool key64 = false;
+  int cbits = 1, sbits = 0;
+  std::vector<RelState> rel;
+  std::vector<IndexState> idx;
+
+  // top-k: fact probabilities per sample [sample][64] and counters
+  std::vector<float> qtab_h;
+  std::vector<uint32_t> topk_next;
+  DevBuf qtab, grad_fact;
+
+  // lineage log (diff add-mult) and per-id tags
+  DevBuf lin_owner, lin_l, lin_r, tag_by_id, adj;
+  size_t lin_n = 0;
+  std::vector<LineageSeg> lin_segs;
+  uint32_t next_id = 0;
+
+  // round scratch
+  DevBuf counts, offs, alt_keys, alt_vals, vals, flags, pos, ukeys, utags,
+      status, nflags, newpos, rflags, rpos, lf, lpos, nkeys, ntags, nids, tmpA_keys, tmpA_tags, tmpB_keys, tmpB_tags,
+      scratch, unpack;
+  uint64_t* host = nullptr;  // pinned readback words
+  DevBuf dtotal;             // device words for totals
+
+  dl_stats stats{};
+  size_t device_bytes = 0;
+
+  ~Engine();
+  // memory
+  void grow(DevBuf& b, size_t bytes, bool keep = false, size_t used = 0);
+  void release(DevBuf& b);
+  uint64_t read_total(int slot);
+  void read_totals();  // all total slots into host[] (one sync)
+  void sync();
+
+  // lifecycle
+  void init(const char* text, const dl_options* o);
+  void add_facts(const char* relation, size_t n, const uint32_t* sample_ids, const uint32_t* const* columns,
+                 const float* tags, int on_device);
+  void clear_facts();
+  void run();
+  size_t relation_size(const char* relation);
+  size_t read_relation(const char* relation, size_t capacity, const dl_relation_out* out, int on_device);
+  void backward(const char* out_relation, const float* grad_out, int on_device);
+  void read_grad(const char* in_relation, float* grad_in, int on_device);
+  void zero_grad();
+
+  int relation_id(const char* name, bool must_exist = true);
+  KeyLayout layout(int ncols) const { return KeyLayout{ncols, cbits, sbits}; }
+  int key_width(int ncols) const { return sbits + ncols * cbits; }
+};
+
+// Typed halves (K = packed key type), in engine_run.hip.
+template <typename K>
+void ingest(Engine& e);
+template <typename K>
+void run_fixpoint(Engine& e);
+template <typename K>
+size_t read_relation_t(Engine& e, int r, size_t capacity, const dl_relation_out* out, int on_device);
+template <typename K>
+void backward_t(Engine& e, int r, const float* grad_out);
+
+}  // namespace dlfix

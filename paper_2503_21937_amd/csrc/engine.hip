@@ -1,0 +1,392 @@
+// Engine lifecycle, fact staging, device memory and the C ABI (dlfix.h).
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "dl_device.h"
+#include "engine.h"
+
+namespace dlfix {
+
+Engine::~Engine() {
+  auto fr = [](DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+  };
+  for (auto& r : rel) {
+    for (auto& c : r.raw_cols) fr(c);
+    fr(r.raw_sample), fr(r.raw_tags), fr(r.raw_local);
+    for (Table* t : {&r.full, &r.full_alt, &r.recent}) fr(t->keys), fr(t->tags), fr(t->ids);
+    fr(r.fact_entry), fr(r.grad), fr(r.fact_slot_d);
+    fr(r.cand_keys), fr(r.cand_tags), fr(r.cand_l), fr(r.cand_r);
+  }
+  for (auto& x : idx) {
+    if (!x.borrowed) fr(x.t.keys), fr(x.t.tags), fr(x.t.ids);
+    fr(x.off);
+  }
+  for (DevBuf* b : {&qtab, &grad_fact, &lin_owner, &lin_l, &lin_r, &tag_by_id, &adj, &counts, &offs, &alt_keys, &alt_vals, &vals, &flags, &pos, &ukeys, &utags, &status,
+                    &nflags, &newpos, &rflags, &rpos, &lf, &lpos, &nkeys, &ntags, &nids, &tmpA_keys, &tmpA_tags,
+                    &tmpB_keys, &tmpB_tags, &scratch, &unpack, &dtotal})
+    fr(*b);
+  if (host) (void)hipHostFree(host);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+void Engine::grow(DevBuf& b, size_t bytes, bool keep, size_t used) {
+  if (bytes <= b.cap) return;
+  size_t cap = std::max<size_t>(bytes + bytes / 4, 256);
+  void* p = nullptr;
+  hipError_t err = hipMalloc(&p, cap);
+  if (err != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{DL_ERR_NOMEM, "device allocation of " + std::to_string(cap) + " bytes failed"};
+  }
+  if (keep && used && b.p) DL_HIP(hipMemcpyAsync(p, b.p, used, hipMemcpyDeviceToDevice, stream));
+  if (b.p) {
+    DL_HIP(hipStreamSynchronize(stream));  // the old buffer may still be read by queued work
+    DL_HIP(hipFree(b.p));
+    device_bytes -= b.cap;
+  }
+  b.p = p;
+  b.cap = cap;
+  device_bytes += cap;
+}
+
+void Engine::release(DevBuf& b) {
+  if (b.p) {
+    DL_HIP(hipStreamSynchronize(stream));
+    DL_HIP(hipFree(b.p));
+    device_bytes -= b.cap;
+  }
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+void Engine::sync() { DL_HIP(hipStreamSynchronize(stream)); }
+
+void Engine::read_totals() {
+  DL_HIP(hipMemcpyAsync(host, dtotal.p, 32 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+  sync();
+}
+
+uint64_t Engine::read_total(int slot) {
+  DL_HIP(hipMemcpyAsync(host, dtotal.as<uint64_t>() + slot, sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+  sync();
+  return host[0];
+}
+
+int Engine::relation_id(const char* name, bool must_exist) {
+  if (!name) throw Error{DL_ERR_ARG, "relation name is NULL"};
+  int r = prog.find(name);
+  if (r < 0 && must_exist) throw Error{DL_ERR_ARG, std::string("unknown relation ") + name};
+  return r;
+}
+
+void Engine::init(const char* text, const dl_options* o) {
+  opts = *o;
+  sr = o->semiring;
+  if (sr < DL_BOOL || sr > DL_DIFF_TOPK) throw Error{DL_ERR_ARG, "unknown semiring"};
+  k = o->k == 0 ? 3 : o->k;
+  if ((sr == DL_TOPK || sr == DL_DIFF_TOPK) && (k < 1 || k > 3)) throw Error{DL_ERR_ARG, "k must be 1..3"};
+  batched = o->batched != 0;
+  converge = !(sr == DL_ADDMULT || sr == DL_DIFF_ADDMULT);
+  lineage = sr == DL_DIFF_ADDMULT;
+  tag_kind = sr == DL_BOOL ? TAG_NONE : (sr == DL_TOPK || sr == DL_DIFF_TOPK) ? TAG_TOPK : TAG_F32;
+  tag_bytes = tag_kind == TAG_NONE ? 0 : tag_kind == TAG_F32 ? 4 : sizeof(TopK);
+  std::string perr;
+  int rc = parse_and_plan(text, !converge, lineage, prog, perr);
+  if (rc) throw Error{(dl_status)rc, perr};
+  rel.assign(prog.rels.size(), RelState{});
+  for (size_t r = 0; r < prog.rels.size(); ++r) rel[r].raw_cols.assign(prog.rels[r].arity, DevBuf{});
+  idx.assign(prog.indexes.size(), IndexState{});
+  if (o->stream) {
+    stream = (hipStream_t)o->stream;
+  } else {
+    DL_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    own_stream = true;
+  }
+  DL_HIP(hipHostMalloc((void**)&host, 64 * sizeof(uint64_t), hipHostMallocDefault));
+  grow(dtotal, 64 * sizeof(uint64_t));
+}
+
+void Engine::clear_facts() {
+  for (auto& r : rel) {
+    r.nraw = 0;
+    r.fact_slot.clear();
+    r.full.n = r.full_alt.n = r.recent.n = 0;
+  }
+  for (auto& x : idx) x.built = false;
+  qtab_h.clear();
+  topk_next.clear();
+  ingested = false;
+  ran = false;
+}
+
+void Engine::add_facts(const char* relation, size_t n, const uint32_t* sample_ids, const uint32_t* const* columns,
+                       const float* tags, int on_device) {
+  int r = relation_id(relation);
+  if (!prog.rels[r].input) throw Error{DL_ERR_ARG, std::string(relation) + " is not an input relation"};
+  if (n == 0) return;
+  const int ar = prog.rels[r].arity;
+  if (!columns) throw Error{DL_ERR_ARG, "columns is NULL"};
+  for (int c = 0; c < ar; ++c)
+    if (!columns[c]) throw Error{DL_ERR_ARG, "a column pointer is NULL"};
+  if (batched && !sample_ids) throw Error{DL_ERR_ARG, "batched engine needs sample ids"};
+  if (sr != DL_BOOL && !tags) throw Error{DL_ERR_ARG, "this semiring needs tags"};
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  RelState& R = rel[r];
+  const bool topk = tag_kind == TAG_TOPK;
+  std::vector<uint32_t> samp_h;
+  std::vector<float> q_h;
+  std::vector<uint32_t> local_h;
+  if (topk) {  // fact ids inside each sample, in add order (host bookkeeping)
+    samp_h.assign(n, 0);
+    q_h.assign(n, 0.0f);
+    if (batched) DL_HIP(hipMemcpy(samp_h.data(), sample_ids, n * 4, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    DL_HIP(hipMemcpy(q_h.data(), tags, n * 4, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    std::vector<uint32_t> next = topk_next;
+    local_h.assign(n, 0);
+    for (size_t i = 0; i < n; ++i) {
+      uint32_t s = samp_h[i];
+      if (s >= next.size()) next.resize((size_t)s + 1, 0);
+      if (next[s] >= 64)
+        throw Error{DL_ERR_PROOF_OVERFLOW, "sample " + std::to_string(s) + " has more than 64 probabilistic facts"};
+      local_h[i] = next[s]++;
+    }
+    topk_next = next;
+    if (qtab_h.size() < topk_next.size() * 64) qtab_h.resize(topk_next.size() * 64, 0.0f);
+    for (size_t i = 0; i < n; ++i) {
+      qtab_h[(size_t)samp_h[i] * 64 + local_h[i]] = q_h[i];
+      R.fact_slot.push_back(samp_h[i] * 64 + local_h[i]);
+    }
+  }
+  const size_t old = R.nraw;
+  for (int c = 0; c < ar; ++c) {
+    grow(R.raw_cols[c], (old + n) * 4, true, old * 4);
+    DL_HIP(hipMemcpyAsync(R.raw_cols[c].as<uint32_t>() + old, columns[c], n * 4, kind, stream));
+  }
+  if (batched) {
+    grow(R.raw_sample, (old + n) * 4, true, old * 4);
+    DL_HIP(hipMemcpyAsync(R.raw_sample.as<uint32_t>() + old, sample_ids, n * 4, kind, stream));
+  }
+  if (tag_kind != TAG_NONE) {
+    grow(R.raw_tags, (old + n) * 4, true, old * 4);
+    DL_HIP(hipMemcpyAsync(R.raw_tags.as<float>() + old, tags, n * 4, kind, stream));
+  }
+  if (topk) {
+    grow(R.raw_local, (old + n) * 4, true, old * 4);
+    DL_HIP(hipMemcpyAsync(R.raw_local.as<uint32_t>() + old, local_h.data(), n * 4, hipMemcpyHostToDevice, stream));
+  }
+  R.nraw = old + n;
+  sync();  // host staging vectors go out of scope
+  ingested = false;
+  ran = false;
+}
+
+static int bits_for(uint32_t maxv) {
+  int b = 1;
+  while (b < 32 && (uint64_t)maxv >= (1ull << b)) ++b;
+  return b;
+}
+
+void Engine::run() {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!ingested) {
+    // id domain and sample domain from the facts
+    uint32_t* dmax = reinterpret_cast<uint32_t*>(dtotal.as<uint64_t>() + 30);
+    DL_HIP(hipMemsetAsync(dmax, 0, 8, stream));
+    for (size_t r = 0; r < rel.size(); ++r) {
+      for (auto& c : rel[r].raw_cols) max_u32(c.as<uint32_t>(), rel[r].nraw, dmax, stream);
+      if (batched) max_u32(rel[r].raw_sample.as<uint32_t>(), rel[r].nraw, dmax + 1, stream);
+    }
+    DL_HIP(hipMemcpyAsync(host, dmax, 8, hipMemcpyDeviceToHost, stream));
+    sync();
+    uint32_t maxid = (uint32_t)host[0], maxs = (uint32_t)(host[0] >> 32);
+    cbits = bits_for(maxid);
+    sbits = batched ? bits_for(maxs) : 0;
+    int width = key_width(prog.max_cols);
+    if (width > 64)
+      throw Error{DL_ERR_UNSUPPORTED, "packed keys need " + std::to_string(width) + " bits (more than 64)"};
+    key64 = width > 32;
+    stats.key_bits = key64 ? 64 : 32;
+    stats.id_bits = (uint32_t)cbits;
+    stats.sample_bits = (uint32_t)sbits;
+    if (key64) ingest<uint64_t>(*this);
+    else ingest<uint32_t>(*this);
+    ingested = true;
+  }
+  if (key64) run_fixpoint<uint64_t>(*this);
+  else run_fixpoint<uint32_t>(*this);
+  ran = true;
+  stats.run_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  stats.device_bytes = device_bytes;
+}
+
+size_t Engine::relation_size(const char* relation) {
+  int r = relation_id(relation);
+  if (!ran) throw Error{DL_ERR_STATE, "run the fixpoint first"};
+  return rel[r].full.n;
+}
+
+size_t Engine::read_relation(const char* relation, size_t capacity, const dl_relation_out* out, int on_device) {
+  int r = relation_id(relation);
+  if (!ran) throw Error{DL_ERR_STATE, "run the fixpoint first"};
+  if (!out) throw Error{DL_ERR_ARG, "out is NULL"};
+  if (capacity < rel[r].full.n) throw Error{DL_ERR_ARG, "capacity below the relation size"};
+  return key64 ? read_relation_t<uint64_t>(*this, r, capacity, out, on_device)
+               : read_relation_t<uint32_t>(*this, r, capacity, out, on_device);
+}
+
+void Engine::backward(const char* out_relation, const float* grad_out, int on_device) {
+  int r = relation_id(out_relation);
+  if (!ran) throw Error{DL_ERR_STATE, "run the fixpoint first"};
+  if (sr != DL_DIFF_ADDMULT && sr != DL_DIFF_TOPK)
+    throw Error{DL_ERR_STATE, "backward needs DL_DIFF_ADDMULT or DL_DIFF_TOPK"};
+  const size_t n = rel[r].full.n;
+  if (n && !grad_out) throw Error{DL_ERR_ARG, "grad_out is NULL"};
+  grow(unpack, n * 4 + 4);
+  if (n)
+    DL_HIP(hipMemcpyAsync(unpack.p, grad_out, n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          stream));
+  if (key64) backward_t<uint64_t>(*this, r, unpack.as<float>());
+  else backward_t<uint32_t>(*this, r, unpack.as<float>());
+  sync();
+}
+
+void Engine::read_grad(const char* in_relation, float* grad_in, int on_device) {
+  int r = relation_id(in_relation);
+  if (!prog.rels[r].input) throw Error{DL_ERR_ARG, "not an input relation"};
+  if (!ran) throw Error{DL_ERR_STATE, "run the fixpoint first"};
+  RelState& R = rel[r];
+  if (!R.nraw) return;
+  if (!grad_in) throw Error{DL_ERR_ARG, "grad_in is NULL"};
+  grow(R.grad, R.nraw * 4);
+  if (tag_kind == TAG_TOPK) {
+    // grad_fact is [sample][64]; gather the slots of this relation's facts
+    grow(R.fact_slot_d, R.nraw * 4);
+    DL_HIP(hipMemcpyAsync(R.fact_slot_d.p, R.fact_slot.data(), R.nraw * 4, hipMemcpyHostToDevice, stream));
+    gather(grad_fact.p, R.fact_slot_d.as<uint32_t>(), R.grad.p, R.nraw, 4, stream);
+  }
+  DL_HIP(hipMemcpyAsync(grad_in, R.grad.p, R.nraw * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        stream));
+  sync();
+}
+
+void Engine::zero_grad() {
+  for (auto& R : rel)
+    if (R.grad.p) DL_HIP(hipMemsetAsync(R.grad.p, 0, R.grad.cap, stream));
+  if (grad_fact.p) DL_HIP(hipMemsetAsync(grad_fact.p, 0, grad_fact.cap, stream));
+  sync();
+}
+
+}  // namespace dlfix
+
+// ---------------------------------------------------------------- C ABI
+using dlfix::Engine;
+using dlfix::Error;
+
+struct dl_engine {
+  Engine e;
+};
+
+template <typename F>
+static dl_status guard(dl_engine* h, F&& f) {
+  if (!h) return DL_ERR_ARG;
+  try {
+    h->e.err.clear();
+    f();
+    return DL_OK;
+  } catch (const Error& x) {
+    h->e.err = x.msg;
+    return x.code;
+  } catch (const std::bad_alloc&) {
+    h->e.err = "host allocation failed";
+    return DL_ERR_NOMEM;
+  } catch (const std::exception& x) {
+    h->e.err = x.what();
+    return DL_ERR_HIP;
+  }
+}
+
+static thread_local std::string g_load_error;
+
+extern "C" {
+
+dl_status dl_load_program(const char* program_text, const dl_options* opts, dl_engine** out) {
+  if (!out) return DL_ERR_ARG;
+  *out = nullptr;
+  if (!program_text || !opts) {
+    g_load_error = "program text or options is NULL";
+    return DL_ERR_ARG;
+  }
+  dl_engine* h = nullptr;
+  try {
+    h = new dl_engine();
+    h->e.init(program_text, opts);
+  } catch (const Error& x) {
+    g_load_error = x.msg;
+    delete h;
+    return x.code;
+  } catch (const std::exception& x) {
+    g_load_error = x.what();
+    delete h;
+    return DL_ERR_HIP;
+  }
+  *out = h;
+  return DL_OK;
+}
+
+dl_status dl_clear_facts(dl_engine* h) {
+  return guard(h, [&] { h->e.clear_facts(); });
+}
+
+dl_status dl_add_facts(dl_engine* h, const char* relation, size_t n, const uint32_t* sample_ids,
+                       const uint32_t* const* columns, const float* tags, int on_device) {
+  return guard(h, [&] { h->e.add_facts(relation, n, sample_ids, columns, tags, on_device); });
+}
+
+dl_status dl_run_fixpoint(dl_engine* h) {
+  return guard(h, [&] { h->e.run(); });
+}
+
+dl_status dl_relation_size(dl_engine* h, const char* relation, size_t* n) {
+  return guard(h, [&] {
+    if (!n) throw Error{DL_ERR_ARG, "n is NULL"};
+    *n = h->e.relation_size(relation);
+  });
+}
+
+dl_status dl_read_relation(dl_engine* h, const char* relation, size_t capacity, const dl_relation_out* out,
+                           int on_device, size_t* n_written) {
+  return guard(h, [&] {
+    size_t n = h->e.read_relation(relation, capacity, out, on_device);
+    if (n_written) *n_written = n;
+  });
+}
+
+dl_status dl_backward(dl_engine* h, const char* out_relation, const float* grad_out, int on_device) {
+  return guard(h, [&] { h->e.backward(out_relation, grad_out, on_device); });
+}
+
+dl_status dl_read_grad(dl_engine* h, const char* in_relation, float* grad_in, int on_device) {
+  return guard(h, [&] { h->e.read_grad(in_relation, grad_in, on_device); });
+}
+
+dl_status dl_zero_grad(dl_engine* h) {
+  return guard(h, [&] { h->e.zero_grad(); });
+}
+
+dl_status dl_get_stats(const dl_engine* h, dl_stats* out) {
+  if (!h || !out) return DL_ERR_ARG;
+  *out = h->e.stats;
+  return DL_OK;
+}
+
+const char* dl_last_error(const dl_engine* h) {
+  if (!h) return g_load_error.c_str();
+  return h->e.err.c_str();
+}
+
+void dl_free(dl_engine* h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,580 @@
+// The semi-naive fixpoint loop (Sec. 3.4, Algorithm 1, Appendix A) over the
+// packed-key relation store, for one key width K.
+//
+// Per stratum: round 1 runs the base plans (rules whose body lies in lower
+// strata or the input) on whole relations; every later round runs the delta
+// plans, each driven by the recent tuples of one atom of the stratum.  All
+// derivations of a round land in one candidate buffer per head relation
+// (this replaces the paper's `append` of the three delta joins) and are then
+// sorted, +-reduced per key, compared with the full relation (difference for
+// frozen add-mult tags, +-merge for the converging semirings, updated only
+// after every join of the round has run: Jacobi order) and merged into it.
+// The new or changed tuples become the next round's recent relation; the
+// stratum ends after the first round that changes nothing.
+#include <algorithm>
+#include <cstring>
+
+#include "dl_device.h"
+#include "engine.h"
+
+namespace dlfix {
+
+namespace {
+
+enum Slot { S_SCAN = 0, S_UNIQUE = 1, S_NEW = 2, S_RECENT = 3, S_LIN = 4 };
+
+uint64_t* total_slot(Engine& e, int s) { return e.dtotal.as<uint64_t>() + s; }
+
+void ensure_scratch(Engine& e, size_t words) { e.grow(e.scratch, (words + 16) * sizeof(uint64_t)); }
+
+template <typename K>
+void sort_pairs(Engine& e, K** kp, uint32_t** vp, size_t n, int bits) {
+  e.grow(e.alt_keys, n * sizeof(K));
+  ensure_scratch(e, radix_scratch_words(n));
+  K* ka = e.alt_keys.as<K>();
+  uint32_t* va = nullptr;
+  if (vp && *vp) {
+    e.grow(e.alt_vals, n * 4);
+    va = e.alt_vals.as<uint32_t>();
+  }
+  radix_sort<K>(kp, vp, &ka, &va, n, bits, e.scratch.as<uint64_t>(), e.stream);
+}
+
+void scan(Engine& e, const uint32_t* in, uint32_t* out, size_t n, int slot, bool sentinel) {
+  ensure_scratch(e, scan_scratch_words(n));
+  scan_u32(in, out, n, total_slot(e, slot), sentinel, e.scratch.as<uint64_t>(), e.stream);
+}
+
+// If a sort left its result in the engine's alternate buffer, move the
+// buffers so that `owner` holds the sorted data.
+void claim(DevBuf& owner, DevBuf& alt, const void* result) {
+  if (result == alt.p) std::swap(owner, alt);
+}
+
+template <typename K>
+void build_index(Engine& e, int i) {
+  const IndexSpec& spec = e.prog.indexes[i];
+  IndexState& ix = e.idx[i];
+  RelState& R = e.rel[spec.rel];
+  const int ar = e.prog.rels[spec.rel].arity;
+  const KeyLayout lay = e.layout(ar);
+  const size_t n = R.full.n;
+  const int pbits = e.sbits + spec.w * e.cbits;
+  if (pbits > 30) throw Error{DL_ERR_UNSUPPORTED, "join key domain above 2^30 (index on " + e.prog.rels[spec.rel].name + ")"};
+  if (spec.identity()) {
+    if (!ix.borrowed) {
+      e.release(ix.t.keys), e.release(ix.t.tags), e.release(ix.t.ids);
+      ix.borrowed = true;
+    }
+    ix.t.keys = R.full.keys;
+    ix.t.tags = R.full.tags;
+    ix.t.ids = R.full.ids;
+  } else {
+    if (ix.borrowed) {
+      ix.t = Table{};
+      ix.borrowed = false;
+    }
+    e.grow(ix.t.keys, n * sizeof(K) + 8);
+    e.grow(e.vals, n * 4 + 4);
+    permute_keys<K>(R.full.keys.as<K>(), n, lay, spec.perm.data(), ix.t.keys.as<K>(), e.stream);
+    iota_u32(e.vals.as<uint32_t>(), n, 0, e.stream);
+    K* kp = ix.t.keys.as<K>();
+    uint32_t* vp = e.vals.as<uint32_t>();
+    sort_pairs<K>(e, &kp, &vp, n, e.key_width(ar));
+    claim(ix.t.keys, e.alt_keys, kp);
+    claim(e.vals, e.alt_vals, vp);
+    if (e.tag_bytes) {
+      e.grow(ix.t.tags, n * e.tag_bytes + 8);
+      gather(R.full.tags.p, e.vals.as<uint32_t>(), ix.t.tags.p, n, e.tag_bytes, e.stream);
+    }
+    if (e.lineage) {
+      e.grow(ix.t.ids, n * 4 + 4);
+      gather(R.full.ids.p, e.vals.as<uint32_t>(), ix.t.ids.p, n, 4, e.stream);
+    }
+  }
+  ix.t.n = n;
+  e.grow(ix.off, (((size_t)1 << pbits) + 1) * 4);
+  csr_build<K>(ix.t.keys.as<K>(), n, e.key_width(ar), pbits, ix.off.as<uint32_t>(), e.stream);
+  ix.built = true;
+  ix.version = R.version;
+}
+
+template <typename K>
+void ensure_index(Engine& e, int i) {
+  IndexState& ix = e.idx[i];
+  const RelState& R = e.rel[e.prog.indexes[i].rel];
+  bool stale = !ix.built || ix.version != R.version;
+  if (ix.borrowed && ix.t.keys.p != R.full.keys.p) stale = true;
+  if (stale) build_index<K>(e, i);
+}
+
+struct Cur {  // the table a plan is currently expanding
+  const void* keys;
+  const void* tags;
+  const uint32_t* ids;
+  size_t n;
+  int ncols;
+  int minpos;  // smallest body position folded into it
+};
+
+template <typename K>
+void run_plan(Engine& e, const Plan& pl) {
+  const Rule& rule = e.prog.rules[pl.rule];
+  RelState& D = e.rel[pl.driver_rel];
+  const Table& dt = pl.delta ? D.recent : D.full;
+  if (dt.n == 0) return;
+  RelState& H = e.rel[pl.head_rel];
+  const int har = e.prog.rels[pl.head_rel].arity;
+  Cur cur{dt.keys.p, dt.tags.p, dt.ids.as<uint32_t>(), dt.n, e.prog.rels[pl.driver_rel].arity, pl.driver_atom};
+
+  JoinArgs a{};
+  a.sr = e.sr;
+  a.k = e.k;
+  a.q = e.qtab.as<float>();
+
+  auto head_room = [&](size_t add) {
+    const size_t used = H.ncand;
+    e.grow(H.cand_keys, (used + add) * sizeof(K), true, used * sizeof(K));
+    if (e.tag_bytes) e.grow(H.cand_tags, (used + add) * e.tag_bytes, true, used * e.tag_bytes);
+    if (e.lineage) {
+      e.grow(H.cand_l, (used + add) * 4, true, used * 4);
+      e.grow(H.cand_r, (used + add) * 4, true, used * 4);
+    }
+  };
+  auto out_ptrs = [&](void** ok, void** ot, uint32_t** ol, uint32_t** orr) {
+    *ok = H.cand_keys.as<K>() + H.ncand;
+    *ot = e.tag_bytes ? (void*)(H.cand_tags.as<uint8_t>() + H.ncand * e.tag_bytes) : nullptr;
+    *ol = e.lineage ? H.cand_l.as<uint32_t>() + H.ncand : nullptr;
+    *orr = e.lineage ? H.cand_r.as<uint32_t>() + H.ncand : nullptr;
+  };
+
+  if (pl.steps.empty()) {  // single-atom rule: permutation projection, tags copied
+    a.dkeys = cur.keys;
+    a.dtags = cur.tags;
+    a.dids = cur.ids;
+    a.n = cur.n;
+    a.dlay = e.layout(cur.ncols);
+    a.olay = e.layout(har);
+    for (int c = 0; c < har; ++c) a.osrc[c] = pl.project[c];
+    head_room(cur.n);
+    void *ok, *ot;
+    uint32_t *ol, *orr;
+    out_ptrs(&ok, &ot, &ol, &orr);
+    project_rows<K>(a, e.tag_kind, ok, ot, ol, orr, e.stream);
+    H.ncand += cur.n;
+    return;
+  }
+
+  DevBuf* tmp_keys[2] = {&e.tmpA_keys, &e.tmpB_keys};
+  DevBuf* tmp_tags[2] = {&e.tmpA_tags, &e.tmpB_tags};
+  for (size_t si = 0; si < pl.steps.size(); ++si) {
+    const Step& step = pl.steps[si];
+    ensure_index<K>(e, step.index);
+    const IndexState& ix = e.idx[step.index];
+    const IndexSpec& spec = e.prog.indexes[step.index];
+    const int iar = e.prog.rels[spec.rel].arity;
+    a.dkeys = cur.keys;
+    a.dtags = cur.tags;
+    a.dids = cur.ids;
+    a.n = cur.n;
+    a.dlay = e.layout(cur.ncols);
+    a.w = spec.w;
+    for (int j = 0; j < spec.w; ++j) a.jsrc[j] = step.join_src[j];
+    a.off = ix.off.as<uint32_t>();
+    a.ikeys = ix.t.keys.p;
+    a.itags = ix.t.tags.p;
+    a.iids = ix.t.ids.as<uint32_t>();
+    a.ilay = e.layout(iar);
+    const int ocols = (int)step.out_vars.size();
+    a.olay = e.layout(ocols);
+    for (int c = 0; c < ocols; ++c) a.osrc[c] = step.out_src[c];
+    a.index_first = step.body_pos < cur.minpos;
+    (void)rule;
+
+    e.grow(e.counts, cur.n * 4 + 4);
+    e.grow(e.offs, (cur.n + 1) * 4);
+    join_count<K>(a, e.counts.as<uint32_t>(), e.stream);
+    scan(e, e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), cur.n, S_SCAN, true);
+    const uint64_t total = e.read_total(S_SCAN);
+    if (total > 0xffffffffull) throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
+    if (total == 0) return;
+    const bool last = si + 1 == pl.steps.size();
+    void *ok, *ot;
+    uint32_t *ol = nullptr, *orr = nullptr;
+    if (last) {
+      head_room(total);
+      out_ptrs(&ok, &ot, &ol, &orr);
+    } else {
+      DevBuf& kb = *tmp_keys[si & 1];
+      DevBuf& tb = *tmp_tags[si & 1];
+      e.grow(kb, total * sizeof(K));
+      if (e.tag_bytes) e.grow(tb, total * e.tag_bytes);
+      ok = kb.p;
+      ot = e.tag_bytes ? tb.p : nullptr;
+    }
+    join_expand<K>(a, e.tag_kind, e.offs.as<uint32_t>(), total, ok, ot, ol, orr, e.stream);
+    if (last) {
+      H.ncand += total;
+    } else {
+      cur = Cur{ok, ot, nullptr, total, ocols, std::min(cur.minpos, step.body_pos)};
+    }
+  }
+}
+
+// Deduplicate a relation's candidates and fold them into the store.
+// Returns the number of tuples that are new or changed (the next recent).
+template <typename K>
+size_t absorb(Engine& e, int r) {
+  RelState& R = e.rel[r];
+  const size_t C = R.ncand;
+  R.ncand = 0;
+  if (C == 0) {
+    R.recent.n = 0;
+    return 0;
+  }
+  e.stats.candidates += C;
+  const int ar = e.prog.rels[r].arity;
+  const size_t kb = sizeof(K), tb = e.tag_bytes;
+  const bool use_perm = e.tag_kind == TAG_TOPK || e.lineage;
+  hipStream_t st = e.stream;
+
+  // 1. sort the candidates by packed key (stable: derivation order kept)
+  K* kp = R.cand_keys.as<K>();
+  uint32_t* vp = nullptr;
+  if (use_perm) {
+    e.grow(e.vals, C * 4);
+    iota_u32(e.vals.as<uint32_t>(), C, 0, st);
+    vp = e.vals.as<uint32_t>();
+  } else if (e.tag_kind == TAG_F32) {
+    vp = R.cand_tags.as<uint32_t>();
+  }
+  sort_pairs<K>(e, &kp, &vp, C, e.key_width(ar));
+
+  // 2. runs of equal keys -> one row each, tags +-folded in sorted order
+  e.grow(e.flags, C * 4);
+  e.grow(e.pos, (C + 1) * 4);
+  head_flags<K>(kp, C, e.flags.as<uint32_t>(), st);
+  scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), C, S_UNIQUE, true);
+  const size_t U = e.read_total(S_UNIQUE);
+  e.stats.unique += U;
+  e.grow(e.ukeys, U * kb);
+  if (tb) e.grow(e.utags, U * tb);
+  const void* tsrc = use_perm ? R.cand_tags.p : (const void*)vp;
+  segment_reduce<K>(kp, e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), C, e.tag_kind, e.sr, e.k, tsrc,
+                    use_perm ? vp : nullptr, e.ukeys.as<K>(), e.utags.p, st);
+
+  // 3. difference / +-merge against the full relation
+  e.grow(e.status, U * 4);
+  diff_merge<K>(e.ukeys.as<K>(), e.utags.p, U, R.full.keys.as<K>(), R.full.tags.p, R.full.n, e.tag_kind, e.sr, e.k,
+                e.converge, e.status.as<uint32_t>(), nullptr, st);
+  e.grow(e.nflags, U * 4);
+  e.grow(e.newpos, (U + 1) * 4);
+  status_flags(e.status.as<uint32_t>(), U, 1u, e.nflags.as<uint32_t>(), st);
+  scan(e, e.nflags.as<uint32_t>(), e.newpos.as<uint32_t>(), U, S_NEW, true);
+  if (e.converge) {
+    e.grow(e.rflags, U * 4);
+    e.grow(e.rpos, (U + 1) * 4);
+    status_flags(e.status.as<uint32_t>(), U, 3u, e.rflags.as<uint32_t>(), st);
+    scan(e, e.rflags.as<uint32_t>(), e.rpos.as<uint32_t>(), U, S_RECENT, true);
+  }
+  e.read_totals();
+  const size_t N = e.host[S_NEW];
+  const size_t Rn = e.converge ? e.host[S_RECENT] : N;
+  const uint32_t* rfl = e.converge ? e.rflags.as<uint32_t>() : e.nflags.as<uint32_t>();
+  const uint32_t* rps = e.converge ? e.rpos.as<uint32_t>() : e.newpos.as<uint32_t>();
+
+  // 4. next recent relation = new (and, converging, changed) tuples, sorted
+  e.grow(R.recent.keys, Rn * kb + 8);
+  compact(e.ukeys.p, rfl, rps, U, kb, R.recent.keys.p, st);
+  if (tb) {
+    e.grow(R.recent.tags, Rn * tb + 8);
+    compact(e.utags.p, rfl, rps, U, tb, R.recent.tags.p, st);
+  }
+  R.recent.n = Rn;
+  if (Rn && e.converge) ++R.version;  // in-place tag updates
+  if (N == 0) return Rn;
+
+  // 5. rows to merge: the new tuples
+  const void* nk;
+  const void* nt;
+  const uint32_t* nid = nullptr;
+  if (e.converge) {
+    e.grow(e.nkeys, N * kb);
+    compact(e.ukeys.p, e.nflags.as<uint32_t>(), e.newpos.as<uint32_t>(), U, kb, e.nkeys.p, st);
+    if (tb) {
+      e.grow(e.ntags, N * tb);
+      compact(e.utags.p, e.nflags.as<uint32_t>(), e.newpos.as<uint32_t>(), U, tb, e.ntags.p, st);
+    }
+    nk = e.nkeys.p;
+    nt = e.ntags.p;
+  } else {
+    nk = R.recent.keys.p;
+    nt = R.recent.tags.p;
+  }
+  if (e.lineage) {
+    // ids of the new tuples, their tags by id, and their discovery derivations
+    const uint32_t base = e.next_id;
+    e.grow(R.recent.ids, N * 4 + 4);
+    iota_u32(R.recent.ids.as<uint32_t>(), N, base, st);
+    nid = R.recent.ids.as<uint32_t>();
+    e.grow(e.tag_by_id, ((size_t)base + N) * 4, true, (size_t)base * 4);
+    DL_HIP(hipMemcpyAsync(e.tag_by_id.as<float>() + base, nt, N * 4, hipMemcpyDeviceToDevice, st));
+    e.grow(e.lf, C * 4);
+    e.grow(e.lpos, (C + 1) * 4);
+    lineage_flags(e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), e.status.as<uint32_t>(), C, e.lf.as<uint32_t>(), st);
+    scan(e, e.lf.as<uint32_t>(), e.lpos.as<uint32_t>(), C, S_LIN, true);
+    const size_t L = e.read_total(S_LIN);
+    const size_t used = e.lin_n;
+    e.grow(e.lin_owner, (used + L) * 4, true, used * 4);
+    e.grow(e.lin_l, (used + L) * 4, true, used * 4);
+    e.grow(e.lin_r, (used + L) * 4, true, used * 4);
+    lineage_emit(e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), e.lf.as<uint32_t>(), e.lpos.as<uint32_t>(),
+                 e.newpos.as<uint32_t>(), vp, R.cand_l.as<uint32_t>(), R.cand_r.as<uint32_t>(), C, base,
+                 e.lin_owner.as<uint32_t>() + used, e.lin_l.as<uint32_t>() + used, e.lin_r.as<uint32_t>() + used, st);
+    e.lin_segs.push_back({used, L});
+    e.lin_n = used + L;
+    e.stats.lineage += L;
+    e.next_id = base + (uint32_t)N;
+  }
+
+  // 6. full' = merge(full, new)
+  const size_t F = R.full.n;
+  e.grow(R.full_alt.keys, (F + N) * kb + 8);
+  if (tb) e.grow(R.full_alt.tags, (F + N) * tb + 8);
+  if (e.lineage) e.grow(R.full_alt.ids, (F + N) * 4 + 4);
+  ensure_scratch(e, merge_scratch_words(F, N));
+  merge_sorted<K>(R.full.keys.as<K>(), R.full.tags.p, R.full.ids.as<uint32_t>(), F, (const K*)nk, nt, nid, N, tb,
+                  R.full_alt.keys.as<K>(), R.full_alt.tags.p, e.lineage ? R.full_alt.ids.as<uint32_t>() : nullptr,
+                  e.scratch.as<uint64_t>(), st);
+  std::swap(R.full, R.full_alt);
+  R.full.n = F + N;
+  ++R.version;
+  return Rn;
+}
+
+}  // namespace
+
+template <typename K>
+void ingest(Engine& e) {
+  hipStream_t st = e.stream;
+  if (e.tag_kind == TAG_TOPK) {
+    size_t q = std::max<size_t>(e.qtab_h.size(), 64);
+    e.grow(e.qtab, q * 4);
+    DL_HIP(hipMemsetAsync(e.qtab.p, 0, q * 4, st));
+    if (!e.qtab_h.empty())
+      DL_HIP(hipMemcpyAsync(e.qtab.p, e.qtab_h.data(), e.qtab_h.size() * 4, hipMemcpyHostToDevice, st));
+    e.grow(e.grad_fact, q * 4);
+    DL_HIP(hipMemsetAsync(e.grad_fact.p, 0, q * 4, st));
+  }
+  uint32_t id = 0;
+  for (size_t r = 0; r < e.rel.size(); ++r) {
+    if (!e.prog.rels[r].input) continue;
+    RelState& R = e.rel[r];
+    const size_t n = R.nraw;
+    const int ar = e.prog.rels[r].arity;
+    R.id_base = id;
+    R.full.n = 0;
+    R.recent.n = 0;
+    ++R.version;
+    if (n == 0) continue;
+    const KeyLayout lay = e.layout(ar);
+    // pack, sort with the fact index as payload, +-merge duplicate facts
+    e.grow(R.cand_keys, n * sizeof(K));
+    std::vector<const uint32_t*> cols(ar);
+    for (int c = 0; c < ar; ++c) cols[c] = R.raw_cols[c].as<uint32_t>();
+    pack_rows<K>(cols.data(), R.raw_sample.as<uint32_t>(), n, lay, R.cand_keys.as<K>(), st);
+    e.grow(e.vals, n * 4);
+    iota_u32(e.vals.as<uint32_t>(), n, 0, st);
+    K* kp = R.cand_keys.as<K>();
+    uint32_t* vp = e.vals.as<uint32_t>();
+    sort_pairs<K>(e, &kp, &vp, n, e.key_width(ar));
+    e.grow(e.flags, n * 4);
+    e.grow(e.pos, (n + 1) * 4);
+    head_flags<K>(kp, n, e.flags.as<uint32_t>(), st);
+    scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), n, S_UNIQUE, true);
+    const size_t U = e.read_total(S_UNIQUE);
+    const void* ftags = nullptr;
+    if (e.tag_kind == TAG_F32) {
+      ftags = R.raw_tags.p;
+    } else if (e.tag_kind == TAG_TOPK) {
+      e.grow(R.cand_tags, n * sizeof(TopK));
+      topk_from_facts(R.raw_tags.as<float>(), R.raw_local.as<uint32_t>(), n, R.cand_tags.as<TopK>(), st);
+      ftags = R.cand_tags.p;
+    }
+    e.grow(R.full.keys, U * sizeof(K) + 8);
+    if (e.tag_bytes) e.grow(R.full.tags, U * e.tag_bytes + 8);
+    segment_reduce<K>(kp, e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), n, e.tag_kind, e.sr, e.k, ftags, vp,
+                      R.full.keys.as<K>(), R.full.tags.p, st);
+    R.full.n = U;
+    e.grow(R.fact_entry, n * 4);
+    seg_scatter(e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), vp, n, id, R.fact_entry.as<uint32_t>(), st);
+    if (e.lineage) {
+      e.grow(R.full.ids, U * 4 + 4);
+      iota_u32(R.full.ids.as<uint32_t>(), U, id, st);
+    }
+    e.grow(R.grad, n * 4);
+    DL_HIP(hipMemsetAsync(R.grad.p, 0, n * 4, st));
+    id += (uint32_t)U;
+  }
+  if (e.lineage) {
+    e.grow(e.tag_by_id, (size_t)id * 4 + 4);
+    for (size_t r = 0; r < e.rel.size(); ++r) {
+      RelState& R = e.rel[r];
+      if (e.prog.rels[r].input && R.full.n)
+        DL_HIP(hipMemcpyAsync(e.tag_by_id.as<float>() + R.id_base, R.full.tags.p, R.full.n * 4,
+                              hipMemcpyDeviceToDevice, st));
+    }
+  }
+  for (auto& x : e.idx) x.built = false;
+  e.sync();
+}
+
+template <typename K>
+void run_fixpoint(Engine& e) {
+  e.stats.strata = 0;
+  e.stats.rounds = 0;
+  e.stats.max_rounds = 0;
+  e.stats.candidates = 0;
+  e.stats.unique = 0;
+  e.stats.lineage = 0;
+  e.stats.derived = 0;
+  uint32_t edb = 0;
+  for (size_t r = 0; r < e.rel.size(); ++r) {
+    RelState& R = e.rel[r];
+    R.ncand = 0;
+    if (e.prog.rels[r].input) {
+      edb += (uint32_t)R.full.n;
+    } else {
+      R.full.n = 0;
+      R.recent.n = 0;
+      ++R.version;
+    }
+  }
+  e.next_id = edb;
+  e.lin_n = 0;
+  e.lin_segs.clear();
+  for (const Stratum& st : e.prog.strata) {
+    int rounds = 1;
+    for (int p : st.base_plans) run_plan<K>(e, e.prog.plans[p]);
+    size_t changed = 0;
+    for (int r : st.rels) changed += absorb<K>(e, r);
+    while (changed && !st.delta_plans.empty()) {
+      ++rounds;
+      for (int p : st.delta_plans) run_plan<K>(e, e.prog.plans[p]);
+      changed = 0;
+      for (int r : st.rels) changed += absorb<K>(e, r);
+    }
+    if (changed) ++rounds;  // non-recursive stratum: its second round derives nothing
+    for (int r : st.rels) e.rel[r].recent.n = 0;
+    e.stats.strata += 1;
+    e.stats.rounds += rounds;
+    e.stats.max_rounds = std::max(e.stats.max_rounds, rounds);
+  }
+  for (size_t r = 0; r < e.rel.size(); ++r)
+    if (e.prog.rels[r].derived) e.stats.derived += e.rel[r].full.n;
+  e.sync();
+}
+
+template <typename K>
+size_t read_relation_t(Engine& e, int r, size_t capacity, const dl_relation_out* out, int on_device) {
+  (void)capacity;
+  RelState& R = e.rel[r];
+  const size_t n = R.full.n;
+  if (n == 0) return 0;
+  hipStream_t st = e.stream;
+  const int ar = e.prog.rels[r].arity;
+  const KeyLayout lay = e.layout(ar);
+  // device staging: columns + sample (u32 each), tags (f32), top-k parts
+  const size_t words = (size_t)(ar + 1) * n + n + (size_t)e.k * n * 3 + n;
+  e.grow(e.unpack, words * 4 + 64);
+  uint32_t* base = e.unpack.as<uint32_t>();
+  uint32_t* dcols[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint32_t* dsample = base + (size_t)ar * n;
+  float* dtag = reinterpret_cast<float*>(dsample + n);
+  uint64_t* dbits = reinterpret_cast<uint64_t*>(((uintptr_t)(dtag + n) + 7) & ~(uintptr_t)7);
+  float* dprob = reinterpret_cast<float*>(dbits + (size_t)e.k * n);
+  uint8_t* dcnt = reinterpret_cast<uint8_t*>(dprob + (size_t)e.k * n);
+  for (int c = 0; c < ar; ++c) dcols[c] = on_device ? out->columns[c] : (out->columns[c] ? base + (size_t)c * n : nullptr);
+  uint32_t* samp = on_device ? out->sample_ids : (out->sample_ids ? dsample : nullptr);
+  const bool need_sample = e.tag_kind == TAG_TOPK && e.batched;
+  uint32_t* samp_k = samp ? samp : (need_sample ? dsample : nullptr);
+  unpack_rows<K>(R.full.keys.as<K>(), n, lay, dcols, e.batched ? samp_k : nullptr, st);
+  if (!e.batched && samp) DL_HIP(hipMemsetAsync(samp, 0, n * 4, st));
+  float* tg = out->tags ? (on_device ? out->tags : dtag) : nullptr;
+  if (tg) {
+    if (e.tag_kind == TAG_F32) DL_HIP(hipMemcpyAsync(tg, R.full.tags.p, n * 4, hipMemcpyDeviceToDevice, st));
+    else if (e.tag_kind == TAG_NONE) fill_f32(tg, n, 1.0f, st);
+    else topk_probability(R.full.tags.as<TopK>(), e.batched ? samp_k : nullptr, n, e.qtab.as<float>(), tg, st);
+  }
+  uint8_t* oc = nullptr;
+  uint64_t* ob = nullptr;
+  float* op = nullptr;
+  if (e.tag_kind == TAG_TOPK) {
+    oc = out->topk_count ? (on_device ? out->topk_count : dcnt) : nullptr;
+    ob = out->topk_bits ? (on_device ? out->topk_bits : dbits) : nullptr;
+    op = out->topk_prob ? (on_device ? out->topk_prob : dprob) : nullptr;
+    if (oc || ob || op) topk_split(R.full.tags.as<TopK>(), n, e.k, oc, ob, op, st);
+  }
+  if (!on_device) {
+    auto d2h = [&](void* dst, const void* src, size_t bytes) {
+      if (dst) DL_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+    };
+    for (int c = 0; c < ar; ++c) d2h(out->columns[c], dcols[c], n * 4);
+    if (out->sample_ids) {
+      if (e.batched) d2h(out->sample_ids, dsample, n * 4);
+      else std::memset(out->sample_ids, 0, n * 4);
+    }
+    d2h(out->tags, dtag, n * 4);
+    if (e.tag_kind == TAG_TOPK) {
+      d2h(out->topk_count, dcnt, n);
+      d2h(out->topk_bits, dbits, (size_t)e.k * n * 8);
+      d2h(out->topk_prob, dprob, (size_t)e.k * n * 4);
+    }
+  }
+  e.sync();
+  return n;
+}
+
+template <typename K>
+void backward_t(Engine& e, int r, const float* gout) {
+  RelState& R = e.rel[r];
+  const size_t n = R.full.n;
+  hipStream_t st = e.stream;
+  if (e.sr == DL_DIFF_TOPK) {
+    uint32_t* samp = nullptr;
+    if (e.batched && n) {
+      e.grow(e.vals, n * 4);
+      samp = e.vals.as<uint32_t>();
+      uint32_t* cols[4] = {nullptr, nullptr, nullptr, nullptr};
+      unpack_rows<K>(R.full.keys.as<K>(), n, e.layout(e.prog.rels[r].arity), cols, samp, st);
+    }
+    topk_backward(R.full.tags.as<TopK>(), samp, gout, n, e.qtab.as<float>(), e.grad_fact.as<float>(), st);
+    return;
+  }
+  // diff add-mult: seed, sweep the recorded derivations in reverse, collect
+  const size_t ids = e.next_id;
+  e.grow(e.adj, ids * 4 + 4);
+  DL_HIP(hipMemsetAsync(e.adj.p, 0, ids * 4 + 4, st));
+  scatter_add(R.full.ids.as<uint32_t>(), gout, n, e.adj.as<float>(), st);
+  for (size_t i = e.lin_segs.size(); i-- > 0;) {
+    const LineageSeg& s = e.lin_segs[i];
+    lineage_backward(e.lin_owner.as<uint32_t>() + s.off, e.lin_l.as<uint32_t>() + s.off,
+                     e.lin_r.as<uint32_t>() + s.off, s.n, e.tag_by_id.as<float>(), e.adj.as<float>(), st);
+  }
+  for (size_t q = 0; q < e.rel.size(); ++q) {
+    if (!e.prog.rels[q].input || !e.rel[q].nraw) continue;
+    gather_add_clamped(e.rel[q].fact_entry.as<uint32_t>(), e.adj.as<float>(), e.tag_by_id.as<float>(),
+                       e.rel[q].nraw, e.rel[q].grad.as<float>(), st);
+  }
+}
+
+template void ingest<uint32_t>(Engine&);
+template void ingest<uint64_t>(Engine&);
+template void run_fixpoint<uint32_t>(Engine&);
+template void run_fixpoint<uint64_t>(Engine&);
+template size_t read_relation_t<uint32_t>(Engine&, int, size_t, const dl_relation_out*, int);
+template size_t read_relation_t<uint64_t>(Engine&, int, size_t, const dl_relation_out*, int);
+template void backward_t<uint32_t>(Engine&, int, const float*);
+template void backward_t<uint64_t>(Engine&, int, const float*);
+
+}  // namespace dlfix

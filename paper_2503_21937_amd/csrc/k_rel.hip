@@ -1,0 +1,719 @@
+// Relational kernels for gfx950: key packing, CSR index build, index join
+// (count / load-balanced expand with the offset tile staged in LDS, fused
+// column gather and x of the tags), +-reduction of equal keys, the
+// difference / +-merge against the full relation, merge-path merge, and the
+// tag and gradient kernels.
+#include "dl_device.h"
+#include "kernels.h"
+
+namespace dlfix {
+
+static unsigned grid_for(size_t n, size_t per_block = BLOCK) {
+  size_t b = (n + per_block - 1) / per_block;
+  return (unsigned)(b < 65536 ? (b ? b : 1) : 65536);
+}
+
+#define GRID_STRIDE(i, n) \
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
+
+// ------------------------------------------------------------ key helpers
+__device__ __forceinline__ uint32_t cmask(int cbits) { return (uint32_t)((1ull << cbits) - 1); }
+
+template <typename K>
+__device__ __forceinline__ uint32_t key_col(K key, int c, const KeyLayout& l) {
+  return (uint32_t)((uint64_t)key >> ((l.ncols - 1 - c) * l.cbits)) & cmask(l.cbits);
+}
+template <typename K>
+__device__ __forceinline__ uint32_t key_sample(K key, const KeyLayout& l) {
+  return l.sbits ? (uint32_t)((uint64_t)key >> (l.ncols * l.cbits)) : 0u;
+}
+template <typename K>
+__device__ __forceinline__ K key_make(uint32_t sample, const uint32_t* cols, const KeyLayout& l) {
+  uint64_t k = l.sbits ? (uint64_t)sample << (l.ncols * l.cbits) : 0ull;
+  for (int c = 0; c < l.ncols; ++c) k |= (uint64_t)cols[c] << ((l.ncols - 1 - c) * l.cbits);
+  return (K)k;
+}
+
+template <typename K>
+__global__ void k_pack(const uint32_t* c0, const uint32_t* c1, const uint32_t* c2, const uint32_t* c3,
+                       const uint32_t* sample, size_t n, KeyLayout l, K* keys) {
+  GRID_STRIDE(i, n) {
+    uint32_t v[4] = {c0 ? c0[i] : 0u, c1 ? c1[i] : 0u, c2 ? c2[i] : 0u, c3 ? c3[i] : 0u};
+    keys[i] = key_make<K>(sample ? sample[i] : 0u, v, l);
+  }
+}
+
+template <typename K>
+void pack_rows(const uint32_t* const* cols, const uint32_t* sample, size_t n, KeyLayout l, K* keys, hipStream_t st) {
+  if (!n) return;
+  const uint32_t* c[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int i = 0; i < l.ncols; ++i) c[i] = cols[i];
+  k_pack<K><<<grid_for(n), BLOCK, 0, st>>>(c[0], c[1], c[2], c[3], l.sbits ? sample : nullptr, n, l, keys);
+}
+
+template <typename K>
+__global__ void k_unpack(const K* keys, size_t n, KeyLayout l, uint32_t* c0, uint32_t* c1, uint32_t* c2, uint32_t* c3,
+                         uint32_t* sample) {
+  GRID_STRIDE(i, n) {
+    K k = keys[i];
+    if (c0) c0[i] = key_col(k, 0, l);
+    if (c1) c1[i] = key_col(k, 1, l);
+    if (c2) c2[i] = key_col(k, 2, l);
+    if (c3) c3[i] = key_col(k, 3, l);
+    if (sample) sample[i] = key_sample(k, l);
+  }
+}
+
+template <typename K>
+void unpack_rows(const K* keys, size_t n, KeyLayout l, uint32_t* const* cols, uint32_t* sample, hipStream_t st) {
+  if (!n) return;
+  uint32_t* c[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int i = 0; i < l.ncols; ++i) c[i] = cols[i];
+  k_unpack<K><<<grid_for(n), BLOCK, 0, st>>>(keys, n, l, c[0], c[1], c[2], c[3], sample);
+}
+
+struct Perm4 {
+  int p[4];
+};
+
+template <typename K>
+__global__ void k_permute(const K* in, size_t n, KeyLayout l, Perm4 perm, K* out) {
+  GRID_STRIDE(i, n) {
+    K k = in[i];
+    uint32_t v[4];
+    for (int c = 0; c < l.ncols; ++c) v[c] = key_col(k, perm.p[c], l);
+    out[i] = key_make<K>(key_sample(k, l), v, l);
+  }
+}
+
+template <typename K>
+void permute_keys(const K* in, size_t n, KeyLayout l, const int* perm, K* out, hipStream_t st) {
+  if (!n) return;
+  Perm4 p{{0, 0, 0, 0}};
+  for (int i = 0; i < l.ncols; ++i) p.p[i] = perm[i];
+  k_permute<K><<<grid_for(n), BLOCK, 0, st>>>(in, n, l, p, out);
+}
+
+// ------------------------------------------------------------------ CSR
+template <typename K>
+__global__ void k_csr(const K* __restrict__ keys, size_t n, int shift, uint64_t domain, uint32_t* __restrict__ off) {
+  GRID_STRIDE(v, domain + 1) {
+    size_t lo = 0, hi = n;  // first row with prefix >= v
+    while (lo < hi) {
+      size_t mid = (lo + hi) >> 1;
+      if (((uint64_t)keys[mid] >> shift) < v) lo = mid + 1;
+      else hi = mid;
+    }
+    off[v] = (uint32_t)lo;
+  }
+}
+
+template <typename K>
+void csr_build(const K* keys, size_t n, int total_bits, int prefix_bits, uint32_t* off, hipStream_t st) {
+  uint64_t domain = 1ull << prefix_bits;
+  k_csr<K><<<grid_for(domain + 1), BLOCK, 0, st>>>(keys, n, total_bits - prefix_bits, domain, off);
+}
+
+// ------------------------------------------------------------------ joins
+template <typename K>
+__device__ __forceinline__ uint64_t join_prefix(K dkey, const JoinArgs& a) {
+  uint64_t p = a.ilay.sbits ? (uint64_t)key_sample(dkey, a.dlay) << (a.w * a.ilay.cbits) : 0ull;
+  for (int j = 0; j < a.w; ++j) p |= (uint64_t)key_col(dkey, a.jsrc[j], a.dlay) << ((a.w - 1 - j) * a.ilay.cbits);
+  return p;
+}
+
+template <typename K>
+__global__ void k_join_count(JoinArgs a, uint32_t* __restrict__ counts) {
+  const K* dk = (const K*)a.dkeys;
+  GRID_STRIDE(i, a.n) {
+    uint64_t p = join_prefix(dk[i], a);
+    counts[i] = a.off[p + 1] - a.off[p];
+  }
+}
+
+template <typename K>
+void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st) {
+  if (a.n) k_join_count<K><<<grid_for(a.n), BLOCK, 0, st>>>(a, counts);
+}
+
+template <int TK>
+struct TagOf {
+  using T = NoTag;
+};
+template <>
+struct TagOf<TAG_F32> {
+  using T = float;
+};
+template <>
+struct TagOf<TAG_TOPK> {
+  using T = TopK;
+};
+
+template <int TK>
+__device__ __forceinline__ typename TagOf<TK>::T tag_otimes(const typename TagOf<TK>::T& x,
+                                                           const typename TagOf<TK>::T& y, const JoinArgs& a,
+                                                           uint32_t sample) {
+  if constexpr (TK == TAG_F32) {
+    return f_otimes(a.sr, x, y);
+  } else if constexpr (TK == TAG_TOPK) {
+    return topk_otimes(x, y, a.k, a.q + (size_t)sample * 64);
+  } else {
+    return NoTag{};
+  }
+}
+
+constexpr int EXP_ITEMS = 4;
+constexpr int EXP_TILE = BLOCK * EXP_ITEMS;
+constexpr int EXP_LDS = 2 * EXP_TILE;
+
+__device__ __forceinline__ size_t upper_bound_u32(const uint32_t* a, size_t n, uint32_t x) {
+  size_t lo = 0, hi = n;
+  while (lo < hi) {
+    size_t mid = (lo + hi) >> 1;
+    if (a[mid] <= x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename K, int TK>
+__global__ __launch_bounds__(BLOCK) void k_join_expand(JoinArgs a, const uint32_t* __restrict__ offs, size_t total,
+                                                       K* __restrict__ okeys, typename TagOf<TK>::T* __restrict__ otags,
+                                                       uint32_t* __restrict__ ol, uint32_t* __restrict__ orr) {
+  using T = typename TagOf<TK>::T;
+  __shared__ uint32_t s_off[EXP_LDS];
+  __shared__ size_t s_r0, s_r1;
+  const K* dk = (const K*)a.dkeys;
+  const K* ik = (const K*)a.ikeys;
+  const T* dt = (const T*)a.dtags;
+  const T* it = (const T*)a.itags;
+  const size_t s0 = (size_t)blockIdx.x * EXP_TILE;
+  const size_t s1 = s0 + EXP_TILE < total ? s0 + EXP_TILE : total;  // exclusive
+  if (threadIdx.x == 0) {
+    s_r0 = upper_bound_u32(offs, a.n + 1, (uint32_t)s0) - 1;
+    s_r1 = upper_bound_u32(offs, a.n + 1, (uint32_t)(s1 - 1)) - 1;
+  }
+  __syncthreads();
+  const size_t r0 = s_r0, r1 = s_r1;
+  const size_t span = r1 - r0 + 2;  // offs[r0 .. r1+1]
+  const bool staged = span <= (size_t)EXP_LDS;
+  if (staged)
+    for (size_t i = threadIdx.x; i < span; i += BLOCK) s_off[i] = offs[r0 + i];
+  __syncthreads();
+#pragma unroll
+  for (int it_ = 0; it_ < EXP_ITEMS; ++it_) {
+    const size_t j = s0 + (size_t)it_ * BLOCK + threadIdx.x;
+    if (j >= s1) break;
+    size_t row;
+    uint32_t base;
+    if (staged) {
+      size_t u = upper_bound_u32(s_off, span, (uint32_t)j);
+      row = r0 + u - 1;
+      base = s_off[u - 1];
+    } else {
+      size_t u = upper_bound_u32(offs + r0, span, (uint32_t)j);
+      row = r0 + u - 1;
+      base = offs[row];
+    }
+    const K dkey = dk[row];
+    const uint64_t p = join_prefix(dkey, a);
+    const uint32_t irow = a.off[p] + ((uint32_t)j - base);
+    const K ikey = ik[irow];
+    uint32_t v[4];
+    for (int c = 0; c < a.olay.ncols; ++c) {
+      int s = a.osrc[c];
+      v[c] = s >= 0 ? key_col(dkey, s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
+    }
+    const uint32_t sample = key_sample(dkey, a.dlay);
+    okeys[j] = key_make<K>(sample, v, a.olay);
+    if constexpr (TK != TAG_NONE) {
+      T x = dt[row], y = it[irow];
+      otags[j] = a.index_first ? tag_otimes<TK>(y, x, a, sample) : tag_otimes<TK>(x, y, a, sample);
+    }
+    if (ol) {
+      ol[j] = a.dids[row];
+      orr[j] = a.iids[irow];
+    }
+  }
+}
+
+template <typename K>
+void join_expand(const JoinArgs& a, int tk, const uint32_t* offs, size_t total, void* okeys, void* otags, uint32_t* ol,
+                 uint32_t* orr, hipStream_t st) {
+  if (!total) return;
+  size_t nb = (total + EXP_TILE - 1) / EXP_TILE;
+  if (tk == TAG_NONE)
+    k_join_expand<K, TAG_NONE><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (NoTag*)otags, ol, orr);
+  else if (tk == TAG_F32)
+    k_join_expand<K, TAG_F32><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (float*)otags, ol, orr);
+  else
+    k_join_expand<K, TAG_TOPK><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (TopK*)otags, ol, orr);
+}
+
+template <typename K, int TK>
+__global__ void k_project(JoinArgs a, K* __restrict__ okeys, typename TagOf<TK>::T* __restrict__ otags,
+                          uint32_t* __restrict__ ol, uint32_t* __restrict__ orr) {
+  using T = typename TagOf<TK>::T;
+  const K* dk = (const K*)a.dkeys;
+  GRID_STRIDE(i, a.n) {
+    K dkey = dk[i];
+    uint32_t v[4];
+    for (int c = 0; c < a.olay.ncols; ++c) v[c] = key_col(dkey, a.osrc[c], a.dlay);
+    okeys[i] = key_make<K>(key_sample(dkey, a.dlay), v, a.olay);
+    if constexpr (TK != TAG_NONE) otags[i] = ((const T*)a.dtags)[i];
+    if (ol) {
+      ol[i] = a.dids[i];
+      orr[i] = ~0u;
+    }
+  }
+}
+
+template <typename K>
+void project_rows(const JoinArgs& a, int tk, void* okeys, void* otags, uint32_t* ol, uint32_t* orr, hipStream_t st) {
+  if (!a.n) return;
+  if (tk == TAG_NONE)
+    k_project<K, TAG_NONE><<<grid_for(a.n), BLOCK, 0, st>>>(a, (K*)okeys, (NoTag*)otags, ol, orr);
+  else if (tk == TAG_F32)
+    k_project<K, TAG_F32><<<grid_for(a.n), BLOCK, 0, st>>>(a, (K*)okeys, (float*)otags, ol, orr);
+  else
+    k_project<K, TAG_TOPK><<<grid_for(a.n), BLOCK, 0, st>>>(a, (K*)okeys, (TopK*)otags, ol, orr);
+}
+
+// ------------------------------------------------------------- reduction
+template <typename K>
+__global__ void k_head_flags(const K* __restrict__ keys, size_t n, uint32_t* __restrict__ flags) {
+  GRID_STRIDE(i, n) flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+template <typename K>
+void head_flags(const K* keys, size_t n, uint32_t* flags, hipStream_t st) {
+  if (n) k_head_flags<K><<<grid_for(n), BLOCK, 0, st>>>(keys, n, flags);
+}
+
+template <typename K, int TK>
+__global__ void k_segment_reduce(const K* __restrict__ keys, const uint32_t* __restrict__ pos,
+                                 const uint32_t* __restrict__ flags, size_t n, int sr, int k,
+                                 const typename TagOf<TK>::T* __restrict__ tags, const uint32_t* __restrict__ perm,
+                                 K* __restrict__ kout, typename TagOf<TK>::T* __restrict__ tout) {
+  using T = typename TagOf<TK>::T;
+  GRID_STRIDE(i, n) {
+    if (!flags[i]) continue;
+    const uint32_t s = pos[i];
+    kout[s] = keys[i];
+    if constexpr (TK != TAG_NONE) {
+      T acc = tags[perm ? perm[i] : i];
+      for (size_t j = i + 1; j < n && !flags[j]; ++j) {
+        T x = tags[perm ? perm[j] : j];
+        if constexpr (TK == TAG_F32) acc = f_oplus(sr, acc, x);
+        else acc = topk_oplus(acc, x, k);
+      }
+      tout[s] = acc;
+    }
+  }
+}
+
+template <typename K>
+void segment_reduce(const K* keys, const uint32_t* pos, const uint32_t* flags, size_t n, int tk, int sr, int k,
+                    const void* tags, const uint32_t* perm, K* kout, void* tout, hipStream_t st) {
+  if (!n) return;
+  if (tk == TAG_NONE)
+    k_segment_reduce<K, TAG_NONE><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const NoTag*)tags, perm,
+                                                                 kout, (NoTag*)tout);
+  else if (tk == TAG_F32)
+    k_segment_reduce<K, TAG_F32><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const float*)tags, perm,
+                                                                kout, (float*)tout);
+  else
+    k_segment_reduce<K, TAG_TOPK><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const TopK*)tags, perm,
+                                                                 kout, (TopK*)tout);
+}
+
+// ------------------------------------------------- difference / +-merge
+constexpr int DIFF_ITEMS = 4;
+constexpr int DIFF_TILE = BLOCK * DIFF_ITEMS;
+constexpr int DIFF_LDS = 4096;
+
+template <typename K>
+__device__ __forceinline__ size_t lower_bound_k(const K* a, size_t lo, size_t hi, K x) {
+  while (lo < hi) {
+    size_t mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename K, int TK>
+__global__ __launch_bounds__(BLOCK) void k_diff(const K* __restrict__ uk, typename TagOf<TK>::T* __restrict__ ut,
+                                                size_t nu, const K* __restrict__ fk,
+                                                typename TagOf<TK>::T* __restrict__ ft, size_t nf, int sr, int k,
+                                                int converge, uint32_t* __restrict__ status,
+                                                uint32_t* __restrict__ fpos) {
+  using T = typename TagOf<TK>::T;
+  __shared__ K s_f[DIFF_LDS];
+  __shared__ size_t s_lo, s_hi;
+  const size_t u0 = (size_t)blockIdx.x * DIFF_TILE;
+  const size_t u1 = u0 + DIFF_TILE < nu ? u0 + DIFF_TILE : nu;
+  if (threadIdx.x == 0) {
+    s_lo = lower_bound_k(fk, 0, nf, uk[u0]);
+    size_t hi = lower_bound_k(fk, s_lo, nf, uk[u1 - 1]);
+    s_hi = hi < nf ? hi + 1 : nf;  // include the possible match of the last key
+  }
+  __syncthreads();
+  const size_t lo = s_lo, hi = s_hi, span = hi - lo;
+  const bool staged = span <= (size_t)DIFF_LDS;
+  if (staged)
+    for (size_t i = threadIdx.x; i < span; i += BLOCK) s_f[i] = fk[lo + i];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < DIFF_ITEMS; ++r) {
+    const size_t i = u0 + (size_t)r * BLOCK + threadIdx.x;
+    if (i >= u1) break;
+    const K key = uk[i];
+    size_t f;
+    bool found;
+    if (staged) {
+      size_t l = lower_bound_k(s_f, 0, span, key);
+      f = lo + l;
+      found = l < span && s_f[l] == key;
+    } else {
+      f = lower_bound_k(fk, lo, hi, key);
+      found = f < hi && fk[f] == key;
+    }
+    if (fpos) fpos[i] = (uint32_t)f;
+    uint32_t s = found ? 0u : 1u;
+    if constexpr (TK != TAG_NONE) {
+      if (found && converge) {
+        T old = ft[f];
+        T nw;
+        if constexpr (TK == TAG_F32) {
+          nw = f_oplus(sr, old, ut[i]);
+          if (__float_as_uint(nw) != __float_as_uint(old)) s = 2u;
+        } else {
+          nw = topk_oplus(old, ut[i], k);
+          if (!topk_same(nw, old)) s = 2u;
+        }
+        if (s == 2u) {
+          ft[f] = nw;
+          ut[i] = nw;
+        }
+      }
+    }
+    status[i] = s;
+  }
+}
+
+template <typename K>
+void diff_merge(const K* uk, const void* ut, size_t nu, const K* fk, void* ft, size_t nf, int tk, int sr, int k,
+                bool converge, uint32_t* status, uint32_t* fpos, hipStream_t st) {
+  if (!nu) return;
+  size_t nb = (nu + DIFF_TILE - 1) / DIFF_TILE;
+  if (tk == TAG_NONE)
+    k_diff<K, TAG_NONE><<<nb, BLOCK, 0, st>>>(uk, (NoTag*)ut, nu, fk, (NoTag*)ft, nf, sr, k, converge, status, fpos);
+  else if (tk == TAG_F32)
+    k_diff<K, TAG_F32><<<nb, BLOCK, 0, st>>>(uk, (float*)ut, nu, fk, (float*)ft, nf, sr, k, converge, status, fpos);
+  else
+    k_diff<K, TAG_TOPK><<<nb, BLOCK, 0, st>>>(uk, (TopK*)ut, nu, fk, (TopK*)ft, nf, sr, k, converge, status, fpos);
+}
+
+// ------------------------------------------------------------ merge path
+constexpr int MERGE_ITEMS = 8;
+constexpr int MERGE_TILE = BLOCK * MERGE_ITEMS;
+
+size_t merge_scratch_words(size_t na, size_t nb) { return (na + nb + MERGE_TILE - 1) / MERGE_TILE + 2; }
+
+// Number of A elements among the first `diag` outputs (A first on ties).
+template <typename K>
+__device__ __forceinline__ size_t merge_path(const K* a, size_t na, const K* b, size_t nb, size_t diag) {
+  size_t lo = diag > nb ? diag - nb : 0;
+  size_t hi = diag < na ? diag : na;
+  while (lo < hi) {
+    size_t mid = (lo + hi) >> 1;
+    if (a[mid] <= b[diag - 1 - mid]) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename K>
+__global__ void k_merge_partition(const K* a, size_t na, const K* b, size_t nb, size_t ntiles, uint64_t* split) {
+  GRID_STRIDE(t, ntiles + 1) {
+    size_t diag = t * (size_t)MERGE_TILE;
+    if (diag > na + nb) diag = na + nb;
+    split[t] = merge_path(a, na, b, nb, diag);
+  }
+}
+
+template <typename K>
+__global__ __launch_bounds__(BLOCK) void k_merge(const K* __restrict__ ak, const uint8_t* __restrict__ at,
+                                                 const uint32_t* __restrict__ aid, size_t na,
+                                                 const K* __restrict__ bk, const uint8_t* __restrict__ bt,
+                                                 const uint32_t* __restrict__ bid, size_t nb, int tag_bytes,
+                                                 const uint64_t* __restrict__ split, K* __restrict__ ok,
+                                                 uint8_t* __restrict__ ot, uint32_t* __restrict__ oid) {
+  __shared__ K s_k[MERGE_TILE];
+  __shared__ uint16_t s_src[MERGE_TILE];
+  const size_t t = blockIdx.x;
+  const size_t d0 = t * (size_t)MERGE_TILE;
+  const size_t d1 = d0 + MERGE_TILE < na + nb ? d0 + MERGE_TILE : na + nb;
+  const size_t a0 = split[t], a1 = split[t + 1];
+  const size_t b0 = d0 - a0, b1 = d1 - a1;
+  const int nta = (int)(a1 - a0), ntb = (int)(b1 - b0), cnt = nta + ntb;
+  for (int i = threadIdx.x; i < nta; i += BLOCK) s_k[i] = ak[a0 + i];
+  for (int i = threadIdx.x; i < ntb; i += BLOCK) s_k[nta + i] = bk[b0 + i];
+  __syncthreads();
+  const K* sa = s_k;
+  const K* sb = s_k + nta;
+  const int d = threadIdx.x * MERGE_ITEMS;
+  uint16_t mine[MERGE_ITEMS];
+  if (d < cnt) {
+    int lo = d > ntb ? d - ntb : 0, hi = d < nta ? d : nta;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (sa[mid] <= sb[d - 1 - mid]) lo = mid + 1;
+      else hi = mid;
+    }
+    int ai = lo, bi = d - lo;
+#pragma unroll
+    for (int s = 0; s < MERGE_ITEMS; ++s) {
+      if (d + s >= cnt) break;
+      bool takeA = bi >= ntb || (ai < nta && sa[ai] <= sb[bi]);
+      mine[s] = takeA ? (uint16_t)ai++ : (uint16_t)(nta + bi++);
+    }
+  }
+  __syncthreads();
+  if (d < cnt) {
+#pragma unroll
+    for (int s = 0; s < MERGE_ITEMS; ++s)
+      if (d + s < cnt) s_src[d + s] = mine[s];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += BLOCK) {
+    const int src = s_src[i];
+    const size_t o = d0 + i;
+    ok[o] = s_k[src];
+    const bool fromA = src < nta;
+    const size_t g = fromA ? a0 + src : b0 + (src - nta);
+    if (oid) oid[o] = fromA ? aid[g] : bid[g];
+    if (tag_bytes == 4) {
+      reinterpret_cast<uint32_t*>(ot)[o] = reinterpret_cast<const uint32_t*>(fromA ? at : bt)[g];
+    } else if (tag_bytes == (int)sizeof(TopK)) {
+      reinterpret_cast<TopK*>(ot)[o] = reinterpret_cast<const TopK*>(fromA ? at : bt)[g];
+    }
+  }
+}
+
+template <typename K>
+void merge_sorted(const K* ak, const void* at, const uint32_t* aid, size_t na, const K* bk, const void* bt,
+                  const uint32_t* bid, size_t nb, size_t tag_bytes, K* ok, void* ot, uint32_t* oid, uint64_t* scratch,
+                  hipStream_t st) {
+  if (na + nb == 0) return;
+  size_t ntiles = (na + nb + MERGE_TILE - 1) / MERGE_TILE;
+  k_merge_partition<K><<<grid_for(ntiles + 1), BLOCK, 0, st>>>(ak, na, bk, nb, ntiles, scratch);
+  k_merge<K><<<ntiles, BLOCK, 0, st>>>(ak, (const uint8_t*)at, aid, na, bk, (const uint8_t*)bt, bid, nb, (int)tag_bytes,
+                                      scratch, ok, (uint8_t*)ot, oid);
+}
+
+// ---------------------------------------------------------------- lineage
+__global__ void k_lineage_flags(const uint32_t* __restrict__ pos, const uint32_t* __restrict__ flags,
+                                const uint32_t* __restrict__ status, size_t n, uint32_t* __restrict__ lf) {
+  GRID_STRIDE(p, n) lf[p] = status[pos[p] + flags[p] - 1] & 1u;
+}
+
+void lineage_flags(const uint32_t* pos, const uint32_t* flags, const uint32_t* status, size_t n, uint32_t* lf,
+                   hipStream_t st) {
+  if (n) k_lineage_flags<<<grid_for(n), BLOCK, 0, st>>>(pos, flags, status, n, lf);
+}
+
+__global__ void k_lineage_emit(const uint32_t* __restrict__ pos, const uint32_t* __restrict__ flags,
+                               const uint32_t* __restrict__ lf, const uint32_t* __restrict__ lpos,
+                               const uint32_t* __restrict__ newpos, const uint32_t* __restrict__ perm,
+                               const uint32_t* __restrict__ cl, const uint32_t* __restrict__ cr, size_t n,
+                               uint32_t id_base, uint32_t* __restrict__ owner, uint32_t* __restrict__ l,
+                               uint32_t* __restrict__ r) {
+  GRID_STRIDE(p, n) {
+    if (!lf[p]) continue;
+    uint32_t s = pos[p] + flags[p] - 1;
+    uint32_t o = lpos[p];
+    uint32_t c = perm[p];
+    owner[o] = id_base + newpos[s];
+    l[o] = cl[c];
+    r[o] = cr[c];
+  }
+}
+
+void lineage_emit(const uint32_t* pos, const uint32_t* flags, const uint32_t* lf, const uint32_t* lpos,
+                  const uint32_t* newpos, const uint32_t* perm, const uint32_t* cl, const uint32_t* cr, size_t n,
+                  uint32_t id_base, uint32_t* owner, uint32_t* l, uint32_t* r, hipStream_t st) {
+  if (n)
+    k_lineage_emit<<<grid_for(n), BLOCK, 0, st>>>(pos, flags, lf, lpos, newpos, perm, cl, cr, n, id_base, owner, l,
+                                                  r);
+}
+
+__global__ void k_seg_scatter(const uint32_t* __restrict__ pos, const uint32_t* __restrict__ flags,
+                              const uint32_t* __restrict__ perm, size_t n, uint32_t base, uint32_t* __restrict__ out) {
+  GRID_STRIDE(p, n) out[perm[p]] = base + pos[p] + flags[p] - 1;
+}
+
+void seg_scatter(const uint32_t* pos, const uint32_t* flags, const uint32_t* perm, size_t n, uint32_t base,
+                 uint32_t* out, hipStream_t st) {
+  if (n) k_seg_scatter<<<grid_for(n), BLOCK, 0, st>>>(pos, flags, perm, n, base, out);
+}
+
+// ------------------------------------------------------------- gradients
+__global__ void k_lineage_backward(const uint32_t* __restrict__ owner, const uint32_t* __restrict__ l,
+                                   const uint32_t* __restrict__ r, size_t n, const float* __restrict__ tag,
+                                   float* adj) {
+  GRID_STRIDE(i, n) {
+    const uint32_t o = owner[i];
+    if (!(tag[o] < 1.0f)) continue;  // clamp: d min(1, s)/ds = 0 once s >= 1
+    const float g = adj[o];
+    if (g == 0.0f) continue;
+    const uint32_t a = l[i], b = r[i];
+    if (b == ~0u) {
+      atomicAdd(&adj[a], g);
+    } else {
+      atomicAdd(&adj[a], __fmul_rn(g, tag[b]));
+      atomicAdd(&adj[b], __fmul_rn(g, tag[a]));
+    }
+  }
+}
+
+void lineage_backward(const uint32_t* owner, const uint32_t* l, const uint32_t* r, size_t n, const float* tag,
+                      float* adj, hipStream_t st) {
+  if (n) k_lineage_backward<<<grid_for(n), BLOCK, 0, st>>>(owner, l, r, n, tag, adj);
+}
+
+__global__ void k_scatter_add(const uint32_t* __restrict__ ids, const float* __restrict__ g, size_t n, float* adj) {
+  GRID_STRIDE(i, n) atomicAdd(&adj[ids[i]], g[i]);
+}
+
+void scatter_add(const uint32_t* ids, const float* g, size_t n, float* adj, hipStream_t st) {
+  if (n) k_scatter_add<<<grid_for(n), BLOCK, 0, st>>>(ids, g, n, adj);
+}
+
+__global__ void k_gather_add_clamped(const uint32_t* __restrict__ ids, const float* __restrict__ adj,
+                                     const float* __restrict__ tag, size_t n, float* __restrict__ out) {
+  GRID_STRIDE(i, n) {
+    uint32_t id = ids[i];
+    if (tag[id] < 1.0f) out[i] += adj[id];
+  }
+}
+
+void gather_add_clamped(const uint32_t* ids, const float* adj, const float* tag, size_t n, float* out, hipStream_t st) {
+  if (n) k_gather_add_clamped<<<grid_for(n), BLOCK, 0, st>>>(ids, adj, tag, n, out);
+}
+
+// ------------------------------------------------------------------ top-k
+__global__ void k_topk_from_facts(const float* __restrict__ q, const uint32_t* __restrict__ local, size_t n,
+                                  TopK* __restrict__ out) {
+  GRID_STRIDE(i, n) {
+    TopK t = topk_empty();
+    t.cnt = 1;
+    t.b[0] = 1ull << local[i];
+    t.p[0] = q[i];
+    out[i] = t;
+  }
+}
+
+void topk_from_facts(const float* q, const uint32_t* local, size_t n, TopK* out, hipStream_t st) {
+  if (n) k_topk_from_facts<<<grid_for(n), BLOCK, 0, st>>>(q, local, n, out);
+}
+
+// P = sum over non-empty subsets S of the kept proofs of (-1)^(|S|+1) times
+// the product of the probabilities of the facts in their union.
+__device__ double incl_excl(const TopK& t, const float* q, int skip_bit, double* dP) {
+  double P = 0;
+  for (uint32_t S = 1; S < (1u << t.cnt); ++S) {
+    uint64_t u = 0;
+    for (uint32_t i = 0; i < t.cnt; ++i)
+      if (S >> i & 1u) u |= t.b[i];
+    double prod = 1.0;
+    uint64_t b = u;
+    while (b) {
+      int i = __builtin_ctzll(b);
+      if (i != skip_bit) prod *= (double)q[i];
+      b &= b - 1;
+    }
+    double sign = (__popc(S) & 1) ? 1.0 : -1.0;
+    if (skip_bit < 0) P += sign * prod;
+    else if (u >> skip_bit & 1ull) *dP += sign * prod;
+  }
+  return P;
+}
+
+__global__ void k_topk_prob(const TopK* __restrict__ t, const uint32_t* __restrict__ sample, size_t n,
+                            const float* __restrict__ qtab, float* __restrict__ prob) {
+  GRID_STRIDE(i, n) {
+    const float* q = qtab + (size_t)(sample ? sample[i] : 0u) * 64;
+    prob[i] = (float)incl_excl(t[i], q, -1, nullptr);
+  }
+}
+
+void topk_probability(const TopK* t, const uint32_t* sample, size_t n, const float* qtab, float* prob,
+                      hipStream_t st) {
+  if (n) k_topk_prob<<<grid_for(n), BLOCK, 0, st>>>(t, sample, n, qtab, prob);
+}
+
+__global__ void k_topk_split(const TopK* __restrict__ t, size_t n, int k, uint8_t* cnt, uint64_t* bits, float* prob) {
+  GRID_STRIDE(i, n) {
+    TopK x = t[i];
+    if (cnt) cnt[i] = (uint8_t)x.cnt;
+    for (int j = 0; j < k; ++j) {
+      if (bits) bits[(size_t)j * n + i] = (uint32_t)j < x.cnt ? x.b[j] : 0ull;
+      if (prob) prob[(size_t)j * n + i] = (uint32_t)j < x.cnt ? x.p[j] : 0.0f;
+    }
+  }
+}
+
+void topk_split(const TopK* t, size_t n, int k, uint8_t* cnt, uint64_t* bits, float* prob, hipStream_t st) {
+  if (n) k_topk_split<<<grid_for(n), BLOCK, 0, st>>>(t, n, k, cnt, bits, prob);
+}
+
+__global__ void k_topk_backward(const TopK* __restrict__ t, const uint32_t* __restrict__ sample,
+                                const float* __restrict__ gout, size_t n, const float* __restrict__ qtab,
+                                float* grad) {
+  GRID_STRIDE(i, n) {
+    const float g = gout[i];
+    if (g == 0.0f) continue;
+    const TopK x = t[i];
+    const uint32_t s = sample ? sample[i] : 0u;
+    const float* q = qtab + (size_t)s * 64;
+    uint64_t all = 0;
+    for (uint32_t j = 0; j < x.cnt; ++j) all |= x.b[j];
+    while (all) {
+      int bit = __builtin_ctzll(all);
+      all &= all - 1;
+      double d = 0;
+      incl_excl(x, q, bit, &d);
+      atomicAdd(&grad[(size_t)s * 64 + bit], (float)((double)g * d));
+    }
+  }
+}
+
+void topk_backward(const TopK* t, const uint32_t* sample, const float* gout, size_t n, const float* qtab,
+                   float* grad, hipStream_t st) {
+  if (n) k_topk_backward<<<grid_for(n), BLOCK, 0, st>>>(t, sample, gout, n, qtab, grad);
+}
+
+// ------------------------------------------------------- instantiations
+#define INST(K)                                                                                                      \
+  template void pack_rows<K>(const uint32_t* const*, const uint32_t*, size_t, KeyLayout, K*, hipStream_t);         \
+  template void unpack_rows<K>(const K*, size_t, KeyLayout, uint32_t* const*, uint32_t*, hipStream_t);             \
+  template void permute_keys<K>(const K*, size_t, KeyLayout, const int*, K*, hipStream_t);                        \
+  template void csr_build<K>(const K*, size_t, int, int, uint32_t*, hipStream_t);                                   \
+  template void join_count<K>(const JoinArgs&, uint32_t*, hipStream_t);                                             \
+  template void join_expand<K>(const JoinArgs&, int, const uint32_t*, size_t, void*, void*, uint32_t*, uint32_t*,   \
+                               hipStream_t);                                                                         \
+  template void project_rows<K>(const JoinArgs&, int, void*, void*, uint32_t*, uint32_t*, hipStream_t);             \
+  template void head_flags<K>(const K*, size_t, uint32_t*, hipStream_t);                                            \
+  template void segment_reduce<K>(const K*, const uint32_t*, const uint32_t*, size_t, int, int, int, const void*,  \
+                                  const uint32_t*, K*, void*, hipStream_t);                                          \
+  template void diff_merge<K>(const K*, const void*, size_t, const K*, void*, size_t, int, int, int, bool,          \
+                              uint32_t*, uint32_t*, hipStream_t);                                                   \
+  template void merge_sorted<K>(const K*, const void*, const uint32_t*, size_t, const K*, const void*,              \
+                                const uint32_t*, size_t, size_t, K*, void*, uint32_t*, uint64_t*, hipStream_t);
+
+INST(uint32_t)
+INST(uint64_t)
+
+}  // namespace dlfix

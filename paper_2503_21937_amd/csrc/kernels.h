@@ -1,0 +1,166 @@
+// Host-callable launchers of the gfx950 kernels.  Every launcher enqueues on
+// `st` and never synchronises; sizes are host values.  Device pointers only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dlfix {
+
+struct TopK;
+
+// ------------------------------------------------------------- primitives
+// Scratch words a scan of n values needs (u64 units).
+size_t scan_scratch_words(size_t n);
+// Exclusive prefix sum of n u32 counts (in may equal out).  The 64-bit total
+// goes to *d_total; if `sentinel`, out[n] receives the (truncated) total.
+void scan_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* d_total, bool sentinel,
+              uint64_t* scratch, hipStream_t st);
+
+// Stable LSD radix sort of (key, value) pairs on the low `key_bits` bits.
+// Sorted data ends in (*keys, *vals); the alternates are used as ping-pong
+// buffers and the pointers are swapped as needed.  vals may be NULL.
+size_t radix_scratch_words(size_t n);
+template <typename K>
+void radix_sort(K** keys, uint32_t** vals, K** keys_alt, uint32_t** vals_alt, size_t n, int key_bits,
+                uint64_t* scratch, hipStream_t st);
+
+void iota_u32(uint32_t* out, size_t n, uint32_t start, hipStream_t st);
+void fill_u32(uint32_t* out, size_t n, uint32_t v, hipStream_t st);
+void fill_f32(float* out, size_t n, float v, hipStream_t st);
+// out[i] = in[idx[i]] for element size `bytes` in {4, 8, sizeof(TopK)}.
+void gather(const void* in, const uint32_t* idx, void* out, size_t n, size_t bytes, hipStream_t st);
+// Max over n u32 values into *d_out (atomic max; *d_out must be initialised).
+void max_u32(const uint32_t* in, size_t n, uint32_t* d_out, hipStream_t st);
+
+// ---------------------------------------------------------- relations
+struct KeyLayout {  // packed key: [sample | c0 | c1 | ...], c0 most significant
+  int ncols;
+  int cbits;
+  int sbits;
+};
+
+template <typename K>
+void pack_rows(const uint32_t* const* cols, const uint32_t* sample, size_t n, KeyLayout lay, K* keys,
+               hipStream_t st);
+template <typename K>
+void unpack_rows(const K* keys, size_t n, KeyLayout lay, uint32_t* const* cols, uint32_t* sample,
+                 hipStream_t st);
+// Re-pack keys with a column permutation (out column j = in column perm[j]).
+template <typename K>
+void permute_keys(const K* in, size_t n, KeyLayout lay, const int* perm, K* out, hipStream_t st);
+
+// CSR offsets over the top `prefix_bits` bits (below `total_bits`) of sorted
+// keys: off[v] = first row whose prefix >= v, for v in [0, 2^prefix_bits].
+template <typename K>
+void csr_build(const K* keys, size_t n, int total_bits, int prefix_bits, uint32_t* off, hipStream_t st);
+
+// Tag payload kinds of the relational kernels.
+enum TagKind : int { TAG_NONE = 0, TAG_F32 = 1, TAG_TOPK = 2 };
+
+struct JoinArgs {
+  // driver table
+  const void* dkeys;
+  const void* dtags;
+  const uint32_t* dids;
+  size_t n;
+  KeyLayout dlay;
+  // join prefix: driver columns forming the index prefix, in index key order
+  int w;
+  int jsrc[4];
+  // index
+  const uint32_t* off;
+  const void* ikeys;
+  const void* itags;
+  const uint32_t* iids;
+  KeyLayout ilay;
+  // output
+  KeyLayout olay;
+  int osrc[4];  // >= 0: driver column, < 0: index column (-1 - c)
+  int sr;       // SemiringKind
+  int k;        // top-k proof count
+  const float* q;  // top-k: per-sample probabilities [sample][64]
+  bool index_first;  // x operand order: index tag first (body order)
+};
+
+// counts[i] = number of index rows matching driver row i.
+template <typename K>
+void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st);
+// Emit every match: slot j of row i (offs = exclusive scan of counts, with
+// sentinel).  Writes keys (and tags, lineage pairs if non-NULL) at out + j.
+template <typename K>
+void join_expand(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t total, void* okeys, void* otags,
+                 uint32_t* olin_l, uint32_t* olin_r, hipStream_t st);
+// Single-atom rule: re-pack driver columns as head columns, copy tags.
+template <typename K>
+void project_rows(const JoinArgs& a, int tag_kind, void* okeys, void* otags, uint32_t* olin_l, uint32_t* olin_r,
+                  hipStream_t st);
+
+// Segment heads of sorted keys: flags[i] = 1 iff i == 0 or key[i] != key[i-1].
+template <typename K>
+void head_flags(const K* keys, size_t n, uint32_t* flags, hipStream_t st);
+// Reduce every run of equal keys (heads given by pos = exclusive scan of
+// flags) to one row: keys_out[s], tag = +-fold in sorted order.  Tags are
+// read through `perm` (sorted position -> candidate index) when non-NULL.
+template <typename K>
+void segment_reduce(const K* keys, const uint32_t* pos, const uint32_t* flags, size_t n, int tag_kind, int sr, int k,
+                    const void* tags, const uint32_t* perm, K* keys_out, void* tags_out, hipStream_t st);
+
+// For every unique candidate (sorted, distinct) find its key in the sorted
+// full relation.  Converging semirings +-merge the tag into full in place.
+// status[i]: 1 = new, 2 = tag changed, 0 = nothing to do.
+template <typename K>
+void diff_merge(const K* ukeys, const void* utags, size_t nu, const K* fkeys, void* ftags, size_t nf, int tag_kind,
+                int sr, int k, bool converge, uint32_t* status, uint32_t* fpos, hipStream_t st);
+
+// out[pos[i]] = in[i] where flag[i] (pos = exclusive scan of flags).
+void compact(const void* in, const uint32_t* flags, const uint32_t* pos, size_t n, size_t bytes, void* out,
+             hipStream_t st);
+// flags[i] = (status[i] & mask) != 0
+void status_flags(const uint32_t* status, size_t n, uint32_t mask, uint32_t* flags, hipStream_t st);
+
+// Merge two sorted, disjoint relations (keys + payload) into out.
+size_t merge_scratch_words(size_t na, size_t nb);
+template <typename K>
+void merge_sorted(const K* ak, const void* at, const uint32_t* aid, size_t na, const K* bk, const void* bt,
+                  const uint32_t* bid, size_t nb, size_t tag_bytes, K* ok, void* ot, uint32_t* oid,
+                  uint64_t* scratch, hipStream_t st);
+
+// out[perm[p]] = base + (run index of sorted position p), run index =
+// pos[p] + flags[p] - 1 (maps every input fact to its merged entry).
+void seg_scatter(const uint32_t* pos, const uint32_t* flags, const uint32_t* perm, size_t n, uint32_t base,
+                 uint32_t* out, hipStream_t st);
+
+// ---------------------------------------------------------- tags & grads
+// Input facts -> tags: f32 copy (bool: none); top-k: [(1 << local_id, q)].
+void topk_from_facts(const float* q, const uint32_t* local_id, size_t n, TopK* out, hipStream_t st);
+// Inclusion-exclusion probability of each row's kept proofs (binary64).
+void topk_probability(const TopK* t, const uint32_t* sample, size_t n, const float* qtab, float* prob,
+                      hipStream_t st);
+void topk_split(const TopK* t, size_t n, int k, uint8_t* cnt, uint64_t* bits, float* prob, hipStream_t st);
+// grad of the inclusion-exclusion probability w.r.t. fact probabilities,
+// scattered into grad_fact[sample*64 + bit].
+void topk_backward(const TopK* t, const uint32_t* sample, const float* gout, size_t n, const float* qtab,
+                   float* grad_fact, hipStream_t st);
+
+// Add-mult lineage: for derivation i of tuple owner[i] with body tuples
+// (l[i], r[i]): g = adj[owner] if tag[owner] < 1; adj[l] += g*tag[r];
+// adj[r] += g*tag[l] (r may be ~0u: single-atom rule, adj[l] += g).
+void lineage_backward(const uint32_t* owner, const uint32_t* l, const uint32_t* r, size_t n, const float* tag_by_id,
+                      float* adj, hipStream_t st);
+// adj[ids[i]] += g[i]
+void scatter_add(const uint32_t* ids, const float* g, size_t n, float* adj, hipStream_t st);
+// out[i] += adj[ids[i]] * (tag[ids[i]] < 1)
+void gather_add_clamped(const uint32_t* ids, const float* adj, const float* tag_by_id, size_t n, float* out,
+                        hipStream_t st);
+// Lineage of new tuples.  For sorted candidate p its run is
+// s = pos[p] + flags[p] - 1.  lineage_flags: lf[p] = status[s] & 1.
+// lineage_emit (lpos = exclusive scan of lf): for every flagged p write
+// owner = id_base + newpos[s] and the pair (cl, cr)[perm[p]] at lpos[p].
+void lineage_flags(const uint32_t* pos, const uint32_t* flags, const uint32_t* status, size_t n, uint32_t* lf,
+                   hipStream_t st);
+void lineage_emit(const uint32_t* pos, const uint32_t* flags, const uint32_t* lf, const uint32_t* lpos,
+                  const uint32_t* newpos, const uint32_t* perm, const uint32_t* cl, const uint32_t* cr, size_t n,
+                  uint32_t id_base, uint32_t* owner, uint32_t* l, uint32_t* r, hipStream_t st);
+
+}  // namespace dlfix

@@ -1,0 +1,339 @@
+// Parser, stratifier and join planner for the supported Datalog fragment.
+#include "program.h"
+
+#include <algorithm>
+#include <cctype>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <stdexcept>
+
+namespace dlfix {
+
+int Program::find(const std::string& name) const {
+  for (size_t i = 0; i < rels.size(); ++i)
+    if (rels[i].name == name) return (int)i;
+  return -1;
+}
+
+namespace {
+
+struct Failure {
+  int code;
+  std::string msg;
+};
+
+class Reader {
+ public:
+  explicit Reader(const char* t) : s_(t) {}
+
+  void run(Program& p) {
+    for (;;) {
+      skip();
+      if (pos_ >= s_.size()) break;
+      if (s_[pos_] == '.') {
+        ++pos_;
+        directive(p);
+      } else {
+        rule(p);
+      }
+    }
+  }
+
+ private:
+  std::string s_;
+  size_t pos_ = 0;
+  int mentions_ = 0;
+
+  [[noreturn]] void parse_error(const std::string& m) {
+    throw Failure{2, "parse error at offset " + std::to_string(pos_) + ": " + m};
+  }
+  void skip() {
+    while (pos_ < s_.size()) {
+      char c = s_[pos_];
+      if (std::isspace((unsigned char)c)) {
+        ++pos_;
+      } else if (c == '#' || (c == '/' && pos_ + 1 < s_.size() && s_[pos_ + 1] == '/')) {
+        while (pos_ < s_.size() && s_[pos_] != '\n') ++pos_;
+      } else {
+        return;
+      }
+    }
+  }
+  bool at(char c) {
+    skip();
+    return pos_ < s_.size() && s_[pos_] == c;
+  }
+  void eat(const char* tok) {
+    skip();
+    size_t n = std::strlen(tok);
+    if (s_.compare(pos_, n, tok) != 0) parse_error(std::string("expected '") + tok + "'");
+    pos_ += n;
+  }
+  std::string name() {
+    skip();
+    size_t b = pos_;
+    if (pos_ < s_.size() && (std::isalpha((unsigned char)s_[pos_]) || s_[pos_] == '_'))
+      while (pos_ < s_.size() && (std::isalnum((unsigned char)s_[pos_]) || s_[pos_] == '_')) ++pos_;
+    if (b == pos_) parse_error("expected a name");
+    return s_.substr(b, pos_ - b);
+  }
+  int integer() {
+    skip();
+    size_t b = pos_;
+    long v = 0;
+    while (pos_ < s_.size() && std::isdigit((unsigned char)s_[pos_]) && v < 1000000) v = v * 10 + (s_[pos_++] - '0');
+    if (b == pos_) parse_error("expected an integer");
+    return (int)v;
+  }
+  int relation(Program& p, const std::string& n, int arity) {
+    int r = p.find(n);
+    if (r < 0) {
+      Relation rel;
+      rel.name = n;
+      rel.arity = arity;
+      rel.first_mention = mentions_++;
+      p.rels.push_back(rel);
+      return (int)p.rels.size() - 1;
+    }
+    if (p.rels[r].arity != arity) parse_error("relation " + n + " used with two arities");
+    return r;
+  }
+  void directive(Program& p) {
+    std::string kw = name();
+    std::string n = name();
+    eat("/");
+    int arity = integer();
+    if (arity < 1 || arity > 4) throw Failure{3, "arity of " + n + " must be 1..4"};
+    int r = relation(p, n, arity);
+    if (kw == "input") p.rels[r].input = true;
+    else if (kw != "output") parse_error("unknown directive ." + kw);
+  }
+  Atom atom(Program& p, std::map<std::string, int>& vars) {
+    std::string n = name();
+    eat("(");
+    Atom a;
+    for (;;) {
+      skip();
+      if (pos_ < s_.size() && std::isdigit((unsigned char)s_[pos_]))
+        throw Failure{3, "constants in atoms are not supported"};
+      std::string v = name();
+      auto it = vars.find(v);
+      int id = it == vars.end() ? (int)vars.size() : it->second;
+      if (it == vars.end()) vars[v] = id;
+      a.vars.push_back(id);
+      if (at(',')) {
+        eat(",");
+        continue;
+      }
+      break;
+    }
+    eat(")");
+    if (a.vars.size() > 4) throw Failure{3, "arity above 4"};
+    a.rel = relation(p, n, (int)a.vars.size());
+    return a;
+  }
+  void rule(Program& p) {
+    std::map<std::string, int> vars;
+    Rule r;
+    r.head = atom(p, vars);
+    eat(":-");
+    for (;;) {
+      r.body.push_back(atom(p, vars));
+      if (at(',')) {
+        eat(",");
+        continue;
+      }
+      break;
+    }
+    eat(".");
+    r.nvars = (int)vars.size();
+    if (r.body.size() > 3) throw Failure{3, "more than 3 body atoms"};
+    for (auto& b : r.body) {
+      std::vector<int> v = b.vars;
+      std::sort(v.begin(), v.end());
+      if (std::adjacent_find(v.begin(), v.end()) != v.end())
+        throw Failure{3, "repeated variable inside a body atom"};
+    }
+    for (int hv : r.head.vars) {
+      bool found = false;
+      for (auto& b : r.body)
+        found = found || std::count(b.vars.begin(), b.vars.end(), hv) > 0;
+      if (!found) throw Failure{3, "head variable not bound by the body"};
+    }
+    p.rules.push_back(r);
+  }
+};
+
+// Strongly connected components of the dependency graph (body -> head) over
+// derived relations, emitted in dependency order, ties by first mention.
+void stratify(Program& p) {
+  const int n = (int)p.rels.size();
+  std::vector<std::vector<char>> dep(n, std::vector<char>(n, 0));  // dep[a][b]: b depends on a
+  for (auto& r : p.rules)
+    for (auto& b : r.body) dep[b.rel][r.head.rel] = 1;
+  for (int k = 0; k < n; ++k)
+    for (int a = 0; a < n; ++a)
+      if (dep[a][k])
+        for (int b = 0; b < n; ++b)
+          if (dep[k][b]) dep[a][b] = 1;
+  std::vector<int> comp(n, -1);
+  std::vector<std::vector<int>> comps;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return p.rels[a].first_mention < p.rels[b].first_mention; });
+  for (int a : order) {
+    if (!p.rels[a].derived || comp[a] >= 0) continue;
+    comp[a] = (int)comps.size();
+    comps.push_back({a});
+    for (int b : order)
+      if (b != a && p.rels[b].derived && comp[b] < 0 && dep[a][b] && dep[b][a]) {
+        comp[b] = comp[a];
+        comps.back().push_back(b);
+      }
+  }
+  std::vector<char> placed(comps.size(), 0);
+  for (size_t step = 0; step < comps.size(); ++step) {
+    int pick = -1;
+    for (size_t c = 0; c < comps.size() && pick < 0; ++c) {  // comps are in first-mention order
+      if (placed[c]) continue;
+      bool ready = true;
+      for (size_t d = 0; d < comps.size(); ++d)
+        if (d != c && !placed[d] && dep[comps[d][0]][comps[c][0]]) ready = false;
+      if (ready) pick = (int)c;
+    }
+    placed[pick] = 1;
+    Stratum st;
+    st.rels = comps[pick];
+    for (int r : st.rels) p.rels[r].stratum = (int)p.strata.size();
+    p.strata.push_back(st);
+  }
+}
+
+int add_index(Program& p, const IndexSpec& ix) {
+  for (size_t i = 0; i < p.indexes.size(); ++i)
+    if (p.indexes[i] == ix) return (int)i;
+  p.indexes.push_back(ix);
+  return (int)p.indexes.size() - 1;
+}
+
+Plan make_plan(Program& p, int rule_id, int driver, bool delta) {
+  const Rule& r = p.rules[rule_id];
+  Plan pl;
+  pl.rule = rule_id;
+  pl.head_rel = r.head.rel;
+  pl.driver_atom = driver;
+  pl.driver_rel = r.body[driver].rel;
+  pl.delta = delta;
+  pl.driver_vars = r.body[driver].vars;
+  pl.max_cols = (int)std::max(r.body[driver].vars.size(), r.head.vars.size());
+  std::vector<int> cur = r.body[driver].vars;
+  std::vector<int> remaining;
+  for (int j = 0; j < (int)r.body.size(); ++j)
+    if (j != driver) remaining.push_back(j);
+  auto has = [](const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); };
+  if (remaining.empty()) {
+    for (int hv : r.head.vars) pl.project.push_back((int)(std::find(cur.begin(), cur.end(), hv) - cur.begin()));
+    return pl;
+  }
+  while (!remaining.empty()) {
+    int pick = -1;
+    for (size_t i = 0; i < remaining.size() && pick < 0; ++i)
+      for (int v : r.body[remaining[i]].vars)
+        if (has(cur, v)) {
+          pick = (int)i;
+          break;
+        }
+    if (pick < 0) throw Failure{3, "a body atom shares no variable with the atoms before it"};
+    const Atom& a = r.body[remaining[pick]];
+    Step st;
+    st.body_pos = remaining[pick];
+    remaining.erase(remaining.begin() + pick);
+    IndexSpec ix;
+    ix.rel = a.rel;
+    for (size_t c = 0; c < a.vars.size(); ++c)
+      if (has(cur, a.vars[c])) {
+        ix.perm.push_back((int)c);
+        st.join_src.push_back((int)(std::find(cur.begin(), cur.end(), a.vars[c]) - cur.begin()));
+      }
+    ix.w = (int)ix.perm.size();
+    for (size_t c = 0; c < a.vars.size(); ++c)
+      if (!has(cur, a.vars[c])) ix.perm.push_back((int)c);
+    st.index = add_index(p, ix);
+    // variables needed after this step
+    std::vector<int> need = r.head.vars;
+    for (int j : remaining)
+      for (int v : r.body[j].vars) need.push_back(v);
+    std::vector<int> out;
+    if (remaining.empty()) {
+      out = r.head.vars;
+    } else {
+      for (int v : cur)
+        if (has(need, v) && !has(out, v)) out.push_back(v);
+      for (int v : a.vars)
+        if (has(need, v) && !has(out, v)) out.push_back(v);
+    }
+    for (int v : out) {
+      if (has(cur, v)) {
+        st.out_src.push_back((int)(std::find(cur.begin(), cur.end(), v) - cur.begin()));
+      } else {
+        int col = (int)(std::find(a.vars.begin(), a.vars.end(), v) - a.vars.begin());
+        int kpos = (int)(std::find(ix.perm.begin(), ix.perm.end(), col) - ix.perm.begin());
+        st.out_src.push_back(-1 - kpos);
+      }
+    }
+    st.out_vars = out;
+    pl.max_cols = std::max(pl.max_cols, (int)out.size());
+    pl.steps.push_back(st);
+    cur = out;
+  }
+  return pl;
+}
+
+void plan(Program& p, bool frozen, bool diff) {
+  for (auto& r : p.rules) p.rels[r.head.rel].derived = true;
+  for (auto& rel : p.rels)
+    if (rel.derived && rel.input) throw Failure{3, "input relation " + rel.name + " is the head of a rule"};
+  stratify(p);
+  for (size_t ri = 0; ri < p.rules.size(); ++ri) {
+    const Rule& r = p.rules[ri];
+    int s = p.rels[r.head.rel].stratum;
+    if (diff && r.body.size() > 2) throw Failure{3, "differentiable add-mult supports at most 2 body atoms"};
+    std::vector<int> same;
+    for (int j = 0; j < (int)r.body.size(); ++j)
+      if (p.rels[r.body[j].rel].derived && p.rels[r.body[j].rel].stratum == s) same.push_back(j);
+    if (frozen && same.size() > 1)
+      throw Failure{3, "add-mult rules may contain at most one atom of their own stratum"};
+    if (same.empty()) {
+      p.plans.push_back(make_plan(p, (int)ri, 0, false));
+      p.strata[s].base_plans.push_back((int)p.plans.size() - 1);
+    } else {
+      p.strata[s].recursive = true;
+      for (int j : same) {
+        p.plans.push_back(make_plan(p, (int)ri, j, true));
+        p.strata[s].delta_plans.push_back((int)p.plans.size() - 1);
+      }
+    }
+  }
+  p.max_cols = 0;
+  for (auto& rel : p.rels) p.max_cols = std::max(p.max_cols, rel.arity);
+  for (auto& pl : p.plans) p.max_cols = std::max(p.max_cols, pl.max_cols);
+}
+
+}  // namespace
+
+int parse_and_plan(const char* text, bool frozen_tags, bool diff_lineage, Program& out, std::string& err) {
+  try {
+    Program p;
+    Reader(text).run(p);
+    if (p.rules.empty()) throw Failure{2, "program has no rules"};
+    plan(p, frozen_tags, diff_lineage);
+    out = std::move(p);
+    return 0;
+  } catch (const Failure& f) {
+    err = f.msg;
+    return f.code;
+  }
+}
+
+}  // namespace dlfix

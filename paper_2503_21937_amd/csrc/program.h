@@ -1,0 +1,94 @@
+// Program text -> rules -> strata -> fixed-function join plans (host only).
+//
+// A plan evaluates one rule with one chosen "driver" atom: the driver's rows
+// are expanded by a chain of binary index joins, one per remaining body atom
+// (join lowering of Sec. 3.3 / Appendix A: build an index on one side, count
+// matches per probe row, scan the counts, emit index pairs and gather
+// columns and x-multiplied tags).  Base plans run once, in the first round of
+// a stratum, with the first body atom as driver; delta plans run in later
+// rounds with an atom of the rule's own stratum as driver, reading only that
+// relation's recent tuples (semi-naive evaluation, Sec. 3.4).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace dlfix {
+
+struct Atom {
+  int rel;
+  std::vector<int> vars;  // variable per column
+};
+
+struct Rule {
+  Atom head;
+  std::vector<Atom> body;
+  int nvars = 0;
+};
+
+struct Relation {
+  std::string name;
+  int arity = 0;
+  bool input = false;
+  bool derived = false;
+  int stratum = -1;      // derived relations only
+  int first_mention = 0;
+};
+
+// Index on a relation: its rows re-packed with the columns in `perm` order;
+// the first `w` of them are the join columns, and a CSR offset array over the
+// (sample, join columns) prefix gives every probe its range of matches.
+struct IndexSpec {
+  int rel;
+  std::vector<int> perm;
+  int w;
+  bool identity() const {
+    for (size_t i = 0; i < perm.size(); ++i)
+      if (perm[i] != (int)i) return false;
+    return true;
+  }
+  bool operator==(const IndexSpec& o) const { return rel == o.rel && perm == o.perm && w == o.w; }
+};
+
+// One binary join: current table (layout `in_vars`) x index rows.
+struct Step {
+  int index;                    // into Plan-set index list
+  std::vector<int> join_src;    // per join column (index key order): column of the current table
+  std::vector<int> out_src;     // per output column: >= 0 current-table column, < 0: index column (-1 - c)
+  std::vector<int> out_vars;    // variables of the output layout (head columns for the last step)
+  int body_pos;                 // body position of the joined atom
+};
+
+struct Plan {
+  int rule;
+  int head_rel;
+  int driver_atom;              // body position of the driver
+  int driver_rel;
+  bool delta;                   // driver reads recent tuples (false: the whole relation)
+  std::vector<int> driver_vars;
+  std::vector<Step> steps;
+  std::vector<int> project;     // no steps: head column j <- driver column project[j]
+  int max_cols;                 // widest table of the plan
+};
+
+struct Stratum {
+  std::vector<int> rels;        // derived relations of this stratum
+  std::vector<int> base_plans;  // plan ids run in round 1
+  std::vector<int> delta_plans; // plan ids run in rounds >= 2
+  bool recursive = false;
+};
+
+struct Program {
+  std::vector<Relation> rels;
+  std::vector<Rule> rules;
+  std::vector<Stratum> strata;
+  std::vector<Plan> plans;
+  std::vector<IndexSpec> indexes;
+  int max_cols = 0;             // widest packed table (columns, excluding the sample)
+  int find(const std::string& name) const;
+};
+
+// Returns 0 on success, else 2 (parse error) or 3 (unsupported) with `err` set.
+int parse_and_plan(const char* text, bool frozen_tags, bool diff_lineage, Program& out, std::string& err);
+
+}  // namespace dlfix

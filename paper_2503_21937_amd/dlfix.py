@@ -1,0 +1,232 @@
+"""Python binding of libdlfix.so (the HIP fixpoint engine).
+
+Argument marshalling only: every step of the fixpoint runs in the library's
+HIP kernels.  Inputs may be numpy arrays (host) or torch tensors (device:
+their data pointers are passed and torch's current stream is used).  There is
+no fallback: if the library is missing or fails to load, this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libdlfix.so")
+
+SEMIRINGS = {"bool": 0, "maxmin": 1, "minplus": 2, "addmult": 3,
+             "diff_addmult": 4, "topk": 5, "diff_topk": 6}
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_PARSE", 3: "ERR_UNSUPPORTED", 4: "ERR_STATE",
+          5: "ERR_NOMEM", 6: "ERR_CAPACITY", 7: "ERR_PROOF_OVERFLOW", 8: "ERR_HIP"}
+EXPORTS = ["dl_load_program", "dl_clear_facts", "dl_add_facts", "dl_run_fixpoint",
+           "dl_relation_size", "dl_read_relation", "dl_backward", "dl_read_grad",
+           "dl_zero_grad", "dl_get_stats", "dl_last_error", "dl_free"]
+
+
+class DLError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [("semiring", C.c_int), ("k", C.c_int), ("batched", C.c_int),
+                ("stream", C.c_void_p)]
+
+
+class RelationOut(C.Structure):
+    _fields_ = [("sample_ids", C.c_void_p), ("columns", C.c_void_p * 4), ("tags", C.c_void_p),
+                ("topk_count", C.c_void_p), ("topk_bits", C.c_void_p), ("topk_prob", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("strata", C.c_int), ("rounds", C.c_int), ("max_rounds", C.c_int),
+                ("candidates", C.c_uint64), ("unique", C.c_uint64), ("derived", C.c_uint64),
+                ("lineage", C.c_uint64), ("run_ms", C.c_double), ("device_bytes", C.c_uint64),
+                ("key_bits", C.c_uint32), ("id_bits", C.c_uint32), ("sample_bits", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdlfix.so (built in-tree by build.py); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        # Load torch first so that the library binds to the HIP runtime torch
+        # already mapped (one runtime per process: device pointers and streams
+        # are then shared, and a second runtime would not see the device).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB):
+            raise ImportError(f"{LIB} is missing: build it with paper_2503_21937_amd/build.py")
+        L = C.CDLL(LIB)
+        vp, sz = C.c_void_p, C.c_size_t
+        L.dl_load_program.argtypes = [C.c_char_p, C.POINTER(Options), C.POINTER(vp)]
+        L.dl_clear_facts.argtypes = [vp]
+        L.dl_add_facts.argtypes = [vp, C.c_char_p, sz, vp, vp, vp, C.c_int]
+        L.dl_run_fixpoint.argtypes = [vp]
+        L.dl_relation_size.argtypes = [vp, C.c_char_p, C.POINTER(sz)]
+        L.dl_read_relation.argtypes = [vp, C.c_char_p, sz, C.POINTER(RelationOut), C.c_int,
+                                       C.POINTER(sz)]
+        L.dl_backward.argtypes = [vp, C.c_char_p, vp, C.c_int]
+        L.dl_read_grad.argtypes = [vp, C.c_char_p, vp, C.c_int]
+        L.dl_zero_grad.argtypes = [vp]
+        L.dl_get_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.dl_last_error.argtypes = [vp]
+        L.dl_last_error.restype = C.c_char_p
+        L.dl_free.argtypes = [vp]
+        for f in EXPORTS[:-2]:
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype):
+    """(pointer, keepalive, on_device) for a numpy array or torch tensor."""
+    if x is None:
+        return None, None, None
+    if _is_torch(x):
+        if not x.is_contiguous():
+            x = x.contiguous()
+        return x.data_ptr(), x, bool(x.is_cuda)
+    a = np.ascontiguousarray(np.asarray(x, dtype=dtype))
+    return a.ctypes.data, a, False
+
+
+def _current_stream() -> int | None:
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:  # torch absent: the engine makes its own stream
+        pass
+    return None
+
+
+class Engine:
+    """One fixpoint engine: a program under one semiring (dlfix.h)."""
+
+    def __init__(self, program: str, semiring: str = "bool", k: int = 3,
+                 batched: bool = False, stream: int | None = None, use_torch_stream: bool = True):
+        self.arity = {}
+        for line in program.splitlines():
+            line = line.strip()
+            if line.startswith(".input") or line.startswith(".output"):
+                name, ar = line.split()[1].split("/")
+                self.arity[name] = int(ar)
+        self.semiring = semiring
+        self.k = k
+        self.batched = batched
+        if stream is None and use_torch_stream:
+            stream = _current_stream()
+        opts = Options(SEMIRINGS[semiring], k, int(batched), stream)
+        h = C.c_void_p()
+        rc = lib().dl_load_program(program.encode(), C.byref(opts), C.byref(h))
+        if rc:
+            raise DLError(rc, lib().dl_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dl_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc:
+            raise DLError(rc, lib().dl_last_error(self.h).decode())
+
+    def add_facts(self, rel: str, cols, tags=None, sample=None):
+        keep = []
+        ptrs = (C.c_void_p * 4)()
+        dev = None
+        n = None
+        for i, c in enumerate(cols):
+            p, a, d = _ptr(c, np.uint32)
+            keep.append(a)
+            ptrs[i] = p
+            dev = d if dev is None else dev
+            n = int(a.shape[0]) if n is None else n
+        tp, ta, _ = _ptr(tags, np.float32)
+        sp, sa, _ = _ptr(sample, np.uint32)
+        keep += [ta, sa]
+        self._check(lib().dl_add_facts(self.h, rel.encode(), n, sp, ptrs, tp, int(bool(dev))))
+
+    def clear_facts(self):
+        self._check(lib().dl_clear_facts(self.h))
+
+    def run(self):
+        self._check(lib().dl_run_fixpoint(self.h))
+        return self
+
+    def size(self, rel: str) -> int:
+        n = C.c_size_t()
+        self._check(lib().dl_relation_size(self.h, rel.encode(), C.byref(n)))
+        return n.value
+
+    def read(self, rel: str, device: bool = False) -> dict:
+        """Relation in canonical order: dict(sample, cols (n x arity), tags,
+        and for top-k cnt (n), bits (n x k), p (n x k))."""
+        n = self.size(rel)
+        ar = self.arity[rel]
+        topk = self.semiring in ("topk", "diff_topk")
+        if device:
+            import torch
+            dv = torch.device("cuda")
+            mk = lambda shape, dt: torch.zeros(shape, dtype=dt, device=dv)
+            u32, f32, u8, u64 = torch.int32, torch.float32, torch.uint8, torch.int64
+        else:
+            mk = lambda shape, dt: np.zeros(shape, dt)
+            u32, f32, u8, u64 = np.uint32, np.float32, np.uint8, np.uint64
+        out = dict(sample=mk(n, u32), cols=[mk(n, u32) for _ in range(ar)], tags=mk(n, f32))
+        if topk:
+            out.update(cnt=mk(n, u8), bits=mk((self.k, n), u64), p=mk((self.k, n), f32))
+        ro = RelationOut()
+        ptr = (lambda t: t.data_ptr()) if device else (lambda a: a.ctypes.data)
+        if n:
+            ro.sample_ids = ptr(out["sample"])
+            for c in range(ar):
+                ro.columns[c] = ptr(out["cols"][c])
+            ro.tags = ptr(out["tags"])
+            if topk:
+                ro.topk_count = ptr(out["cnt"])
+                ro.topk_bits = ptr(out["bits"])
+                ro.topk_prob = ptr(out["p"])
+        w = C.c_size_t()
+        self._check(lib().dl_read_relation(self.h, rel.encode(), n, C.byref(ro), int(device),
+                                           C.byref(w)))
+        if not device:
+            out["cols"] = np.stack(out["cols"], 1) if ar else np.zeros((n, 0), np.uint32)
+            if topk:
+                out["bits"] = out["bits"].T.copy()
+                out["p"] = out["p"].T.copy()
+        return out
+
+    def backward(self, rel: str, grad_out):
+        p, a, dev = _ptr(grad_out, np.float32)
+        self._check(lib().dl_backward(self.h, rel.encode(), p, int(bool(dev))))
+
+    def grad(self, rel: str, n: int, out=None):
+        if out is None:
+            out = np.zeros(n, np.float32)
+        p, a, dev = _ptr(out, np.float32)
+        self._check(lib().dl_read_grad(self.h, rel.encode(), p, int(bool(dev))))
+        return out
+
+    def zero_grad(self):
+        self._check(lib().dl_zero_grad(self.h))
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(lib().dl_get_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}

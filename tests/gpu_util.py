@@ -1,0 +1,40 @@
+"""Helpers shared by the GPU parity tests (HIP path through the C ABI vs the
+CPU oracle on the same seeded inputs)."""
+import numpy as np
+
+TAG_RTOL = 1e-5  # float32 tags vs the binary64 oracle
+
+
+def engine(program, semiring, facts, k=3, batched=False):
+    from paper_2503_21937_amd import dlfix
+    e = dlfix.Engine(program, semiring, k=k, batched=batched)
+    for rel, (cols, tags, sample) in facts.items():
+        e.add_facts(rel, cols, tags, sample)
+    return e.run()
+
+
+def oracle_run(oracle, program, semiring, facts, k=3, batched=False):
+    o = oracle.Oracle(program, semiring, k=k, batched=batched)
+    for rel, (cols, tags, sample) in facts.items():
+        o.add_facts(rel, cols, tags, sample)
+    return o.run()
+
+
+def assert_tags_close(got, want, rtol=TAG_RTOL, what=""):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    assert got.shape == want.shape, what
+    both_inf = np.isinf(got) & np.isinf(want) & (np.sign(got) == np.sign(want))
+    err = np.abs(got - want)
+    bound = rtol * np.maximum(np.abs(got), np.abs(want)) + 1e-35
+    bad = ~both_inf & ~(err <= bound)
+    if bad.any():
+        i = np.argmax(bad)
+        raise AssertionError(f"{what}: {bad.sum()} tags differ, first at {i}: got {got[i]!r} want {want[i]!r}")
+
+
+def same_rows(g, o, batched=False):
+    """Tuple sets equal (bit-exact, canonical order)."""
+    assert np.array_equal(g["cols"], o["cols"]), "tuple sets differ"
+    if batched:
+        assert np.array_equal(g["sample"], o["sample"]), "sample ids differ"

@@ -1,0 +1,66 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/dlfix.h declares, and rejects bad programs before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dl():
+    from paper_2503_21937_amd import dlfix
+    if not os.path.exists(dlfix.LIB):
+        from paper_2503_21937_amd import build
+        build.build()
+    return dlfix
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "dlfix.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dl_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ["dl_load_program", "dl_add_facts", "dl_run_fixpoint", "dl_read_relation",
+              "dl_backward", "dl_read_grad", "dl_free"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(dl):
+    lib = C.CDLL(dl.LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(dl.EXPORTS) == declared()
+
+
+@pytest.mark.parametrize("text,status", [
+    ("path(x, y) :- edge(x, y", 2),                               # parse error
+    ("path(x, z) :- edge(x, 3).", 3),                             # constant
+    ("path(x, z) :- edge(x, x).", 3),                             # repeated variable in an atom
+    ("path(x, w) :- edge(x, y).", 3),                             # unbound head variable
+    ("p(a) :- q(a), r(b).", 3),                                   # disconnected body
+    ("p(a) :- q(a, b), r(b, c), s(c, d), t(d, a).", 3),           # four atoms
+    (".input edge/2\nedge(x, y) :- edge(y, x).", 3),              # head on an input
+])
+def test_rejected_programs(dl, text, status):
+    with pytest.raises(dl.DLError) as ex:
+        dl.Engine(text, "bool", use_torch_stream=False)
+    assert ex.value.status == status
+
+
+def test_frozen_semiring_rejects_two_recursive_atoms(dl):
+    prog = ".input e/2\np(x, y) :- e(x, y).\np(x, z) :- p(x, y), p(y, z)."
+    with pytest.raises(dl.DLError) as ex:
+        dl.Engine(prog, "addmult", use_torch_stream=False)
+    assert ex.value.status == 3
+
+
+def test_bad_options(dl):
+    with pytest.raises(dl.DLError) as ex:
+        dl.Engine(".input e/2\np(x,y) :- e(x,y).", "topk", k=4, use_torch_stream=False)
+    assert ex.value.status == 1
