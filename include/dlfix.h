@@ -103,6 +103,28 @@ typedef struct {
   uint32_t sample_bits;   /* bits of the sample id */
 } dl_stats;
 
+/* Kernel families timed by dl_profile (bit i of the mask = family i). */
+typedef enum {
+  DL_K_JOIN_COUNT = 0,    /* matches per probe row */
+  DL_K_JOIN_EXPAND = 1,   /* load-balanced expand + gather + tag product */
+  DL_K_SORT_HIST = 2,     /* radix sort: per-tile digit histograms */
+  DL_K_SORT_SCATTER = 3,  /* radix sort: stable ranking + scatter */
+  DL_K_SCAN = 4,          /* device-wide exclusive scans */
+  DL_K_REDUCE = 5,        /* segment heads + per-key +-reduction */
+  DL_K_DIFF = 6,          /* difference / +-merge against the full relation */
+  DL_K_MERGE = 7,         /* merge-path merge into the full relation */
+  DL_K_COMPACT = 8,       /* stream compaction, flags, lineage emission */
+  DL_K_INDEX = 9,         /* index build (permute, CSR) */
+  DL_K_BACKWARD = 10,     /* gradient kernels */
+  DL_K_FAMILIES = 11
+} dl_kernel_family;
+
+typedef struct {
+  uint64_t launches;      /* timed launches since the last dl_profile call */
+  double ms;              /* summed event-to-event time of those launches */
+  double bytes;           /* summed algorithmic bytes (minimum reads + writes) */
+} dl_kernel_timing;
+
 /* Parse and plan a program.
  * Text: one statement per '.'-terminated clause; '#' or '//' start comments.
  *   .input name/arity           declares an input (extensional) relation
@@ -156,6 +178,14 @@ dl_status dl_read_grad(dl_engine* e, const char* in_relation, float* grad_in, in
 dl_status dl_zero_grad(dl_engine* e);
 
 dl_status dl_get_stats(const dl_engine* e, dl_stats* out);
+
+/* Time the kernel families in `family_mask` with HIP events recorded on the
+ * engine's stream around each launch (0 switches timing off).  Resets the
+ * totals; later dl_run_fixpoint and dl_backward calls add to them. */
+dl_status dl_profile(dl_engine* e, uint32_t family_mask);
+
+/* Totals of one kernel family since the last dl_profile call. */
+dl_status dl_get_kernel_timing(const dl_engine* e, int family, dl_kernel_timing* out);
 
 /* Owned by the engine; valid until the next call on it.  Never NULL. */
 const char* dl_last_error(const dl_engine* e);

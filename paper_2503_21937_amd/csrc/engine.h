@@ -111,6 +111,8 @@ struct Engine {
   DevBuf dtotal;             // device words for totals
 
   dl_stats stats{};
+  uint32_t prof_mask = 0;
+  dl_kernel_timing kstats[DL_K_FAMILIES]{};
   size_t device_bytes = 0;
 
   ~Engine();

@@ -5,8 +5,43 @@
 
 #include "dl_device.h"
 #include "engine.h"
+#include "prof.h"
 
 namespace dlfix {
+
+thread_local Profiler* g_prof = nullptr;
+
+namespace {
+// Installs a profiler for one engine call when timing is on; folds the event
+// times into the engine's per-family totals when the call is done.
+struct ProfScope {
+  Engine& e;
+  Profiler p;
+  bool on;
+  explicit ProfScope(Engine& eng) : e(eng), on(eng.prof_mask != 0) {
+    if (!on) return;
+    p.mask = e.prof_mask;
+    g_prof = &p;
+  }
+  void finish() {
+    if (!on) return;
+    g_prof = nullptr;
+    on = false;
+    e.sync();
+    for (auto& r : p.recs) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+      dl_kernel_timing& k = e.kstats[r.fam];
+      k.launches += 1;
+      k.ms += ms;
+      k.bytes += r.bytes;
+    }
+  }
+  ~ProfScope() {
+    if (on) g_prof = nullptr;
+  }
+};
+}  // namespace
 
 Engine::~Engine() {
   auto fr = [](DevBuf& b) {
@@ -191,6 +226,7 @@ static int bits_for(uint32_t maxv) {
 
 void Engine::run() {
   auto t0 = std::chrono::steady_clock::now();
+  ProfScope prof(*this);
   if (!ingested) {
     // id domain and sample domain from the facts
     uint32_t* dmax = reinterpret_cast<uint32_t*>(dtotal.as<uint64_t>() + 30);
@@ -217,6 +253,7 @@ void Engine::run() {
   }
   if (key64) run_fixpoint<uint64_t>(*this);
   else run_fixpoint<uint32_t>(*this);
+  prof.finish();
   ran = true;
   stats.run_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   stats.device_bytes = device_bytes;
@@ -248,8 +285,10 @@ void Engine::backward(const char* out_relation, const float* grad_out, int on_de
   if (n)
     DL_HIP(hipMemcpyAsync(unpack.p, grad_out, n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                           stream));
+  ProfScope prof(*this);
   if (key64) backward_t<uint64_t>(*this, r, unpack.as<float>());
   else backward_t<uint32_t>(*this, r, unpack.as<float>());
+  prof.finish();
   sync();
 }
 
@@ -379,6 +418,19 @@ dl_status dl_zero_grad(dl_engine* h) {
 dl_status dl_get_stats(const dl_engine* h, dl_stats* out) {
   if (!h || !out) return DL_ERR_ARG;
   *out = h->e.stats;
+  return DL_OK;
+}
+
+dl_status dl_profile(dl_engine* h, uint32_t family_mask) {
+  return guard(h, [&] {
+    h->e.prof_mask = family_mask & ((1u << DL_K_FAMILIES) - 1);
+    for (auto& k : h->e.kstats) k = dl_kernel_timing{};
+  });
+}
+
+dl_status dl_get_kernel_timing(const dl_engine* h, int family, dl_kernel_timing* out) {
+  if (!h || !out || family < 0 || family >= DL_K_FAMILIES) return DL_ERR_ARG;
+  *out = h->e.kstats[family];
   return DL_OK;
 }
 

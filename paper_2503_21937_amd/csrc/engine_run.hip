@@ -261,7 +261,7 @@ size_t absorb(Engine& e, int r) {
   if (tb) e.grow(e.utags, U * tb);
   const void* tsrc = use_perm ? R.cand_tags.p : (const void*)vp;
   segment_reduce<K>(kp, e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), C, e.tag_kind, e.sr, e.k, tsrc,
-                    use_perm ? vp : nullptr, e.ukeys.as<K>(), e.utags.p, st);
+                    use_perm ? vp : nullptr, e.ukeys.as<K>(), e.utags.p, U, st);
 
   // 3. difference / +-merge against the full relation
   e.grow(e.status, U * 4);
@@ -404,7 +404,7 @@ void ingest(Engine& e) {
     e.grow(R.full.keys, U * sizeof(K) + 8);
     if (e.tag_bytes) e.grow(R.full.tags, U * e.tag_bytes + 8);
     segment_reduce<K>(kp, e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), n, e.tag_kind, e.sr, e.k, ftags, vp,
-                      R.full.keys.as<K>(), R.full.tags.p, st);
+                      R.full.keys.as<K>(), R.full.tags.p, U, st);
     R.full.n = U;
     e.grow(R.fact_entry, n * 4);
     seg_scatter(e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), vp, n, id, R.fact_entry.as<uint32_t>(), st);

@@ -4,6 +4,7 @@
 // the same digit, mbcnt ranks a lane among them), stream compaction, gather.
 #include "dl_device.h"
 #include "kernels.h"
+#include "prof.h"
 
 namespace dlfix {
 
@@ -81,9 +82,11 @@ void scan_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* d_total, bo
     return;
   }
   size_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  DL_PROF_BEGIN(4, st);
   k_scan_reduce<<<nb, BLOCK, 0, st>>>(in, n, scratch);
   k_scan_partials<<<1, BLOCK, 0, st>>>(scratch, nb, d_total);
   k_scan_down<<<nb, BLOCK, 0, st>>>(in, out, n, scratch, d_total, sentinel ? 1 : 0);
+  DL_PROF_END(4, st, n * 8.0);
 }
 
 // ------------------------------------------------------------- radix sort
@@ -211,12 +214,16 @@ void radix_sort(K** keys, uint32_t** vals, K** keys_alt, uint32_t** vals_alt, si
   const bool v = vals && *vals;
   for (int shift = 0; shift < key_bits; shift += RADIX_BITS) {
     int nbits = key_bits - shift < RADIX_BITS ? key_bits - shift : RADIX_BITS;
+    DL_PROF_BEGIN(2, st);
     k_radix_hist<K><<<nb, BLOCK, 0, st>>>(*keys, n, shift, hist, nb);
+    DL_PROF_END(2, st, (double)n * sizeof(K));
     scan_u32(hist, hist, hn, total, false, sc, st);
+    DL_PROF_BEGIN(3, st);
     if (v)
       k_radix_scatter<K, true><<<nb, BLOCK, 0, st>>>(*keys, *vals, *keys_alt, *vals_alt, n, shift, nbits, hist, nb);
     else
       k_radix_scatter<K, false><<<nb, BLOCK, 0, st>>>(*keys, nullptr, *keys_alt, nullptr, n, shift, nbits, hist, nb);
+    DL_PROF_END(3, st, 2.0 * n * (sizeof(K) + (v ? 4 : 0)));
     K* t = *keys;
     *keys = *keys_alt;
     *keys_alt = t;

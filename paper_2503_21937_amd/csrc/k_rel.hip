@@ -5,6 +5,7 @@
 // tag and gradient kernels.
 #include "dl_device.h"
 #include "kernels.h"
+#include "prof.h"
 
 namespace dlfix {
 
@@ -111,7 +112,9 @@ __global__ void k_csr(const K* __restrict__ keys, size_t n, int shift, uint64_t 
 template <typename K>
 void csr_build(const K* keys, size_t n, int total_bits, int prefix_bits, uint32_t* off, hipStream_t st) {
   uint64_t domain = 1ull << prefix_bits;
+  DL_PROF_BEGIN(9, st);
   k_csr<K><<<grid_for(domain + 1), BLOCK, 0, st>>>(keys, n, total_bits - prefix_bits, domain, off);
+  DL_PROF_END(9, st, (domain + 1) * 4.0 + (double)n * sizeof(K));
 }
 
 // ------------------------------------------------------------------ joins
@@ -133,7 +136,10 @@ __global__ void k_join_count(JoinArgs a, uint32_t* __restrict__ counts) {
 
 template <typename K>
 void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st) {
-  if (a.n) k_join_count<K><<<grid_for(a.n), BLOCK, 0, st>>>(a, counts);
+  if (!a.n) return;
+  DL_PROF_BEGIN(0, st);
+  k_join_count<K><<<grid_for(a.n), BLOCK, 0, st>>>(a, counts);
+  DL_PROF_END(0, st, a.n * (sizeof(K) + 12.0));
 }
 
 template <int TK>
@@ -242,12 +248,19 @@ void join_expand(const JoinArgs& a, int tk, const uint32_t* offs, size_t total, 
                  uint32_t* orr, hipStream_t st) {
   if (!total) return;
   size_t nb = (total + EXP_TILE - 1) / EXP_TILE;
+  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : (double)sizeof(TopK);
+  const double lin = ol ? 4.0 : 0.0;
+  // outputs written, index rows read once per output, driver rows and offsets read once
+  const double bytes = total * (sizeof(K) + tb + 2 * lin) + total * (sizeof(K) + tb + lin) +
+                       a.n * (sizeof(K) + tb + lin + 4.0);
+  DL_PROF_BEGIN(1, st);
   if (tk == TAG_NONE)
     k_join_expand<K, TAG_NONE><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (NoTag*)otags, ol, orr);
   else if (tk == TAG_F32)
     k_join_expand<K, TAG_F32><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (float*)otags, ol, orr);
   else
     k_join_expand<K, TAG_TOPK><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (TopK*)otags, ol, orr);
+  DL_PROF_END(1, st, bytes);
 }
 
 template <typename K, int TK>
@@ -287,7 +300,10 @@ __global__ void k_head_flags(const K* __restrict__ keys, size_t n, uint32_t* __r
 
 template <typename K>
 void head_flags(const K* keys, size_t n, uint32_t* flags, hipStream_t st) {
-  if (n) k_head_flags<K><<<grid_for(n), BLOCK, 0, st>>>(keys, n, flags);
+  if (!n) return;
+  DL_PROF_BEGIN(5, st);
+  k_head_flags<K><<<grid_for(n), BLOCK, 0, st>>>(keys, n, flags);
+  DL_PROF_END(5, st, n * (sizeof(K) + 4.0));
 }
 
 template <typename K, int TK>
@@ -314,8 +330,10 @@ __global__ void k_segment_reduce(const K* __restrict__ keys, const uint32_t* __r
 
 template <typename K>
 void segment_reduce(const K* keys, const uint32_t* pos, const uint32_t* flags, size_t n, int tk, int sr, int k,
-                    const void* tags, const uint32_t* perm, K* kout, void* tout, hipStream_t st) {
+                    const void* tags, const uint32_t* perm, K* kout, void* tout, size_t nout, hipStream_t st) {
   if (!n) return;
+  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : (double)sizeof(TopK);
+  DL_PROF_BEGIN(5, st);
   if (tk == TAG_NONE)
     k_segment_reduce<K, TAG_NONE><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const NoTag*)tags, perm,
                                                                  kout, (NoTag*)tout);
@@ -325,6 +343,7 @@ void segment_reduce(const K* keys, const uint32_t* pos, const uint32_t* flags, s
   else
     k_segment_reduce<K, TAG_TOPK><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const TopK*)tags, perm,
                                                                  kout, (TopK*)tout);
+  DL_PROF_END(5, st, n * (sizeof(K) + 8.0 + tb + (perm ? 4.0 : 0.0)) + nout * (sizeof(K) + tb));
 }
 
 // ------------------------------------------------- difference / +-merge
@@ -407,12 +426,15 @@ void diff_merge(const K* uk, const void* ut, size_t nu, const K* fk, void* ft, s
                 bool converge, uint32_t* status, uint32_t* fpos, hipStream_t st) {
   if (!nu) return;
   size_t nb = (nu + DIFF_TILE - 1) / DIFF_TILE;
+  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : (double)sizeof(TopK);
+  DL_PROF_BEGIN(6, st);
   if (tk == TAG_NONE)
     k_diff<K, TAG_NONE><<<nb, BLOCK, 0, st>>>(uk, (NoTag*)ut, nu, fk, (NoTag*)ft, nf, sr, k, converge, status, fpos);
   else if (tk == TAG_F32)
     k_diff<K, TAG_F32><<<nb, BLOCK, 0, st>>>(uk, (float*)ut, nu, fk, (float*)ft, nf, sr, k, converge, status, fpos);
   else
     k_diff<K, TAG_TOPK><<<nb, BLOCK, 0, st>>>(uk, (TopK*)ut, nu, fk, (TopK*)ft, nf, sr, k, converge, status, fpos);
+  DL_PROF_END(6, st, nu * (sizeof(K) + tb + 4.0) + (double)nf * sizeof(K));
 }
 
 // ------------------------------------------------------------ merge path
@@ -509,8 +531,10 @@ void merge_sorted(const K* ak, const void* at, const uint32_t* aid, size_t na, c
   if (na + nb == 0) return;
   size_t ntiles = (na + nb + MERGE_TILE - 1) / MERGE_TILE;
   k_merge_partition<K><<<grid_for(ntiles + 1), BLOCK, 0, st>>>(ak, na, bk, nb, ntiles, scratch);
+  DL_PROF_BEGIN(7, st);
   k_merge<K><<<ntiles, BLOCK, 0, st>>>(ak, (const uint8_t*)at, aid, na, bk, (const uint8_t*)bt, bid, nb, (int)tag_bytes,
                                       scratch, ok, (uint8_t*)ot, oid);
+  DL_PROF_END(7, st, 2.0 * (na + nb) * (sizeof(K) + tag_bytes + (oid ? 4.0 : 0.0)));
 }
 
 // ---------------------------------------------------------------- lineage
@@ -580,7 +604,10 @@ __global__ void k_lineage_backward(const uint32_t* __restrict__ owner, const uin
 
 void lineage_backward(const uint32_t* owner, const uint32_t* l, const uint32_t* r, size_t n, const float* tag,
                       float* adj, hipStream_t st) {
-  if (n) k_lineage_backward<<<grid_for(n), BLOCK, 0, st>>>(owner, l, r, n, tag, adj);
+  if (!n) return;
+  DL_PROF_BEGIN(10, st);
+  k_lineage_backward<<<grid_for(n), BLOCK, 0, st>>>(owner, l, r, n, tag, adj);
+  DL_PROF_END(10, st, n * 28.0);
 }
 
 __global__ void k_scatter_add(const uint32_t* __restrict__ ids, const float* __restrict__ g, size_t n, float* adj) {
@@ -707,7 +734,7 @@ void topk_backward(const TopK* t, const uint32_t* sample, const float* gout, siz
   template void project_rows<K>(const JoinArgs&, int, void*, void*, uint32_t*, uint32_t*, hipStream_t);             \
   template void head_flags<K>(const K*, size_t, uint32_t*, hipStream_t);                                            \
   template void segment_reduce<K>(const K*, const uint32_t*, const uint32_t*, size_t, int, int, int, const void*,  \
-                                  const uint32_t*, K*, void*, hipStream_t);                                          \
+                                  const uint32_t*, K*, void*, size_t, hipStream_t);                                          \
   template void diff_merge<K>(const K*, const void*, size_t, const K*, void*, size_t, int, int, int, bool,          \
                               uint32_t*, uint32_t*, hipStream_t);                                                   \
   template void merge_sorted<K>(const K*, const void*, const uint32_t*, size_t, const K*, const void*,              \

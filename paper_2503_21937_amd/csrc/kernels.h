@@ -104,7 +104,8 @@ void head_flags(const K* keys, size_t n, uint32_t* flags, hipStream_t st);
 // read through `perm` (sorted position -> candidate index) when non-NULL.
 template <typename K>
 void segment_reduce(const K* keys, const uint32_t* pos, const uint32_t* flags, size_t n, int tag_kind, int sr, int k,
-                    const void* tags, const uint32_t* perm, K* keys_out, void* tags_out, hipStream_t st);
+                    const void* tags, const uint32_t* perm, K* keys_out, void* tags_out, size_t n_out,
+                    hipStream_t st);
 
 // For every unique candidate (sorted, distinct) find its key in the sorted
 // full relation.  Converging semirings +-merge the tag into full in place.

@@ -21,7 +21,10 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_PARSE", 3: "ERR_UNSUPPORTED", 4: "ERR_S
           5: "ERR_NOMEM", 6: "ERR_CAPACITY", 7: "ERR_PROOF_OVERFLOW", 8: "ERR_HIP"}
 EXPORTS = ["dl_load_program", "dl_clear_facts", "dl_add_facts", "dl_run_fixpoint",
            "dl_relation_size", "dl_read_relation", "dl_backward", "dl_read_grad",
-           "dl_zero_grad", "dl_get_stats", "dl_last_error", "dl_free"]
+           "dl_zero_grad", "dl_get_stats", "dl_profile", "dl_get_kernel_timing",
+           "dl_last_error", "dl_free"]
+KERNEL_FAMILIES = ["join_count", "join_expand", "sort_hist", "sort_scatter", "scan", "reduce",
+                   "diff", "merge", "compact", "index", "backward"]
 
 
 class DLError(RuntimeError):
@@ -38,6 +41,10 @@ class Options(C.Structure):
 class RelationOut(C.Structure):
     _fields_ = [("sample_ids", C.c_void_p), ("columns", C.c_void_p * 4), ("tags", C.c_void_p),
                 ("topk_count", C.c_void_p), ("topk_bits", C.c_void_p), ("topk_prob", C.c_void_p)]
+
+
+class KernelStats(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("ms", C.c_double), ("bytes", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -76,10 +83,12 @@ def lib():
         L.dl_read_grad.argtypes = [vp, C.c_char_p, vp, C.c_int]
         L.dl_zero_grad.argtypes = [vp]
         L.dl_get_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.dl_profile.argtypes = [vp, C.c_uint32]
+        L.dl_get_kernel_timing.argtypes = [vp, C.c_int, C.POINTER(KernelStats)]
         L.dl_last_error.argtypes = [vp]
         L.dl_last_error.restype = C.c_char_p
         L.dl_free.argtypes = [vp]
-        for f in EXPORTS[:-2]:
+        for f in EXPORTS[:-2]:  # all but dl_last_error, dl_free
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -225,6 +234,24 @@ class Engine:
 
     def zero_grad(self):
         self._check(lib().dl_zero_grad(self.h))
+
+    def profile(self, families=None):
+        """Time the given kernel families (names; None = all, [] = off)."""
+        if families is None:
+            mask = (1 << len(KERNEL_FAMILIES)) - 1
+        else:
+            mask = 0
+            for f in families:
+                mask |= 1 << KERNEL_FAMILIES.index(f)
+        self._check(lib().dl_profile(self.h, mask))
+
+    def kernel_stats(self) -> dict:
+        out = {}
+        for i, name in enumerate(KERNEL_FAMILIES):
+            ks = KernelStats()
+            self._check(lib().dl_get_kernel_timing(self.h, i, C.byref(ks)))
+            out[name] = dict(launches=ks.launches, ms=ks.ms, bytes=ks.bytes)
+        return out
 
     def stats(self) -> dict:
         s = Stats()
