@@ -1,0 +1,46 @@
+"""torch.autograd.Function over the fixpoint engine.
+
+Forward: input-fact probabilities (a float32 CUDA tensor) -> tags of an output
+relation, computed by the HIP engine (differentiable add-mult or top-k).
+Backward: the engine's reverse pass (recorded discovery derivations for
+add-mult, the inclusion-exclusion gradient for top-k) -> gradient of the
+input probabilities.  Torch provides device memory and orders the engine's
+work after its own through a stream synchronisation.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import dlfix
+
+
+class FixpointFunction(torch.autograd.Function):
+    """out_tags = fixpoint(probs); sample ids and columns ride along."""
+
+    @staticmethod
+    def forward(ctx, probs, engine, in_rel, cols, sample, out_rel):
+        torch.cuda.current_stream().synchronize()
+        engine.clear_facts()
+        engine.add_facts(in_rel, cols, probs.detach().contiguous(), sample)
+        engine.run()
+        out = engine.read(out_rel, device=True)
+        ctx.engine, ctx.in_rel, ctx.out_rel, ctx.n_in = engine, in_rel, out_rel, probs.shape[0]
+        osample = out["sample"]
+        ocols = torch.stack(out["cols"], 1) if out["cols"] else torch.zeros((0, 0), dtype=torch.int32)
+        ctx.mark_non_differentiable(osample, ocols)
+        return out["tags"], osample, ocols
+
+    @staticmethod
+    def backward(ctx, grad_tags, _gs, _gc):
+        e = ctx.engine
+        torch.cuda.current_stream().synchronize()
+        e.zero_grad()
+        e.backward(ctx.out_rel, grad_tags.detach().float().contiguous())
+        g = torch.zeros(ctx.n_in, dtype=torch.float32, device=grad_tags.device)
+        e.grad(ctx.in_rel, ctx.n_in, out=g)
+        return g, None, None, None, None, None
+
+
+def fixpoint(probs, engine, in_rel, cols, sample=None, out_rel="path"):
+    """Differentiable fixpoint: returns (tags, sample_ids, columns) of out_rel."""
+    return FixpointFunction.apply(probs, engine, in_rel, cols, sample, out_rel)
