@@ -48,6 +48,89 @@ def cpu_baseline(src, dst, p, n, budget_s: float, seed: int) -> dict:
                       f"({tuples} tuples, {dt:.1f} s, naive Jacobi rounds per column)"}
 
 
+def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int) -> dict:
+    """Batched differentiable reachability on 512 grids: forward + query read +
+    BCE loss + backward to the edge probabilities, all samples in one engine
+    call, against the same engine run one sample at a time."""
+    import numpy as np
+    import torch
+    from paper_2503_21937_amd import dlfix, synth
+    from paper_2503_21937_amd.autograd import fixpoint
+
+    dev = torch.device("cuda")
+    g = synth.grid_batch(seed)
+    S = int(g["ks"].size)
+    ks = torch.tensor(g["ks"], device=dev)
+    labels = torch.tensor(g["labels"], device=dev)
+    src = torch.tensor(g["src"].astype(np.int32), device=dev)
+    dst = torch.tensor(g["dst"].astype(np.int32), device=dev)
+    sample = torch.tensor(g["sample"].astype(np.int32), device=dev)
+    p0 = torch.tensor(g["p"], device=dev)
+
+    def loss_of(tags, osample, ocols, kk, y):
+        target = (ocols[:, 0] == 0) & (ocols[:, 1].long() == kk[osample.long()] ** 2 - 1)
+        pred = tags[target].clamp(1e-6, 1 - 1e-6)
+        return torch.nn.functional.binary_cross_entropy(pred, y[osample[target].long()], reduction="sum")
+
+    eng = dlfix.Engine(synth.TC_PROGRAM, "diff_addmult", batched=True)
+
+    def batched_step():
+        probs = p0.clone().requires_grad_(True)
+        tags, osample, ocols = fixpoint(probs, eng, "edge", [src, dst], sample, "path")
+        loss_of(tags, osample, ocols, ks, labels).backward()
+        return probs.grad
+
+    for _ in range(warmup):
+        batched_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batched_step()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+    st = eng.stats()
+
+    plain = dlfix.Engine(synth.TC_PROGRAM, "diff_addmult")
+    sel = [(g["sample"] == s_) for s_ in range(plain_samples)]
+    per = []
+    for s_ in range(plain_samples):
+        m = torch.tensor(sel[s_], device=dev)
+        per.append((src[m].contiguous(), dst[m].contiguous(), p0[m].contiguous(), ks[s_:s_ + 1], labels[s_:s_ + 1]))
+
+    def plain_step(item):
+        a, b, pp, kk, y = item
+        probs = pp.clone().requires_grad_(True)
+        tags, osample, ocols = fixpoint(probs, plain, "edge", [a, b], None, "path")
+        loss_of(tags, osample, ocols, kk, y).backward()
+
+    plain_step(per[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for item in per:
+        plain_step(item)
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / plain_samples
+    return {"metric": "batched fwd+bwd samples/sec", "workload": f"{S} grids k~U{{5..30}}, diff add-mult, "
+            "query path(0,k^2-1), BCE loss, backward to edge probabilities",
+            "batched_samples_per_s": S / tb, "batched_ms_per_step": tb * 1e3,
+            "plain_samples_per_s": 1.0 / tp, "plain_sample_ms": tp * 1e3,
+            "plain_measured_on": f"first {plain_samples} samples", "speedup": (S / tb) * tp,
+            "derived_tuples": st["derived"], "rounds": st["max_rounds"], "lineage": st["lineage"]}
+
+
+def copy_calibration(mib: int) -> None:
+    """A plain device-to-device copy of known size, for scaling the HBM
+    traffic counters (FETCH_SIZE / WRITE_SIZE) of a profiled run."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 3}), flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +141,10 @@ def main() -> int:
     ap.add_argument("--edges", type=int, default=20000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grids", action="store_true", help="skip the batched fwd+bwd grid workload")
+    ap.add_argument("--plain-samples", type=int, default=32)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -71,6 +158,9 @@ def main() -> int:
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        copy_calibration(args.calibrate_copy)
+        return 0
     src, dst, p = synth.er_graph(args.seed, args.nodes, args.edges, weights=True)
     engines = []
     for sr in SEMIRINGS:
@@ -147,6 +237,8 @@ def main() -> int:
             "avg_launch_bytes": nbytes / launches if launches else 0.0,
         },
     }
+    if not args.no_grids:
+        line["batched"] = grids_fwd_bwd(max(1, min(args.steps, 3)), 1, args.seed, args.plain_samples)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(src, dst, p, args.nodes, args.cpu_budget, args.seed)
     print(json.dumps(line), flush=True)

@@ -74,6 +74,11 @@ typedef struct {
   int k;              /* top-k proof count, 1..3 (ignored otherwise; 0 = 3) */
   int batched;        /* 1: every fact carries a sample id; samples never join each other (Sec. 4.3) */
   void* stream;       /* hipStream_t to run on; NULL: the engine creates its own stream */
+  int dedup;          /* per-round deduplication of derived relations:
+                         0 = automatic (dense-domain when the packed key domain of the relation
+                             is at most 2^30 and the semiring is not top-k, else sort-based),
+                         1 = always sort-based (radix sort, unique, difference, merge),
+                         2 = dense-domain wherever possible */
 } dl_options;
 
 /* Result columns of dl_read_relation.  Any pointer may be NULL (not written).
@@ -101,6 +106,10 @@ typedef struct {
   uint32_t key_bits;      /* width of the packed keys (32 or 64) */
   uint32_t id_bits;       /* bits per column value */
   uint32_t sample_bits;   /* bits of the sample id */
+  int dedup;              /* deduplication setting in force (see dl_options.dedup) */
+  int orient;             /* delta-plan orientation in force: 0 auto, 1 recent-driven, 2 static-driven */
+  int items;              /* join expand tile in force: outputs per thread */
+  double tuned_ms;        /* median run time of the configuration dl_autotune chose */
 } dl_stats;
 
 /* Kernel families timed by dl_profile (bit i of the mask = family i). */
@@ -178,6 +187,19 @@ dl_status dl_read_grad(dl_engine* e, const char* in_relation, float* grad_in, in
 dl_status dl_zero_grad(dl_engine* e);
 
 dl_status dl_get_stats(const dl_engine* e, dl_stats* out);
+
+/* Autotuner.  Times dl_run_fixpoint on the current facts under every
+ * candidate execution configuration -- deduplication (sort-based or
+ * dense-domain), orientation of the delta joins of 2-atom rules (recent
+ * tuples probe the static side, or the static side probes an index over the
+ * recent tuples) and the join expand tile (1, 2, 4 or 8 outputs per thread) --
+ * and keeps the fastest (median of `trials` runs after a warm-up run) for
+ * later runs.  All candidates compute the same relations.  If cache_path is
+ * not NULL the choice is first looked up there, keyed by a hash of the program
+ * text, the semiring, the key layout and log2 of the fact count, and stored
+ * there (one JSON object per line) after tuning.  Ends with a run under the
+ * chosen configuration. */
+dl_status dl_autotune(dl_engine* e, int trials, const char* cache_path);
 
 /* Time the kernel families in `family_mask` with HIP events recorded on the
  * engine's stream around each launch (0 switches timing off).  Resets the

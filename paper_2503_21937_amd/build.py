@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdlfix.so")
-SOURCES = ["program.cpp", "engine.hip", "engine_run.hip", "k_prims.hip", "k_rel.hip"]
+SOURCES = ["program.cpp", "engine.hip", "engine_run.hip", "k_prims.hip", "k_rel.hip", "k_dense.hip"]
 HEADERS = ["dl_device.h", "kernels.h", "engine.h", "program.h"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -51,6 +51,13 @@ struct RelState {
   DevBuf cand_keys, cand_tags, cand_l, cand_r;  // this round's derivations (head rows)
   size_t ncand = 0;
   uint64_t version = 0;  // bumped whenever `full` changes (keys or tags)
+  uint64_t rversion = 0; // bumped whenever `recent` changes
+  // dense-domain deduplication (derived relations whose keys are < 2^dense_w)
+  bool dense = false;
+  int dense_w = 0;
+  bool own_index = false;  // a plan of its own stratum joins against it
+  DevBuf present, touched, dtag, did, log_keys, log_l, log_r, seg_lcount;
+  size_t nseg = 0;         // lineage wave segments emitted this round
   DevBuf fact_entry;  // input facts -> entry id
   DevBuf grad;        // accumulated input gradients (per fact)
   std::vector<uint32_t> fact_slot;  // top-k: sample*64 + local id per fact (host)
@@ -70,8 +77,16 @@ struct LineageSeg {
   size_t off, n;
 };
 
+// Execution choices the autotuner picks among (all give the same result).
+struct ExecConfig {
+  int items = 4;   // join expand tile: outputs per thread (1, 2, 4, 8)
+  int orient = 0;  // delta plans of 2-atom rules: 0 auto, 1 recent-driven, 2 static-driven
+};
+
 struct Engine {
   Program prog;
+  std::string text;
+  ExecConfig cfg;
   dl_options opts{};
   int sr = 0;
   int k = 3;
@@ -134,6 +149,8 @@ struct Engine {
   void backward(const char* out_relation, const float* grad_out, int on_device);
   void read_grad(const char* in_relation, float* grad_in, int on_device);
   void zero_grad();
+  void autotune(int trials, const char* cache_path);
+  std::string tune_key() const;
 
   int relation_id(const char* name, bool must_exist = true);
   KeyLayout layout(int ncols) const { return KeyLayout{ncols, cbits, sbits}; }

@@ -1,6 +1,7 @@
 // Engine lifecycle, fact staging, device memory and the C ABI (dlfix.h).
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 
 #include "dl_device.h"
@@ -54,6 +55,8 @@ Engine::~Engine() {
     for (Table* t : {&r.full, &r.full_alt, &r.recent}) fr(t->keys), fr(t->tags), fr(t->ids);
     fr(r.fact_entry), fr(r.grad), fr(r.fact_slot_d);
     fr(r.cand_keys), fr(r.cand_tags), fr(r.cand_l), fr(r.cand_r);
+    for (DevBuf* b : {&r.present, &r.touched, &r.dtag, &r.did, &r.log_keys, &r.log_l, &r.log_r, &r.seg_lcount})
+      fr(*b);
   }
   for (auto& x : idx) {
     if (!x.borrowed) fr(x.t.keys), fr(x.t.tags), fr(x.t.ids);
@@ -117,7 +120,8 @@ int Engine::relation_id(const char* name, bool must_exist) {
   return r;
 }
 
-void Engine::init(const char* text, const dl_options* o) {
+void Engine::init(const char* program_text, const dl_options* o) {
+  text = program_text;
   opts = *o;
   sr = o->semiring;
   if (sr < DL_BOOL || sr > DL_DIFF_TOPK) throw Error{DL_ERR_ARG, "unknown semiring"};
@@ -129,11 +133,18 @@ void Engine::init(const char* text, const dl_options* o) {
   tag_kind = sr == DL_BOOL ? TAG_NONE : (sr == DL_TOPK || sr == DL_DIFF_TOPK) ? TAG_TOPK : TAG_F32;
   tag_bytes = tag_kind == TAG_NONE ? 0 : tag_kind == TAG_F32 ? 4 : sizeof(TopK);
   std::string perr;
-  int rc = parse_and_plan(text, !converge, lineage, prog, perr);
+  int rc = parse_and_plan(program_text, !converge, lineage, prog, perr);
   if (rc) throw Error{(dl_status)rc, perr};
   rel.assign(prog.rels.size(), RelState{});
   for (size_t r = 0; r < prog.rels.size(); ++r) rel[r].raw_cols.assign(prog.rels[r].arity, DevBuf{});
   idx.assign(prog.indexes.size(), IndexState{});
+  if (o->dedup < 0 || o->dedup > 2) throw Error{DL_ERR_ARG, "dedup must be 0, 1 or 2"};
+  for (const Plan& pl : prog.plans)
+    for (const Step& st : pl.steps) {
+      const IndexSpec& ix = prog.indexes[st.index];
+      if (!ix.recent && prog.rels[ix.rel].derived && prog.rels[ix.rel].stratum == prog.rels[pl.head_rel].stratum)
+        rel[ix.rel].own_index = true;
+    }
   if (o->stream) {
     stream = (hipStream_t)o->stream;
   } else {
@@ -257,6 +268,9 @@ void Engine::run() {
   ran = true;
   stats.run_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   stats.device_bytes = device_bytes;
+  stats.dedup = opts.dedup;
+  stats.orient = cfg.orient;
+  stats.items = cfg.items;
 }
 
 size_t Engine::relation_size(const char* relation) {
@@ -316,6 +330,107 @@ void Engine::zero_grad() {
     if (R.grad.p) DL_HIP(hipMemsetAsync(R.grad.p, 0, R.grad.cap, stream));
   if (grad_fact.p) DL_HIP(hipMemsetAsync(grad_fact.p, 0, grad_fact.cap, stream));
   sync();
+}
+
+// ------------------------------------------------------------- autotuner
+// Key of a tuning decision: the program, the semiring, the packed key width
+// and the input size class (log2 of the fact count).
+std::string Engine::tune_key() const {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the program text
+  for (unsigned char c : text) h = (h ^ c) * 1099511628211ull;
+  size_t facts = 0;
+  for (const auto& r : rel) facts += r.nraw;
+  int lg = 0;
+  while (((size_t)1 << lg) < facts) ++lg;
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%016llx/sr%d/k%d/b%d/key%d/id%d/s%d/f%d", (unsigned long long)h, sr, k,
+                (int)batched, key64 ? 64 : 32, cbits, sbits, lg);
+  return buf;
+}
+
+namespace {
+struct Tuned {
+  int dedup, orient, items;
+  double ms;
+};
+
+bool cache_lookup(const char* path, const std::string& key, Tuned* t) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {  // later lines override earlier ones
+    char k[200];
+    Tuned x{};
+    if (std::sscanf(line, "{\"key\": \"%199[^\"]\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"ms\": %lf",
+                    k, &x.dedup, &x.orient, &x.items, &x.ms) == 5 &&
+        key == k) {
+      *t = x;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const Tuned& t) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%s\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"ms\": %.4f}\n", key.c_str(),
+               t.dedup, t.orient, t.items, t.ms);
+  std::fclose(f);
+}
+}  // namespace
+
+// Time the fixpoint under every candidate configuration on the current facts
+// (median of `trials` runs after one warm-up run) and keep the fastest.
+void Engine::autotune(int trials, const char* cache_path) {
+  if (trials < 1) trials = 1;
+  if (!ingested) run();  // fixes the key layout the decision is keyed on
+  const std::string key = tune_key();
+  Tuned best{opts.dedup, cfg.orient, cfg.items, 1e300};
+  if (cache_path && cache_lookup(cache_path, key, &best)) {
+    opts.dedup = best.dedup;
+    cfg.orient = best.orient;
+    cfg.items = best.items;
+    return;
+  }
+  bool twins = false;
+  for (const Plan& pl : prog.plans) twins = twins || pl.alt >= 0;
+  const int saved_dedup = opts.dedup;
+  const ExecConfig saved = cfg;
+  for (int dedup : {1, 2}) {
+    for (int orient : {1, 2}) {
+      if (orient == 2 && !twins) continue;
+      for (int items : {1, 2, 4, 8}) {
+        opts.dedup = dedup;
+        cfg.orient = orient;
+        cfg.items = items;
+        std::vector<double> ms;
+        try {
+          run();
+          for (int t = 0; t < trials; ++t) {
+            run();
+            ms.push_back(stats.run_ms);
+          }
+        } catch (const Error& x) {
+          if (x.code == DL_ERR_UNSUPPORTED) continue;  // e.g. no dense domain
+          opts.dedup = saved_dedup;
+          cfg = saved;
+          throw;
+        }
+        std::sort(ms.begin(), ms.end());
+        const double med = ms[ms.size() / 2];
+        if (med < best.ms) best = Tuned{dedup, orient, items, med};
+      }
+    }
+  }
+  opts.dedup = best.dedup;
+  cfg.orient = best.orient;
+  cfg.items = best.items;
+  stats.tuned_ms = best.ms;
+  if (cache_path) cache_store(cache_path, key, best);
+  run();  // leave the results of the chosen configuration in place
 }
 
 }  // namespace dlfix
@@ -419,6 +534,10 @@ dl_status dl_get_stats(const dl_engine* h, dl_stats* out) {
   if (!h || !out) return DL_ERR_ARG;
   *out = h->e.stats;
   return DL_OK;
+}
+
+dl_status dl_autotune(dl_engine* h, int trials, const char* cache_path) {
+  return guard(h, [&] { h->e.autotune(trials, cache_path); });
 }
 
 dl_status dl_profile(dl_engine* h, uint32_t family_mask) {

@@ -51,14 +51,88 @@ void claim(DevBuf& owner, DevBuf& alt, const void* result) {
   if (result == alt.p) std::swap(owner, alt);
 }
 
+DenseArgs dense_args(Engine& e, RelState& R) {
+  DenseArgs d{};
+  d.present = R.present.as<uint32_t>();
+  d.touched = R.touched.as<uint32_t>();
+  d.dtag = R.dtag.as<uint32_t>();
+  d.did = e.lineage ? R.did.as<uint32_t>() : nullptr;
+  d.log_keys = R.log_keys.p;
+  d.log_l = R.log_l.as<uint32_t>();
+  d.log_r = R.log_r.as<uint32_t>();
+  d.seg_lcount = R.seg_lcount.as<uint32_t>();
+  d.seg_base = (uint32_t)R.nseg;
+  d.mode = e.sr == DL_BOOL ? DENSE_BOOL : !e.converge ? DENSE_ADD : e.sr == DL_MAXMIN ? DENSE_MAX : DENSE_MIN;
+  return d;
+}
+
+// Decide the deduplication of every derived relation and reset the dense
+// state (presence, touched, semiring zero in every tag word).
+void setup_dense(Engine& e) {
+  const size_t budget = (size_t)16 << 30;
+  for (size_t r = 0; r < e.rel.size(); ++r) {
+    RelState& R = e.rel[r];
+    R.dense = false;
+    if (!e.prog.rels[r].derived) continue;
+    const int w = e.key_width(e.prog.rels[r].arity);
+    const size_t keys = (size_t)1 << std::min(w, 40);
+    const size_t bytes = 2 * bitmap_words(w) * 4 + (e.tag_kind == TAG_F32 ? keys * 4 : 0) + (e.lineage ? keys * 4 : 0);
+    const bool fits = e.tag_kind != TAG_TOPK && w <= 31 && bytes <= budget;
+    if (e.opts.dedup == 2 && !fits)
+      throw Error{DL_ERR_UNSUPPORTED, "dense-domain deduplication does not fit relation " + e.prog.rels[r].name};
+    R.dense = fits && e.opts.dedup != 1;
+    if (!R.dense) continue;
+    R.dense_w = w;
+    const size_t words = bitmap_words(w);
+    e.grow(R.present, words * 4);
+    e.grow(R.touched, words * 4);
+    DL_HIP(hipMemsetAsync(R.present.p, 0, words * 4, e.stream));
+    DL_HIP(hipMemsetAsync(R.touched.p, 0, words * 4, e.stream));
+    if (e.tag_kind == TAG_F32) {
+      e.grow(R.dtag, keys * 4);
+      fill_u32(R.dtag.as<uint32_t>(), keys, dense_init_word(dense_args(e, R).mode), e.stream);
+    }
+    if (e.lineage) e.grow(R.did, keys * 4);
+    R.nseg = 0;
+  }
+}
+
+// Sorted full relation of a dense relation, from its presence bitmap.
+template <typename K>
+void materialize_full(Engine& e, RelState& R) {
+  const size_t words = bitmap_words(R.dense_w);
+  e.grow(e.flags, words * 4);
+  e.grow(e.pos, (words + 1) * 4);
+  bitmap_popcounts(R.present.as<uint32_t>(), words, e.flags.as<uint32_t>(), e.stream);
+  ensure_scratch(e, scan_scratch_words(words));
+  scan_u32(e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), words, total_slot(e, S_SCAN), true,
+           e.scratch.as<uint64_t>(), e.stream);
+  const size_t F = e.read_total(S_SCAN);
+  e.grow(R.full.keys, F * sizeof(K) + 8);
+  float* tags = nullptr;
+  uint32_t* ids = nullptr;
+  if (e.tag_kind == TAG_F32) {
+    e.grow(R.full.tags, F * 4 + 8);
+    tags = R.full.tags.as<float>();
+  }
+  if (e.lineage) {
+    e.grow(R.full.ids, F * 4 + 8);
+    ids = R.full.ids.as<uint32_t>();
+  }
+  bitmap_keys<K>(dense_args(e, R), R.dense_w, e.pos.as<uint32_t>(), R.full.keys.as<K>(), tags, ids, e.stream);
+  R.full.n = F;
+  ++R.version;
+}
+
 template <typename K>
 void build_index(Engine& e, int i) {
   const IndexSpec& spec = e.prog.indexes[i];
   IndexState& ix = e.idx[i];
   RelState& R = e.rel[spec.rel];
+  const Table& src = spec.recent ? R.recent : R.full;
   const int ar = e.prog.rels[spec.rel].arity;
   const KeyLayout lay = e.layout(ar);
-  const size_t n = R.full.n;
+  const size_t n = src.n;
   const int pbits = e.sbits + spec.w * e.cbits;
   if (pbits > 30) throw Error{DL_ERR_UNSUPPORTED, "join key domain above 2^30 (index on " + e.prog.rels[spec.rel].name + ")"};
   if (spec.identity()) {
@@ -66,9 +140,9 @@ void build_index(Engine& e, int i) {
       e.release(ix.t.keys), e.release(ix.t.tags), e.release(ix.t.ids);
       ix.borrowed = true;
     }
-    ix.t.keys = R.full.keys;
-    ix.t.tags = R.full.tags;
-    ix.t.ids = R.full.ids;
+    ix.t.keys = src.keys;
+    ix.t.tags = src.tags;
+    ix.t.ids = src.ids;
   } else {
     if (ix.borrowed) {
       ix.t = Table{};
@@ -76,7 +150,7 @@ void build_index(Engine& e, int i) {
     }
     e.grow(ix.t.keys, n * sizeof(K) + 8);
     e.grow(e.vals, n * 4 + 4);
-    permute_keys<K>(R.full.keys.as<K>(), n, lay, spec.perm.data(), ix.t.keys.as<K>(), e.stream);
+    permute_keys<K>(src.keys.as<K>(), n, lay, spec.perm.data(), ix.t.keys.as<K>(), e.stream);
     iota_u32(e.vals.as<uint32_t>(), n, 0, e.stream);
     K* kp = ix.t.keys.as<K>();
     uint32_t* vp = e.vals.as<uint32_t>();
@@ -85,26 +159,28 @@ void build_index(Engine& e, int i) {
     claim(e.vals, e.alt_vals, vp);
     if (e.tag_bytes) {
       e.grow(ix.t.tags, n * e.tag_bytes + 8);
-      gather(R.full.tags.p, e.vals.as<uint32_t>(), ix.t.tags.p, n, e.tag_bytes, e.stream);
+      gather(src.tags.p, e.vals.as<uint32_t>(), ix.t.tags.p, n, e.tag_bytes, e.stream);
     }
     if (e.lineage) {
       e.grow(ix.t.ids, n * 4 + 4);
-      gather(R.full.ids.p, e.vals.as<uint32_t>(), ix.t.ids.p, n, 4, e.stream);
+      gather(src.ids.p, e.vals.as<uint32_t>(), ix.t.ids.p, n, 4, e.stream);
     }
   }
   ix.t.n = n;
   e.grow(ix.off, (((size_t)1 << pbits) + 1) * 4);
   csr_build<K>(ix.t.keys.as<K>(), n, e.key_width(ar), pbits, ix.off.as<uint32_t>(), e.stream);
   ix.built = true;
-  ix.version = R.version;
+  ix.version = spec.recent ? R.rversion : R.version;
 }
 
 template <typename K>
 void ensure_index(Engine& e, int i) {
   IndexState& ix = e.idx[i];
-  const RelState& R = e.rel[e.prog.indexes[i].rel];
-  bool stale = !ix.built || ix.version != R.version;
-  if (ix.borrowed && ix.t.keys.p != R.full.keys.p) stale = true;
+  const IndexSpec& spec = e.prog.indexes[i];
+  const RelState& R = e.rel[spec.rel];
+  const Table& src = spec.recent ? R.recent : R.full;
+  bool stale = !ix.built || ix.version != (spec.recent ? R.rversion : R.version);
+  if (ix.borrowed && ix.t.keys.p != src.keys.p) stale = true;
   if (stale) build_index<K>(e, i);
 }
 
@@ -131,6 +207,7 @@ void run_plan(Engine& e, const Plan& pl) {
   a.sr = e.sr;
   a.k = e.k;
   a.q = e.qtab.as<float>();
+  a.items = e.cfg.items;
 
   auto head_room = [&](size_t add) {
     const size_t used = H.ncand;
@@ -148,6 +225,24 @@ void run_plan(Engine& e, const Plan& pl) {
     *orr = e.lineage ? H.cand_r.as<uint32_t>() + H.ncand : nullptr;
   };
 
+  // Room for an emission over `add` slots: one wave segment per 256 slots;
+  // returns the emission's arguments (segments start after the round's
+  // earlier emissions into the same relation).
+  auto dense_room = [&](size_t add, int items) {
+    const size_t used = H.nseg, segs = e.lineage ? dense_segments(add, items) : 0;
+    const size_t slots = (used + segs) * DENSE_SEG, uslots = used * DENSE_SEG;
+    if (e.lineage) {
+      e.grow(H.log_keys, slots * sizeof(K), true, uslots * sizeof(K));
+      e.grow(H.log_l, slots * 4, true, uslots * 4);
+      e.grow(H.log_r, slots * 4, true, uslots * 4);
+      e.grow(H.seg_lcount, (used + segs) * 4, true, used * 4);
+    }
+    e.stats.candidates += add;
+    DenseArgs d = dense_args(e, H);
+    H.nseg = used + segs;
+    return d;
+  };
+
   if (pl.steps.empty()) {  // single-atom rule: permutation projection, tags copied
     a.dkeys = cur.keys;
     a.dtags = cur.tags;
@@ -156,6 +251,11 @@ void run_plan(Engine& e, const Plan& pl) {
     a.dlay = e.layout(cur.ncols);
     a.olay = e.layout(har);
     for (int c = 0; c < har; ++c) a.osrc[c] = pl.project[c];
+    if (H.dense) {
+      const DenseArgs d = dense_room(cur.n, 4);
+      project_dense<K>(a, e.tag_kind, d, e.lineage, e.stream);
+      return;
+    }
     head_room(cur.n);
     void *ok, *ot;
     uint32_t *ol, *orr;
@@ -199,6 +299,11 @@ void run_plan(Engine& e, const Plan& pl) {
     if (total > 0xffffffffull) throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
     if (total == 0) return;
     const bool last = si + 1 == pl.steps.size();
+    if (last && H.dense) {
+      const DenseArgs d = dense_room(total, a.items);
+      join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), total, d, e.lineage, e.stream);
+      return;
+    }
     void *ok, *ot;
     uint32_t *ol = nullptr, *orr = nullptr;
     if (last) {
@@ -221,10 +326,74 @@ void run_plan(Engine& e, const Plan& pl) {
   }
 }
 
+// Dense-domain round end: the touched keys are exactly the new and changed
+// tuples; sort them into the next recent relation and publish their state.
+template <typename K>
+size_t absorb_dense(Engine& e, int r) {
+  RelState& R = e.rel[r];
+  hipStream_t st = e.stream;
+  const size_t nseg = R.nseg;
+  R.nseg = 0;
+  // touched popcounts -> positions of the new / changed tuples in key order
+  const size_t words = bitmap_words(R.dense_w);
+  e.grow(e.flags, words * 4);
+  e.grow(e.pos, (words + 1) * 4);
+  bitmap_popcounts(R.touched.as<uint32_t>(), words, e.flags.as<uint32_t>(), st);
+  scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), words, S_UNIQUE, true);
+  if (e.lineage && nseg) {
+    e.grow(e.lpos, (nseg + 1) * 4);
+    scan(e, R.seg_lcount.as<uint32_t>(), e.lpos.as<uint32_t>(), nseg, S_LIN, true);
+  }
+  e.read_totals();
+  const size_t U = e.host[S_UNIQUE], L = e.lineage && nseg ? e.host[S_LIN] : 0;
+  if (U == 0) {
+    R.recent.n = 0;
+    return 0;
+  }
+  e.stats.unique += U;
+  e.grow(R.recent.keys, U * sizeof(K) + 8);
+  float* rtags = nullptr;
+  if (e.tag_kind == TAG_F32) {
+    e.grow(R.recent.tags, U * 4 + 8);
+    rtags = R.recent.tags.as<float>();
+  }
+  const uint32_t base = e.next_id;
+  if (e.lineage) e.grow(e.tag_by_id, ((size_t)base + U) * 4, true, (size_t)base * 4);
+  DenseArgs d = dense_args(e, R);
+  dense_finalize<K>(d, R.dense_w, e.pos.as<uint32_t>(), R.recent.keys.as<K>(), rtags, base,
+                    e.lineage ? e.tag_by_id.as<float>() : nullptr, st);
+  if (e.lineage) {
+    e.grow(R.recent.ids, U * 4 + 4);
+    iota_u32(R.recent.ids.as<uint32_t>(), U, base, st);
+    const size_t used = e.lin_n;
+    e.grow(e.lin_owner, (used + L) * 4 + 4, true, used * 4);
+    e.grow(e.lin_l, (used + L) * 4 + 4, true, used * 4);
+    e.grow(e.lin_r, (used + L) * 4 + 4, true, used * 4);
+    if (L) {
+      e.grow(e.nkeys, L * sizeof(K) + 8);
+      const uint32_t* lc = R.seg_lcount.as<uint32_t>();
+      segments_compact(R.log_keys.p, lc, e.lpos.as<uint32_t>(), nseg, sizeof(K), e.nkeys.p, st);
+      segments_compact(R.log_l.p, lc, e.lpos.as<uint32_t>(), nseg, 4, e.lin_l.as<uint32_t>() + used, st);
+      segments_compact(R.log_r.p, lc, e.lpos.as<uint32_t>(), nseg, 4, e.lin_r.as<uint32_t>() + used, st);
+      dense_owners<K>(d, e.nkeys.as<K>(), L, e.lin_owner.as<uint32_t>() + used, st);
+    }
+    e.lin_segs.push_back({used, L});
+    e.lin_n = used + L;
+    e.stats.lineage += L;
+    e.next_id = base + (uint32_t)U;
+  }
+  R.recent.n = U;
+  ++R.version;
+  ++R.rversion;
+  if (R.own_index) materialize_full<K>(e, R);
+  return U;
+}
+
 // Deduplicate a relation's candidates and fold them into the store.
 // Returns the number of tuples that are new or changed (the next recent).
 template <typename K>
 size_t absorb(Engine& e, int r) {
+  if (e.rel[r].dense) return absorb_dense<K>(e, r);
   RelState& R = e.rel[r];
   const size_t C = R.ncand;
   R.ncand = 0;
@@ -291,6 +460,7 @@ size_t absorb(Engine& e, int r) {
     compact(e.utags.p, rfl, rps, U, tb, R.recent.tags.p, st);
   }
   R.recent.n = Rn;
+  ++R.rversion;
   if (Rn && e.converge) ++R.version;  // in-place tag updates
   if (N == 0) return Rn;
 
@@ -453,6 +623,7 @@ void run_fixpoint(Engine& e) {
   e.next_id = edb;
   e.lin_n = 0;
   e.lin_segs.clear();
+  setup_dense(e);
   for (const Stratum& st : e.prog.strata) {
     int rounds = 1;
     for (int p : st.base_plans) run_plan<K>(e, e.prog.plans[p]);
@@ -460,12 +631,21 @@ void run_fixpoint(Engine& e) {
     for (int r : st.rels) changed += absorb<K>(e, r);
     while (changed && !st.delta_plans.empty()) {
       ++rounds;
-      for (int p : st.delta_plans) run_plan<K>(e, e.prog.plans[p]);
+      for (int p : st.delta_plans) {
+        const Plan& pl = e.prog.plans[p];
+        // orientation: by default dense heads take the static-driven twin
+        // (outputs grouped by the static side: coalesced dense accesses)
+        const bool twin = pl.alt >= 0 && (e.cfg.orient == 2 || (e.cfg.orient == 0 && e.rel[pl.head_rel].dense));
+        run_plan<K>(e, twin ? e.prog.plans[pl.alt] : pl);
+      }
       changed = 0;
       for (int r : st.rels) changed += absorb<K>(e, r);
     }
     if (changed) ++rounds;  // non-recursive stratum: its second round derives nothing
-    for (int r : st.rels) e.rel[r].recent.n = 0;
+    for (int r : st.rels) {
+      if (e.rel[r].dense) materialize_full<K>(e, e.rel[r]);
+      e.rel[r].recent.n = 0;
+    }
     e.stats.strata += 1;
     e.stats.rounds += rounds;
     e.stats.max_rounds = std::max(e.stats.max_rounds, rounds);

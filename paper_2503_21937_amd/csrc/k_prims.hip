@@ -70,6 +70,31 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t* __restrict_
   if (sentinel && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = (uint32_t)*d_total;
 }
 
+// Whole scan in one workgroup when n <= SCAN_TILE (one launch instead of three).
+__global__ __launch_bounds__(BLOCK) void k_scan_small(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                      size_t n, uint64_t* __restrict__ d_total, int sentinel) {
+  __shared__ uint64_t tmp[NWAVES];
+  const size_t base = (size_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS];
+  uint64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0u;
+    s += v[i];
+  }
+  uint64_t tot;
+  uint64_t run = block_exclusive_scan(s, tmp, &tot);
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = (uint32_t)run;
+    run += v[i];
+  }
+  if (threadIdx.x == 0) {
+    *d_total = tot;
+    if (sentinel) out[n] = (uint32_t)tot;
+  }
+}
+
 __global__ void k_empty_scan(uint32_t* out, uint64_t* d_total, int sentinel) {
   *d_total = 0;
   if (sentinel) out[0] = 0;
@@ -83,6 +108,11 @@ void scan_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* d_total, bo
   }
   size_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
   DL_PROF_BEGIN(4, st);
+  if (nb == 1) {
+    k_scan_small<<<1, BLOCK, 0, st>>>(in, out, n, d_total, sentinel ? 1 : 0);
+    DL_PROF_END(4, st, n * 8.0);
+    return;
+  }
   k_scan_reduce<<<nb, BLOCK, 0, st>>>(in, n, scratch);
   k_scan_partials<<<1, BLOCK, 0, st>>>(scratch, nb, d_total);
   k_scan_down<<<nb, BLOCK, 0, st>>>(in, out, n, scratch, d_total, sentinel ? 1 : 0);

@@ -3,37 +3,10 @@
 // column gather and x of the tags), +-reduction of equal keys, the
 // difference / +-merge against the full relation, merge-path merge, and the
 // tag and gradient kernels.
-#include "dl_device.h"
-#include "kernels.h"
 #include "prof.h"
+#include "rel_device.h"
 
 namespace dlfix {
-
-static unsigned grid_for(size_t n, size_t per_block = BLOCK) {
-  size_t b = (n + per_block - 1) / per_block;
-  return (unsigned)(b < 65536 ? (b ? b : 1) : 65536);
-}
-
-#define GRID_STRIDE(i, n) \
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
-
-// ------------------------------------------------------------ key helpers
-__device__ __forceinline__ uint32_t cmask(int cbits) { return (uint32_t)((1ull << cbits) - 1); }
-
-template <typename K>
-__device__ __forceinline__ uint32_t key_col(K key, int c, const KeyLayout& l) {
-  return (uint32_t)((uint64_t)key >> ((l.ncols - 1 - c) * l.cbits)) & cmask(l.cbits);
-}
-template <typename K>
-__device__ __forceinline__ uint32_t key_sample(K key, const KeyLayout& l) {
-  return l.sbits ? (uint32_t)((uint64_t)key >> (l.ncols * l.cbits)) : 0u;
-}
-template <typename K>
-__device__ __forceinline__ K key_make(uint32_t sample, const uint32_t* cols, const KeyLayout& l) {
-  uint64_t k = l.sbits ? (uint64_t)sample << (l.ncols * l.cbits) : 0ull;
-  for (int c = 0; c < l.ncols; ++c) k |= (uint64_t)cols[c] << ((l.ncols - 1 - c) * l.cbits);
-  return (K)k;
-}
 
 template <typename K>
 __global__ void k_pack(const uint32_t* c0, const uint32_t* c1, const uint32_t* c2, const uint32_t* c3,
@@ -119,13 +92,6 @@ void csr_build(const K* keys, size_t n, int total_bits, int prefix_bits, uint32_
 
 // ------------------------------------------------------------------ joins
 template <typename K>
-__device__ __forceinline__ uint64_t join_prefix(K dkey, const JoinArgs& a) {
-  uint64_t p = a.ilay.sbits ? (uint64_t)key_sample(dkey, a.dlay) << (a.w * a.ilay.cbits) : 0ull;
-  for (int j = 0; j < a.w; ++j) p |= (uint64_t)key_col(dkey, a.jsrc[j], a.dlay) << ((a.w - 1 - j) * a.ilay.cbits);
-  return p;
-}
-
-template <typename K>
 __global__ void k_join_count(JoinArgs a, uint32_t* __restrict__ counts) {
   const K* dk = (const K*)a.dkeys;
   GRID_STRIDE(i, a.n) {
@@ -142,51 +108,14 @@ void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st) {
   DL_PROF_END(0, st, a.n * (sizeof(K) + 12.0));
 }
 
-template <int TK>
-struct TagOf {
-  using T = NoTag;
-};
-template <>
-struct TagOf<TAG_F32> {
-  using T = float;
-};
-template <>
-struct TagOf<TAG_TOPK> {
-  using T = TopK;
-};
 
-template <int TK>
-__device__ __forceinline__ typename TagOf<TK>::T tag_otimes(const typename TagOf<TK>::T& x,
-                                                           const typename TagOf<TK>::T& y, const JoinArgs& a,
-                                                           uint32_t sample) {
-  if constexpr (TK == TAG_F32) {
-    return f_otimes(a.sr, x, y);
-  } else if constexpr (TK == TAG_TOPK) {
-    return topk_otimes(x, y, a.k, a.q + (size_t)sample * 64);
-  } else {
-    return NoTag{};
-  }
-}
-
-constexpr int EXP_ITEMS = 4;
-constexpr int EXP_TILE = BLOCK * EXP_ITEMS;
-constexpr int EXP_LDS = 2 * EXP_TILE;
-
-__device__ __forceinline__ size_t upper_bound_u32(const uint32_t* a, size_t n, uint32_t x) {
-  size_t lo = 0, hi = n;
-  while (lo < hi) {
-    size_t mid = (lo + hi) >> 1;
-    if (a[mid] <= x) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
-template <typename K, int TK>
+template <typename K, int TK, int EXP_ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_join_expand(JoinArgs a, const uint32_t* __restrict__ offs, size_t total,
                                                        K* __restrict__ okeys, typename TagOf<TK>::T* __restrict__ otags,
                                                        uint32_t* __restrict__ ol, uint32_t* __restrict__ orr) {
   using T = typename TagOf<TK>::T;
+  constexpr int EXP_TILE = BLOCK * EXP_ITEMS;
+  constexpr int EXP_LDS = 2 * EXP_TILE;
   __shared__ uint32_t s_off[EXP_LDS];
   __shared__ size_t s_r0, s_r1;
   const K* dk = (const K*)a.dkeys;
@@ -247,19 +176,28 @@ template <typename K>
 void join_expand(const JoinArgs& a, int tk, const uint32_t* offs, size_t total, void* okeys, void* otags, uint32_t* ol,
                  uint32_t* orr, hipStream_t st) {
   if (!total) return;
-  size_t nb = (total + EXP_TILE - 1) / EXP_TILE;
+  const int items = a.items == 1 || a.items == 2 || a.items == 8 ? a.items : 4;
+  const size_t nb = (total + (size_t)BLOCK * items - 1) / ((size_t)BLOCK * items);
   const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : (double)sizeof(TopK);
   const double lin = ol ? 4.0 : 0.0;
   // outputs written, index rows read once per output, driver rows and offsets read once
   const double bytes = total * (sizeof(K) + tb + 2 * lin) + total * (sizeof(K) + tb + lin) +
                        a.n * (sizeof(K) + tb + lin + 4.0);
+#define DL_EXPAND(IT)                                                                                          \
+  if (tk == TAG_NONE)                                                                                          \
+    k_join_expand<K, TAG_NONE, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (NoTag*)otags, ol, orr);  \
+  else if (tk == TAG_F32)                                                                                      \
+    k_join_expand<K, TAG_F32, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (float*)otags, ol, orr);   \
+  else                                                                                                         \
+    k_join_expand<K, TAG_TOPK, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (TopK*)otags, ol, orr);
   DL_PROF_BEGIN(1, st);
-  if (tk == TAG_NONE)
-    k_join_expand<K, TAG_NONE><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (NoTag*)otags, ol, orr);
-  else if (tk == TAG_F32)
-    k_join_expand<K, TAG_F32><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (float*)otags, ol, orr);
-  else
-    k_join_expand<K, TAG_TOPK><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (TopK*)otags, ol, orr);
+  switch (items) {
+    case 1: DL_EXPAND(1) break;
+    case 2: DL_EXPAND(2) break;
+    case 8: DL_EXPAND(8) break;
+    default: DL_EXPAND(4) break;
+  }
+#undef DL_EXPAND
   DL_PROF_END(1, st, bytes);
 }
 

@@ -81,7 +81,36 @@ struct JoinArgs {
   int k;        // top-k proof count
   const float* q;  // top-k: per-sample probabilities [sample][64]
   bool index_first;  // x operand order: index tag first (body order)
+  int items;         // expand tile: join outputs per thread (1, 2, 4 or 8)
 };
+
+// Dense-domain deduplication state of one derived relation (key < 2^w):
+// presence and "touched this round" bitmaps, a dense tag word per key and the
+// list of keys touched this round.  Survivors of a join are folded into the
+// dense tag with integer atomics; a derivation that cannot change the
+// relation (key present under frozen tags, or no strict improvement under
+// max / min) is dropped in the join itself.
+enum DenseMode : int { DENSE_BOOL = 0, DENSE_ADD = 1, DENSE_MAX = 2, DENSE_MIN = 3 };
+struct DenseArgs {
+  uint32_t* present;   // bitmap, stable during a round
+  uint32_t* touched;   // bitmap, cleared by dense_finalize
+  uint32_t* dtag;      // per key: f32 bits (DENSE_ADD) or order-preserving u32 of the f32 tag
+  uint32_t* did;       // per key: tuple id (lineage), written by dense_finalize
+  // Lineage entries go to wave-private segments of DENSE_SEG slots: segment
+  // s holds seg_lcount[s] entries at log_*[s * DENSE_SEG ...];
+  // segments_compact gathers them in segment order.
+  void* log_keys;      // lineage log (DENSE_ADD with lineage): key, left id, right id
+  uint32_t* log_l;
+  uint32_t* log_r;
+  uint32_t* seg_lcount;
+  uint32_t seg_base;   // first segment of this launch
+  int mode;
+};
+constexpr int DENSE_SEG = 512;  // slots per wave segment (64 lanes x up to 8 rows)
+// Segments a dense emission over n slots with `items` outputs per thread uses.
+size_t dense_segments(size_t n, int items);
+// Initial dense tag word (semiring zero) for a mode.
+uint32_t dense_init_word(int mode);
 
 // counts[i] = number of index rows matching driver row i.
 template <typename K>
@@ -91,6 +120,32 @@ void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st);
 template <typename K>
 void join_expand(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t total, void* okeys, void* otags,
                  uint32_t* olin_l, uint32_t* olin_r, hipStream_t st);
+// The same join, emitting into a dense-domain relation (see DenseArgs).
+template <typename K>
+void join_expand_dense(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t total, const DenseArgs& d,
+                       bool lineage, hipStream_t st);
+template <typename K>
+void project_dense(const JoinArgs& a, int tag_kind, const DenseArgs& d, bool lineage, hipStream_t st);
+// After the round (pos = exclusive scan of the touched popcounts): write the
+// touched keys in ascending order with their tags (rtags may be NULL), make
+// them present, clear touched, clamp frozen sums and, with lineage, assign
+// ids base.. in key order and record tags by id.
+template <typename K>
+void dense_finalize(const DenseArgs& d, int w, const uint32_t* pos, K* keys, float* rtags, uint32_t id_base,
+                    float* tag_by_id, hipStream_t st);
+// owner[i] = did[keys[i]]
+template <typename K>
+void dense_owners(const DenseArgs& d, const K* keys, size_t n, uint32_t* owner, hipStream_t st);
+// Sorted keys of the set bits of a presence bitmap of 2^w bits; tags and ids
+// gathered from the dense arrays (either may be NULL).  scratch: counts.
+size_t bitmap_words(int w);
+template <typename K>
+void bitmap_keys(const DenseArgs& d, int w, const uint32_t* pos, K* keys, float* tags, uint32_t* ids, hipStream_t st);
+void bitmap_popcounts(const uint32_t* bits, size_t words, uint32_t* counts, hipStream_t st);
+// Gather nseg wave segments (counts, pos = exclusive scan of counts) of
+// `bytes`-wide elements into a contiguous array.
+void segments_compact(const void* in, const uint32_t* counts, const uint32_t* pos, size_t nseg, size_t bytes,
+                      void* out, hipStream_t st);
 // Single-atom rule: re-pack driver columns as head columns, copy tags.
 template <typename K>
 void project_rows(const JoinArgs& a, int tag_kind, void* okeys, void* otags, uint32_t* olin_l, uint32_t* olin_r,

@@ -217,7 +217,7 @@ int add_index(Program& p, const IndexSpec& ix) {
   return (int)p.indexes.size() - 1;
 }
 
-Plan make_plan(Program& p, int rule_id, int driver, bool delta) {
+Plan make_plan(Program& p, int rule_id, int driver, bool delta, int recent_atom = -1) {
   const Rule& r = p.rules[rule_id];
   Plan pl;
   pl.rule = rule_id;
@@ -251,6 +251,7 @@ Plan make_plan(Program& p, int rule_id, int driver, bool delta) {
     remaining.erase(remaining.begin() + pick);
     IndexSpec ix;
     ix.rel = a.rel;
+    ix.recent = st.body_pos == recent_atom;
     for (size_t c = 0; c < a.vars.size(); ++c)
       if (has(cur, a.vars[c])) {
         ix.perm.push_back((int)c);
@@ -311,7 +312,12 @@ void plan(Program& p, bool frozen, bool diff) {
       p.strata[s].recursive = true;
       for (int j : same) {
         p.plans.push_back(make_plan(p, (int)ri, j, true));
-        p.strata[s].delta_plans.push_back((int)p.plans.size() - 1);
+        const int id = (int)p.plans.size() - 1;
+        p.strata[s].delta_plans.push_back(id);
+        if (r.body.size() == 2 && same.size() == 1) {
+          p.plans.push_back(make_plan(p, (int)ri, 1 - j, false, j));
+          p.plans[id].alt = (int)p.plans.size() - 1;
+        }
       }
     }
   }

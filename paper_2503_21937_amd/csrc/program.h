@@ -42,12 +42,15 @@ struct IndexSpec {
   int rel;
   std::vector<int> perm;
   int w;
+  bool recent = false;  // index over the relation's recent tuples (rebuilt every round)
   bool identity() const {
     for (size_t i = 0; i < perm.size(); ++i)
       if (perm[i] != (int)i) return false;
     return true;
   }
-  bool operator==(const IndexSpec& o) const { return rel == o.rel && perm == o.perm && w == o.w; }
+  bool operator==(const IndexSpec& o) const {
+    return rel == o.rel && perm == o.perm && w == o.w && recent == o.recent;
+  }
 };
 
 // One binary join: current table (layout `in_vars`) x index rows.
@@ -69,6 +72,11 @@ struct Plan {
   std::vector<Step> steps;
   std::vector<int> project;     // no steps: head column j <- driver column project[j]
   int max_cols;                 // widest table of the plan
+  // Delta plans of 2-atom rules whose other atom is static also get a
+  // "static-driven" twin: the static relation drives and the recent tuples
+  // are the indexed side (same derivations, output grouped by the static
+  // side's columns).  alt = plan id of the twin, -1 if none.
+  int alt = -1;
 };
 
 struct Stratum {

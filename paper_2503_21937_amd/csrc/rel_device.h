@@ -1,0 +1,79 @@
+// Device helpers shared by the relational kernels: packed-key fields, the
+// join prefix of a probe row, tag types per payload kind, searches.
+#pragma once
+#include "dl_device.h"
+#include "kernels.h"
+
+namespace dlfix {
+
+#define GRID_STRIDE(i, n) \
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
+
+static inline unsigned grid_for(size_t n, size_t per_block = BLOCK) {
+  size_t b = (n + per_block - 1) / per_block;
+  return (unsigned)(b < 65536 ? (b ? b : 1) : 65536);
+}
+
+// ------------------------------------------------------------ key helpers
+__device__ __forceinline__ uint32_t cmask(int cbits) { return (uint32_t)((1ull << cbits) - 1); }
+
+template <typename K>
+__device__ __forceinline__ uint32_t key_col(K key, int c, const KeyLayout& l) {
+  return (uint32_t)((uint64_t)key >> ((l.ncols - 1 - c) * l.cbits)) & cmask(l.cbits);
+}
+template <typename K>
+__device__ __forceinline__ uint32_t key_sample(K key, const KeyLayout& l) {
+  return l.sbits ? (uint32_t)((uint64_t)key >> (l.ncols * l.cbits)) : 0u;
+}
+template <typename K>
+__device__ __forceinline__ K key_make(uint32_t sample, const uint32_t* cols, const KeyLayout& l) {
+  uint64_t k = l.sbits ? (uint64_t)sample << (l.ncols * l.cbits) : 0ull;
+  for (int c = 0; c < l.ncols; ++c) k |= (uint64_t)cols[c] << ((l.ncols - 1 - c) * l.cbits);
+  return (K)k;
+}
+
+template <typename K>
+__device__ __forceinline__ uint64_t join_prefix(K dkey, const JoinArgs& a) {
+  uint64_t p = a.ilay.sbits ? (uint64_t)key_sample(dkey, a.dlay) << (a.w * a.ilay.cbits) : 0ull;
+  for (int j = 0; j < a.w; ++j) p |= (uint64_t)key_col(dkey, a.jsrc[j], a.dlay) << ((a.w - 1 - j) * a.ilay.cbits);
+  return p;
+}
+
+template <int TK>
+struct TagOf {
+  using T = NoTag;
+};
+template <>
+struct TagOf<TAG_F32> {
+  using T = float;
+};
+template <>
+struct TagOf<TAG_TOPK> {
+  using T = TopK;
+};
+
+template <int TK>
+__device__ __forceinline__ typename TagOf<TK>::T tag_otimes(const typename TagOf<TK>::T& x,
+                                                           const typename TagOf<TK>::T& y, const JoinArgs& a,
+                                                           uint32_t sample) {
+  if constexpr (TK == TAG_F32) {
+    return f_otimes(a.sr, x, y);
+  } else if constexpr (TK == TAG_TOPK) {
+    return topk_otimes(x, y, a.k, a.q + (size_t)sample * 64);
+  } else {
+    return NoTag{};
+  }
+}
+
+__device__ __forceinline__ size_t upper_bound_u32(const uint32_t* a, size_t n, uint32_t x) {
+  size_t lo = 0, hi = n;
+  while (lo < hi) {
+    size_t mid = (lo + hi) >> 1;
+    if (a[mid] <= x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+
+}  // namespace dlfix

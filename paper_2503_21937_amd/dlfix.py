@@ -21,7 +21,7 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_PARSE", 3: "ERR_UNSUPPORTED", 4: "ERR_S
           5: "ERR_NOMEM", 6: "ERR_CAPACITY", 7: "ERR_PROOF_OVERFLOW", 8: "ERR_HIP"}
 EXPORTS = ["dl_load_program", "dl_clear_facts", "dl_add_facts", "dl_run_fixpoint",
            "dl_relation_size", "dl_read_relation", "dl_backward", "dl_read_grad",
-           "dl_zero_grad", "dl_get_stats", "dl_profile", "dl_get_kernel_timing",
+           "dl_zero_grad", "dl_get_stats", "dl_autotune", "dl_profile", "dl_get_kernel_timing",
            "dl_last_error", "dl_free"]
 KERNEL_FAMILIES = ["join_count", "join_expand", "sort_hist", "sort_scatter", "scan", "reduce",
                    "diff", "merge", "compact", "index", "backward"]
@@ -35,7 +35,7 @@ class DLError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("semiring", C.c_int), ("k", C.c_int), ("batched", C.c_int),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("dedup", C.c_int)]
 
 
 class RelationOut(C.Structure):
@@ -51,7 +51,8 @@ class Stats(C.Structure):
     _fields_ = [("strata", C.c_int), ("rounds", C.c_int), ("max_rounds", C.c_int),
                 ("candidates", C.c_uint64), ("unique", C.c_uint64), ("derived", C.c_uint64),
                 ("lineage", C.c_uint64), ("run_ms", C.c_double), ("device_bytes", C.c_uint64),
-                ("key_bits", C.c_uint32), ("id_bits", C.c_uint32), ("sample_bits", C.c_uint32)]
+                ("key_bits", C.c_uint32), ("id_bits", C.c_uint32), ("sample_bits", C.c_uint32),
+                ("dedup", C.c_int), ("orient", C.c_int), ("items", C.c_int), ("tuned_ms", C.c_double)]
 
 
 _lib = None
@@ -83,6 +84,7 @@ def lib():
         L.dl_read_grad.argtypes = [vp, C.c_char_p, vp, C.c_int]
         L.dl_zero_grad.argtypes = [vp]
         L.dl_get_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.dl_autotune.argtypes = [vp, C.c_int, C.c_char_p]
         L.dl_profile.argtypes = [vp, C.c_uint32]
         L.dl_get_kernel_timing.argtypes = [vp, C.c_int, C.POINTER(KernelStats)]
         L.dl_last_error.argtypes = [vp]
@@ -123,8 +125,11 @@ def _current_stream() -> int | None:
 class Engine:
     """One fixpoint engine: a program under one semiring (dlfix.h)."""
 
+    DEDUP = {"auto": 0, "sort": 1, "dense": 2}
+
     def __init__(self, program: str, semiring: str = "bool", k: int = 3,
-                 batched: bool = False, stream: int | None = None, use_torch_stream: bool = True):
+                 batched: bool = False, stream: int | None = None, use_torch_stream: bool = True,
+                 dedup: str = "auto"):
         self.arity = {}
         for line in program.splitlines():
             line = line.strip()
@@ -136,7 +141,7 @@ class Engine:
         self.batched = batched
         if stream is None and use_torch_stream:
             stream = _current_stream()
-        opts = Options(SEMIRINGS[semiring], k, int(batched), stream)
+        opts = Options(SEMIRINGS[semiring], k, int(batched), stream, self.DEDUP[dedup])
         h = C.c_void_p()
         rc = lib().dl_load_program(program.encode(), C.byref(opts), C.byref(h))
         if rc:
@@ -234,6 +239,12 @@ class Engine:
 
     def zero_grad(self):
         self._check(lib().dl_zero_grad(self.h))
+
+    def autotune(self, trials: int = 3, cache: str | None = None) -> dict:
+        """Pick the fastest execution configuration for the current facts."""
+        self._check(lib().dl_autotune(self.h, trials, None if cache is None else cache.encode()))
+        st = self.stats()
+        return {k: st[k] for k in ("dedup", "orient", "items", "tuned_ms")}
 
     def profile(self, families=None):
         """Time the given kernel families (names; None = all, [] = off)."""

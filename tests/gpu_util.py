@@ -5,9 +5,12 @@ import numpy as np
 TAG_RTOL = 1e-5  # float32 tags vs the binary64 oracle
 
 
-def engine(program, semiring, facts, k=3, batched=False):
+DEDUP = ["sort", "dense"]  # both deduplication pipelines are parity-tested
+
+
+def engine(program, semiring, facts, k=3, batched=False, dedup="auto"):
     from paper_2503_21937_amd import dlfix
-    e = dlfix.Engine(program, semiring, k=k, batched=batched)
+    e = dlfix.Engine(program, semiring, k=k, batched=batched, dedup=dedup)
     for rel, (cols, tags, sample) in facts.items():
         e.add_facts(rel, cols, tags, sample)
     return e.run()

@@ -3,7 +3,7 @@ with two recursive atoms) against the oracle's naive and worklist solvers."""
 import numpy as np
 import pytest
 
-from gpu_util import engine, oracle_run
+from gpu_util import DEDUP, engine, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -12,20 +12,22 @@ def facts(rels):
     return {name: ([a, b], None, None) for name, (a, b) in rels.items()}
 
 
-def test_small_vs_naive(oracle, synth):
+@pytest.mark.parametrize("dedup", DEDUP)
+def test_small_vs_naive(oracle, synth, dedup):
     rels = synth.andersen(1, v=600, n_addr=300, n_assign=1800, n_load=240, n_store=240)
-    g = engine(synth.ANDERSEN_PROGRAM, "bool", facts(rels))
+    g = engine(synth.ANDERSEN_PROGRAM, "bool", facts(rels), dedup=dedup)
     o = oracle_run(oracle, synth.ANDERSEN_PROGRAM, "bool", facts(rels))
     assert np.array_equal(g.read("pt")["cols"], o.read("pt")["cols"])
     assert g.stats()["max_rounds"] == o.rounds()
 
 
+@pytest.mark.parametrize("dedup", DEDUP)
 @pytest.mark.parametrize("scale", [0.02, 0.03])
-def test_scaled_vs_worklist(oracle, synth, scale):
+def test_scaled_vs_worklist(oracle, synth, scale, dedup):
     v = int(100000 * scale)
     rels = synth.andersen(1, v=v, n_addr=int(50000 * scale), n_assign=int(300000 * scale),
                           n_load=int(40000 * scale), n_store=int(40000 * scale))
-    g = engine(synth.ANDERSEN_PROGRAM, "bool", facts(rels)).read("pt")
+    g = engine(synth.ANDERSEN_PROGRAM, "bool", facts(rels), dedup=dedup).read("pt")
     pv, po = oracle.andersen(v, rels)
     assert np.array_equal(g["cols"][:, 0], pv)
     assert np.array_equal(g["cols"][:, 1], po)

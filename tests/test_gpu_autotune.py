@@ -1,0 +1,69 @@
+"""The autotuner's candidate configurations all compute the oracle's
+relation; its choice is cached and reused."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_tags_close, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def make_engine(synth, sr, src, dst, p):
+    from paper_2503_21937_amd import dlfix
+    e = dlfix.Engine(synth.TC_PROGRAM, sr)
+    e.add_facts("edge", [src, dst], p)
+    return e
+
+
+@pytest.mark.parametrize("sr", ["maxmin", "addmult", "bool"])
+def test_every_configuration_matches_oracle(oracle, synth, sr, tmp_path):
+    src, dst, p = synth.er_graph(5, 300, 1100, weights=True)
+    want = oracle_run(oracle, synth.TC_PROGRAM, sr, {"edge": ([src, dst], p, None)}).read("path")
+    key = _key(make_engine(synth, sr, src, dst, p))
+    for dedup in (1, 2):
+        for orient in (1, 2):
+            for items in (1, 2, 4, 8):
+                e = make_engine(synth, sr, src, dst, p)
+                cache = tmp_path / f"force_{sr}_{dedup}_{orient}_{items}.jsonl"
+                cache.write_text(json.dumps({"key": key, "dedup": dedup, "orient": orient, "items": items,
+                                             "ms": 1.0}) + "\n")
+                cfg = e.autotune(1, str(cache))
+                assert (cfg["dedup"], cfg["orient"], cfg["items"]) == (dedup, orient, items)
+                got = e.read("path")
+                assert np.array_equal(got["cols"], want["cols"]), (dedup, orient, items)
+                if sr == "maxmin":
+                    assert np.array_equal(got["tags"].astype(np.float64), want["value"])
+                elif sr == "addmult":
+                    assert_tags_close(got["tags"], want["value"])
+
+
+def _key(e):
+    """The tuning key the library uses, read back through a throwaway cache."""
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "c.jsonl")
+        e.autotune(1, path)
+        line = open(path).read().splitlines()[-1]
+        return json.loads(line)["key"]
+
+
+def test_autotune_picks_and_caches(oracle, synth, tmp_path):
+    src, dst, p = synth.er_graph(1, 2000, 8000, weights=True)
+    cache = str(tmp_path / "tune.jsonl")
+    e = make_engine(synth, "minplus", src, dst, p)
+    cfg = e.autotune(2, cache)
+    assert cfg["tuned_ms"] > 0
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    assert (rec["dedup"], rec["orient"], rec["items"]) == (cfg["dedup"], cfg["orient"], cfg["items"])
+    e2 = make_engine(synth, "minplus", src, dst, p)
+    cfg2 = e2.autotune(2, cache)  # served from the cache: no new line
+    assert open(cache).read().splitlines() == lines
+    assert (cfg2["dedup"], cfg2["orient"], cfg2["items"]) == (cfg["dedup"], cfg["orient"], cfg["items"])
+    a, b = e.read("path"), e2.read("path")
+    assert np.array_equal(a["cols"], b["cols"])
+    assert np.array_equal(a["tags"], b["tags"])

@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from gpu_util import assert_tags_close, engine, oracle_run, same_rows
+from gpu_util import DEDUP, assert_tags_close, engine, oracle_run, same_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -13,9 +13,9 @@ def tc_facts(src, dst, p, sample=None):
     return {"edge": ([src, dst], p, sample)}
 
 
-def check_tc(oracle, synth, src, dst, p, sr, rounds=True):
+def check_tc(oracle, synth, src, dst, p, sr, rounds=True, dedup="auto"):
     facts = tc_facts(src, dst, None if sr == "bool" else p)
-    g = engine(synth.TC_PROGRAM, sr, facts)
+    g = engine(synth.TC_PROGRAM, sr, facts, dedup=dedup)
     o = oracle_run(oracle, synth.TC_PROGRAM, sr, facts)
     gr, orr = g.read("path"), o.read("path")
     same_rows(gr, orr)
@@ -28,15 +28,17 @@ def check_tc(oracle, synth, src, dst, p, sr, rounds=True):
     return g, gr
 
 
+@pytest.mark.parametrize("dedup", DEDUP)
 @pytest.mark.parametrize("seed", [1, 2, 3])
 @pytest.mark.parametrize("sr", SEMIRINGS)
-def test_er256_parity(oracle, synth, sr, seed):
+def test_er256_parity(oracle, synth, sr, seed, dedup):
     src, dst, p = synth.er_graph(seed, 256, 1024, weights=True)
-    check_tc(oracle, synth, src, dst, p, sr)
+    check_tc(oracle, synth, src, dst, p, sr, dedup=dedup)
 
 
+@pytest.mark.parametrize("dedup", DEDUP)
 @pytest.mark.parametrize("sr", SEMIRINGS)
-def test_edge_cases(oracle, synth, sr):
+def test_edge_cases(oracle, synth, sr, dedup):
     cases = [
         ([0], [1]),                       # one edge
         ([0, 1], [1, 0]),                 # 2-cycle: reflexive paths appear
@@ -49,31 +51,34 @@ def test_edge_cases(oracle, synth, sr):
         s = np.asarray(s, np.uint32)
         d = np.asarray(d, np.uint32)
         p = synth.unit_prob(rng, s.size)
-        check_tc(oracle, synth, s, d, p, sr)
+        check_tc(oracle, synth, s, d, p, sr, dedup=dedup)
 
 
-def test_duplicate_facts_are_merged(oracle, synth):
+@pytest.mark.parametrize("dedup", DEDUP)
+def test_duplicate_facts_are_merged(oracle, synth, dedup):
     src = np.array([0, 0, 1, 1, 2], np.uint32)
     dst = np.array([1, 1, 2, 2, 0], np.uint32)
     p = np.array([0.25, 0.5, 0.125, 0.5, 0.75], np.float32)
     for sr in SEMIRINGS:
-        check_tc(oracle, synth, src, dst, p, sr)
+        check_tc(oracle, synth, src, dst, p, sr, dedup=dedup)
 
 
-def test_no_facts(synth):
+@pytest.mark.parametrize("dedup", DEDUP)
+def test_no_facts(synth, dedup):
     from paper_2503_21937_amd import dlfix
-    e = dlfix.Engine(synth.TC_PROGRAM, "addmult").run()
+    e = dlfix.Engine(synth.TC_PROGRAM, "addmult", dedup=dedup).run()
     assert e.size("path") == 0
     assert e.stats()["rounds"] == 1
 
 
+@pytest.mark.parametrize("dedup", DEDUP)
 @pytest.mark.parametrize("sr", SEMIRINGS)
-def test_er2000_multi_tile(oracle, synth, sr):
+def test_er2000_multi_tile(oracle, synth, sr, dedup):
     """Multi-tile sizes with ragged tails: every join/sort/merge spans many
     workgroups.  Checked column by column against the oracle."""
     n = 2000
     src, dst, p = synth.er_graph(7, n, 7000, weights=True)
-    g = engine(synth.TC_PROGRAM, sr, tc_facts(src, dst, None if sr == "bool" else p))
+    g = engine(synth.TC_PROGRAM, sr, tc_facts(src, dst, None if sr == "bool" else p), dedup=dedup)
     r = g.read("path")
     cols = r["cols"]
     for z in range(3, n, 97):
@@ -86,11 +91,12 @@ def test_er2000_multi_tile(oracle, synth, sr):
             assert_tags_close(r["tags"][m], c["tag"][cols[m, 0]], what=f"{sr} z={z}")
 
 
-def test_determinism(synth):
+@pytest.mark.parametrize("dedup", DEDUP)
+def test_determinism(synth, dedup):
     src, dst, p = synth.er_graph(2, 256, 1024, weights=True)
     for sr in ["bool", "maxmin", "minplus"]:
-        a = engine(synth.TC_PROGRAM, sr, tc_facts(src, dst, p)).read("path")
-        b = engine(synth.TC_PROGRAM, sr, tc_facts(src, dst, p)).read("path")
+        a = engine(synth.TC_PROGRAM, sr, tc_facts(src, dst, p), dedup=dedup).read("path")
+        b = engine(synth.TC_PROGRAM, sr, tc_facts(src, dst, p), dedup=dedup).read("path")
         assert np.array_equal(a["cols"], b["cols"])
         assert np.array_equal(a["tags"].view(np.uint32), b["tags"].view(np.uint32))
 
@@ -109,3 +115,18 @@ def test_device_pointers_roundtrip(oracle, synth):
     cols = np.stack([c.cpu().numpy().astype(np.uint32) for c in r["cols"]], 1)
     assert np.array_equal(cols, o["cols"])
     assert np.array_equal(r["tags"].cpu().numpy().astype(np.float64), o["value"])
+
+
+def test_dedup_pipelines_agree(synth):
+    """The sort-based and the dense-domain pipelines give the same relation."""
+    src, dst, p = synth.er_graph(4, 3000, 12000, weights=True)
+    for sr in SEMIRINGS:
+        a = engine(synth.TC_PROGRAM, sr, tc_facts(src, dst, p), dedup="sort")
+        b = engine(synth.TC_PROGRAM, sr, tc_facts(src, dst, p), dedup="dense")
+        ra, rb = a.read("path"), b.read("path")
+        assert np.array_equal(ra["cols"], rb["cols"]), sr
+        if sr in ("maxmin", "minplus", "bool"):
+            assert np.array_equal(ra["tags"], rb["tags"]), sr
+        else:
+            assert_tags_close(ra["tags"], rb["tags"], rtol=1e-6, what=sr)
+        assert a.stats()["max_rounds"] == b.stats()["max_rounds"], sr
