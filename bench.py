@@ -55,7 +55,7 @@ def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int) -> dic
     import numpy as np
     import torch
     from paper_2503_21937_amd import dlfix, synth
-    from paper_2503_21937_amd.autograd import fixpoint
+    from paper_2503_21937_amd.autograd import fixpoint_query
 
     dev = torch.device("cuda")
     g = synth.grid_batch(seed)
@@ -67,17 +67,19 @@ def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int) -> dic
     sample = torch.tensor(g["sample"].astype(np.int32), device=dev)
     p0 = torch.tensor(g["p"], device=dev)
 
-    def loss_of(tags, osample, ocols, kk, y):
-        target = (ocols[:, 0] == 0) & (ocols[:, 1].long() == kk[osample.long()] ** 2 - 1)
-        pred = tags[target].clamp(1e-6, 1 - 1e-6)
-        return torch.nn.functional.binary_cross_entropy(pred, y[osample[target].long()], reduction="sum")
+    def loss_of(pred, y):
+        return torch.nn.functional.binary_cross_entropy(pred.clamp(1e-6, 1 - 1e-6), y, reduction="sum")
 
+    # query path(0, k^2 - 1) of every sample: read back and seeded on those rows only
+    q_sample = torch.arange(S, dtype=torch.int32, device=dev)
+    q_x = torch.zeros(S, dtype=torch.int32, device=dev)
+    q_z = (ks ** 2 - 1).to(torch.int32)
     eng = dlfix.Engine(synth.TC_PROGRAM, "diff_addmult", batched=True)
 
     def batched_step():
         probs = p0.clone().requires_grad_(True)
-        tags, osample, ocols = fixpoint(probs, eng, "edge", [src, dst], sample, "path")
-        loss_of(tags, osample, ocols, ks, labels).backward()
+        pred = fixpoint_query(probs, eng, "edge", [src, dst], sample, "path", [q_x, q_z], q_sample)
+        loss_of(pred, labels).backward()
         return probs.grad
 
     for _ in range(warmup):
@@ -100,8 +102,9 @@ def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int) -> dic
     def plain_step(item):
         a, b, pp, kk, y = item
         probs = pp.clone().requires_grad_(True)
-        tags, osample, ocols = fixpoint(probs, plain, "edge", [a, b], None, "path")
-        loss_of(tags, osample, ocols, kk, y).backward()
+        pred = fixpoint_query(probs, plain, "edge", [a, b], None, "path",
+                              [q_x[:1], (kk ** 2 - 1).to(torch.int32)], None)
+        loss_of(pred, y).backward()
 
     plain_step(per[0])
     torch.cuda.synchronize()

@@ -79,6 +79,7 @@ typedef struct {
                              is at most 2^30 and the semiring is not top-k, else sort-based),
                          1 = always sort-based (radix sort, unique, difference, merge),
                          2 = dense-domain wherever possible */
+  int no_graphs;      /* 1: never replay round bodies as captured HIP graphs (0: replay where eligible) */
 } dl_options;
 
 /* Result columns of dl_read_relation.  Any pointer may be NULL (not written).
@@ -175,6 +176,20 @@ dl_status dl_relation_size(dl_engine* e, const char* relation, size_t* n);
  * on_device selects device (1) or host (0) pointers for all buffers. */
 dl_status dl_read_relation(dl_engine* e, const char* relation, size_t capacity,
                            const dl_relation_out* out, int on_device, size_t* n_written);
+
+/* Point queries: for n tuples given as columns (SoA; sample ids for batched
+ * engines) write rows[i] = the tuple's row in canonical order or -1 when it
+ * is not in the relation, and tags[i] = its tag as in dl_read_relation (0 when
+ * absent).  Either output may be NULL.  Binary search over the sorted result:
+ * no copy of the relation. */
+dl_status dl_lookup(dl_engine* e, const char* relation, size_t n, const uint32_t* sample_ids,
+                    const uint32_t* const* columns, int64_t* rows, float* tags, int on_device);
+
+/* Reverse mode seeded on selected rows (e.g. from dl_lookup; rows < 0 are
+ * skipped): d(loss)/d(tag of row rows[i]) = grad[i].  Same accumulation as
+ * dl_backward. */
+dl_status dl_backward_rows(dl_engine* e, const char* relation, size_t n, const int64_t* rows, const float* grad,
+                           int on_device);
 
 /* Reverse mode for DIFF_ADDMULT and DIFF_TOPK: grad_out[i] is d(loss)/d(tag)
  * of row i of out_relation in canonical order.  Gradients with respect to the

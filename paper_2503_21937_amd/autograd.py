@@ -44,3 +44,35 @@ class FixpointFunction(torch.autograd.Function):
 def fixpoint(probs, engine, in_rel, cols, sample=None, out_rel="path"):
     """Differentiable fixpoint: returns (tags, sample_ids, columns) of out_rel."""
     return FixpointFunction.apply(probs, engine, in_rel, cols, sample, out_rel)
+
+
+class FixpointQueryFunction(torch.autograd.Function):
+    """tags of selected output tuples = fixpoint(probs); absent tuples give 0.
+
+    Only the queried tuples are read back (binary search in the sorted
+    result) and the reverse pass is seeded on their rows only."""
+
+    @staticmethod
+    def forward(ctx, probs, engine, in_rel, cols, sample, out_rel, q_cols, q_sample):
+        torch.cuda.current_stream().synchronize()
+        engine.clear_facts()
+        engine.add_facts(in_rel, cols, probs.detach().contiguous(), sample)
+        engine.run()
+        rows, tags = engine.lookup(out_rel, q_cols, q_sample)
+        ctx.engine, ctx.in_rel, ctx.out_rel, ctx.n_in, ctx.rows = engine, in_rel, out_rel, probs.shape[0], rows
+        return tags
+
+    @staticmethod
+    def backward(ctx, grad_tags):
+        e = ctx.engine
+        torch.cuda.current_stream().synchronize()
+        e.zero_grad()
+        e.backward_rows(ctx.out_rel, ctx.rows, grad_tags.detach().float().contiguous())
+        g = torch.zeros(ctx.n_in, dtype=torch.float32, device=grad_tags.device)
+        e.grad(ctx.in_rel, ctx.n_in, out=g)
+        return g, None, None, None, None, None, None, None
+
+
+def fixpoint_query(probs, engine, in_rel, cols, sample, out_rel, q_cols, q_sample=None):
+    """Differentiable tags of the query tuples (q_cols, q_sample) of out_rel."""
+    return FixpointQueryFunction.apply(probs, engine, in_rel, cols, sample, out_rel, q_cols, q_sample)

@@ -81,6 +81,7 @@ struct LineageSeg {
 struct ExecConfig {
   int items = 4;   // join expand tile: outputs per thread (1, 2, 4, 8)
   int orient = 0;  // delta plans of 2-atom rules: 0 auto, 1 recent-driven, 2 static-driven
+  int graph = 1;   // replay eligible round bodies as a captured HIP graph
 };
 
 struct Engine {
@@ -121,7 +122,7 @@ struct Engine {
   // round scratch
   DevBuf counts, offs, alt_keys, alt_vals, vals, flags, pos, ukeys, utags,
       status, nflags, newpos, rflags, rpos, lf, lpos, nkeys, ntags, nids, tmpA_keys, tmpA_tags, tmpB_keys, tmpB_tags,
-      scratch, unpack;
+      scratch, unpack, qbuf;
   uint64_t* host = nullptr;  // pinned readback words
   DevBuf dtotal;             // device words for totals
 
@@ -150,6 +151,9 @@ struct Engine {
   void read_grad(const char* in_relation, float* grad_in, int on_device);
   void zero_grad();
   void autotune(int trials, const char* cache_path);
+  void lookup(const char* relation, size_t n, const uint32_t* sample_ids, const uint32_t* const* columns,
+              int64_t* rows, float* tags, int on_device);
+  void backward_rows(const char* relation, size_t n, const int64_t* rows, const float* grad, int on_device);
   std::string tune_key() const;
 
   int relation_id(const char* name, bool must_exist = true);
@@ -165,6 +169,9 @@ void run_fixpoint(Engine& e);
 template <typename K>
 size_t read_relation_t(Engine& e, int r, size_t capacity, const dl_relation_out* out, int on_device);
 template <typename K>
-void backward_t(Engine& e, int r, const float* grad_out);
+void backward_t(Engine& e, int r, const float* grad_out, const int64_t* rows, size_t nrows);
+template <typename K>
+void lookup_t(Engine& e, int r, size_t n, const uint32_t* const* cols, const uint32_t* sample, int64_t* rows,
+              float* tags);
 
 }  // namespace dlfix

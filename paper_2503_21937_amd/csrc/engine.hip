@@ -64,7 +64,7 @@ Engine::~Engine() {
   }
   for (DevBuf* b : {&qtab, &grad_fact, &lin_owner, &lin_l, &lin_r, &tag_by_id, &adj, &counts, &offs, &alt_keys, &alt_vals, &vals, &flags, &pos, &ukeys, &utags, &status,
                     &nflags, &newpos, &rflags, &rpos, &lf, &lpos, &nkeys, &ntags, &nids, &tmpA_keys, &tmpA_tags,
-                    &tmpB_keys, &tmpB_tags, &scratch, &unpack, &dtotal})
+                    &tmpB_keys, &tmpB_tags, &scratch, &unpack, &qbuf, &dtotal})
     fr(*b);
   if (host) (void)hipHostFree(host);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -139,6 +139,7 @@ void Engine::init(const char* program_text, const dl_options* o) {
   for (size_t r = 0; r < prog.rels.size(); ++r) rel[r].raw_cols.assign(prog.rels[r].arity, DevBuf{});
   idx.assign(prog.indexes.size(), IndexState{});
   if (o->dedup < 0 || o->dedup > 2) throw Error{DL_ERR_ARG, "dedup must be 0, 1 or 2"};
+  cfg.graph = o->no_graphs ? 0 : 1;
   for (const Plan& pl : prog.plans)
     for (const Step& st : pl.steps) {
       const IndexSpec& ix = prog.indexes[st.index];
@@ -300,9 +301,65 @@ void Engine::backward(const char* out_relation, const float* grad_out, int on_de
     DL_HIP(hipMemcpyAsync(unpack.p, grad_out, n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                           stream));
   ProfScope prof(*this);
-  if (key64) backward_t<uint64_t>(*this, r, unpack.as<float>());
-  else backward_t<uint32_t>(*this, r, unpack.as<float>());
+  if (key64) backward_t<uint64_t>(*this, r, unpack.as<float>(), nullptr, 0);
+  else backward_t<uint32_t>(*this, r, unpack.as<float>(), nullptr, 0);
   prof.finish();
+  sync();
+}
+
+void Engine::backward_rows(const char* relation, size_t n, const int64_t* rows, const float* grad, int on_device) {
+  int r = relation_id(relation);
+  if (!ran) throw Error{DL_ERR_STATE, "run the fixpoint first"};
+  if (sr != DL_DIFF_ADDMULT && sr != DL_DIFF_TOPK)
+    throw Error{DL_ERR_STATE, "backward needs DL_DIFF_ADDMULT or DL_DIFF_TOPK"};
+  if (n && (!rows || !grad)) throw Error{DL_ERR_ARG, "rows or grad is NULL"};
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  grow(qbuf, n * 12 + 16);
+  int64_t* drows = qbuf.as<int64_t>();
+  float* dgrad = reinterpret_cast<float*>(drows + n);
+  if (n) {
+    DL_HIP(hipMemcpyAsync(drows, rows, n * 8, k, stream));
+    DL_HIP(hipMemcpyAsync(dgrad, grad, n * 4, k, stream));
+  }
+  ProfScope prof(*this);
+  if (key64) backward_t<uint64_t>(*this, r, dgrad, drows, n);
+  else backward_t<uint32_t>(*this, r, dgrad, drows, n);
+  prof.finish();
+  sync();
+}
+
+void Engine::lookup(const char* relation, size_t n, const uint32_t* sample_ids, const uint32_t* const* columns,
+                    int64_t* rows, float* tags, int on_device) {
+  int r = relation_id(relation);
+  if (!ran) throw Error{DL_ERR_STATE, "run the fixpoint first"};
+  const int ar = prog.rels[r].arity;
+  if (n == 0) return;
+  if (!columns) throw Error{DL_ERR_ARG, "columns is NULL"};
+  for (int c = 0; c < ar; ++c)
+    if (!columns[c]) throw Error{DL_ERR_ARG, "a column pointer is NULL"};
+  if (batched && !sample_ids) throw Error{DL_ERR_ARG, "batched engine needs sample ids"};
+  // stage inputs and outputs on the device
+  const size_t in_words = (size_t)(ar + 1) * n;
+  grow(qbuf, in_words * 4 + n * 12 + 64);
+  uint32_t* base = qbuf.as<uint32_t>();
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const uint32_t* dcols[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int c = 0; c < ar; ++c) {
+    DL_HIP(hipMemcpyAsync(base + (size_t)c * n, columns[c], n * 4, k, stream));
+    dcols[c] = base + (size_t)c * n;
+  }
+  const uint32_t* dsample = nullptr;
+  if (batched) {
+    DL_HIP(hipMemcpyAsync(base + (size_t)ar * n, sample_ids, n * 4, k, stream));
+    dsample = base + (size_t)ar * n;
+  }
+  int64_t* drows = reinterpret_cast<int64_t*>(((uintptr_t)(base + in_words) + 7) & ~(uintptr_t)7);
+  float* dtags = reinterpret_cast<float*>(drows + n);
+  if (key64) lookup_t<uint64_t>(*this, r, n, dcols, dsample, drows, dtags);
+  else lookup_t<uint32_t>(*this, r, n, dcols, dsample, drows, dtags);
+  const hipMemcpyKind back = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (rows) DL_HIP(hipMemcpyAsync(rows, drows, n * 8, back, stream));
+  if (tags) DL_HIP(hipMemcpyAsync(tags, dtags, n * 4, back, stream));
   sync();
 }
 
@@ -393,6 +450,8 @@ void Engine::autotune(int trials, const char* cache_path) {
     opts.dedup = best.dedup;
     cfg.orient = best.orient;
     cfg.items = best.items;
+    stats.tuned_ms = best.ms;
+    run();  // results of the cached configuration
     return;
   }
   bool twins = false;
@@ -520,6 +579,16 @@ dl_status dl_read_relation(dl_engine* h, const char* relation, size_t capacity, 
 
 dl_status dl_backward(dl_engine* h, const char* out_relation, const float* grad_out, int on_device) {
   return guard(h, [&] { h->e.backward(out_relation, grad_out, on_device); });
+}
+
+dl_status dl_lookup(dl_engine* h, const char* relation, size_t n, const uint32_t* sample_ids,
+                    const uint32_t* const* columns, int64_t* rows, float* tags, int on_device) {
+  return guard(h, [&] { h->e.lookup(relation, n, sample_ids, columns, rows, tags, on_device); });
+}
+
+dl_status dl_backward_rows(dl_engine* h, const char* relation, size_t n, const int64_t* rows, const float* grad,
+                           int on_device) {
+  return guard(h, [&] { h->e.backward_rows(relation, n, rows, grad, on_device); });
 }
 
 dl_status dl_read_grad(dl_engine* h, const char* in_relation, float* grad_in, int on_device) {

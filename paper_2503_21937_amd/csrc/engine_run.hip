@@ -16,12 +16,13 @@
 
 #include "dl_device.h"
 #include "engine.h"
+#include "prof.h"
 
 namespace dlfix {
 
 namespace {
 
-enum Slot { S_SCAN = 0, S_UNIQUE = 1, S_NEW = 2, S_RECENT = 3, S_LIN = 4 };
+enum Slot { S_SCAN = 0, S_UNIQUE = 1, S_NEW = 2, S_RECENT = 3, S_LIN = 4, S_OVF = 5, S_CAND = 6 };
 
 uint64_t* total_slot(Engine& e, int s) { return e.dtotal.as<uint64_t>() + s; }
 
@@ -62,6 +63,7 @@ DenseArgs dense_args(Engine& e, RelState& R) {
   d.log_r = R.log_r.as<uint32_t>();
   d.seg_lcount = R.seg_lcount.as<uint32_t>();
   d.seg_base = (uint32_t)R.nseg;
+  d.overflow = e.dtotal.as<uint64_t>() + S_OVF;
   d.mode = e.sr == DL_BOOL ? DENSE_BOOL : !e.converge ? DENSE_ADD : e.sr == DL_MAXMIN ? DENSE_MAX : DENSE_MIN;
   return d;
 }
@@ -295,13 +297,25 @@ void run_plan(Engine& e, const Plan& pl) {
     e.grow(e.offs, (cur.n + 1) * 4);
     join_count<K>(a, e.counts.as<uint32_t>(), e.stream);
     scan(e, e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), cur.n, S_SCAN, true);
+    if (si + 1 == pl.steps.size() && H.dense && !e.lineage) {
+      // no host readback: the expand reads the total on the device; the
+      // candidate count and any 32-bit overflow are collected at round end
+      const IndexState& ixs = e.idx[step.index];
+      const size_t in = std::max<size_t>(ixs.t.n, 1);
+      const size_t bound = cur.n > ((size_t)1 << 40) / in ? ((size_t)1 << 40) : cur.n * in;
+      const DenseArgs d = dense_room(0, a.items);
+      accumulate_total(total_slot(e, S_SCAN), total_slot(e, S_CAND), e.stream);
+      join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), 0, total_slot(e, S_SCAN), bound, d, false,
+                           e.stream);
+      return;
+    }
     const uint64_t total = e.read_total(S_SCAN);
     if (total > 0xffffffffull) throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
     if (total == 0) return;
     const bool last = si + 1 == pl.steps.size();
     if (last && H.dense) {
       const DenseArgs d = dense_room(total, a.items);
-      join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), total, d, e.lineage, e.stream);
+      join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), total, nullptr, total, d, e.lineage, e.stream);
       return;
     }
     void *ok, *ot;
@@ -334,17 +348,19 @@ size_t absorb_dense(Engine& e, int r) {
   hipStream_t st = e.stream;
   const size_t nseg = R.nseg;
   R.nseg = 0;
-  // touched popcounts -> positions of the new / changed tuples in key order
-  const size_t words = bitmap_words(R.dense_w);
-  e.grow(e.flags, words * 4);
-  e.grow(e.pos, (words + 1) * 4);
-  bitmap_popcounts(R.touched.as<uint32_t>(), words, e.flags.as<uint32_t>(), st);
-  scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), words, S_UNIQUE, true);
+  // touched counts per bitmap block -> positions of the new / changed tuples
+  const size_t nb = dense_count_blocks(R.dense_w);
+  e.grow(e.flags, nb * 4);
+  e.grow(e.pos, (nb + 1) * 4);
+  DenseArgs d = dense_args(e, R);
+  dense_touched_counts(d, R.dense_w, e.flags.as<uint32_t>(), st);
+  scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, S_UNIQUE, true);
   if (e.lineage && nseg) {
     e.grow(e.lpos, (nseg + 1) * 4);
     scan(e, R.seg_lcount.as<uint32_t>(), e.lpos.as<uint32_t>(), nseg, S_LIN, true);
   }
   e.read_totals();
+  if (e.host[S_OVF]) throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
   const size_t U = e.host[S_UNIQUE], L = e.lineage && nseg ? e.host[S_LIN] : 0;
   if (U == 0) {
     R.recent.n = 0;
@@ -359,7 +375,7 @@ size_t absorb_dense(Engine& e, int r) {
   }
   const uint32_t base = e.next_id;
   if (e.lineage) e.grow(e.tag_by_id, ((size_t)base + U) * 4, true, (size_t)base * 4);
-  DenseArgs d = dense_args(e, R);
+  d = dense_args(e, R);
   dense_finalize<K>(d, R.dense_w, e.pos.as<uint32_t>(), R.recent.keys.as<K>(), rtags, base,
                     e.lineage ? e.tag_by_id.as<float>() : nullptr, st);
   if (e.lineage) {
@@ -522,6 +538,165 @@ size_t absorb(Engine& e, int r) {
   return Rn;
 }
 
+// ------------------------------------------------------ HIP-graph rounds
+// A stratum whose single relation uses the dense-domain path without lineage
+// and whose delta plans are all static-driven single joins against an
+// identity-ordered index over the recent tuples has a round body with only
+// device-side sizes: the recent index is rebuilt from the previous round's
+// count (a device word), the join reads its total on the device, the round
+// end compacts the touched bitmap.  Such a body is captured once per stratum
+// and replayed every round; the host reads back one block of counters per
+// round.
+std::vector<const Plan*> graph_plans(Engine& e, const Stratum& st) {
+  std::vector<const Plan*> out;
+  if (!e.cfg.graph || g_prof || e.lineage || st.rels.size() != 1 || st.delta_plans.empty()) return {};
+  const int r = st.rels[0];
+  if (!e.rel[r].dense || e.cfg.orient == 1) return {};
+  for (int p : st.delta_plans) {
+    const Plan& pl = e.prog.plans[p];
+    if (pl.alt < 0) return {};
+    const Plan& tw = e.prog.plans[pl.alt];
+    if (tw.steps.size() != 1) return {};
+    const IndexSpec& ix = e.prog.indexes[tw.steps[0].index];
+    if (!ix.recent || !ix.identity() || ix.rel != r) return {};
+    if (e.rel[tw.driver_rel].full.n == 0) return {};
+    out.push_back(&tw);
+  }
+  return out;
+}
+
+template <typename K>
+JoinArgs graph_join_args(Engine& e, const Plan& tw, RelState& R, int ar) {
+  const Step& step = tw.steps[0];
+  const IndexSpec& spec = e.prog.indexes[step.index];
+  const RelState& D = e.rel[tw.driver_rel];
+  JoinArgs a{};
+  a.sr = e.sr;
+  a.k = e.k;
+  a.q = e.qtab.as<float>();
+  a.items = e.cfg.items;
+  a.dkeys = D.full.keys.p;
+  a.dtags = D.full.tags.p;
+  a.dids = nullptr;
+  a.n = D.full.n;
+  a.dlay = e.layout(e.prog.rels[tw.driver_rel].arity);
+  a.w = spec.w;
+  for (int j = 0; j < spec.w; ++j) a.jsrc[j] = step.join_src[j];
+  a.off = e.idx[step.index].off.as<uint32_t>();
+  a.ikeys = R.recent.keys.p;
+  a.itags = R.recent.tags.p;
+  a.iids = nullptr;
+  a.ilay = e.layout(ar);
+  const int ocols = (int)step.out_vars.size();
+  a.olay = e.layout(ocols);
+  for (int c = 0; c < ocols; ++c) a.osrc[c] = step.out_src[c];
+  a.index_first = step.body_pos < tw.driver_atom;
+  return a;
+}
+
+// Enqueue one round body (no host interaction: capturable).
+template <typename K>
+void enqueue_graph_round(Engine& e, int r, const std::vector<const Plan*>& plans) {
+  RelState& R = e.rel[r];
+  hipStream_t st = e.stream;
+  const int ar = e.prog.rels[r].arity;
+  for (const Plan* tw : plans) {
+    const Step& step = tw->steps[0];
+    const IndexSpec& spec = e.prog.indexes[step.index];
+    const int pbits = e.sbits + spec.w * e.cbits;
+    csr_build_dn<K>(R.recent.keys.as<K>(), total_slot(e, S_UNIQUE), e.key_width(ar), pbits,
+                    e.idx[step.index].off.as<uint32_t>(), st);
+    const JoinArgs a = graph_join_args<K>(e, *tw, R, ar);
+    join_count<K>(a, e.counts.as<uint32_t>(), st);
+    scan_u32(e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), a.n, total_slot(e, S_SCAN), true,
+             e.scratch.as<uint64_t>(), st);
+    accumulate_total(total_slot(e, S_SCAN), total_slot(e, S_CAND), st);
+    DenseArgs d = dense_args(e, R);
+    join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), 0, total_slot(e, S_SCAN), (size_t)1 << 40, d, false,
+                         st);
+  }
+  const DenseArgs d = dense_args(e, R);
+  const size_t nb = dense_count_blocks(R.dense_w);
+  dense_touched_counts(d, R.dense_w, e.flags.as<uint32_t>(), st);
+  scan_u32(e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, total_slot(e, S_UNIQUE), true, e.scratch.as<uint64_t>(),
+           st);
+  dense_finalize<K>(d, R.dense_w, e.pos.as<uint32_t>(), R.recent.keys.as<K>(),
+                    e.tag_kind == TAG_F32 ? R.recent.tags.as<float>() : nullptr, 0, nullptr, st);
+  DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 32 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+}
+
+// Rounds 2.. of an eligible stratum by graph replay; returns the number of
+// rounds run (the last one changed nothing), or 0 if capture was refused.
+template <typename K>
+int graph_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& plans) {
+  const int r = st.rels[0];
+  RelState& R = e.rel[r];
+  const int ar = e.prog.rels[r].arity;
+  // every buffer the body touches at its final size, before capture
+  const size_t keys = (size_t)1 << R.dense_w;
+  e.grow(R.recent.keys, keys * sizeof(K) + 8, true, R.recent.n * sizeof(K));
+  if (e.tag_kind == TAG_F32) e.grow(R.recent.tags, keys * 4 + 8, true, R.recent.n * 4);
+  size_t words = scan_scratch_words(dense_count_blocks(R.dense_w));
+  for (const Plan* tw : plans) {
+    const size_t n = e.rel[tw->driver_rel].full.n;
+    e.grow(e.counts, n * 4 + 4);
+    e.grow(e.offs, (n + 1) * 4);
+    words = std::max(words, scan_scratch_words(n));
+    const IndexSpec& spec = e.prog.indexes[tw->steps[0].index];
+    e.grow(e.idx[tw->steps[0].index].off, (((size_t)1 << (e.sbits + spec.w * e.cbits)) + 1) * 4);
+  }
+  ensure_scratch(e, words);
+  const size_t nb = dense_count_blocks(R.dense_w);
+  e.grow(e.flags, nb * 4);
+  e.grow(e.pos, (nb + 1) * 4);
+  e.sync();
+
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (hipStreamBeginCapture(e.stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  try {
+    enqueue_graph_round<K>(e, r, plans);
+  } catch (...) {
+    (void)hipStreamEndCapture(e.stream, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return 0;  // fall back to eager rounds
+  }
+  if (hipStreamEndCapture(e.stream, &graph) != hipSuccess || !graph) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipGraphDestroy(graph);
+    return 0;
+  }
+  int rounds = 0;
+  for (;;) {
+    ++rounds;
+    DL_HIP(hipGraphLaunch(exec, e.stream));
+    e.sync();
+    if (e.host[S_OVF]) {
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+      throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
+    }
+    const size_t U = e.host[S_UNIQUE];
+    R.recent.n = U;
+    ++R.version;
+    ++R.rversion;
+    e.stats.unique += U;
+    if (U == 0) break;
+  }
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  for (const Plan* tw : plans) e.idx[tw->steps[0].index].built = false;
+  return rounds;
+}
+
 }  // namespace
 
 template <typename K>
@@ -623,12 +798,21 @@ void run_fixpoint(Engine& e) {
   e.next_id = edb;
   e.lin_n = 0;
   e.lin_segs.clear();
+  DL_HIP(hipMemsetAsync(e.dtotal.p, 0, 32 * sizeof(uint64_t), e.stream));
   setup_dense(e);
   for (const Stratum& st : e.prog.strata) {
     int rounds = 1;
     for (int p : st.base_plans) run_plan<K>(e, e.prog.plans[p]);
     size_t changed = 0;
     for (int r : st.rels) changed += absorb<K>(e, r);
+    if (changed) {
+      const std::vector<const Plan*> gp = graph_plans(e, st);
+      const int gr = gp.empty() ? 0 : graph_rounds<K>(e, st, gp);
+      if (gr > 0) {
+        rounds += gr;
+        changed = 0;
+      }
+    }
     while (changed && !st.delta_plans.empty()) {
       ++rounds;
       for (int p : st.delta_plans) {
@@ -652,7 +836,8 @@ void run_fixpoint(Engine& e) {
   }
   for (size_t r = 0; r < e.rel.size(); ++r)
     if (e.prog.rels[r].derived) e.stats.derived += e.rel[r].full.n;
-  e.sync();
+  e.read_totals();
+  e.stats.candidates += e.host[S_CAND];
 }
 
 template <typename K>
@@ -716,10 +901,23 @@ size_t read_relation_t(Engine& e, int r, size_t capacity, const dl_relation_out*
 }
 
 template <typename K>
-void backward_t(Engine& e, int r, const float* gout) {
+void lookup_t(Engine& e, int r, size_t n, const uint32_t* const* cols, const uint32_t* sample, int64_t* rows,
+              float* tags) {
+  const RelState& R = e.rel[r];
+  lookup_rows<K>(R.full.keys.as<K>(), R.full.n, cols, sample, n, e.tag_kind, R.full.tags.p,
+                 e.layout(e.prog.rels[r].arity), e.qtab.as<float>(), rows, tags, e.stream);
+}
+
+template <typename K>
+void backward_t(Engine& e, int r, const float* gout, const int64_t* rows, size_t nrows) {
   RelState& R = e.rel[r];
   const size_t n = R.full.n;
   hipStream_t st = e.stream;
+  if (e.sr == DL_DIFF_TOPK && rows) {
+    topk_backward_rows<K>(R.full.tags.as<TopK>(), R.full.keys.as<K>(), e.layout(e.prog.rels[r].arity), rows, gout,
+                          nrows, e.qtab.as<float>(), e.grad_fact.as<float>(), st);
+    return;
+  }
   if (e.sr == DL_DIFF_TOPK) {
     uint32_t* samp = nullptr;
     if (e.batched && n) {
@@ -735,7 +933,8 @@ void backward_t(Engine& e, int r, const float* gout) {
   const size_t ids = e.next_id;
   e.grow(e.adj, ids * 4 + 4);
   DL_HIP(hipMemsetAsync(e.adj.p, 0, ids * 4 + 4, st));
-  scatter_add(R.full.ids.as<uint32_t>(), gout, n, e.adj.as<float>(), st);
+  if (rows) scatter_add_rows(R.full.ids.as<uint32_t>(), rows, gout, nrows, e.adj.as<float>(), st);
+  else scatter_add(R.full.ids.as<uint32_t>(), gout, n, e.adj.as<float>(), st);
   for (size_t i = e.lin_segs.size(); i-- > 0;) {
     const LineageSeg& s = e.lin_segs[i];
     lineage_backward(e.lin_owner.as<uint32_t>() + s.off, e.lin_l.as<uint32_t>() + s.off,
@@ -754,7 +953,9 @@ template void run_fixpoint<uint32_t>(Engine&);
 template void run_fixpoint<uint64_t>(Engine&);
 template size_t read_relation_t<uint32_t>(Engine&, int, size_t, const dl_relation_out*, int);
 template size_t read_relation_t<uint64_t>(Engine&, int, size_t, const dl_relation_out*, int);
-template void backward_t<uint32_t>(Engine&, int, const float*);
-template void backward_t<uint64_t>(Engine&, int, const float*);
+template void backward_t<uint32_t>(Engine&, int, const float*, const int64_t*, size_t);
+template void backward_t<uint64_t>(Engine&, int, const float*, const int64_t*, size_t);
+template void lookup_t<uint32_t>(Engine&, int, size_t, const uint32_t* const*, const uint32_t*, int64_t*, float*);
+template void lookup_t<uint64_t>(Engine&, int, size_t, const uint32_t* const*, const uint32_t*, int64_t*, float*);
 
 }  // namespace dlfix

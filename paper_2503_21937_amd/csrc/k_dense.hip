@@ -95,93 +95,97 @@ __device__ __forceinline__ void dense_close(const DenseArgs& d, const WaveSeg& w
 
 // Each wave handles DX_ITEMS rows of 64 join outputs per block and owns one
 // lineage segment (DX_ITEMS * 64 <= DENSE_SEG).
+// Tiles of BLOCK * DX_ITEMS join outputs; a block loops over tiles
+// (tile, tile + gridDim.x, ...).  The total comes from `total`, or from
+// device memory (`dtotal`) when the host did not read it back: then the grid
+// is a fixed size and blocks beyond the last tile exit at once.
 template <typename K, int TK, int DX_ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_join_expand_dense(JoinArgs a, const uint32_t* __restrict__ offs,
-                                                             size_t total, DenseArgs d, int lineage) {
+                                                             size_t total_h, const uint64_t* __restrict__ dtotal,
+                                                             DenseArgs d, int lineage) {
   using T = typename TagOf<TK>::T;
   constexpr int DX_TILE = BLOCK * DX_ITEMS;
-  constexpr int DX_LDS = 2 * DX_TILE;
   static_assert(DX_ITEMS * WAVE <= DENSE_SEG, "a wave's outputs must fit its segment");
-  __shared__ uint32_t s_off[DX_LDS];
-  __shared__ size_t s_r0, s_r1;
+  __shared__ uint32_t s_row[DX_TILE];
+  __shared__ uint32_t s_wave[NWAVES];
+  __shared__ size_t s_r[2];
   const K* dk = (const K*)a.dkeys;
   const K* ik = (const K*)a.ikeys;
   const T* dt = (const T*)a.dtags;
   const T* it = (const T*)a.itags;
-  const size_t s0 = (size_t)blockIdx.x * DX_TILE;
-  const size_t s1 = s0 + DX_TILE < total ? s0 + DX_TILE : total;
-  if (threadIdx.x == 0) {
-    s_r0 = upper_bound_u32(offs, a.n + 1, (uint32_t)s0) - 1;
-    s_r1 = upper_bound_u32(offs, a.n + 1, (uint32_t)(s1 - 1)) - 1;
+  const size_t total = dtotal ? (size_t)*dtotal : total_h;
+  if (total > 0xffffffffull) {  // offsets are 32-bit: refuse, the host reports it
+    if (blockIdx.x == 0 && threadIdx.x == 0 && d.overflow) *d.overflow = 1;
+    return;
   }
-  __syncthreads();
-  const size_t r0 = s_r0, r1 = s_r1;
-  const size_t span = r1 - r0 + 2;
-  const bool staged = span <= (size_t)DX_LDS;
-  if (staged)
-    for (size_t i = threadIdx.x; i < span; i += BLOCK) s_off[i] = offs[r0 + i];
-  __syncthreads();
-  const size_t seg = d.seg_base + (size_t)blockIdx.x * NWAVES + threadIdx.x / WAVE;
-  WaveSeg ws;
-  for (int it_ = 0; it_ < DX_ITEMS; ++it_) {
-    const size_t j = s0 + (size_t)it_ * BLOCK + threadIdx.x;
-    if (s0 + (size_t)it_ * BLOCK >= s1) break;  // uniform across the block
-    const bool act = j < s1;
-    K okey = 0;
-    float t = 0.0f;
-    uint32_t l = 0, r = 0;
-    if (act) {
-      size_t row;
-      uint32_t base;
-      if (staged) {
-        size_t u = upper_bound_u32(s_off, span, (uint32_t)j);
-        row = r0 + u - 1;
-        base = s_off[u - 1];
-      } else {
-        size_t u = upper_bound_u32(offs + r0, span, (uint32_t)j);
-        row = r0 + u - 1;
-        base = offs[row];
+  const size_t ntiles = (total + DX_TILE - 1) / DX_TILE;
+  for (size_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // uniform per block
+    const size_t s0 = tile * DX_TILE;
+    const size_t s1 = s0 + DX_TILE < total ? s0 + DX_TILE : total;
+    tile_rows<DX_ITEMS>(offs, a.n, s0, s1, s_row, s_wave, s_r);
+    const size_t seg = d.seg_base + tile * NWAVES + threadIdx.x / WAVE;
+    WaveSeg ws;
+    for (int it_ = 0; it_ < DX_ITEMS; ++it_) {
+      const size_t j = s0 + (size_t)it_ * BLOCK + threadIdx.x;
+      if (s0 + (size_t)it_ * BLOCK >= s1) break;  // uniform across the block
+      const bool act = j < s1;
+      K okey = 0;
+      float t = 0.0f;
+      uint32_t l = 0, r = 0;
+      if (act) {
+        const size_t row = s_row[j - s0];
+        const uint32_t base = offs[row];
+        const K dkey = dk[row];
+        const uint64_t p = join_prefix(dkey, a);
+        const uint32_t irow = a.off[p] + ((uint32_t)j - base);
+        const K ikey = ik[irow];
+        uint32_t v[4];
+        for (int c = 0; c < a.olay.ncols; ++c) {
+          int s = a.osrc[c];
+          v[c] = s >= 0 ? key_col(dkey, s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
+        }
+        const uint32_t sample = key_sample(dkey, a.dlay);
+        okey = key_make<K>(sample, v, a.olay);
+        if constexpr (TK == TAG_F32) {
+          const float x = dt[row], y = it[irow];
+          t = a.index_first ? f_otimes(a.sr, y, x) : f_otimes(a.sr, x, y);
+        }
+        if (lineage) {
+          l = a.dids[row];
+          r = a.iids[irow];
+        }
       }
-      const K dkey = dk[row];
-      const uint64_t p = join_prefix(dkey, a);
-      const uint32_t irow = a.off[p] + ((uint32_t)j - base);
-      const K ikey = ik[irow];
-      uint32_t v[4];
-      for (int c = 0; c < a.olay.ncols; ++c) {
-        int s = a.osrc[c];
-        v[c] = s >= 0 ? key_col(dkey, s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
-      }
-      const uint32_t sample = key_sample(dkey, a.dlay);
-      okey = key_make<K>(sample, v, a.olay);
-      if constexpr (TK == TAG_F32) {
-        const float x = dt[row], y = it[irow];
-        t = a.index_first ? f_otimes(a.sr, y, x) : f_otimes(a.sr, x, y);
-      }
-      if (lineage) {
-        l = a.dids[row];
-        r = a.iids[irow];
-      }
+      dense_emit<K>(d, ws, seg, act, okey, t, l, r, lineage != 0);
     }
-    dense_emit<K>(d, ws, seg, act, okey, t, l, r, lineage != 0);
+    dense_close(d, ws, seg, lineage != 0);
+    __syncthreads();  // s_row is rebuilt for the next tile
   }
-  dense_close(d, ws, seg, lineage != 0);
 }
 
 template <typename K>
-void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t total, const DenseArgs& d,
-                       bool lineage, hipStream_t st) {
-  if (!total) return;
+void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t total, const uint64_t* dtotal,
+                       size_t max_total, const DenseArgs& d, bool lineage, hipStream_t st) {
   const int items = norm_items(a.items);
-  const size_t nb = (total + (size_t)BLOCK * items - 1) / ((size_t)BLOCK * items);
+  const size_t tile = (size_t)BLOCK * items;
+  size_t nb;
+  if (dtotal) {  // total unknown on the host: bounded, fixed-size grid
+    const size_t need = (max_total + tile - 1) / tile;
+    nb = need < 4096 ? need : 4096;
+    if (nb == 0) return;
+  } else {
+    if (!total) return;
+    nb = (total + tile - 1) / tile;
+  }
   const double tb = tk == TAG_F32 ? 4.0 : 0.0;
   const double lin = lineage ? 4.0 : 0.0;
   // per derivation: index row read, presence word and dense tag read; per probe row: driver row + offset
-  const double bytes = total * (sizeof(K) + tb + lin + 4.0 + tb) + a.n * (sizeof(K) + tb + lin + 4.0);
-#define DL_DEXPAND(IT)                                                                              \
-  if (tk == TAG_F32)                                                                                \
-    k_join_expand_dense<K, TAG_F32, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, d, lineage ? 1 : 0);  \
-  else                                                                                              \
-    k_join_expand_dense<K, TAG_NONE, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, d, lineage ? 1 : 0);
+  const double per = (sizeof(K) + tb + lin + 4.0 + tb);
+  const double bytes = (dtotal ? 0.0 : total * per) + a.n * (sizeof(K) + tb + lin + 4.0);
+#define DL_DEXPAND(IT)                                                                                         \
+  if (tk == TAG_F32)                                                                                           \
+    k_join_expand_dense<K, TAG_F32, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0);     \
+  else                                                                                                         \
+    k_join_expand_dense<K, TAG_NONE, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0);
   DL_PROF_BEGIN(1, st);
   switch (items) {
     case 1: DL_DEXPAND(1) break;
@@ -232,23 +236,69 @@ void project_dense(const JoinArgs& a, int tk, const DenseArgs& d, bool lineage, 
     k_project_dense<K, TAG_NONE><<<nb, BLOCK, 0, st>>>(a, d, lineage ? 1 : 0);
 }
 
-// Round end: the touched bits are exactly the new and changed tuples.  Each
-// word writes its keys in ascending order at pos[word] (pos = exclusive scan
-// of the touched popcounts), so the next recent relation comes out sorted;
-// the word's tuples become present and its touched bits are cleared.
+// Round end: the touched bits are exactly the new and changed tuples.  The
+// bitmap is compacted in key order in two passes over the touched words:
+// per-block popcount sums (dense_touched_counts), their exclusive scan, then
+// dense_finalize, where every thread scans its BM_ITEMS consecutive words
+// inside the block and writes their keys in ascending order.  The touched
+// tuples become present, touched is cleared, frozen sums are clamped.
+constexpr int BM_ITEMS = 16;
+constexpr int BM_TILE = BLOCK * BM_ITEMS;
+
+size_t dense_count_blocks(int w) { return (bitmap_words(w) + BM_TILE - 1) / BM_TILE; }
+
+__global__ void k_acc_total(const uint64_t* __restrict__ src, uint64_t* __restrict__ acc) { *acc += *src; }
+
+void accumulate_total(const uint64_t* src, uint64_t* acc, hipStream_t st) { k_acc_total<<<1, 1, 0, st>>>(src, acc); }
+
+__global__ __launch_bounds__(BLOCK) void k_touched_counts(const uint32_t* __restrict__ bits, size_t words,
+                                                          uint32_t* __restrict__ partial) {
+  __shared__ uint32_t tmp[NWAVES];
+  const size_t base = (size_t)blockIdx.x * BM_TILE + (size_t)threadIdx.x * BM_ITEMS;
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < BM_ITEMS; ++i)
+    if (base + i < words) c += (uint32_t)__popc(bits[base + i]);
+  c = wave_sum(c);
+  if (lane_id() == 0) tmp[threadIdx.x / WAVE] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+}
+
+void dense_touched_counts(const DenseArgs& d, int w, uint32_t* partial, hipStream_t st) {
+  const size_t words = bitmap_words(w);
+  DL_PROF_BEGIN(6, st);
+  k_touched_counts<<<dense_count_blocks(w), BLOCK, 0, st>>>(d.touched, words, partial);
+  DL_PROF_END(6, st, words * 4.0);
+}
+
 template <typename K>
-__global__ void k_dense_finalize(DenseArgs d, size_t words, const uint32_t* __restrict__ pos, K* __restrict__ keys,
-                                 float* __restrict__ rtags, uint32_t id_base, float* __restrict__ tag_by_id) {
-  GRID_STRIDE(wi, words) {
-    uint32_t b = d.touched[wi];
-    if (!b) continue;
-    d.present[wi] |= b;
+__global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t words, const uint32_t* __restrict__ bpos,
+                                                          K* __restrict__ keys, float* __restrict__ rtags,
+                                                          uint32_t id_base, float* __restrict__ tag_by_id) {
+  __shared__ uint32_t tmp[NWAVES];
+  const size_t base = (size_t)blockIdx.x * BM_TILE + (size_t)threadIdx.x * BM_ITEMS;
+  uint32_t b[BM_ITEMS];
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < BM_ITEMS; ++i) {
+    b[i] = base + i < words ? d.touched[base + i] : 0u;
+    c += (uint32_t)__popc(b[i]);
+  }
+  uint32_t tot;
+  uint32_t o = bpos[blockIdx.x] + block_exclusive_scan(c, tmp, &tot);
+  if (c == 0) return;
+#pragma unroll
+  for (int i = 0; i < BM_ITEMS; ++i) {
+    uint32_t x = b[i];
+    if (!x) continue;
+    const size_t wi = base + i;
+    d.present[wi] |= x;
     d.touched[wi] = 0u;
-    uint32_t o = pos[wi];
-    while (b) {
-      const int i = __builtin_ctz(b);
-      b &= b - 1;
-      const uint64_t kk = ((uint64_t)wi << 5) | (uint64_t)i;
+    while (x) {
+      const int bit = __builtin_ctz(x);
+      x &= x - 1;
+      const uint64_t kk = ((uint64_t)wi << 5) | (uint64_t)bit;
       keys[o] = (K)kk;
       float t = 1.0f;
       if (d.mode == DENSE_ADD) {
@@ -268,11 +318,11 @@ __global__ void k_dense_finalize(DenseArgs d, size_t words, const uint32_t* __re
 }
 
 template <typename K>
-void dense_finalize(const DenseArgs& d, int w, const uint32_t* pos, K* keys, float* rtags, uint32_t id_base,
+void dense_finalize(const DenseArgs& d, int w, const uint32_t* bpos, K* keys, float* rtags, uint32_t id_base,
                     float* tag_by_id, hipStream_t st) {
   const size_t words = bitmap_words(w);
   DL_PROF_BEGIN(6, st);
-  k_dense_finalize<K><<<grid_for(words), BLOCK, 0, st>>>(d, words, pos, keys, rtags, id_base, tag_by_id);
+  k_dense_finalize<K><<<dense_count_blocks(w), BLOCK, 0, st>>>(d, words, bpos, keys, rtags, id_base, tag_by_id);
   DL_PROF_END(6, st, words * 12.0);
 }
 
@@ -348,8 +398,8 @@ void bitmap_keys(const DenseArgs& d, int w, const uint32_t* pos, K* keys, float*
 
 
 #define INST(K)                                                                                                       \
-  template void join_expand_dense<K>(const JoinArgs&, int, const uint32_t*, size_t, const DenseArgs&, bool,        \
-                                     hipStream_t);                                                                   \
+  template void join_expand_dense<K>(const JoinArgs&, int, const uint32_t*, size_t, const uint64_t*, size_t,     \
+                                     const DenseArgs&, bool, hipStream_t);                                                                   \
   template void project_dense<K>(const JoinArgs&, int, const DenseArgs&, bool, hipStream_t);                        \
   template void dense_finalize<K>(const DenseArgs&, int, const uint32_t*, K*, float*, uint32_t, float*, hipStream_t);       \
   template void dense_owners<K>(const DenseArgs&, const K*, size_t, uint32_t*, hipStream_t);                                  \

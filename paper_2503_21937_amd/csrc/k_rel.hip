@@ -70,7 +70,9 @@ void permute_keys(const K* in, size_t n, KeyLayout l, const int* perm, K* out, h
 
 // ------------------------------------------------------------------ CSR
 template <typename K>
-__global__ void k_csr(const K* __restrict__ keys, size_t n, int shift, uint64_t domain, uint32_t* __restrict__ off) {
+__global__ void k_csr(const K* __restrict__ keys, size_t n_h, const uint64_t* __restrict__ dn, int shift,
+                      uint64_t domain, uint32_t* __restrict__ off) {
+  const size_t n = dn ? (size_t)*dn : n_h;
   GRID_STRIDE(v, domain + 1) {
     size_t lo = 0, hi = n;  // first row with prefix >= v
     while (lo < hi) {
@@ -86,8 +88,14 @@ template <typename K>
 void csr_build(const K* keys, size_t n, int total_bits, int prefix_bits, uint32_t* off, hipStream_t st) {
   uint64_t domain = 1ull << prefix_bits;
   DL_PROF_BEGIN(9, st);
-  k_csr<K><<<grid_for(domain + 1), BLOCK, 0, st>>>(keys, n, total_bits - prefix_bits, domain, off);
+  k_csr<K><<<grid_for(domain + 1), BLOCK, 0, st>>>(keys, n, nullptr, total_bits - prefix_bits, domain, off);
   DL_PROF_END(9, st, (domain + 1) * 4.0 + (double)n * sizeof(K));
+}
+
+template <typename K>
+void csr_build_dn(const K* keys, const uint64_t* dn, int total_bits, int prefix_bits, uint32_t* off, hipStream_t st) {
+  uint64_t domain = 1ull << prefix_bits;
+  k_csr<K><<<grid_for(domain + 1), BLOCK, 0, st>>>(keys, 0, dn, total_bits - prefix_bits, domain, off);
 }
 
 // ------------------------------------------------------------------ joins
@@ -115,41 +123,22 @@ __global__ __launch_bounds__(BLOCK) void k_join_expand(JoinArgs a, const uint32_
                                                        uint32_t* __restrict__ ol, uint32_t* __restrict__ orr) {
   using T = typename TagOf<TK>::T;
   constexpr int EXP_TILE = BLOCK * EXP_ITEMS;
-  constexpr int EXP_LDS = 2 * EXP_TILE;
-  __shared__ uint32_t s_off[EXP_LDS];
-  __shared__ size_t s_r0, s_r1;
+  __shared__ uint32_t s_row[EXP_TILE];
+  __shared__ uint32_t s_wave[NWAVES];
+  __shared__ size_t s_r[2];
   const K* dk = (const K*)a.dkeys;
   const K* ik = (const K*)a.ikeys;
   const T* dt = (const T*)a.dtags;
   const T* it = (const T*)a.itags;
   const size_t s0 = (size_t)blockIdx.x * EXP_TILE;
   const size_t s1 = s0 + EXP_TILE < total ? s0 + EXP_TILE : total;  // exclusive
-  if (threadIdx.x == 0) {
-    s_r0 = upper_bound_u32(offs, a.n + 1, (uint32_t)s0) - 1;
-    s_r1 = upper_bound_u32(offs, a.n + 1, (uint32_t)(s1 - 1)) - 1;
-  }
-  __syncthreads();
-  const size_t r0 = s_r0, r1 = s_r1;
-  const size_t span = r1 - r0 + 2;  // offs[r0 .. r1+1]
-  const bool staged = span <= (size_t)EXP_LDS;
-  if (staged)
-    for (size_t i = threadIdx.x; i < span; i += BLOCK) s_off[i] = offs[r0 + i];
-  __syncthreads();
+  tile_rows<EXP_ITEMS>(offs, a.n, s0, s1, s_row, s_wave, s_r);
 #pragma unroll
   for (int it_ = 0; it_ < EXP_ITEMS; ++it_) {
     const size_t j = s0 + (size_t)it_ * BLOCK + threadIdx.x;
     if (j >= s1) break;
-    size_t row;
-    uint32_t base;
-    if (staged) {
-      size_t u = upper_bound_u32(s_off, span, (uint32_t)j);
-      row = r0 + u - 1;
-      base = s_off[u - 1];
-    } else {
-      size_t u = upper_bound_u32(offs + r0, span, (uint32_t)j);
-      row = r0 + u - 1;
-      base = offs[row];
-    }
+    const size_t row = s_row[j - s0];
+    const uint32_t base = offs[row];
     const K dkey = dk[row];
     const uint64_t p = join_prefix(dkey, a);
     const uint32_t irow = a.off[p] + ((uint32_t)j - base);
@@ -660,12 +649,102 @@ void topk_backward(const TopK* t, const uint32_t* sample, const float* gout, siz
   if (n) k_topk_backward<<<grid_for(n), BLOCK, 0, st>>>(t, sample, gout, n, qtab, grad);
 }
 
+// ------------------------------------------------------------ point queries
+struct QCols {
+  const uint32_t* c[4];
+  const uint32_t* sample;
+};
+
+template <typename K>
+__global__ void k_lookup(const K* __restrict__ keys, size_t n, QCols qc, size_t nq, int tk,
+                         const void* __restrict__ tags, KeyLayout lay, const float* __restrict__ qtab,
+                         int64_t* __restrict__ rows, float* __restrict__ qtag) {
+  GRID_STRIDE(i, nq) {
+    uint32_t v[4];
+    bool ok = true;
+    for (int c = 0; c < lay.ncols; ++c) {
+      v[c] = qc.c[c][i];
+      ok = ok && ((uint64_t)v[c] >> lay.cbits) == 0;
+    }
+    const uint32_t smp = qc.sample ? qc.sample[i] : 0u;
+    ok = ok && (lay.sbits ? ((uint64_t)smp >> lay.sbits) == 0 : smp == 0);
+    const K q = key_make<K>(smp, v, lay);
+    size_t lo = 0, hi = ok ? n : 0;
+    while (lo < hi) {
+      size_t mid = (lo + hi) >> 1;
+      if (keys[mid] < q) lo = mid + 1;
+      else hi = mid;
+    }
+    const bool found = ok && lo < n && keys[lo] == q;
+    if (rows) rows[i] = found ? (int64_t)lo : -1;
+    if (qtag) {
+      float t = 0.0f;
+      if (found) {
+        if (tk == TAG_F32) t = ((const float*)tags)[lo];
+        else if (tk == TAG_NONE) t = 1.0f;
+        else t = (float)incl_excl(((const TopK*)tags)[lo], qtab + (size_t)key_sample(q, lay) * 64, -1, nullptr);
+      }
+      qtag[i] = t;
+    }
+  }
+}
+
+template <typename K>
+void lookup_rows(const K* keys, size_t n, const uint32_t* const* qcols, const uint32_t* qsample, size_t nq, int tk,
+                 const void* tags, KeyLayout lay, const float* qtab, int64_t* rows, float* qtag, hipStream_t st) {
+  if (!nq) return;
+  QCols qc{{nullptr, nullptr, nullptr, nullptr}, qsample};
+  for (int c = 0; c < lay.ncols; ++c) qc.c[c] = qcols[c];
+  k_lookup<K><<<grid_for(nq), BLOCK, 0, st>>>(keys, n, qc, nq, tk, tags, lay, qtab, rows, qtag);
+}
+
+__global__ void k_scatter_add_rows(const uint32_t* __restrict__ ids, const int64_t* __restrict__ rows,
+                                   const float* __restrict__ g, size_t n, float* adj) {
+  GRID_STRIDE(i, n) {
+    if (rows[i] >= 0) atomicAdd(&adj[ids[rows[i]]], g[i]);
+  }
+}
+
+void scatter_add_rows(const uint32_t* ids, const int64_t* rows, const float* g, size_t n, float* adj, hipStream_t st) {
+  if (n) k_scatter_add_rows<<<grid_for(n), BLOCK, 0, st>>>(ids, rows, g, n, adj);
+}
+
+template <typename K>
+__global__ void k_topk_backward_rows(const TopK* __restrict__ t, const K* __restrict__ keys, KeyLayout lay,
+                                     const int64_t* __restrict__ rows, const float* __restrict__ gout, size_t n,
+                                     const float* __restrict__ qtab, float* grad) {
+  GRID_STRIDE(i, n) {
+    const float g = gout[i];
+    if (g == 0.0f || rows[i] < 0) continue;
+    const size_t r = (size_t)rows[i];
+    const TopK x = t[r];
+    const uint32_t s = key_sample(keys[r], lay);
+    const float* q = qtab + (size_t)s * 64;
+    uint64_t all = 0;
+    for (uint32_t j = 0; j < x.cnt; ++j) all |= x.b[j];
+    while (all) {
+      int bit = __builtin_ctzll(all);
+      all &= all - 1;
+      double d = 0;
+      incl_excl(x, q, bit, &d);
+      atomicAdd(&grad[(size_t)s * 64 + bit], (float)((double)g * d));
+    }
+  }
+}
+
+template <typename K>
+void topk_backward_rows(const TopK* t, const K* keys, KeyLayout lay, const int64_t* rows, const float* g, size_t n,
+                        const float* qtab, float* grad_fact, hipStream_t st) {
+  if (n) k_topk_backward_rows<K><<<grid_for(n), BLOCK, 0, st>>>(t, keys, lay, rows, g, n, qtab, grad_fact);
+}
+
 // ------------------------------------------------------- instantiations
 #define INST(K)                                                                                                      \
   template void pack_rows<K>(const uint32_t* const*, const uint32_t*, size_t, KeyLayout, K*, hipStream_t);         \
   template void unpack_rows<K>(const K*, size_t, KeyLayout, uint32_t* const*, uint32_t*, hipStream_t);             \
   template void permute_keys<K>(const K*, size_t, KeyLayout, const int*, K*, hipStream_t);                        \
   template void csr_build<K>(const K*, size_t, int, int, uint32_t*, hipStream_t);                                   \
+  template void csr_build_dn<K>(const K*, const uint64_t*, int, int, uint32_t*, hipStream_t);                       \
   template void join_count<K>(const JoinArgs&, uint32_t*, hipStream_t);                                             \
   template void join_expand<K>(const JoinArgs&, int, const uint32_t*, size_t, void*, void*, uint32_t*, uint32_t*,   \
                                hipStream_t);                                                                         \
@@ -678,7 +757,15 @@ void topk_backward(const TopK* t, const uint32_t* sample, const float* gout, siz
   template void merge_sorted<K>(const K*, const void*, const uint32_t*, size_t, const K*, const void*,              \
                                 const uint32_t*, size_t, size_t, K*, void*, uint32_t*, uint64_t*, hipStream_t);
 
+#define INST2(K)                                                                                                 \
+  template void lookup_rows<K>(const K*, size_t, const uint32_t* const*, const uint32_t*, size_t, int,           \
+                               const void*, KeyLayout, const float*, int64_t*, float*, hipStream_t);                                                    \
+  template void topk_backward_rows<K>(const TopK*, const K*, KeyLayout, const int64_t*, const float*, size_t,     \
+                                      const float*, float*, hipStream_t);
+
 INST(uint32_t)
 INST(uint64_t)
+INST2(uint32_t)
+INST2(uint64_t)
 
 }  // namespace dlfix

@@ -54,6 +54,9 @@ void permute_keys(const K* in, size_t n, KeyLayout lay, const int* perm, K* out,
 // keys: off[v] = first row whose prefix >= v, for v in [0, 2^prefix_bits].
 template <typename K>
 void csr_build(const K* keys, size_t n, int total_bits, int prefix_bits, uint32_t* off, hipStream_t st);
+// The same with the row count read from device memory (graph replay).
+template <typename K>
+void csr_build_dn(const K* keys, const uint64_t* dn, int total_bits, int prefix_bits, uint32_t* off, hipStream_t st);
 
 // Tag payload kinds of the relational kernels.
 enum TagKind : int { TAG_NONE = 0, TAG_F32 = 1, TAG_TOPK = 2 };
@@ -104,6 +107,7 @@ struct DenseArgs {
   uint32_t* log_r;
   uint32_t* seg_lcount;
   uint32_t seg_base;   // first segment of this launch
+  uint64_t* overflow;  // set to 1 when a device-side total exceeds the 32-bit offsets
   int mode;
 };
 constexpr int DENSE_SEG = 512;  // slots per wave segment (64 lanes x up to 8 rows)
@@ -120,18 +124,26 @@ void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st);
 template <typename K>
 void join_expand(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t total, void* okeys, void* otags,
                  uint32_t* olin_l, uint32_t* olin_r, hipStream_t st);
-// The same join, emitting into a dense-domain relation (see DenseArgs).
+// The same join, emitting into a dense-domain relation (see DenseArgs).  If
+// dtotal is not NULL the total is read on the device (the host passes an
+// upper bound max_total for the grid) and `total` is ignored.
 template <typename K>
-void join_expand_dense(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t total, const DenseArgs& d,
-                       bool lineage, hipStream_t st);
+void join_expand_dense(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t total, const uint64_t* dtotal,
+                       size_t max_total, const DenseArgs& d, bool lineage, hipStream_t st);
+// *acc += *src (device words)
+void accumulate_total(const uint64_t* src, uint64_t* acc, hipStream_t st);
 template <typename K>
 void project_dense(const JoinArgs& a, int tag_kind, const DenseArgs& d, bool lineage, hipStream_t st);
-// After the round (pos = exclusive scan of the touched popcounts): write the
-// touched keys in ascending order with their tags (rtags may be NULL), make
-// them present, clear touched, clamp frozen sums and, with lineage, assign
-// ids base.. in key order and record tags by id.
+// Round end, pass 1: touched-key count of every block of the touched bitmap
+// (dense_count_blocks(w) entries).
+size_t dense_count_blocks(int w);
+void dense_touched_counts(const DenseArgs& d, int w, uint32_t* partial, hipStream_t st);
+// Pass 2 (bpos = exclusive scan of those counts): write the touched keys in
+// ascending order with their tags (rtags may be NULL), make them present,
+// clear touched, clamp frozen sums and, with lineage, assign ids base.. in
+// key order and record tags by id.
 template <typename K>
-void dense_finalize(const DenseArgs& d, int w, const uint32_t* pos, K* keys, float* rtags, uint32_t id_base,
+void dense_finalize(const DenseArgs& d, int w, const uint32_t* bpos, K* keys, float* rtags, uint32_t id_base,
                     float* tag_by_id, hipStream_t st);
 // owner[i] = did[keys[i]]
 template <typename K>
@@ -186,6 +198,21 @@ void merge_sorted(const K* ak, const void* at, const uint32_t* aid, size_t na, c
 // pos[p] + flags[p] - 1 (maps every input fact to its merged entry).
 void seg_scatter(const uint32_t* pos, const uint32_t* flags, const uint32_t* perm, size_t n, uint32_t base,
                  uint32_t* out, hipStream_t st);
+
+// Point queries against a sorted relation (query columns SoA + sample ids,
+// values outside the key layout count as absent): row[i] = position in keys
+// or -1, tag[i] = its tag as a float (1 for bool, inclusion-exclusion
+// probability for top-k, 0 if absent).
+template <typename K>
+void lookup_rows(const K* keys, size_t n, const uint32_t* const* qcols, const uint32_t* qsample, size_t nq,
+                 int tag_kind, const void* tags, KeyLayout lay, const float* qtab, int64_t* rows, float* qtag,
+                 hipStream_t st);
+// adj[ids[rows[i]]] += g[i] for rows[i] >= 0
+void scatter_add_rows(const uint32_t* ids, const int64_t* rows, const float* g, size_t n, float* adj, hipStream_t st);
+// top-k gradient seeded on selected rows of a relation
+template <typename K>
+void topk_backward_rows(const TopK* t, const K* keys, KeyLayout lay, const int64_t* rows, const float* g, size_t n,
+                        const float* qtab, float* grad_fact, hipStream_t st);
 
 // ---------------------------------------------------------- tags & grads
 // Input facts -> tags: f32 copy (bool: none); top-k: [(1 << local_id, q)].

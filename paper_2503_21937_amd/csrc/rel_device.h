@@ -76,4 +76,54 @@ __device__ __forceinline__ size_t upper_bound_u32(const uint32_t* a, size_t n, u
 }
 
 
+// Owning probe row of every output slot of the tile [s0, s1) of a
+// load-balanced expansion (offs = exclusive scan of the match counts, with
+// sentinel offs[n] = total): every row with matches marks the slot where its
+// outputs start, then an inclusive max-scan over the tile carries each row
+// id over its slots (rows without matches mark nothing, so the last marked
+// row at or before a slot owns it).  Result: s_row[t] for t < s1 - s0.
+// Must be called by the whole 256-thread block; s_row holds BLOCK * ITEMS.
+template <int ITEMS>
+__device__ __forceinline__ void tile_rows(const uint32_t* __restrict__ offs, size_t n, size_t s0, size_t s1,
+                                          uint32_t* s_row, uint32_t* s_wave, size_t* s_r) {
+  constexpr int TILE = BLOCK * ITEMS;
+  if (threadIdx.x == 0) {
+    s_r[0] = upper_bound_u32(offs, n + 1, (uint32_t)s0) - 1;
+    s_r[1] = upper_bound_u32(offs, n + 1, (uint32_t)(s1 - 1)) - 1;
+  }
+  for (int t = threadIdx.x; t < TILE; t += BLOCK) s_row[t] = 0u;
+  __syncthreads();
+  const size_t r0 = s_r[0], r1 = s_r[1];
+  if (threadIdx.x == 0) s_row[0] = (uint32_t)r0;
+  for (size_t r = r0 + 1 + threadIdx.x; r <= r1; r += BLOCK) {
+    const uint32_t o = offs[r];
+    if (o < s1 && offs[r + 1] > o) s_row[o - s0] = (uint32_t)r;
+  }
+  __syncthreads();
+  // inclusive max-scan over the tile: blocked per thread, then across threads
+  uint32_t v[ITEMS];
+  uint32_t m = 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    v[i] = s_row[threadIdx.x * ITEMS + i];
+    m = v[i] > m ? v[i] : m;
+    v[i] = m;
+  }
+  const int lane = lane_id(), w = threadIdx.x / WAVE;
+  uint32_t inc = m;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    uint32_t t = __shfl_up(inc, d, WAVE);
+    if (lane >= d) inc = t > inc ? t : inc;
+  }
+  if (lane == WAVE - 1) s_wave[w] = inc;
+  uint32_t before = __shfl_up(inc, 1, WAVE);
+  if (lane == 0) before = 0;
+  __syncthreads();
+  for (int i = 0; i < w; ++i) before = s_wave[i] > before ? s_wave[i] : before;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) s_row[threadIdx.x * ITEMS + i] = v[i] > before ? v[i] : before;
+  __syncthreads();
+}
+
 }  // namespace dlfix

@@ -20,7 +20,7 @@ SEMIRINGS = {"bool": 0, "maxmin": 1, "minplus": 2, "addmult": 3,
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_PARSE", 3: "ERR_UNSUPPORTED", 4: "ERR_STATE",
           5: "ERR_NOMEM", 6: "ERR_CAPACITY", 7: "ERR_PROOF_OVERFLOW", 8: "ERR_HIP"}
 EXPORTS = ["dl_load_program", "dl_clear_facts", "dl_add_facts", "dl_run_fixpoint",
-           "dl_relation_size", "dl_read_relation", "dl_backward", "dl_read_grad",
+           "dl_relation_size", "dl_read_relation", "dl_lookup", "dl_backward_rows", "dl_backward", "dl_read_grad",
            "dl_zero_grad", "dl_get_stats", "dl_autotune", "dl_profile", "dl_get_kernel_timing",
            "dl_last_error", "dl_free"]
 KERNEL_FAMILIES = ["join_count", "join_expand", "sort_hist", "sort_scatter", "scan", "reduce",
@@ -35,7 +35,7 @@ class DLError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("semiring", C.c_int), ("k", C.c_int), ("batched", C.c_int),
-                ("stream", C.c_void_p), ("dedup", C.c_int)]
+                ("stream", C.c_void_p), ("dedup", C.c_int), ("no_graphs", C.c_int)]
 
 
 class RelationOut(C.Structure):
@@ -81,6 +81,8 @@ def lib():
         L.dl_read_relation.argtypes = [vp, C.c_char_p, sz, C.POINTER(RelationOut), C.c_int,
                                        C.POINTER(sz)]
         L.dl_backward.argtypes = [vp, C.c_char_p, vp, C.c_int]
+        L.dl_lookup.argtypes = [vp, C.c_char_p, sz, vp, vp, vp, vp, C.c_int]
+        L.dl_backward_rows.argtypes = [vp, C.c_char_p, sz, vp, vp, C.c_int]
         L.dl_read_grad.argtypes = [vp, C.c_char_p, vp, C.c_int]
         L.dl_zero_grad.argtypes = [vp]
         L.dl_get_stats.argtypes = [vp, C.POINTER(Stats)]
@@ -129,7 +131,7 @@ class Engine:
 
     def __init__(self, program: str, semiring: str = "bool", k: int = 3,
                  batched: bool = False, stream: int | None = None, use_torch_stream: bool = True,
-                 dedup: str = "auto"):
+                 dedup: str = "auto", graphs: bool = True):
         self.arity = {}
         for line in program.splitlines():
             line = line.strip()
@@ -141,7 +143,7 @@ class Engine:
         self.batched = batched
         if stream is None and use_torch_stream:
             stream = _current_stream()
-        opts = Options(SEMIRINGS[semiring], k, int(batched), stream, self.DEDUP[dedup])
+        opts = Options(SEMIRINGS[semiring], k, int(batched), stream, self.DEDUP[dedup], int(not graphs))
         h = C.c_void_p()
         rc = lib().dl_load_program(program.encode(), C.byref(opts), C.byref(h))
         if rc:
@@ -225,6 +227,36 @@ class Engine:
                 out["bits"] = out["bits"].T.copy()
                 out["p"] = out["p"].T.copy()
         return out
+
+    def lookup(self, rel: str, cols, sample=None, device: bool = False):
+        """Rows (canonical index or -1) and tags of the given tuples."""
+        keep = []
+        ptrs = (C.c_void_p * 4)()
+        n, dev = None, False
+        for i, c in enumerate(cols):
+            p_, a, d = _ptr(c, np.uint32)
+            keep.append(a)
+            ptrs[i] = p_
+            n, dev = int(a.shape[0]), bool(d)
+        sp, sa, _ = _ptr(sample, np.uint32)
+        keep.append(sa)
+        if dev:
+            import torch
+            rows = torch.empty(n, dtype=torch.int64, device=cols[0].device)
+            tags = torch.empty(n, dtype=torch.float32, device=cols[0].device)
+            rp, tp = rows.data_ptr(), tags.data_ptr()
+        else:
+            rows = np.empty(n, np.int64)
+            tags = np.empty(n, np.float32)
+            rp, tp = rows.ctypes.data, tags.ctypes.data
+        self._check(lib().dl_lookup(self.h, rel.encode(), n, sp, ptrs, rp, tp, int(dev)))
+        return rows, tags
+
+    def backward_rows(self, rel: str, rows, grad):
+        rp, ra, dev = _ptr(rows, np.int64)
+        gp, ga, _ = _ptr(grad, np.float32)
+        n = int(ra.shape[0])
+        self._check(lib().dl_backward_rows(self.h, rel.encode(), n, rp, gp, int(bool(dev))))
 
     def backward(self, rel: str, grad_out):
         p, a, dev = _ptr(grad_out, np.float32)

@@ -130,3 +130,29 @@ def test_dedup_pipelines_agree(synth):
         else:
             assert_tags_close(ra["tags"], rb["tags"], rtol=1e-6, what=sr)
         assert a.stats()["max_rounds"] == b.stats()["max_rounds"], sr
+
+
+def test_graph_replay_matches_eager_rounds(synth):
+    """Round bodies replayed from a captured HIP graph give the relation the
+    eagerly launched rounds give, on repeated runs of one engine with other
+    GPU work and synchronisations in between."""
+    import torch
+    from paper_2503_21937_amd import dlfix
+    src, dst, p = synth.er_graph(6, 3000, 12000, weights=True)
+    for sr in SEMIRINGS:
+        eager = dlfix.Engine(synth.TC_PROGRAM, sr, graphs=False)
+        eager.add_facts("edge", [src, dst], p)
+        ref = eager.run().read("path")
+        g = dlfix.Engine(synth.TC_PROGRAM, sr, graphs=True)
+        g.add_facts("edge", [src, dst], p)
+        for rep in range(3):
+            x = torch.randn(1 << 20, device="cuda")
+            (x * 2).sum().item()
+            got = g.run().read("path")
+            torch.cuda.synchronize()
+            assert np.array_equal(got["cols"], ref["cols"]), (sr, rep)
+            if sr == "addmult":
+                assert_tags_close(got["tags"], ref["tags"], rtol=1e-6, what=sr)
+            else:
+                assert np.array_equal(got["tags"], ref["tags"]), (sr, rep)
+            assert g.stats()["max_rounds"] == eager.stats()["max_rounds"]
