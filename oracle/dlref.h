@@ -72,6 +72,15 @@ void ref_zero_grad(ref_engine*);
 const char* ref_error(ref_engine*);
 void ref_free(ref_engine*);
 
+/* The oracle's tag algebra, exposed for the semiring-law tests.
+ * Scalar semirings: *out = a (+ or x) b with op 0 = plus, 1 = times; the
+ * top-k form takes proof lists (cnt, bits[3]) over facts with probabilities
+ * q[64] and writes the resulting list.  zero/one return the identities. */
+int ref_scalar_op(int semiring, int op, double a, double b, double* out);
+int ref_scalar_identity(int semiring, int which, double* out);
+int ref_topk_op(int k, int op, int acnt, const uint64_t* abits, int bcnt, const uint64_t* bbits,
+                const float* q, int* ocnt, uint64_t* obits, float* oprob);
+
 /* Single target column z of the transitive closure program
  *     path(x, y) :- edge(x, y).
  *     path(x, z) :- edge(x, y), path(y, z).

@@ -774,4 +774,48 @@ const char* ref_error(ref_engine* e) { return e->err.c_str(); }
 
 void ref_free(ref_engine* e) { delete e; }
 
+int ref_scalar_op(int semiring, int op, double a, double b, double* out) {
+  if (semiring < REF_BOOL || semiring > REF_DIFF_ADDMULT) return 1;
+  Semiring sr{semiring, 1};
+  Tag x, y;
+  x.v = a;
+  y.v = b;
+  std::vector<float> q;
+  *out = (op ? sr.otimes(x, y, q) : sr.oplus(x, y, q)).v;
+  return 0;
+}
+
+int ref_scalar_identity(int semiring, int which, double* out) {
+  if (semiring < REF_BOOL || semiring > REF_DIFF_ADDMULT) return 1;
+  Semiring sr{semiring, 1};
+  if (which == 0) *out = sr.zero().v;  // absorbing for x, neutral for +
+  else *out = semiring == REF_MINPLUS ? 0.0 : 1.0;
+  return 0;
+}
+
+int ref_topk_op(int k, int op, int acnt, const uint64_t* abits, int bcnt, const uint64_t* bbits, const float* q,
+                int* ocnt, uint64_t* obits, float* oprob) {
+  if (k < 1 || k > KMAX || acnt < 0 || acnt > KMAX || bcnt < 0 || bcnt > KMAX) return 1;
+  Semiring sr{REF_TOPK, k};
+  std::vector<float> qv(q, q + 64);
+  Tag a, b;
+  a.cnt = acnt;
+  b.cnt = bcnt;
+  for (int i = 0; i < acnt; ++i) {
+    a.bits[i] = abits[i];
+    a.p[i] = Semiring::proof_prob(abits[i], qv);
+  }
+  for (int i = 0; i < bcnt; ++i) {
+    b.bits[i] = bbits[i];
+    b.p[i] = Semiring::proof_prob(bbits[i], qv);
+  }
+  Tag t = op ? sr.otimes(a, b, qv) : sr.oplus(a, b, qv);
+  *ocnt = t.cnt;
+  for (int i = 0; i < KMAX; ++i) {
+    obits[i] = i < t.cnt ? t.bits[i] : 0;
+    oprob[i] = i < t.cnt ? t.p[i] : 0.0f;
+  }
+  return 0;
+}
+
 }  // extern "C"

@@ -60,6 +60,9 @@ def lib():
         L.ref_error.argtypes = [vp]
         L.ref_error.restype = C.c_char_p
         L.ref_free.argtypes = [vp]
+        L.ref_scalar_op.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double)]
+        L.ref_scalar_identity.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double)]
+        L.ref_topk_op.argtypes = [C.c_int, C.c_int, C.c_int, vp, C.c_int, vp, vp, vp, vp, vp]
         L.ref_tc_column.argtypes = [C.c_int, sz, vp, vp, vp, C.c_int, C.c_uint32,
                                     vp, vp, vp, vp, vp, vp]
         L.ref_andersen.argtypes = [C.c_uint32, sz, vp, sz, vp, sz, vp, sz, vp]
@@ -196,3 +199,33 @@ def andersen(nvars: int, rels: dict) -> tuple[np.ndarray, np.ndarray]:
     lib().ref_pts_read(h, _p(v), _p(o))
     lib().ref_pts_free(h)
     return v, o
+
+
+def scalar_op(semiring: str, op: str, a: float, b: float) -> float:
+    out = C.c_double()
+    if lib().ref_scalar_op(SEMIRINGS[semiring], 1 if op == "times" else 0, a, b, C.byref(out)):
+        raise ValueError(semiring)
+    return out.value
+
+
+def scalar_identity(semiring: str, which: str) -> float:
+    out = C.c_double()
+    if lib().ref_scalar_identity(SEMIRINGS[semiring], 1 if which == "one" else 0, C.byref(out)):
+        raise ValueError(semiring)
+    return out.value
+
+
+def topk_op(k: int, op: str, a, b, q):
+    """a, b: lists of proof bitsets; returns (bits list, probs list)."""
+    ab = np.zeros(3, np.uint64)
+    bb = np.zeros(3, np.uint64)
+    ab[: len(a)] = a
+    bb[: len(b)] = b
+    qa = np.ascontiguousarray(q, np.float32)
+    cnt = C.c_int()
+    ob = np.zeros(3, np.uint64)
+    op_ = np.zeros(3, np.float32)
+    if lib().ref_topk_op(k, 1 if op == "times" else 0, len(a), _p(ab), len(b), _p(bb), _p(qa), C.byref(cnt),
+                         _p(ob), _p(op_)):
+        raise ValueError("topk_op")
+    return [int(x) for x in ob[: cnt.value]], [float(x) for x in op_[: cnt.value]]
