@@ -145,8 +145,8 @@ typedef struct {
  * head variable occurs in the body; every body atom after the first shares a
  * variable with the atoms before it.  Strata are the strongly connected
  * components of the predicate graph, evaluated in dependency order
- * (Algorithm 1).  Under the ADDMULT forms a rule may contain at most one atom
- * of its own stratum, and DIFF_ADDMULT rules have at most 2 body atoms.
+ * (Algorithm 1).  DIFF_ADDMULT rules have at most 2 body atoms (a recorded
+ * derivation holds two body ids).
  * Anything else returns DL_ERR_UNSUPPORTED.  On success *out owns a new
  * engine (free with dl_free). */
 dl_status dl_load_program(const char* program_text, const dl_options* opts, dl_engine** out);

@@ -89,6 +89,10 @@ class Oracle:
             if line.startswith(".input") or line.startswith(".output"):
                 name, ar = line.split()[1].split("/")
                 self.arity[name] = int(ar)
+            elif ":-" in line:  # a rule head names a derived relation
+                head = line.split(":-")[0]
+                name, args = head.split("(", 1)
+                self.arity.setdefault(name.strip(), args.count(",") + 1)
         self.semiring = semiring
         self.batched = batched
         h = C.c_void_p()

@@ -102,6 +102,7 @@ void setup_dense(Engine& e) {
 // Sorted full relation of a dense relation, from its presence bitmap.
 template <typename K>
 void materialize_full(Engine& e, RelState& R) {
+  std::swap(R.full, R.full_alt);  // the previous materialisation stays as the stable part
   const size_t words = bitmap_words(R.dense_w);
   e.grow(e.flags, words * 4);
   e.grow(e.pos, (words + 1) * 4);
@@ -131,7 +132,7 @@ void build_index(Engine& e, int i) {
   const IndexSpec& spec = e.prog.indexes[i];
   IndexState& ix = e.idx[i];
   RelState& R = e.rel[spec.rel];
-  const Table& src = spec.recent ? R.recent : R.full;
+  const Table& src = spec.recent ? R.recent : spec.stable ? R.full_alt : R.full;
   const int ar = e.prog.rels[spec.rel].arity;
   const KeyLayout lay = e.layout(ar);
   const size_t n = src.n;
@@ -180,7 +181,7 @@ void ensure_index(Engine& e, int i) {
   IndexState& ix = e.idx[i];
   const IndexSpec& spec = e.prog.indexes[i];
   const RelState& R = e.rel[spec.rel];
-  const Table& src = spec.recent ? R.recent : R.full;
+  const Table& src = spec.recent ? R.recent : spec.stable ? R.full_alt : R.full;
   bool stale = !ix.built || ix.version != (spec.recent ? R.rversion : R.version);
   if (ix.borrowed && ix.t.keys.p != src.keys.p) stale = true;
   if (stale) build_index<K>(e, i);
@@ -791,6 +792,7 @@ void run_fixpoint(Engine& e) {
       edb += (uint32_t)R.full.n;
     } else {
       R.full.n = 0;
+      R.full_alt.n = 0;
       R.recent.n = 0;
       ++R.version;
     }

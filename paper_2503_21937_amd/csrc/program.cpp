@@ -217,7 +217,10 @@ int add_index(Program& p, const IndexSpec& ix) {
   return (int)p.indexes.size() - 1;
 }
 
-Plan make_plan(Program& p, int rule_id, int driver, bool delta, int recent_atom = -1) {
+// stable_before: under frozen tags, same-stratum atoms before the delta atom
+// read the stable part (full minus recent), so that every derivation with at
+// least one recent atom is enumerated exactly once, by its first recent atom.
+Plan make_plan(Program& p, int rule_id, int driver, bool delta, int recent_atom = -1, bool stable_before = false) {
   const Rule& r = p.rules[rule_id];
   Plan pl;
   pl.rule = rule_id;
@@ -252,6 +255,8 @@ Plan make_plan(Program& p, int rule_id, int driver, bool delta, int recent_atom 
     IndexSpec ix;
     ix.rel = a.rel;
     ix.recent = st.body_pos == recent_atom;
+    ix.stable = stable_before && st.body_pos < driver && p.rels[a.rel].derived &&
+                p.rels[a.rel].stratum == p.rels[r.head.rel].stratum;
     for (size_t c = 0; c < a.vars.size(); ++c)
       if (has(cur, a.vars[c])) {
         ix.perm.push_back((int)c);
@@ -303,15 +308,13 @@ void plan(Program& p, bool frozen, bool diff) {
     std::vector<int> same;
     for (int j = 0; j < (int)r.body.size(); ++j)
       if (p.rels[r.body[j].rel].derived && p.rels[r.body[j].rel].stratum == s) same.push_back(j);
-    if (frozen && same.size() > 1)
-      throw Failure{3, "add-mult rules may contain at most one atom of their own stratum"};
     if (same.empty()) {
       p.plans.push_back(make_plan(p, (int)ri, 0, false));
       p.strata[s].base_plans.push_back((int)p.plans.size() - 1);
     } else {
       p.strata[s].recursive = true;
       for (int j : same) {
-        p.plans.push_back(make_plan(p, (int)ri, j, true));
+        p.plans.push_back(make_plan(p, (int)ri, j, true, -1, frozen && same.size() > 1));
         const int id = (int)p.plans.size() - 1;
         p.strata[s].delta_plans.push_back(id);
         if (r.body.size() == 2 && same.size() == 1) {

@@ -43,13 +43,14 @@ struct IndexSpec {
   std::vector<int> perm;
   int w;
   bool recent = false;  // index over the relation's recent tuples (rebuilt every round)
+  bool stable = false;  // index over full minus recent (the relation before the last round)
   bool identity() const {
     for (size_t i = 0; i < perm.size(); ++i)
       if (perm[i] != (int)i) return false;
     return true;
   }
   bool operator==(const IndexSpec& o) const {
-    return rel == o.rel && perm == o.perm && w == o.w && recent == o.recent;
+    return rel == o.rel && perm == o.perm && w == o.w && recent == o.recent && stable == o.stable;
   }
 };
 

@@ -53,10 +53,23 @@ def test_rejected_programs(dl, text, status):
     assert ex.value.status == status
 
 
-def test_frozen_semiring_rejects_two_recursive_atoms(dl):
+def test_frozen_semiring_accepts_nonlinear_recursion(dl):
+    # several atoms of the rule's own stratum: each is planned as the delta
+    # atom once, with the atoms before it on the stable part (Appendix A)
+    # without a device the load gets past parsing and planning and only then
+    # fails on stream creation (DL_ERR_HIP)
+    def loads(text, sr):
+        try:
+            dl.Engine(text, sr, use_torch_stream=False)
+        except dl.DLError as ex:
+            assert ex.status == 8, ex
     prog = ".input e/2\np(x, y) :- e(x, y).\np(x, z) :- p(x, y), p(y, z)."
+    for sr in ("addmult", "diff_addmult"):
+        loads(prog, sr)
+    prog3 = ".input e/2\np(x, y) :- e(x, y).\np(x, w) :- p(x, y), p(y, z), p(z, w)."
+    loads(prog3, "addmult")
     with pytest.raises(dl.DLError) as ex:
-        dl.Engine(prog, "addmult", use_torch_stream=False)
+        dl.Engine(prog3, "diff_addmult", use_torch_stream=False)
     assert ex.value.status == 3
 
 

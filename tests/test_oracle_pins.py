@@ -405,3 +405,69 @@ def test_batched_equals_separate_runs(oracle, synth):
         sel = res["sample"] == s
         assert np.array_equal(res["cols"][sel], one["cols"])
         assert np.array_equal(res["value"][sel], one["value"])
+
+
+# ------------------------------------------------- non-linear frozen add-mult
+NONLINEAR_TC = ".input edge/2\n.output path/2\npath(x, y) :- edge(x, y).\npath(x, z) :- path(x, y), path(y, z).\n"
+
+
+def test_nonlinear_chain_addmult_counts(oracle):
+    """Chain 0->1->...->n-1 under path(x,z) :- path(x,y), path(y,z).
+
+    Jacobi rounds double the known path length: a path of length L appears in
+    round d(L) = 1 for L = 1, else ceil(log2 L) + 1.  Frozen add-mult sums the
+    derivations of the discovery round, i.e. the split points y whose two
+    halves were both known one round earlier, so tag = c(L) * prod(p) with
+    c(1) = 1 and c(L) = sum over admissible splits of c(a) c(L - a) -- a count
+    of balanced split trees computed here without any relation machinery."""
+    n = 14
+    rng = np.random.default_rng(5)
+    p = rng.uniform(0.05, 0.3, n - 1).astype(np.float32)
+    d = {1: 1}
+    for L in range(2, n):
+        d[L] = math.ceil(math.log2(L)) + 1
+    c = {1: 1}
+    for L in range(2, n):
+        c[L] = sum(c[a] * c[L - a] for a in range(1, L) if d[a] < d[L] and d[L - a] < d[L])
+    src = np.arange(n - 1, dtype=np.uint32)
+    o = run(oracle, NONLINEAR_TC, "addmult", {"edge": ([src, src + 1], p)})
+    r = o.read("path")
+    got = {(int(a), int(b)): (v, f) for (a, b), v, f in zip(r["cols"], r["value"], r["round"])}
+    assert len(got) == n * (n - 1) // 2
+    for x in range(n):
+        for z in range(x + 1, n):
+            L = z - x
+            want = min(1.0, c[L] * math.prod(float(q) for q in p[x:z]))
+            v, f = got[(x, z)]
+            assert f == d[L]
+            assert v == pytest.approx(want, rel=1e-12)
+    assert o.rounds() == d[n - 1] + 1
+
+
+@pytest.mark.parametrize("program", ["nonlinear", "mutual"])
+def test_diff_addmult_gradient_nonlinear_vs_finite_differences(oracle, synth, program):
+    text = NONLINEAR_TC if program == "nonlinear" else (
+        ".input edge/2\na(x, y) :- edge(x, y).\nb(x, z) :- a(x, y), edge(y, z).\n"
+        "a(x, z) :- b(x, y), a(y, z).\n")
+    out = "path" if program == "nonlinear" else "a"
+    rng = np.random.default_rng(4)
+    src, dst, _ = synth.er_graph(5, 16, 34, weights=True)
+    p = rng.uniform(0.05, 0.25, src.size).astype(np.float32)
+
+    def fwd(q):
+        return run(oracle, text, "diff_addmult", {"edge": ([src, dst], q)})
+
+    r = fwd(p)
+    res = r.read(out)
+    assert (res["value"] < 1).all()
+    g_out = rng.standard_normal(res["cols"].shape[0])
+    r.backward(out, g_out)
+    g = r.grad("edge", src.size)
+    for e in range(src.size):
+        h = 1e-3
+        qp, qm = p.copy(), p.copy()
+        qp[e] += np.float32(h)
+        qm[e] -= np.float32(h)
+        vp, vm = fwd(qp).read(out)["value"], fwd(qm).read(out)["value"]
+        fd = float(g_out @ (vp - vm)) / (float(qp[e]) - float(qm[e]))
+        assert g[e] == pytest.approx(fd, rel=1e-3, abs=1e-8), e
