@@ -80,6 +80,14 @@ typedef struct {
                          1 = always sort-based (radix sort, unique, difference, merge),
                          2 = dense-domain wherever possible */
   int no_graphs;      /* 1: never replay round bodies as captured HIP graphs (0: replay where eligible) */
+  int lineage;        /* DIFF_ADDMULT derivation lineage for dl_backward:
+                         0 = automatic (recorded during the run; dropped and recomputed round by
+                             round in dl_backward once it would exceed lineage_budget),
+                         1 = always recorded (12 bytes per discovery derivation),
+                         2 = never recorded: dl_backward re-runs each round's joins on the
+                             relation as it stood then (rebuilt from discovery ids) */
+  size_t lineage_budget;  /* lineage = 0: bytes of recorded lineage allowed before it is dropped
+                             (0: a quarter of the device memory free at creation) */
 } dl_options;
 
 /* Result columns of dl_read_relation.  Any pointer may be NULL (not written).
@@ -111,6 +119,8 @@ typedef struct {
   int orient;             /* delta-plan orientation in force: 0 auto, 1 recent-driven, 2 static-driven */
   int items;              /* join expand tile in force: outputs per thread */
   double tuned_ms;        /* median run time of the configuration dl_autotune chose */
+  int lineage_mode;       /* DIFF_ADDMULT after the last run: 1 lineage recorded, 2 recomputed in
+                             dl_backward (0 for the other semirings) */
 } dl_stats;
 
 /* Kernel families timed by dl_profile (bit i of the mask = family i). */
@@ -193,7 +203,11 @@ dl_status dl_backward_rows(dl_engine* e, const char* relation, size_t n, const i
 
 /* Reverse mode for DIFF_ADDMULT and DIFF_TOPK: grad_out[i] is d(loss)/d(tag)
  * of row i of out_relation in canonical order.  Gradients with respect to the
- * input facts' tags are accumulated (+=) into the engine until dl_zero_grad. */
+ * input facts' tags are accumulated (+=) into the engine until dl_zero_grad.
+ * DIFF_ADDMULT sweeps the discovery derivations round by round in reverse
+ * (a tuple's tag is the clamped sum over the derivations of the round that
+ * found it); without recorded lineage (dl_options.lineage) each round's
+ * derivations are recomputed first, which costs about one forward join pass. */
 dl_status dl_backward(dl_engine* e, const char* out_relation, const float* grad_out, int on_device);
 
 /* Accumulated input gradients of an input relation, in dl_add_facts order. */

@@ -58,6 +58,7 @@ struct RelState {
   bool own_index = false;  // a plan of its own stratum joins against it
   DevBuf present, touched, dtag, did, log_keys, log_l, log_r, seg_lcount;
   size_t nseg = 0;         // lineage wave segments emitted this round
+  Table view_full, view_recent, view_stable;  // a past round's state (lineage recomputation)
   DevBuf fact_entry;  // input facts -> entry id
   DevBuf grad;        // accumulated input gradients (per fact)
   std::vector<uint32_t> fact_slot;  // top-k: sample*64 + local id per fact (host)
@@ -113,11 +114,17 @@ struct Engine {
   std::vector<uint32_t> topk_next;
   DevBuf qtab, grad_fact;
 
-  // lineage log (diff add-mult) and per-id tags
+  // lineage log (diff add-mult) and per-id tags.  Ids are handed out in
+  // discovery order, so round_ids[s][i] (the first id of round i + 1 of
+  // stratum s; last entry = end) also describes the relations as they stood
+  // at any round: the reverse pass rebuilds them when lineage is not recorded.
   DevBuf lin_owner, lin_l, lin_r, tag_by_id, adj;
   size_t lin_n = 0;
   std::vector<LineageSeg> lin_segs;
   uint32_t next_id = 0;
+  bool record = false;        // discovery derivations are being recorded
+  size_t lin_budget = 0;      // bytes of recorded lineage allowed
+  std::vector<std::vector<uint32_t>> round_ids;
 
   // round scratch
   DevBuf counts, offs, alt_keys, alt_vals, vals, flags, pos, ukeys, utags,

@@ -52,7 +52,8 @@ Engine::~Engine() {
   for (auto& r : rel) {
     for (auto& c : r.raw_cols) fr(c);
     fr(r.raw_sample), fr(r.raw_tags), fr(r.raw_local);
-    for (Table* t : {&r.full, &r.full_alt, &r.recent}) fr(t->keys), fr(t->tags), fr(t->ids);
+    for (Table* t : {&r.full, &r.full_alt, &r.recent, &r.view_full, &r.view_recent, &r.view_stable})
+      fr(t->keys), fr(t->tags), fr(t->ids);
     fr(r.fact_entry), fr(r.grad), fr(r.fact_slot_d);
     fr(r.cand_keys), fr(r.cand_tags), fr(r.cand_l), fr(r.cand_r);
     for (DevBuf* b : {&r.present, &r.touched, &r.dtag, &r.did, &r.log_keys, &r.log_l, &r.log_r, &r.seg_lcount})
@@ -154,6 +155,16 @@ void Engine::init(const char* program_text, const dl_options* o) {
   }
   DL_HIP(hipHostMalloc((void**)&host, 64 * sizeof(uint64_t), hipHostMallocDefault));
   grow(dtotal, 64 * sizeof(uint64_t));
+  if (o->lineage < 0 || o->lineage > 2) throw Error{DL_ERR_ARG, "lineage must be 0, 1 or 2"};
+  if (o->lineage == 0 && o->lineage_budget) {
+    lin_budget = o->lineage_budget;
+  } else if (o->lineage == 0) {
+    size_t free_b = 0, total_b = 0;
+    DL_HIP(hipMemGetInfo(&free_b, &total_b));
+    lin_budget = free_b / 4;
+  } else {
+    lin_budget = o->lineage == 1 ? SIZE_MAX : 0;
+  }
 }
 
 void Engine::clear_facts() {

@@ -52,6 +52,18 @@ void claim(DevBuf& owner, DevBuf& alt, const void* result) {
   if (result == alt.p) std::swap(owner, alt);
 }
 
+// Whether a round's L discovery derivations can be added to the recorded
+// lineage.  Past the budget the whole record is dropped (memory returned) and
+// the reverse pass recomputes every round's derivations instead.
+bool keep_lineage(Engine& e, size_t L) {
+  if ((e.lin_n + L) * 12 <= e.lin_budget) return true;
+  e.record = false;
+  e.lin_n = 0;
+  e.lin_segs.clear();
+  e.release(e.lin_owner), e.release(e.lin_l), e.release(e.lin_r);
+  return false;
+}
+
 DenseArgs dense_args(Engine& e, RelState& R) {
   DenseArgs d{};
   d.present = R.present.as<uint32_t>();
@@ -216,7 +228,7 @@ void run_plan(Engine& e, const Plan& pl) {
     const size_t used = H.ncand;
     e.grow(H.cand_keys, (used + add) * sizeof(K), true, used * sizeof(K));
     if (e.tag_bytes) e.grow(H.cand_tags, (used + add) * e.tag_bytes, true, used * e.tag_bytes);
-    if (e.lineage) {
+    if (e.record) {
       e.grow(H.cand_l, (used + add) * 4, true, used * 4);
       e.grow(H.cand_r, (used + add) * 4, true, used * 4);
     }
@@ -224,17 +236,17 @@ void run_plan(Engine& e, const Plan& pl) {
   auto out_ptrs = [&](void** ok, void** ot, uint32_t** ol, uint32_t** orr) {
     *ok = H.cand_keys.as<K>() + H.ncand;
     *ot = e.tag_bytes ? (void*)(H.cand_tags.as<uint8_t>() + H.ncand * e.tag_bytes) : nullptr;
-    *ol = e.lineage ? H.cand_l.as<uint32_t>() + H.ncand : nullptr;
-    *orr = e.lineage ? H.cand_r.as<uint32_t>() + H.ncand : nullptr;
+    *ol = e.record ? H.cand_l.as<uint32_t>() + H.ncand : nullptr;
+    *orr = e.record ? H.cand_r.as<uint32_t>() + H.ncand : nullptr;
   };
 
   // Room for an emission over `add` slots: one wave segment per 256 slots;
   // returns the emission's arguments (segments start after the round's
   // earlier emissions into the same relation).
   auto dense_room = [&](size_t add, int items) {
-    const size_t used = H.nseg, segs = e.lineage ? dense_segments(add, items) : 0;
+    const size_t used = H.nseg, segs = e.record ? dense_segments(add, items) : 0;
     const size_t slots = (used + segs) * DENSE_SEG, uslots = used * DENSE_SEG;
-    if (e.lineage) {
+    if (e.record) {
       e.grow(H.log_keys, slots * sizeof(K), true, uslots * sizeof(K));
       e.grow(H.log_l, slots * 4, true, uslots * 4);
       e.grow(H.log_r, slots * 4, true, uslots * 4);
@@ -256,7 +268,7 @@ void run_plan(Engine& e, const Plan& pl) {
     for (int c = 0; c < har; ++c) a.osrc[c] = pl.project[c];
     if (H.dense) {
       const DenseArgs d = dense_room(cur.n, 4);
-      project_dense<K>(a, e.tag_kind, d, e.lineage, e.stream);
+      project_dense<K>(a, e.tag_kind, d, e.record, e.stream);
       return;
     }
     head_room(cur.n);
@@ -298,7 +310,7 @@ void run_plan(Engine& e, const Plan& pl) {
     e.grow(e.offs, (cur.n + 1) * 4);
     join_count<K>(a, e.counts.as<uint32_t>(), e.stream);
     scan(e, e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), cur.n, S_SCAN, true);
-    if (si + 1 == pl.steps.size() && H.dense && !e.lineage) {
+    if (si + 1 == pl.steps.size() && H.dense && !e.record) {
       // no host readback: the expand reads the total on the device; the
       // candidate count and any 32-bit overflow are collected at round end
       const IndexState& ixs = e.idx[step.index];
@@ -316,7 +328,7 @@ void run_plan(Engine& e, const Plan& pl) {
     const bool last = si + 1 == pl.steps.size();
     if (last && H.dense) {
       const DenseArgs d = dense_room(total, a.items);
-      join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), total, nullptr, total, d, e.lineage, e.stream);
+      join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), total, nullptr, total, d, e.record, e.stream);
       return;
     }
     void *ok, *ot;
@@ -356,13 +368,13 @@ size_t absorb_dense(Engine& e, int r) {
   DenseArgs d = dense_args(e, R);
   dense_touched_counts(d, R.dense_w, e.flags.as<uint32_t>(), st);
   scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, S_UNIQUE, true);
-  if (e.lineage && nseg) {
+  if (e.record && nseg) {
     e.grow(e.lpos, (nseg + 1) * 4);
     scan(e, R.seg_lcount.as<uint32_t>(), e.lpos.as<uint32_t>(), nseg, S_LIN, true);
   }
   e.read_totals();
   if (e.host[S_OVF]) throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
-  const size_t U = e.host[S_UNIQUE], L = e.lineage && nseg ? e.host[S_LIN] : 0;
+  const size_t U = e.host[S_UNIQUE], L = e.record && nseg ? e.host[S_LIN] : 0;
   if (U == 0) {
     R.recent.n = 0;
     return 0;
@@ -382,6 +394,9 @@ size_t absorb_dense(Engine& e, int r) {
   if (e.lineage) {
     e.grow(R.recent.ids, U * 4 + 4);
     iota_u32(R.recent.ids.as<uint32_t>(), U, base, st);
+    e.next_id = base + (uint32_t)U;
+  }
+  if (e.record && keep_lineage(e, L)) {
     const size_t used = e.lin_n;
     e.grow(e.lin_owner, (used + L) * 4 + 4, true, used * 4);
     e.grow(e.lin_l, (used + L) * 4 + 4, true, used * 4);
@@ -397,7 +412,6 @@ size_t absorb_dense(Engine& e, int r) {
     e.lin_segs.push_back({used, L});
     e.lin_n = used + L;
     e.stats.lineage += L;
-    e.next_id = base + (uint32_t)U;
   }
   R.recent.n = U;
   ++R.version;
@@ -421,7 +435,7 @@ size_t absorb(Engine& e, int r) {
   e.stats.candidates += C;
   const int ar = e.prog.rels[r].arity;
   const size_t kb = sizeof(K), tb = e.tag_bytes;
-  const bool use_perm = e.tag_kind == TAG_TOPK || e.lineage;
+  const bool use_perm = e.tag_kind == TAG_TOPK || e.record;
   hipStream_t st = e.stream;
 
   // 1. sort the candidates by packed key (stable: derivation order kept)
@@ -506,22 +520,27 @@ size_t absorb(Engine& e, int r) {
     nid = R.recent.ids.as<uint32_t>();
     e.grow(e.tag_by_id, ((size_t)base + N) * 4, true, (size_t)base * 4);
     DL_HIP(hipMemcpyAsync(e.tag_by_id.as<float>() + base, nt, N * 4, hipMemcpyDeviceToDevice, st));
+    e.next_id = base + (uint32_t)N;
+  }
+  if (e.record) {
     e.grow(e.lf, C * 4);
     e.grow(e.lpos, (C + 1) * 4);
     lineage_flags(e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), e.status.as<uint32_t>(), C, e.lf.as<uint32_t>(), st);
     scan(e, e.lf.as<uint32_t>(), e.lpos.as<uint32_t>(), C, S_LIN, true);
     const size_t L = e.read_total(S_LIN);
-    const size_t used = e.lin_n;
-    e.grow(e.lin_owner, (used + L) * 4, true, used * 4);
-    e.grow(e.lin_l, (used + L) * 4, true, used * 4);
-    e.grow(e.lin_r, (used + L) * 4, true, used * 4);
-    lineage_emit(e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), e.lf.as<uint32_t>(), e.lpos.as<uint32_t>(),
-                 e.newpos.as<uint32_t>(), vp, R.cand_l.as<uint32_t>(), R.cand_r.as<uint32_t>(), C, base,
-                 e.lin_owner.as<uint32_t>() + used, e.lin_l.as<uint32_t>() + used, e.lin_r.as<uint32_t>() + used, st);
-    e.lin_segs.push_back({used, L});
-    e.lin_n = used + L;
-    e.stats.lineage += L;
-    e.next_id = base + (uint32_t)N;
+    if (keep_lineage(e, L)) {
+      const size_t used = e.lin_n;
+      e.grow(e.lin_owner, (used + L) * 4, true, used * 4);
+      e.grow(e.lin_l, (used + L) * 4, true, used * 4);
+      e.grow(e.lin_r, (used + L) * 4, true, used * 4);
+      lineage_emit(e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), e.lf.as<uint32_t>(), e.lpos.as<uint32_t>(),
+                   e.newpos.as<uint32_t>(), vp, R.cand_l.as<uint32_t>(), R.cand_r.as<uint32_t>(), C,
+                   e.next_id - (uint32_t)N, e.lin_owner.as<uint32_t>() + used, e.lin_l.as<uint32_t>() + used,
+                   e.lin_r.as<uint32_t>() + used, st);
+      e.lin_segs.push_back({used, L});
+      e.lin_n = used + L;
+      e.stats.lineage += L;
+    }
   }
 
   // 6. full' = merge(full, new)
@@ -800,10 +819,13 @@ void run_fixpoint(Engine& e) {
   e.next_id = edb;
   e.lin_n = 0;
   e.lin_segs.clear();
+  e.record = e.lineage && e.lin_budget > 0;
+  e.round_ids.clear();
   DL_HIP(hipMemsetAsync(e.dtotal.p, 0, 32 * sizeof(uint64_t), e.stream));
   setup_dense(e);
   for (const Stratum& st : e.prog.strata) {
     int rounds = 1;
+    std::vector<uint32_t> ids{e.next_id};
     for (int p : st.base_plans) run_plan<K>(e, e.prog.plans[p]);
     size_t changed = 0;
     for (int r : st.rels) changed += absorb<K>(e, r);
@@ -825,8 +847,11 @@ void run_fixpoint(Engine& e) {
         run_plan<K>(e, twin ? e.prog.plans[pl.alt] : pl);
       }
       changed = 0;
+      ids.push_back(e.next_id);
       for (int r : st.rels) changed += absorb<K>(e, r);
     }
+    ids.push_back(e.next_id);
+    if (e.lineage) e.round_ids.push_back(std::move(ids));
     if (changed) ++rounds;  // non-recursive stratum: its second round derives nothing
     for (int r : st.rels) {
       if (e.rel[r].dense) materialize_full<K>(e, e.rel[r]);
@@ -840,6 +865,7 @@ void run_fixpoint(Engine& e) {
     if (e.prog.rels[r].derived) e.stats.derived += e.rel[r].full.n;
   e.read_totals();
   e.stats.candidates += e.host[S_CAND];
+  e.stats.lineage_mode = !e.lineage ? 0 : e.record ? 1 : 2;
 }
 
 template <typename K>
@@ -910,6 +936,99 @@ void lookup_t(Engine& e, int r, size_t n, const uint32_t* const* cols, const uin
                  e.layout(e.prog.rels[r].arity), e.qtab.as<float>(), rows, tags, e.stream);
 }
 
+// ------------------------------------------------- lineage recomputation
+// Rows of `src` whose id lies in [lo, hi), in key order, into `dst`.
+template <typename K>
+void select_ids(Engine& e, const Table& src, uint32_t lo, uint32_t hi, Table& dst) {
+  const size_t n = src.n;
+  dst.n = 0;
+  if (n == 0 || lo >= hi) return;
+  hipStream_t st = e.stream;
+  e.grow(e.flags, n * 4);
+  e.grow(e.pos, (n + 1) * 4);
+  range_flags(src.ids.as<uint32_t>(), n, lo, hi, e.flags.as<uint32_t>(), st);
+  scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), n, S_SCAN, true);
+  const size_t m = e.read_total(S_SCAN);
+  e.grow(dst.keys, m * sizeof(K) + 8);
+  e.grow(dst.tags, m * 4 + 8);
+  e.grow(dst.ids, m * 4 + 8);
+  compact(src.keys.p, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), n, sizeof(K), dst.keys.p, st);
+  compact(src.tags.p, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), n, 4, dst.tags.p, st);
+  compact(src.ids.p, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), n, 4, dst.ids.p, st);
+  dst.n = m;
+}
+
+// Put the relations of stratum `si` into (or back from) the state they had
+// when the joins of round `round` (1-based) ran: full = ids below the round's
+// first id, recent = the previous round's ids, stable = older ids.
+template <typename K>
+void swap_views(Engine& e, const Stratum& st, int si, int round, bool enter) {
+  const std::vector<uint32_t>& ids = e.round_ids[si];
+  for (int r : st.rels) {
+    RelState& R = e.rel[r];
+    if (enter) {
+      const uint32_t b = ids[round - 1], a = round >= 2 ? ids[round - 2] : b;
+      select_ids<K>(e, R.full, 0, b, R.view_full);
+      select_ids<K>(e, R.full, a, b, R.view_recent);
+      select_ids<K>(e, R.full, 0, a, R.view_stable);
+    }
+    std::swap(R.full, R.view_full);
+    std::swap(R.recent, R.view_recent);
+    std::swap(R.full_alt, R.view_stable);
+    ++R.version;
+    ++R.rversion;
+  }
+}
+
+// Reverse sweep without recorded lineage: for each round, newest first,
+// re-run its joins on the relations as they stood, keep the derivations
+// whose head was discovered in that round, and push the adjoints through
+// them.
+template <typename K>
+void recompute_backward(Engine& e) {
+  hipStream_t st = e.stream;
+  const bool saved_record = e.record;
+  for (size_t si = e.prog.strata.size(); si-- > 0;) {
+    const Stratum& S = e.prog.strata[si];
+    const std::vector<uint32_t>& ids = e.round_ids[si];
+    const int rounds = (int)ids.size() - 1;
+    std::vector<bool> dense(e.rel.size());
+    for (int r : S.rels) dense[r] = e.rel[r].dense;
+    for (int round = rounds; round >= 1; --round) {
+      const uint32_t lo = ids[round - 1], hi = ids[round];
+      if (lo == hi) continue;
+      swap_views<K>(e, S, (int)si, round, true);
+      e.record = true;
+      for (int r : S.rels) {
+        e.rel[r].dense = false;
+        e.rel[r].ncand = 0;
+      }
+      try {
+        for (int p : round == 1 ? S.base_plans : S.delta_plans) run_plan<K>(e, e.prog.plans[p]);
+      } catch (...) {
+        swap_views<K>(e, S, (int)si, round, false);
+        for (int r : S.rels) e.rel[r].dense = dense[r], e.rel[r].ncand = 0;
+        e.record = saved_record;
+        throw;
+      }
+      swap_views<K>(e, S, (int)si, round, false);
+      e.record = saved_record;
+      for (int r : S.rels) {
+        RelState& H = e.rel[r];
+        H.dense = dense[r];
+        const size_t c = H.ncand;
+        H.ncand = 0;
+        if (!c) continue;
+        e.grow(e.lin_owner, c * 4 + 4);
+        match_owner<K>(H.cand_keys.as<K>(), c, H.full.keys.as<K>(), H.full.ids.as<uint32_t>(), H.full.n, lo, hi,
+                       e.lin_owner.as<uint32_t>(), st);
+        lineage_backward(e.lin_owner.as<uint32_t>(), H.cand_l.as<uint32_t>(), H.cand_r.as<uint32_t>(), c,
+                         e.tag_by_id.as<float>(), e.adj.as<float>(), st);
+      }
+    }
+  }
+}
+
 template <typename K>
 void backward_t(Engine& e, int r, const float* gout, const int64_t* rows, size_t nrows) {
   RelState& R = e.rel[r];
@@ -937,10 +1056,14 @@ void backward_t(Engine& e, int r, const float* gout, const int64_t* rows, size_t
   DL_HIP(hipMemsetAsync(e.adj.p, 0, ids * 4 + 4, st));
   if (rows) scatter_add_rows(R.full.ids.as<uint32_t>(), rows, gout, nrows, e.adj.as<float>(), st);
   else scatter_add(R.full.ids.as<uint32_t>(), gout, n, e.adj.as<float>(), st);
-  for (size_t i = e.lin_segs.size(); i-- > 0;) {
-    const LineageSeg& s = e.lin_segs[i];
-    lineage_backward(e.lin_owner.as<uint32_t>() + s.off, e.lin_l.as<uint32_t>() + s.off,
-                     e.lin_r.as<uint32_t>() + s.off, s.n, e.tag_by_id.as<float>(), e.adj.as<float>(), st);
+  if (e.record) {
+    for (size_t i = e.lin_segs.size(); i-- > 0;) {
+      const LineageSeg& s = e.lin_segs[i];
+      lineage_backward(e.lin_owner.as<uint32_t>() + s.off, e.lin_l.as<uint32_t>() + s.off,
+                       e.lin_r.as<uint32_t>() + s.off, s.n, e.tag_by_id.as<float>(), e.adj.as<float>(), st);
+    }
+  } else {
+    recompute_backward<K>(e);
   }
   for (size_t q = 0; q < e.rel.size(); ++q) {
     if (!e.prog.rels[q].input || !e.rel[q].nraw) continue;

@@ -355,4 +355,16 @@ void status_flags(const uint32_t* status, size_t n, uint32_t mask, uint32_t* fla
   if (n) k_status_flags<<<grid_for(n), BLOCK, 0, st>>>(status, n, mask, flags);
 }
 
+__global__ void k_range_flags(const uint32_t* __restrict__ ids, size_t n, uint32_t lo, uint32_t hi,
+                              uint32_t* __restrict__ flags) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t v = ids[i];
+    flags[i] = (v >= lo && v < hi) ? 1u : 0u;
+  }
+}
+
+void range_flags(const uint32_t* ids, size_t n, uint32_t lo, uint32_t hi, uint32_t* flags, hipStream_t st) {
+  if (n) k_range_flags<<<grid_for(n), BLOCK, 0, st>>>(ids, n, lo, hi, flags);
+}
+
 }  // namespace dlfix

@@ -516,6 +516,7 @@ __global__ void k_lineage_backward(const uint32_t* __restrict__ owner, const uin
                                    float* adj) {
   GRID_STRIDE(i, n) {
     const uint32_t o = owner[i];
+    if (o == ~0u) continue;          // recomputed derivation of an older tuple
     if (!(tag[o] < 1.0f)) continue;  // clamp: d min(1, s)/ds = 0 once s >= 1
     const float g = adj[o];
     if (g == 0.0f) continue;
@@ -697,6 +698,40 @@ void lookup_rows(const K* keys, size_t n, const uint32_t* const* qcols, const ui
   for (int c = 0; c < lay.ncols; ++c) qc.c[c] = qcols[c];
   k_lookup<K><<<grid_for(nq), BLOCK, 0, st>>>(keys, n, qc, nq, tk, tags, lay, qtab, rows, qtag);
 }
+
+// Owner of each recomputed derivation: the id of its head tuple if that id
+// lies in [lo, hi) (the tuple was discovered in the round being replayed),
+// else ~0 (a derivation of an older tuple, ignored under frozen tags).
+template <typename K>
+__global__ void k_match_owner(const K* __restrict__ ckeys, size_t n, const K* __restrict__ fkeys,
+                              const uint32_t* __restrict__ fids, size_t F, uint32_t lo, uint32_t hi,
+                              uint32_t* __restrict__ owner) {
+  GRID_STRIDE(i, n) {
+    const K q = ckeys[i];
+    size_t a = 0, b = F;
+    while (a < b) {
+      size_t mid = (a + b) >> 1;
+      if (fkeys[mid] < q) a = mid + 1;
+      else b = mid;
+    }
+    uint32_t o = ~0u;
+    if (a < F && fkeys[a] == q) {
+      const uint32_t id = fids[a];
+      if (id >= lo && id < hi) o = id;
+    }
+    owner[i] = o;
+  }
+}
+
+template <typename K>
+void match_owner(const K* ckeys, size_t n, const K* fkeys, const uint32_t* fids, size_t F, uint32_t lo, uint32_t hi,
+                 uint32_t* owner, hipStream_t st) {
+  if (n) k_match_owner<K><<<grid_for(n), BLOCK, 0, st>>>(ckeys, n, fkeys, fids, F, lo, hi, owner);
+}
+template void match_owner<uint32_t>(const uint32_t*, size_t, const uint32_t*, const uint32_t*, size_t, uint32_t,
+                                    uint32_t, uint32_t*, hipStream_t);
+template void match_owner<uint64_t>(const uint64_t*, size_t, const uint64_t*, const uint32_t*, size_t, uint32_t,
+                                    uint32_t, uint32_t*, hipStream_t);
 
 __global__ void k_scatter_add_rows(const uint32_t* __restrict__ ids, const int64_t* __restrict__ rows,
                                    const float* __restrict__ g, size_t n, float* adj) {

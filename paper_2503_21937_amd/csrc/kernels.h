@@ -186,6 +186,13 @@ void compact(const void* in, const uint32_t* flags, const uint32_t* pos, size_t 
              hipStream_t st);
 // flags[i] = (status[i] & mask) != 0
 void status_flags(const uint32_t* status, size_t n, uint32_t mask, uint32_t* flags, hipStream_t st);
+// flags[i] = 1 iff lo <= ids[i] < hi.
+void range_flags(const uint32_t* ids, size_t n, uint32_t lo, uint32_t hi, uint32_t* flags, hipStream_t st);
+// owner[i] = id of the row of fkeys equal to ckeys[i] when that id is in
+// [lo, hi), else ~0 (fkeys sorted, fids aligned with it).
+template <typename K>
+void match_owner(const K* ckeys, size_t n, const K* fkeys, const uint32_t* fids, size_t F, uint32_t lo, uint32_t hi,
+                 uint32_t* owner, hipStream_t st);
 
 // Merge two sorted, disjoint relations (keys + payload) into out.
 size_t merge_scratch_words(size_t na, size_t nb);

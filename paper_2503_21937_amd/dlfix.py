@@ -35,7 +35,8 @@ class DLError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("semiring", C.c_int), ("k", C.c_int), ("batched", C.c_int),
-                ("stream", C.c_void_p), ("dedup", C.c_int), ("no_graphs", C.c_int)]
+                ("stream", C.c_void_p), ("dedup", C.c_int), ("no_graphs", C.c_int),
+                ("lineage", C.c_int), ("lineage_budget", C.c_size_t)]
 
 
 class RelationOut(C.Structure):
@@ -52,7 +53,8 @@ class Stats(C.Structure):
                 ("candidates", C.c_uint64), ("unique", C.c_uint64), ("derived", C.c_uint64),
                 ("lineage", C.c_uint64), ("run_ms", C.c_double), ("device_bytes", C.c_uint64),
                 ("key_bits", C.c_uint32), ("id_bits", C.c_uint32), ("sample_bits", C.c_uint32),
-                ("dedup", C.c_int), ("orient", C.c_int), ("items", C.c_int), ("tuned_ms", C.c_double)]
+                ("dedup", C.c_int), ("orient", C.c_int), ("items", C.c_int), ("tuned_ms", C.c_double),
+                ("lineage_mode", C.c_int)]
 
 
 _lib = None
@@ -128,22 +130,28 @@ class Engine:
     """One fixpoint engine: a program under one semiring (dlfix.h)."""
 
     DEDUP = {"auto": 0, "sort": 1, "dense": 2}
+    LINEAGE = {"auto": 0, "store": 1, "recompute": 2}
 
     def __init__(self, program: str, semiring: str = "bool", k: int = 3,
                  batched: bool = False, stream: int | None = None, use_torch_stream: bool = True,
-                 dedup: str = "auto", graphs: bool = True):
+                 dedup: str = "auto", graphs: bool = True, lineage: str = "auto",
+                 lineage_budget: int = 0):
         self.arity = {}
         for line in program.splitlines():
             line = line.strip()
             if line.startswith(".input") or line.startswith(".output"):
                 name, ar = line.split()[1].split("/")
                 self.arity[name] = int(ar)
+            elif ":-" in line:  # a rule head names a derived relation
+                name, args = line.split(":-")[0].split("(", 1)
+                self.arity.setdefault(name.strip(), args.count(",") + 1)
         self.semiring = semiring
         self.k = k
         self.batched = batched
         if stream is None and use_torch_stream:
             stream = _current_stream()
-        opts = Options(SEMIRINGS[semiring], k, int(batched), stream, self.DEDUP[dedup], int(not graphs))
+        opts = Options(SEMIRINGS[semiring], k, int(batched), stream, self.DEDUP[dedup], int(not graphs),
+                       self.LINEAGE[lineage], lineage_budget)
         h = C.c_void_p()
         rc = lib().dl_load_program(program.encode(), C.byref(opts), C.byref(h))
         if rc:

@@ -8,9 +8,9 @@ TAG_RTOL = 1e-5  # float32 tags vs the binary64 oracle
 DEDUP = ["sort", "dense"]  # both deduplication pipelines are parity-tested
 
 
-def engine(program, semiring, facts, k=3, batched=False, dedup="auto"):
+def engine(program, semiring, facts, k=3, batched=False, dedup="auto", **kw):
     from paper_2503_21937_amd import dlfix
-    e = dlfix.Engine(program, semiring, k=k, batched=batched, dedup=dedup)
+    e = dlfix.Engine(program, semiring, k=k, batched=batched, dedup=dedup, **kw)
     for rel, (cols, tags, sample) in facts.items():
         e.add_facts(rel, cols, tags, sample)
     return e.run()
