@@ -52,6 +52,11 @@ struct RelState {
   size_t ncand = 0;
   uint64_t version = 0;  // bumped whenever `full` changes (keys or tags)
   uint64_t rversion = 0; // bumped whenever `recent` changes
+  // stable part (full minus recent, read under frozen tags): full_alt after
+  // a round that added tuples (the merge or materialisation leaves the
+  // previous state there), full itself after a round that added none
+  bool stable_full = false;
+  uint64_t sversion = 0;  // bumped whenever the stable part may change
   // dense-domain deduplication (derived relations whose keys are < 2^dense_w)
   bool dense = false;
   int dense_w = 0;

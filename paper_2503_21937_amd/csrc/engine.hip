@@ -29,6 +29,7 @@ struct ProfScope {
     g_prof = nullptr;
     on = false;
     e.sync();
+    p.resolve();
     for (auto& r : p.recs) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;

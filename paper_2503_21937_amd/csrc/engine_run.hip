@@ -115,13 +115,11 @@ void setup_dense(Engine& e) {
 template <typename K>
 void materialize_full(Engine& e, RelState& R) {
   std::swap(R.full, R.full_alt);  // the previous materialisation stays as the stable part
-  const size_t words = bitmap_words(R.dense_w);
-  e.grow(e.flags, words * 4);
-  e.grow(e.pos, (words + 1) * 4);
-  bitmap_popcounts(R.present.as<uint32_t>(), words, e.flags.as<uint32_t>(), e.stream);
-  ensure_scratch(e, scan_scratch_words(words));
-  scan_u32(e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), words, total_slot(e, S_SCAN), true,
-           e.scratch.as<uint64_t>(), e.stream);
+  const size_t nb = dense_count_blocks(R.dense_w);
+  e.grow(e.flags, nb * 4);
+  e.grow(e.pos, (nb + 1) * 4);
+  bitmap_block_counts(R.present.as<uint32_t>(), R.dense_w, e.flags.as<uint32_t>(), e.stream);
+  scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, S_SCAN, true);
   const size_t F = e.read_total(S_SCAN);
   e.grow(R.full.keys, F * sizeof(K) + 8);
   float* tags = nullptr;
@@ -139,12 +137,22 @@ void materialize_full(Engine& e, RelState& R) {
   ++R.version;
 }
 
+const Table& index_source(const RelState& R, const IndexSpec& spec) {
+  if (spec.recent) return R.recent;
+  if (spec.stable) return R.stable_full ? R.full : R.full_alt;
+  return R.full;
+}
+
+uint64_t index_version(const RelState& R, const IndexSpec& spec) {
+  return spec.recent ? R.rversion : spec.stable ? R.sversion : R.version;
+}
+
 template <typename K>
 void build_index(Engine& e, int i) {
   const IndexSpec& spec = e.prog.indexes[i];
   IndexState& ix = e.idx[i];
   RelState& R = e.rel[spec.rel];
-  const Table& src = spec.recent ? R.recent : spec.stable ? R.full_alt : R.full;
+  const Table& src = index_source(R, spec);
   const int ar = e.prog.rels[spec.rel].arity;
   const KeyLayout lay = e.layout(ar);
   const size_t n = src.n;
@@ -185,7 +193,7 @@ void build_index(Engine& e, int i) {
   e.grow(ix.off, (((size_t)1 << pbits) + 1) * 4);
   csr_build<K>(ix.t.keys.as<K>(), n, e.key_width(ar), pbits, ix.off.as<uint32_t>(), e.stream);
   ix.built = true;
-  ix.version = spec.recent ? R.rversion : R.version;
+  ix.version = index_version(R, spec);
 }
 
 template <typename K>
@@ -193,8 +201,8 @@ void ensure_index(Engine& e, int i) {
   IndexState& ix = e.idx[i];
   const IndexSpec& spec = e.prog.indexes[i];
   const RelState& R = e.rel[spec.rel];
-  const Table& src = spec.recent ? R.recent : spec.stable ? R.full_alt : R.full;
-  bool stale = !ix.built || ix.version != (spec.recent ? R.rversion : R.version);
+  const Table& src = index_source(R, spec);
+  bool stale = !ix.built || ix.version != index_version(R, spec);
   if (ix.borrowed && ix.t.keys.p != src.keys.p) stale = true;
   if (stale) build_index<K>(e, i);
 }
@@ -366,7 +374,7 @@ size_t absorb_dense(Engine& e, int r) {
   e.grow(e.flags, nb * 4);
   e.grow(e.pos, (nb + 1) * 4);
   DenseArgs d = dense_args(e, R);
-  dense_touched_counts(d, R.dense_w, e.flags.as<uint32_t>(), st);
+  bitmap_block_counts(d.touched, R.dense_w, e.flags.as<uint32_t>(), st);
   scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, S_UNIQUE, true);
   if (e.record && nseg) {
     e.grow(e.lpos, (nseg + 1) * 4);
@@ -420,11 +428,25 @@ size_t absorb_dense(Engine& e, int r) {
   return U;
 }
 
+template <typename K>
+size_t absorb_sorted(Engine& e, int r);
+
+// Fold a relation's round into the store; returns the size of the next
+// recent relation.  Under frozen tags that is the number of new tuples, and
+// none new means the stable part is the whole relation.
+template <typename K>
+size_t absorb(Engine& e, int r) {
+  RelState& R = e.rel[r];
+  const size_t n = R.dense ? absorb_dense<K>(e, r) : absorb_sorted<K>(e, r);
+  R.stable_full = n == 0;
+  ++R.sversion;
+  return n;
+}
+
 // Deduplicate a relation's candidates and fold them into the store.
 // Returns the number of tuples that are new or changed (the next recent).
 template <typename K>
-size_t absorb(Engine& e, int r) {
-  if (e.rel[r].dense) return absorb_dense<K>(e, r);
+size_t absorb_sorted(Engine& e, int r) {
   RelState& R = e.rel[r];
   const size_t C = R.ncand;
   R.ncand = 0;
@@ -637,7 +659,7 @@ void enqueue_graph_round(Engine& e, int r, const std::vector<const Plan*>& plans
   }
   const DenseArgs d = dense_args(e, R);
   const size_t nb = dense_count_blocks(R.dense_w);
-  dense_touched_counts(d, R.dense_w, e.flags.as<uint32_t>(), st);
+  bitmap_block_counts(d.touched, R.dense_w, e.flags.as<uint32_t>(), st);
   scan_u32(e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, total_slot(e, S_UNIQUE), true, e.scratch.as<uint64_t>(),
            st);
   dense_finalize<K>(d, R.dense_w, e.pos.as<uint32_t>(), R.recent.keys.as<K>(),
@@ -813,7 +835,9 @@ void run_fixpoint(Engine& e) {
       R.full.n = 0;
       R.full_alt.n = 0;
       R.recent.n = 0;
+      R.stable_full = false;
       ++R.version;
+      ++R.sversion;
     }
   }
   e.next_id = edb;
@@ -975,8 +999,10 @@ void swap_views(Engine& e, const Stratum& st, int si, int round, bool enter) {
     std::swap(R.full, R.view_full);
     std::swap(R.recent, R.view_recent);
     std::swap(R.full_alt, R.view_stable);
+    R.stable_full = false;  // a view's stable part is explicit
     ++R.version;
     ++R.rversion;
+    ++R.sversion;
   }
 }
 

@@ -45,12 +45,21 @@ struct WaveSeg {
 template <typename K>
 __device__ __forceinline__ void dense_emit(const DenseArgs& d, WaveSeg& ws, size_t seg, bool act, K key, float t,
                                            uint32_t l, uint32_t r, bool lineage) {
+  // The presence, touched and tag words are loaded together up front and
+  // every atomic is issued without waiting for its result.  A derivation
+  // marks its key touched when it beats the tag it read: that value is no
+  // older than the round's start and tags only move one way inside a round,
+  // so the final tag then differs from the round-start tag; conversely the
+  // first derivation to write the final value saw a smaller one.  A stale
+  // touched word only costs a redundant atomicOr.
   bool keep = false, logit = false;
   if (act) {
     const uint64_t kk = (uint64_t)key;
     const size_t w = kk >> 5;
     const uint32_t bit = 1u << (kk & 31);
-    const bool present = (d.present[w] & bit) != 0u;
+    const uint32_t pw = d.present[w];
+    const uint32_t tw = d.touched[w];
+    const bool present = (pw & bit) != 0u;
     switch (d.mode) {
       case DENSE_BOOL:
         keep = !present;
@@ -63,19 +72,25 @@ __device__ __forceinline__ void dense_emit(const DenseArgs& d, WaveSeg& ws, size
         }
         break;
       case DENSE_MAX: {
-        const uint32_t o = to_ordered(t);
-        if (o > d.dtag[kk]) keep = o > atomicMax(d.dtag + kk, o);
+        const uint32_t o = to_ordered(t), cur = d.dtag[kk];
+        if (o > cur) {
+          atomicMax(d.dtag + kk, o);
+          keep = true;
+        }
         keep = keep || !present;
         break;
       }
       default: {  // DENSE_MIN
-        const uint32_t o = to_ordered(t);
-        if (o < d.dtag[kk]) keep = o < atomicMin(d.dtag + kk, o);
+        const uint32_t o = to_ordered(t), cur = d.dtag[kk];
+        if (o < cur) {
+          atomicMin(d.dtag + kk, o);
+          keep = true;
+        }
         keep = keep || !present;
         break;
       }
     }
-    if (keep && !(d.touched[w] & bit)) atomicOr(d.touched + w, bit);
+    if (keep && !(tw & bit)) atomicOr(d.touched + w, bit);
   }
   if (lineage) {
     const uint64_t lm = ballot(logit);
@@ -195,6 +210,7 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   }
 #undef DL_DEXPAND
   DL_PROF_END(1, st, bytes);
+  if (dtotal) DL_PROF_DEFER(1, st, dtotal, per);
 }
 
 constexpr int PX_ITEMS = 4;  // projection: rows per thread (fixed tile)
@@ -236,14 +252,17 @@ void project_dense(const JoinArgs& a, int tk, const DenseArgs& d, bool lineage, 
     k_project_dense<K, TAG_NONE><<<nb, BLOCK, 0, st>>>(a, d, lineage ? 1 : 0);
 }
 
-// Round end: the touched bits are exactly the new and changed tuples.  The
-// bitmap is compacted in key order in two passes over the touched words:
-// per-block popcount sums (dense_touched_counts), their exclusive scan, then
-// dense_finalize, where every thread scans its BM_ITEMS consecutive words
-// inside the block and writes their keys in ascending order.  The touched
-// tuples become present, touched is cleared, frozen sums are clamped.
+// Round end: the touched bits are exactly the new and changed tuples.  A
+// bitmap is compacted in key order in two passes: per-block popcount sums
+// (bitmap_block_counts), their exclusive scan, then an emission pass in which
+// every wave walks BM_ITEMS groups of 64 consecutive words (one word per lane:
+// coalesced) and expands their set bits cooperatively, so that consecutive
+// lanes write consecutive keys whatever the bit density (wave_expand_bits).
+// dense_finalize also makes the touched tuples present, clears touched,
+// clamps frozen sums and, with lineage, hands out ids in key order.
 constexpr int BM_ITEMS = 16;
 constexpr int BM_TILE = BLOCK * BM_ITEMS;
+constexpr int BM_WAVE_WORDS = WAVE * BM_ITEMS;
 
 size_t dense_count_blocks(int w) { return (bitmap_words(w) + BM_TILE - 1) / BM_TILE; }
 
@@ -251,55 +270,100 @@ __global__ void k_acc_total(const uint64_t* __restrict__ src, uint64_t* __restri
 
 void accumulate_total(const uint64_t* src, uint64_t* acc, hipStream_t st) { k_acc_total<<<1, 1, 0, st>>>(src, acc); }
 
-__global__ __launch_bounds__(BLOCK) void k_touched_counts(const uint32_t* __restrict__ bits, size_t words,
-                                                          uint32_t* __restrict__ partial) {
+__global__ __launch_bounds__(BLOCK) void k_block_counts(const uint32_t* __restrict__ bits, size_t words,
+                                                        uint32_t* __restrict__ partial) {
   __shared__ uint32_t tmp[NWAVES];
-  const size_t base = (size_t)blockIdx.x * BM_TILE + (size_t)threadIdx.x * BM_ITEMS;
+  const size_t base = (size_t)blockIdx.x * BM_TILE + threadIdx.x;
   uint32_t c = 0;
 #pragma unroll
-  for (int i = 0; i < BM_ITEMS; ++i)
-    if (base + i < words) c += (uint32_t)__popc(bits[base + i]);
+  for (int i = 0; i < BM_ITEMS; ++i) {
+    const size_t wi = base + (size_t)i * BLOCK;
+    if (wi < words) c += (uint32_t)__popc(bits[wi]);
+  }
   c = wave_sum(c);
   if (lane_id() == 0) tmp[threadIdx.x / WAVE] = c;
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = tmp[0] + tmp[1] + tmp[2] + tmp[3];
 }
 
-void dense_touched_counts(const DenseArgs& d, int w, uint32_t* partial, hipStream_t st) {
+void bitmap_block_counts(const uint32_t* bits, int w, uint32_t* partial, hipStream_t st) {
   const size_t words = bitmap_words(w);
   DL_PROF_BEGIN(6, st);
-  k_touched_counts<<<dense_count_blocks(w), BLOCK, 0, st>>>(d.touched, words, partial);
+  k_block_counts<<<dense_count_blocks(w), BLOCK, 0, st>>>(bits, words, partial);
   DL_PROF_END(6, st, words * 4.0);
+}
+
+// Position of the n-th (from 0) set bit of x, which has more than n.
+__device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t n) {
+  uint32_t pos = 0;
+#pragma unroll
+  for (int sh = 16; sh > 0; sh >>= 1) {
+    const uint32_t low = (uint32_t)__popc(x & ((1u << sh) - 1u));
+    if (n >= low) {
+      n -= low;
+      x >>= sh;
+      pos += sh;
+    }
+  }
+  return pos;
+}
+
+// The set bits of 64 words, word wbase + lane in each lane, become slots
+// base, base + 1, ... in key order: f(slot, key) runs with consecutive
+// lanes on consecutive slots (source lane by a binary search over the wave's
+// inclusive popcount scan, bit by rank select).  Called by the whole wave;
+// returns the number of bits.
+template <typename F>
+__device__ __forceinline__ uint32_t wave_expand_bits(uint32_t x, uint64_t wbase, uint32_t base, F&& f) {
+  const uint32_t cnt = (uint32_t)__popc(x);
+  const uint32_t incl = wave_inclusive_scan(cnt);
+  const uint32_t excl = incl - cnt;
+  const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+  for (uint32_t j0 = 0; j0 < total; j0 += WAVE) {  // uniform across the wave
+    const uint32_t j = j0 + (uint32_t)lane_id();
+    int src = 0;  // lanes whose inclusive count is <= j
+#pragma unroll
+    for (int step = WAVE / 2; step > 0; step >>= 1) {
+      const uint32_t v = __shfl(incl, src + step - 1, WAVE);
+      if (v <= j) src += step;
+    }
+    const uint32_t word = __shfl(x, src, WAVE);
+    const uint32_t before = __shfl(excl, src, WAVE);
+    if (j < total) f(base + j, ((wbase + (uint64_t)src) << 5) | select_bit(word, j - before));
+  }
+  return total;
 }
 
 template <typename K>
 __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t words, const uint32_t* __restrict__ bpos,
                                                           K* __restrict__ keys, float* __restrict__ rtags,
                                                           uint32_t id_base, float* __restrict__ tag_by_id) {
-  __shared__ uint32_t tmp[NWAVES];
-  const size_t base = (size_t)blockIdx.x * BM_TILE + (size_t)threadIdx.x * BM_ITEMS;
-  uint32_t b[BM_ITEMS];
+  __shared__ uint32_t s_tot[NWAVES];
+  const int lane = lane_id(), wv = threadIdx.x / WAVE;
+  const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
-    b[i] = base + i < words ? d.touched[base + i] : 0u;
-    c += (uint32_t)__popc(b[i]);
+    const size_t wi = w0 + (size_t)i * WAVE + lane;
+    if (wi < words) c += (uint32_t)__popc(d.touched[wi]);
   }
-  uint32_t tot;
-  uint32_t o = bpos[blockIdx.x] + block_exclusive_scan(c, tmp, &tot);
-  if (c == 0) return;
-#pragma unroll
+  c = wave_sum(c);
+  if (lane == 0) s_tot[wv] = c;
+  __syncthreads();
+  if (c == 0) return;  // wave-uniform; no barrier follows
+  uint32_t o = bpos[blockIdx.x];
+  for (int i = 0; i < wv; ++i) o += s_tot[i];
   for (int i = 0; i < BM_ITEMS; ++i) {
-    uint32_t x = b[i];
-    if (!x) continue;
-    const size_t wi = base + i;
-    d.present[wi] |= x;
-    d.touched[wi] = 0u;
-    while (x) {
-      const int bit = __builtin_ctz(x);
-      x &= x - 1;
-      const uint64_t kk = ((uint64_t)wi << 5) | (uint64_t)bit;
-      keys[o] = (K)kk;
+    const size_t wb = w0 + (size_t)i * WAVE;
+    const size_t wi = wb + lane;
+    const uint32_t x = wi < words ? d.touched[wi] : 0u;
+    if (!__ballot(x != 0u)) continue;
+    if (x) {
+      d.present[wi] |= x;
+      d.touched[wi] = 0u;
+    }
+    o += wave_expand_bits(x, wb, o, [&](uint32_t slot, uint64_t kk) {
+      keys[slot] = (K)kk;
       float t = 1.0f;
       if (d.mode == DENSE_ADD) {
         t = fminf(1.0f, __uint_as_float(d.dtag[kk]));
@@ -307,13 +371,12 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
       } else if (d.mode != DENSE_BOOL) {
         t = from_ordered(d.dtag[kk]);
       }
-      if (rtags) rtags[o] = t;
+      if (rtags) rtags[slot] = t;
       if (d.did) {
-        d.did[kk] = id_base + o;
-        tag_by_id[id_base + o] = t;
+        d.did[kk] = id_base + slot;
+        tag_by_id[id_base + slot] = t;
       }
-      ++o;
-    }
+    });
   }
 }
 
@@ -361,41 +424,50 @@ void segments_compact(const void* in, const uint32_t* cnt, const uint32_t* pos, 
 
 size_t bitmap_words(int w) { return w >= 5 ? (size_t)1 << (w - 5) : 1; }
 
-__global__ void k_popc(const uint32_t* __restrict__ bits, size_t words, uint32_t* __restrict__ counts) {
-  GRID_STRIDE(i, words) counts[i] = (uint32_t)__popc(bits[i]);
-}
-
-void bitmap_popcounts(const uint32_t* bits, size_t words, uint32_t* counts, hipStream_t st) {
-  if (words) k_popc<<<grid_for(words), BLOCK, 0, st>>>(bits, words, counts);
-}
-
+// Sorted keys of the present bits (one block per BM_TILE words, block
+// offsets from bitmap_block_counts + scan), with their tags and ids.
 template <typename K>
-__global__ void k_bitmap_keys(DenseArgs d, size_t words, const uint32_t* __restrict__ pos, K* __restrict__ keys,
-                              float* __restrict__ tags, uint32_t* __restrict__ ids) {
-  GRID_STRIDE(wi, words) {
-    uint32_t b = d.present[wi];
-    uint32_t o = pos[wi];
-    while (b) {
-      const int i = __builtin_ctz(b);
-      b &= b - 1;
-      const uint64_t kk = ((uint64_t)wi << 5) | (uint64_t)i;
-      keys[o] = (K)kk;
+__global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words, const uint32_t* __restrict__ bpos,
+                                                       K* __restrict__ keys, float* __restrict__ tags,
+                                                       uint32_t* __restrict__ ids) {
+  __shared__ uint32_t s_tot[NWAVES];
+  const int lane = lane_id(), wv = threadIdx.x / WAVE;
+  const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < BM_ITEMS; ++i) {
+    const size_t wi = w0 + (size_t)i * WAVE + lane;
+    if (wi < words) c += (uint32_t)__popc(d.present[wi]);
+  }
+  c = wave_sum(c);
+  if (lane == 0) s_tot[wv] = c;
+  __syncthreads();
+  if (c == 0) return;  // wave-uniform; no barrier follows
+  uint32_t o = bpos[blockIdx.x];
+  for (int i = 0; i < wv; ++i) o += s_tot[i];
+  for (int i = 0; i < BM_ITEMS; ++i) {
+    const size_t wb = w0 + (size_t)i * WAVE;
+    const size_t wi = wb + lane;
+    const uint32_t x = wi < words ? d.present[wi] : 0u;
+    if (!__ballot(x != 0u)) continue;
+    o += wave_expand_bits(x, wb, o, [&](uint32_t slot, uint64_t kk) {
+      keys[slot] = (K)kk;
       if (tags) {
-        const uint32_t x = d.dtag[kk];
-        tags[o] = d.mode == DENSE_ADD ? __uint_as_float(x) : d.mode == DENSE_BOOL ? 1.0f : from_ordered(x);
+        const uint32_t v = d.dtag[kk];
+        tags[slot] = d.mode == DENSE_ADD ? __uint_as_float(v) : d.mode == DENSE_BOOL ? 1.0f : from_ordered(v);
       }
-      if (ids) ids[o] = d.did[kk];
-      ++o;
-    }
+      if (ids) ids[slot] = d.did[kk];
+    });
   }
 }
 
 template <typename K>
-void bitmap_keys(const DenseArgs& d, int w, const uint32_t* pos, K* keys, float* tags, uint32_t* ids, hipStream_t st) {
+void bitmap_keys(const DenseArgs& d, int w, const uint32_t* bpos, K* keys, float* tags, uint32_t* ids, hipStream_t st) {
   const size_t words = bitmap_words(w);
-  k_bitmap_keys<K><<<grid_for(words), BLOCK, 0, st>>>(d, words, pos, keys, tags, ids);
+  DL_PROF_BEGIN(6, st);
+  k_bitmap_keys<K><<<dense_count_blocks(w), BLOCK, 0, st>>>(d, words, bpos, keys, tags, ids);
+  DL_PROF_END(6, st, words * 4.0);
 }
-
 
 #define INST(K)                                                                                                       \
   template void join_expand_dense<K>(const JoinArgs&, int, const uint32_t*, size_t, const uint64_t*, size_t,     \

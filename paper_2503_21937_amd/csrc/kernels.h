@@ -134,10 +134,10 @@ void join_expand_dense(const JoinArgs& a, int tag_kind, const uint32_t* offs, si
 void accumulate_total(const uint64_t* src, uint64_t* acc, hipStream_t st);
 template <typename K>
 void project_dense(const JoinArgs& a, int tag_kind, const DenseArgs& d, bool lineage, hipStream_t st);
-// Round end, pass 1: touched-key count of every block of the touched bitmap
-// (dense_count_blocks(w) entries).
+// Pass 1 of a bitmap compaction: set-bit count of every block of a bitmap of
+// 2^w bits (dense_count_blocks(w) entries).
 size_t dense_count_blocks(int w);
-void dense_touched_counts(const DenseArgs& d, int w, uint32_t* partial, hipStream_t st);
+void bitmap_block_counts(const uint32_t* bits, int w, uint32_t* partial, hipStream_t st);
 // Pass 2 (bpos = exclusive scan of those counts): write the touched keys in
 // ascending order with their tags (rtags may be NULL), make them present,
 // clear touched, clamp frozen sums and, with lineage, assign ids base.. in
@@ -148,12 +148,12 @@ void dense_finalize(const DenseArgs& d, int w, const uint32_t* bpos, K* keys, fl
 // owner[i] = did[keys[i]]
 template <typename K>
 void dense_owners(const DenseArgs& d, const K* keys, size_t n, uint32_t* owner, hipStream_t st);
-// Sorted keys of the set bits of a presence bitmap of 2^w bits; tags and ids
-// gathered from the dense arrays (either may be NULL).  scratch: counts.
+// Sorted keys of the set bits of the presence bitmap (2^w bits; bpos =
+// exclusive scan of its block counts), tags and ids gathered from the dense
+// arrays (either may be NULL).
 size_t bitmap_words(int w);
 template <typename K>
-void bitmap_keys(const DenseArgs& d, int w, const uint32_t* pos, K* keys, float* tags, uint32_t* ids, hipStream_t st);
-void bitmap_popcounts(const uint32_t* bits, size_t words, uint32_t* counts, hipStream_t st);
+void bitmap_keys(const DenseArgs& d, int w, const uint32_t* bpos, K* keys, float* tags, uint32_t* ids, hipStream_t st);
 // Gather nseg wave segments (counts, pos = exclusive scan of counts) of
 // `bytes`-wide elements into a contiguous array.
 void segments_compact(const void* in, const uint32_t* counts, const uint32_t* pos, size_t nseg, size_t bytes,

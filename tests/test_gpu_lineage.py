@@ -40,7 +40,9 @@ def test_grid_batch_recompute_vs_oracle(oracle, synth, dedup, mode):
     # the recorded sweep gives the same gradients
     se = engine(synth.TC_PROGRAM, "diff_addmult", facts, batched=True, dedup=dedup, lineage="store")
     assert se.stats()["lineage_mode"] == 1
-    np.testing.assert_allclose(gg, grads(se, "path", gout, g["src"].size), rtol=1e-5, atol=1e-7)
+    # (float atomics: the sums may be taken in another order)
+    ref = grads(se, "path", gout, g["src"].size)
+    np.testing.assert_allclose(gg, ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max())
 
 
 @pytest.mark.parametrize("dedup", DEDUP)
