@@ -121,6 +121,8 @@ typedef struct {
   double tuned_ms;        /* median run time of the configuration dl_autotune chose */
   int lineage_mode;       /* DIFF_ADDMULT after the last run: 1 lineage recorded, 2 recomputed in
                              dl_backward (0 for the other semirings) */
+  int rows;               /* row-window joins in force: 0 off, 1 for launches with many derivations
+                             per window (default), 2 wherever they apply */
 } dl_stats;
 
 /* Kernel families timed by dl_profile (bit i of the mask = family i). */
@@ -221,7 +223,9 @@ dl_status dl_get_stats(const dl_engine* e, dl_stats* out);
  * candidate execution configuration -- deduplication (sort-based or
  * dense-domain), orientation of the delta joins of 2-atom rules (recent
  * tuples probe the static side, or the static side probes an index over the
- * recent tuples) and the join expand tile (1, 2, 4 or 8 outputs per thread) --
+ * recent tuples), the join expand tile (1, 2, 4 or 8 outputs per thread) and,
+ * for dense heads of static-driven joins, whether derivations are folded per
+ * head-key window in LDS (row windows) or scattered with global atomics --
  * and keeps the fastest (median of `trials` runs after a warm-up run) for
  * later runs.  All candidates compute the same relations.  If cache_path is
  * not NULL the choice is first looked up there, keyed by a hash of the program

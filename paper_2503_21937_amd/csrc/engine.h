@@ -62,6 +62,8 @@ struct RelState {
   int dense_w = 0;
   bool own_index = false;  // a plan of its own stratum joins against it
   DevBuf present, touched, dtag, did, log_keys, log_l, log_r, seg_lcount;
+  DevBuf goff;                   // as a join driver: CSR over its (sample, first column) prefix
+  uint64_t goff_version = ~0ull;  // `version` it was built from
   size_t nseg = 0;         // lineage wave segments emitted this round
   Table view_full, view_recent, view_stable;  // a past round's state (lineage recomputation)
   DevBuf fact_entry;  // input facts -> entry id
@@ -88,6 +90,7 @@ struct ExecConfig {
   int items = 4;   // join expand tile: outputs per thread (1, 2, 4, 8)
   int orient = 0;  // delta plans of 2-atom rules: 0 auto, 1 recent-driven, 2 static-driven
   int graph = 1;   // replay eligible round bodies as a captured HIP graph
+  int rows = 1;    // row-window variant of the dense join where it applies
 };
 
 struct Engine {

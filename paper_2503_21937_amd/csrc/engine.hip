@@ -57,7 +57,7 @@ Engine::~Engine() {
       fr(t->keys), fr(t->tags), fr(t->ids);
     fr(r.fact_entry), fr(r.grad), fr(r.fact_slot_d);
     fr(r.cand_keys), fr(r.cand_tags), fr(r.cand_l), fr(r.cand_r);
-    for (DevBuf* b : {&r.present, &r.touched, &r.dtag, &r.did, &r.log_keys, &r.log_l, &r.log_r, &r.seg_lcount})
+    for (DevBuf* b : {&r.present, &r.touched, &r.dtag, &r.did, &r.log_keys, &r.log_l, &r.log_r, &r.seg_lcount, &r.goff})
       fr(*b);
   }
   for (auto& x : idx) {
@@ -284,6 +284,7 @@ void Engine::run() {
   stats.dedup = opts.dedup;
   stats.orient = cfg.orient;
   stats.items = cfg.items;
+  stats.rows = cfg.rows;
 }
 
 size_t Engine::relation_size(const char* relation) {
@@ -419,7 +420,7 @@ std::string Engine::tune_key() const {
 
 namespace {
 struct Tuned {
-  int dedup, orient, items;
+  int dedup, orient, items, rows;
   double ms;
 };
 
@@ -431,9 +432,13 @@ bool cache_lookup(const char* path, const std::string& key, Tuned* t) {
   while (std::fgets(line, sizeof line, f)) {  // later lines override earlier ones
     char k[200];
     Tuned x{};
-    if (std::sscanf(line, "{\"key\": \"%199[^\"]\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"ms\": %lf",
-                    k, &x.dedup, &x.orient, &x.items, &x.ms) == 5 &&
-        key == k) {
+    x.rows = 1;
+    const bool ok =
+        std::sscanf(line, "{\"key\": \"%199[^\"]\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"rows\": %d, \"ms\": %lf",
+                    k, &x.dedup, &x.orient, &x.items, &x.rows, &x.ms) == 6 ||
+        std::sscanf(line, "{\"key\": \"%199[^\"]\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"ms\": %lf",
+                    k, &x.dedup, &x.orient, &x.items, &x.ms) == 5;
+    if (ok && key == k) {
       *t = x;
       found = true;
     }
@@ -445,8 +450,8 @@ bool cache_lookup(const char* path, const std::string& key, Tuned* t) {
 void cache_store(const char* path, const std::string& key, const Tuned& t) {
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "{\"key\": \"%s\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"ms\": %.4f}\n", key.c_str(),
-               t.dedup, t.orient, t.items, t.ms);
+  std::fprintf(f, "{\"key\": \"%s\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"rows\": %d, \"ms\": %.4f}\n",
+               key.c_str(), t.dedup, t.orient, t.items, t.rows, t.ms);
   std::fclose(f);
 }
 }  // namespace
@@ -457,11 +462,12 @@ void Engine::autotune(int trials, const char* cache_path) {
   if (trials < 1) trials = 1;
   if (!ingested) run();  // fixes the key layout the decision is keyed on
   const std::string key = tune_key();
-  Tuned best{opts.dedup, cfg.orient, cfg.items, 1e300};
+  Tuned best{opts.dedup, cfg.orient, cfg.items, cfg.rows, 1e300};
   if (cache_path && cache_lookup(cache_path, key, &best)) {
     opts.dedup = best.dedup;
     cfg.orient = best.orient;
     cfg.items = best.items;
+    cfg.rows = best.rows;
     stats.tuned_ms = best.ms;
     run();  // results of the cached configuration
     return;
@@ -474,31 +480,37 @@ void Engine::autotune(int trials, const char* cache_path) {
     for (int orient : {1, 2}) {
       if (orient == 2 && !twins) continue;
       for (int items : {1, 2, 4, 8}) {
-        opts.dedup = dedup;
-        cfg.orient = orient;
-        cfg.items = items;
-        std::vector<double> ms;
-        try {
-          run();
-          for (int t = 0; t < trials; ++t) {
+        // row windows only exist for dense heads of static-driven joins
+        for (int rows : {1, 0}) {
+          if (rows == 0 && (dedup != 2 || orient != 2)) continue;
+          opts.dedup = dedup;
+          cfg.orient = orient;
+          cfg.items = items;
+          cfg.rows = rows;
+          std::vector<double> ms;
+          try {
             run();
-            ms.push_back(stats.run_ms);
+            for (int t = 0; t < trials; ++t) {
+              run();
+              ms.push_back(stats.run_ms);
+            }
+          } catch (const Error& x) {
+            if (x.code == DL_ERR_UNSUPPORTED) break;  // e.g. no dense domain
+            opts.dedup = saved_dedup;
+            cfg = saved;
+            throw;
           }
-        } catch (const Error& x) {
-          if (x.code == DL_ERR_UNSUPPORTED) continue;  // e.g. no dense domain
-          opts.dedup = saved_dedup;
-          cfg = saved;
-          throw;
+          std::sort(ms.begin(), ms.end());
+          const double med = ms[ms.size() / 2];
+          if (med < best.ms) best = Tuned{dedup, orient, items, rows, med};
         }
-        std::sort(ms.begin(), ms.end());
-        const double med = ms[ms.size() / 2];
-        if (med < best.ms) best = Tuned{dedup, orient, items, med};
       }
     }
   }
   opts.dedup = best.dedup;
   cfg.orient = best.orient;
   cfg.items = best.items;
+  cfg.rows = best.rows;
   stats.tuned_ms = best.ms;
   if (cache_path) cache_store(cache_path, key, best);
   run();  // leave the results of the chosen configuration in place

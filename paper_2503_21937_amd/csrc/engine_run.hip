@@ -52,6 +52,13 @@ void claim(DevBuf& owner, DevBuf& alt, const void* result) {
   if (result == alt.p) std::swap(owner, alt);
 }
 
+// Device-side failure flag of the dense join kernels (read with the totals).
+void check_overflow(Engine& e) {
+  const uint64_t f = e.host[S_OVF];
+  if (f == 1) throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
+  if (f) throw Error{DL_ERR_HIP, "row-window join: a derivation fell outside its window"};
+}
+
 // Whether a round's L discovery derivations can be added to the recorded
 // lineage.  Past the budget the whole record is dropped (memory returned) and
 // the reverse pass recomputes every round's derivations instead.
@@ -207,6 +214,33 @@ void ensure_index(Engine& e, int i) {
   if (stale) build_index<K>(e, i);
 }
 
+// Row windows (k_join_expand_rows) for a single-join plan driven by a whole
+// relation whose head key starts with the driver's (sample, first column)
+// prefix; a window must hold 2^5..2^13 keys.  Builds the driver's prefix CSR
+// when the relation changed.  The row variant takes launches with at least
+// one derivation per 8 window keys of the driver's groups.
+template <typename K>
+bool row_windows(Engine& e, const Plan& pl, RowWindows* rw) {
+  if (pl.delta || pl.steps.size() != 1 || pl.steps[0].out_src.empty() || pl.steps[0].out_src[0] != 0) return false;
+  const int har = e.prog.rels[pl.head_rel].arity;
+  const int wbits = e.cbits * (har - 1), pbits = e.sbits + e.cbits;
+  if (har < 2 || wbits < 5 || wbits > 13 || pbits > 30) return false;
+  RelState& D = e.rel[pl.driver_rel];
+  if (D.full.n == 0) return false;
+  const size_t groups = (size_t)1 << pbits;
+  if (D.goff_version != D.version) {
+    e.grow(D.goff, (groups + 1) * 4);
+    csr_build<K>(D.full.keys.as<K>(), D.full.n, e.key_width(e.prog.rels[pl.driver_rel].arity), pbits,
+                 D.goff.as<uint32_t>(), e.stream);
+    D.goff_version = D.version;
+  }
+  rw->goff = D.goff.as<uint32_t>();
+  rw->ngroups = groups;
+  rw->wbits = wbits;
+  rw->from = e.cfg.rows == 2 ? 0 : (uint64_t)std::min(groups, D.full.n) * ((uint64_t)1 << wbits) / 8;
+  return true;
+}
+
 struct Cur {  // the table a plan is currently expanding
   const void* keys;
   const void* tags;
@@ -326,8 +360,10 @@ void run_plan(Engine& e, const Plan& pl) {
       const size_t bound = cur.n > ((size_t)1 << 40) / in ? ((size_t)1 << 40) : cur.n * in;
       const DenseArgs d = dense_room(0, a.items);
       accumulate_total(total_slot(e, S_SCAN), total_slot(e, S_CAND), e.stream);
+      RowWindows rw{};
+      const bool rows = e.cfg.rows && row_windows<K>(e, pl, &rw);
       join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), 0, total_slot(e, S_SCAN), bound, d, false,
-                           e.stream);
+                           e.stream, rows ? &rw : nullptr);
       return;
     }
     const uint64_t total = e.read_total(S_SCAN);
@@ -381,7 +417,7 @@ size_t absorb_dense(Engine& e, int r) {
     scan(e, R.seg_lcount.as<uint32_t>(), e.lpos.as<uint32_t>(), nseg, S_LIN, true);
   }
   e.read_totals();
-  if (e.host[S_OVF]) throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
+  check_overflow(e);
   const size_t U = e.host[S_UNIQUE], L = e.record && nseg ? e.host[S_LIN] : 0;
   if (U == 0) {
     R.recent.n = 0;
@@ -654,8 +690,10 @@ void enqueue_graph_round(Engine& e, int r, const std::vector<const Plan*>& plans
              e.scratch.as<uint64_t>(), st);
     accumulate_total(total_slot(e, S_SCAN), total_slot(e, S_CAND), st);
     DenseArgs d = dense_args(e, R);
+    RowWindows rw{};
+    const bool rows = e.cfg.rows && row_windows<K>(e, *tw, &rw);
     join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), 0, total_slot(e, S_SCAN), (size_t)1 << 40, d, false,
-                         st);
+                         st, rows ? &rw : nullptr);
   }
   const DenseArgs d = dense_args(e, R);
   const size_t nb = dense_count_blocks(R.dense_w);
@@ -724,7 +762,7 @@ int graph_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
     if (e.host[S_OVF]) {
       (void)hipGraphExecDestroy(exec);
       (void)hipGraphDestroy(graph);
-      throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
+      check_overflow(e);
     }
     const size_t U = e.host[S_UNIQUE];
     R.recent.n = U;

@@ -41,25 +41,40 @@ struct WaveSeg {
   uint32_t ln = 0;
 };
 
-// Called by every lane of the wave; `act` marks lanes holding a derivation.
+// Words a derivation's update depends on, loaded before any update of the
+// tile is issued (so that the loads of several derivations overlap).
+struct DenseProbe {
+  uint32_t pw = 0, tw = 0, cur = 0;
+};
+
 template <typename K>
-__device__ __forceinline__ void dense_emit(const DenseArgs& d, WaveSeg& ws, size_t seg, bool act, K key, float t,
-                                           uint32_t l, uint32_t r, bool lineage) {
-  // The presence, touched and tag words are loaded together up front and
-  // every atomic is issued without waiting for its result.  A derivation
-  // marks its key touched when it beats the tag it read: that value is no
-  // older than the round's start and tags only move one way inside a round,
-  // so the final tag then differs from the round-start tag; conversely the
-  // first derivation to write the final value saw a smaller one.  A stale
-  // touched word only costs a redundant atomicOr.
+__device__ __forceinline__ DenseProbe dense_load(const DenseArgs& d, bool act, K key) {
+  DenseProbe pr;
+  if (act) {
+    const uint64_t kk = (uint64_t)key;
+    pr.pw = d.present[kk >> 5];
+    pr.tw = d.touched[kk >> 5];
+    if (d.mode == DENSE_MAX || d.mode == DENSE_MIN) pr.cur = d.dtag[kk];
+  }
+  return pr;
+}
+
+// Called by every lane of the wave; `act` marks lanes holding a derivation.
+// Every atomic is issued without waiting for its result.  A derivation marks
+// its key touched when it beats the tag it read: that value is no older than
+// the round's start and tags only move one way inside a round, so the final
+// tag then differs from the round-start tag; conversely the first
+// derivation to write the final value saw a smaller one.  A stale touched
+// word only costs a redundant atomicOr.
+template <typename K>
+__device__ __forceinline__ void dense_apply(const DenseArgs& d, WaveSeg& ws, size_t seg, bool act, K key, float t,
+                                            uint32_t l, uint32_t r, bool lineage, const DenseProbe& pr) {
   bool keep = false, logit = false;
   if (act) {
     const uint64_t kk = (uint64_t)key;
     const size_t w = kk >> 5;
     const uint32_t bit = 1u << (kk & 31);
-    const uint32_t pw = d.present[w];
-    const uint32_t tw = d.touched[w];
-    const bool present = (pw & bit) != 0u;
+    const bool present = (pr.pw & bit) != 0u;
     switch (d.mode) {
       case DENSE_BOOL:
         keep = !present;
@@ -72,8 +87,8 @@ __device__ __forceinline__ void dense_emit(const DenseArgs& d, WaveSeg& ws, size
         }
         break;
       case DENSE_MAX: {
-        const uint32_t o = to_ordered(t), cur = d.dtag[kk];
-        if (o > cur) {
+        const uint32_t o = to_ordered(t);
+        if (o > pr.cur) {
           atomicMax(d.dtag + kk, o);
           keep = true;
         }
@@ -81,8 +96,8 @@ __device__ __forceinline__ void dense_emit(const DenseArgs& d, WaveSeg& ws, size
         break;
       }
       default: {  // DENSE_MIN
-        const uint32_t o = to_ordered(t), cur = d.dtag[kk];
-        if (o < cur) {
+        const uint32_t o = to_ordered(t);
+        if (o < pr.cur) {
           atomicMin(d.dtag + kk, o);
           keep = true;
         }
@@ -90,7 +105,7 @@ __device__ __forceinline__ void dense_emit(const DenseArgs& d, WaveSeg& ws, size
         break;
       }
     }
-    if (keep && !(tw & bit)) atomicOr(d.touched + w, bit);
+    if (keep && !(pr.tw & bit)) atomicOr(d.touched + w, bit);
   }
   if (lineage) {
     const uint64_t lm = ballot(logit);
@@ -102,6 +117,12 @@ __device__ __forceinline__ void dense_emit(const DenseArgs& d, WaveSeg& ws, size
     }
     ws.ln += (uint32_t)__popcll(lm);
   }
+}
+
+template <typename K>
+__device__ __forceinline__ void dense_emit(const DenseArgs& d, WaveSeg& ws, size_t seg, bool act, K key, float t,
+                                           uint32_t l, uint32_t r, bool lineage) {
+  dense_apply<K>(d, ws, seg, act, key, t, l, r, lineage, dense_load<K>(d, act, key));
 }
 
 __device__ __forceinline__ void dense_close(const DenseArgs& d, const WaveSeg& ws, size_t seg, bool lineage) {
@@ -117,7 +138,7 @@ __device__ __forceinline__ void dense_close(const DenseArgs& d, const WaveSeg& w
 template <typename K, int TK, int DX_ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_join_expand_dense(JoinArgs a, const uint32_t* __restrict__ offs,
                                                              size_t total_h, const uint64_t* __restrict__ dtotal,
-                                                             DenseArgs d, int lineage) {
+                                                             DenseArgs d, int lineage, uint64_t skip_at) {
   using T = typename TagOf<TK>::T;
   constexpr int DX_TILE = BLOCK * DX_ITEMS;
   static_assert(DX_ITEMS * WAVE <= DENSE_SEG, "a wave's outputs must fit its segment");
@@ -133,6 +154,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_expand_dense(JoinArgs a, const u
     if (blockIdx.x == 0 && threadIdx.x == 0 && d.overflow) *d.overflow = 1;
     return;
   }
+  if (total >= skip_at) return;  // the row-window kernel takes this launch
   const size_t ntiles = (total + DX_TILE - 1) / DX_TILE;
   for (size_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // uniform per block
     const size_t s0 = tile * DX_TILE;
@@ -140,46 +162,227 @@ __global__ __launch_bounds__(BLOCK) void k_join_expand_dense(JoinArgs a, const u
     tile_rows<DX_ITEMS>(offs, a.n, s0, s1, s_row, s_wave, s_r);
     const size_t seg = d.seg_base + tile * NWAVES + threadIdx.x / WAVE;
     WaveSeg ws;
-    for (int it_ = 0; it_ < DX_ITEMS; ++it_) {
-      const size_t j = s0 + (size_t)it_ * BLOCK + threadIdx.x;
-      if (s0 + (size_t)it_ * BLOCK >= s1) break;  // uniform across the block
-      const bool act = j < s1;
-      K okey = 0;
-      float t = 0.0f;
-      uint32_t l = 0, r = 0;
-      if (act) {
-        const size_t row = s_row[j - s0];
-        const uint32_t base = offs[row];
-        const K dkey = dk[row];
-        const uint64_t p = join_prefix(dkey, a);
-        const uint32_t irow = a.off[p] + ((uint32_t)j - base);
-        const K ikey = ik[irow];
+    // The items of a thread go through each dependent step together (probe
+    // row -> CSR offset -> index row -> dense words), so that their loads
+    // overlap instead of paying one memory latency per item and step.
+    bool act[DX_ITEMS];
+    uint32_t row[DX_ITEMS], irow[DX_ITEMS], base[DX_ITEMS];
+    K dkey[DX_ITEMS], okey[DX_ITEMS];
+    float t[DX_ITEMS];
+#pragma unroll
+    for (int q = 0; q < DX_ITEMS; ++q) {
+      const size_t j = s0 + (size_t)q * BLOCK + threadIdx.x;
+      act[q] = j < s1;
+      row[q] = act[q] ? s_row[j - s0] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < DX_ITEMS; ++q) {
+      base[q] = act[q] ? offs[row[q]] : 0u;
+      dkey[q] = act[q] ? dk[row[q]] : (K)0;
+    }
+#pragma unroll
+    for (int q = 0; q < DX_ITEMS; ++q) {
+      const uint32_t j = (uint32_t)(s0 + (size_t)q * BLOCK + threadIdx.x);
+      irow[q] = act[q] ? a.off[join_prefix(dkey[q], a)] + (j - base[q]) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < DX_ITEMS; ++q) {
+      okey[q] = 0;
+      t[q] = 0.0f;
+      if (act[q]) {
+        const K ikey = ik[irow[q]];
         uint32_t v[4];
         for (int c = 0; c < a.olay.ncols; ++c) {
           int s = a.osrc[c];
-          v[c] = s >= 0 ? key_col(dkey, s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
+          v[c] = s >= 0 ? key_col(dkey[q], s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
         }
-        const uint32_t sample = key_sample(dkey, a.dlay);
-        okey = key_make<K>(sample, v, a.olay);
+        okey[q] = key_make<K>(key_sample(dkey[q], a.dlay), v, a.olay);
         if constexpr (TK == TAG_F32) {
-          const float x = dt[row], y = it[irow];
-          t = a.index_first ? f_otimes(a.sr, y, x) : f_otimes(a.sr, x, y);
-        }
-        if (lineage) {
-          l = a.dids[row];
-          r = a.iids[irow];
+          const float x = dt[row[q]], y = it[irow[q]];
+          t[q] = a.index_first ? f_otimes(a.sr, y, x) : f_otimes(a.sr, x, y);
         }
       }
-      dense_emit<K>(d, ws, seg, act, okey, t, l, r, lineage != 0);
+    }
+    DenseProbe pr[DX_ITEMS];
+#pragma unroll
+    for (int q = 0; q < DX_ITEMS; ++q) pr[q] = dense_load<K>(d, act[q], okey[q]);
+#pragma unroll
+    for (int q = 0; q < DX_ITEMS; ++q) {
+      if (s0 + (size_t)q * BLOCK >= s1) break;  // uniform across the block
+      uint32_t l = 0, r = 0;
+      if (lineage && act[q]) {
+        l = a.dids[row[q]];
+        r = a.iids[irow[q]];
+      }
+      dense_apply<K>(d, ws, seg, act[q], okey[q], t[q], l, r, lineage != 0, pr[q]);
     }
     dense_close(d, ws, seg, lineage != 0);
     __syncthreads();  // s_row is rebuilt for the next tile
   }
 }
 
+// Row-window variant for static-driven joins whose head key starts with the
+// driver's (sample, first column) prefix p: all derivations of the driver
+// rows with prefix p land in the window of head keys [p << wbits, (p + 1) <<
+// wbits).  One workgroup owns one window at a time: it loads the window's
+// presence bits and tags into LDS, folds every derivation of the group there
+// with LDS atomics (duplicates across the group's driver rows meet in LDS),
+// and writes back only the entries it changed, with plain coalesced stores
+// (no other workgroup of the launch touches the window).  This trades one
+// streaming pass over the windows for scattered global atomics and pays off
+// when the launch has many derivations per window; the host sets the
+// threshold `from` and both variants test the device-side total.
+constexpr int RW_BITS = 13;  // largest window: 8192 keys (32 KB of tags)
+constexpr int RW_KEYS = 1 << RW_BITS;
+constexpr int RW_ROWS = 256;   // driver rows of a group staged in LDS
+constexpr int RW_BLOCK = 512;  // 8 waves: the window's LDS is shared by more waves
+
+template <typename K, int TK, int RX_ITEMS>
+__global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const uint32_t* __restrict__ offs,
+                                                               size_t total_h, const uint64_t* __restrict__ dtotal,
+                                                               DenseArgs d, RowWindows rw) {
+  using T = typename TagOf<TK>::T;
+  constexpr int TILE = RW_BLOCK * RX_ITEMS;
+  __shared__ uint32_t s_tag[TK == TAG_F32 ? RW_KEYS : 1];
+  __shared__ uint32_t s_pres[RW_KEYS / 32];
+  __shared__ uint32_t s_new[RW_KEYS / 32];
+  // per driver row of the group: first output slot, index row of the first
+  // output minus that slot (mod 2^32), key and tag
+  __shared__ uint32_t s_offs[RW_ROWS + 1];
+  __shared__ uint32_t s_ibase[RW_ROWS];
+  __shared__ K s_dkey[RW_ROWS];
+  __shared__ float s_dtag[TK == TAG_F32 ? RW_ROWS : 1];
+  const size_t total = dtotal ? (size_t)*dtotal : total_h;
+  if (total < rw.from || total > 0xffffffffull) return;  // scattered kernel's launch (or overflow, reported there)
+  const K* dk = (const K*)a.dkeys;
+  const K* ik = (const K*)a.ikeys;
+  const T* dt = (const T*)a.dtags;
+  const T* it = (const T*)a.itags;
+  const uint32_t W = 1u << rw.wbits, NWD = (W + 31) / 32;
+  for (size_t g = blockIdx.x; g < rw.ngroups; g += gridDim.x) {  // uniform per block
+    const uint32_t r0 = rw.goff[g], r1 = rw.goff[g + 1];
+    if (r0 == r1) continue;
+    const uint32_t s0 = offs[r0], s1 = offs[r1];
+    if (s0 == s1) continue;
+    const uint32_t nr = r1 - r0;
+    const bool lds_rows = nr <= (uint32_t)RW_ROWS;  // else rows are read from global memory
+    const uint64_t kb = (uint64_t)g << rw.wbits;
+    const size_t wb = kb >> 5;
+    for (uint32_t i = threadIdx.x; i < NWD; i += RW_BLOCK) {
+      s_pres[i] = d.present[wb + i];
+      s_new[i] = 0u;
+    }
+    if constexpr (TK == TAG_F32) {
+      // 16-byte loads, several in flight per thread (the window is
+      // W >= 32 keys long and W-aligned, hence 128-byte aligned)
+      const uint4* src = reinterpret_cast<const uint4*>(d.dtag + kb);
+      uint4* dst = reinterpret_cast<uint4*>(s_tag);
+#pragma unroll 4
+      for (uint32_t i = threadIdx.x; i < W / 4; i += RW_BLOCK) dst[i] = src[i];
+    }
+    if (lds_rows) {
+      for (uint32_t i = threadIdx.x; i <= nr; i += RW_BLOCK) {
+        const uint32_t o = offs[r0 + i];
+        s_offs[i] = o;
+        if (i < nr) {
+          const K key = dk[r0 + i];
+          s_dkey[i] = key;
+          s_ibase[i] = a.off[join_prefix(key, a)] - o;
+          if constexpr (TK == TAG_F32) s_dtag[i] = dt[r0 + i];
+        }
+      }
+    }
+    __syncthreads();
+    // the group's outputs, TILE at a time: each output finds its driver row
+    // by a binary search over the group's offsets (last row starting at or
+    // before it); the items of a thread take each step together
+    for (uint32_t t0 = s0; t0 < s1; t0 += TILE) {
+      uint32_t row[RX_ITEMS], irow[RX_ITEMS];
+      K dkey[RX_ITEMS];
+      float x[RX_ITEMS];
+      bool act[RX_ITEMS];
+#pragma unroll
+      for (int q = 0; q < RX_ITEMS; ++q) {
+        const uint32_t j = t0 + (uint32_t)(q * RW_BLOCK) + threadIdx.x;
+        act[q] = j < s1;
+        uint32_t lo = 0, hi = nr;  // invariant: start(lo) <= j < start(hi)
+        while (act[q] && hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          const uint32_t o = lds_rows ? s_offs[mid] : offs[r0 + mid];
+          if (o <= j) lo = mid;
+          else hi = mid;
+        }
+        row[q] = lo;
+        if (lds_rows) {
+          dkey[q] = s_dkey[lo];
+          irow[q] = s_ibase[lo] + j;
+          if constexpr (TK == TAG_F32) x[q] = s_dtag[lo];
+        }
+      }
+      if (!lds_rows) {
+#pragma unroll
+        for (int q = 0; q < RX_ITEMS; ++q) {
+          const uint32_t j = t0 + (uint32_t)(q * RW_BLOCK) + threadIdx.x;
+          const uint32_t r = r0 + row[q];
+          dkey[q] = act[q] ? dk[r] : (K)0;
+          irow[q] = act[q] ? a.off[join_prefix(dkey[q], a)] + (j - offs[r]) : 0u;
+          if constexpr (TK == TAG_F32) x[q] = act[q] ? dt[r] : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RX_ITEMS; ++q) {
+        if (!act[q]) continue;
+        const K ikey = ik[irow[q]];
+        uint32_t v[4];
+        for (int c = 0; c < a.olay.ncols; ++c) {
+          const int s = a.osrc[c];
+          v[c] = s >= 0 ? key_col(dkey[q], s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
+        }
+        const uint64_t lk = (uint64_t)key_make<K>(key_sample(dkey[q], a.dlay), v, a.olay) - kb;
+        if (lk >= W) {  // the host only picks this kernel when every key lies in its window
+          if (d.overflow) *d.overflow = 2;
+          continue;
+        }
+        const uint32_t loc = (uint32_t)lk;
+        const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
+        const bool present = (s_pres[wi] & bit) != 0u;
+        bool mark = false;
+        if constexpr (TK == TAG_F32) {
+          const float y = it[irow[q]];
+          const float t = a.index_first ? f_otimes(a.sr, y, x[q]) : f_otimes(a.sr, x[q], y);
+          if (d.mode == DENSE_ADD) {
+            if (!present) {
+              atomicAdd(reinterpret_cast<float*>(s_tag) + loc, t);
+              mark = true;
+            }
+          } else if (d.mode == DENSE_MAX) {
+            const uint32_t o = to_ordered(t);
+            mark = (o > s_tag[loc] && o > atomicMax(s_tag + loc, o)) || !present;
+          } else {
+            const uint32_t o = to_ordered(t);
+            mark = (o < s_tag[loc] && o < atomicMin(s_tag + loc, o)) || !present;
+          }
+        } else {
+          mark = !present;
+        }
+        if (mark && !(s_new[wi] & bit)) atomicOr(s_new + wi, bit);
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < NWD; i += RW_BLOCK) {
+      const uint32_t nb = s_new[i];
+      if (nb) d.touched[wb + i] |= nb;
+    }
+    if constexpr (TK == TAG_F32)
+      for (uint32_t i = threadIdx.x; i < W; i += RW_BLOCK)
+        if (s_new[i >> 5] >> (i & 31) & 1u) d.dtag[kb + i] = s_tag[i];
+    __syncthreads();  // the window's LDS is reloaded for the next group
+  }
+}
+
 template <typename K>
 void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t total, const uint64_t* dtotal,
-                       size_t max_total, const DenseArgs& d, bool lineage, hipStream_t st) {
+                       size_t max_total, const DenseArgs& d, bool lineage, hipStream_t st, const RowWindows* rw) {
   const int items = norm_items(a.items);
   const size_t tile = (size_t)BLOCK * items;
   size_t nb;
@@ -196,11 +399,20 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   // per derivation: index row read, presence word and dense tag read; per probe row: driver row + offset
   const double per = (sizeof(K) + tb + lin + 4.0 + tb);
   const double bytes = (dtotal ? 0.0 : total * per) + a.n * (sizeof(K) + tb + lin + 4.0);
-#define DL_DEXPAND(IT)                                                                                         \
-  if (tk == TAG_F32)                                                                                           \
-    k_join_expand_dense<K, TAG_F32, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0);     \
-  else                                                                                                         \
-    k_join_expand_dense<K, TAG_NONE, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0);
+  // row windows: both variants are launched and each checks the total
+  const bool rows = rw && !lineage && rw->wbits <= RW_BITS && (dtotal || total >= rw->from);
+  const uint64_t skip_at = rows ? rw->from : ~0ull;
+  const unsigned nrb = rows ? (unsigned)(rw->ngroups < 2048 ? rw->ngroups : 2048) : 0u;
+#define DL_DEXPAND(IT)                                                                                               \
+  if (tk == TAG_F32) {                                                                                               \
+    if (!rows || dtotal)                                                                                             \
+      k_join_expand_dense<K, TAG_F32, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0, skip_at); \
+    if (rows) k_join_expand_rows<K, TAG_F32, IT><<<nrb, RW_BLOCK, 0, st>>>(a, offs, total, dtotal, d, *rw);         \
+  } else {                                                                                                           \
+    if (!rows || dtotal)                                                                                             \
+      k_join_expand_dense<K, TAG_NONE, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0, skip_at); \
+    if (rows) k_join_expand_rows<K, TAG_NONE, IT><<<nrb, RW_BLOCK, 0, st>>>(a, offs, total, dtotal, d, *rw);        \
+  }
   DL_PROF_BEGIN(1, st);
   switch (items) {
     case 1: DL_DEXPAND(1) break;
@@ -471,7 +683,7 @@ void bitmap_keys(const DenseArgs& d, int w, const uint32_t* bpos, K* keys, float
 
 #define INST(K)                                                                                                       \
   template void join_expand_dense<K>(const JoinArgs&, int, const uint32_t*, size_t, const uint64_t*, size_t,     \
-                                     const DenseArgs&, bool, hipStream_t);                                                                   \
+                                     const DenseArgs&, bool, hipStream_t, const RowWindows*);                                                \
   template void project_dense<K>(const JoinArgs&, int, const DenseArgs&, bool, hipStream_t);                        \
   template void dense_finalize<K>(const DenseArgs&, int, const uint32_t*, K*, float*, uint32_t, float*, hipStream_t);       \
   template void dense_owners<K>(const DenseArgs&, const K*, size_t, uint32_t*, hipStream_t);                                  \

@@ -127,9 +127,20 @@ void join_expand(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t t
 // The same join, emitting into a dense-domain relation (see DenseArgs).  If
 // dtotal is not NULL the total is read on the device (the host passes an
 // upper bound max_total for the grid) and `total` is ignored.
+// Row windows of a static-driven join whose head keys start with the
+// driver's (sample, first column) prefix: goff is the CSR of the driver rows
+// over that prefix (ngroups prefixes), a head window holds 2^wbits keys
+// (wbits <= 13), and launches with at least `from` derivations use them.
+struct RowWindows {
+  const uint32_t* goff;
+  size_t ngroups;
+  int wbits;
+  uint64_t from;
+};
 template <typename K>
 void join_expand_dense(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t total, const uint64_t* dtotal,
-                       size_t max_total, const DenseArgs& d, bool lineage, hipStream_t st);
+                       size_t max_total, const DenseArgs& d, bool lineage, hipStream_t st,
+                       const RowWindows* rw = nullptr);
 // *acc += *src (device words)
 void accumulate_total(const uint64_t* src, uint64_t* acc, hipStream_t st);
 template <typename K>

@@ -54,7 +54,7 @@ class Stats(C.Structure):
                 ("lineage", C.c_uint64), ("run_ms", C.c_double), ("device_bytes", C.c_uint64),
                 ("key_bits", C.c_uint32), ("id_bits", C.c_uint32), ("sample_bits", C.c_uint32),
                 ("dedup", C.c_int), ("orient", C.c_int), ("items", C.c_int), ("tuned_ms", C.c_double),
-                ("lineage_mode", C.c_int)]
+                ("lineage_mode", C.c_int), ("rows", C.c_int)]
 
 
 _lib = None
@@ -284,7 +284,7 @@ class Engine:
         """Pick the fastest execution configuration for the current facts."""
         self._check(lib().dl_autotune(self.h, trials, None if cache is None else cache.encode()))
         st = self.stats()
-        return {k: st[k] for k in ("dedup", "orient", "items", "tuned_ms")}
+        return {k: st[k] for k in ("dedup", "orient", "items", "rows", "tuned_ms")}
 
     def profile(self, families=None):
         """Time the given kernel families (names; None = all, [] = off)."""

@@ -18,26 +18,27 @@ def make_engine(synth, sr, src, dst, p):
     return e
 
 
-@pytest.mark.parametrize("sr", ["maxmin", "addmult", "bool"])
+@pytest.mark.parametrize("sr", ["maxmin", "minplus", "addmult", "bool"])
 def test_every_configuration_matches_oracle(oracle, synth, sr, tmp_path):
     src, dst, p = synth.er_graph(5, 300, 1100, weights=True)
     want = oracle_run(oracle, synth.TC_PROGRAM, sr, {"edge": ([src, dst], p, None)}).read("path")
     key = _key(make_engine(synth, sr, src, dst, p))
-    for dedup in (1, 2):
-        for orient in (1, 2):
-            for items in (1, 2, 4, 8):
-                e = make_engine(synth, sr, src, dst, p)
-                cache = tmp_path / f"force_{sr}_{dedup}_{orient}_{items}.jsonl"
-                cache.write_text(json.dumps({"key": key, "dedup": dedup, "orient": orient, "items": items,
-                                             "ms": 1.0}) + "\n")
-                cfg = e.autotune(1, str(cache))
-                assert (cfg["dedup"], cfg["orient"], cfg["items"]) == (dedup, orient, items)
-                got = e.read("path")
-                assert np.array_equal(got["cols"], want["cols"]), (dedup, orient, items)
-                if sr == "maxmin":
-                    assert np.array_equal(got["tags"].astype(np.float64), want["value"])
-                elif sr == "addmult":
-                    assert_tags_close(got["tags"], want["value"])
+    configs = [(dedup, orient, items, 1) for dedup in (1, 2) for orient in (1, 2) for items in (1, 2, 4, 8)]
+    # row windows: off, and forced onto every launch they apply to
+    configs += [(2, 2, items, rows) for items in (1, 4, 8) for rows in (0, 2)]
+    for dedup, orient, items, rows in configs:
+        e = make_engine(synth, sr, src, dst, p)
+        cache = tmp_path / f"force_{sr}_{dedup}_{orient}_{items}_{rows}.jsonl"
+        cache.write_text(json.dumps({"key": key, "dedup": dedup, "orient": orient, "items": items,
+                                     "rows": rows, "ms": 1.0}) + "\n")
+        cfg = e.autotune(1, str(cache))
+        assert (cfg["dedup"], cfg["orient"], cfg["items"], cfg["rows"]) == (dedup, orient, items, rows)
+        got = e.read("path")
+        assert np.array_equal(got["cols"], want["cols"]), (dedup, orient, items, rows)
+        if sr == "maxmin":
+            assert np.array_equal(got["tags"].astype(np.float64), want["value"])
+        elif sr in ("addmult", "minplus"):
+            assert_tags_close(got["tags"], want["value"])
 
 
 def _key(e):
@@ -67,3 +68,24 @@ def test_autotune_picks_and_caches(oracle, synth, tmp_path):
     a, b = e.read("path"), e2.read("path")
     assert np.array_equal(a["cols"], b["cols"])
     assert np.array_equal(a["tags"], b["tags"])
+
+
+@pytest.mark.parametrize("rows", [0, 2])
+def test_row_windows_batched(oracle, synth, tmp_path, rows):
+    """Row windows keyed by (sample, first column) on a batch of grids."""
+    from paper_2503_21937_amd import dlfix
+    g = synth.grid_batch(9, samples=24, kmin=3, kmax=12)
+    facts = {"edge": ([g["src"], g["dst"]], g["p"], g["sample"])}
+    for sr in ("addmult", "maxmin", "bool"):
+        e = dlfix.Engine(synth.TC_PROGRAM, sr, batched=True)
+        e.add_facts("edge", [g["src"], g["dst"]], g["p"], g["sample"])
+        key = _key(e)
+        cache = tmp_path / f"rows_{sr}_{rows}.jsonl"
+        cache.write_text(json.dumps({"key": key, "dedup": 2, "orient": 2, "items": 4, "rows": rows,
+                                     "ms": 1.0}) + "\n")
+        assert e.autotune(1, str(cache))["rows"] == rows
+        got = e.read("path")
+        want = oracle_run(oracle, synth.TC_PROGRAM, sr, facts, batched=True).read("path")
+        assert np.array_equal(got["cols"], want["cols"]) and np.array_equal(got["sample"], want["sample"])
+        if sr != "bool":
+            assert_tags_close(got["tags"], want["value"])
