@@ -27,6 +27,37 @@ sys.path.insert(0, ROOT)
 
 SEMIRINGS = ("addmult", "maxmin", "minplus")
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# sources of the join_expand family (row-window and scattered dense joins)
+EXPAND_SOURCES = ("paper_2503_21937_amd/csrc/k_dense.hip", "paper_2503_21937_amd/csrc/rel_device.h",
+                  "paper_2503_21937_amd/csrc/dl_device.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "join_expand_er5000_traffic.txt")
+
+
+def expand_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in EXPAND_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of the dominant family from the committed PMC
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
+    the kernel sources changed since the counters were taken."""
+    if kernel != "join_expand" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if "=" in line:
+                k, v = (x.strip() for x in line.split("=", 1))
+                vals[k] = v
+    if vals.get("source_sha256") != expand_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(src, dst, p, n, budget_s: float, seed: int) -> dict:
@@ -234,7 +265,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(dominant),
             "launches": int(launches),
             "avg_launch_us": ms * 1e3 / launches if launches else 0.0,
             "avg_launch_bytes": nbytes / launches if launches else 0.0,

@@ -472,7 +472,7 @@ void project_dense(const JoinArgs& a, int tk, const DenseArgs& d, bool lineage, 
 // lanes write consecutive keys whatever the bit density (wave_expand_bits).
 // dense_finalize also makes the touched tuples present, clears touched,
 // clamps frozen sums and, with lineage, hands out ids in key order.
-constexpr int BM_ITEMS = 16;
+constexpr int BM_ITEMS = 8;
 constexpr int BM_TILE = BLOCK * BM_ITEMS;
 constexpr int BM_WAVE_WORDS = WAVE * BM_ITEMS;
 
@@ -553,11 +553,13 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
   __shared__ uint32_t s_tot[NWAVES];
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
+  uint32_t b[BM_ITEMS];  // the lane's words, loaded together
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
     const size_t wi = w0 + (size_t)i * WAVE + lane;
-    if (wi < words) c += (uint32_t)__popc(d.touched[wi]);
+    b[i] = wi < words ? d.touched[wi] : 0u;
+    c += (uint32_t)__popc(b[i]);
   }
   c = wave_sum(c);
   if (lane == 0) s_tot[wv] = c;
@@ -565,14 +567,14 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
   if (c == 0) return;  // wave-uniform; no barrier follows
   uint32_t o = bpos[blockIdx.x];
   for (int i = 0; i < wv; ++i) o += s_tot[i];
+#pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
-    const size_t wb = w0 + (size_t)i * WAVE;
-    const size_t wi = wb + lane;
-    const uint32_t x = wi < words ? d.touched[wi] : 0u;
+    const uint32_t x = b[i];
     if (!__ballot(x != 0u)) continue;
+    const size_t wb = w0 + (size_t)i * WAVE;
     if (x) {
-      d.present[wi] |= x;
-      d.touched[wi] = 0u;
+      d.present[wb + lane] |= x;
+      d.touched[wb + lane] = 0u;
     }
     o += wave_expand_bits(x, wb, o, [&](uint32_t slot, uint64_t kk) {
       keys[slot] = (K)kk;
@@ -645,11 +647,13 @@ __global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words
   __shared__ uint32_t s_tot[NWAVES];
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
+  uint32_t b[BM_ITEMS];
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
     const size_t wi = w0 + (size_t)i * WAVE + lane;
-    if (wi < words) c += (uint32_t)__popc(d.present[wi]);
+    b[i] = wi < words ? d.present[wi] : 0u;
+    c += (uint32_t)__popc(b[i]);
   }
   c = wave_sum(c);
   if (lane == 0) s_tot[wv] = c;
@@ -657,12 +661,11 @@ __global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words
   if (c == 0) return;  // wave-uniform; no barrier follows
   uint32_t o = bpos[blockIdx.x];
   for (int i = 0; i < wv; ++i) o += s_tot[i];
+#pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
-    const size_t wb = w0 + (size_t)i * WAVE;
-    const size_t wi = wb + lane;
-    const uint32_t x = wi < words ? d.present[wi] : 0u;
+    const uint32_t x = b[i];
     if (!__ballot(x != 0u)) continue;
-    o += wave_expand_bits(x, wb, o, [&](uint32_t slot, uint64_t kk) {
+    o += wave_expand_bits(x, w0 + (size_t)i * WAVE, o, [&](uint32_t slot, uint64_t kk) {
       keys[slot] = (K)kk;
       if (tags) {
         const uint32_t v = d.dtag[kk];

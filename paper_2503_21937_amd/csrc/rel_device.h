@@ -75,6 +75,27 @@ __device__ __forceinline__ size_t upper_bound_u32(const uint32_t* a, size_t n, u
   return lo;
 }
 
+// upper_bound by a whole wave: first index i in [0, n] with a[i] > x (a
+// sorted).  Each step the 64 lanes probe evenly spaced positions and a ballot
+// narrows the range 64-fold, so a search costs ~log64(n) dependent loads
+// instead of log2(n).  Must be called by all lanes; the result is uniform.
+__device__ __forceinline__ size_t wave_upper_bound(const uint32_t* a, size_t n, uint32_t x) {
+  const size_t lane = (size_t)lane_id();
+  size_t lo = 0, hi = n;  // every a[i] with i < lo is <= x; the answer lies in [lo, hi]
+  while (hi - lo > (size_t)WAVE) {
+    const size_t step = (hi - lo + WAVE - 1) / WAVE;
+    const size_t pos = lo + lane * step;
+    const bool le = pos < hi && a[pos] <= x;
+    const uint32_t cnt = (uint32_t)__popcll(ballot(le));  // le holds on a prefix of the lanes
+    if (cnt == 0) return lo;
+    const size_t nlo = lo + (cnt - 1) * step + 1, nhi = lo + cnt * step;
+    lo = nlo;
+    hi = nhi < hi ? nhi : hi;
+  }
+  const size_t pos = lo + lane;
+  const bool le = pos < hi && a[pos] <= x;
+  return lo + (size_t)__popcll(ballot(le));
+}
 
 // Owning probe row of every output slot of the tile [s0, s1) of a
 // load-balanced expansion (offs = exclusive scan of the match counts, with
@@ -87,9 +108,10 @@ template <int ITEMS>
 __device__ __forceinline__ void tile_rows(const uint32_t* __restrict__ offs, size_t n, size_t s0, size_t s1,
                                           uint32_t* s_row, uint32_t* s_wave, size_t* s_r) {
   constexpr int TILE = BLOCK * ITEMS;
-  if (threadIdx.x == 0) {
-    s_r[0] = upper_bound_u32(offs, n + 1, (uint32_t)s0) - 1;
-    s_r[1] = upper_bound_u32(offs, n + 1, (uint32_t)(s1 - 1)) - 1;
+  const int wv = threadIdx.x / WAVE;
+  if (wv < 2) {  // wave 0 finds the tile's first row, wave 1 its last
+    const size_t r = wave_upper_bound(offs, n + 1, (uint32_t)(wv == 0 ? s0 : s1 - 1)) - 1;
+    if (lane_id() == 0) s_r[wv] = r;
   }
   for (int t = threadIdx.x; t < TILE; t += BLOCK) s_row[t] = 0u;
   __syncthreads();

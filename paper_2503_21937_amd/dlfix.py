@@ -160,7 +160,8 @@ class Engine:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().dl_free(self.h)
+            if _lib is not None:  # at interpreter exit the module may be torn down first
+                _lib.dl_free(self.h)
             self.h = None
 
     def __del__(self):
