@@ -255,6 +255,7 @@ def main() -> int:
             "derived_per_step": derived,
             "rounds": {sr: stats[sr]["max_rounds"] for sr in SEMIRINGS},
             "candidates": {sr: stats[sr]["candidates"] for sr in SEMIRINGS},
+            "new_or_changed": {sr: stats[sr]["unique"] for sr in SEMIRINGS},
             "kernel_ms_share": {k: round(v / sum(totals.values()), 4) for k, v in
                                 sorted(totals.items(), key=lambda kv: -kv[1])},
         },

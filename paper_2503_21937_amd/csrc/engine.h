@@ -57,9 +57,10 @@ struct RelState {
   // previous state there), full itself after a round that added none
   bool stable_full = false;
   uint64_t sversion = 0;  // bumped whenever the stable part may change
-  // dense-domain deduplication (derived relations whose keys are < 2^dense_w)
+  // dense-domain deduplication (derived relations with a small key domain)
   bool dense = false;
-  int dense_w = 0;
+  size_t dense_keys = 0;  // size of the dense index domain (see DenseArgs)
+  int dense_cols = 0;
   bool own_index = false;  // a plan of its own stratum joins against it
   DevBuf present, touched, dtag, did, log_keys, log_l, log_r, seg_lcount;
   DevBuf goff;                   // as a join driver: CSR over its (sample, first column) prefix
@@ -114,6 +115,7 @@ struct Engine {
   bool ran = false;
   bool key64 = false;
   int cbits = 1, sbits = 0;
+  uint32_t max_id = 0, max_sample = 0;
   std::vector<RelState> rel;
   std::vector<IndexState> idx;
 

@@ -262,6 +262,8 @@ void Engine::run() {
     DL_HIP(hipMemcpyAsync(host, dmax, 8, hipMemcpyDeviceToHost, stream));
     sync();
     uint32_t maxid = (uint32_t)host[0], maxs = (uint32_t)(host[0] >> 32);
+    max_id = maxid;
+    max_sample = batched ? maxs : 0;
     cbits = bits_for(maxid);
     sbits = batched ? bits_for(maxs) : 0;
     int width = key_width(prog.max_cols);

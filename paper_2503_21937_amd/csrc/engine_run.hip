@@ -84,7 +84,24 @@ DenseArgs dense_args(Engine& e, RelState& R) {
   d.seg_base = (uint32_t)R.nseg;
   d.overflow = e.dtotal.as<uint64_t>() + S_OVF;
   d.mode = e.sr == DL_BOOL ? DENSE_BOOL : !e.converge ? DENSE_ADD : e.sr == DL_MAXMIN ? DENSE_MAX : DENSE_MIN;
+  d.dn = e.max_id + 1;
+  d.dnp = (d.dn + 31) / 32 * 32;
+  d.dcols = R.dense_cols;
+  d.dcbits = e.cbits;
+  dense_divisors(d);
   return d;
+}
+
+// Dense index domain of a relation of arity `ar`: (samples) x dn^(ar-1) x
+// dnp, dn = ids in use, dnp = dn rounded up to 32 (see DenseArgs).
+uint64_t dense_domain(const Engine& e, int ar) {
+  const uint64_t dn = (uint64_t)e.max_id + 1, dnp = (dn + 31) / 32 * 32;
+  uint64_t keys = (uint64_t)e.max_sample + 1;
+  for (int c = 0; c + 1 < ar; ++c) {
+    keys *= dn;
+    if (keys > ((uint64_t)1 << 40)) return keys;
+  }
+  return keys * dnp;
 }
 
 // Decide the deduplication of every derived relation and reset the dense
@@ -95,16 +112,17 @@ void setup_dense(Engine& e) {
     RelState& R = e.rel[r];
     R.dense = false;
     if (!e.prog.rels[r].derived) continue;
-    const int w = e.key_width(e.prog.rels[r].arity);
-    const size_t keys = (size_t)1 << std::min(w, 40);
-    const size_t bytes = 2 * bitmap_words(w) * 4 + (e.tag_kind == TAG_F32 ? keys * 4 : 0) + (e.lineage ? keys * 4 : 0);
-    const bool fits = e.tag_kind != TAG_TOPK && w <= 31 && bytes <= budget;
+    const uint64_t dom = dense_domain(e, e.prog.rels[r].arity);
+    const size_t keys = (size_t)std::min<uint64_t>(dom, (uint64_t)1 << 40);
+    const size_t bytes = 2 * bitmap_words(keys) * 4 + (e.tag_kind == TAG_F32 ? keys * 4 : 0) + (e.lineage ? keys * 4 : 0);
+    const bool fits = e.tag_kind != TAG_TOPK && dom <= ((uint64_t)1 << 31) && bytes <= budget;
     if (e.opts.dedup == 2 && !fits)
       throw Error{DL_ERR_UNSUPPORTED, "dense-domain deduplication does not fit relation " + e.prog.rels[r].name};
     R.dense = fits && e.opts.dedup != 1;
     if (!R.dense) continue;
-    R.dense_w = w;
-    const size_t words = bitmap_words(w);
+    R.dense_keys = keys;
+    R.dense_cols = e.prog.rels[r].arity;
+    const size_t words = bitmap_words(keys);
     e.grow(R.present, words * 4);
     e.grow(R.touched, words * 4);
     DL_HIP(hipMemsetAsync(R.present.p, 0, words * 4, e.stream));
@@ -122,10 +140,10 @@ void setup_dense(Engine& e) {
 template <typename K>
 void materialize_full(Engine& e, RelState& R) {
   std::swap(R.full, R.full_alt);  // the previous materialisation stays as the stable part
-  const size_t nb = dense_count_blocks(R.dense_w);
+  const size_t nb = dense_count_blocks(R.dense_keys);
   e.grow(e.flags, nb * 4);
   e.grow(e.pos, (nb + 1) * 4);
-  bitmap_block_counts(R.present.as<uint32_t>(), R.dense_w, e.flags.as<uint32_t>(), e.stream);
+  bitmap_block_counts(R.present.as<uint32_t>(), R.dense_keys, e.flags.as<uint32_t>(), e.stream);
   scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, S_SCAN, true);
   const size_t F = e.read_total(S_SCAN);
   e.grow(R.full.keys, F * sizeof(K) + 8);
@@ -139,7 +157,7 @@ void materialize_full(Engine& e, RelState& R) {
     e.grow(R.full.ids, F * 4 + 8);
     ids = R.full.ids.as<uint32_t>();
   }
-  bitmap_keys<K>(dense_args(e, R), R.dense_w, e.pos.as<uint32_t>(), R.full.keys.as<K>(), tags, ids, e.stream);
+  bitmap_keys<K>(dense_args(e, R), R.dense_keys, e.pos.as<uint32_t>(), R.full.keys.as<K>(), tags, ids, e.stream);
   R.full.n = F;
   ++R.version;
 }
@@ -223,8 +241,13 @@ template <typename K>
 bool row_windows(Engine& e, const Plan& pl, RowWindows* rw) {
   if (pl.delta || pl.steps.size() != 1 || pl.steps[0].out_src.empty() || pl.steps[0].out_src[0] != 0) return false;
   const int har = e.prog.rels[pl.head_rel].arity;
-  const int wbits = e.cbits * (har - 1), pbits = e.sbits + e.cbits;
-  if (har < 2 || wbits < 5 || wbits > 13 || pbits > 30) return false;
+  const int pbits = e.sbits + e.cbits;
+  if (har < 2 || pbits > 30 || !e.rel[pl.head_rel].dense) return false;
+  // window: the dense indexes of one (sample, col 0) prefix, dn^(har-2) * dnp
+  const uint64_t dn = (uint64_t)e.max_id + 1;
+  uint64_t wkeys = (dn + 31) / 32 * 32;
+  for (int c = 2; c < har; ++c) wkeys *= dn;
+  if (wkeys > 8192) return false;
   RelState& D = e.rel[pl.driver_rel];
   if (D.full.n == 0) return false;
   const size_t groups = (size_t)1 << pbits;
@@ -236,8 +259,8 @@ bool row_windows(Engine& e, const Plan& pl, RowWindows* rw) {
   }
   rw->goff = D.goff.as<uint32_t>();
   rw->ngroups = groups;
-  rw->wbits = wbits;
-  rw->from = e.cfg.rows == 2 ? 0 : (uint64_t)std::min(groups, D.full.n) * ((uint64_t)1 << wbits) / 8;
+  rw->wkeys = (uint32_t)wkeys;
+  rw->from = e.cfg.rows == 2 ? 0 : (uint64_t)std::min(groups, D.full.n) * wkeys / 8;
   return true;
 }
 
@@ -406,11 +429,11 @@ size_t absorb_dense(Engine& e, int r) {
   const size_t nseg = R.nseg;
   R.nseg = 0;
   // touched counts per bitmap block -> positions of the new / changed tuples
-  const size_t nb = dense_count_blocks(R.dense_w);
+  const size_t nb = dense_count_blocks(R.dense_keys);
   e.grow(e.flags, nb * 4);
   e.grow(e.pos, (nb + 1) * 4);
   DenseArgs d = dense_args(e, R);
-  bitmap_block_counts(d.touched, R.dense_w, e.flags.as<uint32_t>(), st);
+  bitmap_block_counts(d.touched, R.dense_keys, e.flags.as<uint32_t>(), st);
   scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, S_UNIQUE, true);
   if (e.record && nseg) {
     e.grow(e.lpos, (nseg + 1) * 4);
@@ -433,7 +456,7 @@ size_t absorb_dense(Engine& e, int r) {
   const uint32_t base = e.next_id;
   if (e.lineage) e.grow(e.tag_by_id, ((size_t)base + U) * 4, true, (size_t)base * 4);
   d = dense_args(e, R);
-  dense_finalize<K>(d, R.dense_w, e.pos.as<uint32_t>(), R.recent.keys.as<K>(), rtags, base,
+  dense_finalize<K>(d, R.dense_keys, e.pos.as<uint32_t>(), R.recent.keys.as<K>(), rtags, base,
                     e.lineage ? e.tag_by_id.as<float>() : nullptr, st);
   if (e.lineage) {
     e.grow(R.recent.ids, U * 4 + 4);
@@ -696,11 +719,11 @@ void enqueue_graph_round(Engine& e, int r, const std::vector<const Plan*>& plans
                          st, rows ? &rw : nullptr);
   }
   const DenseArgs d = dense_args(e, R);
-  const size_t nb = dense_count_blocks(R.dense_w);
-  bitmap_block_counts(d.touched, R.dense_w, e.flags.as<uint32_t>(), st);
+  const size_t nb = dense_count_blocks(R.dense_keys);
+  bitmap_block_counts(d.touched, R.dense_keys, e.flags.as<uint32_t>(), st);
   scan_u32(e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, total_slot(e, S_UNIQUE), true, e.scratch.as<uint64_t>(),
            st);
-  dense_finalize<K>(d, R.dense_w, e.pos.as<uint32_t>(), R.recent.keys.as<K>(),
+  dense_finalize<K>(d, R.dense_keys, e.pos.as<uint32_t>(), R.recent.keys.as<K>(),
                     e.tag_kind == TAG_F32 ? R.recent.tags.as<float>() : nullptr, 0, nullptr, st);
   DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 32 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
 }
@@ -713,10 +736,10 @@ int graph_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
   RelState& R = e.rel[r];
   const int ar = e.prog.rels[r].arity;
   // every buffer the body touches at its final size, before capture
-  const size_t keys = (size_t)1 << R.dense_w;
+  const size_t keys = R.dense_keys;
   e.grow(R.recent.keys, keys * sizeof(K) + 8, true, R.recent.n * sizeof(K));
   if (e.tag_kind == TAG_F32) e.grow(R.recent.tags, keys * 4 + 8, true, R.recent.n * 4);
-  size_t words = scan_scratch_words(dense_count_blocks(R.dense_w));
+  size_t words = scan_scratch_words(dense_count_blocks(R.dense_keys));
   for (const Plan* tw : plans) {
     const size_t n = e.rel[tw->driver_rel].full.n;
     e.grow(e.counts, n * 4 + 4);
@@ -726,7 +749,7 @@ int graph_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
     e.grow(e.idx[tw->steps[0].index].off, (((size_t)1 << (e.sbits + spec.w * e.cbits)) + 1) * 4);
   }
   ensure_scratch(e, words);
-  const size_t nb = dense_count_blocks(R.dense_w);
+  const size_t nb = dense_count_blocks(R.dense_keys);
   e.grow(e.flags, nb * 4);
   e.grow(e.pos, (nb + 1) * 4);
   e.sync();

@@ -30,6 +30,48 @@ uint32_t dense_init_word(int mode) {
 
 static int norm_items(int items) { return items == 1 || items == 2 || items == 8 ? items : 4; }
 
+// Packed key -> dense index (mixed radix, see DenseArgs) and back.  Dense
+// domains hold fewer than 2^32 keys.
+template <typename K>
+__device__ __forceinline__ uint32_t dense_index(const DenseArgs& d, K key) {
+  const uint64_t k = (uint64_t)key;
+  const uint32_t mask = (1u << d.dcbits) - 1u;
+  uint32_t idx = (uint32_t)(k >> (d.dcols * d.dcbits));  // sample
+  for (int c = 0; c + 1 < d.dcols; ++c) idx = idx * d.dn + ((uint32_t)(k >> ((d.dcols - 1 - c) * d.dcbits)) & mask);
+  return idx * d.dnp + ((uint32_t)k & mask);
+}
+
+static void divisor(uint32_t dv, uint32_t* m, uint8_t* s1, uint8_t* s2) {
+  int l = 0;
+  while (l < 32 && ((uint64_t)1 << l) < dv) ++l;  // l = ceil(log2 dv)
+  *m = (uint32_t)(((((uint64_t)1 << l) - dv) << 32) / dv + 1);
+  *s1 = (uint8_t)(l < 1 ? l : 1);
+  *s2 = (uint8_t)(l > 1 ? l - 1 : 0);
+}
+
+void dense_divisors(DenseArgs& d) {
+  divisor(d.dn, &d.dn_m, &d.dn_s1, &d.dn_s2);
+  divisor(d.dnp, &d.dnp_m, &d.dnp_s1, &d.dnp_s2);
+}
+
+__device__ __forceinline__ uint32_t fast_div(uint32_t n, uint32_t m, uint32_t s1, uint32_t s2) {
+  const uint32_t t = __umulhi(n, m);
+  return (t + ((n - t) >> s1)) >> s2;
+}
+
+template <typename K>
+__device__ __forceinline__ K dense_key(const DenseArgs& d, uint32_t idx) {
+  uint32_t q = fast_div(idx, d.dnp_m, d.dnp_s1, d.dnp_s2);
+  uint64_t k = idx - q * d.dnp;
+  idx = q;
+  for (int c = 1; c < d.dcols; ++c) {
+    q = fast_div(idx, d.dn_m, d.dn_s1, d.dn_s2);
+    k |= (uint64_t)(idx - q * d.dn) << (c * d.dcbits);
+    idx = q;
+  }
+  return (K)(k | ((uint64_t)idx << (d.dcols * d.dcbits)));
+}
+
 size_t dense_segments(size_t n, int items) {
   const size_t tile = (size_t)BLOCK * norm_items(items);
   return (n + tile - 1) / tile * NWAVES;
@@ -51,7 +93,7 @@ template <typename K>
 __device__ __forceinline__ DenseProbe dense_load(const DenseArgs& d, bool act, K key) {
   DenseProbe pr;
   if (act) {
-    const uint64_t kk = (uint64_t)key;
+    const uint32_t kk = dense_index(d, key);
     pr.pw = d.present[kk >> 5];
     pr.tw = d.touched[kk >> 5];
     if (d.mode == DENSE_MAX || d.mode == DENSE_MIN) pr.cur = d.dtag[kk];
@@ -71,7 +113,7 @@ __device__ __forceinline__ void dense_apply(const DenseArgs& d, WaveSeg& ws, siz
                                             uint32_t l, uint32_t r, bool lineage, const DenseProbe& pr) {
   bool keep = false, logit = false;
   if (act) {
-    const uint64_t kk = (uint64_t)key;
+    const uint32_t kk = dense_index(d, key);
     const size_t w = kk >> 5;
     const uint32_t bit = 1u << (kk & 31);
     const bool present = (pr.pw & bit) != 0u;
@@ -223,15 +265,15 @@ __global__ __launch_bounds__(BLOCK) void k_join_expand_dense(JoinArgs a, const u
 
 // Row-window variant for static-driven joins whose head key starts with the
 // driver's (sample, first column) prefix p: all derivations of the driver
-// rows with prefix p land in the window of head keys [p << wbits, (p + 1) <<
-// wbits).  One workgroup owns one window at a time: it loads the window's
-// presence bits and tags into LDS, folds every derivation of the group there
-// with LDS atomics (duplicates across the group's driver rows meet in LDS),
-// and writes back only the entries it changed, with plain coalesced stores
-// (no other workgroup of the launch touches the window).  This trades one
-// streaming pass over the windows for scattered global atomics and pays off
-// when the launch has many derivations per window; the host sets the
-// threshold `from` and both variants test the device-side total.
+// rows with prefix p land in one window of the head's dense indexes (the
+// keys with that prefix).  One workgroup owns one window at a time: it loads
+// the window's presence bits and tags into LDS, folds every derivation of the
+// group there with LDS atomics (duplicates across the group's driver rows
+// meet in LDS), and writes back only the entries it changed, with plain
+// coalesced stores (no other workgroup of the launch touches the window).
+// This trades one streaming pass over the windows for scattered global
+// atomics and pays off when the launch has many derivations per window; the
+// host sets the threshold `from` and both variants test the device-side total.
 constexpr int RW_BITS = 13;  // largest window: 8192 keys (32 KB of tags)
 constexpr int RW_KEYS = 1 << RW_BITS;
 constexpr int RW_ROWS = 256;   // driver rows of a group staged in LDS
@@ -258,7 +300,8 @@ __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const
   const K* ik = (const K*)a.ikeys;
   const T* dt = (const T*)a.dtags;
   const T* it = (const T*)a.itags;
-  const uint32_t W = 1u << rw.wbits, NWD = (W + 31) / 32;
+  const uint32_t W = rw.wkeys, NWD = W / 32;
+  const uint32_t pmask = (1u << d.dcbits) - 1u;
   for (size_t g = blockIdx.x; g < rw.ngroups; g += gridDim.x) {  // uniform per block
     const uint32_t r0 = rw.goff[g], r1 = rw.goff[g + 1];
     if (r0 == r1) continue;
@@ -266,7 +309,8 @@ __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const
     if (s0 == s1) continue;
     const uint32_t nr = r1 - r0;
     const bool lds_rows = nr <= (uint32_t)RW_ROWS;  // else rows are read from global memory
-    const uint64_t kb = (uint64_t)g << rw.wbits;
+    // window of the prefix (sample, col 0): dense indexes kb .. kb + W - 1
+    const uint64_t kb = ((uint64_t)(g >> d.dcbits) * d.dn + ((uint32_t)g & pmask)) * W;
     const size_t wb = kb >> 5;
     for (uint32_t i = threadIdx.x; i < NWD; i += RW_BLOCK) {
       s_pres[i] = d.present[wb + i];
@@ -338,7 +382,11 @@ __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const
           const int s = a.osrc[c];
           v[c] = s >= 0 ? key_col(dkey[q], s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
         }
-        const uint64_t lk = (uint64_t)key_make<K>(key_sample(dkey[q], a.dlay), v, a.olay) - kb;
+        // offset in the window of the prefix (sample, v[0]): the remaining
+        // columns in mixed radix (dn per middle column, dnp for the last)
+        uint32_t lk = 0;
+        for (int c = 1; c + 1 < a.olay.ncols; ++c) lk = lk * d.dn + v[c];
+        lk = lk * d.dnp + v[a.olay.ncols - 1];
         if (lk >= W) {  // the host only picks this kernel when every key lies in its window
           if (d.overflow) *d.overflow = 2;
           continue;
@@ -400,7 +448,8 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   const double per = (sizeof(K) + tb + lin + 4.0 + tb);
   const double bytes = (dtotal ? 0.0 : total * per) + a.n * (sizeof(K) + tb + lin + 4.0);
   // row windows: both variants are launched and each checks the total
-  const bool rows = rw && !lineage && rw->wbits <= RW_BITS && (dtotal || total >= rw->from);
+  const bool rows = rw && !lineage && rw->wkeys <= (uint32_t)RW_KEYS && rw->wkeys % 32 == 0 &&
+                    (dtotal || total >= rw->from);
   const uint64_t skip_at = rows ? rw->from : ~0ull;
   const unsigned nrb = rows ? (unsigned)(rw->ngroups < 2048 ? rw->ngroups : 2048) : 0u;
 #define DL_DEXPAND(IT)                                                                                               \
@@ -472,11 +521,11 @@ void project_dense(const JoinArgs& a, int tk, const DenseArgs& d, bool lineage, 
 // lanes write consecutive keys whatever the bit density (wave_expand_bits).
 // dense_finalize also makes the touched tuples present, clears touched,
 // clamps frozen sums and, with lineage, hands out ids in key order.
-constexpr int BM_ITEMS = 8;
+constexpr int BM_ITEMS = 2;
 constexpr int BM_TILE = BLOCK * BM_ITEMS;
 constexpr int BM_WAVE_WORDS = WAVE * BM_ITEMS;
 
-size_t dense_count_blocks(int w) { return (bitmap_words(w) + BM_TILE - 1) / BM_TILE; }
+size_t dense_count_blocks(size_t keys) { return (bitmap_words(keys) + BM_TILE - 1) / BM_TILE; }
 
 __global__ void k_acc_total(const uint64_t* __restrict__ src, uint64_t* __restrict__ acc) { *acc += *src; }
 
@@ -498,10 +547,10 @@ __global__ __launch_bounds__(BLOCK) void k_block_counts(const uint32_t* __restri
   if (threadIdx.x == 0) partial[blockIdx.x] = tmp[0] + tmp[1] + tmp[2] + tmp[3];
 }
 
-void bitmap_block_counts(const uint32_t* bits, int w, uint32_t* partial, hipStream_t st) {
-  const size_t words = bitmap_words(w);
+void bitmap_block_counts(const uint32_t* bits, size_t keys, uint32_t* partial, hipStream_t st) {
+  const size_t words = bitmap_words(keys);
   DL_PROF_BEGIN(6, st);
-  k_block_counts<<<dense_count_blocks(w), BLOCK, 0, st>>>(bits, words, partial);
+  k_block_counts<<<dense_count_blocks(keys), BLOCK, 0, st>>>(bits, words, partial);
   DL_PROF_END(6, st, words * 4.0);
 }
 
@@ -521,12 +570,12 @@ __device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t n) {
 }
 
 // The set bits of 64 words, word wbase + lane in each lane, become slots
-// base, base + 1, ... in key order: f(slot, key) runs with consecutive
-// lanes on consecutive slots (source lane by a binary search over the wave's
-// inclusive popcount scan, bit by rank select).  Called by the whole wave;
-// returns the number of bits.
+// base, base + 1, ... in index order: f(slot, index, aux, bit) runs with
+// consecutive lanes on consecutive slots (source lane by a binary search over
+// the wave's inclusive popcount scan, bit by rank select); aux is the source
+// lane's `aux` value.  Called by the whole wave; returns the number of bits.
 template <typename F>
-__device__ __forceinline__ uint32_t wave_expand_bits(uint32_t x, uint64_t wbase, uint32_t base, F&& f) {
+__device__ __forceinline__ uint32_t wave_expand_bits(uint32_t x, uint64_t wbase, uint32_t base, uint64_t aux, F&& f) {
   const uint32_t cnt = (uint32_t)__popc(x);
   const uint32_t incl = wave_inclusive_scan(cnt);
   const uint32_t excl = incl - cnt;
@@ -541,7 +590,10 @@ __device__ __forceinline__ uint32_t wave_expand_bits(uint32_t x, uint64_t wbase,
     }
     const uint32_t word = __shfl(x, src, WAVE);
     const uint32_t before = __shfl(excl, src, WAVE);
-    if (j < total) f(base + j, ((wbase + (uint64_t)src) << 5) | select_bit(word, j - before));
+    const uint64_t ax = ((uint64_t)(uint32_t)__shfl((uint32_t)(aux >> 32), src, WAVE) << 32) |
+                        (uint32_t)__shfl((uint32_t)aux, src, WAVE);
+    const uint32_t bit = select_bit(word, j - before);
+    if (j < total) f(base + j, ((wbase + (uint64_t)src) << 5) | bit, ax, bit);
   }
   return total;
 }
@@ -576,8 +628,11 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
       d.present[wb + lane] |= x;
       d.touched[wb + lane] = 0u;
     }
-    o += wave_expand_bits(x, wb, o, [&](uint32_t slot, uint64_t kk) {
-      keys[slot] = (K)kk;
+    // a word's 32 indexes share all columns but the last (dnp is a multiple
+    // of 32): one index-to-key conversion per word, the bit adds to the key
+    const uint64_t kbase = x ? (uint64_t)dense_key<K>(d, (uint32_t)((wb + lane) << 5)) : 0ull;
+    o += wave_expand_bits(x, wb, o, kbase, [&](uint32_t slot, uint64_t kk, uint64_t kb, uint32_t bit) {
+      keys[slot] = (K)(kb + bit);
       float t = 1.0f;
       if (d.mode == DENSE_ADD) {
         t = fminf(1.0f, __uint_as_float(d.dtag[kk]));
@@ -595,17 +650,17 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
 }
 
 template <typename K>
-void dense_finalize(const DenseArgs& d, int w, const uint32_t* bpos, K* keys, float* rtags, uint32_t id_base,
+void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* bpos, K* keys, float* rtags, uint32_t id_base,
                     float* tag_by_id, hipStream_t st) {
-  const size_t words = bitmap_words(w);
+  const size_t words = bitmap_words(nkeys);
   DL_PROF_BEGIN(6, st);
-  k_dense_finalize<K><<<dense_count_blocks(w), BLOCK, 0, st>>>(d, words, bpos, keys, rtags, id_base, tag_by_id);
+  k_dense_finalize<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, bpos, keys, rtags, id_base, tag_by_id);
   DL_PROF_END(6, st, words * 12.0);
 }
 
 template <typename K>
 __global__ void k_dense_owners(DenseArgs d, const K* __restrict__ keys, size_t n, uint32_t* __restrict__ owner) {
-  GRID_STRIDE(i, n) owner[i] = d.did[(uint64_t)keys[i]];
+  GRID_STRIDE(i, n) owner[i] = d.did[dense_index(d, keys[i])];
 }
 
 template <typename K>
@@ -636,7 +691,7 @@ void segments_compact(const void* in, const uint32_t* cnt, const uint32_t* pos, 
   DL_PROF_END(8, st, nseg * 8.0);
 }
 
-size_t bitmap_words(int w) { return w >= 5 ? (size_t)1 << (w - 5) : 1; }
+size_t bitmap_words(size_t keys) { return (keys + 31) / 32; }
 
 // Sorted keys of the present bits (one block per BM_TILE words, block
 // offsets from bitmap_block_counts + scan), with their tags and ids.
@@ -665,8 +720,10 @@ __global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words
   for (int i = 0; i < BM_ITEMS; ++i) {
     const uint32_t x = b[i];
     if (!__ballot(x != 0u)) continue;
-    o += wave_expand_bits(x, w0 + (size_t)i * WAVE, o, [&](uint32_t slot, uint64_t kk) {
-      keys[slot] = (K)kk;
+    const size_t wb = w0 + (size_t)i * WAVE;
+    const uint64_t kbase = x ? (uint64_t)dense_key<K>(d, (uint32_t)((wb + lane) << 5)) : 0ull;
+    o += wave_expand_bits(x, wb, o, kbase, [&](uint32_t slot, uint64_t kk, uint64_t kb, uint32_t bit) {
+      keys[slot] = (K)(kb + bit);
       if (tags) {
         const uint32_t v = d.dtag[kk];
         tags[slot] = d.mode == DENSE_ADD ? __uint_as_float(v) : d.mode == DENSE_BOOL ? 1.0f : from_ordered(v);
@@ -677,10 +734,11 @@ __global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words
 }
 
 template <typename K>
-void bitmap_keys(const DenseArgs& d, int w, const uint32_t* bpos, K* keys, float* tags, uint32_t* ids, hipStream_t st) {
-  const size_t words = bitmap_words(w);
+void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* bpos, K* keys, float* tags, uint32_t* ids,
+                 hipStream_t st) {
+  const size_t words = bitmap_words(nkeys);
   DL_PROF_BEGIN(6, st);
-  k_bitmap_keys<K><<<dense_count_blocks(w), BLOCK, 0, st>>>(d, words, bpos, keys, tags, ids);
+  k_bitmap_keys<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, bpos, keys, tags, ids);
   DL_PROF_END(6, st, words * 4.0);
 }
 
@@ -688,9 +746,9 @@ void bitmap_keys(const DenseArgs& d, int w, const uint32_t* bpos, K* keys, float
   template void join_expand_dense<K>(const JoinArgs&, int, const uint32_t*, size_t, const uint64_t*, size_t,     \
                                      const DenseArgs&, bool, hipStream_t, const RowWindows*);                                                \
   template void project_dense<K>(const JoinArgs&, int, const DenseArgs&, bool, hipStream_t);                        \
-  template void dense_finalize<K>(const DenseArgs&, int, const uint32_t*, K*, float*, uint32_t, float*, hipStream_t);       \
+  template void dense_finalize<K>(const DenseArgs&, size_t, const uint32_t*, K*, float*, uint32_t, float*, hipStream_t);    \
   template void dense_owners<K>(const DenseArgs&, const K*, size_t, uint32_t*, hipStream_t);                                  \
-  template void bitmap_keys<K>(const DenseArgs&, int, const uint32_t*, K*, float*, uint32_t*, hipStream_t);
+  template void bitmap_keys<K>(const DenseArgs&, size_t, const uint32_t*, K*, float*, uint32_t*, hipStream_t);
 
 INST(uint32_t)
 INST(uint64_t)

@@ -109,7 +109,20 @@ struct DenseArgs {
   uint32_t seg_base;   // first segment of this launch
   uint64_t* overflow;  // set to 1 when a device-side total exceeds the 32-bit offsets
   int mode;
+  // Dense index of a packed key: mixed radix over (sample, col 0, ..., col
+  // last) with dn ids per column and the last column padded to dnp (a
+  // multiple of 32), so the keys of one (sample, col 0) prefix form a
+  // word-aligned window.  Order-preserving: index order is key order.
+  uint32_t dn, dnp;
+  int dcols, dcbits;   // relation arity, bits per column of the packed key
+  // division by dn and dnp through multiply-high and shifts (Granlund and
+  // Montgomery, division by invariant integers): q = (t + ((n - t) >> s1))
+  // >> s2 with t = mulhi(n, m), exact for every 32-bit n
+  uint32_t dn_m, dnp_m;
+  uint8_t dn_s1, dn_s2, dnp_s1, dnp_s2;
 };
+// Fills the multiply-high constants of DenseArgs for its dn and dnp.
+void dense_divisors(DenseArgs& d);
 constexpr int DENSE_SEG = 512;  // slots per wave segment (64 lanes x up to 8 rows)
 // Segments a dense emission over n slots with `items` outputs per thread uses.
 size_t dense_segments(size_t n, int items);
@@ -129,12 +142,13 @@ void join_expand(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t t
 // upper bound max_total for the grid) and `total` is ignored.
 // Row windows of a static-driven join whose head keys start with the
 // driver's (sample, first column) prefix: goff is the CSR of the driver rows
-// over that prefix (ngroups prefixes), a head window holds 2^wbits keys
-// (wbits <= 13), and launches with at least `from` derivations use them.
+// over the packed prefix (ngroups prefixes), the head keys of a prefix fill a
+// window of wkeys dense indexes (a multiple of 32, at most 8192), and
+// launches with at least `from` derivations use them.
 struct RowWindows {
   const uint32_t* goff;
   size_t ngroups;
-  int wbits;
+  uint32_t wkeys;
   uint64_t from;
 };
 template <typename K>
@@ -147,14 +161,14 @@ template <typename K>
 void project_dense(const JoinArgs& a, int tag_kind, const DenseArgs& d, bool lineage, hipStream_t st);
 // Pass 1 of a bitmap compaction: set-bit count of every block of a bitmap of
 // 2^w bits (dense_count_blocks(w) entries).
-size_t dense_count_blocks(int w);
-void bitmap_block_counts(const uint32_t* bits, int w, uint32_t* partial, hipStream_t st);
+size_t dense_count_blocks(size_t keys);
+void bitmap_block_counts(const uint32_t* bits, size_t keys, uint32_t* partial, hipStream_t st);
 // Pass 2 (bpos = exclusive scan of those counts): write the touched keys in
 // ascending order with their tags (rtags may be NULL), make them present,
 // clear touched, clamp frozen sums and, with lineage, assign ids base.. in
 // key order and record tags by id.
 template <typename K>
-void dense_finalize(const DenseArgs& d, int w, const uint32_t* bpos, K* keys, float* rtags, uint32_t id_base,
+void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* bpos, K* keys, float* rtags, uint32_t id_base,
                     float* tag_by_id, hipStream_t st);
 // owner[i] = did[keys[i]]
 template <typename K>
@@ -162,9 +176,10 @@ void dense_owners(const DenseArgs& d, const K* keys, size_t n, uint32_t* owner, 
 // Sorted keys of the set bits of the presence bitmap (2^w bits; bpos =
 // exclusive scan of its block counts), tags and ids gathered from the dense
 // arrays (either may be NULL).
-size_t bitmap_words(int w);
+size_t bitmap_words(size_t keys);
 template <typename K>
-void bitmap_keys(const DenseArgs& d, int w, const uint32_t* bpos, K* keys, float* tags, uint32_t* ids, hipStream_t st);
+void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* bpos, K* keys, float* tags, uint32_t* ids,
+                 hipStream_t st);
 // Gather nseg wave segments (counts, pos = exclusive scan of counts) of
 // `bytes`-wide elements into a contiguous array.
 void segments_compact(const void* in, const uint32_t* counts, const uint32_t* pos, size_t nseg, size_t bytes,
