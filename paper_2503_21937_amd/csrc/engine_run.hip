@@ -41,9 +41,9 @@ void sort_pairs(Engine& e, K** kp, uint32_t** vp, size_t n, int bits) {
   radix_sort<K>(kp, vp, &ka, &va, n, bits, e.scratch.as<uint64_t>(), e.stream);
 }
 
-void scan(Engine& e, const uint32_t* in, uint32_t* out, size_t n, int slot, bool sentinel) {
+void scan(Engine& e, const uint32_t* in, uint32_t* out, size_t n, int slot, bool sentinel, uint64_t* acc = nullptr) {
   ensure_scratch(e, scan_scratch_words(n));
-  scan_u32(in, out, n, total_slot(e, slot), sentinel, e.scratch.as<uint64_t>(), e.stream);
+  scan_u32(in, out, n, total_slot(e, slot), sentinel, e.scratch.as<uint64_t>(), e.stream, acc);
 }
 
 // If a sort left its result in the engine's alternate buffer, move the
@@ -157,7 +157,7 @@ void materialize_full(Engine& e, RelState& R) {
     e.grow(R.full.ids, F * 4 + 8);
     ids = R.full.ids.as<uint32_t>();
   }
-  bitmap_keys<K>(dense_args(e, R), R.dense_keys, e.pos.as<uint32_t>(), R.full.keys.as<K>(), tags, ids, e.stream);
+  bitmap_keys<K>(dense_args(e, R), R.dense_keys, e.flags.as<uint32_t>(), R.full.keys.as<K>(), tags, ids, e.stream);
   R.full.n = F;
   ++R.version;
 }
@@ -374,15 +374,18 @@ void run_plan(Engine& e, const Plan& pl) {
     e.grow(e.counts, cur.n * 4 + 4);
     e.grow(e.offs, (cur.n + 1) * 4);
     join_count<K>(a, e.counts.as<uint32_t>(), e.stream);
-    scan(e, e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), cur.n, S_SCAN, true);
-    if (si + 1 == pl.steps.size() && H.dense && !e.record) {
+    const bool nosync = si + 1 == pl.steps.size() && H.dense && !e.record;
+    // without a host readback the scan also adds its total to the run's
+    // candidate count (collected at round end)
+    scan(e, e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), cur.n, S_SCAN, true,
+         nosync ? total_slot(e, S_CAND) : nullptr);
+    if (nosync) {
       // no host readback: the expand reads the total on the device; the
       // candidate count and any 32-bit overflow are collected at round end
       const IndexState& ixs = e.idx[step.index];
       const size_t in = std::max<size_t>(ixs.t.n, 1);
       const size_t bound = cur.n > ((size_t)1 << 40) / in ? ((size_t)1 << 40) : cur.n * in;
       const DenseArgs d = dense_room(0, a.items);
-      accumulate_total(total_slot(e, S_SCAN), total_slot(e, S_CAND), e.stream);
       RowWindows rw{};
       const bool rows = e.cfg.rows && row_windows<K>(e, pl, &rw);
       join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), 0, total_slot(e, S_SCAN), bound, d, false,
@@ -434,6 +437,25 @@ size_t absorb_dense(Engine& e, int r) {
   e.grow(e.pos, (nb + 1) * 4);
   DenseArgs d = dense_args(e, R);
   bitmap_block_counts(d.touched, R.dense_keys, e.flags.as<uint32_t>(), st);
+  if (!e.lineage && R.dense_keys * (sizeof(K) + 4) <= ((size_t)1 << 30)) {
+    // recent sized for the whole domain: compact first, read the count after
+    // (one host sync per relation and round)
+    e.grow(R.recent.keys, R.dense_keys * sizeof(K) + 8);
+    if (e.tag_kind == TAG_F32) e.grow(R.recent.tags, R.dense_keys * 4 + 8);
+    dense_finalize<K>(d, R.dense_keys, e.flags.as<uint32_t>(), R.recent.keys.as<K>(),
+                      e.tag_kind == TAG_F32 ? R.recent.tags.as<float>() : nullptr, 0, nullptr, total_slot(e, S_UNIQUE),
+                      st);
+    e.read_totals();
+    check_overflow(e);
+    const size_t U = e.host[S_UNIQUE];
+    R.recent.n = U;
+    if (U == 0) return 0;
+    e.stats.unique += U;
+    ++R.version;
+    ++R.rversion;
+    if (R.own_index) materialize_full<K>(e, R);
+    return U;
+  }
   scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, S_UNIQUE, true);
   if (e.record && nseg) {
     e.grow(e.lpos, (nseg + 1) * 4);
@@ -456,8 +478,8 @@ size_t absorb_dense(Engine& e, int r) {
   const uint32_t base = e.next_id;
   if (e.lineage) e.grow(e.tag_by_id, ((size_t)base + U) * 4, true, (size_t)base * 4);
   d = dense_args(e, R);
-  dense_finalize<K>(d, R.dense_keys, e.pos.as<uint32_t>(), R.recent.keys.as<K>(), rtags, base,
-                    e.lineage ? e.tag_by_id.as<float>() : nullptr, st);
+  dense_finalize<K>(d, R.dense_keys, e.flags.as<uint32_t>(), R.recent.keys.as<K>(), rtags, base,
+                    e.lineage ? e.tag_by_id.as<float>() : nullptr, nullptr, st);
   if (e.lineage) {
     e.grow(R.recent.ids, U * 4 + 4);
     iota_u32(R.recent.ids.as<uint32_t>(), U, base, st);
@@ -710,8 +732,7 @@ void enqueue_graph_round(Engine& e, int r, const std::vector<const Plan*>& plans
     const JoinArgs a = graph_join_args<K>(e, *tw, R, ar);
     join_count<K>(a, e.counts.as<uint32_t>(), st);
     scan_u32(e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), a.n, total_slot(e, S_SCAN), true,
-             e.scratch.as<uint64_t>(), st);
-    accumulate_total(total_slot(e, S_SCAN), total_slot(e, S_CAND), st);
+             e.scratch.as<uint64_t>(), st, total_slot(e, S_CAND));
     DenseArgs d = dense_args(e, R);
     RowWindows rw{};
     const bool rows = e.cfg.rows && row_windows<K>(e, *tw, &rw);
@@ -719,12 +740,10 @@ void enqueue_graph_round(Engine& e, int r, const std::vector<const Plan*>& plans
                          st, rows ? &rw : nullptr);
   }
   const DenseArgs d = dense_args(e, R);
-  const size_t nb = dense_count_blocks(R.dense_keys);
   bitmap_block_counts(d.touched, R.dense_keys, e.flags.as<uint32_t>(), st);
-  scan_u32(e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, total_slot(e, S_UNIQUE), true, e.scratch.as<uint64_t>(),
-           st);
-  dense_finalize<K>(d, R.dense_keys, e.pos.as<uint32_t>(), R.recent.keys.as<K>(),
-                    e.tag_kind == TAG_F32 ? R.recent.tags.as<float>() : nullptr, 0, nullptr, st);
+  dense_finalize<K>(d, R.dense_keys, e.flags.as<uint32_t>(), R.recent.keys.as<K>(),
+                    e.tag_kind == TAG_F32 ? R.recent.tags.as<float>() : nullptr, 0, nullptr, total_slot(e, S_UNIQUE),
+                    st);
   DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 32 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
 }
 
@@ -734,7 +753,6 @@ template <typename K>
 int graph_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& plans) {
   const int r = st.rels[0];
   RelState& R = e.rel[r];
-  const int ar = e.prog.rels[r].arity;
   // every buffer the body touches at its final size, before capture
   const size_t keys = R.dense_keys;
   e.grow(R.recent.keys, keys * sizeof(K) + 8, true, R.recent.n * sizeof(K));
@@ -747,6 +765,8 @@ int graph_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
     words = std::max(words, scan_scratch_words(n));
     const IndexSpec& spec = e.prog.indexes[tw->steps[0].index];
     e.grow(e.idx[tw->steps[0].index].off, (((size_t)1 << (e.sbits + spec.w * e.cbits)) + 1) * 4);
+    RowWindows rw{};
+    if (e.cfg.rows) (void)row_windows<K>(e, *tw, &rw);  // builds the driver's prefix CSR outside the graph
   }
   ensure_scratch(e, words);
   const size_t nb = dense_count_blocks(R.dense_keys);

@@ -527,10 +527,6 @@ constexpr int BM_WAVE_WORDS = WAVE * BM_ITEMS;
 
 size_t dense_count_blocks(size_t keys) { return (bitmap_words(keys) + BM_TILE - 1) / BM_TILE; }
 
-__global__ void k_acc_total(const uint64_t* __restrict__ src, uint64_t* __restrict__ acc) { *acc += *src; }
-
-void accumulate_total(const uint64_t* src, uint64_t* acc, hipStream_t st) { k_acc_total<<<1, 1, 0, st>>>(src, acc); }
-
 __global__ __launch_bounds__(BLOCK) void k_block_counts(const uint32_t* __restrict__ bits, size_t words,
                                                         uint32_t* __restrict__ partial) {
   __shared__ uint32_t tmp[NWAVES];
@@ -598,11 +594,40 @@ __device__ __forceinline__ uint32_t wave_expand_bits(uint32_t x, uint64_t wbase,
   return total;
 }
 
+// The block's first output slot: the sum of the earlier blocks' counts (from
+// bitmap_block_counts), reduced by the block itself instead of a separate scan
+// launch; the last block also writes the grand total.  Every wave of the block
+// must call it (one barrier).
+__device__ __forceinline__ uint32_t block_first_slot(const uint32_t* __restrict__ counts, uint32_t own_wave_count,
+                                                     uint32_t* s_tot, uint32_t* s_pre, uint64_t* d_total) {
+  const int lane = lane_id(), wv = threadIdx.x / WAVE;
+  uint32_t pre = 0;
+  for (size_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) pre += counts[i];
+  pre = wave_sum(pre);
+  if (lane == 0) {
+    s_tot[wv] = own_wave_count;
+    s_pre[wv] = pre;
+  }
+  __syncthreads();
+  uint32_t o = 0, all = 0;
+  for (int i = 0; i < NWAVES; ++i) {
+    o += s_pre[i] + (i < wv ? s_tot[i] : 0u);
+    all += s_tot[i];
+  }
+  if (d_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    uint32_t p = 0;
+    for (int i = 0; i < NWAVES; ++i) p += s_pre[i];
+    *d_total = (uint64_t)p + all;
+  }
+  return o;
+}
+
 template <typename K>
-__global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t words, const uint32_t* __restrict__ bpos,
+__global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t words, const uint32_t* __restrict__ counts,
                                                           K* __restrict__ keys, float* __restrict__ rtags,
-                                                          uint32_t id_base, float* __restrict__ tag_by_id) {
-  __shared__ uint32_t s_tot[NWAVES];
+                                                          uint32_t id_base, float* __restrict__ tag_by_id,
+                                                          uint64_t* __restrict__ d_total) {
+  __shared__ uint32_t s_tot[NWAVES], s_pre[NWAVES];
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
   uint32_t b[BM_ITEMS];  // the lane's words, loaded together
@@ -614,11 +639,8 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
     c += (uint32_t)__popc(b[i]);
   }
   c = wave_sum(c);
-  if (lane == 0) s_tot[wv] = c;
-  __syncthreads();
+  uint32_t o = block_first_slot(counts, c, s_tot, s_pre, d_total);
   if (c == 0) return;  // wave-uniform; no barrier follows
-  uint32_t o = bpos[blockIdx.x];
-  for (int i = 0; i < wv; ++i) o += s_tot[i];
 #pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
     const uint32_t x = b[i];
@@ -650,11 +672,12 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
 }
 
 template <typename K>
-void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* bpos, K* keys, float* rtags, uint32_t id_base,
-                    float* tag_by_id, hipStream_t st) {
+void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* rtags, uint32_t id_base,
+                    float* tag_by_id, uint64_t* d_total, hipStream_t st) {
   const size_t words = bitmap_words(nkeys);
   DL_PROF_BEGIN(6, st);
-  k_dense_finalize<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, bpos, keys, rtags, id_base, tag_by_id);
+  k_dense_finalize<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, counts, keys, rtags, id_base, tag_by_id,
+                                                                   d_total);
   DL_PROF_END(6, st, words * 12.0);
 }
 
@@ -696,10 +719,10 @@ size_t bitmap_words(size_t keys) { return (keys + 31) / 32; }
 // Sorted keys of the present bits (one block per BM_TILE words, block
 // offsets from bitmap_block_counts + scan), with their tags and ids.
 template <typename K>
-__global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words, const uint32_t* __restrict__ bpos,
+__global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words, const uint32_t* __restrict__ counts,
                                                        K* __restrict__ keys, float* __restrict__ tags,
                                                        uint32_t* __restrict__ ids) {
-  __shared__ uint32_t s_tot[NWAVES];
+  __shared__ uint32_t s_tot[NWAVES], s_pre[NWAVES];
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
   uint32_t b[BM_ITEMS];
@@ -711,11 +734,8 @@ __global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words
     c += (uint32_t)__popc(b[i]);
   }
   c = wave_sum(c);
-  if (lane == 0) s_tot[wv] = c;
-  __syncthreads();
+  uint32_t o = block_first_slot(counts, c, s_tot, s_pre, nullptr);
   if (c == 0) return;  // wave-uniform; no barrier follows
-  uint32_t o = bpos[blockIdx.x];
-  for (int i = 0; i < wv; ++i) o += s_tot[i];
 #pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
     const uint32_t x = b[i];
@@ -734,11 +754,11 @@ __global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words
 }
 
 template <typename K>
-void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* bpos, K* keys, float* tags, uint32_t* ids,
+void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* tags, uint32_t* ids,
                  hipStream_t st) {
   const size_t words = bitmap_words(nkeys);
   DL_PROF_BEGIN(6, st);
-  k_bitmap_keys<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, bpos, keys, tags, ids);
+  k_bitmap_keys<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, counts, keys, tags, ids);
   DL_PROF_END(6, st, words * 4.0);
 }
 
@@ -746,7 +766,8 @@ void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* bpos, K* keys
   template void join_expand_dense<K>(const JoinArgs&, int, const uint32_t*, size_t, const uint64_t*, size_t,     \
                                      const DenseArgs&, bool, hipStream_t, const RowWindows*);                                                \
   template void project_dense<K>(const JoinArgs&, int, const DenseArgs&, bool, hipStream_t);                        \
-  template void dense_finalize<K>(const DenseArgs&, size_t, const uint32_t*, K*, float*, uint32_t, float*, hipStream_t);    \
+  template void dense_finalize<K>(const DenseArgs&, size_t, const uint32_t*, K*, float*, uint32_t, float*, uint64_t*,        \
+                                  hipStream_t);                                                                             \
   template void dense_owners<K>(const DenseArgs&, const K*, size_t, uint32_t*, hipStream_t);                                  \
   template void bitmap_keys<K>(const DenseArgs&, size_t, const uint32_t*, K*, float*, uint32_t*, hipStream_t);
 

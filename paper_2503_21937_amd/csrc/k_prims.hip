@@ -34,7 +34,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t* __restric
 
 // One block scans the partials (exclusive, in place), looping with a carry.
 __global__ __launch_bounds__(BLOCK) void k_scan_partials(uint64_t* __restrict__ partial, size_t nb,
-                                                         uint64_t* __restrict__ d_total) {
+                                                         uint64_t* __restrict__ d_total, uint64_t* __restrict__ acc) {
   __shared__ uint64_t tmp[NWAVES];
   uint64_t carry = 0;
   for (size_t b0 = 0; b0 < nb; b0 += BLOCK) {
@@ -45,7 +45,10 @@ __global__ __launch_bounds__(BLOCK) void k_scan_partials(uint64_t* __restrict__ 
     if (i < nb) partial[i] = carry + ex;
     carry += tot;
   }
-  if (threadIdx.x == 0) *d_total = carry;
+  if (threadIdx.x == 0) {
+    *d_total = carry;
+    if (acc) *acc += carry;
+  }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
@@ -72,7 +75,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t* __restrict_
 
 // Whole scan in one workgroup when n <= SCAN_TILE (one launch instead of three).
 __global__ __launch_bounds__(BLOCK) void k_scan_small(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                                                      size_t n, uint64_t* __restrict__ d_total, int sentinel) {
+                                                      size_t n, uint64_t* __restrict__ d_total, int sentinel,
+                                                      uint64_t* __restrict__ acc) {
   __shared__ uint64_t tmp[NWAVES];
   const size_t base = (size_t)threadIdx.x * SCAN_ITEMS;
   uint32_t v[SCAN_ITEMS];
@@ -92,6 +96,46 @@ __global__ __launch_bounds__(BLOCK) void k_scan_small(const uint32_t* __restrict
   if (threadIdx.x == 0) {
     *d_total = tot;
     if (sentinel) out[n] = (uint32_t)tot;
+    if (acc) *acc += tot;
+  }
+}
+
+// Down-sweep that finds its block's carry itself: the sum of the partials of
+// the blocks before it (nb small), so the partials need no scan launch; the
+// last block publishes the total (and the sentinel, and the accumulation).
+constexpr size_t SCAN_FUSED_MAX_BLOCKS = 2048;
+
+__global__ __launch_bounds__(BLOCK) void k_scan_down_carry(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                           size_t n, const uint64_t* __restrict__ partial,
+                                                           uint64_t* __restrict__ d_total, int sentinel,
+                                                           uint64_t* __restrict__ acc) {
+  __shared__ uint64_t tmp[NWAVES], s_pre[NWAVES];
+  uint64_t pre = 0;
+  for (size_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) pre += partial[i];
+  pre = wave_sum(pre);
+  if (lane_id() == 0) s_pre[threadIdx.x / WAVE] = pre;
+  const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS];
+  uint64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0u;
+    s += v[i];
+  }
+  uint64_t tot;
+  const uint64_t ex = block_exclusive_scan(s, tmp, &tot);  // its barriers also publish s_pre
+  const uint64_t carry = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3];
+  uint64_t run = carry + ex;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = (uint32_t)run;
+    run += v[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    const uint64_t total = carry + tot;
+    *d_total = total;
+    if (sentinel) out[n] = (uint32_t)total;
+    if (acc) *acc += total;
   }
 }
 
@@ -101,7 +145,7 @@ __global__ void k_empty_scan(uint32_t* out, uint64_t* d_total, int sentinel) {
 }
 
 void scan_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* d_total, bool sentinel, uint64_t* scratch,
-              hipStream_t st) {
+              hipStream_t st, uint64_t* acc) {
   if (n == 0) {
     k_empty_scan<<<1, 1, 0, st>>>(out, d_total, sentinel ? 1 : 0);
     return;
@@ -109,12 +153,17 @@ void scan_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* d_total, bo
   size_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
   DL_PROF_BEGIN(4, st);
   if (nb == 1) {
-    k_scan_small<<<1, BLOCK, 0, st>>>(in, out, n, d_total, sentinel ? 1 : 0);
+    k_scan_small<<<1, BLOCK, 0, st>>>(in, out, n, d_total, sentinel ? 1 : 0, acc);
     DL_PROF_END(4, st, n * 8.0);
     return;
   }
   k_scan_reduce<<<nb, BLOCK, 0, st>>>(in, n, scratch);
-  k_scan_partials<<<1, BLOCK, 0, st>>>(scratch, nb, d_total);
+  if (nb <= SCAN_FUSED_MAX_BLOCKS) {  // two launches instead of three
+    k_scan_down_carry<<<nb, BLOCK, 0, st>>>(in, out, n, scratch, d_total, sentinel ? 1 : 0, acc);
+    DL_PROF_END(4, st, n * 8.0);
+    return;
+  }
+  k_scan_partials<<<1, BLOCK, 0, st>>>(scratch, nb, d_total, acc);
   k_scan_down<<<nb, BLOCK, 0, st>>>(in, out, n, scratch, d_total, sentinel ? 1 : 0);
   DL_PROF_END(4, st, n * 8.0);
 }

@@ -13,9 +13,11 @@ struct TopK;
 // Scratch words a scan of n values needs (u64 units).
 size_t scan_scratch_words(size_t n);
 // Exclusive prefix sum of n u32 counts (in may equal out).  The 64-bit total
-// goes to *d_total; if `sentinel`, out[n] receives the (truncated) total.
+// goes to *d_total; if `sentinel`, out[n] receives the (truncated) total; if
+// `acc`, the total is also added to *acc.
 void scan_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* d_total, bool sentinel,
-              uint64_t* scratch, hipStream_t st);
+              uint64_t* scratch, hipStream_t st,
+              uint64_t* acc = nullptr);
 
 // Stable LSD radix sort of (key, value) pairs on the low `key_bits` bits.
 // Sorted data ends in (*keys, *vals); the alternates are used as ping-pong
@@ -155,30 +157,28 @@ template <typename K>
 void join_expand_dense(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t total, const uint64_t* dtotal,
                        size_t max_total, const DenseArgs& d, bool lineage, hipStream_t st,
                        const RowWindows* rw = nullptr);
-// *acc += *src (device words)
-void accumulate_total(const uint64_t* src, uint64_t* acc, hipStream_t st);
 template <typename K>
 void project_dense(const JoinArgs& a, int tag_kind, const DenseArgs& d, bool lineage, hipStream_t st);
 // Pass 1 of a bitmap compaction: set-bit count of every block of a bitmap of
 // 2^w bits (dense_count_blocks(w) entries).
 size_t dense_count_blocks(size_t keys);
 void bitmap_block_counts(const uint32_t* bits, size_t keys, uint32_t* partial, hipStream_t st);
-// Pass 2 (bpos = exclusive scan of those counts): write the touched keys in
-// ascending order with their tags (rtags may be NULL), make them present,
-// clear touched, clamp frozen sums and, with lineage, assign ids base.. in
-// key order and record tags by id.
+// Pass 2 (counts = those block counts; every block sums the ones before it):
+// write the touched keys in ascending order with their tags (rtags may be
+// NULL), make them present, clear touched, clamp frozen sums and, with
+// lineage, assign ids base.. in key order and record tags by id.  The number
+// of keys goes to *d_total when d_total is not NULL.
 template <typename K>
-void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* bpos, K* keys, float* rtags, uint32_t id_base,
-                    float* tag_by_id, hipStream_t st);
+void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* rtags, uint32_t id_base,
+                    float* tag_by_id, uint64_t* d_total, hipStream_t st);
 // owner[i] = did[keys[i]]
 template <typename K>
 void dense_owners(const DenseArgs& d, const K* keys, size_t n, uint32_t* owner, hipStream_t st);
-// Sorted keys of the set bits of the presence bitmap (2^w bits; bpos =
-// exclusive scan of its block counts), tags and ids gathered from the dense
-// arrays (either may be NULL).
+// Sorted keys of the set bits of the presence bitmap (counts = its block
+// counts), tags and ids gathered from the dense arrays (either may be NULL).
 size_t bitmap_words(size_t keys);
 template <typename K>
-void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* bpos, K* keys, float* tags, uint32_t* ids,
+void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* tags, uint32_t* ids,
                  hipStream_t st);
 // Gather nseg wave segments (counts, pos = exclusive scan of counts) of
 // `bytes`-wide elements into a contiguous array.
