@@ -144,6 +144,7 @@ struct Engine {
   DevBuf dtotal;             // device words for totals
 
   dl_stats stats{};
+  uint64_t deferred_units = 0;  // derivations of joins whose totals stayed on the device (last run)
   uint32_t prof_mask = 0;
   dl_kernel_timing kstats[DL_K_FAMILIES]{};
   size_t device_bytes = 0;

@@ -29,7 +29,7 @@ struct ProfScope {
     g_prof = nullptr;
     on = false;
     e.sync();
-    p.resolve();
+    if (p.deferred_fam >= 0) e.kstats[p.deferred_fam].bytes += p.deferred_per * (double)e.deferred_units;
     for (auto& r : p.recs) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;

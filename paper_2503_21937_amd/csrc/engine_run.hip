@@ -970,6 +970,7 @@ void run_fixpoint(Engine& e) {
     if (e.prog.rels[r].derived) e.stats.derived += e.rel[r].full.n;
   e.read_totals();
   e.stats.candidates += e.host[S_CAND];
+  e.deferred_units = e.host[S_CAND];
   e.stats.lineage_mode = !e.lineage ? 0 : e.record ? 1 : 2;
 }
 

@@ -471,7 +471,7 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   }
 #undef DL_DEXPAND
   DL_PROF_END(1, st, bytes);
-  if (dtotal) DL_PROF_DEFER(1, st, dtotal, per);
+  if (dtotal) DL_PROF_DEFER(1, per);
 }
 
 constexpr int PX_ITEMS = 4;  // projection: rows per thread (fixed tile)

@@ -404,12 +404,6 @@ void status_flags(const uint32_t* status, size_t n, uint32_t mask, uint32_t* fla
   if (n) k_status_flags<<<grid_for(n), BLOCK, 0, st>>>(status, n, mask, flags);
 }
 
-__global__ void k_copy_word(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *dst = *src;
-}
-
-void copy_word(const uint64_t* src, uint64_t* dst, hipStream_t st) { k_copy_word<<<1, 64, 0, st>>>(src, dst); }
-
 __global__ void k_range_flags(const uint32_t* __restrict__ ids, size_t n, uint32_t lo, uint32_t hi,
                               uint32_t* __restrict__ flags) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {

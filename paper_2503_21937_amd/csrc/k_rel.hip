@@ -84,18 +84,65 @@ __global__ void k_csr(const K* __restrict__ keys, size_t n_h, const uint64_t* __
   }
 }
 
+// Small domains: one wave per prefix, a 64-ary search (each step the lanes
+// probe evenly spaced keys and a ballot narrows the range 64-fold), so the
+// latency is ~log64(n) dependent loads instead of log2(n) -- the per-prefix
+// searches of a small domain are too few to hide a long chain.
+template <typename K>
+__global__ __launch_bounds__(BLOCK) void k_csr_wave(const K* __restrict__ keys, size_t n_h,
+                                                    const uint64_t* __restrict__ dn, int shift, uint64_t domain,
+                                                    uint32_t* __restrict__ off) {
+  const size_t n = dn ? (size_t)*dn : n_h;
+  const size_t lane = (size_t)lane_id();
+  for (uint64_t v = ((size_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE; v <= domain;
+       v += (size_t)gridDim.x * NWAVES) {  // uniform per wave
+    size_t lo = 0, hi = n;  // first row with prefix >= v lies in [lo, hi]
+    while (hi - lo > (size_t)WAVE) {
+      const size_t step = (hi - lo + WAVE - 1) / WAVE;
+      const size_t pos = lo + lane * step;
+      const bool below = pos < hi && ((uint64_t)keys[pos] >> shift) < v;
+      const uint32_t cnt = (uint32_t)__popcll(ballot(below));  // `below` holds on a prefix of the lanes
+      if (cnt == 0) {
+        hi = lo;
+        break;
+      }
+      const size_t nlo = lo + (cnt - 1) * step + 1, nhi = lo + cnt * step;
+      lo = nlo;
+      hi = nhi < hi ? nhi : hi;
+    }
+    const size_t pos = lo + lane;
+    const bool below = pos < hi && ((uint64_t)keys[pos] >> shift) < v;
+    const size_t r = lo + (size_t)__popcll(ballot(below));
+    if (lane == 0) off[v] = (uint32_t)r;
+  }
+}
+
+constexpr uint64_t CSR_WAVE_DOMAIN = 1ull << 16;  // up to here a wave per prefix
+
+template <typename K>
+static void csr_launch(const K* keys, size_t n, const uint64_t* dn, int shift, uint64_t domain, uint32_t* off,
+                       hipStream_t st) {
+  if (domain < CSR_WAVE_DOMAIN) {
+    const size_t waves = domain + 1;
+    const size_t blocks = (waves + NWAVES - 1) / NWAVES;
+    k_csr_wave<K><<<(unsigned)(blocks < 8192 ? blocks : 8192), BLOCK, 0, st>>>(keys, n, dn, shift, domain, off);
+  } else {
+    k_csr<K><<<grid_for(domain + 1), BLOCK, 0, st>>>(keys, n, dn, shift, domain, off);
+  }
+}
+
 template <typename K>
 void csr_build(const K* keys, size_t n, int total_bits, int prefix_bits, uint32_t* off, hipStream_t st) {
   uint64_t domain = 1ull << prefix_bits;
   DL_PROF_BEGIN(9, st);
-  k_csr<K><<<grid_for(domain + 1), BLOCK, 0, st>>>(keys, n, nullptr, total_bits - prefix_bits, domain, off);
+  csr_launch<K>(keys, n, nullptr, total_bits - prefix_bits, domain, off, st);
   DL_PROF_END(9, st, (domain + 1) * 4.0 + (double)n * sizeof(K));
 }
 
 template <typename K>
 void csr_build_dn(const K* keys, const uint64_t* dn, int total_bits, int prefix_bits, uint32_t* off, hipStream_t st) {
   uint64_t domain = 1ull << prefix_bits;
-  k_csr<K><<<grid_for(domain + 1), BLOCK, 0, st>>>(keys, 0, dn, total_bits - prefix_bits, domain, off);
+  csr_launch<K>(keys, 0, dn, total_bits - prefix_bits, domain, off, st);
 }
 
 // ------------------------------------------------------------------ joins

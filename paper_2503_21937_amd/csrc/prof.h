@@ -10,24 +10,21 @@
 
 namespace dlfix {
 
-// Copies *src to *dst on the stream (a one-thread kernel; k_prims.hip).
-void copy_word(const uint64_t* src, uint64_t* dst, hipStream_t st);
-
 struct Profiler {
   struct Rec {
     hipEvent_t a, b;
     int fam;
     double bytes;
-    double per_unit;  // bytes per unit of a count known only on the device
-    int slot;         // its copy in `counts` (-1: none)
   };
-  static constexpr int MAX_DEFERRED = 1 << 16;
   uint32_t mask = 0;
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
-  uint64_t* counts = nullptr;  // device copies of deferred counts
-  int ncounts = 0;
+  // Launches whose unit count only the device knows add `deferred_per`
+  // bytes per unit to family `deferred_fam`; the engine supplies the run's
+  // total of those units afterwards (it accumulates them on the device).
+  int deferred_fam = -1;
+  double deferred_per = 0.0;
   hipEvent_t get() {
     if (used == pool.size()) {
       hipEvent_t ev;
@@ -47,31 +44,15 @@ struct Profiler {
   void end(int fam, hipStream_t st, double bytes) {
     if (!(mask >> fam & 1u) || recs.empty() || recs.back().fam != fam) return;
     recs.back().bytes = bytes;
-    recs.back().per_unit = 0.0;
-    recs.back().slot = -1;
     (void)hipEventRecord(recs.back().b, st);
   }
-  // The last launch also moved per_unit bytes for each of *dcount units, a
-  // count that only the device knows: snapshot it after the launch.
-  void defer(int fam, hipStream_t st, const uint64_t* dcount, double per_unit) {
-    if (!(mask >> fam & 1u) || recs.empty() || recs.back().fam != fam) return;
-    if (!counts && hipMalloc((void**)&counts, MAX_DEFERRED * sizeof(uint64_t)) != hipSuccess) counts = nullptr;
-    if (!counts || ncounts == MAX_DEFERRED) return;
-    recs.back().per_unit = per_unit;
-    recs.back().slot = ncounts;
-    copy_word(dcount, counts + ncounts++, st);
-  }
-  // After the stream has drained: fold the deferred counts into the bytes.
-  void resolve() {
-    if (!ncounts) return;
-    std::vector<uint64_t> h(ncounts);
-    if (hipMemcpy(h.data(), counts, ncounts * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess) return;
-    for (Rec& r : recs)
-      if (r.slot >= 0) r.bytes += r.per_unit * (double)h[r.slot];
+  void defer(int fam, double per_unit) {
+    if (!(mask >> fam & 1u)) return;
+    deferred_fam = fam;
+    deferred_per = per_unit;
   }
   ~Profiler() {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-    if (counts) (void)hipFree(counts);
   }
 };
 
@@ -87,7 +68,7 @@ extern thread_local Profiler* g_prof;
   do {                               \
     if (::dlfix::g_prof) ::dlfix::g_prof->end((fam), (st), (double)(bytes)); \
   } while (0)
-#define DL_PROF_DEFER(fam, st, dcount, per_unit) \
-  do {                                            \
-    if (::dlfix::g_prof) ::dlfix::g_prof->defer((fam), (st), (dcount), (double)(per_unit)); \
+#define DL_PROF_DEFER(fam, per_unit) \
+  do {                                \
+    if (::dlfix::g_prof) ::dlfix::g_prof->defer((fam), (double)(per_unit)); \
   } while (0)
