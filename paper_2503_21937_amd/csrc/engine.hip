@@ -30,9 +30,13 @@ struct ProfScope {
     on = false;
     e.sync();
     if (p.deferred_fam >= 0) e.kstats[p.deferred_fam].bytes += p.deferred_per * (double)e.deferred_units;
+
     for (auto& r : p.recs) {
       float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+      if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+        (void)hipGetLastError();  // do not leave the error for the next caller
+        continue;
+      }
       dl_kernel_timing& k = e.kstats[r.fam];
       k.launches += 1;
       k.ms += ms;

@@ -22,7 +22,10 @@ namespace dlfix {
 
 namespace {
 
-enum Slot { S_SCAN = 0, S_UNIQUE = 1, S_NEW = 2, S_RECENT = 3, S_LIN = 4, S_OVF = 5, S_CAND = 6 };
+// Device words of totals (64 x u64): slots 0..6 below, 30 = id / sample
+// maxima at ingest, 32.. = round log of a graph batch (count, then totals).
+enum Slot { S_SCAN = 0, S_UNIQUE = 1, S_NEW = 2, S_RECENT = 3, S_LIN = 4, S_OVF = 5, S_CAND = 6, S_LOG = 32 };
+constexpr int GRAPH_ROUNDS = 4;  // round bodies per captured graph
 
 uint64_t* total_slot(Engine& e, int s) { return e.dtotal.as<uint64_t>() + s; }
 
@@ -661,18 +664,18 @@ size_t absorb_sorted(Engine& e, int r) {
   return Rn;
 }
 
-// ------------------------------------------------------ HIP-graph rounds
+// ------------------------------------------------ batched (graph) rounds
 // A stratum whose single relation uses the dense-domain path without lineage
 // and whose delta plans are all static-driven single joins against an
 // identity-ordered index over the recent tuples has a round body with only
 // device-side sizes: the recent index is rebuilt from the previous round's
 // count (a device word), the join reads its total on the device, the round
-// end compacts the touched bitmap.  Such a body is captured once per stratum
-// and replayed every round; the host reads back one block of counters per
-// round.
+// end compacts the touched bitmap.  Such bodies run several rounds per host
+// sync (as one captured HIP graph where allowed), the host reading back one
+// block of counters and the round log per batch.
 std::vector<const Plan*> graph_plans(Engine& e, const Stratum& st) {
   std::vector<const Plan*> out;
-  if (!e.cfg.graph || g_prof || e.lineage || st.rels.size() != 1 || st.delta_plans.empty()) return {};
+  if (e.lineage || st.rels.size() != 1 || st.delta_plans.empty()) return {};
   const int r = st.rels[0];
   if (!e.rel[r].dense || e.cfg.orient == 1) return {};
   for (int p : st.delta_plans) {
@@ -743,8 +746,7 @@ void enqueue_graph_round(Engine& e, int r, const std::vector<const Plan*>& plans
   bitmap_block_counts(d.touched, R.dense_keys, e.flags.as<uint32_t>(), st);
   dense_finalize<K>(d, R.dense_keys, e.flags.as<uint32_t>(), R.recent.keys.as<K>(),
                     e.tag_kind == TAG_F32 ? R.recent.tags.as<float>() : nullptr, 0, nullptr, total_slot(e, S_UNIQUE),
-                    st);
-  DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 32 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+                    st, total_slot(e, S_LOG));
 }
 
 // Rounds 2.. of an eligible stratum by graph replay; returns the number of
@@ -774,48 +776,63 @@ int graph_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
   e.grow(e.pos, (nb + 1) * 4);
   e.sync();
 
+  // Rounds go in batches of GRAPH_ROUNDS round bodies: the host syncs once
+  // per batch and reads each round's new-tuple count from the round log;
+  // rounds after the fixpoint in a batch find an empty recent relation and
+  // change nothing.  A batch is one captured HIP graph, or -- while kernels
+  // are timed (events inside graphs cannot be timed) or when capture is
+  // refused -- the same launches enqueued directly.
+  auto enqueue_batch = [&] {
+    fill_u32(reinterpret_cast<uint32_t*>(total_slot(e, S_LOG)), 2, 0u, e.stream);  // log entries = 0
+    for (int i = 0; i < GRAPH_ROUNDS; ++i) enqueue_graph_round<K>(e, r, plans);
+    DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, e.stream));
+  };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  if (hipStreamBeginCapture(e.stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
-    (void)hipGetLastError();
-    return 0;
-  }
-  try {
-    enqueue_graph_round<K>(e, r, plans);
-  } catch (...) {
-    (void)hipStreamEndCapture(e.stream, &graph);
+  auto release = [&] {
+    if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  };
+  if (e.cfg.graph && !g_prof && hipStreamBeginCapture(e.stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
+    bool ok = true;
+    try {
+      enqueue_batch();
+    } catch (...) {
+      ok = false;
+    }
+    if (hipStreamEndCapture(e.stream, &graph) != hipSuccess || !graph) ok = false;
+    if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
+    if (!ok) {
+      release();
+      (void)hipGetLastError();
+    }
+  } else {
     (void)hipGetLastError();
-    return 0;  // fall back to eager rounds
-  }
-  if (hipStreamEndCapture(e.stream, &graph) != hipSuccess || !graph) {
-    (void)hipGetLastError();
-    return 0;
-  }
-  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-    (void)hipGetLastError();
-    (void)hipGraphDestroy(graph);
-    return 0;
   }
   int rounds = 0;
-  for (;;) {
-    ++rounds;
-    DL_HIP(hipGraphLaunch(exec, e.stream));
+  bool done = false;
+  while (!done) {
+    if (exec) DL_HIP(hipGraphLaunch(exec, e.stream));
+    else enqueue_batch();
     e.sync();
     if (e.host[S_OVF]) {
-      (void)hipGraphExecDestroy(exec);
-      (void)hipGraphDestroy(graph);
+      release();
       check_overflow(e);
     }
-    const size_t U = e.host[S_UNIQUE];
-    R.recent.n = U;
-    ++R.version;
-    ++R.rversion;
-    e.stats.unique += U;
-    if (U == 0) break;
+    const uint64_t* log = e.host + S_LOG;
+    for (uint64_t i = 0; i < log[0] && !done; ++i) {
+      const size_t U = log[1 + i];
+      ++rounds;
+      ++R.version;
+      ++R.rversion;
+      e.stats.unique += U;
+      done = U == 0;
+    }
   }
-  (void)hipGraphExecDestroy(exec);
-  (void)hipGraphDestroy(graph);
+  R.recent.n = 0;
+  release();
   for (const Plan* tw : plans) e.idx[tw->steps[0].index].built = false;
   return rounds;
 }

@@ -599,7 +599,8 @@ __device__ __forceinline__ uint32_t wave_expand_bits(uint32_t x, uint64_t wbase,
 // launch; the last block also writes the grand total.  Every wave of the block
 // must call it (one barrier).
 __device__ __forceinline__ uint32_t block_first_slot(const uint32_t* __restrict__ counts, uint32_t own_wave_count,
-                                                     uint32_t* s_tot, uint32_t* s_pre, uint64_t* d_total) {
+                                                     uint32_t* s_tot, uint32_t* s_pre, uint64_t* d_total,
+                                                     uint64_t* log = nullptr) {
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   uint32_t pre = 0;
   for (size_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) pre += counts[i];
@@ -618,6 +619,7 @@ __device__ __forceinline__ uint32_t block_first_slot(const uint32_t* __restrict_
     uint32_t p = 0;
     for (int i = 0; i < NWAVES; ++i) p += s_pre[i];
     *d_total = (uint64_t)p + all;
+    if (log) log[1 + log[0]++] = (uint64_t)p + all;  // round log: count, then one total per round
   }
   return o;
 }
@@ -626,7 +628,7 @@ template <typename K>
 __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t words, const uint32_t* __restrict__ counts,
                                                           K* __restrict__ keys, float* __restrict__ rtags,
                                                           uint32_t id_base, float* __restrict__ tag_by_id,
-                                                          uint64_t* __restrict__ d_total) {
+                                                          uint64_t* __restrict__ d_total, uint64_t* __restrict__ log) {
   __shared__ uint32_t s_tot[NWAVES], s_pre[NWAVES];
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
@@ -639,7 +641,7 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
     c += (uint32_t)__popc(b[i]);
   }
   c = wave_sum(c);
-  uint32_t o = block_first_slot(counts, c, s_tot, s_pre, d_total);
+  uint32_t o = block_first_slot(counts, c, s_tot, s_pre, d_total, log);
   if (c == 0) return;  // wave-uniform; no barrier follows
 #pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
@@ -673,11 +675,11 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
 
 template <typename K>
 void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* rtags, uint32_t id_base,
-                    float* tag_by_id, uint64_t* d_total, hipStream_t st) {
+                    float* tag_by_id, uint64_t* d_total, hipStream_t st, uint64_t* log) {
   const size_t words = bitmap_words(nkeys);
   DL_PROF_BEGIN(6, st);
   k_dense_finalize<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, counts, keys, rtags, id_base, tag_by_id,
-                                                                   d_total);
+                                                                   d_total, log);
   DL_PROF_END(6, st, words * 12.0);
 }
 
@@ -767,7 +769,7 @@ void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* ke
                                      const DenseArgs&, bool, hipStream_t, const RowWindows*);                                                \
   template void project_dense<K>(const JoinArgs&, int, const DenseArgs&, bool, hipStream_t);                        \
   template void dense_finalize<K>(const DenseArgs&, size_t, const uint32_t*, K*, float*, uint32_t, float*, uint64_t*,        \
-                                  hipStream_t);                                                                             \
+                                  hipStream_t, uint64_t*);                                                                  \
   template void dense_owners<K>(const DenseArgs&, const K*, size_t, uint32_t*, hipStream_t);                                  \
   template void bitmap_keys<K>(const DenseArgs&, size_t, const uint32_t*, K*, float*, uint32_t*, hipStream_t);
 

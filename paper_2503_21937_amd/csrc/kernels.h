@@ -167,10 +167,11 @@ void bitmap_block_counts(const uint32_t* bits, size_t keys, uint32_t* partial, h
 // write the touched keys in ascending order with their tags (rtags may be
 // NULL), make them present, clear touched, clamp frozen sums and, with
 // lineage, assign ids base.. in key order and record tags by id.  The number
-// of keys goes to *d_total when d_total is not NULL.
+// of keys goes to *d_total when d_total is not NULL, and is appended to `log`
+// (log[0] = entries, then one per call) when log is not NULL.
 template <typename K>
 void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* rtags, uint32_t id_base,
-                    float* tag_by_id, uint64_t* d_total, hipStream_t st);
+                    float* tag_by_id, uint64_t* d_total, hipStream_t st, uint64_t* log = nullptr);
 // owner[i] = did[keys[i]]
 template <typename K>
 void dense_owners(const DenseArgs& d, const K* keys, size_t n, uint32_t* owner, hipStream_t st);
