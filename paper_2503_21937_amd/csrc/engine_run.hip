@@ -160,7 +160,7 @@ void materialize_full(Engine& e, RelState& R) {
     e.grow(R.full.ids, F * 4 + 8);
     ids = R.full.ids.as<uint32_t>();
   }
-  bitmap_keys<K>(dense_args(e, R), R.dense_keys, e.flags.as<uint32_t>(), R.full.keys.as<K>(), tags, ids, e.stream);
+  bitmap_keys<K>(dense_args(e, R), R.dense_keys, e.pos.as<uint32_t>(), true, R.full.keys.as<K>(), tags, ids, e.stream);
   R.full.n = F;
   ++R.version;
 }
@@ -445,9 +445,11 @@ size_t absorb_dense(Engine& e, int r) {
     // (one host sync per relation and round)
     e.grow(R.recent.keys, R.dense_keys * sizeof(K) + 8);
     if (e.tag_kind == TAG_F32) e.grow(R.recent.tags, R.dense_keys * 4 + 8);
-    dense_finalize<K>(d, R.dense_keys, e.flags.as<uint32_t>(), R.recent.keys.as<K>(),
+    const bool pre = nb > dense_self_prefix_blocks();
+    if (pre) scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, S_UNIQUE, true);
+    dense_finalize<K>(d, R.dense_keys, (pre ? e.pos : e.flags).as<uint32_t>(), R.recent.keys.as<K>(),
                       e.tag_kind == TAG_F32 ? R.recent.tags.as<float>() : nullptr, 0, nullptr, total_slot(e, S_UNIQUE),
-                      st);
+                      st, nullptr, pre);
     e.read_totals();
     check_overflow(e);
     const size_t U = e.host[S_UNIQUE];
@@ -481,8 +483,8 @@ size_t absorb_dense(Engine& e, int r) {
   const uint32_t base = e.next_id;
   if (e.lineage) e.grow(e.tag_by_id, ((size_t)base + U) * 4, true, (size_t)base * 4);
   d = dense_args(e, R);
-  dense_finalize<K>(d, R.dense_keys, e.flags.as<uint32_t>(), R.recent.keys.as<K>(), rtags, base,
-                    e.lineage ? e.tag_by_id.as<float>() : nullptr, nullptr, st);
+  dense_finalize<K>(d, R.dense_keys, e.pos.as<uint32_t>(), R.recent.keys.as<K>(), rtags, base,
+                    e.lineage ? e.tag_by_id.as<float>() : nullptr, nullptr, st, nullptr, true);
   if (e.lineage) {
     e.grow(R.recent.ids, U * 4 + 4);
     iota_u32(R.recent.ids.as<uint32_t>(), U, base, st);
@@ -494,12 +496,8 @@ size_t absorb_dense(Engine& e, int r) {
     e.grow(e.lin_l, (used + L) * 4 + 4, true, used * 4);
     e.grow(e.lin_r, (used + L) * 4 + 4, true, used * 4);
     if (L) {
-      e.grow(e.nkeys, L * sizeof(K) + 8);
-      const uint32_t* lc = R.seg_lcount.as<uint32_t>();
-      segments_compact(R.log_keys.p, lc, e.lpos.as<uint32_t>(), nseg, sizeof(K), e.nkeys.p, st);
-      segments_compact(R.log_l.p, lc, e.lpos.as<uint32_t>(), nseg, 4, e.lin_l.as<uint32_t>() + used, st);
-      segments_compact(R.log_r.p, lc, e.lpos.as<uint32_t>(), nseg, 4, e.lin_r.as<uint32_t>() + used, st);
-      dense_owners<K>(d, e.nkeys.as<K>(), L, e.lin_owner.as<uint32_t>() + used, st);
+      segments_lineage<K>(d, e.lpos.as<uint32_t>(), nseg, e.lin_owner.as<uint32_t>() + used,
+                          e.lin_l.as<uint32_t>() + used, e.lin_r.as<uint32_t>() + used, st);
     }
     e.lin_segs.push_back({used, L});
     e.lin_n = used + L;
@@ -744,9 +742,14 @@ void enqueue_graph_round(Engine& e, int r, const std::vector<const Plan*>& plans
   }
   const DenseArgs d = dense_args(e, R);
   bitmap_block_counts(d.touched, R.dense_keys, e.flags.as<uint32_t>(), st);
-  dense_finalize<K>(d, R.dense_keys, e.flags.as<uint32_t>(), R.recent.keys.as<K>(),
+  const size_t nb = dense_count_blocks(R.dense_keys);
+  const bool pre = nb > dense_self_prefix_blocks();
+  if (pre)
+    scan_u32(e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, total_slot(e, S_UNIQUE), true, e.scratch.as<uint64_t>(),
+             st);
+  dense_finalize<K>(d, R.dense_keys, (pre ? e.pos : e.flags).as<uint32_t>(), R.recent.keys.as<K>(),
                     e.tag_kind == TAG_F32 ? R.recent.tags.as<float>() : nullptr, 0, nullptr, total_slot(e, S_UNIQUE),
-                    st, total_slot(e, S_LOG));
+                    st, total_slot(e, S_LOG), pre);
 }
 
 // Rounds 2.. of an eligible stratum by graph replay; returns the number of

@@ -594,16 +594,25 @@ __device__ __forceinline__ uint32_t wave_expand_bits(uint32_t x, uint64_t wbase,
   return total;
 }
 
-// The block's first output slot: the sum of the earlier blocks' counts (from
-// bitmap_block_counts), reduced by the block itself instead of a separate scan
-// launch; the last block also writes the grand total.  Every wave of the block
-// must call it (one barrier).
-__device__ __forceinline__ uint32_t block_first_slot(const uint32_t* __restrict__ counts, uint32_t own_wave_count,
-                                                     uint32_t* s_tot, uint32_t* s_pre, uint64_t* d_total,
-                                                     uint64_t* log = nullptr) {
+// The block's first output slot.  `counts` holds the blocks' counts (from
+// bitmap_block_counts) and the block sums the earlier ones itself instead of
+// a separate scan launch -- or, with `prefixed`, counts already holds the
+// exclusive scan (large bitmaps: the per-block sums would grow quadratically).
+// The last block also writes the grand total.  Every wave of the block must
+// call it (one barrier).
+constexpr size_t BM_SELF_PREFIX_MAX = 2048;  // blocks up to which each block sums its own prefix
+size_t dense_self_prefix_blocks() { return BM_SELF_PREFIX_MAX; }
+
+__device__ __forceinline__ uint32_t block_first_slot(const uint32_t* __restrict__ counts, int prefixed,
+                                                     uint32_t own_wave_count, uint32_t* s_tot, uint32_t* s_pre,
+                                                     uint64_t* d_total, uint64_t* log = nullptr) {
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   uint32_t pre = 0;
-  for (size_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) pre += counts[i];
+  if (prefixed) {
+    if (threadIdx.x == 0) pre = counts[blockIdx.x];
+  } else {
+    for (size_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) pre += counts[i];
+  }
   pre = wave_sum(pre);
   if (lane == 0) {
     s_tot[wv] = own_wave_count;
@@ -628,7 +637,8 @@ template <typename K>
 __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t words, const uint32_t* __restrict__ counts,
                                                           K* __restrict__ keys, float* __restrict__ rtags,
                                                           uint32_t id_base, float* __restrict__ tag_by_id,
-                                                          uint64_t* __restrict__ d_total, uint64_t* __restrict__ log) {
+                                                          uint64_t* __restrict__ d_total, uint64_t* __restrict__ log,
+                                                          int prefixed) {
   __shared__ uint32_t s_tot[NWAVES], s_pre[NWAVES];
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
@@ -641,7 +651,7 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
     c += (uint32_t)__popc(b[i]);
   }
   c = wave_sum(c);
-  uint32_t o = block_first_slot(counts, c, s_tot, s_pre, d_total, log);
+  uint32_t o = block_first_slot(counts, prefixed, c, s_tot, s_pre, d_total, log);
   if (c == 0) return;  // wave-uniform; no barrier follows
 #pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
@@ -675,44 +685,40 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
 
 template <typename K>
 void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* rtags, uint32_t id_base,
-                    float* tag_by_id, uint64_t* d_total, hipStream_t st, uint64_t* log) {
+                    float* tag_by_id, uint64_t* d_total, hipStream_t st, uint64_t* log, bool prefixed) {
   const size_t words = bitmap_words(nkeys);
   DL_PROF_BEGIN(6, st);
   k_dense_finalize<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, counts, keys, rtags, id_base, tag_by_id,
-                                                                   d_total, log);
+                                                                   d_total, log, prefixed ? 1 : 0);
   DL_PROF_END(6, st, words * 12.0);
 }
 
+// One block per lineage segment: its entries go to their compacted position
+// as (owner id, left id, right id), the owner found through the dense id of
+// the logged head key (assigned by this round's dense_finalize).
 template <typename K>
-__global__ void k_dense_owners(DenseArgs d, const K* __restrict__ keys, size_t n, uint32_t* __restrict__ owner) {
-  GRID_STRIDE(i, n) owner[i] = d.did[dense_index(d, keys[i])];
-}
-
-template <typename K>
-void dense_owners(const DenseArgs& d, const K* keys, size_t n, uint32_t* owner, hipStream_t st) {
-  if (n) k_dense_owners<K><<<grid_for(n), BLOCK, 0, st>>>(d, keys, n, owner);
-}
-
-// One block per segment: copy its elements to their compacted position.
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_segments_compact(const T* __restrict__ in, const uint32_t* __restrict__ cnt,
-                                                            const uint32_t* __restrict__ pos, size_t nseg,
-                                                            T* __restrict__ out) {
+__global__ __launch_bounds__(BLOCK) void k_segments_lineage(DenseArgs d, const uint32_t* __restrict__ pos, size_t nseg,
+                                                            uint32_t* __restrict__ owner, uint32_t* __restrict__ l,
+                                                            uint32_t* __restrict__ r) {
+  const K* lk = reinterpret_cast<const K*>(d.log_keys);
   for (size_t s = blockIdx.x; s < nseg; s += gridDim.x) {
-    const uint32_t c = cnt[s], o = pos[s];
-    for (uint32_t i = threadIdx.x; i < c; i += BLOCK) out[o + i] = in[s * DENSE_SEG + i];
+    const uint32_t c = d.seg_lcount[s], o = pos[s];
+    for (uint32_t i = threadIdx.x; i < c; i += BLOCK) {
+      const size_t src = s * DENSE_SEG + i;
+      owner[o + i] = d.did[dense_index(d, lk[src])];
+      l[o + i] = d.log_l[src];
+      r[o + i] = d.log_r[src];
+    }
   }
 }
 
-void segments_compact(const void* in, const uint32_t* cnt, const uint32_t* pos, size_t nseg, size_t bytes, void* out,
+template <typename K>
+void segments_lineage(const DenseArgs& d, const uint32_t* pos, size_t nseg, uint32_t* owner, uint32_t* l, uint32_t* r,
                       hipStream_t st) {
   if (!nseg) return;
   const unsigned g = (unsigned)(nseg < 65536 ? nseg : 65536);
   DL_PROF_BEGIN(8, st);
-  if (bytes == 4)
-    k_segments_compact<uint32_t><<<g, BLOCK, 0, st>>>((const uint32_t*)in, cnt, pos, nseg, (uint32_t*)out);
-  else
-    k_segments_compact<uint64_t><<<g, BLOCK, 0, st>>>((const uint64_t*)in, cnt, pos, nseg, (uint64_t*)out);
+  k_segments_lineage<K><<<g, BLOCK, 0, st>>>(d, pos, nseg, owner, l, r);
   DL_PROF_END(8, st, nseg * 8.0);
 }
 
@@ -722,7 +728,7 @@ size_t bitmap_words(size_t keys) { return (keys + 31) / 32; }
 // offsets from bitmap_block_counts + scan), with their tags and ids.
 template <typename K>
 __global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words, const uint32_t* __restrict__ counts,
-                                                       K* __restrict__ keys, float* __restrict__ tags,
+                                                       int prefixed, K* __restrict__ keys, float* __restrict__ tags,
                                                        uint32_t* __restrict__ ids) {
   __shared__ uint32_t s_tot[NWAVES], s_pre[NWAVES];
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
@@ -736,7 +742,7 @@ __global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words
     c += (uint32_t)__popc(b[i]);
   }
   c = wave_sum(c);
-  uint32_t o = block_first_slot(counts, c, s_tot, s_pre, nullptr);
+  uint32_t o = block_first_slot(counts, prefixed, c, s_tot, s_pre, nullptr);
   if (c == 0) return;  // wave-uniform; no barrier follows
 #pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
@@ -756,11 +762,11 @@ __global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words
 }
 
 template <typename K>
-void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* tags, uint32_t* ids,
-                 hipStream_t st) {
+void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, bool prefixed, K* keys, float* tags,
+                 uint32_t* ids, hipStream_t st) {
   const size_t words = bitmap_words(nkeys);
   DL_PROF_BEGIN(6, st);
-  k_bitmap_keys<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, counts, keys, tags, ids);
+  k_bitmap_keys<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, counts, prefixed ? 1 : 0, keys, tags, ids);
   DL_PROF_END(6, st, words * 4.0);
 }
 
@@ -769,9 +775,10 @@ void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* ke
                                      const DenseArgs&, bool, hipStream_t, const RowWindows*);                                                \
   template void project_dense<K>(const JoinArgs&, int, const DenseArgs&, bool, hipStream_t);                        \
   template void dense_finalize<K>(const DenseArgs&, size_t, const uint32_t*, K*, float*, uint32_t, float*, uint64_t*,        \
-                                  hipStream_t, uint64_t*);                                                                  \
-  template void dense_owners<K>(const DenseArgs&, const K*, size_t, uint32_t*, hipStream_t);                                  \
-  template void bitmap_keys<K>(const DenseArgs&, size_t, const uint32_t*, K*, float*, uint32_t*, hipStream_t);
+                                  hipStream_t, uint64_t*, bool);                                                            \
+  template void segments_lineage<K>(const DenseArgs&, const uint32_t*, size_t, uint32_t*, uint32_t*, uint32_t*,            \
+                                    hipStream_t);                                                                          \
+  template void bitmap_keys<K>(const DenseArgs&, size_t, const uint32_t*, bool, K*, float*, uint32_t*, hipStream_t);
 
 INST(uint32_t)
 INST(uint64_t)

@@ -103,7 +103,7 @@ struct DenseArgs {
   uint32_t* did;       // per key: tuple id (lineage), written by dense_finalize
   // Lineage entries go to wave-private segments of DENSE_SEG slots: segment
   // s holds seg_lcount[s] entries at log_*[s * DENSE_SEG ...];
-  // segments_compact gathers them in segment order.
+  // segments_lineage gathers them in segment order.
   void* log_keys;      // lineage log (DENSE_ADD with lineage): key, left id, right id
   uint32_t* log_l;
   uint32_t* log_r;
@@ -159,11 +159,14 @@ void join_expand_dense(const JoinArgs& a, int tag_kind, const uint32_t* offs, si
                        const RowWindows* rw = nullptr);
 template <typename K>
 void project_dense(const JoinArgs& a, int tag_kind, const DenseArgs& d, bool lineage, hipStream_t st);
-// Pass 1 of a bitmap compaction: set-bit count of every block of a bitmap of
-// 2^w bits (dense_count_blocks(w) entries).
+// Pass 1 of a bitmap compaction: set-bit count of every block of a bitmap
+// over `keys` dense indexes (dense_count_blocks(keys) entries).
 size_t dense_count_blocks(size_t keys);
+size_t dense_self_prefix_blocks();
 void bitmap_block_counts(const uint32_t* bits, size_t keys, uint32_t* partial, hipStream_t st);
-// Pass 2 (counts = those block counts; every block sums the ones before it):
+// Pass 2 (counts = those block counts, every block summing the ones before
+// it; or, with `prefixed`, their exclusive scan -- for more than
+// dense_self_prefix_blocks() blocks):
 // write the touched keys in ascending order with their tags (rtags may be
 // NULL), make them present, clear touched, clamp frozen sums and, with
 // lineage, assign ids base.. in key order and record tags by id.  The number
@@ -171,20 +174,20 @@ void bitmap_block_counts(const uint32_t* bits, size_t keys, uint32_t* partial, h
 // (log[0] = entries, then one per call) when log is not NULL.
 template <typename K>
 void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* rtags, uint32_t id_base,
-                    float* tag_by_id, uint64_t* d_total, hipStream_t st, uint64_t* log = nullptr);
-// owner[i] = did[keys[i]]
+                    float* tag_by_id, uint64_t* d_total, hipStream_t st, uint64_t* log = nullptr,
+                    bool prefixed = false);
+// The round's lineage segments (d.seg_lcount entries each, pos = exclusive
+// scan of those counts) compacted into (owner id, left id, right id).
 template <typename K>
-void dense_owners(const DenseArgs& d, const K* keys, size_t n, uint32_t* owner, hipStream_t st);
-// Sorted keys of the set bits of the presence bitmap (counts = its block
-// counts), tags and ids gathered from the dense arrays (either may be NULL).
+void segments_lineage(const DenseArgs& d, const uint32_t* pos, size_t nseg, uint32_t* owner, uint32_t* l, uint32_t* r,
+                      hipStream_t st);
+// Sorted keys of the set bits of the presence bitmap (counts and prefixed as
+// for dense_finalize), tags and ids gathered from the dense arrays (either
+// may be NULL).
 size_t bitmap_words(size_t keys);
 template <typename K>
-void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* tags, uint32_t* ids,
-                 hipStream_t st);
-// Gather nseg wave segments (counts, pos = exclusive scan of counts) of
-// `bytes`-wide elements into a contiguous array.
-void segments_compact(const void* in, const uint32_t* counts, const uint32_t* pos, size_t nseg, size_t bytes,
-                      void* out, hipStream_t st);
+void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, bool prefixed, K* keys, float* tags,
+                 uint32_t* ids, hipStream_t st);
 // Single-atom rule: re-pack driver columns as head columns, copy tags.
 template <typename K>
 void project_rows(const JoinArgs& a, int tag_kind, void* okeys, void* otags, uint32_t* olin_l, uint32_t* olin_r,
