@@ -401,7 +401,10 @@ void run_plan(Engine& e, const Plan& pl) {
     const bool last = si + 1 == pl.steps.size();
     if (last && H.dense) {
       const DenseArgs d = dense_room(total, a.items);
-      join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), total, nullptr, total, d, e.record, e.stream);
+      RowWindows rw{};
+      const bool rows = e.cfg.rows && row_windows<K>(e, pl, &rw);
+      join_expand_dense<K>(a, e.tag_kind, e.offs.as<uint32_t>(), total, nullptr, total, d, e.record, e.stream,
+                           rows ? &rw : nullptr);
       return;
     }
     void *ok, *ot;

@@ -282,7 +282,7 @@ constexpr int RW_BLOCK = 512;  // 8 waves: the window's LDS is shared by more wa
 template <typename K, int TK, int RX_ITEMS>
 __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const uint32_t* __restrict__ offs,
                                                                size_t total_h, const uint64_t* __restrict__ dtotal,
-                                                               DenseArgs d, RowWindows rw) {
+                                                               DenseArgs d, RowWindows rw, int lineage) {
   using T = typename TagOf<TK>::T;
   constexpr int TILE = RW_BLOCK * RX_ITEMS;
   __shared__ uint32_t s_tag[TK == TAG_F32 ? RW_KEYS : 1];
@@ -294,6 +294,7 @@ __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const
   __shared__ uint32_t s_ibase[RW_ROWS];
   __shared__ K s_dkey[RW_ROWS];
   __shared__ float s_dtag[TK == TAG_F32 ? RW_ROWS : 1];
+  __shared__ uint32_t s_did[RW_ROWS];  // lineage: driver row ids
   const size_t total = dtotal ? (size_t)*dtotal : total_h;
   if (total < rw.from || total > 0xffffffffull) return;  // scattered kernel's launch (or overflow, reported there)
   const K* dk = (const K*)a.dkeys;
@@ -333,6 +334,7 @@ __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const
           s_dkey[i] = key;
           s_ibase[i] = a.off[join_prefix(key, a)] - o;
           if constexpr (TK == TAG_F32) s_dtag[i] = dt[r0 + i];
+          if (lineage) s_did[i] = a.dids[r0 + i];
         }
       }
     }
@@ -375,45 +377,78 @@ __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const
       }
 #pragma unroll
       for (int q = 0; q < RX_ITEMS; ++q) {
-        if (!act[q]) continue;
-        const K ikey = ik[irow[q]];
-        uint32_t v[4];
-        for (int c = 0; c < a.olay.ncols; ++c) {
-          const int s = a.osrc[c];
-          v[c] = s >= 0 ? key_col(dkey[q], s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
-        }
-        // offset in the window of the prefix (sample, v[0]): the remaining
-        // columns in mixed radix (dn per middle column, dnp for the last)
-        uint32_t lk = 0;
-        for (int c = 1; c + 1 < a.olay.ncols; ++c) lk = lk * d.dn + v[c];
-        lk = lk * d.dnp + v[a.olay.ncols - 1];
-        if (lk >= W) {  // the host only picks this kernel when every key lies in its window
-          if (d.overflow) *d.overflow = 2;
-          continue;
-        }
-        const uint32_t loc = (uint32_t)lk;
-        const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
-        const bool present = (s_pres[wi] & bit) != 0u;
-        bool mark = false;
-        if constexpr (TK == TAG_F32) {
-          const float y = it[irow[q]];
-          const float t = a.index_first ? f_otimes(a.sr, y, x[q]) : f_otimes(a.sr, x[q], y);
-          if (d.mode == DENSE_ADD) {
-            if (!present) {
-              atomicAdd(reinterpret_cast<float*>(s_tag) + loc, t);
-              mark = true;
-            }
-          } else if (d.mode == DENSE_MAX) {
-            const uint32_t o = to_ordered(t);
-            mark = (o > s_tag[loc] && o > atomicMax(s_tag + loc, o)) || !present;
-          } else {
-            const uint32_t o = to_ordered(t);
-            mark = (o < s_tag[loc] && o < atomicMin(s_tag + loc, o)) || !present;
+        if (t0 + (uint32_t)(q * RW_BLOCK) >= s1) break;  // uniform across the block
+        bool logit = false;
+        K okey = 0;
+        if (act[q]) {
+          const K ikey = ik[irow[q]];
+          uint32_t v[4];
+          for (int c = 0; c < a.olay.ncols; ++c) {
+            const int s = a.osrc[c];
+            v[c] = s >= 0 ? key_col(dkey[q], s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
           }
-        } else {
-          mark = !present;
+          // offset in the window of the prefix (sample, v[0]): the remaining
+          // columns in mixed radix (dn per middle column, dnp for the last)
+          uint32_t lk = 0;
+          for (int c = 1; c + 1 < a.olay.ncols; ++c) lk = lk * d.dn + v[c];
+          lk = lk * d.dnp + v[a.olay.ncols - 1];
+          if (lk >= W) {  // the host only picks this kernel when every key lies in its window
+            if (d.overflow) *d.overflow = 2;
+          } else {
+            const uint32_t loc = lk;
+            const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
+            const bool present = (s_pres[wi] & bit) != 0u;
+            bool mark = false;
+            if constexpr (TK == TAG_F32) {
+              const float y = it[irow[q]];
+              const float t = a.index_first ? f_otimes(a.sr, y, x[q]) : f_otimes(a.sr, x[q], y);
+              if (d.mode == DENSE_ADD) {
+                if (!present) {
+                  atomicAdd(reinterpret_cast<float*>(s_tag) + loc, t);
+                  mark = true;
+                  logit = lineage != 0;
+                }
+              } else if (d.mode == DENSE_MAX) {
+                const uint32_t o = to_ordered(t);
+                mark = (o > s_tag[loc] && o > atomicMax(s_tag + loc, o)) || !present;
+              } else {
+                const uint32_t o = to_ordered(t);
+                mark = (o < s_tag[loc] && o < atomicMin(s_tag + loc, o)) || !present;
+              }
+            } else {
+              mark = !present;
+            }
+            if (mark && !(s_new[wi] & bit)) atomicOr(s_new + wi, bit);
+            if (logit) okey = key_make<K>(key_sample(dkey[q], a.dlay), v, a.olay);
+          }
         }
-        if (mark && !(s_new[wi] & bit)) atomicOr(s_new + wi, bit);
+        if (lineage) {
+          // discovery derivations go to the segment of their output slot
+          // (DENSE_SEG slots each); a wave's 64 consecutive slots touch at most
+          // two segments, each claimed with one atomic add
+          const uint32_t j = t0 + (uint32_t)(q * RW_BLOCK) + threadIdx.x;
+          const uint32_t sj = j / DENSE_SEG;
+          const uint32_t s_first = __shfl(sj, 0, WAVE);
+          const uint64_t lm = ballot(logit);
+          const uint64_t second = ballot(sj != s_first);
+          const uint64_t m1 = lm & ~second, m2 = lm & second;
+          uint32_t b1 = 0, b2 = 0;
+          const int lane = lane_id();
+          if (m1 && lane == __builtin_ctzll(m1))
+            b1 = atomicAdd(d.seg_lcount + d.seg_base + s_first, (uint32_t)__popcll(m1));
+          if (m2 && lane == __builtin_ctzll(m2))
+            b2 = atomicAdd(d.seg_lcount + d.seg_base + s_first + 1, (uint32_t)__popcll(m2));
+          b1 = __shfl(b1, m1 ? __builtin_ctzll(m1) : 0, WAVE);
+          b2 = __shfl(b2, m2 ? __builtin_ctzll(m2) : 0, WAVE);
+          if (logit) {
+            const bool in2 = (second >> lane) & 1ull;
+            const uint32_t p = in2 ? b2 + rank_below(m2) : b1 + rank_below(m1);
+            const size_t o = (size_t)(d.seg_base + sj) * DENSE_SEG + p;
+            reinterpret_cast<K*>(d.log_keys)[o] = okey;
+            d.log_l[o] = lds_rows ? s_did[row[q]] : a.dids[r0 + row[q]];
+            d.log_r[o] = a.iids[irow[q]];
+          }
+        }
       }
     }
     __syncthreads();
@@ -448,19 +483,23 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   const double per = (sizeof(K) + tb + lin + 4.0 + tb);
   const double bytes = (dtotal ? 0.0 : total * per) + a.n * (sizeof(K) + tb + lin + 4.0);
   // row windows: both variants are launched and each checks the total
-  const bool rows = rw && !lineage && rw->wkeys <= (uint32_t)RW_KEYS && rw->wkeys % 32 == 0 &&
+  // (with lineage the total is known on the host and only one variant runs)
+  const bool rows = rw && rw->wkeys <= (uint32_t)RW_KEYS && rw->wkeys % 32 == 0 && (!lineage || !dtotal) &&
                     (dtotal || total >= rw->from);
+  if (rows && lineage) fill_u32(d.seg_lcount + d.seg_base, dense_segments(total, items), 0u, st);
   const uint64_t skip_at = rows ? rw->from : ~0ull;
   const unsigned nrb = rows ? (unsigned)(rw->ngroups < 2048 ? rw->ngroups : 2048) : 0u;
 #define DL_DEXPAND(IT)                                                                                               \
   if (tk == TAG_F32) {                                                                                               \
     if (!rows || dtotal)                                                                                             \
       k_join_expand_dense<K, TAG_F32, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0, skip_at); \
-    if (rows) k_join_expand_rows<K, TAG_F32, IT><<<nrb, RW_BLOCK, 0, st>>>(a, offs, total, dtotal, d, *rw);         \
+    if (rows) k_join_expand_rows<K, TAG_F32, IT><<<nrb, RW_BLOCK, 0, st>>>(a, offs, total, dtotal, d, *rw,         \
+                                                                            lineage ? 1 : 0);                     \
   } else {                                                                                                           \
     if (!rows || dtotal)                                                                                             \
       k_join_expand_dense<K, TAG_NONE, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0, skip_at); \
-    if (rows) k_join_expand_rows<K, TAG_NONE, IT><<<nrb, RW_BLOCK, 0, st>>>(a, offs, total, dtotal, d, *rw);        \
+    if (rows) k_join_expand_rows<K, TAG_NONE, IT><<<nrb, RW_BLOCK, 0, st>>>(a, offs, total, dtotal, d, *rw,        \
+                                                                             lineage ? 1 : 0);                    \
   }
   DL_PROF_BEGIN(1, st);
   switch (items) {

@@ -76,7 +76,7 @@ def test_row_windows_batched(oracle, synth, tmp_path, rows):
     from paper_2503_21937_amd import dlfix
     g = synth.grid_batch(9, samples=24, kmin=3, kmax=12)
     facts = {"edge": ([g["src"], g["dst"]], g["p"], g["sample"])}
-    for sr in ("addmult", "maxmin", "bool"):
+    for sr in ("addmult", "maxmin", "bool", "diff_addmult"):
         e = dlfix.Engine(synth.TC_PROGRAM, sr, batched=True)
         e.add_facts("edge", [g["src"], g["dst"]], g["p"], g["sample"])
         key = _key(e)
@@ -85,7 +85,14 @@ def test_row_windows_batched(oracle, synth, tmp_path, rows):
                                      "ms": 1.0}) + "\n")
         assert e.autotune(1, str(cache))["rows"] == rows
         got = e.read("path")
-        want = oracle_run(oracle, synth.TC_PROGRAM, sr, facts, batched=True).read("path")
+        o = oracle_run(oracle, synth.TC_PROGRAM, sr, facts, batched=True)
+        want = o.read("path")
         assert np.array_equal(got["cols"], want["cols"]) and np.array_equal(got["sample"], want["sample"])
         if sr != "bool":
             assert_tags_close(got["tags"], want["value"])
+        if sr == "diff_addmult":  # lineage logged by the row-window kernel
+            gout = np.random.default_rng(4).normal(size=want["cols"].shape[0])
+            e.backward("path", gout.astype(np.float32))
+            o.backward("path", gout)
+            np.testing.assert_allclose(e.grad("edge", g["src"].size), o.grad("edge", g["src"].size),
+                                       rtol=1e-4, atol=1e-6)
