@@ -137,7 +137,7 @@ struct Engine {
   std::vector<std::vector<uint32_t>> round_ids;
 
   // round scratch
-  DevBuf counts, offs, alt_keys, alt_vals, vals, flags, pos, ukeys, utags,
+  DevBuf counts, offs, istart, alt_keys, alt_vals, vals, flags, pos, ukeys, utags,
       status, nflags, newpos, rflags, rpos, lf, lpos, nkeys, ntags, nids, tmpA_keys, tmpA_tags, tmpB_keys, tmpB_tags,
       scratch, unpack, qbuf;
   uint64_t* host = nullptr;  // pinned readback words

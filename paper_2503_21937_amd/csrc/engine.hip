@@ -68,7 +68,7 @@ Engine::~Engine() {
     if (!x.borrowed) fr(x.t.keys), fr(x.t.tags), fr(x.t.ids);
     fr(x.off);
   }
-  for (DevBuf* b : {&qtab, &grad_fact, &lin_owner, &lin_l, &lin_r, &tag_by_id, &adj, &counts, &offs, &alt_keys, &alt_vals, &vals, &flags, &pos, &ukeys, &utags, &status,
+  for (DevBuf* b : {&qtab, &grad_fact, &lin_owner, &lin_l, &lin_r, &tag_by_id, &adj, &counts, &offs, &istart, &alt_keys, &alt_vals, &vals, &flags, &pos, &ukeys, &utags, &status,
                     &nflags, &newpos, &rflags, &rpos, &lf, &lpos, &nkeys, &ntags, &nids, &tmpA_keys, &tmpA_tags,
                     &tmpB_keys, &tmpB_tags, &scratch, &unpack, &qbuf, &dtotal})
     fr(*b);

@@ -376,6 +376,8 @@ void run_plan(Engine& e, const Plan& pl) {
 
     e.grow(e.counts, cur.n * 4 + 4);
     e.grow(e.offs, (cur.n + 1) * 4);
+    e.grow(e.istart, cur.n * 4 + 4);
+    a.istart = e.istart.as<uint32_t>();
     join_count<K>(a, e.counts.as<uint32_t>(), e.stream);
     const bool nosync = si + 1 == pl.steps.size() && H.dense && !e.record;
     // without a host readback the scan also adds its total to the run's
@@ -718,6 +720,7 @@ JoinArgs graph_join_args(Engine& e, const Plan& tw, RelState& R, int ar) {
   a.olay = e.layout(ocols);
   for (int c = 0; c < ocols; ++c) a.osrc[c] = step.out_src[c];
   a.index_first = step.body_pos < tw.driver_atom;
+  a.istart = e.istart.as<uint32_t>();
   return a;
 }
 
@@ -770,6 +773,7 @@ int graph_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
     const size_t n = e.rel[tw->driver_rel].full.n;
     e.grow(e.counts, n * 4 + 4);
     e.grow(e.offs, (n + 1) * 4);
+    e.grow(e.istart, n * 4 + 4);
     words = std::max(words, scan_scratch_words(n));
     const IndexSpec& spec = e.prog.indexes[tw->steps[0].index];
     e.grow(e.idx[tw->steps[0].index].off, (((size_t)1 << (e.sbits + spec.w * e.cbits)) + 1) * 4);

@@ -221,11 +221,12 @@ __global__ __launch_bounds__(BLOCK) void k_join_expand_dense(JoinArgs a, const u
     for (int q = 0; q < DX_ITEMS; ++q) {
       base[q] = act[q] ? offs[row[q]] : 0u;
       dkey[q] = act[q] ? dk[row[q]] : (K)0;
+      irow[q] = act[q] ? a.istart[row[q]] : 0u;
     }
 #pragma unroll
     for (int q = 0; q < DX_ITEMS; ++q) {
       const uint32_t j = (uint32_t)(s0 + (size_t)q * BLOCK + threadIdx.x);
-      irow[q] = act[q] ? a.off[join_prefix(dkey[q], a)] + (j - base[q]) : 0u;
+      irow[q] += j - base[q];
     }
 #pragma unroll
     for (int q = 0; q < DX_ITEMS; ++q) {
@@ -303,11 +304,32 @@ __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const
   const T* it = (const T*)a.itags;
   const uint32_t W = rw.wkeys, NWD = W / 32;
   const uint32_t pmask = (1u << d.dcbits) - 1u;
-  for (size_t g = blockIdx.x; g < rw.ngroups; g += gridDim.x) {  // uniform per block
-    const uint32_t r0 = rw.goff[g], r1 = rw.goff[g + 1];
-    if (r0 == r1) continue;
-    const uint32_t s0 = offs[r0], s1 = offs[r1];
-    if (s0 == s1) continue;
+  // The next group's driver rows are fetched while the current one is
+  // processed (its CSR bounds at the top, their output slots after the
+  // window load), so a group starts without waiting on those loads.
+  size_t g = blockIdx.x;
+  uint32_t r0 = 0, r1 = 0, s0 = 0, s1 = 0;
+  if (g < rw.ngroups) {
+    r0 = rw.goff[g];
+    r1 = rw.goff[g + 1];
+    s0 = offs[r0];
+    s1 = offs[r1];
+  }
+  for (; g < rw.ngroups; g += gridDim.x) {  // uniform per block
+    const size_t gn = g + gridDim.x;
+    uint32_t nr0 = 0, nr1 = 0, ns0 = 0, ns1 = 0;
+    if (gn < rw.ngroups) {
+      nr0 = rw.goff[gn];
+      nr1 = rw.goff[gn + 1];
+    }
+    if (r0 == r1 || s0 == s1) {  // nothing to derive in this group
+      if (gn < rw.ngroups) {
+        ns0 = offs[nr0];
+        ns1 = offs[nr1];
+      }
+      r0 = nr0, r1 = nr1, s0 = ns0, s1 = ns1;
+      continue;
+    }
     const uint32_t nr = r1 - r0;
     const bool lds_rows = nr <= (uint32_t)RW_ROWS;  // else rows are read from global memory
     // window of the prefix (sample, col 0): dense indexes kb .. kb + W - 1
@@ -325,6 +347,10 @@ __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const
 #pragma unroll 4
       for (uint32_t i = threadIdx.x; i < W / 4; i += RW_BLOCK) dst[i] = src[i];
     }
+    if (gn < rw.ngroups) {
+      ns0 = offs[nr0];
+      ns1 = offs[nr1];
+    }
     if (lds_rows) {
       for (uint32_t i = threadIdx.x; i <= nr; i += RW_BLOCK) {
         const uint32_t o = offs[r0 + i];
@@ -332,7 +358,7 @@ __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const
         if (i < nr) {
           const K key = dk[r0 + i];
           s_dkey[i] = key;
-          s_ibase[i] = a.off[join_prefix(key, a)] - o;
+          s_ibase[i] = a.istart[r0 + i] - o;
           if constexpr (TK == TAG_F32) s_dtag[i] = dt[r0 + i];
           if (lineage) s_did[i] = a.dids[r0 + i];
         }
@@ -371,7 +397,7 @@ __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const
           const uint32_t j = t0 + (uint32_t)(q * RW_BLOCK) + threadIdx.x;
           const uint32_t r = r0 + row[q];
           dkey[q] = act[q] ? dk[r] : (K)0;
-          irow[q] = act[q] ? a.off[join_prefix(dkey[q], a)] + (j - offs[r]) : 0u;
+          irow[q] = act[q] ? a.istart[r] + (j - offs[r]) : 0u;
           if constexpr (TK == TAG_F32) x[q] = act[q] ? dt[r] : 0.0f;
         }
       }
@@ -460,6 +486,7 @@ __global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const
       for (uint32_t i = threadIdx.x; i < W; i += RW_BLOCK)
         if (s_new[i >> 5] >> (i & 31) & 1u) d.dtag[kb + i] = s_tag[i];
     __syncthreads();  // the window's LDS is reloaded for the next group
+    r0 = nr0, r1 = nr1, s0 = ns0, s1 = ns1;
   }
 }
 

@@ -151,7 +151,9 @@ __global__ void k_join_count(JoinArgs a, uint32_t* __restrict__ counts) {
   const K* dk = (const K*)a.dkeys;
   GRID_STRIDE(i, a.n) {
     uint64_t p = join_prefix(dk[i], a);
-    counts[i] = a.off[p + 1] - a.off[p];
+    const uint32_t b = a.off[p];
+    counts[i] = a.off[p + 1] - b;
+    if (a.istart) a.istart[i] = b;
   }
 }
 

@@ -87,6 +87,7 @@ struct JoinArgs {
   const float* q;  // top-k: per-sample probabilities [sample][64]
   bool index_first;  // x operand order: index tag first (body order)
   int items;         // expand tile: join outputs per thread (1, 2, 4 or 8)
+  uint32_t* istart;  // per driver row: first matching index row (join_count writes it when not NULL)
 };
 
 // Dense-domain deduplication state of one derived relation (key < 2^w):
@@ -133,7 +134,7 @@ uint32_t dense_init_word(int mode);
 
 // counts[i] = number of index rows matching driver row i.
 template <typename K>
-void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st);
+void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st);  // also fills a.istart if set
 // Emit every match: slot j of row i (offs = exclusive scan of counts, with
 // sentinel).  Writes keys (and tags, lineage pairs if non-NULL) at out + j.
 template <typename K>
