@@ -88,7 +88,7 @@ struct LineageSeg {
 
 // Execution choices the autotuner picks among (all give the same result).
 struct ExecConfig {
-  int items = 4;   // join expand tile: outputs per thread (1, 2, 4, 8)
+  int items = 2;   // join expand tile: outputs per thread (1, 2, 4, 8)
   int orient = 0;  // delta plans of 2-atom rules: 0 auto, 1 recent-driven, 2 static-driven
   int graph = 1;   // replay eligible round bodies as a captured HIP graph
   int rows = 1;    // row-window variant of the dense join where it applies

@@ -281,7 +281,7 @@ constexpr int RW_ROWS = 256;   // driver rows of a group staged in LDS
 constexpr int RW_BLOCK = 512;  // 8 waves: the window's LDS is shared by more waves
 
 template <typename K, int TK, int RX_ITEMS>
-__global__ __launch_bounds__(RW_BLOCK) void k_join_expand_rows(JoinArgs a, const uint32_t* __restrict__ offs,
+__global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, const uint32_t* __restrict__ offs,
                                                                size_t total_h, const uint64_t* __restrict__ dtotal,
                                                                DenseArgs d, RowWindows rw, int lineage) {
   using T = typename TagOf<TK>::T;
