@@ -8,6 +8,9 @@ max-min and min-plus semirings (three engines, inputs already resident in
 HBM).  The metric is derived tuples per second: the tuples of `path` at the
 fixpoint, summed over the three semirings, divided by the step time.
 
+Before anything is timed every engine runs the library's autotuner on its
+facts (dl_autotune, fresh cache) and keeps the chosen execution
+configuration (reported under "exec"; --no-tune keeps the defaults).
 The dominant kernel family is found by an untimed profiled step; during the
 timed steps only that family is bracketed with HIP events on the engine's
 stream, which yields the live roofline figure.  The CPU baseline times the
@@ -79,7 +82,7 @@ def cpu_baseline(src, dst, p, n, budget_s: float, seed: int) -> dict:
                       f"({tuples} tuples, {dt:.1f} s, naive Jacobi rounds per column)"}
 
 
-def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int) -> dict:
+def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int, tune_cache: str | None = None) -> dict:
     """Batched differentiable reachability on 512 grids: forward + query read +
     BCE loss + backward to the edge probabilities, all samples in one engine
     call, against the same engine run one sample at a time."""
@@ -106,6 +109,9 @@ def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int) -> dic
     q_x = torch.zeros(S, dtype=torch.int32, device=dev)
     q_z = (ks ** 2 - 1).to(torch.int32)
     eng = dlfix.Engine(synth.TC_PROGRAM, "diff_addmult", batched=True)
+    if tune_cache:  # untimed: the autotuner picks the execution configuration on these facts
+        eng.add_facts("edge", [src, dst], p0, sample)
+        eng.autotune(1, tune_cache)
 
     def batched_step():
         probs = p0.clone().requires_grad_(True)
@@ -124,6 +130,10 @@ def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int) -> dic
     st = eng.stats()
 
     plain = dlfix.Engine(synth.TC_PROGRAM, "diff_addmult")
+    if tune_cache:
+        m0 = torch.tensor(g["sample"] == 0, device=dev)
+        plain.add_facts("edge", [src[m0].contiguous(), dst[m0].contiguous()], p0[m0].contiguous())
+        plain.autotune(1, tune_cache)
     sel = [(g["sample"] == s_) for s_ in range(plain_samples)]
     per = []
     for s_ in range(plain_samples):
@@ -149,7 +159,8 @@ def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int) -> dic
             "batched_samples_per_s": S / tb, "batched_ms_per_step": tb * 1e3,
             "plain_samples_per_s": 1.0 / tp, "plain_sample_ms": tp * 1e3,
             "plain_measured_on": f"first {plain_samples} samples", "speedup": (S / tb) * tp,
-            "derived_tuples": st["derived"], "rounds": st["max_rounds"], "lineage": st["lineage"]}
+            "derived_tuples": st["derived"], "rounds": st["max_rounds"], "lineage": st["lineage"],
+            "exec": {k: st[k] for k in ("dedup", "orient", "items", "rows")}}
 
 
 def copy_calibration(mib: int) -> None:
@@ -177,6 +188,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grids", action="store_true", help="skip the batched fwd+bwd grid workload")
     ap.add_argument("--plain-samples", type=int, default=32)
+    ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuner; use default configurations")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -196,10 +208,14 @@ def main() -> int:
         copy_calibration(args.calibrate_copy)
         return 0
     src, dst, p = synth.er_graph(args.seed, args.nodes, args.edges, weights=True)
+    import tempfile
+    tune_cache = None if args.no_tune else os.path.join(tempfile.mkdtemp(prefix="dlfix_bench_"), "tune.jsonl")
     engines = []
     for sr in SEMIRINGS:
         e = dlfix.Engine(synth.TC_PROGRAM, sr)
         e.add_facts("edge", [src, dst], p)
+        if tune_cache:  # untimed: the autotuner's configuration for these facts
+            e.autotune(1, tune_cache)
         engines.append(e)
 
     def step():
@@ -256,6 +272,7 @@ def main() -> int:
             "rounds": {sr: stats[sr]["max_rounds"] for sr in SEMIRINGS},
             "candidates": {sr: stats[sr]["candidates"] for sr in SEMIRINGS},
             "new_or_changed": {sr: stats[sr]["unique"] for sr in SEMIRINGS},
+            "exec": {sr: {k: stats[sr][k] for k in ("dedup", "orient", "items", "rows")} for sr in SEMIRINGS},
             "kernel_ms_share": {k: round(v / sum(totals.values()), 4) for k, v in
                                 sorted(totals.items(), key=lambda kv: -kv[1])},
         },
@@ -273,7 +290,7 @@ def main() -> int:
         },
     }
     if not args.no_grids:
-        line["batched"] = grids_fwd_bwd(max(1, min(args.steps, 3)), 1, args.seed, args.plain_samples)
+        line["batched"] = grids_fwd_bwd(max(1, min(args.steps, 3)), 1, args.seed, args.plain_samples, tune_cache)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(src, dst, p, args.nodes, args.cpu_budget, args.seed)
     print(json.dumps(line), flush=True)

@@ -61,6 +61,7 @@ struct RelState {
   bool dense = false;
   size_t dense_keys = 0;  // size of the dense index domain (see DenseArgs)
   int dense_cols = 0;
+  DevBuf dense_sbase;     // batched: first dense index of every sample (+ domain size)
   bool own_index = false;  // a plan of its own stratum joins against it
   DevBuf present, touched, dtag, did, log_keys, log_l, log_r, seg_lcount;
   DevBuf goff;                   // as a join driver: CSR over its (sample, first column) prefix
@@ -116,6 +117,8 @@ struct Engine {
   bool key64 = false;
   int cbits = 1, sbits = 0;
   uint32_t max_id = 0, max_sample = 0;
+  std::vector<uint32_t> sample_ids;  // batched: ids in use per sample (largest id + 1)
+  DevBuf d_sn, d_snp;                // per sample: ids in use, padded to 32 (dense index radix)
   std::vector<RelState> rel;
   std::vector<IndexState> idx;
 

@@ -61,14 +61,15 @@ Engine::~Engine() {
       fr(t->keys), fr(t->tags), fr(t->ids);
     fr(r.fact_entry), fr(r.grad), fr(r.fact_slot_d);
     fr(r.cand_keys), fr(r.cand_tags), fr(r.cand_l), fr(r.cand_r);
-    for (DevBuf* b : {&r.present, &r.touched, &r.dtag, &r.did, &r.log_keys, &r.log_l, &r.log_r, &r.seg_lcount, &r.goff})
+    for (DevBuf* b : {&r.present, &r.touched, &r.dtag, &r.did, &r.log_keys, &r.log_l, &r.log_r, &r.seg_lcount, &r.goff,
+                      &r.dense_sbase})
       fr(*b);
   }
   for (auto& x : idx) {
     if (!x.borrowed) fr(x.t.keys), fr(x.t.tags), fr(x.t.ids);
     fr(x.off);
   }
-  for (DevBuf* b : {&qtab, &grad_fact, &lin_owner, &lin_l, &lin_r, &tag_by_id, &adj, &counts, &offs, &istart, &alt_keys, &alt_vals, &vals, &flags, &pos, &ukeys, &utags, &status,
+  for (DevBuf* b : {&d_sn, &d_snp, &qtab, &grad_fact, &lin_owner, &lin_l, &lin_r, &tag_by_id, &adj, &counts, &offs, &istart, &alt_keys, &alt_vals, &vals, &flags, &pos, &ukeys, &utags, &status,
                     &nflags, &newpos, &rflags, &rpos, &lf, &lpos, &nkeys, &ntags, &nids, &tmpA_keys, &tmpA_tags,
                     &tmpB_keys, &tmpB_tags, &scratch, &unpack, &qbuf, &dtotal})
     fr(*b);
@@ -268,6 +269,30 @@ void Engine::run() {
     uint32_t maxid = (uint32_t)host[0], maxs = (uint32_t)(host[0] >> 32);
     max_id = maxid;
     max_sample = batched ? maxs : 0;
+    sample_ids.clear();
+    if (batched) {  // ids in use per sample: the dense domains size every sample by its own ids
+      const size_t ns = (size_t)maxs + 1;
+      grow(d_sn, ns * 4 + 4);
+      grow(d_snp, ns * 4 + 4);
+      DL_HIP(hipMemsetAsync(d_sn.p, 0, ns * 4, stream));
+      for (size_t r = 0; r < rel.size(); ++r) {
+        std::vector<const uint32_t*> cols;
+        for (auto& c : rel[r].raw_cols) cols.push_back(c.as<uint32_t>());
+        sample_max_u32(cols.data(), (int)cols.size(), rel[r].raw_sample.as<uint32_t>(), rel[r].nraw,
+                       d_sn.as<uint32_t>(), stream);
+      }
+      sample_ids.resize(ns);
+      DL_HIP(hipMemcpyAsync(sample_ids.data(), d_sn.p, ns * 4, hipMemcpyDeviceToHost, stream));
+      sync();
+      std::vector<uint32_t> np(ns);
+      for (size_t s = 0; s < ns; ++s) {
+        sample_ids[s] += 1;
+        np[s] = (sample_ids[s] + 31) / 32 * 32;
+      }
+      DL_HIP(hipMemcpyAsync(d_sn.p, sample_ids.data(), ns * 4, hipMemcpyHostToDevice, stream));
+      DL_HIP(hipMemcpyAsync(d_snp.p, np.data(), ns * 4, hipMemcpyHostToDevice, stream));
+      sync();
+    }
     cbits = bits_for(maxid);
     sbits = batched ? bits_for(maxs) : 0;
     int width = key_width(prog.max_cols);

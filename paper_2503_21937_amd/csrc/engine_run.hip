@@ -92,19 +92,37 @@ DenseArgs dense_args(Engine& e, RelState& R) {
   d.dcols = R.dense_cols;
   d.dcbits = e.cbits;
   dense_divisors(d);
+  d.nsamp = e.batched ? (uint32_t)e.sample_ids.size() : 1u;
+  d.sbase = R.dense_sbase.as<uint32_t>();
+  d.sn = e.d_sn.as<uint32_t>();
+  d.snp = e.d_snp.as<uint32_t>();
   return d;
 }
 
-// Dense index domain of a relation of arity `ar`: (samples) x dn^(ar-1) x
-// dnp, dn = ids in use, dnp = dn rounded up to 32 (see DenseArgs).
-uint64_t dense_domain(const Engine& e, int ar) {
-  const uint64_t dn = (uint64_t)e.max_id + 1, dnp = (dn + 31) / 32 * 32;
-  uint64_t keys = (uint64_t)e.max_sample + 1;
+// Dense index block of one sample for a relation of arity `ar`: n^(ar-1) x
+// np keys, n = the sample's ids in use, np = n rounded up to 32.
+uint64_t dense_block(uint64_t n, int ar) {
+  uint64_t keys = (n + 31) / 32 * 32;
   for (int c = 0; c + 1 < ar; ++c) {
-    keys *= dn;
+    keys *= n;
     if (keys > ((uint64_t)1 << 40)) return keys;
   }
-  return keys * dnp;
+  return keys;
+}
+
+// Dense index domain of a relation of arity `ar` (see DenseArgs): one block
+// per sample, sized by the sample's own ids when batched.
+uint64_t dense_domain(const Engine& e, int ar, std::vector<uint32_t>* sbase = nullptr) {
+  if (!e.batched) return dense_block((uint64_t)e.max_id + 1, ar);
+  uint64_t keys = 0;
+  if (sbase) sbase->assign(e.sample_ids.size() + 1, 0u);
+  for (size_t s = 0; s < e.sample_ids.size(); ++s) {
+    if (sbase) (*sbase)[s] = (uint32_t)std::min<uint64_t>(keys, 0xffffffffu);
+    keys += dense_block(e.sample_ids[s], ar);
+    if (keys > ((uint64_t)1 << 40)) return keys;
+  }
+  if (sbase) sbase->back() = (uint32_t)std::min<uint64_t>(keys, 0xffffffffu);
+  return keys;
 }
 
 // Decide the deduplication of every derived relation and reset the dense
@@ -125,6 +143,13 @@ void setup_dense(Engine& e) {
     if (!R.dense) continue;
     R.dense_keys = keys;
     R.dense_cols = e.prog.rels[r].arity;
+    if (e.batched) {
+      std::vector<uint32_t> sb;
+      (void)dense_domain(e, e.prog.rels[r].arity, &sb);
+      e.grow(R.dense_sbase, sb.size() * 4);
+      DL_HIP(hipMemcpyAsync(R.dense_sbase.p, sb.data(), sb.size() * 4, hipMemcpyHostToDevice, e.stream));
+      e.sync();  // sb is a host temporary
+    }
     const size_t words = bitmap_words(keys);
     e.grow(R.present, words * 4);
     e.grow(R.touched, words * 4);
@@ -238,18 +263,27 @@ void ensure_index(Engine& e, int i) {
 // Row windows (k_join_expand_rows) for a single-join plan driven by a whole
 // relation whose head key starts with the driver's (sample, first column)
 // prefix; a window must hold 2^5..2^13 keys.  Builds the driver's prefix CSR
-// when the relation changed.  The row variant takes launches with at least
-// one derivation per 8 window keys of the driver's groups.
+// when the relation changed.  The row variant takes launches with many
+// derivations per window (see `from` below).
 template <typename K>
 bool row_windows(Engine& e, const Plan& pl, RowWindows* rw) {
   if (pl.delta || pl.steps.size() != 1 || pl.steps[0].out_src.empty() || pl.steps[0].out_src[0] != 0) return false;
   const int har = e.prog.rels[pl.head_rel].arity;
   const int pbits = e.sbits + e.cbits;
   if (har < 2 || pbits > 30 || !e.rel[pl.head_rel].dense) return false;
-  // window: the dense indexes of one (sample, col 0) prefix, dn^(har-2) * dnp
-  const uint64_t dn = (uint64_t)e.max_id + 1;
-  uint64_t wkeys = (dn + 31) / 32 * 32;
-  for (int c = 2; c < har; ++c) wkeys *= dn;
+  // window: the dense indexes of one (sample, col 0) prefix, n^(har-2) * np
+  // for the sample's n ids in use; the largest window must fit LDS
+  uint64_t wkeys = 0;
+  auto window = [&](uint64_t n) {
+    uint64_t w = (n + 31) / 32 * 32;
+    for (int c = 2; c < har; ++c) w *= n;
+    return w;
+  };
+  if (e.batched) {
+    for (uint32_t n : e.sample_ids) wkeys = std::max(wkeys, window(n));
+  } else {
+    wkeys = window((uint64_t)e.max_id + 1);
+  }
   if (wkeys > 8192) return false;
   RelState& D = e.rel[pl.driver_rel];
   if (D.full.n == 0) return false;
@@ -263,7 +297,12 @@ bool row_windows(Engine& e, const Plan& pl, RowWindows* rw) {
   rw->goff = D.goff.as<uint32_t>();
   rw->ngroups = groups;
   rw->wkeys = (uint32_t)wkeys;
-  rw->from = e.cfg.rows == 2 ? 0 : (uint64_t)std::min(groups, D.full.n) * wkeys / 8;
+  // at least one derivation per 8 keys of the head's dense domain (all
+  // windows), and ~512 per driver group so that a group's fixed latency
+  // (bounds, window load and write-back) is amortised
+  const uint64_t per_keys = (uint64_t)e.rel[pl.head_rel].dense_keys / 8;
+  const uint64_t per_group = (uint64_t)std::min(groups, D.full.n) * 512;
+  rw->from = e.cfg.rows == 2 ? 0 : std::max(per_keys, per_group);
   return true;
 }
 

@@ -36,9 +36,16 @@ template <typename K>
 __device__ __forceinline__ uint32_t dense_index(const DenseArgs& d, K key) {
   const uint64_t k = (uint64_t)key;
   const uint32_t mask = (1u << d.dcbits) - 1u;
-  uint32_t idx = (uint32_t)(k >> (d.dcols * d.dcbits));  // sample
-  for (int c = 0; c + 1 < d.dcols; ++c) idx = idx * d.dn + ((uint32_t)(k >> ((d.dcols - 1 - c) * d.dcbits)) & mask);
-  return idx * d.dnp + ((uint32_t)k & mask);
+  const uint32_t s = (uint32_t)(k >> (d.dcols * d.dcbits));
+  uint32_t base = 0, n = d.dn, np = d.dnp;
+  if (d.nsamp > 1) {
+    base = d.sbase[s];
+    n = d.sn[s];
+    np = d.snp[s];
+  }
+  uint32_t idx = 0;
+  for (int c = 0; c + 1 < d.dcols; ++c) idx = idx * n + ((uint32_t)(k >> ((d.dcols - 1 - c) * d.dcbits)) & mask);
+  return base + idx * np + ((uint32_t)k & mask);
 }
 
 static void divisor(uint32_t dv, uint32_t* m, uint8_t* s1, uint8_t* s2) {
@@ -61,6 +68,23 @@ __device__ __forceinline__ uint32_t fast_div(uint32_t n, uint32_t m, uint32_t s1
 
 template <typename K>
 __device__ __forceinline__ K dense_key(const DenseArgs& d, uint32_t idx) {
+  if (d.nsamp > 1) {  // the sample whose block holds idx, then its own radix
+    uint32_t lo = 0, hi = d.nsamp;  // sbase[lo] <= idx < sbase[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (d.sbase[mid] <= idx) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t n = d.sn[lo], np = d.snp[lo];
+    uint32_t r = idx - d.sbase[lo];
+    uint64_t k = r % np;
+    r /= np;
+    for (int c = 1; c < d.dcols; ++c) {
+      k |= (uint64_t)(r % n) << (c * d.dcbits);
+      r /= n;
+    }
+    return (K)(k | ((uint64_t)lo << (d.dcols * d.dcbits)));
+  }
   uint32_t q = fast_div(idx, d.dnp_m, d.dnp_s1, d.dnp_s2);
   uint64_t k = idx - q * d.dnp;
   idx = q;
@@ -302,7 +326,6 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
   const K* ik = (const K*)a.ikeys;
   const T* dt = (const T*)a.dtags;
   const T* it = (const T*)a.itags;
-  const uint32_t W = rw.wkeys, NWD = W / 32;
   const uint32_t pmask = (1u << d.dcbits) - 1u;
   // The next group's driver rows are fetched while the current one is
   // processed (its CSR bounds at the top, their output slots after the
@@ -332,8 +355,19 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
     }
     const uint32_t nr = r1 - r0;
     const bool lds_rows = nr <= (uint32_t)RW_ROWS;  // else rows are read from global memory
-    // window of the prefix (sample, col 0): dense indexes kb .. kb + W - 1
-    const uint64_t kb = ((uint64_t)(g >> d.dcbits) * d.dn + ((uint32_t)g & pmask)) * W;
+    // window of the prefix (sample, col 0): dense indexes kb .. kb + W - 1,
+    // W = n^(arity-2) * np for the sample's n and np (a multiple of 32)
+    const uint32_t gs = (uint32_t)(g >> d.dcbits), c0 = (uint32_t)g & pmask;
+    uint32_t gn_ = d.dn, gnp = d.dnp, gbase = 0;
+    if (d.nsamp > 1) {
+      gn_ = d.sn[gs];
+      gnp = d.snp[gs];
+      gbase = d.sbase[gs];
+    }
+    uint32_t W = gnp;
+    for (int c = 2; c < a.olay.ncols; ++c) W *= gn_;
+    const uint64_t kb = (uint64_t)gbase + (uint64_t)c0 * W;
+    const uint32_t NWD = W / 32;
     const size_t wb = kb >> 5;
     for (uint32_t i = threadIdx.x; i < NWD; i += RW_BLOCK) {
       s_pres[i] = d.present[wb + i];
@@ -416,8 +450,8 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
           // offset in the window of the prefix (sample, v[0]): the remaining
           // columns in mixed radix (dn per middle column, dnp for the last)
           uint32_t lk = 0;
-          for (int c = 1; c + 1 < a.olay.ncols; ++c) lk = lk * d.dn + v[c];
-          lk = lk * d.dnp + v[a.olay.ncols - 1];
+          for (int c = 1; c + 1 < a.olay.ncols; ++c) lk = lk * gn_ + v[c];
+          lk = lk * gnp + v[a.olay.ncols - 1];
           if (lk >= W) {  // the host only picks this kernel when every key lies in its window
             if (d.overflow) *d.overflow = 2;
           } else {
@@ -511,7 +545,7 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   const double bytes = (dtotal ? 0.0 : total * per) + a.n * (sizeof(K) + tb + lin + 4.0);
   // row windows: both variants are launched and each checks the total
   // (with lineage the total is known on the host and only one variant runs)
-  const bool rows = rw && rw->wkeys <= (uint32_t)RW_KEYS && rw->wkeys % 32 == 0 && (!lineage || !dtotal) &&
+  const bool rows = rw && rw->wkeys <= (uint32_t)RW_KEYS && (!lineage || !dtotal) &&
                     (dtotal || total >= rw->from);
   if (rows && lineage) fill_u32(d.seg_lcount + d.seg_base, dense_segments(total, items), 0u, st);
   const uint64_t skip_at = rows ? rw->from : ~0ull;

@@ -372,6 +372,48 @@ __global__ void k_max(const uint32_t* __restrict__ in, size_t n, uint32_t* out) 
   if (lane_id() == 0) atomicMax(out, m);
 }
 
+struct Cols4 {
+  const uint32_t* c[4];
+};
+
+// Facts usually come grouped by sample: a wave whose active lanes share one
+// sample reduces first and issues a single atomic.
+__global__ void k_sample_max(Cols4 cols, int ncols, const uint32_t* __restrict__ sample, size_t n,
+                             uint32_t* __restrict__ smax) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t n_pad = (n + WAVE - 1) / WAVE * WAVE;  // whole waves stay in the loop together
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n_pad; i += stride) {
+    const bool act = i < n;
+    uint32_t m = 0, s = 0;
+    if (act) {
+      for (int c = 0; c < ncols; ++c) m = cols.c[c][i] > m ? cols.c[c][i] : m;
+      s = sample[i];
+    }
+    const uint64_t live = ballot(act);
+    const int first = live ? __builtin_ctzll(live) : 0;
+    const uint32_t s0 = __shfl(s, first, WAVE);
+    if (ballot(act && s != s0) == 0ull) {  // one sample in the wave
+      uint32_t w = m;
+#pragma unroll
+      for (int d = WAVE / 2; d > 0; d >>= 1) {
+        const uint32_t o = __shfl_xor(w, d, WAVE);
+        w = o > w ? o : w;
+      }
+      if (live && lane_id() == first) atomicMax(smax + s0, w);
+    } else if (act) {
+      atomicMax(smax + s, m);
+    }
+  }
+}
+
+void sample_max_u32(const uint32_t* const* cols, int ncols, const uint32_t* sample, size_t n, uint32_t* smax,
+                    hipStream_t st) {
+  if (!n) return;
+  Cols4 c{{nullptr, nullptr, nullptr, nullptr}};
+  for (int i = 0; i < ncols && i < 4; ++i) c.c[i] = cols[i];
+  k_sample_max<<<grid_for(n) < 2048 ? grid_for(n) : 2048, BLOCK, 0, st>>>(c, ncols, sample, n, smax);
+}
+
 void max_u32(const uint32_t* in, size_t n, uint32_t* d_out, hipStream_t st) {
   if (n) k_max<<<grid_for(n) < 2048 ? grid_for(n) : 2048, BLOCK, 0, st>>>(in, n, d_out);
 }

@@ -34,6 +34,10 @@ void fill_f32(float* out, size_t n, float v, hipStream_t st);
 void gather(const void* in, const uint32_t* idx, void* out, size_t n, size_t bytes, hipStream_t st);
 // Max over n u32 values into *d_out (atomic max; *d_out must be initialised).
 void max_u32(const uint32_t* in, size_t n, uint32_t* d_out, hipStream_t st);
+// smax[sample[i]] = max(smax[...], largest column value of row i); smax must
+// hold (largest sample + 1) words, cleared beforehand.
+void sample_max_u32(const uint32_t* const* cols, int ncols, const uint32_t* sample, size_t n, uint32_t* smax,
+                    hipStream_t st);
 
 // ---------------------------------------------------------- relations
 struct KeyLayout {  // packed key: [sample | c0 | c1 | ...], c0 most significant
@@ -112,12 +116,19 @@ struct DenseArgs {
   uint32_t seg_base;   // first segment of this launch
   uint64_t* overflow;  // set to 1 when a device-side total exceeds the 32-bit offsets
   int mode;
-  // Dense index of a packed key: mixed radix over (sample, col 0, ..., col
-  // last) with dn ids per column and the last column padded to dnp (a
-  // multiple of 32), so the keys of one (sample, col 0) prefix form a
-  // word-aligned window.  Order-preserving: index order is key order.
+  // Dense index of a packed key: mixed radix over (col 0, ..., col last)
+  // with dn ids per column and the last column padded to dnp (a multiple of
+  // 32), so the keys of one (sample, col 0) prefix form a word-aligned
+  // window; samples follow one another.  Order-preserving: index order is
+  // key order.  With one sample dn/dnp hold the sizes; batched engines size
+  // every sample by its own ids: sample s starts at sbase[s] (sbase[nsamp] =
+  // domain size) with sn[s] ids per column, the last padded to snp[s].
   uint32_t dn, dnp;
   int dcols, dcbits;   // relation arity, bits per column of the packed key
+  uint32_t nsamp;      // samples (1: dn / dnp, else the tables)
+  const uint32_t* sbase;
+  const uint32_t* sn;
+  const uint32_t* snp;
   // division by dn and dnp through multiply-high and shifts (Granlund and
   // Montgomery, division by invariant integers): q = (t + ((n - t) >> s1))
   // >> s2 with t = mulhi(n, m), exact for every 32-bit n
