@@ -66,14 +66,28 @@ __device__ __forceinline__ uint32_t fast_div(uint32_t n, uint32_t m, uint32_t s1
   return (t + ((n - t) >> s1)) >> s2;
 }
 
+// Sample whose dense block holds idx (batched engines).
+__device__ __forceinline__ uint32_t dense_sample(const DenseArgs& d, uint32_t idx) {
+  uint32_t lo = 0, hi = d.nsamp;  // sbase[lo] <= idx < sbase[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (d.sbase[mid] <= idx) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// idx -> packed key; `s_from` is a sample at or before idx's (batched), so
+// that a run of nearby indexes walks forward instead of searching.
 template <typename K>
-__device__ __forceinline__ K dense_key(const DenseArgs& d, uint32_t idx) {
+__device__ __forceinline__ K dense_key(const DenseArgs& d, uint32_t idx, uint32_t s_from = ~0u) {
   if (d.nsamp > 1) {  // the sample whose block holds idx, then its own radix
-    uint32_t lo = 0, hi = d.nsamp;  // sbase[lo] <= idx < sbase[hi]
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (d.sbase[mid] <= idx) lo = mid;
-      else hi = mid;
+    uint32_t lo;
+    if (s_from == ~0u) {
+      lo = dense_sample(d, idx);
+    } else {
+      lo = s_from;
+      while (lo + 1 < d.nsamp && d.sbase[lo + 1] <= idx) ++lo;
     }
     const uint32_t n = d.sn[lo], np = d.snp[lo];
     uint32_t r = idx - d.sbase[lo];
@@ -753,6 +767,8 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
   c = wave_sum(c);
   uint32_t o = block_first_slot(counts, prefixed, c, s_tot, s_pre, d_total, log);
   if (c == 0) return;  // wave-uniform; no barrier follows
+  // batched: the sample of the wave's first word, searched once
+  const uint32_t s_hint = d.nsamp > 1 ? __shfl(lane == 0 ? dense_sample(d, (uint32_t)(w0 << 5)) : 0u, 0, WAVE) : ~0u;
 #pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
     const uint32_t x = b[i];
@@ -764,7 +780,7 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
     }
     // a word's 32 indexes share all columns but the last (dnp is a multiple
     // of 32): one index-to-key conversion per word, the bit adds to the key
-    const uint64_t kbase = x ? (uint64_t)dense_key<K>(d, (uint32_t)((wb + lane) << 5)) : 0ull;
+    const uint64_t kbase = x ? (uint64_t)dense_key<K>(d, (uint32_t)((wb + lane) << 5), s_hint) : 0ull;
     o += wave_expand_bits(x, wb, o, kbase, [&](uint32_t slot, uint64_t kk, uint64_t kb, uint32_t bit) {
       keys[slot] = (K)(kb + bit);
       float t = 1.0f;
@@ -793,17 +809,19 @@ void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K*
   DL_PROF_END(6, st, words * 12.0);
 }
 
-// One block per lineage segment: its entries go to their compacted position
-// as (owner id, left id, right id), the owner found through the dense id of
-// the logged head key (assigned by this round's dense_finalize).
+// One wave per lineage segment (segments are short): its entries go to
+// their compacted position as (owner id, left id, right id), the owner found
+// through the dense id of the logged head key (assigned by this round's
+// dense_finalize).
 template <typename K>
 __global__ __launch_bounds__(BLOCK) void k_segments_lineage(DenseArgs d, const uint32_t* __restrict__ pos, size_t nseg,
                                                             uint32_t* __restrict__ owner, uint32_t* __restrict__ l,
                                                             uint32_t* __restrict__ r) {
   const K* lk = reinterpret_cast<const K*>(d.log_keys);
-  for (size_t s = blockIdx.x; s < nseg; s += gridDim.x) {
+  const size_t w0 = (size_t)blockIdx.x * NWAVES + threadIdx.x / WAVE, ws = (size_t)gridDim.x * NWAVES;
+  for (size_t s = w0; s < nseg; s += ws) {
     const uint32_t c = d.seg_lcount[s], o = pos[s];
-    for (uint32_t i = threadIdx.x; i < c; i += BLOCK) {
+    for (uint32_t i = (uint32_t)lane_id(); i < c; i += WAVE) {
       const size_t src = s * DENSE_SEG + i;
       owner[o + i] = d.did[dense_index(d, lk[src])];
       l[o + i] = d.log_l[src];
@@ -816,7 +834,8 @@ template <typename K>
 void segments_lineage(const DenseArgs& d, const uint32_t* pos, size_t nseg, uint32_t* owner, uint32_t* l, uint32_t* r,
                       hipStream_t st) {
   if (!nseg) return;
-  const unsigned g = (unsigned)(nseg < 65536 ? nseg : 65536);
+  const size_t blocks = (nseg + NWAVES - 1) / NWAVES;
+  const unsigned g = (unsigned)(blocks < 65536 ? blocks : 65536);
   DL_PROF_BEGIN(8, st);
   k_segments_lineage<K><<<g, BLOCK, 0, st>>>(d, pos, nseg, owner, l, r);
   DL_PROF_END(8, st, nseg * 8.0);
@@ -844,12 +863,13 @@ __global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words
   c = wave_sum(c);
   uint32_t o = block_first_slot(counts, prefixed, c, s_tot, s_pre, nullptr);
   if (c == 0) return;  // wave-uniform; no barrier follows
+  const uint32_t s_hint = d.nsamp > 1 ? __shfl(lane == 0 ? dense_sample(d, (uint32_t)(w0 << 5)) : 0u, 0, WAVE) : ~0u;
 #pragma unroll
   for (int i = 0; i < BM_ITEMS; ++i) {
     const uint32_t x = b[i];
     if (!__ballot(x != 0u)) continue;
     const size_t wb = w0 + (size_t)i * WAVE;
-    const uint64_t kbase = x ? (uint64_t)dense_key<K>(d, (uint32_t)((wb + lane) << 5)) : 0ull;
+    const uint64_t kbase = x ? (uint64_t)dense_key<K>(d, (uint32_t)((wb + lane) << 5), s_hint) : 0ull;
     o += wave_expand_bits(x, wb, o, kbase, [&](uint32_t slot, uint64_t kk, uint64_t kb, uint32_t bit) {
       keys[slot] = (K)(kb + bit);
       if (tags) {
