@@ -25,7 +25,7 @@ namespace {
 // Device words of totals (64 x u64): slots 0..6 below, 30 = id / sample
 // maxima at ingest, 32.. = round log of a graph batch (count, then totals).
 enum Slot { S_SCAN = 0, S_UNIQUE = 1, S_NEW = 2, S_RECENT = 3, S_LIN = 4, S_OVF = 5, S_CAND = 6, S_LOG = 32 };
-constexpr int GRAPH_ROUNDS = 4;  // round bodies per captured graph
+constexpr int BATCH_ROUNDS = 4;  // round bodies per host synchronisation (one graph)
 
 uint64_t* total_slot(Engine& e, int s) { return e.dtotal.as<uint64_t>() + s; }
 
@@ -715,7 +715,7 @@ size_t absorb_sorted(Engine& e, int r) {
 // end compacts the touched bitmap.  Such bodies run several rounds per host
 // sync (as one captured HIP graph where allowed), the host reading back one
 // block of counters and the round log per batch.
-std::vector<const Plan*> graph_plans(Engine& e, const Stratum& st) {
+std::vector<const Plan*> batch_plans(Engine& e, const Stratum& st) {
   std::vector<const Plan*> out;
   if (e.lineage || st.rels.size() != 1 || st.delta_plans.empty()) return {};
   const int r = st.rels[0];
@@ -734,7 +734,7 @@ std::vector<const Plan*> graph_plans(Engine& e, const Stratum& st) {
 }
 
 template <typename K>
-JoinArgs graph_join_args(Engine& e, const Plan& tw, RelState& R, int ar) {
+JoinArgs batch_join_args(Engine& e, const Plan& tw, RelState& R, int ar) {
   const Step& step = tw.steps[0];
   const IndexSpec& spec = e.prog.indexes[step.index];
   const RelState& D = e.rel[tw.driver_rel];
@@ -765,7 +765,7 @@ JoinArgs graph_join_args(Engine& e, const Plan& tw, RelState& R, int ar) {
 
 // Enqueue one round body (no host interaction: capturable).
 template <typename K>
-void enqueue_graph_round(Engine& e, int r, const std::vector<const Plan*>& plans) {
+void enqueue_round_body(Engine& e, int r, const std::vector<const Plan*>& plans) {
   RelState& R = e.rel[r];
   hipStream_t st = e.stream;
   const int ar = e.prog.rels[r].arity;
@@ -775,7 +775,7 @@ void enqueue_graph_round(Engine& e, int r, const std::vector<const Plan*>& plans
     const int pbits = e.sbits + spec.w * e.cbits;
     csr_build_dn<K>(R.recent.keys.as<K>(), total_slot(e, S_UNIQUE), e.key_width(ar), pbits,
                     e.idx[step.index].off.as<uint32_t>(), st);
-    const JoinArgs a = graph_join_args<K>(e, *tw, R, ar);
+    const JoinArgs a = batch_join_args<K>(e, *tw, R, ar);
     join_count<K>(a, e.counts.as<uint32_t>(), st);
     scan_u32(e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), a.n, total_slot(e, S_SCAN), true,
              e.scratch.as<uint64_t>(), st, total_slot(e, S_CAND));
@@ -797,13 +797,13 @@ void enqueue_graph_round(Engine& e, int r, const std::vector<const Plan*>& plans
                     st, total_slot(e, S_LOG), pre);
 }
 
-// Rounds 2.. of an eligible stratum by graph replay; returns the number of
-// rounds run (the last one changed nothing), or 0 if capture was refused.
+// Rounds 2.. of an eligible stratum in batches of device-sized round bodies;
+// returns the number of rounds run (the last one changed nothing).
 template <typename K>
-int graph_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& plans) {
+int batch_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& plans) {
   const int r = st.rels[0];
   RelState& R = e.rel[r];
-  // every buffer the body touches at its final size, before capture
+  // every buffer the body touches at its final size, before any batch (and capture)
   const size_t keys = R.dense_keys;
   e.grow(R.recent.keys, keys * sizeof(K) + 8, true, R.recent.n * sizeof(K));
   if (e.tag_kind == TAG_F32) e.grow(R.recent.tags, keys * 4 + 8, true, R.recent.n * 4);
@@ -825,7 +825,7 @@ int graph_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
   e.grow(e.pos, (nb + 1) * 4);
   e.sync();
 
-  // Rounds go in batches of GRAPH_ROUNDS round bodies: the host syncs once
+  // Rounds go in batches of BATCH_ROUNDS round bodies: the host syncs once
   // per batch and reads each round's new-tuple count from the round log;
   // rounds after the fixpoint in a batch find an empty recent relation and
   // change nothing.  A batch is one captured HIP graph, or -- while kernels
@@ -833,7 +833,7 @@ int graph_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
   // refused -- the same launches enqueued directly.
   auto enqueue_batch = [&] {
     fill_u32(reinterpret_cast<uint32_t*>(total_slot(e, S_LOG)), 2, 0u, e.stream);  // log entries = 0
-    for (int i = 0; i < GRAPH_ROUNDS; ++i) enqueue_graph_round<K>(e, r, plans);
+    for (int i = 0; i < BATCH_ROUNDS; ++i) enqueue_round_body<K>(e, r, plans);
     DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, e.stream));
   };
   hipGraph_t graph = nullptr;
@@ -1001,8 +1001,8 @@ void run_fixpoint(Engine& e) {
     size_t changed = 0;
     for (int r : st.rels) changed += absorb<K>(e, r);
     if (changed) {
-      const std::vector<const Plan*> gp = graph_plans(e, st);
-      const int gr = gp.empty() ? 0 : graph_rounds<K>(e, st, gp);
+      const std::vector<const Plan*> gp = batch_plans(e, st);
+      const int gr = gp.empty() ? 0 : batch_rounds<K>(e, st, gp);
       if (gr > 0) {
         rounds += gr;
         changed = 0;
