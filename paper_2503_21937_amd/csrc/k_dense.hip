@@ -20,6 +20,10 @@ __device__ __forceinline__ float from_ordered(uint32_t o) {
   return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
 }
 
+__device__ __forceinline__ uint32_t dense_init_word_dev(int mode) {
+  return mode == DENSE_MAX ? 0x80000000u : mode == DENSE_MIN ? (0x7f800000u | 0x80000000u) : 0u;
+}
+
 uint32_t dense_init_word(int mode) {
   switch (mode) {
     case DENSE_MAX: return 0x80000000u;          // ordered(+0.0f): max-min zero
@@ -315,8 +319,9 @@ __global__ __launch_bounds__(BLOCK) void k_join_expand_dense(JoinArgs a, const u
 // host sets the threshold `from` and both variants test the device-side total.
 constexpr int RW_BITS = 13;  // largest window: 8192 keys (32 KB of tags)
 constexpr int RW_KEYS = 1 << RW_BITS;
-constexpr int RW_ROWS = 256;   // driver rows of a group staged in LDS
+constexpr int RW_ROWS = 255;   // driver rows of a group staged in LDS (4 workgroups fit a CU)
 constexpr int RW_BLOCK = 512;  // 8 waves: the window's LDS is shared by more waves
+constexpr int RW_WAVES = RW_BLOCK / WAVE;
 
 template <typename K, int TK, int RX_ITEMS>
 __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, const uint32_t* __restrict__ offs,
@@ -334,6 +339,7 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
   __shared__ K s_dkey[RW_ROWS];
   __shared__ float s_dtag[TK == TAG_F32 ? RW_ROWS : 1];
   __shared__ uint32_t s_did[RW_ROWS];  // lineage: driver row ids
+  __shared__ uint32_t s_cpre[RW_ROWS + 1];  // chunks of 64 outputs before each row
   const size_t total = dtotal ? (size_t)*dtotal : total_h;
   if (total < rw.from || total > 0xffffffffull) return;  // scattered kernel's launch (or overflow, reported there)
   const K* dk = (const K*)a.dkeys;
@@ -413,115 +419,155 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
       }
     }
     __syncthreads();
-    // the group's outputs, TILE at a time: each output finds its driver row
-    // by a binary search over the group's offsets (last row starting at or
-    // before it); the items of a thread take each step together
-    for (uint32_t t0 = s0; t0 < s1; t0 += TILE) {
-      uint32_t row[RX_ITEMS], irow[RX_ITEMS];
-      K dkey[RX_ITEMS];
-      float x[RX_ITEMS];
-      bool act[RX_ITEMS];
-#pragma unroll
-      for (int q = 0; q < RX_ITEMS; ++q) {
-        const uint32_t j = t0 + (uint32_t)(q * RW_BLOCK) + threadIdx.x;
-        act[q] = j < s1;
-        uint32_t lo = 0, hi = nr;  // invariant: start(lo) <= j < start(hi)
-        while (act[q] && hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          const uint32_t o = lds_rows ? s_offs[mid] : offs[r0 + mid];
-          if (o <= j) lo = mid;
-          else hi = mid;
+    // One derivation: fold it into the window; with lineage, log it if it is
+    // a discovery (called by whole waves: the segment claims are ballots).
+    auto fold = [&](bool act, uint32_t j, K dkey, uint32_t irow, float x, uint32_t lrow) {
+      bool logit = false;
+      K okey = 0;
+      if (act) {
+        const K ikey = ik[irow];
+        uint32_t v[4];
+        for (int c = 0; c < a.olay.ncols; ++c) {
+          const int s = a.osrc[c];
+          v[c] = s >= 0 ? key_col(dkey, s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
         }
-        row[q] = lo;
-        if (lds_rows) {
-          dkey[q] = s_dkey[lo];
-          irow[q] = s_ibase[lo] + j;
-          if constexpr (TK == TAG_F32) x[q] = s_dtag[lo];
-        }
-      }
-      if (!lds_rows) {
-#pragma unroll
-        for (int q = 0; q < RX_ITEMS; ++q) {
-          const uint32_t j = t0 + (uint32_t)(q * RW_BLOCK) + threadIdx.x;
-          const uint32_t r = r0 + row[q];
-          dkey[q] = act[q] ? dk[r] : (K)0;
-          irow[q] = act[q] ? a.istart[r] + (j - offs[r]) : 0u;
-          if constexpr (TK == TAG_F32) x[q] = act[q] ? dt[r] : 0.0f;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < RX_ITEMS; ++q) {
-        if (t0 + (uint32_t)(q * RW_BLOCK) >= s1) break;  // uniform across the block
-        bool logit = false;
-        K okey = 0;
-        if (act[q]) {
-          const K ikey = ik[irow[q]];
-          uint32_t v[4];
-          for (int c = 0; c < a.olay.ncols; ++c) {
-            const int s = a.osrc[c];
-            v[c] = s >= 0 ? key_col(dkey[q], s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
-          }
-          // offset in the window of the prefix (sample, v[0]): the remaining
-          // columns in mixed radix (dn per middle column, dnp for the last)
-          uint32_t lk = 0;
-          for (int c = 1; c + 1 < a.olay.ncols; ++c) lk = lk * gn_ + v[c];
-          lk = lk * gnp + v[a.olay.ncols - 1];
-          if (lk >= W) {  // the host only picks this kernel when every key lies in its window
-            if (d.overflow) *d.overflow = 2;
-          } else {
-            const uint32_t loc = lk;
-            const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
-            const bool present = (s_pres[wi] & bit) != 0u;
-            bool mark = false;
-            if constexpr (TK == TAG_F32) {
-              const float y = it[irow[q]];
-              const float t = a.index_first ? f_otimes(a.sr, y, x[q]) : f_otimes(a.sr, x[q], y);
-              if (d.mode == DENSE_ADD) {
-                if (!present) {
-                  atomicAdd(reinterpret_cast<float*>(s_tag) + loc, t);
-                  mark = true;
-                  logit = lineage != 0;
-                }
-              } else if (d.mode == DENSE_MAX) {
-                const uint32_t o = to_ordered(t);
-                mark = (o > s_tag[loc] && o > atomicMax(s_tag + loc, o)) || !present;
-              } else {
-                const uint32_t o = to_ordered(t);
-                mark = (o < s_tag[loc] && o < atomicMin(s_tag + loc, o)) || !present;
+        // offset in the window of the prefix (sample, v[0]): the remaining
+        // columns in mixed radix (n per middle column, np for the last)
+        uint32_t lk = 0;
+        for (int c = 1; c + 1 < a.olay.ncols; ++c) lk = lk * gn_ + v[c];
+        lk = lk * gnp + v[a.olay.ncols - 1];
+        if (lk >= W) {  // the host only picks this kernel when every key lies in its window
+          if (d.overflow) *d.overflow = 2;
+        } else {
+          const uint32_t loc = lk;
+          const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
+          bool mark = false;
+          if constexpr (TK == TAG_F32) {
+            const float y = it[irow];
+            const float t = a.index_first ? f_otimes(a.sr, y, x) : f_otimes(a.sr, x, y);
+            if (d.mode == DENSE_ADD) {
+              if (!(s_pres[wi] & bit)) {
+                atomicAdd(reinterpret_cast<float*>(s_tag) + loc, t);
+                mark = true;
+                logit = lineage != 0;
               }
             } else {
-              mark = !present;
+              // an absent key holds the semiring zero: the presence bit only
+              // matters for a derivation that does not beat that zero
+              const uint32_t o = to_ordered(t), zero = dense_init_word_dev(d.mode);
+              if (d.mode == DENSE_MAX) {
+                mark = o > s_tag[loc] && o > atomicMax(s_tag + loc, o);
+                if (!mark && o <= zero) mark = !(s_pres[wi] & bit);
+              } else {
+                mark = o < s_tag[loc] && o < atomicMin(s_tag + loc, o);
+                if (!mark && o >= zero) mark = !(s_pres[wi] & bit);
+              }
             }
-            if (mark && !(s_new[wi] & bit)) atomicOr(s_new + wi, bit);
-            if (logit) okey = key_make<K>(key_sample(dkey[q], a.dlay), v, a.olay);
+          } else {
+            mark = !(s_pres[wi] & bit);
           }
+          if (mark && !(s_new[wi] & bit)) atomicOr(s_new + wi, bit);
+          if (logit) okey = key_make<K>(key_sample(dkey, a.dlay), v, a.olay);
         }
-        if (lineage) {
-          // discovery derivations go to the segment of their output slot
-          // (DENSE_SEG slots each); a wave's 64 consecutive slots touch at most
-          // two segments, each claimed with one atomic add
-          const uint32_t j = t0 + (uint32_t)(q * RW_BLOCK) + threadIdx.x;
-          const uint32_t sj = j / DENSE_SEG;
-          const uint32_t s_first = __shfl(sj, 0, WAVE);
-          const uint64_t lm = ballot(logit);
-          const uint64_t second = ballot(sj != s_first);
-          const uint64_t m1 = lm & ~second, m2 = lm & second;
-          uint32_t b1 = 0, b2 = 0;
-          const int lane = lane_id();
-          if (m1 && lane == __builtin_ctzll(m1))
-            b1 = atomicAdd(d.seg_lcount + d.seg_base + s_first, (uint32_t)__popcll(m1));
-          if (m2 && lane == __builtin_ctzll(m2))
-            b2 = atomicAdd(d.seg_lcount + d.seg_base + s_first + 1, (uint32_t)__popcll(m2));
-          b1 = __shfl(b1, m1 ? __builtin_ctzll(m1) : 0, WAVE);
-          b2 = __shfl(b2, m2 ? __builtin_ctzll(m2) : 0, WAVE);
-          if (logit) {
-            const bool in2 = (second >> lane) & 1ull;
-            const uint32_t p = in2 ? b2 + rank_below(m2) : b1 + rank_below(m1);
-            const size_t o = (size_t)(d.seg_base + sj) * DENSE_SEG + p;
-            reinterpret_cast<K*>(d.log_keys)[o] = okey;
-            d.log_l[o] = lds_rows ? s_did[row[q]] : a.dids[r0 + row[q]];
-            d.log_r[o] = a.iids[irow[q]];
+      }
+      if (lineage) {
+        // discovery derivations go to the segment of their output slot
+        // (DENSE_SEG slots each); a wave's lanes hold consecutive slots, so
+        // they touch at most two segments, each claimed with one atomic add
+        const uint32_t sj = j / DENSE_SEG;
+        const uint32_t s_first = __shfl(sj, 0, WAVE);
+        const uint64_t lm = ballot(logit);
+        const uint64_t second = ballot(sj != s_first);
+        const uint64_t m1 = lm & ~second, m2 = lm & second;
+        uint32_t b1 = 0, b2 = 0;
+        const int lane = lane_id();
+        if (m1 && lane == __builtin_ctzll(m1))
+          b1 = atomicAdd(d.seg_lcount + d.seg_base + s_first, (uint32_t)__popcll(m1));
+        if (m2 && lane == __builtin_ctzll(m2))
+          b2 = atomicAdd(d.seg_lcount + d.seg_base + s_first + 1, (uint32_t)__popcll(m2));
+        b1 = __shfl(b1, m1 ? __builtin_ctzll(m1) : 0, WAVE);
+        b2 = __shfl(b2, m2 ? __builtin_ctzll(m2) : 0, WAVE);
+        if (logit) {
+          const bool in2 = (second >> lane) & 1ull;
+          const uint32_t p = in2 ? b2 + rank_below(m2) : b1 + rank_below(m1);
+          const size_t o = (size_t)(d.seg_base + sj) * DENSE_SEG + p;
+          reinterpret_cast<K*>(d.log_keys)[o] = okey;
+          d.log_l[o] = lrow;
+          d.log_r[o] = a.iids[irow];
+        }
+      }
+    };
+    if (lds_rows) {
+      // Chunks of 64 consecutive outputs of one driver row, taken by the
+      // waves in turn: a wave's lanes share the row (its key, tag and index
+      // base are read once per chunk), and no lane searches for its row.
+      if (threadIdx.x < WAVE) {  // chunk counts of the rows, scanned by one wave
+        uint32_t cnt[4], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t i = (uint32_t)threadIdx.x * 4 + k;
+          cnt[k] = i < nr ? (s_offs[i + 1] - s_offs[i] + WAVE - 1) / WAVE : 0u;
+          sum += cnt[k];
+        }
+        uint32_t run = wave_inclusive_scan(sum) - sum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t i = (uint32_t)threadIdx.x * 4 + k;
+          if (i <= nr) s_cpre[i] = run;
+          run += cnt[k];
+        }
+      }
+      __syncthreads();
+      const uint32_t nch = s_cpre[nr], wv = threadIdx.x / WAVE;
+      const uint32_t lane = (uint32_t)lane_id();
+      for (uint32_t cb = wv; cb < nch; cb += RW_WAVES * RX_ITEMS) {  // uniform per wave
+        bool act[RX_ITEMS];
+        uint32_t jj[RX_ITEMS], irow[RX_ITEMS], lrow[RX_ITEMS];
+        K dkey[RX_ITEMS];
+        float x[RX_ITEMS];
+#pragma unroll
+        for (int q = 0; q < RX_ITEMS; ++q) {
+          const uint32_t c = cb + (uint32_t)q * RW_WAVES;
+          uint32_t lo = 0, hi = nr;  // last row whose first chunk is at or before c
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_cpre[mid] <= c) lo = mid;
+            else hi = mid;
           }
+          const uint32_t j = s_offs[lo] + (c - s_cpre[lo]) * WAVE + lane;
+          act[q] = c < nch && j < s_offs[lo + 1];
+          jj[q] = j;
+          dkey[q] = s_dkey[lo];
+          irow[q] = s_ibase[lo] + j;
+          x[q] = 0.0f;
+          if constexpr (TK == TAG_F32) x[q] = s_dtag[lo];
+          lrow[q] = lineage ? s_did[lo] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < RX_ITEMS; ++q)
+          if (cb + (uint32_t)q * RW_WAVES < nch) fold(act[q], jj[q], dkey[q], irow[q], x[q], lrow[q]);
+      }
+    } else {
+      // many driver rows: each output searches its row among the group's
+      // offsets in global memory
+      for (uint32_t t0 = s0; t0 < s1; t0 += TILE) {
+#pragma unroll
+        for (int q = 0; q < RX_ITEMS; ++q) {
+          if (t0 + (uint32_t)(q * RW_BLOCK) >= s1) break;  // uniform across the block
+          const uint32_t j = t0 + (uint32_t)(q * RW_BLOCK) + threadIdx.x;
+          const bool act = j < s1;
+          uint32_t lo = 0, hi = nr;  // invariant: start(lo) <= j < start(hi)
+          while (act && hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (offs[r0 + mid] <= j) lo = mid;
+            else hi = mid;
+          }
+          const uint32_t r = r0 + lo;
+          const K dkey = act ? dk[r] : (K)0;
+          const uint32_t irow = act ? a.istart[r] + (j - offs[r]) : 0u;
+          float x = 0.0f;
+          if constexpr (TK == TAG_F32) x = act ? dt[r] : 0.0f;
+          fold(act, j, dkey, irow, x, (lineage && act) ? a.dids[r] : 0u);
         }
       }
     }

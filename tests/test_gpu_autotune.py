@@ -96,3 +96,30 @@ def test_row_windows_batched(oracle, synth, tmp_path, rows):
             o.backward("path", gout)
             np.testing.assert_allclose(e.grad("edge", g["src"].size), o.grad("edge", g["src"].size),
                                        rtol=1e-4, atol=1e-6)
+
+
+@pytest.mark.parametrize("sr", ["maxmin", "addmult", "bool"])
+def test_row_windows_hub_driver(oracle, synth, tmp_path, sr):
+    """A driver group with more rows than the LDS row staging holds (a hub
+    with 400 out-edges) takes the global-memory row search."""
+    from paper_2503_21937_amd import dlfix
+    rng = np.random.default_rng(12)
+    n = 600
+    src0, dst0, _ = synth.er_graph(12, n, 1500, weights=True)
+    hub = np.zeros(400, np.uint32)
+    hub_dst = rng.choice(np.arange(1, n, dtype=np.uint32), 400, replace=False)
+    src = np.concatenate([src0, hub]).astype(np.uint32)
+    dst = np.concatenate([dst0, hub_dst]).astype(np.uint32)
+    p = rng.uniform(0.05, 0.9, src.size).astype(np.float32)
+    e = make_engine(synth, sr, src, dst, p)
+    key = _key(e)
+    cache = tmp_path / "hub.jsonl"
+    cache.write_text(json.dumps({"key": key, "dedup": 2, "orient": 2, "items": 2, "rows": 2, "ms": 1.0}) + "\n")
+    assert e.autotune(1, str(cache))["rows"] == 2
+    got = e.read("path")
+    want = oracle_run(oracle, synth.TC_PROGRAM, sr, {"edge": ([src, dst], p, None)}).read("path")
+    assert np.array_equal(got["cols"], want["cols"])
+    if sr == "maxmin":
+        assert np.array_equal(got["tags"].astype(np.float64), want["value"])
+    elif sr == "addmult":
+        assert_tags_close(got["tags"], want["value"])
