@@ -189,6 +189,9 @@ def main() -> int:
     ap.add_argument("--no-grids", action="store_true", help="skip the batched fwd+bwd grid workload")
     ap.add_argument("--plain-samples", type=int, default=32)
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuner; use default configurations")
+    ap.add_argument("--tune-cache", default=None, metavar="PATH",
+                    help="autotuner cache to read and extend (default: a fresh temporary file); a profiled "
+                         "run that reuses the cache of an earlier run executes no tuning trials")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -209,7 +212,8 @@ def main() -> int:
         return 0
     src, dst, p = synth.er_graph(args.seed, args.nodes, args.edges, weights=True)
     import tempfile
-    tune_cache = None if args.no_tune else os.path.join(tempfile.mkdtemp(prefix="dlfix_bench_"), "tune.jsonl")
+    tune_cache = None if args.no_tune else (
+        args.tune_cache or os.path.join(tempfile.mkdtemp(prefix="dlfix_bench_"), "tune.jsonl"))
     engines = []
     for sr in SEMIRINGS:
         e = dlfix.Engine(synth.TC_PROGRAM, sr)

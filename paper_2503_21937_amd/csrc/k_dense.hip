@@ -323,11 +323,17 @@ constexpr int RW_ROWS = 255;   // driver rows of a group staged in LDS (4 workgr
 constexpr int RW_BLOCK = 512;  // 8 waves: the window's LDS is shared by more waves
 constexpr int RW_WAVES = RW_BLOCK / WAVE;
 
-template <typename K, int TK, int RX_ITEMS>
+// FM >= 0 selects the specialised variant for the most common shape: 32-bit
+// keys, one sample, a binary head whose second column comes from the index
+// row, no lineage, and the dense mode FM with its semiring's product (min for
+// DENSE_MAX, + for DENSE_MIN, * for DENSE_ADD); FM = -1 is the general one.
+template <typename K, int TK, int RX_ITEMS, int FM>
 __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, const uint32_t* __restrict__ offs,
                                                                size_t total_h, const uint64_t* __restrict__ dtotal,
-                                                               DenseArgs d, RowWindows rw, int lineage) {
+                                                               DenseArgs d, RowWindows rw, int lineage_arg) {
   using T = typename TagOf<TK>::T;
+  constexpr bool FAST = FM >= 0;
+  const int lineage = FAST ? 0 : lineage_arg;
   constexpr int TILE = RW_BLOCK * RX_ITEMS;
   __shared__ uint32_t s_tag[TK == TAG_F32 ? RW_KEYS : 1];
   __shared__ uint32_t s_pres[RW_KEYS / 32];
@@ -347,6 +353,20 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
   const T* dt = (const T*)a.dtags;
   const T* it = (const T*)a.itags;
   const uint32_t pmask = (1u << d.dcbits) - 1u;
+  // Output columns 1.. (column 0 is the group's): which key holds each and
+  // at which shift, fixed for the launch, so a derivation extracts them with
+  // one shift and mask apiece.
+  const int nc = FAST ? 2 : a.olay.ncols;
+  bool from_index[4];
+  uint32_t shf[4], msk[4];
+#pragma unroll
+  for (int c = 1; c < (FAST ? 2 : 4); ++c) {
+    const int s = c < nc ? a.osrc[c] : 0;
+    from_index[c] = s < 0;
+    const KeyLayout& l = s < 0 ? a.ilay : a.dlay;
+    shf[c] = (uint32_t)((l.ncols - 1 - (s < 0 ? -1 - s : s)) * l.cbits);
+    msk[c] = cmask(l.cbits);
+  }
   // The next group's driver rows are fetched while the current one is
   // processed (its CSR bounds at the top, their output slots after the
   // window load), so a group starts without waiting on those loads.
@@ -379,13 +399,13 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
     // W = n^(arity-2) * np for the sample's n and np (a multiple of 32)
     const uint32_t gs = (uint32_t)(g >> d.dcbits), c0 = (uint32_t)g & pmask;
     uint32_t gn_ = d.dn, gnp = d.dnp, gbase = 0;
-    if (d.nsamp > 1) {
+    if (!FAST && d.nsamp > 1) {
       gn_ = d.sn[gs];
       gnp = d.snp[gs];
       gbase = d.sbase[gs];
     }
     uint32_t W = gnp;
-    for (int c = 2; c < a.olay.ncols; ++c) W *= gn_;
+    for (int c = 2; c < nc; ++c) W *= gn_;
     const uint64_t kb = (uint64_t)gbase + (uint64_t)c0 * W;
     const uint32_t NWD = W / 32;
     const size_t wb = kb >> 5;
@@ -419,23 +439,27 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
       }
     }
     __syncthreads();
-    // One derivation: fold it into the window; with lineage, log it if it is
-    // a discovery (called by whole waves: the segment claims are ballots).
-    auto fold = [&](bool act, uint32_t j, K dkey, uint32_t irow, float x, uint32_t lrow) {
+    // One derivation whose index row (key ikey, tag y) is already loaded:
+    // fold it into the window; with lineage, log it if it is a discovery
+    // (called by whole waves: the segment claims are ballots).  A wave loads
+    // the index rows of all its chunks first, so their latencies overlap.
+    // A derivation marks its key when it makes it present or improves its
+    // tag: it then beats the value it read, and the final value beats the
+    // key's value before the launch, so the window's atomics need no result.
+    auto fold = [&](bool act, uint32_t j, K dkey, K ikey, float x, float y, uint32_t irow, uint32_t lrow) {
       bool logit = false;
       K okey = 0;
       if (act) {
-        const K ikey = ik[irow];
-        uint32_t v[4];
-        for (int c = 0; c < a.olay.ncols; ++c) {
-          const int s = a.osrc[c];
-          v[c] = s >= 0 ? key_col(dkey, s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
-        }
         // offset in the window of the prefix (sample, v[0]): the remaining
         // columns in mixed radix (n per middle column, np for the last)
-        uint32_t lk = 0;
-        for (int c = 1; c + 1 < a.olay.ncols; ++c) lk = lk * gn_ + v[c];
-        lk = lk * gnp + v[a.olay.ncols - 1];
+        uint32_t v[4], lk = 0;
+#pragma unroll
+        for (int c = 1; c < 4; ++c) {
+          if (c < nc) {
+            v[c] = (uint32_t)((uint64_t)(from_index[c] ? ikey : dkey) >> shf[c]) & msk[c];
+            lk = lk * (c + 1 < nc ? gn_ : gnp) + v[c];
+          }
+        }
         if (lk >= W) {  // the host only picks this kernel when every key lies in its window
           if (d.overflow) *d.overflow = 2;
         } else {
@@ -443,7 +467,6 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
           const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
           bool mark = false;
           if constexpr (TK == TAG_F32) {
-            const float y = it[irow];
             const float t = a.index_first ? f_otimes(a.sr, y, x) : f_otimes(a.sr, x, y);
             if (d.mode == DENSE_ADD) {
               if (!(s_pres[wi] & bit)) {
@@ -456,18 +479,23 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
               // matters for a derivation that does not beat that zero
               const uint32_t o = to_ordered(t), zero = dense_init_word_dev(d.mode);
               if (d.mode == DENSE_MAX) {
-                mark = o > s_tag[loc] && o > atomicMax(s_tag + loc, o);
-                if (!mark && o <= zero) mark = !(s_pres[wi] & bit);
+                mark = o > s_tag[loc];
+                if (mark) atomicMax(s_tag + loc, o);
+                else if (o <= zero) mark = !(s_pres[wi] & bit);
               } else {
-                mark = o < s_tag[loc] && o < atomicMin(s_tag + loc, o);
-                if (!mark && o >= zero) mark = !(s_pres[wi] & bit);
+                mark = o < s_tag[loc];
+                if (mark) atomicMin(s_tag + loc, o);
+                else if (o >= zero) mark = !(s_pres[wi] & bit);
               }
             }
           } else {
             mark = !(s_pres[wi] & bit);
           }
-          if (mark && !(s_new[wi] & bit)) atomicOr(s_new + wi, bit);
-          if (logit) okey = key_make<K>(key_sample(dkey, a.dlay), v, a.olay);
+          if (mark) atomicOr(s_new + wi, bit);
+          if (logit) {
+            v[0] = key_col(dkey, 0, a.dlay);
+            okey = key_make<K>(key_sample(dkey, a.dlay), v, a.olay);
+          }
         }
       }
       if (lineage) {
@@ -497,10 +525,40 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
         }
       }
     };
+    // Specialised fold (FAST): the head's second column is the index row's
+    // column at shf[1]; the product and the merge are fixed by FM.
+    auto fold_fast = [&](bool act, K ikey, float x, float y) {
+      if (!act) return;
+      const uint32_t loc = (uint32_t)((uint64_t)ikey >> shf[1]) & msk[1];
+      if (loc >= W) {  // the host only picks this kernel when every key lies in its window
+        if (d.overflow) *d.overflow = 2;
+        return;
+      }
+      const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
+      const float p = a.index_first ? y : x, r = a.index_first ? x : y;  // body order of the operands
+      bool mark;
+      if constexpr (FM == DENSE_BOOL) {
+        mark = !(s_pres[wi] & bit);
+      } else if constexpr (FM == DENSE_ADD) {
+        mark = !(s_pres[wi] & bit);
+        if (mark) atomicAdd(reinterpret_cast<float*>(s_tag) + loc, __fmul_rn(p, r));
+      } else if constexpr (FM == DENSE_MAX) {
+        const uint32_t o = to_ordered(fminf(p, r));
+        mark = o > s_tag[loc];
+        if (mark) atomicMax(s_tag + loc, o);
+        else if (o <= 0x80000000u) mark = !(s_pres[wi] & bit);  // does not beat the zero +0.0
+      } else {
+        const uint32_t o = to_ordered(__fadd_rn(p, r));
+        mark = o < s_tag[loc];
+        if (mark) atomicMin(s_tag + loc, o);
+        else if (o >= (0x7f800000u | 0x80000000u)) mark = !(s_pres[wi] & bit);  // does not beat +inf
+      }
+      if (mark) atomicOr(s_new + wi, bit);
+    };
     if (lds_rows) {
-      // Chunks of 64 consecutive outputs of one driver row, taken by the
-      // waves in turn: a wave's lanes share the row (its key, tag and index
-      // base are read once per chunk), and no lane searches for its row.
+      // Chunks of 64 consecutive outputs of one driver row; every wave takes
+      // a contiguous range of chunks and walks the rows along it (a wave's
+      // lanes share the row: its key, tag and index base are LDS broadcasts).
       if (threadIdx.x < WAVE) {  // chunk counts of the rows, scanned by one wave
         uint32_t cnt[4], sum = 0;
 #pragma unroll
@@ -520,54 +578,91 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
       __syncthreads();
       const uint32_t nch = s_cpre[nr], wv = threadIdx.x / WAVE;
       const uint32_t lane = (uint32_t)lane_id();
-      for (uint32_t cb = wv; cb < nch; cb += RW_WAVES * RX_ITEMS) {  // uniform per wave
+      const uint32_t per = (nch + RW_WAVES - 1) / RW_WAVES;
+      uint32_t c = wv * per;
+      const uint32_t ce = c + per < nch ? c + per : nch;
+      // the row state is uniform per wave: read from LDS into scalars
+      auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
+      uint32_t lo = 0;
+      if (c < ce) {  // the row of chunk c: s_cpre[lo] <= c < s_cpre[lo + 1]
+        uint32_t hi = nr;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (uni(s_cpre[mid]) <= c) lo = mid;
+          else hi = mid;
+        }
+      }
+      for (; c < ce; c += RX_ITEMS) {  // uniform per wave
         bool act[RX_ITEMS];
         uint32_t jj[RX_ITEMS], irow[RX_ITEMS], lrow[RX_ITEMS];
-        K dkey[RX_ITEMS];
-        float x[RX_ITEMS];
+        K dkey[RX_ITEMS], ikey[RX_ITEMS];
+        float x[RX_ITEMS], y[RX_ITEMS];
 #pragma unroll
         for (int q = 0; q < RX_ITEMS; ++q) {
-          const uint32_t c = cb + (uint32_t)q * RW_WAVES;
-          uint32_t lo = 0, hi = nr;  // last row whose first chunk is at or before c
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (s_cpre[mid] <= c) lo = mid;
-            else hi = mid;
-          }
-          const uint32_t j = s_offs[lo] + (c - s_cpre[lo]) * WAVE + lane;
-          act[q] = c < nch && j < s_offs[lo + 1];
+          const uint32_t cq = c + (uint32_t)q;
+          if (cq < ce)
+            while (uni(s_cpre[lo + 1]) <= cq) ++lo;  // empty rows own no chunk
+          const uint32_t j = uni(s_offs[lo]) + (cq - uni(s_cpre[lo])) * WAVE + lane;
+          act[q] = cq < ce && j < uni(s_offs[lo + 1]);
           jj[q] = j;
-          dkey[q] = s_dkey[lo];
-          irow[q] = s_ibase[lo] + j;
+          if constexpr (sizeof(K) == 8)
+            dkey[q] = ((K)uni((uint32_t)(s_dkey[lo] >> 32)) << 32) | (K)uni((uint32_t)s_dkey[lo]);
+          else
+            dkey[q] = (K)uni((uint32_t)s_dkey[lo]);
+          irow[q] = uni(s_ibase[lo]) + j;
           x[q] = 0.0f;
-          if constexpr (TK == TAG_F32) x[q] = s_dtag[lo];
-          lrow[q] = lineage ? s_did[lo] : 0u;
+          if constexpr (TK == TAG_F32) x[q] = __uint_as_float(uni(__float_as_uint(s_dtag[lo])));
+          lrow[q] = lineage ? uni(s_did[lo]) : 0u;
         }
 #pragma unroll
-        for (int q = 0; q < RX_ITEMS; ++q)
-          if (cb + (uint32_t)q * RW_WAVES < nch) fold(act[q], jj[q], dkey[q], irow[q], x[q], lrow[q]);
+        for (int q = 0; q < RX_ITEMS; ++q) {
+          ikey[q] = act[q] ? ik[irow[q]] : (K)0;
+          y[q] = 0.0f;
+          if constexpr (TK == TAG_F32) y[q] = act[q] ? it[irow[q]] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < RX_ITEMS; ++q) {
+          if constexpr (FAST) fold_fast(act[q], ikey[q], x[q], y[q]);
+          else if (c + (uint32_t)q < ce) fold(act[q], jj[q], dkey[q], ikey[q], x[q], y[q], irow[q], lrow[q]);
+        }
       }
     } else {
       // many driver rows: each output searches its row among the group's
       // offsets in global memory
       for (uint32_t t0 = s0; t0 < s1; t0 += TILE) {
+        bool act[RX_ITEMS];
+        uint32_t jj[RX_ITEMS], irow[RX_ITEMS], lrow[RX_ITEMS];
+        K dkey[RX_ITEMS], ikey[RX_ITEMS];
+        float x[RX_ITEMS], y[RX_ITEMS];
 #pragma unroll
         for (int q = 0; q < RX_ITEMS; ++q) {
-          if (t0 + (uint32_t)(q * RW_BLOCK) >= s1) break;  // uniform across the block
           const uint32_t j = t0 + (uint32_t)(q * RW_BLOCK) + threadIdx.x;
-          const bool act = j < s1;
+          act[q] = j < s1;
           uint32_t lo = 0, hi = nr;  // invariant: start(lo) <= j < start(hi)
-          while (act && hi - lo > 1) {
+          while (act[q] && hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
             if (offs[r0 + mid] <= j) lo = mid;
             else hi = mid;
           }
           const uint32_t r = r0 + lo;
-          const K dkey = act ? dk[r] : (K)0;
-          const uint32_t irow = act ? a.istart[r] + (j - offs[r]) : 0u;
-          float x = 0.0f;
-          if constexpr (TK == TAG_F32) x = act ? dt[r] : 0.0f;
-          fold(act, j, dkey, irow, x, (lineage && act) ? a.dids[r] : 0u);
+          jj[q] = j;
+          dkey[q] = act[q] ? dk[r] : (K)0;
+          irow[q] = act[q] ? a.istart[r] + (j - offs[r]) : 0u;
+          x[q] = 0.0f;
+          if constexpr (TK == TAG_F32) x[q] = act[q] ? dt[r] : 0.0f;
+          lrow[q] = (lineage && act[q]) ? a.dids[r] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < RX_ITEMS; ++q) {
+          ikey[q] = act[q] ? ik[irow[q]] : (K)0;
+          y[q] = 0.0f;
+          if constexpr (TK == TAG_F32) y[q] = act[q] ? it[irow[q]] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < RX_ITEMS; ++q) {
+          if constexpr (FAST) fold_fast(act[q], ikey[q], x[q], y[q]);
+          else if (t0 + (uint32_t)(q * RW_BLOCK) < s1)  // uniform across the block
+            fold(act[q], jj[q], dkey[q], ikey[q], x[q], y[q], irow[q], lrow[q]);
         }
       }
     }
@@ -576,9 +671,15 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
       const uint32_t nb = s_new[i];
       if (nb) d.touched[wb + i] |= nb;
     }
-    if constexpr (TK == TAG_F32)
-      for (uint32_t i = threadIdx.x; i < W; i += RW_BLOCK)
-        if (s_new[i >> 5] >> (i & 31) & 1u) d.dtag[kb + i] = s_tag[i];
+    if constexpr (TK == TAG_F32) {
+      // four keys per thread: one 16-byte store when any of them changed (an
+      // unchanged key is rewritten with the value it had at the launch's
+      // start: no other workgroup writes this window)
+      uint4* dst = reinterpret_cast<uint4*>(d.dtag + kb);
+      const uint4* src = reinterpret_cast<const uint4*>(s_tag);
+      for (uint32_t i = threadIdx.x; i < W / 4; i += RW_BLOCK)
+        if ((s_new[i >> 3] >> ((i & 7) * 4)) & 0xfu) dst[i] = src[i];
+    }
     __syncthreads();  // the window's LDS is reloaded for the next group
     r0 = nr0, r1 = nr1, s0 = ns0, s1 = ns1;
   }
@@ -610,17 +711,41 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   if (rows && lineage) fill_u32(d.seg_lcount + d.seg_base, dense_segments(total, items), 0u, st);
   const uint64_t skip_at = rows ? rw->from : ~0ull;
   const unsigned nrb = rows ? (unsigned)(rw->ngroups < 2048 ? rw->ngroups : 2048) : 0u;
+  // the specialised row-window variant (see k_join_expand_rows)
+  int fm = -1;
+  if (rows && sizeof(K) == 4 && d.nsamp <= 1 && !lineage && a.olay.ncols == 2 && a.osrc[1] < 0) {
+    if (tk == TAG_NONE && d.mode == DENSE_BOOL) fm = DENSE_BOOL;
+    else if (tk == TAG_F32 && d.mode == DENSE_ADD && (a.sr == SR_ADDMULT || a.sr == SR_DIFF_ADDMULT)) fm = DENSE_ADD;
+    else if (tk == TAG_F32 && d.mode == DENSE_MAX && a.sr == SR_MAXMIN) fm = DENSE_MAX;
+    else if (tk == TAG_F32 && d.mode == DENSE_MIN && a.sr == SR_MINPLUS) fm = DENSE_MIN;
+  }
+#define DL_ROWS(TK, IT, FM) \
+  k_join_expand_rows<K, TK, IT, FM><<<nrb, RW_BLOCK, 0, st>>>(a, offs, total, dtotal, d, *rw, lineage ? 1 : 0)
 #define DL_DEXPAND(IT)                                                                                               \
   if (tk == TAG_F32) {                                                                                               \
     if (!rows || dtotal)                                                                                             \
       k_join_expand_dense<K, TAG_F32, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0, skip_at); \
-    if (rows) k_join_expand_rows<K, TAG_F32, IT><<<nrb, RW_BLOCK, 0, st>>>(a, offs, total, dtotal, d, *rw,         \
-                                                                            lineage ? 1 : 0);                     \
+    if (rows) {                                                                                                      \
+      if constexpr (sizeof(K) == 4) {                                                                                \
+        if (fm == DENSE_MAX) DL_ROWS(TAG_F32, IT, DENSE_MAX);                                                        \
+        else if (fm == DENSE_MIN) DL_ROWS(TAG_F32, IT, DENSE_MIN);                                                   \
+        else if (fm == DENSE_ADD) DL_ROWS(TAG_F32, IT, DENSE_ADD);                                                   \
+        else DL_ROWS(TAG_F32, IT, -1);                                                                               \
+      } else {                                                                                                       \
+        DL_ROWS(TAG_F32, IT, -1);                                                                                    \
+      }                                                                                                              \
+    }                                                                                                                \
   } else {                                                                                                           \
     if (!rows || dtotal)                                                                                             \
       k_join_expand_dense<K, TAG_NONE, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0, skip_at); \
-    if (rows) k_join_expand_rows<K, TAG_NONE, IT><<<nrb, RW_BLOCK, 0, st>>>(a, offs, total, dtotal, d, *rw,        \
-                                                                             lineage ? 1 : 0);                    \
+    if (rows) {                                                                                                      \
+      if constexpr (sizeof(K) == 4) {                                                                                \
+        if (fm == DENSE_BOOL) DL_ROWS(TAG_NONE, IT, DENSE_BOOL);                                                     \
+        else DL_ROWS(TAG_NONE, IT, -1);                                                                              \
+      } else {                                                                                                       \
+        DL_ROWS(TAG_NONE, IT, -1);                                                                                   \
+      }                                                                                                              \
+    }                                                                                                                \
   }
   DL_PROF_BEGIN(1, st);
   switch (items) {
@@ -630,6 +755,7 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
     default: DL_DEXPAND(4) break;
   }
 #undef DL_DEXPAND
+#undef DL_ROWS
   DL_PROF_END(1, st, bytes);
   if (dtotal) DL_PROF_DEFER(1, per);
 }

@@ -123,3 +123,37 @@ def test_row_windows_hub_driver(oracle, synth, tmp_path, sr):
         assert np.array_equal(got["tags"].astype(np.float64), want["value"])
     elif sr == "addmult":
         assert_tags_close(got["tags"], want["value"])
+
+
+SHAPES_PROGRAM = """
+.input edge/2
+.output hop/3
+.output via/2
+path(x, y) :- edge(x, y).
+path(x, z) :- edge(x, y), path(y, z).
+hop(x, y, z) :- edge(x, y), path(y, z).
+via(x, y) :- edge(x, y), path(y, z).
+"""
+
+
+@pytest.mark.parametrize("sr", ["maxmin", "minplus", "addmult", "bool"])
+def test_row_windows_general_shapes(oracle, synth, tmp_path, sr):
+    """Row windows forced onto heads the specialised variant does not take:
+    a ternary head (window of n * np keys) and a binary head whose second
+    column comes from the driver row."""
+    from paper_2503_21937_amd import dlfix
+    src, dst, p = synth.er_graph(21, 60, 200, weights=True)
+    e = dlfix.Engine(SHAPES_PROGRAM, sr)
+    e.add_facts("edge", [src, dst], p)
+    key = _key(e)
+    cache = tmp_path / "shapes.jsonl"
+    cache.write_text(json.dumps({"key": key, "dedup": 2, "orient": 2, "items": 2, "rows": 2, "ms": 1.0}) + "\n")
+    assert e.autotune(1, str(cache))["rows"] == 2
+    o = oracle_run(oracle, SHAPES_PROGRAM, sr, {"edge": ([src, dst], p, None)})
+    for rel in ("path", "hop", "via"):
+        got, want = e.read(rel), o.read(rel)
+        assert np.array_equal(got["cols"], want["cols"]), rel
+        if sr == "maxmin":
+            assert np.array_equal(got["tags"].astype(np.float64), want["value"]), rel
+        elif sr in ("addmult", "minplus"):
+            assert_tags_close(got["tags"], want["value"], what=rel)
