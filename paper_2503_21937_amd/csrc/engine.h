@@ -145,6 +145,7 @@ struct Engine {
       scratch, unpack, qbuf;
   uint64_t* host = nullptr;  // pinned readback words
   DevBuf dtotal;             // device words for totals
+  DevBuf cs_state;           // single-pass count+scan: tile sums and flags (kept zeroed between launches)
 
   dl_stats stats{};
   uint64_t deferred_units = 0;  // derivations of joins whose totals stayed on the device (last run)

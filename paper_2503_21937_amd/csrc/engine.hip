@@ -71,7 +71,7 @@ Engine::~Engine() {
   }
   for (DevBuf* b : {&d_sn, &d_snp, &qtab, &grad_fact, &lin_owner, &lin_l, &lin_r, &tag_by_id, &adj, &counts, &offs, &istart, &alt_keys, &alt_vals, &vals, &flags, &pos, &ukeys, &utags, &status,
                     &nflags, &newpos, &rflags, &rpos, &lf, &lpos, &nkeys, &ntags, &nids, &tmpA_keys, &tmpA_tags,
-                    &tmpB_keys, &tmpB_tags, &scratch, &unpack, &qbuf, &dtotal})
+                    &tmpB_keys, &tmpB_tags, &scratch, &unpack, &qbuf, &dtotal, &cs_state})
     fr(*b);
   if (host) (void)hipHostFree(host);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -161,6 +161,8 @@ void Engine::init(const char* program_text, const dl_options* o) {
   }
   DL_HIP(hipHostMalloc((void**)&host, 64 * sizeof(uint64_t), hipHostMallocDefault));
   grow(dtotal, 64 * sizeof(uint64_t));
+  grow(cs_state, count_scan_state_words() * sizeof(uint64_t));
+  fill_u32(cs_state.as<uint32_t>(), count_scan_state_words() * 2, 0u, stream);
   if (o->lineage < 0 || o->lineage > 2) throw Error{DL_ERR_ARG, "lineage must be 0, 1 or 2"};
   if (o->lineage == 0 && o->lineage_budget) {
     lin_budget = o->lineage_budget;

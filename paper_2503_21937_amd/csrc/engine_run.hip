@@ -59,6 +59,7 @@ void claim(DevBuf& owner, DevBuf& alt, const void* result) {
 void check_overflow(Engine& e) {
   const uint64_t f = e.host[S_OVF];
   if (f == 1) throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
+  if (f == 3) throw Error{DL_ERR_HIP, "join count scan: a look-back wait did not end"};
   if (f) throw Error{DL_ERR_HIP, "row-window join: a derivation fell outside its window"};
 }
 
@@ -297,11 +298,13 @@ bool row_windows(Engine& e, const Plan& pl, RowWindows* rw) {
   rw->goff = D.goff.as<uint32_t>();
   rw->ngroups = groups;
   rw->wkeys = (uint32_t)wkeys;
-  // at least one derivation per 8 keys of the head's dense domain (all
-  // windows), and ~512 per driver group so that a group's fixed latency
-  // (bounds, window load and write-back) is amortised
-  const uint64_t per_keys = (uint64_t)e.rel[pl.head_rel].dense_keys / 8;
-  const uint64_t per_group = (uint64_t)std::min(groups, D.full.n) * 512;
+  // at least one derivation per 12 keys of the head's dense domain: the
+  // window loads and write-backs (8 bytes a key) then cost about what the
+  // scattered kernel spends on that many derivations (~100 bytes of HBM
+  // traffic each in latency terms); and ~128 per driver group so that a
+  // group's fixed latency (bounds, barriers) is amortised
+  const uint64_t per_keys = (uint64_t)e.rel[pl.head_rel].dense_keys / 12;
+  const uint64_t per_group = (uint64_t)std::min(groups, D.full.n) * 128;
   rw->from = e.cfg.rows == 2 ? 0 : std::max(per_keys, per_group);
   return true;
 }
@@ -417,12 +420,15 @@ void run_plan(Engine& e, const Plan& pl) {
     e.grow(e.offs, (cur.n + 1) * 4);
     e.grow(e.istart, cur.n * 4 + 4);
     a.istart = e.istart.as<uint32_t>();
-    join_count<K>(a, e.counts.as<uint32_t>(), e.stream);
     const bool nosync = si + 1 == pl.steps.size() && H.dense && !e.record;
     // without a host readback the scan also adds its total to the run's
     // candidate count (collected at round end)
-    scan(e, e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), cur.n, S_SCAN, true,
-         nosync ? total_slot(e, S_CAND) : nullptr);
+    if (!join_count_scan<K>(a, e.offs.as<uint32_t>(), e.cs_state.as<uint64_t>(), total_slot(e, S_SCAN),
+                            nosync ? total_slot(e, S_CAND) : nullptr, total_slot(e, S_OVF), e.stream)) {
+      join_count<K>(a, e.counts.as<uint32_t>(), e.stream);
+      scan(e, e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), cur.n, S_SCAN, true,
+           nosync ? total_slot(e, S_CAND) : nullptr);
+    }
     if (nosync) {
       // no host readback: the expand reads the total on the device; the
       // candidate count and any 32-bit overflow are collected at round end
@@ -776,9 +782,12 @@ void enqueue_round_body(Engine& e, int r, const std::vector<const Plan*>& plans)
     csr_build_dn<K>(R.recent.keys.as<K>(), total_slot(e, S_UNIQUE), e.key_width(ar), pbits,
                     e.idx[step.index].off.as<uint32_t>(), st);
     const JoinArgs a = batch_join_args<K>(e, *tw, R, ar);
-    join_count<K>(a, e.counts.as<uint32_t>(), st);
-    scan_u32(e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), a.n, total_slot(e, S_SCAN), true,
-             e.scratch.as<uint64_t>(), st, total_slot(e, S_CAND));
+    if (!join_count_scan<K>(a, e.offs.as<uint32_t>(), e.cs_state.as<uint64_t>(), total_slot(e, S_SCAN),
+                            total_slot(e, S_CAND), total_slot(e, S_OVF), st)) {
+      join_count<K>(a, e.counts.as<uint32_t>(), st);
+      scan_u32(e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), a.n, total_slot(e, S_SCAN), true,
+               e.scratch.as<uint64_t>(), st, total_slot(e, S_CAND));
+    }
     DenseArgs d = dense_args(e, R);
     RowWindows rw{};
     const bool rows = e.cfg.rows && row_windows<K>(e, *tw, &rw);

@@ -576,7 +576,10 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
         }
       }
       __syncthreads();
-      const uint32_t nch = s_cpre[nr], wv = threadIdx.x / WAVE;
+      // wave-uniform (scalar) chunk bounds: the compiler cannot see that
+      // threadIdx.x / WAVE is the same on every lane
+      const uint32_t nch = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_cpre[nr]);
+      const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
       const uint32_t lane = (uint32_t)lane_id();
       const uint32_t per = (nch + RW_WAVES - 1) / RW_WAVES;
       uint32_t c = wv * per;
@@ -710,7 +713,10 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
                     (dtotal || total >= rw->from);
   if (rows && lineage) fill_u32(d.seg_lcount + d.seg_base, dense_segments(total, items), 0u, st);
   const uint64_t skip_at = rows ? rw->from : ~0ull;
-  const unsigned nrb = rows ? (unsigned)(rw->ngroups < 2048 ? rw->ngroups : 2048) : 0u;
+  // one workgroup per group (up to 16384; beyond, workgroups loop): the
+  // dispatcher hands the next group to whichever CU frees a slot first, which
+  // balances groups of very different sizes
+  const unsigned nrb = rows ? (unsigned)(rw->ngroups < 16384 ? rw->ngroups : 16384) : 0u;
   // the specialised row-window variant (see k_join_expand_rows)
   int fm = -1;
   if (rows && sizeof(K) == 4 && d.nsamp <= 1 && !lineage && a.olay.ncols == 2 && a.osrc[1] < 0) {

@@ -166,6 +166,102 @@ void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st) {
 }
 
 
+// Join counts and their exclusive scan in one launch (single-pass scan with
+// a look-back over tile sums).  Workgroup b counts the matches of its tile of
+// CS_TILE driver rows, publishes the tile sum (the sum, then a flag), adds
+// the sums of all tiles before it and writes its offsets.  It waits only on
+// lower-numbered workgroups, which were dispatched before it and publish
+// before they wait, so every wait ends; the wait is also bounded (flag 3 in
+// *err, never expected).  The last tile writes the total; the last workgroup
+// to finish clears the flags for the next launch.
+constexpr int CS_ITEMS = 1;
+constexpr int CS_TILE = BLOCK * CS_ITEMS;
+
+size_t count_scan_state_words() { return CS_MAX_TILES * 3 + 2; }
+
+template <typename K>
+__global__ __launch_bounds__(BLOCK) void k_join_count_scan(JoinArgs a, uint32_t* __restrict__ offs,
+                                                           uint64_t* __restrict__ state, uint64_t* __restrict__ d_total,
+                                                           uint64_t* __restrict__ acc, uint64_t* __restrict__ err) {
+  __shared__ uint64_t tmp[NWAVES], s_pre[NWAVES];
+  __shared__ int s_last;
+  uint64_t* sums = state;
+  uint32_t* flags = reinterpret_cast<uint32_t*>(state + CS_MAX_TILES);
+  uint32_t* done = flags + CS_MAX_TILES;
+  const K* dk = (const K*)a.dkeys;
+  const size_t base = (size_t)blockIdx.x * CS_TILE + (size_t)threadIdx.x * CS_ITEMS;
+  uint32_t c[CS_ITEMS];
+  uint64_t s = 0;
+#pragma unroll
+  for (int q = 0; q < CS_ITEMS; ++q) {
+    const size_t i = base + q;
+    c[q] = 0;
+    if (i < a.n) {
+      const uint64_t p = join_prefix(dk[i], a);
+      const uint32_t b = a.off[p];
+      c[q] = a.off[p + 1] - b;
+      if (a.istart) a.istart[i] = b;
+    }
+    s += c[q];
+  }
+  uint64_t tot;
+  const uint64_t ex = block_exclusive_scan(s, tmp, &tot);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(sums + blockIdx.x, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(flags + blockIdx.x, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  uint64_t pre = 0;
+  for (size_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(flags + i, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      if (++spins > (1u << 24)) {
+        *err = 3;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    pre += __hip_atomic_load(sums + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  pre = wave_sum(pre);
+  if (lane_id() == 0) s_pre[threadIdx.x / WAVE] = pre;
+  __syncthreads();
+  const uint64_t carry = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3];
+  uint64_t run = carry + ex;
+#pragma unroll
+  for (int q = 0; q < CS_ITEMS; ++q) {
+    if (base + q < a.n) offs[base + q] = (uint32_t)run;
+    run += c[q];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    const uint64_t total = carry + tot;
+    *d_total = total;
+    offs[a.n] = (uint32_t)total;
+    if (acc) *acc += total;
+  }
+  __syncthreads();  // every look-back read of this workgroup is done
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last) {
+    for (size_t i = threadIdx.x; i < gridDim.x; i += BLOCK)
+      __hip_atomic_store(flags + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <typename K>
+bool join_count_scan(const JoinArgs& a, uint32_t* offs, uint64_t* state, uint64_t* d_total, uint64_t* acc,
+                     uint64_t* err, hipStream_t st) {
+  const size_t nt = (a.n + CS_TILE - 1) / CS_TILE;
+  if (a.n == 0 || nt > CS_MAX_TILES) return false;
+  DL_PROF_BEGIN(0, st);
+  k_join_count_scan<K><<<(unsigned)nt, BLOCK, 0, st>>>(a, offs, state, d_total, acc, err);
+  DL_PROF_END(0, st, a.n * (sizeof(K) + 12.0));
+  return true;
+}
+
 template <typename K, int TK, int EXP_ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_join_expand(JoinArgs a, const uint32_t* __restrict__ offs, size_t total,
                                                        K* __restrict__ okeys, typename TagOf<TK>::T* __restrict__ otags,
@@ -830,6 +926,7 @@ void topk_backward_rows(const TopK* t, const K* keys, KeyLayout lay, const int64
   template void csr_build<K>(const K*, size_t, int, int, uint32_t*, hipStream_t);                                   \
   template void csr_build_dn<K>(const K*, const uint64_t*, int, int, uint32_t*, hipStream_t);                       \
   template void join_count<K>(const JoinArgs&, uint32_t*, hipStream_t);                                             \
+  template bool join_count_scan<K>(const JoinArgs&, uint32_t*, uint64_t*, uint64_t*, uint64_t*, uint64_t*, hipStream_t);                                             \
   template void join_expand<K>(const JoinArgs&, int, const uint32_t*, size_t, void*, void*, uint32_t*, uint32_t*,   \
                                hipStream_t);                                                                         \
   template void project_rows<K>(const JoinArgs&, int, void*, void*, uint32_t*, uint32_t*, hipStream_t);             \

@@ -146,6 +146,16 @@ uint32_t dense_init_word(int mode);
 // counts[i] = number of index rows matching driver row i.
 template <typename K>
 void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st);  // also fills a.istart if set
+// Counts and their exclusive scan (offs[0..n], total in *d_total, added to
+// *acc when set) in one launch for up to CS_MAX_TILES tiles of 2048 driver
+// rows; false (nothing launched) otherwise or when n == 0.  `state` holds
+// count_scan_state_words() zeroed words, left zeroed; *err = 3 reports a
+// look-back wait that did not end.
+constexpr size_t CS_MAX_TILES = 2048;
+size_t count_scan_state_words();
+template <typename K>
+bool join_count_scan(const JoinArgs& a, uint32_t* offs, uint64_t* state, uint64_t* d_total, uint64_t* acc,
+                     uint64_t* err, hipStream_t st);
 // Emit every match: slot j of row i (offs = exclusive scan of counts, with
 // sentinel).  Writes keys (and tags, lineage pairs if non-NULL) at out + j.
 template <typename K>
