@@ -769,9 +769,20 @@ JoinArgs batch_join_args(Engine& e, const Plan& tw, RelState& R, int ar) {
   return a;
 }
 
-// Enqueue one round body (no host interaction: capturable).
+// Whether the round end can write the recent index's CSR itself (see
+// DenseCsr): one plan, one sample, an index on the first column of the
+// recent tuples in key order.
+bool finalize_writes_csr(const Engine& e, int r, const std::vector<const Plan*>& plans) {
+  if (plans.size() != 1 || e.batched || e.prog.rels[r].arity < 2) return false;
+  const IndexSpec& spec = e.prog.indexes[plans[0]->steps[0].index];
+  return spec.rel == r && spec.w == 1 && spec.identity() && spec.recent;
+}
+
+// Enqueue one round body (no host interaction: capturable).  With
+// `fin_csr` the previous body's round end (or the caller, before the first
+// body) has written the recent index.
 template <typename K>
-void enqueue_round_body(Engine& e, int r, const std::vector<const Plan*>& plans) {
+void enqueue_round_body(Engine& e, int r, const std::vector<const Plan*>& plans, bool fin_csr) {
   RelState& R = e.rel[r];
   hipStream_t st = e.stream;
   const int ar = e.prog.rels[r].arity;
@@ -779,8 +790,9 @@ void enqueue_round_body(Engine& e, int r, const std::vector<const Plan*>& plans)
     const Step& step = tw->steps[0];
     const IndexSpec& spec = e.prog.indexes[step.index];
     const int pbits = e.sbits + spec.w * e.cbits;
-    csr_build_dn<K>(R.recent.keys.as<K>(), total_slot(e, S_UNIQUE), e.key_width(ar), pbits,
-                    e.idx[step.index].off.as<uint32_t>(), st);
+    if (!fin_csr)
+      csr_build_dn<K>(R.recent.keys.as<K>(), total_slot(e, S_UNIQUE), e.key_width(ar), pbits,
+                      e.idx[step.index].off.as<uint32_t>(), st);
     const JoinArgs a = batch_join_args<K>(e, *tw, R, ar);
     if (!join_count_scan<K>(a, e.offs.as<uint32_t>(), e.cs_state.as<uint64_t>(), total_slot(e, S_SCAN),
                             total_slot(e, S_CAND), total_slot(e, S_OVF), st)) {
@@ -801,9 +813,14 @@ void enqueue_round_body(Engine& e, int r, const std::vector<const Plan*>& plans)
   if (pre)
     scan_u32(e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, total_slot(e, S_UNIQUE), true, e.scratch.as<uint64_t>(),
              st);
+  DenseCsr csr;
+  if (fin_csr) {
+    const uint32_t n = e.max_id + 1;
+    csr = dense_csr(e.idx[plans[0]->steps[0].index].off.as<uint32_t>(), (uint32_t)(R.dense_keys / n / 32), n);
+  }
   dense_finalize<K>(d, R.dense_keys, (pre ? e.pos : e.flags).as<uint32_t>(), R.recent.keys.as<K>(),
                     e.tag_kind == TAG_F32 ? R.recent.tags.as<float>() : nullptr, 0, nullptr, total_slot(e, S_UNIQUE),
-                    st, total_slot(e, S_LOG), pre);
+                    st, total_slot(e, S_LOG), pre, fin_csr ? &csr : nullptr);
 }
 
 // Rounds 2.. of an eligible stratum in batches of device-sized round bodies;
@@ -832,6 +849,13 @@ int batch_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
   const size_t nb = dense_count_blocks(R.dense_keys);
   e.grow(e.flags, nb * 4);
   e.grow(e.pos, (nb + 1) * 4);
+  // the first body's recent index (later ones come from the round ends)
+  const bool fin_csr = finalize_writes_csr(e, r, plans);
+  if (fin_csr) {
+    const int ir = plans[0]->steps[0].index;
+    csr_build<K>(R.recent.keys.as<K>(), R.recent.n, e.key_width(e.prog.rels[r].arity), e.sbits + e.cbits,
+                 e.idx[ir].off.as<uint32_t>(), e.stream);
+  }
   e.sync();
 
   // Rounds go in batches of BATCH_ROUNDS round bodies: the host syncs once
@@ -842,7 +866,7 @@ int batch_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
   // refused -- the same launches enqueued directly.
   auto enqueue_batch = [&] {
     fill_u32(reinterpret_cast<uint32_t*>(total_slot(e, S_LOG)), 2, 0u, e.stream);  // log entries = 0
-    for (int i = 0; i < BATCH_ROUNDS; ++i) enqueue_round_body<K>(e, r, plans);
+    for (int i = 0; i < BATCH_ROUNDS; ++i) enqueue_round_body<K>(e, r, plans, fin_csr);
     DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, e.stream));
   };
   hipGraph_t graph = nullptr;

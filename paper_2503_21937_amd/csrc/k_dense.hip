@@ -925,12 +925,21 @@ __device__ __forceinline__ uint32_t block_first_slot(const uint32_t* __restrict_
   return o;
 }
 
+DenseCsr dense_csr(uint32_t* off, uint32_t wwords, uint32_t n) {
+  DenseCsr c;
+  c.off = off;
+  c.wwords = wwords;
+  c.n = n;
+  divisor(wwords, &c.m, &c.s1, &c.s2);
+  return c;
+}
+
 template <typename K>
 __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t words, const uint32_t* __restrict__ counts,
                                                           K* __restrict__ keys, float* __restrict__ rtags,
                                                           uint32_t id_base, float* __restrict__ tag_by_id,
                                                           uint64_t* __restrict__ d_total, uint64_t* __restrict__ log,
-                                                          int prefixed) {
+                                                          int prefixed, DenseCsr csr) {
   __shared__ uint32_t s_tot[NWAVES], s_pre[NWAVES];
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
@@ -944,6 +953,25 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
   }
   c = wave_sum(c);
   uint32_t o = block_first_slot(counts, prefixed, c, s_tot, s_pre, d_total, log);
+  if (csr.off) {
+    // group starts: a word wi with wi % wwords == 0 opens first-column group
+    // wi / wwords, whose first key (if any) gets the slot after every set bit
+    // of the words before it
+    uint32_t run = o;
+#pragma unroll
+    for (int i = 0; i < BM_ITEMS; ++i) {
+      const uint32_t cnt = (uint32_t)__popc(b[i]);
+      const uint32_t incl = wave_inclusive_scan(cnt);
+      const size_t wi = w0 + (size_t)i * WAVE + lane;
+      if (wi < words) {
+        const uint32_t q = fast_div((uint32_t)wi, csr.m, csr.s1, csr.s2);
+        if ((uint32_t)wi == q * csr.wwords) csr.off[q] = run + incl - cnt;
+      }
+      run += __shfl(incl, WAVE - 1, WAVE);
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) csr.off[csr.n] = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3] +
+                                                                            s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
+  }
   if (c == 0) return;  // wave-uniform; no barrier follows
   // batched: the sample of the wave's first word, searched once
   const uint32_t s_hint = d.nsamp > 1 ? __shfl(lane == 0 ? dense_sample(d, (uint32_t)(w0 << 5)) : 0u, 0, WAVE) : ~0u;
@@ -979,11 +1007,13 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
 
 template <typename K>
 void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* rtags, uint32_t id_base,
-                    float* tag_by_id, uint64_t* d_total, hipStream_t st, uint64_t* log, bool prefixed) {
+                    float* tag_by_id, uint64_t* d_total, hipStream_t st, uint64_t* log, bool prefixed,
+                    const DenseCsr* csr) {
   const size_t words = bitmap_words(nkeys);
   DL_PROF_BEGIN(6, st);
   k_dense_finalize<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, counts, keys, rtags, id_base, tag_by_id,
-                                                                   d_total, log, prefixed ? 1 : 0);
+                                                                   d_total, log, prefixed ? 1 : 0,
+                                                                   csr ? *csr : DenseCsr{});
   DL_PROF_END(6, st, words * 12.0);
 }
 
@@ -1073,7 +1103,7 @@ void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, bool 
                                      const DenseArgs&, bool, hipStream_t, const RowWindows*);                                                \
   template void project_dense<K>(const JoinArgs&, int, const DenseArgs&, bool, hipStream_t);                        \
   template void dense_finalize<K>(const DenseArgs&, size_t, const uint32_t*, K*, float*, uint32_t, float*, uint64_t*,        \
-                                  hipStream_t, uint64_t*, bool);                                                            \
+                                  hipStream_t, uint64_t*, bool, const DenseCsr*);                                           \
   template void segments_lineage<K>(const DenseArgs&, const uint32_t*, size_t, uint32_t*, uint32_t*, uint32_t*,            \
                                     hipStream_t);                                                                          \
   template void bitmap_keys<K>(const DenseArgs&, size_t, const uint32_t*, bool, K*, float*, uint32_t*, hipStream_t);

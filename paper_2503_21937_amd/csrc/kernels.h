@@ -194,10 +194,23 @@ void bitmap_block_counts(const uint32_t* bits, size_t keys, uint32_t* partial, h
 // lineage, assign ids base.. in key order and record tags by id.  The number
 // of keys goes to *d_total when d_total is not NULL, and is appended to `log`
 // (log[0] = entries, then one per call) when log is not NULL.
+// With `csr` (one sample, an index on the first column over the written
+// keys): also write that index's CSR offsets, off[c] = slot of the first key
+// with first column c for c <= n (the domain's groups are whole bitmap words:
+// a group spans n^(arity-2) * np keys, a multiple of 32), so that the next
+// round needs no separate index build.
+struct DenseCsr {
+  uint32_t* off = nullptr;
+  uint32_t wwords = 0;  // bitmap words per first-column group
+  uint32_t n = 0;       // groups (ids in use)
+  uint32_t m = 0;       // division by wwords: multiply-high and shifts
+  uint8_t s1 = 0, s2 = 0;
+};
+DenseCsr dense_csr(uint32_t* off, uint32_t wwords, uint32_t n);
 template <typename K>
 void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* rtags, uint32_t id_base,
                     float* tag_by_id, uint64_t* d_total, hipStream_t st, uint64_t* log = nullptr,
-                    bool prefixed = false);
+                    bool prefixed = false, const DenseCsr* csr = nullptr);
 // The round's lineage segments (d.seg_lcount entries each, pos = exclusive
 // scan of those counts) compacted into (owner id, left id, right id).
 template <typename K>
