@@ -219,11 +219,17 @@ __device__ __forceinline__ void dense_close(const DenseArgs& d, const WaveSeg& w
 // (tile, tile + gridDim.x, ...).  The total comes from `total`, or from
 // device memory (`dtotal`) when the host did not read it back: then the grid
 // is a fixed size and blocks beyond the last tile exit at once.
-template <typename K, int TK, int DX_ITEMS>
+// FM >= 0: the specialised variant (32-bit keys, one sample, binary head of
+// a driver column and an index column, no lineage, dense mode FM with its
+// semiring's product): the dense index is c0 * dnp + c1, computed from the
+// two columns without building the packed key.
+template <typename K, int TK, int DX_ITEMS, int FM>
 __global__ __launch_bounds__(BLOCK) void k_join_expand_dense(JoinArgs a, const uint32_t* __restrict__ offs,
                                                              size_t total_h, const uint64_t* __restrict__ dtotal,
-                                                             DenseArgs d, int lineage, uint64_t skip_at) {
+                                                             DenseArgs d, int lineage_arg, uint64_t skip_at) {
   using T = typename TagOf<TK>::T;
+  constexpr bool FAST = FM >= 0;
+  const int lineage = FAST ? 0 : lineage_arg;
   constexpr int DX_TILE = BLOCK * DX_ITEMS;
   static_assert(DX_ITEMS * WAVE <= DENSE_SEG, "a wave's outputs must fit its segment");
   __shared__ uint32_t s_row[DX_TILE];
@@ -269,6 +275,64 @@ __global__ __launch_bounds__(BLOCK) void k_join_expand_dense(JoinArgs a, const u
     for (int q = 0; q < DX_ITEMS; ++q) {
       const uint32_t j = (uint32_t)(s0 + (size_t)q * BLOCK + threadIdx.x);
       irow[q] += j - base[q];
+    }
+    if constexpr (FAST) {
+      // column 0 from the driver key, column 1 from the index key
+      const uint32_t sh0 = (uint32_t)((a.dlay.ncols - 1 - a.osrc[0]) * a.dlay.cbits);
+      const uint32_t sh1 = (uint32_t)((a.ilay.ncols - 1 - (-1 - a.osrc[1])) * a.ilay.cbits);
+      const uint32_t m0 = cmask(a.dlay.cbits), m1 = cmask(a.ilay.cbits);
+      uint32_t kk[DX_ITEMS];
+      float tt[DX_ITEMS];
+#pragma unroll
+      for (int q = 0; q < DX_ITEMS; ++q) {
+        kk[q] = 0;
+        tt[q] = 0.0f;
+        if (act[q]) {
+          const K ikey = ik[irow[q]];
+          kk[q] = (((uint32_t)dkey[q] >> sh0) & m0) * d.dnp + (((uint32_t)ikey >> sh1) & m1);
+          if constexpr (TK == TAG_F32) {
+            const float x = dt[row[q]], y = it[irow[q]];
+            const float p = a.index_first ? y : x, r = a.index_first ? x : y;
+            tt[q] = FM == DENSE_ADD ? __fmul_rn(p, r) : FM == DENSE_MAX ? fminf(p, r) : __fadd_rn(p, r);
+          }
+        }
+      }
+      uint32_t pw[DX_ITEMS], tw[DX_ITEMS], cur[DX_ITEMS];
+#pragma unroll
+      for (int q = 0; q < DX_ITEMS; ++q) {
+        pw[q] = tw[q] = cur[q] = 0;
+        if (act[q]) {
+          pw[q] = d.present[kk[q] >> 5];
+          tw[q] = d.touched[kk[q] >> 5];
+          if constexpr (FM == DENSE_MAX || FM == DENSE_MIN) cur[q] = d.dtag[kk[q]];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < DX_ITEMS; ++q) {
+        if (!act[q]) continue;
+        const uint32_t bit = 1u << (kk[q] & 31);
+        const bool present = (pw[q] & bit) != 0u;
+        bool keep;
+        if constexpr (FM == DENSE_BOOL) {
+          keep = !present;
+        } else if constexpr (FM == DENSE_ADD) {
+          keep = !present;
+          if (keep) atomicAdd(reinterpret_cast<float*>(d.dtag) + kk[q], tt[q]);
+        } else if constexpr (FM == DENSE_MAX) {
+          const uint32_t o = to_ordered(tt[q]);
+          keep = o > cur[q];
+          if (keep) atomicMax(d.dtag + kk[q], o);
+          keep = keep || !present;
+        } else {
+          const uint32_t o = to_ordered(tt[q]);
+          keep = o < cur[q];
+          if (keep) atomicMin(d.dtag + kk[q], o);
+          keep = keep || !present;
+        }
+        if (keep && !(tw[q] & bit)) atomicOr(d.touched + (kk[q] >> 5), bit);
+      }
+      __syncthreads();  // s_row is rebuilt for the next tile
+      continue;
     }
 #pragma unroll
     for (int q = 0; q < DX_ITEMS; ++q) {
@@ -717,9 +781,9 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   // dispatcher hands the next group to whichever CU frees a slot first, which
   // balances groups of very different sizes
   const unsigned nrb = rows ? (unsigned)(rw->ngroups < 16384 ? rw->ngroups : 16384) : 0u;
-  // the specialised row-window variant (see k_join_expand_rows)
+  // the specialised variants (see k_join_expand_rows, k_join_expand_dense)
   int fm = -1;
-  if (rows && sizeof(K) == 4 && d.nsamp <= 1 && !lineage && a.olay.ncols == 2 && a.osrc[1] < 0) {
+  if (sizeof(K) == 4 && d.nsamp <= 1 && !lineage && a.olay.ncols == 2 && a.osrc[0] >= 0 && a.osrc[1] < 0) {
     if (tk == TAG_NONE && d.mode == DENSE_BOOL) fm = DENSE_BOOL;
     else if (tk == TAG_F32 && d.mode == DENSE_ADD && (a.sr == SR_ADDMULT || a.sr == SR_DIFF_ADDMULT)) fm = DENSE_ADD;
     else if (tk == TAG_F32 && d.mode == DENSE_MAX && a.sr == SR_MAXMIN) fm = DENSE_MAX;
@@ -727,10 +791,20 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   }
 #define DL_ROWS(TK, IT, FM) \
   k_join_expand_rows<K, TK, IT, FM><<<nrb, RW_BLOCK, 0, st>>>(a, offs, total, dtotal, d, *rw, lineage ? 1 : 0)
+#define DL_SCAT(TK, IT, FM)                                                                                  \
+  k_join_expand_dense<K, TK, IT, FM><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0, skip_at)
 #define DL_DEXPAND(IT)                                                                                               \
   if (tk == TAG_F32) {                                                                                               \
-    if (!rows || dtotal)                                                                                             \
-      k_join_expand_dense<K, TAG_F32, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0, skip_at); \
+    if (!rows || dtotal) {                                                                                           \
+      if constexpr (sizeof(K) == 4) {                                                                                \
+        if (fm == DENSE_MAX) DL_SCAT(TAG_F32, IT, DENSE_MAX);                                                        \
+        else if (fm == DENSE_MIN) DL_SCAT(TAG_F32, IT, DENSE_MIN);                                                   \
+        else if (fm == DENSE_ADD) DL_SCAT(TAG_F32, IT, DENSE_ADD);                                                   \
+        else DL_SCAT(TAG_F32, IT, -1);                                                                               \
+      } else {                                                                                                       \
+        DL_SCAT(TAG_F32, IT, -1);                                                                                    \
+      }                                                                                                              \
+    }                                                                                                                \
     if (rows) {                                                                                                      \
       if constexpr (sizeof(K) == 4) {                                                                                \
         if (fm == DENSE_MAX) DL_ROWS(TAG_F32, IT, DENSE_MAX);                                                        \
@@ -742,8 +816,14 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
       }                                                                                                              \
     }                                                                                                                \
   } else {                                                                                                           \
-    if (!rows || dtotal)                                                                                             \
-      k_join_expand_dense<K, TAG_NONE, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0, skip_at); \
+    if (!rows || dtotal) {                                                                                           \
+      if constexpr (sizeof(K) == 4) {                                                                                \
+        if (fm == DENSE_BOOL) DL_SCAT(TAG_NONE, IT, DENSE_BOOL);                                                     \
+        else DL_SCAT(TAG_NONE, IT, -1);                                                                              \
+      } else {                                                                                                       \
+        DL_SCAT(TAG_NONE, IT, -1);                                                                                   \
+      }                                                                                                              \
+    }                                                                                                                \
     if (rows) {                                                                                                      \
       if constexpr (sizeof(K) == 4) {                                                                                \
         if (fm == DENSE_BOOL) DL_ROWS(TAG_NONE, IT, DENSE_BOOL);                                                     \
@@ -762,6 +842,7 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   }
 #undef DL_DEXPAND
 #undef DL_ROWS
+#undef DL_SCAT
   DL_PROF_END(1, st, bytes);
   if (dtotal) DL_PROF_DEFER(1, per);
 }

@@ -172,35 +172,38 @@ void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st) {
 // the sums of all tiles before it and writes its offsets.  It waits only on
 // lower-numbered workgroups, which were dispatched before it and publish
 // before they wait, so every wait ends; the wait is also bounded (flag 3 in
-// *err, never expected).  The last tile writes the total; the last workgroup
-// to finish clears the flags for the next launch.
+// *err, never expected).  Launches alternate between two flag sets (a parity
+// word): the last workgroup, dispatched after every other one has read the
+// parity, clears the set of the previous launch (all of whose workgroups
+// have ended) and flips the parity.
 constexpr int CS_ITEMS = 1;
 constexpr int CS_TILE = BLOCK * CS_ITEMS;
 
-size_t count_scan_state_words() { return CS_MAX_TILES * 3 + 2; }
+size_t count_scan_state_words() { return CS_MAX_TILES * 2 + 2; }
 
 template <typename K>
 __global__ __launch_bounds__(BLOCK) void k_join_count_scan(JoinArgs a, uint32_t* __restrict__ offs,
                                                            uint64_t* __restrict__ state, uint64_t* __restrict__ d_total,
                                                            uint64_t* __restrict__ acc, uint64_t* __restrict__ err) {
   __shared__ uint64_t tmp[NWAVES], s_pre[NWAVES];
-  __shared__ int s_last;
-  uint64_t* sums = state;
-  uint32_t* flags = reinterpret_cast<uint32_t*>(state + CS_MAX_TILES);
-  uint32_t* done = flags + CS_MAX_TILES;
+  uint64_t* sums = state;                                                   // [CS_MAX_TILES]
+  uint32_t* flag_sets = reinterpret_cast<uint32_t*>(state + CS_MAX_TILES);  // [2][CS_MAX_TILES]
+  uint32_t* parity = flag_sets + 2 * CS_MAX_TILES;
+  const uint32_t par = __hip_atomic_load(parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u;
+  uint32_t* flags = flag_sets + par * CS_MAX_TILES;
   const K* dk = (const K*)a.dkeys;
   const size_t base = (size_t)blockIdx.x * CS_TILE + (size_t)threadIdx.x * CS_ITEMS;
-  uint32_t c[CS_ITEMS];
+  uint32_t c[CS_ITEMS], st[CS_ITEMS];
   uint64_t s = 0;
 #pragma unroll
   for (int q = 0; q < CS_ITEMS; ++q) {
     const size_t i = base + q;
     c[q] = 0;
+    st[q] = 0;
     if (i < a.n) {
       const uint64_t p = join_prefix(dk[i], a);
-      const uint32_t b = a.off[p];
-      c[q] = a.off[p + 1] - b;
-      if (a.istart) a.istart[i] = b;
+      st[q] = a.off[p];
+      c[q] = a.off[p + 1] - st[q];
     }
     s += c[q];
   }
@@ -229,25 +232,23 @@ __global__ __launch_bounds__(BLOCK) void k_join_count_scan(JoinArgs a, uint32_t*
   uint64_t run = carry + ex;
 #pragma unroll
   for (int q = 0; q < CS_ITEMS; ++q) {
-    if (base + q < a.n) offs[base + q] = (uint32_t)run;
+    if (base + q < a.n) {
+      offs[base + q] = (uint32_t)run;
+      if (a.istart) a.istart[base + q] = st[q];
+    }
     run += c[q];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-    const uint64_t total = carry + tot;
-    *d_total = total;
-    offs[a.n] = (uint32_t)total;
-    if (acc) *acc += total;
-  }
-  __syncthreads();  // every look-back read of this workgroup is done
-  if (threadIdx.x == 0) {
-    __threadfence();
-    s_last = atomicAdd(done, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (s_last) {
-    for (size_t i = threadIdx.x; i < gridDim.x; i += BLOCK)
-      __hip_atomic_store(flags + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (threadIdx.x == 0) __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (blockIdx.x == gridDim.x - 1) {
+    if (threadIdx.x == 0) {
+      const uint64_t total = carry + tot;
+      *d_total = total;
+      offs[a.n] = (uint32_t)total;
+      if (acc) *acc += total;
+    }
+    uint32_t* prev = flag_sets + (1u - par) * CS_MAX_TILES;
+    for (size_t i = threadIdx.x; i < CS_MAX_TILES; i += BLOCK)
+      __hip_atomic_store(prev + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(parity, 1u - par, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
