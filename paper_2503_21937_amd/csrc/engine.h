@@ -65,6 +65,7 @@ struct RelState {
   bool own_index = false;  // a plan of its own stratum joins against it
   DevBuf present, touched, dtag, did, log_keys, log_l, log_r, seg_lcount;
   DevBuf goff;                   // as a join driver: CSR over its (sample, first column) prefix
+  DevBuf lb_state;               // round-end compaction: look-back statuses (kept in a reusable state)
   uint64_t goff_version = ~0ull;  // `version` it was built from
   size_t nseg = 0;         // lineage wave segments emitted this round
   Table view_full, view_recent, view_stable;  // a past round's state (lineage recomputation)

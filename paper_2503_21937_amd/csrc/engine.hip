@@ -62,7 +62,7 @@ Engine::~Engine() {
     fr(r.fact_entry), fr(r.grad), fr(r.fact_slot_d);
     fr(r.cand_keys), fr(r.cand_tags), fr(r.cand_l), fr(r.cand_r);
     for (DevBuf* b : {&r.present, &r.touched, &r.dtag, &r.did, &r.log_keys, &r.log_l, &r.log_r, &r.seg_lcount, &r.goff,
-                      &r.dense_sbase})
+                      &r.dense_sbase, &r.lb_state})
       fr(*b);
   }
   for (auto& x : idx) {

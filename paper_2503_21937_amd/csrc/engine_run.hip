@@ -59,7 +59,7 @@ void claim(DevBuf& owner, DevBuf& alt, const void* result) {
 void check_overflow(Engine& e) {
   const uint64_t f = e.host[S_OVF];
   if (f == 1) throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
-  if (f == 3) throw Error{DL_ERR_HIP, "join count scan: a look-back wait did not end"};
+  if (f == 3) throw Error{DL_ERR_HIP, "single-pass scan: a look-back wait did not end"};
   if (f) throw Error{DL_ERR_HIP, "row-window join: a derivation fell outside its window"};
 }
 
@@ -144,6 +144,9 @@ void setup_dense(Engine& e) {
     if (!R.dense) continue;
     R.dense_keys = keys;
     R.dense_cols = e.prog.rels[r].arity;
+    const size_t lbw = lookback_state_words(dense_count_blocks(keys));
+    e.grow(R.lb_state, lbw * 8);
+    fill_u32(R.lb_state.as<uint32_t>(), lbw * 2, 0u, e.stream);
     if (e.batched) {
       std::vector<uint32_t> sb;
       (void)dense_domain(e, e.prog.rels[r].arity, &sb);
@@ -489,17 +492,14 @@ size_t absorb_dense(Engine& e, int r) {
   e.grow(e.flags, nb * 4);
   e.grow(e.pos, (nb + 1) * 4);
   DenseArgs d = dense_args(e, R);
-  bitmap_block_counts(d.touched, R.dense_keys, e.flags.as<uint32_t>(), st);
   if (!e.lineage && R.dense_keys * (sizeof(K) + 4) <= ((size_t)1 << 30)) {
-    // recent sized for the whole domain: compact first, read the count after
-    // (one host sync per relation and round)
+    // recent sized for the whole domain: compact first (single pass), read
+    // the count after (one host sync per relation and round)
     e.grow(R.recent.keys, R.dense_keys * sizeof(K) + 8);
     if (e.tag_kind == TAG_F32) e.grow(R.recent.tags, R.dense_keys * 4 + 8);
-    const bool pre = nb > dense_self_prefix_blocks();
-    if (pre) scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, S_UNIQUE, true);
-    dense_finalize<K>(d, R.dense_keys, (pre ? e.pos : e.flags).as<uint32_t>(), R.recent.keys.as<K>(),
+    dense_finalize<K>(d, R.dense_keys, nullptr, R.recent.keys.as<K>(),
                       e.tag_kind == TAG_F32 ? R.recent.tags.as<float>() : nullptr, 0, nullptr, total_slot(e, S_UNIQUE),
-                      st, nullptr, pre);
+                      st, nullptr, false, nullptr, R.lb_state.as<uint64_t>());
     e.read_totals();
     check_overflow(e);
     const size_t U = e.host[S_UNIQUE];
@@ -511,6 +511,7 @@ size_t absorb_dense(Engine& e, int r) {
     if (R.own_index) materialize_full<K>(e, R);
     return U;
   }
+  bitmap_block_counts(d.touched, R.dense_keys, e.flags.as<uint32_t>(), st);
   scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, S_UNIQUE, true);
   if (e.record && nseg) {
     e.grow(e.lpos, (nseg + 1) * 4);
@@ -807,20 +808,14 @@ void enqueue_round_body(Engine& e, int r, const std::vector<const Plan*>& plans,
                          st, rows ? &rw : nullptr);
   }
   const DenseArgs d = dense_args(e, R);
-  bitmap_block_counts(d.touched, R.dense_keys, e.flags.as<uint32_t>(), st);
-  const size_t nb = dense_count_blocks(R.dense_keys);
-  const bool pre = nb > dense_self_prefix_blocks();
-  if (pre)
-    scan_u32(e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), nb, total_slot(e, S_UNIQUE), true, e.scratch.as<uint64_t>(),
-             st);
   DenseCsr csr;
   if (fin_csr) {
     const uint32_t n = e.max_id + 1;
     csr = dense_csr(e.idx[plans[0]->steps[0].index].off.as<uint32_t>(), (uint32_t)(R.dense_keys / n / 32), n);
   }
-  dense_finalize<K>(d, R.dense_keys, (pre ? e.pos : e.flags).as<uint32_t>(), R.recent.keys.as<K>(),
+  dense_finalize<K>(d, R.dense_keys, nullptr, R.recent.keys.as<K>(),
                     e.tag_kind == TAG_F32 ? R.recent.tags.as<float>() : nullptr, 0, nullptr, total_slot(e, S_UNIQUE),
-                    st, total_slot(e, S_LOG), pre, fin_csr ? &csr : nullptr);
+                    st, total_slot(e, S_LOG), false, fin_csr ? &csr : nullptr, R.lb_state.as<uint64_t>());
 }
 
 // Rounds 2.. of an eligible stratum in batches of device-sized round bodies;

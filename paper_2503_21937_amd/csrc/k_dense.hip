@@ -1015,12 +1015,71 @@ DenseCsr dense_csr(uint32_t* off, uint32_t wwords, uint32_t n) {
   return c;
 }
 
+// The block's first output slot in a single pass (no separate count
+// launch): the block publishes its count (flag bit 63 over the value), then
+// its threads add up the published counts of all blocks before it, each
+// spinning until that block has published -- which every block does before
+// it waits on anything, so the spins end (they are bounded besides, flag 3
+// in *err).  The blocks run together, so summing every predecessor takes one
+// round of loads where a chained look-back would walk back block by block.
+// Launches alternate between two status sets (a parity word after them);
+// the last block, having seen every other block publish, clears the
+// previous launch's set and flips the parity.  The last block also writes
+// the grand total (and the round log).
+constexpr uint64_t LB_PUB = 1ull << 63;
+
+size_t lookback_state_words(size_t blocks) { return 2 * blocks + 1; }
+
+__device__ __forceinline__ uint32_t block_first_slot_published(uint64_t* lb, size_t cap, uint32_t own_wave_count,
+                                                               uint32_t* s_tot, uint32_t* s_pre, uint64_t* d_total,
+                                                               uint64_t* log, uint64_t* err) {
+  const int lane = lane_id(), wv = threadIdx.x / WAVE;
+  const uint32_t par = (uint32_t)__hip_atomic_load(lb + 2 * cap, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u;
+  uint64_t* stat = lb + par * cap;
+  if (lane == 0) s_tot[wv] = own_wave_count;
+  __syncthreads();
+  const uint32_t own = s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
+  if (threadIdx.x == 0)
+    __hip_atomic_store(stat + blockIdx.x, LB_PUB | own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t pre = 0;
+  for (size_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) {
+    uint64_t v;
+    uint32_t spins = 0;
+    while (!((v = __hip_atomic_load(stat + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & LB_PUB)) {
+      if (++spins > (1u << 24)) {
+        *err = 3;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    pre += v & 0xffffffffull;
+  }
+  pre = wave_sum(pre);
+  if (lane == 0) s_pre[wv] = (uint32_t)pre;
+  __syncthreads();
+  const uint32_t base = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3];
+  if (blockIdx.x == gridDim.x - 1) {  // every block has published: clear the other set, flip
+    uint64_t* prev = lb + (1u - par) * cap;
+    for (size_t i = threadIdx.x; i < gridDim.x; i += BLOCK)
+      __hip_atomic_store(prev + i, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(lb + 2 * cap, (uint64_t)(1u - par), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      *d_total = (uint64_t)base + own;
+      if (log) log[1 + log[0]++] = (uint64_t)base + own;
+    }
+  }
+  uint32_t o = base;
+  for (int i = 0; i < wv; ++i) o += s_tot[i];
+  return o;
+}
+
 template <typename K>
 __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t words, const uint32_t* __restrict__ counts,
                                                           K* __restrict__ keys, float* __restrict__ rtags,
                                                           uint32_t id_base, float* __restrict__ tag_by_id,
                                                           uint64_t* __restrict__ d_total, uint64_t* __restrict__ log,
-                                                          int prefixed, DenseCsr csr) {
+                                                          int prefixed, DenseCsr csr, uint64_t* __restrict__ lb,
+                                                          size_t lb_cap) {
   __shared__ uint32_t s_tot[NWAVES], s_pre[NWAVES];
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
@@ -1033,7 +1092,8 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
     c += (uint32_t)__popc(b[i]);
   }
   c = wave_sum(c);
-  uint32_t o = block_first_slot(counts, prefixed, c, s_tot, s_pre, d_total, log);
+  uint32_t o = lb ? block_first_slot_published(lb, lb_cap, c, s_tot, s_pre, d_total, log, d.overflow)
+                  : block_first_slot(counts, prefixed, c, s_tot, s_pre, d_total, log);
   if (csr.off) {
     // group starts: a word wi with wi % wwords == 0 opens first-column group
     // wi / wwords, whose first key (if any) gets the slot after every set bit
@@ -1050,8 +1110,7 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
       }
       run += __shfl(incl, WAVE - 1, WAVE);
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) csr.off[csr.n] = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3] +
-                                                                            s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
+    if (blockIdx.x == gridDim.x - 1 && lane == WAVE - 1 && wv == NWAVES - 1) csr.off[csr.n] = run;
   }
   if (c == 0) return;  // wave-uniform; no barrier follows
   // batched: the sample of the wave's first word, searched once
@@ -1089,12 +1148,12 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
 template <typename K>
 void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* rtags, uint32_t id_base,
                     float* tag_by_id, uint64_t* d_total, hipStream_t st, uint64_t* log, bool prefixed,
-                    const DenseCsr* csr) {
+                    const DenseCsr* csr, uint64_t* lookback) {
   const size_t words = bitmap_words(nkeys);
+  const size_t nb = dense_count_blocks(nkeys);
   DL_PROF_BEGIN(6, st);
-  k_dense_finalize<K><<<dense_count_blocks(nkeys), BLOCK, 0, st>>>(d, words, counts, keys, rtags, id_base, tag_by_id,
-                                                                   d_total, log, prefixed ? 1 : 0,
-                                                                   csr ? *csr : DenseCsr{});
+  k_dense_finalize<K><<<nb, BLOCK, 0, st>>>(d, words, counts, keys, rtags, id_base, tag_by_id, d_total, log,
+                                            prefixed ? 1 : 0, csr ? *csr : DenseCsr{}, lookback, nb);
   DL_PROF_END(6, st, words * 12.0);
 }
 
@@ -1184,7 +1243,7 @@ void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, bool 
                                      const DenseArgs&, bool, hipStream_t, const RowWindows*);                                                \
   template void project_dense<K>(const JoinArgs&, int, const DenseArgs&, bool, hipStream_t);                        \
   template void dense_finalize<K>(const DenseArgs&, size_t, const uint32_t*, K*, float*, uint32_t, float*, uint64_t*,        \
-                                  hipStream_t, uint64_t*, bool, const DenseCsr*);                                           \
+                                  hipStream_t, uint64_t*, bool, const DenseCsr*, uint64_t*);                                \
   template void segments_lineage<K>(const DenseArgs&, const uint32_t*, size_t, uint32_t*, uint32_t*, uint32_t*,            \
                                     hipStream_t);                                                                          \
   template void bitmap_keys<K>(const DenseArgs&, size_t, const uint32_t*, bool, K*, float*, uint32_t*, hipStream_t);

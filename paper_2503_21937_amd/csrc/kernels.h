@@ -207,10 +207,15 @@ struct DenseCsr {
   uint8_t s1 = 0, s2 = 0;
 };
 DenseCsr dense_csr(uint32_t* off, uint32_t wwords, uint32_t n);
+// With `lookback` (lookback_state_words(dense_count_blocks(nkeys)) zeroed
+// words, left in a reusable state; d_total must be set): every block
+// publishes its count and sums the published counts before it, so `counts`
+// is not read -- no bitmap_block_counts launch is needed.
+size_t lookback_state_words(size_t blocks);
 template <typename K>
 void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* rtags, uint32_t id_base,
                     float* tag_by_id, uint64_t* d_total, hipStream_t st, uint64_t* log = nullptr,
-                    bool prefixed = false, const DenseCsr* csr = nullptr);
+                    bool prefixed = false, const DenseCsr* csr = nullptr, uint64_t* lookback = nullptr);
 // The round's lineage segments (d.seg_lcount entries each, pos = exclusive
 // scan of those counts) compacted into (owner id, left id, right id).
 template <typename K>
