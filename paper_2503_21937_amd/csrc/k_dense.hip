@@ -399,7 +399,8 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
   constexpr bool FAST = FM >= 0;
   const int lineage = FAST ? 0 : lineage_arg;
   constexpr int TILE = RW_BLOCK * RX_ITEMS;
-  __shared__ uint32_t s_tag[TK == TAG_F32 ? RW_KEYS : 1];
+  // window tags; in a launch below the threshold, the tile's slot -> row map
+  __shared__ uint32_t s_tag[RW_KEYS];
   __shared__ uint32_t s_pres[RW_KEYS / 32];
   __shared__ uint32_t s_new[RW_KEYS / 32];
   // per driver row of the group: first output slot, index row of the first
@@ -409,14 +410,16 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
   __shared__ K s_dkey[RW_ROWS];
   __shared__ float s_dtag[TK == TAG_F32 ? RW_ROWS : 1];
   __shared__ uint32_t s_did[RW_ROWS];  // lineage: driver row ids
-  __shared__ uint32_t s_cpre[RW_ROWS + 1];  // chunks of 64 outputs before each row
+  __shared__ __align__(8) uint32_t s_cpre[RW_ROWS + 1];  // chunks of 64 outputs before each row
   const size_t total = dtotal ? (size_t)*dtotal : total_h;
-  if (total < rw.from || total > 0xffffffffull) return;  // scattered kernel's launch (or overflow, reported there)
+  if (total > 0xffffffffull) {  // offsets are 32-bit: refuse, the host reports it
+    if (blockIdx.x == 0 && threadIdx.x == 0 && d.overflow) *d.overflow = 1;
+    return;
+  }
   const K* dk = (const K*)a.dkeys;
   const K* ik = (const K*)a.ikeys;
   const T* dt = (const T*)a.dtags;
   const T* it = (const T*)a.itags;
-  const uint32_t pmask = (1u << d.dcbits) - 1u;
   // Output columns 1.. (column 0 is the group's): which key holds each and
   // at which shift, fixed for the launch, so a derivation extracts them with
   // one shift and mask apiece.
@@ -431,6 +434,106 @@ __global__ __launch_bounds__(RW_BLOCK, 8) void k_join_expand_rows(JoinArgs a, co
     shf[c] = (uint32_t)((l.ncols - 1 - (s < 0 ? -1 - s : s)) * l.cbits);
     msk[c] = cmask(l.cbits);
   }
+  if (total < rw.from) {
+    // Too few derivations for windows (the total is only known on the
+    // device): scattered dense updates over load-balanced tiles of
+    // RW_BLOCK * RX_ITEMS outputs, as k_join_expand_dense does (no lineage:
+    // the host launches this kernel below the threshold only without it).
+    if (lineage) return;
+    uint32_t* s_row = s_tag;
+    uint32_t* s_wv = s_cpre;
+    size_t* s_r = reinterpret_cast<size_t*>(s_cpre + 2 * RW_WAVES);
+    const size_t ntiles = (total + TILE - 1) / TILE;
+    for (size_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // uniform per block
+      const size_t t0 = tile * TILE;
+      const size_t t1 = t0 + TILE < total ? t0 + TILE : total;
+      tile_rows<RX_ITEMS, RW_BLOCK>(offs, a.n, t0, t1, s_row, s_wv, s_r);
+      bool act[RX_ITEMS];
+      uint32_t row[RX_ITEMS], irow[RX_ITEMS];
+      K dkey[RX_ITEMS], ikey[RX_ITEMS];
+      float x[RX_ITEMS], y[RX_ITEMS];
+#pragma unroll
+      for (int q = 0; q < RX_ITEMS; ++q) {
+        const size_t j = t0 + (size_t)q * RW_BLOCK + threadIdx.x;
+        act[q] = j < t1;
+        row[q] = act[q] ? s_row[j - t0] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < RX_ITEMS; ++q) {
+        const uint32_t j = (uint32_t)(t0 + (size_t)q * RW_BLOCK + threadIdx.x);
+        dkey[q] = act[q] ? dk[row[q]] : (K)0;
+        irow[q] = act[q] ? a.istart[row[q]] + (j - offs[row[q]]) : 0u;
+        x[q] = 0.0f;
+        if constexpr (TK == TAG_F32) x[q] = act[q] ? dt[row[q]] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < RX_ITEMS; ++q) {
+        ikey[q] = act[q] ? ik[irow[q]] : (K)0;
+        y[q] = 0.0f;
+        if constexpr (TK == TAG_F32) y[q] = act[q] ? it[irow[q]] : 0.0f;
+      }
+      uint32_t kk[RX_ITEMS];
+      float tt[RX_ITEMS];
+#pragma unroll
+      for (int q = 0; q < RX_ITEMS; ++q) {
+        // the head key's dense index (mixed radix) and the derivation's tag
+        kk[q] = 0;
+        tt[q] = 0.0f;
+        if (act[q]) {
+          if constexpr (FAST) {
+            kk[q] = ((uint32_t)dkey[q] >> (uint32_t)((a.dlay.ncols - 1) * a.dlay.cbits) & cmask(a.dlay.cbits)) * d.dnp +
+                    (((uint32_t)ikey[q] >> shf[1]) & msk[1]);
+          } else {
+            uint32_t v[4];
+            for (int c = 0; c < a.olay.ncols; ++c) {
+              const int sc = a.osrc[c];
+              v[c] = sc >= 0 ? key_col(dkey[q], sc, a.dlay) : key_col(ikey[q], -1 - sc, a.ilay);
+            }
+            kk[q] = dense_index(d, key_make<K>(key_sample(dkey[q], a.dlay), v, a.olay));
+          }
+          if constexpr (TK == TAG_F32) tt[q] = a.index_first ? f_otimes(a.sr, y[q], x[q]) : f_otimes(a.sr, x[q], y[q]);
+        }
+      }
+      uint32_t pw[RX_ITEMS], tw[RX_ITEMS], cur[RX_ITEMS];
+#pragma unroll
+      for (int q = 0; q < RX_ITEMS; ++q) {
+        pw[q] = tw[q] = cur[q] = 0;
+        if (act[q]) {
+          pw[q] = d.present[kk[q] >> 5];
+          tw[q] = d.touched[kk[q] >> 5];
+          if (d.mode == DENSE_MAX || d.mode == DENSE_MIN) cur[q] = d.dtag[kk[q]];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RX_ITEMS; ++q) {
+        if (!act[q]) continue;
+        const uint32_t bit = 1u << (kk[q] & 31);
+        const bool present = (pw[q] & bit) != 0u;
+        const int mode = FAST ? FM : d.mode;
+        bool keep = false;
+        if (mode == DENSE_BOOL) {
+          keep = !present;
+        } else if (mode == DENSE_ADD) {
+          keep = !present;
+          if (keep) atomicAdd(reinterpret_cast<float*>(d.dtag) + kk[q], tt[q]);
+        } else if (mode == DENSE_MAX) {
+          const uint32_t o = to_ordered(tt[q]);
+          keep = o > cur[q];
+          if (keep) atomicMax(d.dtag + kk[q], o);
+          keep = keep || !present;
+        } else {
+          const uint32_t o = to_ordered(tt[q]);
+          keep = o < cur[q];
+          if (keep) atomicMin(d.dtag + kk[q], o);
+          keep = keep || !present;
+        }
+        if (keep && !(tw[q] & bit)) atomicOr(d.touched + (kk[q] >> 5), bit);
+      }
+      __syncthreads();  // s_row is rebuilt for the next tile
+    }
+    return;
+  }
+  const uint32_t pmask = (1u << d.dcbits) - 1u;
   // The next group's driver rows are fetched while the current one is
   // processed (its CSR bounds at the top, their output slots after the
   // window load), so a group starts without waiting on those loads.
@@ -771,16 +874,23 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   // per derivation: index row read, presence word and dense tag read; per probe row: driver row + offset
   const double per = (sizeof(K) + tb + lin + 4.0 + tb);
   const double bytes = (dtotal ? 0.0 : total * per) + a.n * (sizeof(K) + tb + lin + 4.0);
-  // row windows: both variants are launched and each checks the total
-  // (with lineage the total is known on the host and only one variant runs)
+  // row windows: one launch of the row-window kernel, which reads the total
+  // and falls back to scattered tiles below the threshold when the total is
+  // only known on the device (with lineage the total is known on the host)
   const bool rows = rw && rw->wkeys <= (uint32_t)RW_KEYS && (!lineage || !dtotal) &&
                     (dtotal || total >= rw->from);
   if (rows && lineage) fill_u32(d.seg_lcount + d.seg_base, dense_segments(total, items), 0u, st);
-  const uint64_t skip_at = rows ? rw->from : ~0ull;
+  const uint64_t skip_at = ~0ull;
   // one workgroup per group (up to 16384; beyond, workgroups loop): the
   // dispatcher hands the next group to whichever CU frees a slot first, which
-  // balances groups of very different sizes
-  const unsigned nrb = rows ? (unsigned)(rw->ngroups < 16384 ? rw->ngroups : 16384) : 0u;
+  // balances groups of very different sizes; with a device total, at least
+  // as many workgroups as the fallback's tiles need (up to 4096)
+  unsigned nrb = rows ? (unsigned)(rw->ngroups < 16384 ? rw->ngroups : 16384) : 0u;
+  if (rows && dtotal) {
+    const size_t rtile = (size_t)RW_BLOCK * items, need = (max_total + rtile - 1) / rtile;
+    const unsigned ns = (unsigned)(need < 4096 ? need : 4096);
+    nrb = nrb > ns ? nrb : ns;
+  }
   // the specialised variants (see k_join_expand_rows, k_join_expand_dense)
   int fm = -1;
   if (sizeof(K) == 4 && d.nsamp <= 1 && !lineage && a.olay.ncols == 2 && a.osrc[0] >= 0 && a.osrc[1] < 0) {
@@ -795,7 +905,7 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   k_join_expand_dense<K, TK, IT, FM><<<nb, BLOCK, 0, st>>>(a, offs, total, dtotal, d, lineage ? 1 : 0, skip_at)
 #define DL_DEXPAND(IT)                                                                                               \
   if (tk == TAG_F32) {                                                                                               \
-    if (!rows || dtotal) {                                                                                           \
+    if (!rows) {                                                                                                     \
       if constexpr (sizeof(K) == 4) {                                                                                \
         if (fm == DENSE_MAX) DL_SCAT(TAG_F32, IT, DENSE_MAX);                                                        \
         else if (fm == DENSE_MIN) DL_SCAT(TAG_F32, IT, DENSE_MIN);                                                   \
@@ -816,7 +926,7 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
       }                                                                                                              \
     }                                                                                                                \
   } else {                                                                                                           \
-    if (!rows || dtotal) {                                                                                           \
+    if (!rows) {                                                                                                     \
       if constexpr (sizeof(K) == 4) {                                                                                \
         if (fm == DENSE_BOOL) DL_SCAT(TAG_NONE, IT, DENSE_BOOL);                                                     \
         else DL_SCAT(TAG_NONE, IT, -1);                                                                              \

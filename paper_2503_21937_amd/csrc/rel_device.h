@@ -103,21 +103,22 @@ __device__ __forceinline__ size_t wave_upper_bound(const uint32_t* a, size_t n, 
 // outputs start, then an inclusive max-scan over the tile carries each row
 // id over its slots (rows without matches mark nothing, so the last marked
 // row at or before a slot owns it).  Result: s_row[t] for t < s1 - s0.
-// Must be called by the whole 256-thread block; s_row holds BLOCK * ITEMS.
-template <int ITEMS>
+// Must be called by the whole BS-thread block; s_row holds BS * ITEMS,
+// s_wave BS / WAVE.
+template <int ITEMS, int BS = BLOCK>
 __device__ __forceinline__ void tile_rows(const uint32_t* __restrict__ offs, size_t n, size_t s0, size_t s1,
                                           uint32_t* s_row, uint32_t* s_wave, size_t* s_r) {
-  constexpr int TILE = BLOCK * ITEMS;
+  constexpr int TILE = BS * ITEMS;
   const int wv = threadIdx.x / WAVE;
   if (wv < 2) {  // wave 0 finds the tile's first row, wave 1 its last
     const size_t r = wave_upper_bound(offs, n + 1, (uint32_t)(wv == 0 ? s0 : s1 - 1)) - 1;
     if (lane_id() == 0) s_r[wv] = r;
   }
-  for (int t = threadIdx.x; t < TILE; t += BLOCK) s_row[t] = 0u;
+  for (int t = threadIdx.x; t < TILE; t += BS) s_row[t] = 0u;
   __syncthreads();
   const size_t r0 = s_r[0], r1 = s_r[1];
   if (threadIdx.x == 0) s_row[0] = (uint32_t)r0;
-  for (size_t r = r0 + 1 + threadIdx.x; r <= r1; r += BLOCK) {
+  for (size_t r = r0 + 1 + threadIdx.x; r <= r1; r += BS) {
     const uint32_t o = offs[r];
     if (o < s1 && offs[r + 1] > o) s_row[o - s0] = (uint32_t)r;
   }

@@ -70,9 +70,11 @@ def test_autotune_picks_and_caches(oracle, synth, tmp_path):
     assert np.array_equal(a["tags"], b["tags"])
 
 
-@pytest.mark.parametrize("rows", [0, 2])
+@pytest.mark.parametrize("rows", [0, 1, 2])
 def test_row_windows_batched(oracle, synth, tmp_path, rows):
-    """Row windows keyed by (sample, first column) on a batch of grids."""
+    """Row windows keyed by (sample, first column) on a batch of grids (rows
+    1: launches below the threshold take the row-window kernel's scattered
+    fallback)."""
     from paper_2503_21937_amd import dlfix
     g = synth.grid_batch(9, samples=24, kmin=3, kmax=12)
     facts = {"edge": ([g["src"], g["dst"]], g["p"], g["sample"])}
@@ -136,19 +138,21 @@ via(x, y) :- edge(x, y), path(y, z).
 """
 
 
+@pytest.mark.parametrize("rows", [1, 2])
 @pytest.mark.parametrize("sr", ["maxmin", "minplus", "addmult", "bool"])
-def test_row_windows_general_shapes(oracle, synth, tmp_path, sr):
-    """Row windows forced onto heads the specialised variant does not take:
-    a ternary head (window of n * np keys) and a binary head whose second
-    column comes from the driver row."""
+def test_row_windows_general_shapes(oracle, synth, tmp_path, sr, rows):
+    """Row windows on heads the specialised variant does not take: a ternary
+    head (window of n * np keys) and a binary head whose second column comes
+    from the driver row; forced (rows 2) or by threshold (rows 1, where small
+    launches take the kernel's scattered fallback)."""
     from paper_2503_21937_amd import dlfix
     src, dst, p = synth.er_graph(21, 60, 200, weights=True)
     e = dlfix.Engine(SHAPES_PROGRAM, sr)
     e.add_facts("edge", [src, dst], p)
     key = _key(e)
     cache = tmp_path / "shapes.jsonl"
-    cache.write_text(json.dumps({"key": key, "dedup": 2, "orient": 2, "items": 2, "rows": 2, "ms": 1.0}) + "\n")
-    assert e.autotune(1, str(cache))["rows"] == 2
+    cache.write_text(json.dumps({"key": key, "dedup": 2, "orient": 2, "items": 2, "rows": rows, "ms": 1.0}) + "\n")
+    assert e.autotune(1, str(cache))["rows"] == rows
     o = oracle_run(oracle, SHAPES_PROGRAM, sr, {"edge": ([src, dst], p, None)})
     for rel in ("path", "hop", "via"):
         got, want = e.read(rel), o.read(rel)
