@@ -1,0 +1,31 @@
+"""Kernel timing (dl_profile): a timed run gives the same relation as an
+untimed one, and engines built with and without round graphs (timed rounds
+are launched directly) report the same launches and algorithmic bytes per
+family."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("sr", ["maxmin", "addmult"])
+def test_profiled_graphs_match_direct_launches(synth, sr):
+    from paper_2503_21937_amd import dlfix
+    src, dst, p = synth.er_graph(3, 1500, 6000, weights=True)
+    runs = {}
+    for graphs in (True, False):
+        e = dlfix.Engine(synth.TC_PROGRAM, sr, dedup="dense", graphs=graphs)
+        e.add_facts("edge", [src, dst], p)
+        plain = e.run().read("path")
+        e.profile(["join_expand", "join_count"])
+        timed = e.run().read("path")
+        ks = e.kernel_stats()
+        assert np.array_equal(plain["cols"], timed["cols"])
+        assert np.array_equal(plain["tags"], timed["tags"]) or sr == "addmult"
+        runs[graphs] = (timed, ks)
+    (g, kg), (d, kd) = runs[True], runs[False]
+    assert np.array_equal(g["cols"], d["cols"])
+    for fam in ("join_expand", "join_count"):
+        assert kg[fam]["launches"] == kd[fam]["launches"] > 0, fam
+        assert kg[fam]["ms"] > 0 and kd[fam]["ms"] > 0, fam
+        assert kg[fam]["bytes"] == pytest.approx(kd[fam]["bytes"], rel=1e-9), fam
