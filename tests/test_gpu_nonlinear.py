@@ -80,3 +80,19 @@ def test_nonlinear_gradients(oracle, synth, dedup):
     g.backward("path", gout.astype(np.float32))
     o.backward("path", gout)
     np.testing.assert_allclose(g.grad("edge", src.size), o.grad("edge", src.size), rtol=1e-4, atol=1e-6)
+
+
+# Same Generation without its inequality (arithmetic selections are not
+# supported): a recursive atom between two static atoms, planned as two binary
+# joins through an intermediate relation (differentiable add-mult records
+# derivations of at most two body atoms, so it is not among the semirings).
+SAME_GEN = (".input edge/2\nsg(x, y) :- edge(p, x), edge(p, y).\n"
+            "sg(x, y) :- edge(a, x), sg(a, b), edge(b, y).\n")
+
+
+@pytest.mark.parametrize("dedup", DEDUP)
+@pytest.mark.parametrize("sr", ["bool", "maxmin", "minplus", "addmult"])
+def test_same_generation(oracle, synth, sr, dedup):
+    src, dst, _ = synth.er_graph(8, 60, 110, weights=True)
+    p = small_probs(np.random.default_rng(8), src.size)
+    check(oracle, SAME_GEN, sr, {"edge": ([src, dst], p, None)}, ["sg"], dedup)
