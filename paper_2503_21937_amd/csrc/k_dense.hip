@@ -379,8 +379,10 @@ __global__ __launch_bounds__(BLOCK) void k_join_expand_dense(JoinArgs a, const u
 // meet in LDS), and writes back only the entries it changed, with plain
 // coalesced stores (no other workgroup of the launch touches the window).
 // This trades one streaming pass over the windows for scattered global
-// atomics and pays off when the launch has many derivations per window; the
-// host sets the threshold `from` and both variants test the device-side total.
+// atomics and pays off when the launch has many derivations per window: the
+// host sets the threshold `from`; a launch whose total is only known on the
+// device reads it and, below the threshold, runs load-balanced scattered
+// tiles itself (one launch per join either way).
 constexpr int RW_BITS = 13;  // largest window: 8192 keys (32 KB of tags)
 constexpr int RW_KEYS = 1 << RW_BITS;
 constexpr int RW_ROWS = 255;   // driver rows of a group staged in LDS (4 workgroups fit a CU)

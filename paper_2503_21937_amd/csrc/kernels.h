@@ -170,10 +170,10 @@ void join_expand(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t t
 // window of wkeys dense indexes (a multiple of 32, at most 8192), and
 // launches with at least `from` derivations use them.
 struct RowWindows {
-  const uint32_t* goff;
-  size_t ngroups;
-  uint32_t wkeys;
-  uint64_t from;
+  const uint32_t* goff;  // driver CSR over its (sample, first column) prefix: ngroups + 1 offsets
+  size_t ngroups;        // 2^(sample bits + column bits)
+  uint32_t wkeys;        // largest window (dense keys of one prefix)
+  uint64_t from;         // derivations per launch from which windows are used
 };
 template <typename K>
 void join_expand_dense(const JoinArgs& a, int tag_kind, const uint32_t* offs, size_t total, const uint64_t* dtotal,
