@@ -156,3 +156,27 @@ def test_graph_replay_matches_eager_rounds(synth):
             else:
                 assert np.array_equal(got["tags"], ref["tags"]), (sr, rep)
             assert g.stats()["max_rounds"] == eager.stats()["max_rounds"]
+
+
+JOIN2 = ".input a/2\n.input b/2\n.output c/2\nc(x, z) :- a(x, y), b(y, z).\n"
+
+
+@pytest.mark.parametrize("dedup", DEDUP)
+@pytest.mark.parametrize("sr", ["bool", "maxmin"])
+@pytest.mark.parametrize("n", [1, 255, 256, 257, 513, 70000])
+def test_join_counts_across_tiles(oracle, sr, dedup, n):
+    """Single-pass count + scan: probe-row counts at and around multiples of
+    its 256-row tiles (one tile, a tile and one row, many tiles)."""
+    rng = np.random.default_rng(n)
+    ax = rng.integers(0, 400, n).astype(np.uint32)
+    ay = rng.integers(0, 300, n).astype(np.uint32)
+    bx = rng.integers(0, 300, 900).astype(np.uint32)
+    bz = rng.integers(0, 400, 900).astype(np.uint32)
+    pa = rng.uniform(0.1, 0.9, n).astype(np.float32) if sr != "bool" else None
+    pb = rng.uniform(0.1, 0.9, 900).astype(np.float32) if sr != "bool" else None
+    facts = {"a": ([ax, ay], pa, None), "b": ([bx, bz], pb, None)}
+    g = engine(JOIN2, sr, facts, dedup=dedup).read("c")
+    o = oracle_run(oracle, JOIN2, sr, facts).read("c")
+    same_rows(g, o)
+    if sr == "maxmin":
+        assert np.array_equal(g["tags"].astype(np.float64), o["value"])
