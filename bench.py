@@ -196,8 +196,8 @@ def main() -> int:
                     help="only run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the engine runs on one GPU (asked for {args.gpus}); sharding the fixpoint "
+              "across GPUs is a design only, not implemented", file=sys.stderr)
         return 2
 
     import torch
