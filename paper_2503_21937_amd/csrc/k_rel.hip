@@ -166,18 +166,20 @@ void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st) {
 }
 
 
-// Join counts and their exclusive scan in one launch (single-pass scan with
-// a look-back over tile sums).  Workgroup b counts the matches of its tile of
-// CS_TILE driver rows, publishes the tile sum (the sum, then a flag), adds
-// the sums of all tiles before it and writes its offsets.  It waits only on
-// lower-numbered workgroups, which were dispatched before it and publish
-// before they wait, so every wait ends; the wait is also bounded (flag 3 in
-// *err, never expected).  Launches alternate between two flag sets (a parity
-// word): the last workgroup, dispatched after every other one has read the
-// parity, clears the set of the previous launch (all of whose workgroups
-// have ended) and flips the parity.
+// Join counts and their exclusive scan in one launch (single-pass scan).
+// Workgroup b counts the matches of its tile of CS_TILE driver rows,
+// publishes the tile sum (one 64-bit word: flag bit 63 over the sum), adds
+// the published sums of all tiles before it and writes its offsets.  It waits
+// only on lower-numbered workgroups, which were dispatched before it and
+// publish before they wait, so every wait ends; the wait is also bounded
+// (flag 3 in *err, never expected).  Launches alternate between two status
+// sets (a parity word): the last workgroup, dispatched after every other one
+// has read the parity and done only once all have published, clears the set
+// of the previous launch (all of whose workgroups have ended) and flips the
+// parity.
 constexpr int CS_ITEMS = 1;
 constexpr int CS_TILE = BLOCK * CS_ITEMS;
+constexpr uint64_t CS_PUB = 1ull << 63;
 
 size_t count_scan_state_words() { return CS_MAX_TILES * 2 + 2; }
 
@@ -186,11 +188,9 @@ __global__ __launch_bounds__(BLOCK) void k_join_count_scan(JoinArgs a, uint32_t*
                                                            uint64_t* __restrict__ state, uint64_t* __restrict__ d_total,
                                                            uint64_t* __restrict__ acc, uint64_t* __restrict__ err) {
   __shared__ uint64_t tmp[NWAVES], s_pre[NWAVES];
-  uint64_t* sums = state;                                                   // [CS_MAX_TILES]
-  uint32_t* flag_sets = reinterpret_cast<uint32_t*>(state + CS_MAX_TILES);  // [2][CS_MAX_TILES]
-  uint32_t* parity = flag_sets + 2 * CS_MAX_TILES;
-  const uint32_t par = __hip_atomic_load(parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u;
-  uint32_t* flags = flag_sets + par * CS_MAX_TILES;
+  uint64_t* parity = state + 2 * CS_MAX_TILES;
+  const uint32_t par = (uint32_t)__hip_atomic_load(parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u;
+  uint64_t* stat = state + par * CS_MAX_TILES;
   const K* dk = (const K*)a.dkeys;
   const size_t base = (size_t)blockIdx.x * CS_TILE + (size_t)threadIdx.x * CS_ITEMS;
   uint32_t c[CS_ITEMS], st[CS_ITEMS];
@@ -209,21 +209,19 @@ __global__ __launch_bounds__(BLOCK) void k_join_count_scan(JoinArgs a, uint32_t*
   }
   uint64_t tot;
   const uint64_t ex = block_exclusive_scan(s, tmp, &tot);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(sums + blockIdx.x, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(flags + blockIdx.x, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x == 0) __hip_atomic_store(stat + blockIdx.x, CS_PUB | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   uint64_t pre = 0;
   for (size_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) {
+    uint64_t v;
     uint32_t spins = 0;
-    while (__hip_atomic_load(flags + i, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+    while (!((v = __hip_atomic_load(stat + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & CS_PUB)) {
       if (++spins > (1u << 24)) {
         *err = 3;
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
-    pre += __hip_atomic_load(sums + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pre += v & ~CS_PUB;
   }
   pre = wave_sum(pre);
   if (lane_id() == 0) s_pre[threadIdx.x / WAVE] = pre;
@@ -245,10 +243,10 @@ __global__ __launch_bounds__(BLOCK) void k_join_count_scan(JoinArgs a, uint32_t*
       offs[a.n] = (uint32_t)total;
       if (acc) *acc += total;
     }
-    uint32_t* prev = flag_sets + (1u - par) * CS_MAX_TILES;
+    uint64_t* prev = state + (1u - par) * CS_MAX_TILES;
     for (size_t i = threadIdx.x; i < CS_MAX_TILES; i += BLOCK)
-      __hip_atomic_store(prev + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (threadIdx.x == 0) __hip_atomic_store(parity, 1u - par, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(prev + i, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(parity, (uint64_t)(1u - par), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
