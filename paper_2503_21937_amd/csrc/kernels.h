@@ -147,11 +147,11 @@ uint32_t dense_init_word(int mode);
 template <typename K>
 void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st);  // also fills a.istart if set
 // Counts and their exclusive scan (offs[0..n], total in *d_total, added to
-// *acc when set) in one launch for up to CS_MAX_TILES tiles of 2048 driver
+// *acc when set) in one launch for up to CS_MAX_TILES tiles of 256 driver
 // rows; false (nothing launched) otherwise or when n == 0.  `state` holds
 // count_scan_state_words() zeroed words, left zeroed; *err = 3 reports a
 // look-back wait that did not end.
-constexpr size_t CS_MAX_TILES = 2048;
+constexpr size_t CS_MAX_TILES = 8192;
 size_t count_scan_state_words();
 template <typename K>
 bool join_count_scan(const JoinArgs& a, uint32_t* offs, uint64_t* state, uint64_t* d_total, uint64_t* acc,
