@@ -13,9 +13,16 @@ facts (dl_autotune, fresh cache) and keeps the chosen execution
 configuration (reported under "exec"; --no-tune keeps the defaults).
 The dominant kernel family is found by an untimed profiled step; during the
 timed steps only that family is bracketed with HIP events on the engine's
-stream, which yields the live roofline figure.  The CPU baseline times the
-CPU oracle (single thread) on a bounded sample of target columns of the same
-workload.
+stream, which yields the live roofline figure: the family's algorithmic
+bytes (every probe row and every derivation read once: key + tag, plus the
+lineage ids when recorded) over its event-timed launches.  The CPU baseline
+times the CPU oracle on a bounded sample of target columns of the same
+workload, on one thread and on the host's threads (up to 16).
+
+The same line carries the batched forward + backward samples/s of the
+512-grid and 256-scene workloads against the one-sample-at-a-time engine,
+and context figures (the small cache-resident graph; the points-to
+fixpoint at a reduced scale).
 """
 from __future__ import annotations
 
@@ -63,23 +70,53 @@ def measured_traffic(kernel: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(src, dst, p, n, budget_s: float, seed: int) -> dict:
-    """Oracle on sampled target columns: tuples derived per CPU second."""
+def host_cpu() -> dict:
+    """The host's logical CPU count and model (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
+def cpu_baseline(src, dst, p, n, budget_s: float, seed: int, threads: int) -> dict:
+    """The oracle's column solver on a bounded seeded sample of target
+    columns, single-threaded and then on `threads` host threads (independent
+    columns; ctypes releases the GIL): derived tuples per second."""
+    import concurrent.futures as cf
     import numpy as np
     from oracle import ref
     ref.build()
-    order = np.random.default_rng(seed).permutation(n)
+    order = [int(z) for z in np.random.default_rng(seed).permutation(n)]
+
+    def column(z):
+        return sum(int(ref.tc_column(n, src, dst, p, sr, z)["present"].sum()) for sr in SEMIRINGS)
+
     tuples, cols, t0 = 0, 0, time.perf_counter()
     for z in order:
-        for sr in SEMIRINGS:
-            tuples += int(ref.tc_column(n, src, dst, p, sr, int(z))["present"].sum())
+        tuples += column(z)
         cols += 1
         if time.perf_counter() - t0 >= budget_s and cols >= 8:
             break
-    dt = time.perf_counter() - t0
-    return {"value": tuples / dt, "unit": "derived tuples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{cols} of {n} target columns x {len(SEMIRINGS)} semirings "
-                      f"({tuples} tuples, {dt:.1f} s, naive Jacobi rounds per column)"}
+    dt1 = time.perf_counter() - t0
+    # the same number of columns per thread, on all threads together
+    sample = order[: min(n, cols * threads)]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        tuples_mt = sum(ex.map(column, sample))
+    dtm = time.perf_counter() - t0
+    return {"value": tuples_mt / dtm, "unit": "derived tuples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sample)} of {n} target columns x {len(SEMIRINGS)} semirings of the same graph "
+                      f"({tuples_mt} tuples, {dtm:.1f} s on {threads} threads, naive Jacobi rounds per column)",
+            "single_thread": {"value": tuples / dt1, "cores": 1,
+                              "sample": f"{cols} columns x {len(SEMIRINGS)} semirings ({tuples} tuples, "
+                                        f"{dt1:.1f} s)"},
+            "host": host_cpu()}
 
 
 def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int, tune_cache: str | None = None) -> dict:
@@ -134,6 +171,7 @@ def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int, tune_c
         m0 = torch.tensor(g["sample"] == 0, device=dev)
         plain.add_facts("edge", [src[m0].contiguous(), dst[m0].contiguous()], p0[m0].contiguous())
         plain.autotune(1, tune_cache)
+    plain_samples = min(plain_samples, S)
     sel = [(g["sample"] == s_) for s_ in range(plain_samples)]
     per = []
     for s_ in range(plain_samples):
@@ -158,9 +196,134 @@ def grids_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int, tune_c
             "query path(0,k^2-1), BCE loss, backward to edge probabilities",
             "batched_samples_per_s": S / tb, "batched_ms_per_step": tb * 1e3,
             "plain_samples_per_s": 1.0 / tp, "plain_sample_ms": tp * 1e3,
-            "plain_measured_on": f"first {plain_samples} samples", "speedup": (S / tb) * tp,
+            "plain_measured_on": f"all {S} samples" if plain_samples >= S else f"first {plain_samples} samples",
+            "speedup": (S / tb) * tp,
             "derived_tuples": st["derived"], "rounds": st["max_rounds"], "lineage": st["lineage"],
             "exec": {k: st[k] for k in ("dedup", "orient", "items", "rows")}}
+
+
+TOPK_RELS = [f"u{i}" for i in range(8)] + [f"r{i}" for i in range(4)]
+
+
+def scenes_fwd_bwd(steps: int, warmup: int, seed: int, plain_samples: int) -> dict:
+    """Batched top-3 proofs on 256 relational scenes: facts upload, fixpoint,
+    read of both output relations (inclusion-exclusion probabilities), a
+    seeded N(0, 1) gradient on every output tuple, reverse pass and read of
+    the input-fact gradients -- all samples in one engine, against the same
+    engine run one sample at a time."""
+    import numpy as np
+    import torch
+    from paper_2503_21937_amd import dlfix, synth
+
+    dev = torch.device("cuda")
+    sc = synth.topk_scenes(seed)
+    S = int(sc["ns"].size)
+
+    def dev_facts(sel_of):
+        out = {}
+        for r in TOPK_RELS:
+            parts = sc[r]
+            m = sel_of(parts[0])
+            cols = [torch.tensor(c[m].astype(np.int32), device=dev) for c in parts[1:-1]]
+            out[r] = (cols, torch.tensor(parts[-1][m], device=dev),
+                      torch.tensor(parts[0][m].astype(np.int32), device=dev))
+        return out
+
+    def step(eng, facts, grads, batched):
+        eng.clear_facts()
+        for r, (cols, p, smp) in facts.items():
+            eng.add_facts(r, cols, p, smp if batched else None)
+        eng.run()
+        outs = {rel: eng.read(rel, device=True) for rel in ("q", "reach")}
+        eng.zero_grad()
+        for rel in ("q", "reach"):
+            n = outs[rel]["tags"].shape[0]
+            if rel not in grads or grads[rel].shape[0] != n:
+                grads[rel] = torch.tensor(synth.normal_grads(len(grads) + 3, n), device=dev)
+            eng.backward(rel, grads[rel])
+        for r, (cols, p, smp) in facts.items():
+            eng.grad(r, p.shape[0], out=torch.empty_like(p))
+        return outs
+
+    eng = dlfix.Engine(synth.TOPK_PROGRAM, "diff_topk", k=3, batched=True)
+    facts = dev_facts(lambda s_: np.ones(s_.size, bool))
+    grads = {}
+    for _ in range(warmup):
+        step(eng, facts, grads, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        outs = step(eng, facts, grads, True)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+    derived = sum(int(o["tags"].shape[0]) for o in outs.values())
+
+    plain = dlfix.Engine(synth.TOPK_PROGRAM, "diff_topk", k=3)
+    per = [dev_facts(lambda s_, i=i: s_ == i) for i in range(plain_samples)]
+    pgrads = [dict() for _ in range(plain_samples)]
+    step(plain, per[0], pgrads[0], False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(plain_samples):
+        step(plain, per[i], pgrads[i], False)
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / plain_samples
+    return {"metric": "batched fwd+bwd samples/sec",
+            "workload": f"{S} scenes of 10-40 objects, 8 unary + 4 binary probabilistic relations, 3-way join "
+                        "rule + recursive rule, diff top-3 proofs, gradient on every output tuple",
+            "batched_samples_per_s": S / tb, "batched_ms_per_step": tb * 1e3,
+            "plain_samples_per_s": 1.0 / tp, "plain_sample_ms": tp * 1e3,
+            "plain_measured_on": f"all {plain_samples} samples" if plain_samples == S
+            else f"first {plain_samples} samples",
+            "speedup": (S / tb) * tp, "derived_tuples": derived}
+
+
+def tc_context(seed: int, n: int, m: int, semiring: str, steps: int, tune_cache: str | None) -> dict:
+    """Derived tuples/s of one transitive-closure fixpoint (context figures:
+    the small graph is cache-resident)."""
+    from paper_2503_21937_amd import dlfix, synth
+    import torch
+    src, dst, p = synth.er_graph(seed, n, m, weights=True)
+    e = dlfix.Engine(synth.TC_PROGRAM, semiring)
+    e.add_facts("edge", [src, dst], None if semiring == "bool" else p)
+    if tune_cache:
+        e.autotune(1, tune_cache)
+    e.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = e.stats()
+    return {"workload": f"transitive closure, ER {n} nodes / {m} edges (seed {seed}), {semiring}",
+            "derived_tuples_per_s": st["derived"] / dt, "ms_per_run": dt * 1e3, "derived": st["derived"],
+            "rounds": st["max_rounds"], "note": "working set fits the 256 MB last-level cache"}
+
+
+def andersen_context(seed: int, scale: float, steps: int) -> dict:
+    """Derived tuples/s of the four-rule points-to fixpoint on the Zipf(1.2)
+    facts with every count (ids included) scaled by `scale`."""
+    from paper_2503_21937_amd import dlfix, synth
+    import torch
+    v = int(100000 * scale)
+    rels = synth.andersen(seed, v=v, n_addr=int(50000 * scale), n_assign=int(300000 * scale),
+                          n_load=int(40000 * scale), n_store=int(40000 * scale))
+    e = dlfix.Engine(synth.ANDERSEN_PROGRAM, "bool")
+    for name, (a, b) in rels.items():
+        e.add_facts(name, [a, b])
+    e.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = e.stats()
+    return {"workload": f"points-to (addr/assign/load/store), Zipf(1.2) facts at scale {scale} of the "
+                        f"100k-variable configuration ({v} ids)",
+            "derived_tuples_per_s": st["derived"] / dt, "ms_per_run": dt * 1e3, "derived": st["derived"],
+            "candidates": st["candidates"], "rounds": st["max_rounds"]}
 
 
 def copy_calibration(mib: int) -> None:
@@ -187,7 +350,12 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grids", action="store_true", help="skip the batched fwd+bwd grid workload")
-    ap.add_argument("--plain-samples", type=int, default=32)
+    ap.add_argument("--plain-samples", type=int, default=512,
+                    help="grid samples the one-sample-at-a-time engine is timed on (all 512 by default)")
+    ap.add_argument("--no-scenes", action="store_true", help="skip the batched top-3 scenes workload")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the context figures (small cache-resident graph, points-to)")
+    ap.add_argument("--andersen-scale", type=float, default=0.1)
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuner; use default configurations")
     ap.add_argument("--tune-cache", default=None, metavar="PATH",
                     help="autotuner cache to read and extend (default: a fresh temporary file); a profiled "
@@ -295,8 +463,15 @@ def main() -> int:
     }
     if not args.no_grids:
         line["batched"] = grids_fwd_bwd(max(1, min(args.steps, 3)), 1, args.seed, args.plain_samples, tune_cache)
+    if not args.no_scenes:
+        line["batched_topk"] = scenes_fwd_bwd(max(1, min(args.steps, 3)), 1, args.seed, 256)
+    if not args.no_context:
+        line["context"] = {"tc_small": tc_context(args.seed, 256, 1024, "bool", 10, tune_cache)}
+        if args.andersen_scale > 0:
+            line["context"]["points_to"] = andersen_context(args.seed, args.andersen_scale, 3)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(src, dst, p, args.nodes, args.cpu_budget, args.seed)
+        threads = max(1, min(16, os.cpu_count() or 1))
+        line["cpu_baseline"] = cpu_baseline(src, dst, p, args.nodes, args.cpu_budget, args.seed, threads)
     print(json.dumps(line), flush=True)
     return 0
 

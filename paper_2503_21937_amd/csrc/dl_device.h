@@ -60,6 +60,73 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* tmp, T* total) {
   return before + inc - v;
 }
 
+// Decoupled look-back of a single-pass scan across the workgroups of a
+// launch (Merrill and Garland's chained scan, with a whole block reading a
+// window of predecessors at a time).  Each workgroup's status is one 64-bit
+// word, flag and value together (so a relaxed load sees both): LB_AGG = the
+// block's own sum is published, LB_INC = its inclusive prefix is published.
+// Block b publishes LB_AGG | agg, then reads the statuses of the BLOCK
+// workgroups before it (each thread one word, spinning until that word has a
+// flag), adds everything from the latest LB_INC in the window on, and moves
+// one window further back only when the window holds no LB_INC; finally it
+// publishes LB_INC | (prefix + agg).  Block 0 publishes LB_INC at once, so a
+// window that reaches it always ends the walk, and the work per block is
+// bounded by how far the last published prefix lags behind -- not by b, as
+// when every block sums all of its predecessors.  Waits are only on
+// lower-numbered workgroups, which are dispatched earlier and publish before
+// they wait, so they end; they are bounded besides (*err = 3 if a spin runs
+// out, never expected).  When it returns, every block before b has published
+// (an LB_INC at block j implies that all blocks up to j have).  Returns the
+// exclusive prefix of block b to every thread.  Called by all threads of a
+// BLOCK-thread workgroup; `sh` is __shared__ storage of 2 * NWAVES words.
+constexpr uint64_t LB_AGG = 1ull << 62;
+constexpr uint64_t LB_INC = 1ull << 63;
+constexpr uint64_t LB_VAL = LB_AGG - 1;
+
+__device__ __forceinline__ uint64_t block_lookback(uint64_t* stat, uint64_t agg, uint64_t* sh,
+                                                   uint64_t* err) {
+  const uint32_t b = blockIdx.x;
+  if (b == 0) {
+    if (threadIdx.x == 0) __hip_atomic_store(stat, LB_INC | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(stat + b, LB_AGG | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int lane = lane_id(), wv = threadIdx.x / WAVE;
+  uint64_t pre = 0;
+  for (int64_t end = b;; end -= BLOCK) {
+    const int64_t i = end - BLOCK + (int64_t)threadIdx.x;
+    uint64_t v = 0;
+    if (i >= 0) {
+      uint32_t spins = 0;
+      while (!((v = __hip_atomic_load(stat + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & (LB_AGG | LB_INC))) {
+        if (++spins > (1u << 24)) {
+          *err = 3;
+          v = LB_INC;  // end the walk; the result is reported as failed
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    // latest inclusive prefix in the window (position in the block), -1 if none
+    const uint64_t m = __ballot(i >= 0 && (v & LB_INC));
+    if (lane == 0) sh[wv] = m ? (uint64_t)(wv * WAVE + 63 - __builtin_clzll(m)) + 1 : 0;
+    __syncthreads();
+    int64_t hi = -1;
+#pragma unroll
+    for (int w = 0; w < NWAVES; ++w)
+      if (sh[w]) hi = (int64_t)sh[w] - 1;
+    const uint64_t mine = wave_sum<uint64_t>(i >= 0 && (int64_t)threadIdx.x >= hi ? (v & LB_VAL) : 0ull);
+    if (lane == 0) sh[NWAVES + wv] = mine;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NWAVES; ++w) pre += sh[NWAVES + w];
+    __syncthreads();  // sh is rewritten by the next window
+    if (hi >= 0) break;
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(stat + b, LB_INC | (pre + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return pre;
+}
+
 // ---------------------------------------------------------------- tag types
 // Bool: presence is the tag (nothing stored).
 struct NoTag {};

@@ -871,11 +871,12 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
     if (!total) return;
     nb = (total + tile - 1) / tile;
   }
+  // algorithmic bytes of a join: every probe row read once (key + tag), every
+  // derivation once (key + tag, and a lineage pair of two 4-byte ids when
+  // recorded); the dense words a derivation is folded into are not counted
   const double tb = tk == TAG_F32 ? 4.0 : 0.0;
-  const double lin = lineage ? 4.0 : 0.0;
-  // per derivation: index row read, presence word and dense tag read; per probe row: driver row + offset
-  const double per = (sizeof(K) + tb + lin + 4.0 + tb);
-  const double bytes = (dtotal ? 0.0 : total * per) + a.n * (sizeof(K) + tb + lin + 4.0);
+  const double per = sizeof(K) + tb + (lineage ? 8.0 : 0.0);
+  const double bytes = (dtotal ? 0.0 : total * per) + a.n * (sizeof(K) + tb);
   // row windows: one launch of the row-window kernel, which reads the total
   // and falls back to scattered tiles below the threshold when the total is
   // only known on the device (with lineage the total is known on the host)
@@ -1128,22 +1129,16 @@ DenseCsr dense_csr(uint32_t* off, uint32_t wwords, uint32_t n) {
 }
 
 // The block's first output slot in a single pass (no separate count
-// launch): the block publishes its count (flag bit 63 over the value), then
-// its threads add up the published counts of all blocks before it, each
-// spinning until that block has published -- which every block does before
-// it waits on anything, so the spins end (they are bounded besides, flag 3
-// in *err).  The blocks run together, so summing every predecessor takes one
-// round of loads where a chained look-back would walk back block by block.
-// Launches alternate between two status sets (a parity word after them);
-// the last block, having seen every other block publish, clears the
+// launch): a decoupled look-back over the blocks' touched counts
+// (block_lookback).  Launches alternate between two status sets (a parity
+// word after them); the last block, whose look-back ends only after every
+// other block has published (and so has read the parity), clears the
 // previous launch's set and flips the parity.  The last block also writes
 // the grand total (and the round log).
-constexpr uint64_t LB_PUB = 1ull << 63;
-
 size_t lookback_state_words(size_t blocks) { return 2 * blocks + 1; }
 
 __device__ __forceinline__ uint32_t block_first_slot_published(uint64_t* lb, size_t cap, uint32_t own_wave_count,
-                                                               uint32_t* s_tot, uint32_t* s_pre, uint64_t* d_total,
+                                                               uint32_t* s_tot, uint64_t* sh, uint64_t* d_total,
                                                                uint64_t* log, uint64_t* err) {
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const uint32_t par = (uint32_t)__hip_atomic_load(lb + 2 * cap, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u;
@@ -1151,25 +1146,7 @@ __device__ __forceinline__ uint32_t block_first_slot_published(uint64_t* lb, siz
   if (lane == 0) s_tot[wv] = own_wave_count;
   __syncthreads();
   const uint32_t own = s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
-  if (threadIdx.x == 0)
-    __hip_atomic_store(stat + blockIdx.x, LB_PUB | own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  uint64_t pre = 0;
-  for (size_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) {
-    uint64_t v;
-    uint32_t spins = 0;
-    while (!((v = __hip_atomic_load(stat + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & LB_PUB)) {
-      if (++spins > (1u << 24)) {
-        *err = 3;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    pre += v & 0xffffffffull;
-  }
-  pre = wave_sum(pre);
-  if (lane == 0) s_pre[wv] = (uint32_t)pre;
-  __syncthreads();
-  const uint32_t base = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3];
+  const uint32_t base = (uint32_t)block_lookback(stat, own, sh, err);
   if (blockIdx.x == gridDim.x - 1) {  // every block has published: clear the other set, flip
     uint64_t* prev = lb + (1u - par) * cap;
     for (size_t i = threadIdx.x; i < gridDim.x; i += BLOCK)
@@ -1193,6 +1170,7 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
                                                           int prefixed, DenseCsr csr, uint64_t* __restrict__ lb,
                                                           size_t lb_cap) {
   __shared__ uint32_t s_tot[NWAVES], s_pre[NWAVES];
+  __shared__ uint64_t s_lb[2 * NWAVES];
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
   uint32_t b[BM_ITEMS];  // the lane's words, loaded together
@@ -1204,7 +1182,7 @@ __global__ __launch_bounds__(BLOCK) void k_dense_finalize(DenseArgs d, size_t wo
     c += (uint32_t)__popc(b[i]);
   }
   c = wave_sum(c);
-  uint32_t o = lb ? block_first_slot_published(lb, lb_cap, c, s_tot, s_pre, d_total, log, d.overflow)
+  uint32_t o = lb ? block_first_slot_published(lb, lb_cap, c, s_tot, s_lb, d_total, log, d.overflow)
                   : block_first_slot(counts, prefixed, c, s_tot, s_pre, d_total, log);
   if (csr.off) {
     // group starts: a word wi with wi % wwords == 0 opens first-column group
@@ -1310,6 +1288,7 @@ __global__ __launch_bounds__(BLOCK) void k_bitmap_keys(DenseArgs d, size_t words
                                                        int prefixed, K* __restrict__ keys, float* __restrict__ tags,
                                                        uint32_t* __restrict__ ids) {
   __shared__ uint32_t s_tot[NWAVES], s_pre[NWAVES];
+  __shared__ uint64_t s_lb[2 * NWAVES];
   const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const size_t w0 = (size_t)blockIdx.x * BM_TILE + (size_t)wv * BM_WAVE_WORDS;
   uint32_t b[BM_ITEMS];

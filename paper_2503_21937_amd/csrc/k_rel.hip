@@ -167,19 +167,16 @@ void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st) {
 
 
 // Join counts and their exclusive scan in one launch (single-pass scan).
-// Workgroup b counts the matches of its tile of CS_TILE driver rows,
-// publishes the tile sum (one 64-bit word: flag bit 63 over the sum), adds
-// the published sums of all tiles before it and writes its offsets.  It waits
-// only on lower-numbered workgroups, which were dispatched before it and
-// publish before they wait, so every wait ends; the wait is also bounded
-// (flag 3 in *err, never expected).  Launches alternate between two status
-// sets (a parity word): the last workgroup, dispatched after every other one
-// has read the parity and done only once all have published, clears the set
-// of the previous launch (all of whose workgroups have ended) and flips the
-// parity.
+// Workgroup b counts the matches of its tile of CS_TILE driver rows and gets
+// the sum of the tiles before it by a decoupled look-back (block_lookback),
+// then writes its offsets; the last tile writes the total.  Launches
+// alternate between two status sets (a parity word after them): the last
+// workgroup, whose look-back ends only once every other workgroup has
+// published (and so has read the parity), clears the set of the previous
+// launch (all of whose workgroups have ended) and flips the parity, so the
+// set a launch starts on is always clear.
 constexpr int CS_ITEMS = 1;
 constexpr int CS_TILE = BLOCK * CS_ITEMS;
-constexpr uint64_t CS_PUB = 1ull << 63;
 
 size_t count_scan_state_words() { return CS_MAX_TILES * 2 + 2; }
 
@@ -187,7 +184,7 @@ template <typename K>
 __global__ __launch_bounds__(BLOCK) void k_join_count_scan(JoinArgs a, uint32_t* __restrict__ offs,
                                                            uint64_t* __restrict__ state, uint64_t* __restrict__ d_total,
                                                            uint64_t* __restrict__ acc, uint64_t* __restrict__ err) {
-  __shared__ uint64_t tmp[NWAVES], s_pre[NWAVES];
+  __shared__ uint64_t tmp[NWAVES], sh[2 * NWAVES];
   uint64_t* parity = state + 2 * CS_MAX_TILES;
   const uint32_t par = (uint32_t)__hip_atomic_load(parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u;
   uint64_t* stat = state + par * CS_MAX_TILES;
@@ -209,24 +206,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_count_scan(JoinArgs a, uint32_t*
   }
   uint64_t tot;
   const uint64_t ex = block_exclusive_scan(s, tmp, &tot);
-  if (threadIdx.x == 0) __hip_atomic_store(stat + blockIdx.x, CS_PUB | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  uint64_t pre = 0;
-  for (size_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) {
-    uint64_t v;
-    uint32_t spins = 0;
-    while (!((v = __hip_atomic_load(stat + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & CS_PUB)) {
-      if (++spins > (1u << 24)) {
-        *err = 3;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    pre += v & ~CS_PUB;
-  }
-  pre = wave_sum(pre);
-  if (lane_id() == 0) s_pre[threadIdx.x / WAVE] = pre;
-  __syncthreads();
-  const uint64_t carry = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3];
+  const uint64_t carry = block_lookback(stat, tot, sh, err);
   uint64_t run = carry + ex;
 #pragma unroll
   for (int q = 0; q < CS_ITEMS; ++q) {
@@ -312,10 +292,9 @@ void join_expand(const JoinArgs& a, int tk, const uint32_t* offs, size_t total, 
   const int items = a.items == 1 || a.items == 2 || a.items == 8 ? a.items : 4;
   const size_t nb = (total + (size_t)BLOCK * items - 1) / ((size_t)BLOCK * items);
   const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : (double)sizeof(TopK);
-  const double lin = ol ? 4.0 : 0.0;
-  // outputs written, index rows read once per output, driver rows and offsets read once
-  const double bytes = total * (sizeof(K) + tb + 2 * lin) + total * (sizeof(K) + tb + lin) +
-                       a.n * (sizeof(K) + tb + lin + 4.0);
+  // algorithmic bytes of a join: probe rows read once (key + tag), every
+  // derivation once (key + tag, plus its two lineage ids when recorded)
+  const double bytes = total * (sizeof(K) + tb + (ol ? 8.0 : 0.0)) + a.n * (sizeof(K) + tb);
 #define DL_EXPAND(IT)                                                                                          \
   if (tk == TAG_NONE)                                                                                          \
     k_join_expand<K, TAG_NONE, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (NoTag*)otags, ol, orr);  \

@@ -149,8 +149,10 @@ void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st);  // also f
 // Counts and their exclusive scan (offs[0..n], total in *d_total, added to
 // *acc when set) in one launch for up to CS_MAX_TILES tiles of 256 driver
 // rows; false (nothing launched) otherwise or when n == 0.  `state` holds
-// count_scan_state_words() zeroed words, left zeroed; *err = 3 reports a
-// look-back wait that did not end.
+// count_scan_state_words() words, zeroed before the first launch: two sets
+// of tile statuses and a parity word; each launch works on one set and
+// clears the other, so the next launch starts on a clear set; *err = 3
+// reports a look-back wait that did not end.
 constexpr size_t CS_MAX_TILES = 8192;
 size_t count_scan_state_words();
 template <typename K>
@@ -207,10 +209,11 @@ struct DenseCsr {
   uint8_t s1 = 0, s2 = 0;
 };
 DenseCsr dense_csr(uint32_t* off, uint32_t wwords, uint32_t n);
-// With `lookback` (lookback_state_words(dense_count_blocks(nkeys)) zeroed
-// words, left in a reusable state; d_total must be set): every block
-// publishes its count and sums the published counts before it, so `counts`
-// is not read -- no bitmap_block_counts launch is needed.
+// With `lookback` (lookback_state_words(dense_count_blocks(nkeys)) words,
+// zeroed before the first launch and kept across launches; d_total must be
+// set): the blocks find their first slots by a decoupled look-back over
+// their published counts, so `counts` is not read -- no bitmap_block_counts
+// launch is needed.
 size_t lookback_state_words(size_t blocks);
 template <typename K>
 void dense_finalize(const DenseArgs& d, size_t nkeys, const uint32_t* counts, K* keys, float* rtags, uint32_t id_base,

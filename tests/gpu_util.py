@@ -41,3 +41,16 @@ def same_rows(g, o, batched=False):
     assert np.array_equal(g["cols"], o["cols"]), "tuple sets differ"
     if batched:
         assert np.array_equal(g["sample"], o["sample"]), "sample ids differ"
+
+
+def tune_key(e):
+    """The autotuner's key for an engine's current facts, read back through a
+    throwaway cache (forcing a configuration then means writing that key)."""
+    import json
+    import os
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "c.jsonl")
+        e.autotune(1, path)
+        line = open(path).read().splitlines()[-1]
+        return json.loads(line)["key"]

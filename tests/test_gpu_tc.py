@@ -180,3 +180,34 @@ def test_join_counts_across_tiles(oracle, sr, dedup, n):
     same_rows(g, o)
     if sr == "maxmin":
         assert np.array_equal(g["tags"].astype(np.float64), o["value"])
+
+
+@pytest.mark.parametrize("dedup", DEDUP)
+@pytest.mark.parametrize("n", [2048 * 256 + 1, 8192 * 256])
+def test_join_counts_many_tiles(dedup, n):
+    """Single-pass count + scan at its largest sizes (2049 and 8192 tiles of
+    256 distinct probe rows), checked against the boolean and max-min matrix
+    products computed here (c = a o b)."""
+    from scipy.sparse import csr_matrix
+    rng = np.random.default_rng(n)
+    nx, ny, nz = 8192, 300, 400
+    cell = rng.choice(nx * ny, size=n, replace=False)
+    ax, ay = (cell // ny).astype(np.uint32), (cell % ny).astype(np.uint32)
+    bcell = rng.choice(ny * nz, size=900, replace=False)
+    bx, bz = (bcell // nz).astype(np.uint32), (bcell % nz).astype(np.uint32)
+    pa = rng.uniform(0.1, 0.9, n).astype(np.float32)
+    pb = rng.uniform(0.1, 0.9, 900).astype(np.float32)
+    facts = {"a": ([ax, ay], pa, None), "b": ([bx, bz], pb, None)}
+    A = csr_matrix((np.ones(n), (ax, ay)), shape=(nx, ny))
+    B = csr_matrix((np.ones(900), (bx, bz)), shape=(ny, nz))
+    want = np.argwhere((A @ B).toarray() > 0).astype(np.uint32)
+    g = engine(JOIN2, "bool", facts, dedup=dedup).read("c")
+    assert np.array_equal(g["cols"], want)
+    # max-min: c(x, z) = max over y of min(a(x, y), b(y, z)), by rows of b
+    C = np.zeros((nx, nz), np.float64)
+    for y, z, q in zip(bx, bz, pb.astype(np.float64)):
+        m = ay == y
+        np.maximum.at(C[:, z], ax[m], np.minimum(pa[m].astype(np.float64), q))
+    g = engine(JOIN2, "maxmin", facts, dedup=dedup).read("c")
+    assert np.array_equal(g["cols"], want)
+    assert np.array_equal(g["tags"].astype(np.float64), C[want[:, 0], want[:, 1]])
