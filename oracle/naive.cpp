@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <map>
 #include <memory>
@@ -31,9 +32,25 @@ struct Atom {
   int rel;
   std::vector<Term> args;
 };
+// Arithmetic over u32 values (Sec. 5, expression evaluation: head terms
+// computed from the bound variables, comparisons filtering derivations).
+// + - * wrap modulo 2^32, / and % are unsigned; a division by zero voids the
+// derivation.
+struct Expr {
+  enum Op { VAR, CONST, ADD, SUB, MUL, DIV, MOD } op = CONST;
+  uint32_t v = 0;  // variable index or constant
+  std::vector<Expr> kids;
+};
+enum Cmp { CMP_EQ, CMP_NE, CMP_LT, CMP_LE, CMP_GT, CMP_GE };
+struct Cond {
+  Cmp cmp;
+  Expr a, b;
+};
 struct Rule {
   Atom head;
+  std::vector<Expr> head_terms;  // one per head column
   std::vector<Atom> body;
+  std::vector<Cond> conds;       // every one must hold for a derivation to count
   int nvars;
 };
 struct RelInfo {
@@ -116,6 +133,113 @@ struct Parser {
     if (prog.rels[r].arity != arity) fail("arity mismatch for " + name);
     return r;
   }
+  int var(std::map<std::string, int>& vars, const std::string& v) {
+    auto it = vars.find(v);
+    int id = it == vars.end() ? (int)vars.size() : it->second;
+    if (it == vars.end()) vars[v] = id;
+    return id;
+  }
+  // expr := term {(+|-) term}; term := factor {(*|/|%) factor};
+  // factor := number | variable | ( expr )
+  Expr factor(std::map<std::string, int>& vars) {
+    skip();
+    Expr x;
+    if (peek('(')) {
+      expect("(");
+      x = expr(vars);
+      expect(")");
+    } else if (i < s.size() && std::isdigit((unsigned char)s[i])) {
+      x.op = Expr::CONST;
+      x.v = number();
+    } else {
+      x.op = Expr::VAR;
+      x.v = (uint32_t)var(vars, ident());
+    }
+    return x;
+  }
+  Expr term(std::map<std::string, int>& vars) {
+    Expr x = factor(vars);
+    for (;;) {
+      Expr::Op op;
+      if (peek('*')) op = Expr::MUL;
+      else if (peek('/') && !(i + 1 < s.size() && s[i + 1] == '/')) op = Expr::DIV;
+      else if (peek('%')) op = Expr::MOD;
+      else return x;
+      ++i;
+      Expr y;
+      y.op = op;
+      y.kids = {x, factor(vars)};
+      x = y;
+    }
+  }
+  Expr expr(std::map<std::string, int>& vars) {
+    Expr x = term(vars);
+    for (;;) {
+      Expr::Op op;
+      if (peek('+')) op = Expr::ADD;
+      else if (peek('-')) op = Expr::SUB;
+      else return x;
+      ++i;
+      Expr y;
+      y.op = op;
+      y.kids = {x, term(vars)};
+      x = y;
+    }
+  }
+  Cond comparison(std::map<std::string, int>& vars) {
+    Cond c;
+    c.a = expr(vars);
+    skip();
+    static const struct {
+      const char* t;
+      Cmp c;
+    } ops[] = {{"==", CMP_EQ}, {"!=", CMP_NE}, {"<=", CMP_LE}, {">=", CMP_GE},
+               {"<", CMP_LT},  {">", CMP_GT},  {"=", CMP_EQ}};
+    bool found = false;
+    for (auto& o : ops)
+      if (s.compare(i, std::strlen(o.t), o.t) == 0) {
+        i += std::strlen(o.t);
+        c.cmp = o.c;
+        found = true;
+        break;
+      }
+    if (!found) fail("expected a comparison operator");
+    c.b = expr(vars);
+    return c;
+  }
+  // The head: a relation whose arguments are expressions over the body's
+  // variables (a plain variable or constant is the common case).
+  Atom head(std::map<std::string, int>& vars, std::vector<Expr>& terms) {
+    std::string name = ident();
+    expect("(");
+    std::vector<Term> args;
+    if (!peek(')')) {
+      for (;;) {
+        Expr x = expr(vars);
+        terms.push_back(x);
+        args.push_back({x.op == Expr::VAR, x.v});  // only meaningful for VAR / CONST
+        if (peek(',')) {
+          expect(",");
+          continue;
+        }
+        break;
+      }
+    }
+    expect(")");
+    return {relation(name, (int)args.size()), args};
+  }
+  // A body item is an atom `name(...)` or a comparison `expr op expr`.
+  bool next_is_atom() {
+    skip();
+    size_t save = i;
+    bool atom = false;
+    if (i < s.size() && (std::isalpha((unsigned char)s[i]) || s[i] == '_')) {
+      (void)ident();
+      atom = peek('(');
+    }
+    i = save;
+    return atom;
+  }
   Atom atom(std::map<std::string, int>& vars) {
     std::string name = ident();
     expect("(");
@@ -140,7 +264,6 @@ struct Parser {
       }
     }
     expect(")");
-    if (args.empty()) fail("nullary relations are not supported");
     return {relation(name, (int)args.size()), args};
   }
   void parse() {
@@ -153,7 +276,7 @@ struct Parser {
         std::string name = ident();
         expect("/");
         int arity = (int)number();
-        if (arity < 1 || arity > 4) fail("arity must be 1..4");
+        if (arity < 0 || arity > 4) fail("arity must be 0..4");
         int r = relation(name, arity);
         if (kw == "input") prog.rels[r].input = true;
         else if (kw != "output") fail("unknown directive ." + kw);
@@ -161,10 +284,11 @@ struct Parser {
       }
       std::map<std::string, int> vars;
       Rule rule;
-      rule.head = atom(vars);
+      rule.head = head(vars, rule.head_terms);
       expect(":-");
       for (;;) {
-        rule.body.push_back(atom(vars));
+        if (next_is_atom()) rule.body.push_back(atom(vars));
+        else rule.conds.push_back(comparison(vars));
         if (peek(',')) {
           expect(",");
           continue;
@@ -177,8 +301,13 @@ struct Parser {
       for (auto& a : rule.body)
         for (auto& t : a.args)
           if (t.var) inbody[t.v] = true;
-      for (auto& t : rule.head.args)
-        if (t.var && !inbody[t.v]) fail("head variable not bound by the body");
+      if (rule.body.empty()) fail("a rule needs a body atom");
+      std::function<void(const Expr&)> bound = [&](const Expr& x) {
+        if (x.op == Expr::VAR && !inbody[x.v]) fail("variable not bound by a body atom");
+        for (auto& k : x.kids) bound(k);
+      };
+      for (auto& t : rule.head_terms) bound(t);
+      for (auto& c : rule.conds) bound(c.a), bound(c.b);
       prog.rules.push_back(rule);
     }
     for (auto& r : prog.rules) prog.rels[r.head.rel].idb = true;
@@ -412,9 +541,46 @@ struct Evaluator {
     return m;
   }
 
+  static uint32_t eval(const Expr& x, const std::vector<uint32_t>& val, bool& ok) {
+    switch (x.op) {
+      case Expr::VAR: return val[x.v];
+      case Expr::CONST: return x.v;
+      default: break;
+    }
+    const uint32_t a = eval(x.kids[0], val, ok), b = eval(x.kids[1], val, ok);
+    switch (x.op) {
+      case Expr::ADD: return a + b;
+      case Expr::SUB: return a - b;
+      case Expr::MUL: return a * b;
+      default:
+        if (b == 0) {
+          ok = false;
+          return 0;
+        }
+        return x.op == Expr::DIV ? a / b : a % b;
+    }
+  }
+  static bool holds(const Cond& c, const std::vector<uint32_t>& val) {
+    bool ok = true;
+    const uint32_t a = eval(c.a, val, ok), b = eval(c.b, val, ok);
+    if (!ok) return false;
+    switch (c.cmp) {
+      case CMP_EQ: return a == b;
+      case CMP_NE: return a != b;
+      case CMP_LT: return a < b;
+      case CMP_LE: return a <= b;
+      case CMP_GT: return a > b;
+      default: return a >= b;
+    }
+  }
+
   void produce(const Rule& r, const std::vector<uint32_t>& val, const std::vector<Entry*>& body) {
+    for (const Cond& c : r.conds)
+      if (!holds(c, val)) return;
     Key h;
-    for (auto& t : r.head.args) h.push_back(t.var ? val[t.v] : t.v);
+    bool ok = true;
+    for (auto& t : r.head_terms) h.push_back(eval(t, val, ok));
+    if (!ok) return;
     Rel& target = db.rel[r.head.rel];
     bool present = target.count(h) != 0;
     const Semiring& sr = e->sr;

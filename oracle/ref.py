@@ -92,7 +92,8 @@ class Oracle:
             elif ":-" in line:  # a rule head names a derived relation
                 head = line.split(":-")[0]
                 name, args = head.split("(", 1)
-                self.arity.setdefault(name.strip(), args.count(",") + 1)
+                args = args.rsplit(")", 1)[0]
+                self.arity.setdefault(name.strip(), args.count(",") + 1 if args.strip() else 0)
         self.semiring = semiring
         self.batched = batched
         h = C.c_void_p()
