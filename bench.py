@@ -301,6 +301,30 @@ def tc_context(seed: int, n: int, m: int, semiring: str, steps: int, tune_cache:
             "rounds": st["max_rounds"], "note": "working set fits the 256 MB last-level cache"}
 
 
+def sg_context(seed: int, n: int, m: int, semiring: str, steps: int, tune_cache: str | None) -> dict:
+    """Derived tuples/s of the Same Generation fixpoint (non-linear recursion
+    with an x != y selection) on the benchmark's graph."""
+    from paper_2503_21937_amd import dlfix, synth
+    import torch
+    src, dst, p = synth.er_graph(seed, n, m, weights=True)
+    e = dlfix.Engine(synth.SG_PROGRAM, semiring)
+    e.add_facts("edge", [src, dst], None if semiring == "bool" else p)
+    if tune_cache:
+        e.autotune(1, tune_cache)
+    e.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = e.stats()
+    return {"workload": f"same generation, ER {n} nodes / {m} edges (seed {seed}), {semiring}",
+            "derived_tuples_per_s": st["derived"] / dt, "ms_per_run": dt * 1e3, "derived": st["derived"],
+            "candidates": st["candidates"], "rounds": st["max_rounds"],
+            "exec": {k: st[k] for k in ("dedup", "orient", "items", "rows")}}
+
+
 def andersen_context(seed: int, scale: float, steps: int) -> dict:
     """Derived tuples/s of the four-rule points-to fixpoint on the Zipf(1.2)
     facts with every count (ids included) scaled by `scale`."""
@@ -355,7 +379,7 @@ def main() -> int:
     ap.add_argument("--no-scenes", action="store_true", help="skip the batched top-3 scenes workload")
     ap.add_argument("--no-context", action="store_true",
                     help="skip the context figures (small cache-resident graph, points-to)")
-    ap.add_argument("--andersen-scale", type=float, default=0.1)
+    ap.add_argument("--andersen-scale", type=float, default=0.05)
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuner; use default configurations")
     ap.add_argument("--tune-cache", default=None, metavar="PATH",
                     help="autotuner cache to read and extend (default: a fresh temporary file); a profiled "
@@ -467,6 +491,8 @@ def main() -> int:
         line["batched_topk"] = scenes_fwd_bwd(max(1, min(args.steps, 3)), 1, args.seed, 256)
     if not args.no_context:
         line["context"] = {"tc_small": tc_context(args.seed, 256, 1024, "bool", 10, tune_cache)}
+        line["context"]["same_generation"] = [sg_context(args.seed, args.nodes, args.edges, sr, 3, tune_cache)
+                                              for sr in ("bool", "maxmin")]
         if args.andersen_scale > 0:
             line["context"]["points_to"] = andersen_context(args.seed, args.andersen_scale, 3)
     if not args.no_cpu_baseline:

@@ -36,7 +36,8 @@ typedef enum {
   DL_ERR_PARSE = 2,           /* program text does not parse */
   DL_ERR_UNSUPPORTED = 3,     /* construct outside the supported fragment (see dl_load_program) */
   DL_ERR_STATE = 4,           /* call out of order (e.g. read before run) */
-  DL_ERR_NOMEM = 5,           /* device allocation failed; engine and facts stay valid */
+  DL_ERR_NOMEM = 5,           /* device allocation failed or the workspace is full; the engine and its
+                                 facts stay valid: rerun after dl_set_workspace with a larger block */
   DL_ERR_CAPACITY = 6,        /* a size exceeds an index width (e.g. > 2^32 join outputs in one round) */
   DL_ERR_PROOF_OVERFLOW = 7,  /* top-k: more than 64 probabilistic facts in one sample */
   DL_ERR_HIP = 8              /* a HIP runtime call failed */
@@ -87,7 +88,15 @@ typedef struct {
                          2 = never recorded: dl_backward re-runs each round's joins on the
                              relation as it stood then (rebuilt from discovery ids) */
   size_t lineage_budget;  /* lineage = 0: bytes of recorded lineage allowed before it is dropped
-                             (0: a quarter of the device memory free at creation) */
+                             (0: a quarter of the device memory free at creation, or of the workspace) */
+  void* workspace;        /* device memory the engine keeps ALL its device buffers in (facts, relations,
+                             indexes, round scratch), e.g. a torch tensor's storage; borrowed until
+                             dl_free or dl_set_workspace.  The engine then never calls hipMalloc /
+                             hipFree: buffers are ranges of this block, reused across iterations and
+                             runs (Sec. 4.1, buffer reuse), and growing a buffer never waits for the
+                             stream.  Its contents on entry do not matter.  NULL: the engine makes
+                             its own hipMalloc allocations. */
+  size_t workspace_bytes; /* size of `workspace` in bytes (at least 256) */
 } dl_options;
 
 /* Result columns of dl_read_relation.  Any pointer may be NULL (not written).
@@ -123,6 +132,8 @@ typedef struct {
                              dl_backward (0 for the other semirings) */
   int rows;               /* row-window joins in force: 0 off, 1 for launches with many derivations
                              per window (default), 2 wherever they apply */
+  uint64_t device_allocs; /* hipMalloc calls the engine has made since creation (0 with a workspace) */
+  uint64_t workspace_peak;/* largest number of workspace bytes in use at once (0 without a workspace) */
 } dl_stats;
 
 /* Kernel families timed by dl_profile (bit i of the mask = family i). */
@@ -147,7 +158,9 @@ typedef struct {
   double bytes;           /* summed algorithmic bytes (minimum reads + writes) */
 } dl_kernel_timing;
 
-/* Parse and plan a program.
+/* Parse and plan a program: the RAM program of Algorithm 1 (rules as
+ * relational-algebra operators over columnar relations, Sec. 3.3; strata
+ * evaluated one after the other, each to its fixpoint).
  * Text: one statement per '.'-terminated clause; '#' or '//' start comments.
  *   .input name/arity           declares an input (extensional) relation
  *   .output name/arity          optional; any derived relation can be read
@@ -163,10 +176,13 @@ typedef struct {
  * engine (free with dl_free). */
 dl_status dl_load_program(const char* program_text, const dl_options* opts, dl_engine** out);
 
-/* Drop all facts and results, keep the program. */
+/* Drop all facts and results, keep the program (and every device buffer, for
+ * reuse by the next facts: Sec. 4.1, buffer reuse across runs). */
 dl_status dl_clear_facts(dl_engine* e);
 
-/* Append n facts to input relation `relation`.
+/* Append n facts to input relation `relation` (the extensional database F_T
+ * that Algorithm 1 takes as input; one column array per attribute, Sec. 3.3
+ * columnar relations; in batched engines a sample-id column, Sec. 4.3).
  * columns: `arity` pointers to n uint32 values each (SoA).
  * sample_ids: n values (batched engines; ignored otherwise, may be NULL).
  * tags: n binary32 values (probability / weight); NULL allowed for BOOL.
@@ -176,20 +192,40 @@ dl_status dl_add_facts(dl_engine* e, const char* relation, size_t n,
                        const uint32_t* sample_ids, const uint32_t* const* columns,
                        const float* tags, int on_device);
 
-/* Evaluate every stratum to its fixpoint.  Blocks until the result is on the
- * device (one small device-to-host read per join step and per iteration). */
+/* Evaluate every stratum to its fixpoint (Algorithm 1: stable = {}, recent =
+ * F_T, then semi-naive iterations until an iteration adds or changes nothing;
+ * Appendix A for the stable / recent / delta joins of one iteration).
+ * Blocks until the result is on the device (small device-to-host reads of
+ * counts, at most one per join step and per iteration).  DL_ERR_NOMEM: a
+ * buffer did not fit (device memory or workspace); the facts are kept and the
+ * call can be repeated, after dl_set_workspace where a workspace is used. */
 dl_status dl_run_fixpoint(dl_engine* e);
 
-/* Number of tuples of a relation (after dl_run_fixpoint for derived ones). */
+/* Move the engine's device buffers into a new workspace block (p != NULL,
+ * `bytes` long, contents irrelevant) or into separate hipMalloc allocations
+ * (p == NULL); the previous block is no longer used when the call returns
+ * (the call waits for the engine's stream).  Facts, results and indexes are
+ * kept.  DL_ERR_NOMEM (nothing moved) when the live buffers do not fit.
+ * This is the recovery path after a run returned DL_ERR_NOMEM (Sec. 4.1:
+ * the engine's memory is one arena whose buffers are reused). */
+dl_status dl_set_workspace(dl_engine* e, void* p, size_t bytes);
+
+/* Number of tuples of a relation (after dl_run_fixpoint for derived ones):
+ * |F_T| restricted to one relation at the fixpoint (Algorithm 1 result). */
 dl_status dl_relation_size(dl_engine* e, const char* relation, size_t* n);
 
-/* Copy a relation out (see dl_relation_out).  `capacity` rows are available
+/* Copy a relation out (see dl_relation_out): the derived facts of the
+ * fixpoint with their tags (Algorithm 1 result; per sample in batched
+ * engines, Sec. 4.3; top-k tags as their kept proofs, Sec. 3.5).  The engine
+ * keeps each relation as sorted packed keys; the columns are unpacked here
+ * (Sec. 3.3 columnar layout).  `capacity` rows are available
  * in every given buffer; fewer than the relation size gives DL_ERR_ARG.
  * on_device selects device (1) or host (0) pointers for all buffers. */
 dl_status dl_read_relation(dl_engine* e, const char* relation, size_t capacity,
                            const dl_relation_out* out, int on_device, size_t* n_written);
 
-/* Point queries: for n tuples given as columns (SoA; sample ids for batched
+/* Point queries (a lookup of the result database, Sec. 3.3 relations held
+ * sorted): for n tuples given as columns (SoA; sample ids for batched
  * engines) write rows[i] = the tuple's row in canonical order or -1 when it
  * is not in the relation, and tags[i] = its tag as in dl_read_relation (0 when
  * absent).  Either output may be NULL.  Binary search over the sorted result:
@@ -199,11 +235,14 @@ dl_status dl_lookup(dl_engine* e, const char* relation, size_t n, const uint32_t
 
 /* Reverse mode seeded on selected rows (e.g. from dl_lookup; rows < 0 are
  * skipped): d(loss)/d(tag of row rows[i]) = grad[i].  Same accumulation as
- * dl_backward. */
+ * dl_backward (Sec. 3.5, differentiable semirings). */
 dl_status dl_backward_rows(dl_engine* e, const char* relation, size_t n, const int64_t* rows, const float* grad,
                            int on_device);
 
-/* Reverse mode for DIFF_ADDMULT and DIFF_TOPK: grad_out[i] is d(loss)/d(tag)
+/* Reverse mode for DIFF_ADDMULT and DIFF_TOPK (Sec. 3.5: differentiable
+ * provenance semirings, whose tags carry derivatives with respect to the input
+ * facts' probabilities; computed here in reverse mode over the recorded or
+ * recomputed derivations): grad_out[i] is d(loss)/d(tag)
  * of row i of out_relation in canonical order.  Gradients with respect to the
  * input facts' tags are accumulated (+=) into the engine until dl_zero_grad.
  * DIFF_ADDMULT sweeps the discovery derivations round by round in reverse
@@ -212,7 +251,9 @@ dl_status dl_backward_rows(dl_engine* e, const char* relation, size_t n, const i
  * derivations are recomputed first, which costs about one forward join pass. */
 dl_status dl_backward(dl_engine* e, const char* out_relation, const float* grad_out, int on_device);
 
-/* Accumulated input gradients of an input relation, in dl_add_facts order. */
+/* Accumulated input gradients of an input relation, in dl_add_facts order
+ * (the derivative of the loss with respect to each input fact's probability,
+ * Sec. 3.5). */
 dl_status dl_read_grad(dl_engine* e, const char* in_relation, float* grad_in, int on_device);
 
 dl_status dl_zero_grad(dl_engine* e);

@@ -14,6 +14,19 @@ import torch
 from . import dlfix
 
 
+def with_room(engine, call):
+    """call(); when an engine with a workspace tensor runs out of room
+    (DL_ERR_NOMEM) it gets a tensor twice the size (allocated by torch; the
+    engine moves its buffers there) and the call is repeated."""
+    while True:
+        try:
+            return call()
+        except dlfix.DLError as x:
+            if x.status != 5 or engine.workspace is None:  # 5: DL_ERR_NOMEM
+                raise
+            engine.set_workspace(engine.workspace.nbytes * 2)
+
+
 class FixpointFunction(torch.autograd.Function):
     """out_tags = fixpoint(probs); sample ids and columns ride along."""
 
@@ -22,8 +35,8 @@ class FixpointFunction(torch.autograd.Function):
         torch.cuda.current_stream().synchronize()
         engine.clear_facts()
         engine.add_facts(in_rel, cols, probs.detach().contiguous(), sample)
-        engine.run()
-        out = engine.read(out_rel, device=True)
+        with_room(engine, engine.run)
+        out = with_room(engine, lambda: engine.read(out_rel, device=True))
         ctx.engine, ctx.in_rel, ctx.out_rel, ctx.n_in = engine, in_rel, out_rel, probs.shape[0]
         osample = out["sample"]
         ocols = torch.stack(out["cols"], 1) if out["cols"] else torch.zeros((0, 0), dtype=torch.int32)
@@ -34,10 +47,10 @@ class FixpointFunction(torch.autograd.Function):
     def backward(ctx, grad_tags, _gs, _gc):
         e = ctx.engine
         torch.cuda.current_stream().synchronize()
-        e.zero_grad()
-        e.backward(ctx.out_rel, grad_tags.detach().float().contiguous())
+        gt = grad_tags.detach().float().contiguous()
+        with_room(e, lambda: (e.zero_grad(), e.backward(ctx.out_rel, gt)))  # a retry starts from zero
         g = torch.zeros(ctx.n_in, dtype=torch.float32, device=grad_tags.device)
-        e.grad(ctx.in_rel, ctx.n_in, out=g)
+        with_room(e, lambda: e.grad(ctx.in_rel, ctx.n_in, out=g))
         return g, None, None, None, None, None
 
 
@@ -57,8 +70,8 @@ class FixpointQueryFunction(torch.autograd.Function):
         torch.cuda.current_stream().synchronize()
         engine.clear_facts()
         engine.add_facts(in_rel, cols, probs.detach().contiguous(), sample)
-        engine.run()
-        rows, tags = engine.lookup(out_rel, q_cols, q_sample)
+        with_room(engine, engine.run)
+        rows, tags = with_room(engine, lambda: engine.lookup(out_rel, q_cols, q_sample))
         ctx.engine, ctx.in_rel, ctx.out_rel, ctx.n_in, ctx.rows = engine, in_rel, out_rel, probs.shape[0], rows
         return tags
 
@@ -66,10 +79,10 @@ class FixpointQueryFunction(torch.autograd.Function):
     def backward(ctx, grad_tags):
         e = ctx.engine
         torch.cuda.current_stream().synchronize()
-        e.zero_grad()
-        e.backward_rows(ctx.out_rel, ctx.rows, grad_tags.detach().float().contiguous())
+        gt = grad_tags.detach().float().contiguous()
+        with_room(e, lambda: (e.zero_grad(), e.backward_rows(ctx.out_rel, ctx.rows, gt)))  # a retry starts from zero
         g = torch.zeros(ctx.n_in, dtype=torch.float32, device=grad_tags.device)
-        e.grad(ctx.in_rel, ctx.n_in, out=g)
+        with_room(e, lambda: e.grad(ctx.in_rel, ctx.n_in, out=g))
         return g, None, None, None, None, None, None, None
 
 

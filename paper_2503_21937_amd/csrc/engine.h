@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -35,6 +36,24 @@ struct DevBuf {
   T* as() const {
     return static_cast<T*>(p);
   }
+};
+
+// Host-side allocator over one device range: the caller's workspace
+// (dl_options.workspace) or the library's static per-device array.  First
+// fit over a free list ordered by address; a released range merges with its
+// free neighbours.  Ranges are 256-byte aligned.  It makes no device call:
+// releasing a range that queued kernels still read is safe because every
+// later user of the range is enqueued on the same stream (Sec. 4.1 buffer
+// reuse, with the arena standing in for the allocator).
+struct Arena {
+  char* base = nullptr;
+  size_t bytes = 0;
+  size_t used = 0, peak = 0;
+  std::map<size_t, size_t> free_list;  // offset -> length
+  void reset(void* p, size_t n);
+  void* alloc(size_t n);  // nullptr when no free range is large enough
+  void release(void* p, size_t n);
+  size_t largest_free() const;
 };
 
 struct Table {
@@ -111,6 +130,10 @@ struct Engine {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
+  // device memory: hipMalloc per buffer, or ranges of one arena (workspace)
+  bool use_arena = false;
+  Arena arena;
+  uint64_t device_allocs = 0;  // hipMalloc calls made by this engine
 
   // data-dependent layout, fixed at ingest
   bool ingested = false;
@@ -143,7 +166,8 @@ struct Engine {
   // round scratch
   DevBuf counts, offs, istart, alt_keys, alt_vals, vals, flags, pos, ukeys, utags,
       status, nflags, newpos, rflags, rpos, lf, lpos, nkeys, ntags, nids, tmpA_keys, tmpA_tags, tmpB_keys, tmpB_tags,
-      scratch, unpack, qbuf;
+      work, unpack, qbuf,  // work: scan and radix-sort partials
+      ev_keys, ev_tags, ev_l, ev_r;  // output rows of a plan with evaluation, before the condition compacts them
   uint64_t* host = nullptr;  // pinned readback words
   DevBuf dtotal;             // device words for totals
   DevBuf cs_state;           // single-pass count+scan: tile sums and flags (kept zeroed between launches)
@@ -158,6 +182,11 @@ struct Engine {
   // memory
   void grow(DevBuf& b, size_t bytes, bool keep = false, size_t used = 0);
   void release(DevBuf& b);
+  void set_workspace(void* p, size_t bytes);
+  // every device buffer the engine owns (index tables that alias a relation
+  // are not visited: they are re-pointed when the index is next used)
+  template <typename F>
+  void for_each_buf(F&& f);
   uint64_t read_total(int slot);
   void read_totals();  // all total slots into host[] (one sync)
   void sync();
@@ -183,6 +212,29 @@ struct Engine {
   KeyLayout layout(int ncols) const { return KeyLayout{ncols, cbits, sbits}; }
   int key_width(int ncols) const { return sbits + ncols * cbits; }
 };
+
+template <typename F>
+void Engine::for_each_buf(F&& f) {
+  for (auto& r : rel) {
+    for (auto& c : r.raw_cols) f(c);
+    for (DevBuf* b : {&r.raw_sample, &r.raw_tags, &r.raw_local}) f(*b);
+    for (Table* t : {&r.full, &r.full_alt, &r.recent, &r.view_full, &r.view_recent, &r.view_stable})
+      f(t->keys), f(t->tags), f(t->ids);
+    for (DevBuf* b : {&r.fact_entry, &r.grad, &r.fact_slot_d, &r.cand_keys, &r.cand_tags, &r.cand_l, &r.cand_r,
+                      &r.present, &r.touched, &r.dtag, &r.did, &r.log_keys, &r.log_l, &r.log_r, &r.seg_lcount,
+                      &r.goff, &r.dense_sbase, &r.lb_state})
+      f(*b);
+  }
+  for (auto& x : idx) {
+    if (!x.borrowed) f(x.t.keys), f(x.t.tags), f(x.t.ids);
+    f(x.off);
+  }
+  for (DevBuf* b : {&d_sn, &d_snp, &qtab, &grad_fact, &lin_owner, &lin_l, &lin_r, &tag_by_id, &adj, &counts, &offs,
+                    &istart, &alt_keys, &alt_vals, &vals, &flags, &pos, &ukeys, &utags, &status, &nflags, &newpos,
+                    &rflags, &rpos, &lf, &lpos, &nkeys, &ntags, &nids, &tmpA_keys, &tmpA_tags, &tmpB_keys,
+                    &tmpB_tags, &work, &unpack, &qbuf, &dtotal, &cs_state, &ev_keys, &ev_tags, &ev_l, &ev_r})
+    f(*b);
+}
 
 // Typed halves (K = packed key type), in engine_run.hip.
 template <typename K>

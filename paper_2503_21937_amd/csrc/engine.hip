@@ -50,46 +50,104 @@ struct ProfScope {
 }  // namespace
 
 Engine::~Engine() {
-  auto fr = [](DevBuf& b) {
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-  };
-  for (auto& r : rel) {
-    for (auto& c : r.raw_cols) fr(c);
-    fr(r.raw_sample), fr(r.raw_tags), fr(r.raw_local);
-    for (Table* t : {&r.full, &r.full_alt, &r.recent, &r.view_full, &r.view_recent, &r.view_stable})
-      fr(t->keys), fr(t->tags), fr(t->ids);
-    fr(r.fact_entry), fr(r.grad), fr(r.fact_slot_d);
-    fr(r.cand_keys), fr(r.cand_tags), fr(r.cand_l), fr(r.cand_r);
-    for (DevBuf* b : {&r.present, &r.touched, &r.dtag, &r.did, &r.log_keys, &r.log_l, &r.log_r, &r.seg_lcount, &r.goff,
-                      &r.dense_sbase, &r.lb_state})
-      fr(*b);
-  }
-  for (auto& x : idx) {
-    if (!x.borrowed) fr(x.t.keys), fr(x.t.tags), fr(x.t.ids);
-    fr(x.off);
-  }
-  for (DevBuf* b : {&d_sn, &d_snp, &qtab, &grad_fact, &lin_owner, &lin_l, &lin_r, &tag_by_id, &adj, &counts, &offs, &istart, &alt_keys, &alt_vals, &vals, &flags, &pos, &ukeys, &utags, &status,
-                    &nflags, &newpos, &rflags, &rpos, &lf, &lpos, &nkeys, &ntags, &nids, &tmpA_keys, &tmpA_tags,
-                    &tmpB_keys, &tmpB_tags, &scratch, &unpack, &qbuf, &dtotal, &cs_state})
-    fr(*b);
+  // arena ranges belong to the caller's workspace (or the static array)
+  if (!use_arena) for_each_buf([](DevBuf& b) {
+      if (b.p) (void)hipFree(b.p);
+      b.p = nullptr;
+    });
   if (host) (void)hipHostFree(host);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+// ------------------------------------------------------------- arena
+namespace {
+constexpr size_t ARENA_ALIGN = 256;
+size_t align_up(size_t n) { return (n + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN; }
+}  // namespace
+
+void Arena::reset(void* p, size_t n) {
+  // the first range starts at the first aligned address inside [p, p + n)
+  const uintptr_t a = (reinterpret_cast<uintptr_t>(p) + ARENA_ALIGN - 1) & ~(uintptr_t)(ARENA_ALIGN - 1);
+  const size_t skip = (size_t)(a - reinterpret_cast<uintptr_t>(p));
+  base = reinterpret_cast<char*>(a);
+  bytes = n > skip ? (n - skip) / ARENA_ALIGN * ARENA_ALIGN : 0;
+  used = peak = 0;
+  free_list.clear();
+  if (bytes) free_list[0] = bytes;
+}
+
+void* Arena::alloc(size_t n) {
+  n = align_up(std::max<size_t>(n, 1));
+  for (auto it = free_list.begin(); it != free_list.end(); ++it) {
+    if (it->second < n) continue;
+    const size_t off = it->first, len = it->second;
+    free_list.erase(it);
+    if (len > n) free_list[off + n] = len - n;
+    used += n;
+    peak = std::max(peak, used);
+    return base + off;
+  }
+  return nullptr;
+}
+
+void Arena::release(void* p, size_t n) {
+  if (!p) return;
+  n = align_up(std::max<size_t>(n, 1));
+  size_t off = (size_t)(static_cast<char*>(p) - base);
+  used -= n;
+  auto next = free_list.lower_bound(off);
+  if (next != free_list.end() && off + n == next->first) {  // merge with the range after
+    n += next->second;
+    next = free_list.erase(next);
+  }
+  if (next != free_list.begin()) {  // merge with the range before
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += n;
+      return;
+    }
+  }
+  free_list[off] = n;
+}
+
+size_t Arena::largest_free() const {
+  size_t m = 0;
+  for (const auto& f : free_list) m = std::max(m, f.second);
+  return m;
 }
 
 void Engine::grow(DevBuf& b, size_t bytes, bool keep, size_t used) {
   if (bytes <= b.cap) return;
   size_t cap = std::max<size_t>(bytes + bytes / 4, 256);
   void* p = nullptr;
-  hipError_t err = hipMalloc(&p, cap);
-  if (err != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error{DL_ERR_NOMEM, "device allocation of " + std::to_string(cap) + " bytes failed"};
+  if (use_arena) {
+    cap = align_up(cap);
+    p = arena.alloc(cap);
+    if (!p) {  // no room for the growth margin: the exact size
+      cap = align_up(bytes);
+      p = arena.alloc(cap);
+    }
+    if (!p)
+      throw Error{DL_ERR_NOMEM, "workspace exhausted: a buffer of " + std::to_string(bytes) + " bytes does not fit (" +
+                                    std::to_string(arena.used) + " of " + std::to_string(arena.bytes) +
+                                    " bytes in use, largest free range " + std::to_string(arena.largest_free()) +
+                                    "); give the engine a larger workspace (dl_set_workspace)"};
+  } else {
+    hipError_t err = hipMalloc(&p, cap);
+    if (err != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{DL_ERR_NOMEM, "device allocation of " + std::to_string(cap) + " bytes failed"};
+    }
+    ++device_allocs;
   }
   if (keep && used && b.p) DL_HIP(hipMemcpyAsync(p, b.p, used, hipMemcpyDeviceToDevice, stream));
   if (b.p) {
-    DL_HIP(hipStreamSynchronize(stream));  // the old buffer may still be read by queued work
-    DL_HIP(hipFree(b.p));
+    if (use_arena) {
+      arena.release(b.p, b.cap);  // later users of the range are ordered after the copy on the stream
+    } else {
+      DL_HIP(hipStreamSynchronize(stream));  // the old buffer may still be read by queued work
+      DL_HIP(hipFree(b.p));
+    }
     device_bytes -= b.cap;
   }
   b.p = p;
@@ -99,12 +157,74 @@ void Engine::grow(DevBuf& b, size_t bytes, bool keep, size_t used) {
 
 void Engine::release(DevBuf& b) {
   if (b.p) {
-    DL_HIP(hipStreamSynchronize(stream));
-    DL_HIP(hipFree(b.p));
+    if (use_arena) {
+      arena.release(b.p, b.cap);
+    } else {
+      DL_HIP(hipStreamSynchronize(stream));
+      DL_HIP(hipFree(b.p));
+    }
     device_bytes -= b.cap;
   }
   b.p = nullptr;
   b.cap = 0;
+}
+
+// Move every live buffer into a new home: the range [p, p + n) (p != NULL)
+// or separate hipMalloc allocations (p == NULL).  On failure nothing moves.
+void Engine::set_workspace(void* p, size_t n) {
+  if (p && n < ARENA_ALIGN) throw Error{DL_ERR_ARG, "workspace below 256 bytes"};
+  sync();
+  Arena na;
+  if (p) na.reset(p, n);
+  struct Move {
+    DevBuf* b;
+    void* to;
+  };
+  std::vector<Move> moves;
+  auto undo = [&] {
+    if (!p)
+      for (auto& m : moves) (void)hipFree(m.to);
+  };
+  try {
+    for_each_buf([&](DevBuf& b) {
+      if (!b.p) return;
+      void* q = nullptr;
+      if (p) {
+        q = na.alloc(b.cap);
+        if (!q)
+          throw Error{DL_ERR_NOMEM, "the new workspace (" + std::to_string(n) + " bytes) cannot hold the engine's " +
+                                        std::to_string(device_bytes) + " bytes of live buffers"};
+      } else {
+        if (hipMalloc(&q, b.cap) != hipSuccess) {
+          (void)hipGetLastError();
+          throw Error{DL_ERR_NOMEM, "device allocation of " + std::to_string(b.cap) + " bytes failed"};
+        }
+        ++device_allocs;
+      }
+      moves.push_back(Move{&b, q});
+    });
+  } catch (...) {
+    undo();
+    throw;
+  }
+  for (auto& m : moves) DL_HIP(hipMemcpyAsync(m.to, m.b->p, m.b->cap, hipMemcpyDeviceToDevice, stream));
+  sync();
+  for (auto& m : moves) {
+    if (!use_arena) DL_HIP(hipFree(m.b->p));
+    m.b->p = m.to;
+    if (p) m.b->cap = align_up(m.b->cap);
+  }
+  for (auto& x : idx)
+    if (x.borrowed) {  // aliases of moved relation buffers: re-pointed at the next use
+      x.t = Table{};
+      x.built = false;
+    }
+  use_arena = p != nullptr;
+  arena = na;
+  if (!use_arena) arena = Arena{};
+  device_bytes = 0;
+  for_each_buf([&](DevBuf& b) { device_bytes += b.cap; });
+  stats.device_bytes = device_bytes;
 }
 
 void Engine::sync() { DL_HIP(hipStreamSynchronize(stream)); }
@@ -159,6 +279,11 @@ void Engine::init(const char* program_text, const dl_options* o) {
     DL_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     own_stream = true;
   }
+  if (o->workspace) {
+    if (o->workspace_bytes < ARENA_ALIGN) throw Error{DL_ERR_ARG, "workspace below 256 bytes"};
+    use_arena = true;
+    arena.reset(o->workspace, o->workspace_bytes);
+  }
   DL_HIP(hipHostMalloc((void**)&host, 64 * sizeof(uint64_t), hipHostMallocDefault));
   grow(dtotal, 64 * sizeof(uint64_t));
   grow(cs_state, count_scan_state_words() * sizeof(uint64_t));
@@ -166,6 +291,8 @@ void Engine::init(const char* program_text, const dl_options* o) {
   if (o->lineage < 0 || o->lineage > 2) throw Error{DL_ERR_ARG, "lineage must be 0, 1 or 2"};
   if (o->lineage == 0 && o->lineage_budget) {
     lin_budget = o->lineage_budget;
+  } else if (o->lineage == 0 && use_arena) {
+    lin_budget = arena.bytes / 4;
   } else if (o->lineage == 0) {
     size_t free_b = 0, total_b = 0;
     DL_HIP(hipMemGetInfo(&free_b, &total_b));
@@ -257,6 +384,7 @@ static int bits_for(uint32_t maxv) {
 
 void Engine::run() {
   auto t0 = std::chrono::steady_clock::now();
+  ran = false;  // a run that fails part way leaves no result to read
   ProfScope prof(*this);
   if (!ingested) {
     // id domain and sample domain from the facts
@@ -269,7 +397,7 @@ void Engine::run() {
     DL_HIP(hipMemcpyAsync(host, dmax, 8, hipMemcpyDeviceToHost, stream));
     sync();
     uint32_t maxid = (uint32_t)host[0], maxs = (uint32_t)(host[0] >> 32);
-    max_id = maxid;
+    max_id = std::max(maxid, prog.max_const);  // program constants belong to the id domain
     max_sample = batched ? maxs : 0;
     sample_ids.clear();
     if (batched) {  // ids in use per sample: the dense domains size every sample by its own ids
@@ -288,7 +416,7 @@ void Engine::run() {
       sync();
       std::vector<uint32_t> np(ns);
       for (size_t s = 0; s < ns; ++s) {
-        sample_ids[s] += 1;
+        sample_ids[s] = std::max(sample_ids[s] + 1, prog.max_const + 1);
         np[s] = (sample_ids[s] + 31) / 32 * 32;
       }
       DL_HIP(hipMemcpyAsync(d_sn.p, sample_ids.data(), ns * 4, hipMemcpyHostToDevice, stream));
@@ -619,6 +747,10 @@ dl_status dl_run_fixpoint(dl_engine* h) {
   return guard(h, [&] { h->e.run(); });
 }
 
+dl_status dl_set_workspace(dl_engine* h, void* p, size_t bytes) {
+  return guard(h, [&] { h->e.set_workspace(p, bytes); });
+}
+
 dl_status dl_relation_size(dl_engine* h, const char* relation, size_t* n) {
   return guard(h, [&] {
     if (!n) throw Error{DL_ERR_ARG, "n is NULL"};
@@ -659,6 +791,9 @@ dl_status dl_zero_grad(dl_engine* h) {
 dl_status dl_get_stats(const dl_engine* h, dl_stats* out) {
   if (!h || !out) return DL_ERR_ARG;
   *out = h->e.stats;
+  out->device_allocs = h->e.device_allocs;
+  out->workspace_peak = h->e.use_arena ? h->e.arena.peak : 0;
+  out->device_bytes = h->e.device_bytes;
   return DL_OK;
 }
 

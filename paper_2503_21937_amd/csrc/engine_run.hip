@@ -29,7 +29,7 @@ constexpr int BATCH_ROUNDS = 4;  // round bodies per host synchronisation (one g
 
 uint64_t* total_slot(Engine& e, int s) { return e.dtotal.as<uint64_t>() + s; }
 
-void ensure_scratch(Engine& e, size_t words) { e.grow(e.scratch, (words + 16) * sizeof(uint64_t)); }
+void ensure_scratch(Engine& e, size_t words) { e.grow(e.work, (words + 16) * sizeof(uint64_t)); }
 
 template <typename K>
 void sort_pairs(Engine& e, K** kp, uint32_t** vp, size_t n, int bits) {
@@ -41,12 +41,12 @@ void sort_pairs(Engine& e, K** kp, uint32_t** vp, size_t n, int bits) {
     e.grow(e.alt_vals, n * 4);
     va = e.alt_vals.as<uint32_t>();
   }
-  radix_sort<K>(kp, vp, &ka, &va, n, bits, e.scratch.as<uint64_t>(), e.stream);
+  radix_sort<K>(kp, vp, &ka, &va, n, bits, e.work.as<uint64_t>(), e.stream);
 }
 
 void scan(Engine& e, const uint32_t* in, uint32_t* out, size_t n, int slot, bool sentinel, uint64_t* acc = nullptr) {
   ensure_scratch(e, scan_scratch_words(n));
-  scan_u32(in, out, n, total_slot(e, slot), sentinel, e.scratch.as<uint64_t>(), e.stream, acc);
+  scan_u32(in, out, n, total_slot(e, slot), sentinel, e.work.as<uint64_t>(), e.stream, acc);
 }
 
 // If a sort left its result in the engine's alternate buffer, move the
@@ -60,7 +60,40 @@ void check_overflow(Engine& e) {
   const uint64_t f = e.host[S_OVF];
   if (f == 1) throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
   if (f == 3) throw Error{DL_ERR_HIP, "single-pass scan: a look-back wait did not end"};
+  if (f == 4)
+    throw Error{DL_ERR_CAPACITY, "a computed head value lies outside the ids in use (the largest id of the facts "
+                                 "and of the program's constants)"};
   if (f) throw Error{DL_ERR_HIP, "row-window join: a derivation fell outside its window"};
+}
+
+// The plan's evaluation code (condition, computed head columns) in the
+// kernels' form; limits: EVAL_MAX instructions, EVAL_STACK operands deep.
+void set_eval(Engine& e, const Plan& pl, JoinArgs& a) {
+  EvalCode& c = a.ev;
+  c = EvalCode{};
+  if (!pl.eval) return;
+  auto put = [&](const std::vector<Ins>& code) {
+    int depth = 0;
+    for (const Ins& ins : code) {
+      if (c.n >= (uint32_t)EVAL_MAX)
+        throw Error{DL_ERR_UNSUPPORTED, "the expressions of a rule exceed " + std::to_string(EVAL_MAX) + " instructions"};
+      c.op[c.n] = (uint8_t)ins.op;
+      c.arg[c.n] = ins.arg;
+      ++c.n;
+      depth += (ins.op == EV_SRC || ins.op == EV_CONST) ? 1 : -1;
+      if (depth > EVAL_STACK)
+        throw Error{DL_ERR_UNSUPPORTED, "an expression needs more than " + std::to_string(EVAL_STACK) + " stack slots"};
+    }
+  };
+  put(pl.filter);
+  c.fend = c.n;
+  for (size_t col = 0; col < pl.code.size() && col < 4; ++col) {
+    c.cbeg[col] = c.n;
+    put(pl.code[col]);
+    c.cend[col] = c.n;
+  }
+  c.dn = e.max_id + 1;
+  c.sn = e.batched ? e.d_sn.as<uint32_t>() : nullptr;
 }
 
 // Whether a round's L discovery derivations can be added to the recorded
@@ -133,7 +166,8 @@ void setup_dense(Engine& e) {
   for (size_t r = 0; r < e.rel.size(); ++r) {
     RelState& R = e.rel[r];
     R.dense = false;
-    if (!e.prog.rels[r].derived) continue;
+    // nullary relations (at most one tuple per sample) always take the sort path
+    if (!e.prog.rels[r].derived || e.prog.rels[r].arity == 0) continue;
     const uint64_t dom = dense_domain(e, e.prog.rels[r].arity);
     const size_t keys = (size_t)std::min<uint64_t>(dom, (uint64_t)1 << 40);
     const size_t bytes = 2 * bitmap_words(keys) * 4 + (e.tag_kind == TAG_F32 ? keys * 4 : 0) + (e.lineage ? keys * 4 : 0);
@@ -271,7 +305,7 @@ void ensure_index(Engine& e, int i) {
 // derivations per window (see `from` below).
 template <typename K>
 bool row_windows(Engine& e, const Plan& pl, RowWindows* rw) {
-  if (pl.delta || pl.steps.size() != 1 || pl.steps[0].out_src.empty() || pl.steps[0].out_src[0] != 0) return false;
+  if (pl.eval || pl.delta || pl.steps.size() != 1 || pl.steps[0].out_src.empty() || pl.steps[0].out_src[0] != 0) return false;
   const int har = e.prog.rels[pl.head_rel].arity;
   const int pbits = e.sbits + e.cbits;
   if (har < 2 || pbits > 30 || !e.rel[pl.head_rel].dense) return false;
@@ -336,6 +370,9 @@ void run_plan(Engine& e, const Plan& pl) {
   a.k = e.k;
   a.q = e.qtab.as<float>();
   a.items = e.cfg.items;
+  a.err = total_slot(e, S_OVF);
+  set_eval(e, pl, a);
+  const EvalCode ev_out = a.ev;  // applies at the plan's output only
 
   auto head_room = [&](size_t add) {
     const size_t used = H.ncand;
@@ -351,6 +388,42 @@ void run_plan(Engine& e, const Plan& pl) {
     *ot = e.tag_bytes ? (void*)(H.cand_tags.as<uint8_t>() + H.ncand * e.tag_bytes) : nullptr;
     *ol = e.record ? H.cand_l.as<uint32_t>() + H.ncand : nullptr;
     *orr = e.record ? H.cand_r.as<uint32_t>() + H.ncand : nullptr;
+  };
+  // Sort path with evaluation: the output rows of n slots go to staging
+  // buffers with a keep flag each; the survivors are appended to the head's
+  // candidates in slot order (flag, scan, compaction).
+  auto stage = [&](size_t n, void** ok, void** ot, uint32_t** ol, uint32_t** orr) {
+    e.grow(e.ev_keys, n * sizeof(K) + 8);
+    if (e.tag_bytes) e.grow(e.ev_tags, n * e.tag_bytes + 8);
+    if (e.record) {
+      e.grow(e.ev_l, n * 4 + 4);
+      e.grow(e.ev_r, n * 4 + 4);
+    }
+    e.grow(e.flags, n * 4 + 4);
+    e.grow(e.pos, (n + 1) * 4);
+    a.keep = e.flags.as<uint32_t>();
+    *ok = e.ev_keys.p;
+    *ot = e.tag_bytes ? e.ev_tags.p : nullptr;
+    *ol = e.record ? e.ev_l.as<uint32_t>() : nullptr;
+    *orr = e.record ? e.ev_r.as<uint32_t>() : nullptr;
+  };
+  auto append_kept = [&](size_t n) {
+    scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), n, S_SCAN, true);
+    const size_t kept = e.read_total(S_SCAN);
+    if (!kept) return;
+    head_room(kept);
+    void *ok, *ot;
+    uint32_t *ol, *orr;
+    out_ptrs(&ok, &ot, &ol, &orr);
+    const uint32_t* f = e.flags.as<uint32_t>();
+    const uint32_t* pos = e.pos.as<uint32_t>();
+    compact(e.ev_keys.p, f, pos, n, sizeof(K), ok, e.stream);
+    if (e.tag_bytes) compact(e.ev_tags.p, f, pos, n, e.tag_bytes, ot, e.stream);
+    if (e.record) {
+      compact(e.ev_l.p, f, pos, n, 4, ol, e.stream);
+      compact(e.ev_r.p, f, pos, n, 4, orr, e.stream);
+    }
+    H.ncand += kept;
   };
 
   // Room for an emission over `add` slots: one wave segment per 256 slots;
@@ -384,9 +457,15 @@ void run_plan(Engine& e, const Plan& pl) {
       project_dense<K>(a, e.tag_kind, d, e.record, e.stream);
       return;
     }
-    head_room(cur.n);
     void *ok, *ot;
     uint32_t *ol, *orr;
+    if (a.ev.n) {
+      stage(cur.n, &ok, &ot, &ol, &orr);
+      project_rows<K>(a, e.tag_kind, ok, ot, ol, orr, e.stream);
+      append_kept(cur.n);
+      return;
+    }
+    head_room(cur.n);
     out_ptrs(&ok, &ot, &ol, &orr);
     project_rows<K>(a, e.tag_kind, ok, ot, ol, orr, e.stream);
     H.ncand += cur.n;
@@ -397,6 +476,8 @@ void run_plan(Engine& e, const Plan& pl) {
   DevBuf* tmp_tags[2] = {&e.tmpA_tags, &e.tmpB_tags};
   for (size_t si = 0; si < pl.steps.size(); ++si) {
     const Step& step = pl.steps[si];
+    a.ev = si + 1 == pl.steps.size() ? ev_out : EvalCode{};
+    a.keep = nullptr;
     ensure_index<K>(e, step.index);
     const IndexState& ix = e.idx[step.index];
     const IndexSpec& spec = e.prog.indexes[step.index];
@@ -459,7 +540,9 @@ void run_plan(Engine& e, const Plan& pl) {
     }
     void *ok, *ot;
     uint32_t *ol = nullptr, *orr = nullptr;
-    if (last) {
+    if (last && a.ev.n) {
+      stage(total, &ok, &ot, &ol, &orr);
+    } else if (last) {
       head_room(total);
       out_ptrs(&ok, &ot, &ol, &orr);
     } else {
@@ -471,7 +554,9 @@ void run_plan(Engine& e, const Plan& pl) {
       ot = e.tag_bytes ? tb.p : nullptr;
     }
     join_expand<K>(a, e.tag_kind, e.offs.as<uint32_t>(), total, ok, ot, ol, orr, e.stream);
-    if (last) {
+    if (last && a.ev.n) {
+      append_kept(total);
+    } else if (last) {
       H.ncand += total;
     } else {
       cur = Cur{ok, ot, nullptr, total, ocols, std::min(cur.minpos, step.body_pos)};
@@ -706,7 +791,7 @@ size_t absorb_sorted(Engine& e, int r) {
   ensure_scratch(e, merge_scratch_words(F, N));
   merge_sorted<K>(R.full.keys.as<K>(), R.full.tags.p, R.full.ids.as<uint32_t>(), F, (const K*)nk, nt, nid, N, tb,
                   R.full_alt.keys.as<K>(), R.full_alt.tags.p, e.lineage ? R.full_alt.ids.as<uint32_t>() : nullptr,
-                  e.scratch.as<uint64_t>(), st);
+                  e.work.as<uint64_t>(), st);
   std::swap(R.full, R.full_alt);
   R.full.n = F + N;
   ++R.version;
@@ -729,7 +814,7 @@ std::vector<const Plan*> batch_plans(Engine& e, const Stratum& st) {
   if (!e.rel[r].dense || e.cfg.orient == 1) return {};
   for (int p : st.delta_plans) {
     const Plan& pl = e.prog.plans[p];
-    if (pl.alt < 0) return {};
+    if (pl.alt < 0 || pl.eval) return {};
     const Plan& tw = e.prog.plans[pl.alt];
     if (tw.steps.size() != 1) return {};
     const IndexSpec& ix = e.prog.indexes[tw.steps[0].index];
@@ -799,7 +884,7 @@ void enqueue_round_body(Engine& e, int r, const std::vector<const Plan*>& plans,
                             total_slot(e, S_CAND), total_slot(e, S_OVF), st)) {
       join_count<K>(a, e.counts.as<uint32_t>(), st);
       scan_u32(e.counts.as<uint32_t>(), e.offs.as<uint32_t>(), a.n, total_slot(e, S_SCAN), true,
-               e.scratch.as<uint64_t>(), st, total_slot(e, S_CAND));
+               e.work.as<uint64_t>(), st, total_slot(e, S_CAND));
     }
     DenseArgs d = dense_args(e, R);
     RowWindows rw{};
@@ -1063,6 +1148,7 @@ void run_fixpoint(Engine& e) {
   for (size_t r = 0; r < e.rel.size(); ++r)
     if (e.prog.rels[r].derived) e.stats.derived += e.rel[r].full.n;
   e.read_totals();
+  check_overflow(e);
   e.stats.candidates += e.host[S_CAND];
   e.deferred_units = e.host[S_CAND];
   e.stats.lineage_mode = !e.lineage ? 0 : e.record ? 1 : 2;

@@ -341,10 +341,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_expand_dense(JoinArgs a, const u
       if (act[q]) {
         const K ikey = ik[irow[q]];
         uint32_t v[4];
-        for (int c = 0; c < a.olay.ncols; ++c) {
-          int s = a.osrc[c];
-          v[c] = s >= 0 ? key_col(dkey[q], s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
-        }
+        act[q] = out_cols<K>(a, dkey[q], ikey, v);  // with evaluation: the condition and computed columns
         okey[q] = key_make<K>(key_sample(dkey[q], a.dlay), v, a.olay);
         if constexpr (TK == TAG_F32) {
           const float x = dt[row[q]], y = it[irow[q]];
@@ -880,7 +877,7 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   // row windows: one launch of the row-window kernel, which reads the total
   // and falls back to scattered tiles below the threshold when the total is
   // only known on the device (with lineage the total is known on the host)
-  const bool rows = rw && rw->wkeys <= (uint32_t)RW_KEYS && (!lineage || !dtotal) &&
+  const bool rows = rw && !a.ev.n && rw->wkeys <= (uint32_t)RW_KEYS && (!lineage || !dtotal) &&
                     (dtotal || total >= rw->from);
   if (rows && lineage) fill_u32(d.seg_lcount + d.seg_base, dense_segments(total, items), 0u, st);
   const uint64_t skip_at = ~0ull;
@@ -896,7 +893,8 @@ void join_expand_dense(const JoinArgs& a, int tk, const uint32_t* offs, size_t t
   }
   // the specialised variants (see k_join_expand_rows, k_join_expand_dense)
   int fm = -1;
-  if (sizeof(K) == 4 && d.nsamp <= 1 && !lineage && a.olay.ncols == 2 && a.osrc[0] >= 0 && a.osrc[1] < 0) {
+  if (sizeof(K) == 4 && d.nsamp <= 1 && !lineage && !a.ev.n && a.olay.ncols == 2 && a.osrc[0] >= 0 &&
+      a.osrc[1] < 0) {
     if (tk == TAG_NONE && d.mode == DENSE_BOOL) fm = DENSE_BOOL;
     else if (tk == TAG_F32 && d.mode == DENSE_ADD && (a.sr == SR_ADDMULT || a.sr == SR_DIFF_ADDMULT)) fm = DENSE_ADD;
     else if (tk == TAG_F32 && d.mode == DENSE_MAX && a.sr == SR_MAXMIN) fm = DENSE_MAX;
@@ -972,14 +970,14 @@ __global__ __launch_bounds__(BLOCK) void k_project_dense(JoinArgs a, DenseArgs d
     const size_t i0 = (size_t)blockIdx.x * PX_TILE + (size_t)it_ * BLOCK;
     if (i0 >= a.n) break;  // uniform across the block
     const size_t i = i0 + threadIdx.x;
-    const bool act = i < a.n;
     K okey = 0;
     float t = 0.0f;
     uint32_t l = 0;
+    bool act = i < a.n;
     if (act) {
       const K dkey = dk[i];
       uint32_t v[4];
-      for (int c = 0; c < a.olay.ncols; ++c) v[c] = key_col(dkey, a.osrc[c], a.dlay);
+      act = out_cols<K>(a, dkey, dkey, v);  // sources are driver columns only
       okey = key_make<K>(key_sample(dkey, a.dlay), v, a.olay);
       if constexpr (TK == TAG_F32) t = ((const float*)a.dtags)[i];
       if (lineage) l = a.dids[i];

@@ -268,10 +268,8 @@ __global__ __launch_bounds__(BLOCK) void k_join_expand(JoinArgs a, const uint32_
     const uint32_t irow = a.off[p] + ((uint32_t)j - base);
     const K ikey = ik[irow];
     uint32_t v[4];
-    for (int c = 0; c < a.olay.ncols; ++c) {
-      int s = a.osrc[c];
-      v[c] = s >= 0 ? key_col(dkey, s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
-    }
+    const bool ok = out_cols<K>(a, dkey, ikey, v);
+    if (a.keep) a.keep[j] = ok ? 1u : 0u;
     const uint32_t sample = key_sample(dkey, a.dlay);
     okeys[j] = key_make<K>(sample, v, a.olay);
     if constexpr (TK != TAG_NONE) {
@@ -321,7 +319,8 @@ __global__ void k_project(JoinArgs a, K* __restrict__ okeys, typename TagOf<TK>:
   GRID_STRIDE(i, a.n) {
     K dkey = dk[i];
     uint32_t v[4];
-    for (int c = 0; c < a.olay.ncols; ++c) v[c] = key_col(dkey, a.osrc[c], a.dlay);
+    const bool ok = out_cols<K>(a, dkey, dkey, v);  // sources are driver columns only
+    if (a.keep) a.keep[i] = ok ? 1u : 0u;
     okeys[i] = key_make<K>(key_sample(dkey, a.dlay), v, a.olay);
     if constexpr (TK != TAG_NONE) otags[i] = ((const T*)a.dtags)[i];
     if (ol) {

@@ -67,6 +67,26 @@ void csr_build_dn(const K* keys, const uint64_t* dn, int total_bits, int prefix_
 // Tag payload kinds of the relational kernels.
 enum TagKind : int { TAG_NONE = 0, TAG_F32 = 1, TAG_TOPK = 2 };
 
+// Expression evaluation at a plan's output (Sec. 5: a bytecode program for a
+// small stack machine run by each thread on one output row; Sec. 3.3
+// eval<alpha>).  ops: the EvalOp codes of program.h; an EV_SRC operand is a
+// column of the driver row (>= 0) or of the index row (-1 - c); EV_CONST
+// carries the value.  [0, fend) is the condition (none when fend == 0);
+// computed head column c is [cbeg[c], cend[c]) (a plain column when empty).
+// A computed value must be below the ids in use (`dn`, or sn[sample] in
+// batched engines): it becomes a column of a packed key and a dense index.
+constexpr int EVAL_MAX = 48;
+constexpr int EVAL_STACK = 8;
+struct EvalCode {
+  const uint32_t* sn;  // batched: ids in use per sample, else NULL
+  uint32_t n;          // instructions (0: nothing to evaluate)
+  uint32_t fend;
+  uint32_t cbeg[4], cend[4];
+  uint32_t dn;
+  uint8_t op[EVAL_MAX];
+  int32_t arg[EVAL_MAX];
+};
+
 struct JoinArgs {
   // driver table
   const void* dkeys;
@@ -92,6 +112,10 @@ struct JoinArgs {
   bool index_first;  // x operand order: index tag first (body order)
   int items;         // expand tile: join outputs per thread (1, 2, 4 or 8)
   uint32_t* istart;  // per driver row: first matching index row (join_count writes it when not NULL)
+  // evaluation at the output (last join step or projection)
+  EvalCode ev;
+  uint32_t* keep;    // sort path with evaluation: per output row, 1 if it survives (else NULL)
+  uint64_t* err;     // evaluation errors: a computed value outside the ids in use sets 4
 };
 
 // Dense-domain deduplication state of one derived relation (key < 2^w):

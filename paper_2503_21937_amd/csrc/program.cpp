@@ -44,6 +44,7 @@ class Reader {
   std::string s_;
   size_t pos_ = 0;
   int mentions_ = 0;
+  std::map<uint32_t, int> const_vars_;  // constants of the rule being read -> their variable
 
   [[noreturn]] void parse_error(const std::string& m) {
     throw Failure{2, "parse error at offset " + std::to_string(pos_) + ": " + m};
@@ -86,6 +87,106 @@ class Reader {
     if (b == pos_) parse_error("expected an integer");
     return (int)v;
   }
+  uint32_t u32() {
+    skip();
+    size_t b = pos_;
+    uint64_t v = 0;
+    while (pos_ < s_.size() && std::isdigit((unsigned char)s_[pos_])) {
+      v = v * 10 + (uint64_t)(s_[pos_++] - '0');
+      if (v > 0xffffffffull) parse_error("constant above 2^32 - 1");
+    }
+    if (b == pos_) parse_error("expected a constant");
+    return (uint32_t)v;
+  }
+  bool digit() {
+    skip();
+    return pos_ < s_.size() && std::isdigit((unsigned char)s_[pos_]);
+  }
+  static int var_id(std::map<std::string, int>& vars, const std::string& v) {
+    auto it = vars.find(v);
+    if (it != vars.end()) return it->second;
+    const int id = (int)vars.size();
+    vars[v] = id;
+    return id;
+  }
+  // A variable no name can clash with (names start with a letter or '_').
+  static int fresh(std::map<std::string, int>& vars) { return var_id(vars, "#" + std::to_string(vars.size())); }
+  void constant(Program& p, std::vector<Ins>& code, uint32_t v) {
+    code.push_back({EV_CONST, (int32_t)v});
+    p.max_const = std::max(p.max_const, v);
+  }
+  // Postfix code of an expression: sum := product {(+|-) product},
+  // product := operand {(*|/|%) operand}, operand := constant | variable | ( sum ).
+  void operand(Program& p, std::map<std::string, int>& vars, std::vector<Ins>& code) {
+    if (at('(')) {
+      eat("(");
+      sum(p, vars, code);
+      eat(")");
+    } else if (digit()) {
+      constant(p, code, u32());
+    } else {
+      code.push_back({EV_VAR, var_id(vars, name())});
+    }
+  }
+  void product(Program& p, std::map<std::string, int>& vars, std::vector<Ins>& code) {
+    operand(p, vars, code);
+    for (;;) {
+      EvalOp op;
+      if (at('*')) op = EV_MUL;
+      else if (at('/')) op = EV_DIV;
+      else if (at('%')) op = EV_MOD;
+      else return;
+      ++pos_;
+      operand(p, vars, code);
+      code.push_back({op, 0});
+    }
+  }
+  void sum(Program& p, std::map<std::string, int>& vars, std::vector<Ins>& code) {
+    product(p, vars, code);
+    for (;;) {
+      EvalOp op;
+      if (at('+')) op = EV_ADD;
+      else if (at('-')) op = EV_SUB;
+      else return;
+      ++pos_;
+      product(p, vars, code);
+      code.push_back({op, 0});
+    }
+  }
+  // lhs op rhs, appended to the rule's filter (conjunction)
+  void comparison(Program& p, std::map<std::string, int>& vars, std::vector<Ins>& filter) {
+    std::vector<Ins> code;
+    sum(p, vars, code);
+    skip();
+    static const struct {
+      const char* t;
+      EvalOp op;
+    } ops[] = {{"==", EV_EQ}, {"!=", EV_NE}, {"<=", EV_LE}, {">=", EV_GE}, {"<", EV_LT}, {">", EV_GT}, {"=", EV_EQ}};
+    EvalOp op = EV_AND;
+    for (auto& o : ops)
+      if (s_.compare(pos_, std::strlen(o.t), o.t) == 0) {
+        pos_ += std::strlen(o.t);
+        op = o.op;
+        break;
+      }
+    if (op == EV_AND) parse_error("expected a comparison operator");
+    sum(p, vars, code);
+    code.push_back({op, 0});
+    const bool first = filter.empty();
+    filter.insert(filter.end(), code.begin(), code.end());
+    if (!first) filter.push_back({EV_AND, 0});
+  }
+  bool next_is_atom() {
+    skip();
+    const size_t save = pos_;
+    bool atom = false;
+    if (pos_ < s_.size() && (std::isalpha((unsigned char)s_[pos_]) || s_[pos_] == '_')) {
+      (void)name();
+      atom = at('(');
+    }
+    pos_ = save;
+    return atom;
+  }
   int relation(Program& p, const std::string& n, int arity) {
     int r = p.find(n);
     if (r < 0) {
@@ -104,29 +205,72 @@ class Reader {
     std::string n = name();
     eat("/");
     int arity = integer();
-    if (arity < 1 || arity > 4) throw Failure{3, "arity of " + n + " must be 1..4"};
+    if (arity < 0 || arity > 4) throw Failure{3, "arity of " + n + " must be 0..4"};
     int r = relation(p, n, arity);
     if (kw == "input") p.rels[r].input = true;
     else if (kw != "output") parse_error("unknown directive ." + kw);
   }
-  Atom atom(Program& p, std::map<std::string, int>& vars) {
+  // A body atom.  A constant, or a variable already used in the same atom,
+  // becomes a fresh variable with an equality condition (a selection).
+  Atom atom(Program& p, std::map<std::string, int>& vars, std::vector<Ins>& filter) {
     std::string n = name();
     eat("(");
     Atom a;
-    for (;;) {
-      skip();
-      if (pos_ < s_.size() && std::isdigit((unsigned char)s_[pos_]))
-        throw Failure{3, "constants in atoms are not supported"};
-      std::string v = name();
-      auto it = vars.find(v);
-      int id = it == vars.end() ? (int)vars.size() : it->second;
-      if (it == vars.end()) vars[v] = id;
-      a.vars.push_back(id);
-      if (at(',')) {
-        eat(",");
-        continue;
+    while (!at(')')) {
+      int id;
+      if (digit()) {
+        // one variable per distinct constant of the rule: atoms that share a
+        // constant join on it
+        const uint32_t k = u32();
+        auto it = const_vars_.find(k);
+        if (it != const_vars_.end() && !std::count(a.vars.begin(), a.vars.end(), it->second)) {
+          id = it->second;
+        } else {
+          id = fresh(vars);
+          if (it == const_vars_.end()) const_vars_[k] = id;
+          std::vector<Ins> eq{{EV_VAR, id}};
+          constant(p, eq, k);
+          eq.push_back({EV_EQ, 0});
+          const bool first = filter.empty();
+          filter.insert(filter.end(), eq.begin(), eq.end());
+          if (!first) filter.push_back({EV_AND, 0});
+        }
+      } else {
+        id = var_id(vars, name());
+        if (std::count(a.vars.begin(), a.vars.end(), id)) {
+          const int again = fresh(vars);
+          const bool first = filter.empty();
+          filter.insert(filter.end(), {{EV_VAR, again}, {EV_VAR, id}, {EV_EQ, 0}});
+          if (!first) filter.push_back({EV_AND, 0});
+          id = again;
+        }
       }
-      break;
+      a.vars.push_back(id);
+      if (!at(',')) break;
+      eat(",");
+    }
+    eat(")");
+    if (a.vars.size() > 4) throw Failure{3, "arity above 4"};
+    a.rel = relation(p, n, (int)a.vars.size());
+    return a;
+  }
+  // The head: every argument is an expression over the body's variables.
+  Atom head(Program& p, std::map<std::string, int>& vars, std::vector<std::vector<Ins>>& code) {
+    std::string n = name();
+    eat("(");
+    Atom a;
+    while (!at(')')) {
+      std::vector<Ins> c;
+      sum(p, vars, c);
+      if (c.size() == 1 && c[0].op == EV_VAR) {
+        a.vars.push_back(c[0].arg);
+        c.clear();
+      } else {
+        a.vars.push_back(-1);
+      }
+      code.push_back(c);
+      if (!at(',')) break;
+      eat(",");
     }
     eat(")");
     if (a.vars.size() > 4) throw Failure{3, "arity above 4"};
@@ -135,11 +279,13 @@ class Reader {
   }
   void rule(Program& p) {
     std::map<std::string, int> vars;
+    const_vars_.clear();
     Rule r;
-    r.head = atom(p, vars);
+    r.head = head(p, vars, r.head_code);
     eat(":-");
     for (;;) {
-      r.body.push_back(atom(p, vars));
+      if (next_is_atom()) r.body.push_back(atom(p, vars, r.filter));
+      else comparison(p, vars, r.filter);
       if (at(',')) {
         eat(",");
         continue;
@@ -148,6 +294,7 @@ class Reader {
     }
     eat(".");
     r.nvars = (int)vars.size();
+    if (r.body.empty()) throw Failure{3, "a rule needs a body atom"};
     if (r.body.size() > 3) throw Failure{3, "more than 3 body atoms"};
     for (auto& b : r.body) {
       std::vector<int> v = b.vars;
@@ -155,12 +302,18 @@ class Reader {
       if (std::adjacent_find(v.begin(), v.end()) != v.end())
         throw Failure{3, "repeated variable inside a body atom"};
     }
-    for (int hv : r.head.vars) {
-      bool found = false;
+    auto bound = [&](int v) {
       for (auto& b : r.body)
-        found = found || std::count(b.vars.begin(), b.vars.end(), hv) > 0;
-      if (!found) throw Failure{3, "head variable not bound by the body"};
-    }
+        if (std::count(b.vars.begin(), b.vars.end(), v)) return true;
+      return false;
+    };
+    for (int hv : r.head.vars)
+      if (hv >= 0 && !bound(hv)) throw Failure{3, "head variable not bound by the body"};
+    for (auto& c : r.head_code)
+      for (auto& ins : c)
+        if (ins.op == EV_VAR && !bound(ins.arg)) throw Failure{3, "head expression variable not bound by the body"};
+    for (auto& ins : r.filter)
+      if (ins.op == EV_VAR && !bound(ins.arg)) throw Failure{3, "condition variable not bound by the body"};
     p.rules.push_back(r);
   }
 };
@@ -235,8 +388,30 @@ Plan make_plan(Program& p, int rule_id, int driver, bool delta, int recent_atom 
   for (int j = 0; j < (int)r.body.size(); ++j)
     if (j != driver) remaining.push_back(j);
   auto has = [](const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); };
+  // variables the evaluation at the plan's output reads
+  std::vector<int> eval_vars;
+  for (auto& c : r.head_code)
+    for (auto& ins : c)
+      if (ins.op == EV_VAR) eval_vars.push_back(ins.arg);
+  for (auto& ins : r.filter)
+    if (ins.op == EV_VAR) eval_vars.push_back(ins.arg);
+  pl.eval = r.eval();
+  // EV_VAR -> EV_SRC through `src_of` (the variable's column in the plan's
+  // last table: >= 0 current table, < 0 index key position)
+  auto resolve = [&](const std::function<int(int)>& src_of) {
+    auto tr = [&](std::vector<Ins> code) {
+      for (auto& ins : code)
+        if (ins.op == EV_VAR) ins = Ins{EV_SRC, src_of(ins.arg)};
+      return code;
+    };
+    pl.filter = tr(r.filter);
+    pl.code.clear();
+    for (auto& c : r.head_code) pl.code.push_back(tr(c));
+  };
   if (remaining.empty()) {
-    for (int hv : r.head.vars) pl.project.push_back((int)(std::find(cur.begin(), cur.end(), hv) - cur.begin()));
+    auto col = [&](int v) { return (int)(std::find(cur.begin(), cur.end(), v) - cur.begin()); };
+    for (int hv : r.head.vars) pl.project.push_back(hv >= 0 ? col(hv) : 0);
+    if (pl.eval) resolve(col);
     return pl;
   }
   while (!remaining.empty()) {
@@ -268,26 +443,26 @@ Plan make_plan(Program& p, int rule_id, int driver, bool delta, int recent_atom 
     st.index = add_index(p, ix);
     // variables needed after this step
     std::vector<int> need = r.head.vars;
+    need.insert(need.end(), eval_vars.begin(), eval_vars.end());
     for (int j : remaining)
       for (int v : r.body[j].vars) need.push_back(v);
     std::vector<int> out;
     if (remaining.empty()) {
-      out = r.head.vars;
+      out = r.head.vars;  // -1: a computed column
     } else {
       for (int v : cur)
         if (has(need, v) && !has(out, v)) out.push_back(v);
       for (int v : a.vars)
         if (has(need, v) && !has(out, v)) out.push_back(v);
     }
-    for (int v : out) {
-      if (has(cur, v)) {
-        st.out_src.push_back((int)(std::find(cur.begin(), cur.end(), v) - cur.begin()));
-      } else {
-        int col = (int)(std::find(a.vars.begin(), a.vars.end(), v) - a.vars.begin());
-        int kpos = (int)(std::find(ix.perm.begin(), ix.perm.end(), col) - ix.perm.begin());
-        st.out_src.push_back(-1 - kpos);
-      }
-    }
+    auto src_of = [&](int v) {
+      if (has(cur, v)) return (int)(std::find(cur.begin(), cur.end(), v) - cur.begin());
+      int col = (int)(std::find(a.vars.begin(), a.vars.end(), v) - a.vars.begin());
+      int kpos = (int)(std::find(ix.perm.begin(), ix.perm.end(), col) - ix.perm.begin());
+      return -1 - kpos;
+    };
+    for (int v : out) st.out_src.push_back(v >= 0 ? src_of(v) : 0);
+    if (remaining.empty() && pl.eval) resolve(src_of);
     st.out_vars = out;
     pl.max_cols = std::max(pl.max_cols, (int)out.size());
     pl.steps.push_back(st);

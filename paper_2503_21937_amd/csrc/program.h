@@ -17,13 +17,37 @@ namespace dlfix {
 
 struct Atom {
   int rel;
-  std::vector<int> vars;  // variable per column
+  std::vector<int> vars;  // variable per column (head: -1 where the column is computed)
+};
+
+// Expression evaluation (Sec. 5, bytecode interpreter; Sec. 3.3 eval<alpha>
+// in the lowering of Project): a postfix program for a small stack machine
+// over u32 values.  Operands are the rule's variables (VAR, arg = variable
+// id; after planning: SRC, arg = column of the current table if >= 0, of the
+// index row if < 0 as -1 - key position) and constants.  + - * wrap modulo
+// 2^32, / and % are unsigned and void the derivation when the divisor is 0,
+// comparisons are unsigned and push 0 or 1.
+enum EvalOp : uint8_t {
+  EV_VAR = 0, EV_SRC, EV_CONST, EV_ADD, EV_SUB, EV_MUL, EV_DIV, EV_MOD,
+  EV_EQ, EV_NE, EV_LT, EV_LE, EV_GT, EV_GE, EV_AND
+};
+struct Ins {
+  EvalOp op;
+  int32_t arg = 0;  // variable / source (VAR, SRC) or constant (CONST, as u32)
 };
 
 struct Rule {
   Atom head;
+  std::vector<std::vector<Ins>> head_code;  // per head column: empty = the plain variable head.vars[c]
+  std::vector<Ins> filter;                  // empty = no condition; else pushes 1 when the derivation counts
   std::vector<Atom> body;
   int nvars = 0;
+  bool eval() const {
+    if (!filter.empty()) return true;
+    for (auto& c : head_code)
+      if (!c.empty()) return true;
+    return false;
+  }
 };
 
 struct Relation {
@@ -73,6 +97,12 @@ struct Plan {
   std::vector<Step> steps;
   std::vector<int> project;     // no steps: head column j <- driver column project[j]
   int max_cols;                 // widest table of the plan
+  // Evaluation at the plan's output (the last step, or the projection when
+  // there are no steps): `filter` and the computed head columns, with EV_SRC
+  // operands; head column c is computed when code[c] is non-empty.
+  bool eval = false;
+  std::vector<Ins> filter;
+  std::vector<std::vector<Ins>> code;
   // Delta plans of 2-atom rules whose other atom is static also get a
   // "static-driven" twin: the static relation drives and the recent tuples
   // are the indexed side (same derivations, output grouped by the static
@@ -94,6 +124,7 @@ struct Program {
   std::vector<Plan> plans;
   std::vector<IndexSpec> indexes;
   int max_cols = 0;             // widest packed table (columns, excluding the sample)
+  uint32_t max_const = 0;       // largest constant of the program (a lower bound of the id domain)
   int find(const std::string& name) const;
 };
 

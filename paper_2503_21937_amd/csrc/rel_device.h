@@ -3,6 +3,7 @@
 #pragma once
 #include "dl_device.h"
 #include "kernels.h"
+#include "program.h"  // EvalOp codes
 
 namespace dlfix {
 
@@ -30,6 +31,80 @@ __device__ __forceinline__ K key_make(uint32_t sample, const uint32_t* cols, con
   uint64_t k = l.sbits ? (uint64_t)sample << (l.ncols * l.cbits) : 0ull;
   for (int c = 0; c < l.ncols; ++c) k |= (uint64_t)cols[c] << ((l.ncols - 1 - c) * l.cbits);
   return (K)k;
+}
+
+// Runs instructions [b, e) of the evaluation code on one output row (driver
+// key dkey, index key ikey) with a fixed-size stack in thread-local memory;
+// returns false when a division by zero voids the row.  The instruction
+// stream is the same for every lane.
+template <typename K>
+__device__ bool eval_run(const EvalCode& c, uint32_t b, uint32_t e, K dkey, const KeyLayout& dl, K ikey,
+                         const KeyLayout& il, uint32_t* out) {
+  uint32_t st[EVAL_STACK];
+  int sp = 0;
+  for (uint32_t i = b; i < e; ++i) {
+    const int op = c.op[i];
+    const int32_t a = c.arg[i];
+    if (op == EV_SRC) {
+      st[sp++] = a >= 0 ? key_col(dkey, a, dl) : key_col(ikey, -1 - a, il);
+      continue;
+    }
+    if (op == EV_CONST) {
+      st[sp++] = (uint32_t)a;
+      continue;
+    }
+    const uint32_t y = st[--sp], x = st[--sp];
+    uint32_t r;
+    switch (op) {
+      case EV_ADD: r = x + y; break;
+      case EV_SUB: r = x - y; break;
+      case EV_MUL: r = x * y; break;
+      case EV_DIV:
+        if (!y) return false;
+        r = x / y;
+        break;
+      case EV_MOD:
+        if (!y) return false;
+        r = x % y;
+        break;
+      case EV_EQ: r = x == y; break;
+      case EV_NE: r = x != y; break;
+      case EV_LT: r = x < y; break;
+      case EV_LE: r = x <= y; break;
+      case EV_GT: r = x > y; break;
+      case EV_GE: r = x >= y; break;
+      default: r = (x != 0u) & (y != 0u); break;  // EV_AND
+    }
+    st[sp++] = r;
+  }
+  *out = st[0];
+  return true;
+}
+
+// The output row's columns v[0 .. olay.ncols) from the plain sources (osrc)
+// and, with evaluation, the computed ones; false when the row is filtered
+// out or a division by zero voids it.  A computed value outside the ids in
+// use drops the row and reports error 4.
+template <typename K>
+__device__ __forceinline__ bool out_cols(const JoinArgs& a, K dkey, K ikey, uint32_t* v) {
+  for (int c = 0; c < a.olay.ncols; ++c) {
+    const int s = a.osrc[c];
+    v[c] = s >= 0 ? key_col(dkey, s, a.dlay) : key_col(ikey, -1 - s, a.ilay);
+  }
+  if (!a.ev.n) return true;
+  uint32_t f = 1;
+  if (a.ev.fend && (!eval_run<K>(a.ev, 0, a.ev.fend, dkey, a.dlay, ikey, a.ilay, &f) || !f)) return false;
+  for (int c = 0; c < a.olay.ncols; ++c) {
+    if (a.ev.cbeg[c] == a.ev.cend[c]) continue;
+    uint32_t x;
+    if (!eval_run<K>(a.ev, a.ev.cbeg[c], a.ev.cend[c], dkey, a.dlay, ikey, a.ilay, &x)) return false;
+    if (x >= (a.ev.sn ? a.ev.sn[key_sample(dkey, a.dlay)] : a.ev.dn)) {
+      if (a.err) *a.err = 4;
+      return false;
+    }
+    v[c] = x;
+  }
+  return true;
 }
 
 template <typename K>

@@ -19,7 +19,7 @@ SEMIRINGS = {"bool": 0, "maxmin": 1, "minplus": 2, "addmult": 3,
              "diff_addmult": 4, "topk": 5, "diff_topk": 6}
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_PARSE", 3: "ERR_UNSUPPORTED", 4: "ERR_STATE",
           5: "ERR_NOMEM", 6: "ERR_CAPACITY", 7: "ERR_PROOF_OVERFLOW", 8: "ERR_HIP"}
-EXPORTS = ["dl_load_program", "dl_clear_facts", "dl_add_facts", "dl_run_fixpoint",
+EXPORTS = ["dl_load_program", "dl_clear_facts", "dl_add_facts", "dl_run_fixpoint", "dl_set_workspace",
            "dl_relation_size", "dl_read_relation", "dl_lookup", "dl_backward_rows", "dl_backward", "dl_read_grad",
            "dl_zero_grad", "dl_get_stats", "dl_autotune", "dl_profile", "dl_get_kernel_timing",
            "dl_last_error", "dl_free"]
@@ -36,7 +36,8 @@ class DLError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("semiring", C.c_int), ("k", C.c_int), ("batched", C.c_int),
                 ("stream", C.c_void_p), ("dedup", C.c_int), ("no_graphs", C.c_int),
-                ("lineage", C.c_int), ("lineage_budget", C.c_size_t)]
+                ("lineage", C.c_int), ("lineage_budget", C.c_size_t),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
 
 
 class RelationOut(C.Structure):
@@ -54,7 +55,8 @@ class Stats(C.Structure):
                 ("lineage", C.c_uint64), ("run_ms", C.c_double), ("device_bytes", C.c_uint64),
                 ("key_bits", C.c_uint32), ("id_bits", C.c_uint32), ("sample_bits", C.c_uint32),
                 ("dedup", C.c_int), ("orient", C.c_int), ("items", C.c_int), ("tuned_ms", C.c_double),
-                ("lineage_mode", C.c_int), ("rows", C.c_int)]
+                ("lineage_mode", C.c_int), ("rows", C.c_int),
+                ("device_allocs", C.c_uint64), ("workspace_peak", C.c_uint64)]
 
 
 _lib = None
@@ -79,6 +81,7 @@ def lib():
         L.dl_clear_facts.argtypes = [vp]
         L.dl_add_facts.argtypes = [vp, C.c_char_p, sz, vp, vp, vp, C.c_int]
         L.dl_run_fixpoint.argtypes = [vp]
+        L.dl_set_workspace.argtypes = [vp, vp, sz]
         L.dl_relation_size.argtypes = [vp, C.c_char_p, C.POINTER(sz)]
         L.dl_read_relation.argtypes = [vp, C.c_char_p, sz, C.POINTER(RelationOut), C.c_int,
                                        C.POINTER(sz)]
@@ -126,6 +129,18 @@ def _current_stream() -> int | None:
     return None
 
 
+def _workspace(ws):
+    """A device tensor for a workspace argument (None, byte count or tensor)."""
+    if ws is None:
+        return None
+    if isinstance(ws, int):
+        import torch
+        return torch.empty(ws, dtype=torch.uint8, device="cuda")
+    if not (_is_torch(ws) and ws.is_cuda and ws.is_contiguous()):
+        raise ValueError("workspace must be a byte count or a contiguous device tensor")
+    return ws
+
+
 class Engine:
     """One fixpoint engine: a program under one semiring (dlfix.h)."""
 
@@ -135,7 +150,10 @@ class Engine:
     def __init__(self, program: str, semiring: str = "bool", k: int = 3,
                  batched: bool = False, stream: int | None = None, use_torch_stream: bool = True,
                  dedup: str = "auto", graphs: bool = True, lineage: str = "auto",
-                 lineage_budget: int = 0):
+                 lineage_budget: int = 0, workspace=None):
+        """workspace: None (the library allocates), a byte count (a torch
+        uint8 tensor of that size is allocated here and kept), or a device
+        tensor whose storage the engine keeps all its buffers in."""
         self.arity = {}
         for line in program.splitlines():
             line = line.strip()
@@ -144,14 +162,17 @@ class Engine:
                 self.arity[name] = int(ar)
             elif ":-" in line:  # a rule head names a derived relation
                 name, args = line.split(":-")[0].split("(", 1)
-                self.arity.setdefault(name.strip(), args.count(",") + 1)
+                args = args.rsplit(")", 1)[0]
+                self.arity.setdefault(name.strip(), args.count(",") + 1 if args.strip() else 0)
         self.semiring = semiring
         self.k = k
         self.batched = batched
         if stream is None and use_torch_stream:
             stream = _current_stream()
+        self.workspace = _workspace(workspace)
+        wp, wn = (None, 0) if self.workspace is None else (self.workspace.data_ptr(), self.workspace.nbytes)
         opts = Options(SEMIRINGS[semiring], k, int(batched), stream, self.DEDUP[dedup], int(not graphs),
-                       self.LINEAGE[lineage], lineage_budget)
+                       self.LINEAGE[lineage], lineage_budget, wp, wn)
         h = C.c_void_p()
         rc = lib().dl_load_program(program.encode(), C.byref(opts), C.byref(h))
         if rc:
@@ -163,6 +184,7 @@ class Engine:
             if _lib is not None:  # at interpreter exit the module may be torn down first
                 _lib.dl_free(self.h)
             self.h = None
+        self.workspace = None  # only after the engine is gone
 
     def __del__(self):
         self.close()
@@ -186,6 +208,14 @@ class Engine:
         sp, sa, _ = _ptr(sample, np.uint32)
         keep += [ta, sa]
         self._check(lib().dl_add_facts(self.h, rel.encode(), n, sp, ptrs, tp, int(bool(dev))))
+
+    def set_workspace(self, workspace):
+        """Move the engine's buffers into a new workspace (bytes or tensor;
+        None: library allocations).  The previous one is released after."""
+        ws = _workspace(workspace)
+        wp, wn = (None, 0) if ws is None else (ws.data_ptr(), ws.nbytes)
+        self._check(lib().dl_set_workspace(self.h, wp, wn))
+        self.workspace = ws
 
     def clear_facts(self):
         self._check(lib().dl_clear_facts(self.h))

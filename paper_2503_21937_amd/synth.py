@@ -22,6 +22,24 @@ path(x, y) :- edge(x, y).
 path(x, z) :- edge(x, y), path(y, z).
 """
 
+# Same Generation (the paper's second discrete workload), with its selection
+SG_PROGRAM = """
+.input edge/2
+.output sg/2
+sg(x, y) :- edge(p, x), edge(p, y), x != y.
+sg(x, y) :- edge(a, x), sg(a, b), edge(b, y).
+"""
+
+# The motivating program: reachability between the endpoints of a grid
+PATHFINDER_PROGRAM = """
+.input edge/2
+.input is_endpoint/1
+.output endpoints_connected/0
+path(x, y) :- edge(x, y).
+path(x, z) :- path(x, y), edge(y, z).
+endpoints_connected() :- is_endpoint(x), is_endpoint(y), path(x, y), x != y.
+"""
+
 ANDERSEN_PROGRAM = """
 .input addr/2
 .input assign/2

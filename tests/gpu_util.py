@@ -54,3 +54,39 @@ def tune_key(e):
         e.autotune(1, path)
         line = open(path).read().splitlines()[-1]
         return json.loads(line)["key"]
+
+
+def tc_closure(oracle, n, src, dst, p, sr, threads=16):
+    """Transitive closure of a graph from the oracle's column solver (every
+    target column evolves on its own in the naive rounds): (present[x, z],
+    tag[x, z]) for all pairs.  Much faster than the generic evaluator."""
+    import concurrent.futures as cf
+    pres = np.zeros((n, n), bool)
+    tag = np.zeros((n, n), np.float64)
+
+    def col(z):
+        c = oracle.tc_column(n, src, dst, None if sr == "bool" else p, sr, z)
+        pres[:, z] = c["present"]
+        tag[:, z] = c["tag"]
+
+    with cf.ThreadPoolExecutor(threads) as ex:  # ctypes calls release the GIL
+        list(ex.map(col, range(n)))
+    return pres, tag
+
+
+def check_closure(read, closure, sr, what=""):
+    """A read `path` relation equals the closure: sets exact, max-min tags
+    bit-exact, other float tags within TAG_RTOL."""
+    pres, tag = closure
+    cols = read["cols"]
+    got = np.zeros(pres.shape, bool)
+    got[cols[:, 0], cols[:, 1]] = True
+    assert cols.shape[0] == int(pres.sum()), what
+    assert np.array_equal(got, pres), what
+    if sr == "bool":
+        return
+    want = tag[cols[:, 0], cols[:, 1]]
+    if sr == "maxmin":
+        assert np.array_equal(read["tags"].astype(np.float64), want), what
+    else:
+        assert_tags_close(read["tags"], want, what=what)

@@ -40,9 +40,12 @@ def test_library_exports_every_declared_symbol(dl):
 
 @pytest.mark.parametrize("text,status", [
     ("path(x, y) :- edge(x, y", 2),                               # parse error
-    ("path(x, z) :- edge(x, 3).", 3),                             # constant
-    ("path(x, z) :- edge(x, x).", 3),                             # repeated variable in an atom
+    ("path(x, z) :- edge(x, 3).", 3),                             # unbound head variable (beside a constant)
     ("path(x, w) :- edge(x, y).", 3),                             # unbound head variable
+    ("p(x) :- e(x, y), z > 1.", 3),                               # condition on an unbound variable
+    ("p(x, w + 1) :- e(x, y).", 3),                               # head expression on an unbound variable
+    ("p(x) :- x > 1.", 3),                                        # no body atom
+    ("p(x) :- e(x, y), x <> y.", 2),                              # unknown comparison
     ("p(a) :- q(a), r(b).", 3),                                   # disconnected body
     ("p(a) :- q(a, b), r(b, c), s(c, d), t(d, a).", 3),           # four atoms
     (".input edge/2\nedge(x, y) :- edge(y, x).", 3),              # head on an input
@@ -71,6 +74,21 @@ def test_frozen_semiring_accepts_nonlinear_recursion(dl):
     with pytest.raises(dl.DLError) as ex:
         dl.Engine(prog3, "diff_addmult", use_torch_stream=False)
     assert ex.value.status == 3
+
+
+def test_expressions_are_accepted(dl):
+    """Constants and repeated variables in atoms, comparisons, arithmetic head
+    terms and nullary heads get past parsing and planning (without a device
+    the load then fails on stream creation, DL_ERR_HIP)."""
+    for text in ("path(x, z) :- edge(x, 3), edge(3, z).",
+                 "loop(x) :- edge(x, x).",
+                 "sg(x, y) :- edge(p, x), edge(p, y), x != y.",
+                 "walk(x, z, d + 1) :- walk(x, y, d), edge(y, z), d < 4.",
+                 "q(x, (y * 3 + 1) % 7, y / 2) :- e(x, y), x <= y, x >= 1, y == 2 * x.",
+                 "any() :- e(x, y), x != y."):
+        with pytest.raises(dl.DLError) as ex:
+            dl.Engine(".input edge/2\n.input e/2\n" + text, "bool", use_torch_stream=False)
+        assert ex.value.status == 8, (text, ex.value)
 
 
 def test_bad_options(dl):
