@@ -176,6 +176,25 @@ typedef struct {
  * engine (free with dl_free). */
 dl_status dl_load_program(const char* program_text, const dl_options* opts, dl_engine** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * dl_load_program, but the engine keeps ALL its device buffers in the
+ * library's own static array on the current device, DL_STATIC_WORKSPACE_MIB
+ * MiB large, which every device the library runs on holds until the process
+ * ends.  Neither this call nor any later call on the engine calls hipMalloc,
+ * hipFree, hipHostMalloc or any other allocating routine, and the engine
+ * creates no stream (opts->stream NULL means the null stream).
+ * opts->workspace must be NULL (else DL_ERR_ARG).
+ * Limits: inputs whose buffers do not fit the array give DL_ERR_NOMEM with a
+ * message naming the static workspace; dl_set_workspace is refused
+ * (DL_ERR_STATE).  The array is shared by all such engines on a device and
+ * keeps the contents of the last one (the engine clears what must start at
+ * zero): each call of dl_load_program_static hands it to the new engine, and
+ * every later call on an earlier engine of that device returns DL_ERR_STATE.
+ * Calls on such engines that overlap in time on one device race. */
+#define DL_STATIC_WORKSPACE_MIB 128
+dl_status dl_load_program_static(const char* program_text, const dl_options* opts, dl_engine** out);
+
 /* Drop all facts and results, keep the program (and every device buffer, for
  * reuse by the next facts: Sec. 4.1, buffer reuse across runs). */
 dl_status dl_clear_facts(dl_engine* e);

@@ -134,6 +134,11 @@ struct Engine {
   bool use_arena = false;
   Arena arena;
   uint64_t device_allocs = 0;  // hipMalloc calls made by this engine
+  // engines of dl_load_program_static: the device whose static array is the
+  // arena (-1 otherwise) and the generation of that array they hold
+  int static_dev = -1;
+  uint64_t static_gen = 0;
+  uint64_t host_words[64] = {};
 
   // data-dependent layout, fixed at ingest
   bool ingested = false;

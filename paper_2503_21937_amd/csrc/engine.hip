@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "dl_device.h"
 #include "engine.h"
@@ -55,7 +56,7 @@ Engine::~Engine() {
       if (b.p) (void)hipFree(b.p);
       b.p = nullptr;
     });
-  if (host) (void)hipHostFree(host);
+  if (host && host != host_words) (void)hipHostFree(host);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -128,10 +129,13 @@ void Engine::grow(DevBuf& b, size_t bytes, bool keep, size_t used) {
       p = arena.alloc(cap);
     }
     if (!p)
-      throw Error{DL_ERR_NOMEM, "workspace exhausted: a buffer of " + std::to_string(bytes) + " bytes does not fit (" +
-                                    std::to_string(arena.used) + " of " + std::to_string(arena.bytes) +
-                                    " bytes in use, largest free range " + std::to_string(arena.largest_free()) +
-                                    "); give the engine a larger workspace (dl_set_workspace)"};
+      throw Error{DL_ERR_NOMEM,
+                  std::string(static_dev >= 0 ? "the library's static workspace" : "workspace") +
+                      " exhausted: a buffer of " + std::to_string(bytes) + " bytes does not fit (" +
+                      std::to_string(arena.used) + " of " + std::to_string(arena.bytes) +
+                      " bytes in use, largest free range " + std::to_string(arena.largest_free()) + "); " +
+                      (static_dev >= 0 ? "the input is beyond what an engine of dl_load_program_static can hold"
+                                       : "give the engine a larger workspace (dl_set_workspace)")};
   } else {
     hipError_t err = hipMalloc(&p, cap);
     if (err != hipSuccess) {
@@ -172,6 +176,7 @@ void Engine::release(DevBuf& b) {
 // Move every live buffer into a new home: the range [p, p + n) (p != NULL)
 // or separate hipMalloc allocations (p == NULL).  On failure nothing moves.
 void Engine::set_workspace(void* p, size_t n) {
+  if (static_dev >= 0) throw Error{DL_ERR_STATE, "an engine of dl_load_program_static keeps the static workspace"};
   if (p && n < ARENA_ALIGN) throw Error{DL_ERR_ARG, "workspace below 256 bytes"};
   sync();
   Arena na;
@@ -273,18 +278,22 @@ void Engine::init(const char* program_text, const dl_options* o) {
       if (!ix.recent && prog.rels[ix.rel].derived && prog.rels[ix.rel].stratum == prog.rels[pl.head_rel].stratum)
         rel[ix.rel].own_index = true;
     }
-  if (o->stream) {
-    stream = (hipStream_t)o->stream;
+  if (o->stream || static_dev >= 0) {
+    stream = (hipStream_t)o->stream;  // static engines never create a stream: NULL is the null stream
   } else {
     DL_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     own_stream = true;
   }
-  if (o->workspace) {
-    if (o->workspace_bytes < ARENA_ALIGN) throw Error{DL_ERR_ARG, "workspace below 256 bytes"};
-    use_arena = true;
-    arena.reset(o->workspace, o->workspace_bytes);
+  if (static_dev >= 0) {  // the arena over the static array was set by the caller
+    host = host_words;    // readback words in the engine itself (no pinned allocation)
+  } else {
+    if (o->workspace) {
+      if (o->workspace_bytes < ARENA_ALIGN) throw Error{DL_ERR_ARG, "workspace below 256 bytes"};
+      use_arena = true;
+      arena.reset(o->workspace, o->workspace_bytes);
+    }
+    DL_HIP(hipHostMalloc((void**)&host, 64 * sizeof(uint64_t), hipHostMallocDefault));
   }
-  DL_HIP(hipHostMalloc((void**)&host, 64 * sizeof(uint64_t), hipHostMallocDefault));
   grow(dtotal, 64 * sizeof(uint64_t));
   grow(cs_state, count_scan_state_words() * sizeof(uint64_t));
   fill_u32(cs_state.as<uint32_t>(), count_scan_state_words() * 2, 0u, stream);
@@ -687,11 +696,58 @@ struct dl_engine {
   Engine e;
 };
 
+// ------------------------------------------------------ static workspace
+// Device memory the library itself holds for callers that cannot allocate
+// (dl_load_program_static): one array on every device the library runs on,
+// kept until the process ends.  In host code `scratch` is only a stand-in
+// for the symbol: its device address comes from hipGetSymbolAddress, once
+// per device with that device current, and only that address is used.
+constexpr size_t STATIC_WORKSPACE_BYTES = (size_t)DL_STATIC_WORKSPACE_MIB << 20;
+static __device__ __align__(256) uint8_t scratch[STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+struct StaticSlot {
+  void* ptr = nullptr;  // device address of `scratch` on this device
+  uint64_t gen = 0;     // bumped by every dl_load_program_static on this device
+};
+std::mutex g_static_mu;
+StaticSlot g_static[MAX_DEVICES];
+
+// The current device's array (resolved on first use) and a new generation.
+void static_claim(int* dev, void** ptr, uint64_t* gen) {
+  DL_HIP(hipGetDevice(dev));
+  if (*dev < 0 || *dev >= MAX_DEVICES) throw Error{DL_ERR_ARG, "device ordinal beyond the static workspace table"};
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  StaticSlot& s = g_static[*dev];
+  if (!s.ptr) {
+    void* p = nullptr;
+    const hipError_t rc = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (rc != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error{DL_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(rc)};
+    }
+    s.ptr = p;
+  }
+  *ptr = s.ptr;
+  *gen = ++s.gen;
+}
+
+// Whether a static engine still holds its device's array.
+bool static_current(const Engine& e) {
+  if (e.static_dev < 0) return true;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  return g_static[e.static_dev].gen == e.static_gen;
+}
+}  // namespace
+
 template <typename F>
 static dl_status guard(dl_engine* h, F&& f) {
   if (!h) return DL_ERR_ARG;
   try {
     h->e.err.clear();
+    if (!static_current(h->e))
+      throw Error{DL_ERR_STATE, "a later dl_load_program_static on this device took over the static workspace"};
     f();
     return DL_OK;
   } catch (const Error& x) {
@@ -720,6 +776,39 @@ dl_status dl_load_program(const char* program_text, const dl_options* opts, dl_e
   dl_engine* h = nullptr;
   try {
     h = new dl_engine();
+    h->e.init(program_text, opts);
+  } catch (const Error& x) {
+    g_load_error = x.msg;
+    delete h;
+    return x.code;
+  } catch (const std::exception& x) {
+    g_load_error = x.what();
+    delete h;
+    return DL_ERR_HIP;
+  }
+  *out = h;
+  return DL_OK;
+}
+
+dl_status dl_load_program_static(const char* program_text, const dl_options* opts, dl_engine** out) {
+  if (!out) return DL_ERR_ARG;
+  *out = nullptr;
+  if (!program_text || !opts || opts->workspace) {
+    g_load_error = opts && opts->workspace ? "dl_load_program_static takes no workspace (it uses the static one)"
+                                           : "program text or options is NULL";
+    return DL_ERR_ARG;
+  }
+  dl_engine* h = nullptr;
+  try {
+    int dev = 0;
+    void* ptr = nullptr;
+    uint64_t gen = 0;
+    static_claim(&dev, &ptr, &gen);
+    h = new dl_engine();
+    h->e.static_dev = dev;
+    h->e.static_gen = gen;
+    h->e.use_arena = true;
+    h->e.arena.reset(ptr, STATIC_WORKSPACE_BYTES);
     h->e.init(program_text, opts);
   } catch (const Error& x) {
     g_load_error = x.msg;

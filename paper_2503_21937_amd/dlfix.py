@@ -19,7 +19,7 @@ SEMIRINGS = {"bool": 0, "maxmin": 1, "minplus": 2, "addmult": 3,
              "diff_addmult": 4, "topk": 5, "diff_topk": 6}
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_PARSE", 3: "ERR_UNSUPPORTED", 4: "ERR_STATE",
           5: "ERR_NOMEM", 6: "ERR_CAPACITY", 7: "ERR_PROOF_OVERFLOW", 8: "ERR_HIP"}
-EXPORTS = ["dl_load_program", "dl_clear_facts", "dl_add_facts", "dl_run_fixpoint", "dl_set_workspace",
+EXPORTS = ["dl_load_program", "dl_load_program_static", "dl_clear_facts", "dl_add_facts", "dl_run_fixpoint", "dl_set_workspace",
            "dl_relation_size", "dl_read_relation", "dl_lookup", "dl_backward_rows", "dl_backward", "dl_read_grad",
            "dl_zero_grad", "dl_get_stats", "dl_autotune", "dl_profile", "dl_get_kernel_timing",
            "dl_last_error", "dl_free"]
@@ -78,6 +78,7 @@ def lib():
         L = C.CDLL(LIB)
         vp, sz = C.c_void_p, C.c_size_t
         L.dl_load_program.argtypes = [C.c_char_p, C.POINTER(Options), C.POINTER(vp)]
+        L.dl_load_program_static.argtypes = [C.c_char_p, C.POINTER(Options), C.POINTER(vp)]
         L.dl_clear_facts.argtypes = [vp]
         L.dl_add_facts.argtypes = [vp, C.c_char_p, sz, vp, vp, vp, C.c_int]
         L.dl_run_fixpoint.argtypes = [vp]
@@ -150,10 +151,12 @@ class Engine:
     def __init__(self, program: str, semiring: str = "bool", k: int = 3,
                  batched: bool = False, stream: int | None = None, use_torch_stream: bool = True,
                  dedup: str = "auto", graphs: bool = True, lineage: str = "auto",
-                 lineage_budget: int = 0, workspace=None):
+                 lineage_budget: int = 0, workspace=None, static: bool = False):
         """workspace: None (the library allocates), a byte count (a torch
         uint8 tensor of that size is allocated here and kept), or a device
-        tensor whose storage the engine keeps all its buffers in."""
+        tensor whose storage the engine keeps all its buffers in.
+        static: keep every buffer in the library's static per-device array
+        (dl_load_program_static); no workspace then."""
         self.arity = {}
         for line in program.splitlines():
             line = line.strip()
@@ -174,7 +177,8 @@ class Engine:
         opts = Options(SEMIRINGS[semiring], k, int(batched), stream, self.DEDUP[dedup], int(not graphs),
                        self.LINEAGE[lineage], lineage_budget, wp, wn)
         h = C.c_void_p()
-        rc = lib().dl_load_program(program.encode(), C.byref(opts), C.byref(h))
+        load = lib().dl_load_program_static if static else lib().dl_load_program
+        rc = load(program.encode(), C.byref(opts), C.byref(h))
         if rc:
             raise DLError(rc, lib().dl_last_error(None).decode())
         self.h = h
