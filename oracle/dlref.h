@@ -38,7 +38,8 @@ enum {
   REF_ADDMULT = 3,
   REF_DIFF_ADDMULT = 4,
   REF_TOPK = 5,
-  REF_DIFF_TOPK = 6
+  REF_DIFF_TOPK = 6,
+  REF_DIFF_MAXMIN = 7  /* max-min with the input fact its value comes from (see ref_read_fid) */
 };
 
 typedef struct ref_engine ref_engine;
@@ -63,6 +64,15 @@ int ref_num_strata(ref_engine*);
 int ref_read(ref_engine*, const char* rel, uint32_t* sample_ids, uint32_t* cols,
              double* value, int32_t* cnt, uint64_t* bits, float* p,
              double* prob, int32_t* round_found);
+/* Differentiable max-min: the input fact (numbered 0, 1, ... over all
+ * ref_add_facts calls in order) whose probability each tuple's tag equals;
+ * its derivative with respect to that probability is 1, to all others 0.
+ * Tags are (value, fact): x keeps the smaller value, + the larger one, and
+ * equal values keep the smaller fact number. */
+int ref_read_fid(ref_engine*, const char* rel, uint32_t* fid);
+/* The pair operations of differentiable max-min (op 0 = plus, 1 = times). */
+int ref_vid_op(int op, double av, uint32_t aid, double bv, uint32_t bid, double* ov, uint32_t* oid);
+
 /* Reverse mode: seed d(loss)/d(tag) for every tuple of out_rel (canonical
  * order) and accumulate the input-fact gradients. */
 int ref_backward(ref_engine*, const char* out_rel, const double* grad_out);

@@ -366,6 +366,7 @@ struct Parser {
 const int KMAX = 3;
 struct Tag {
   double v = 0;
+  uint32_t fid = 0;  // differentiable max-min: the input fact the value comes from
   int cnt = 0;
   uint64_t bits[KMAX] = {0, 0, 0};
   float p[KMAX] = {0, 0, 0};
@@ -410,6 +411,12 @@ struct Semiring {
     if (kind == REF_MINPLUS) t.v = std::numeric_limits<double>::infinity();
     return t;
   }
+  // differentiable max-min: the smaller (times) or larger (plus) value; on
+  // equal values the smaller fact number
+  static Tag pick(const Tag& a, const Tag& b, bool larger) {
+    if (a.v != b.v) return (a.v > b.v) == larger ? a : b;
+    return a.fid <= b.fid ? a : b;
+  }
   Tag otimes(const Tag& a, const Tag& b, const std::vector<float>& q) const {
     Tag t;
     switch (kind) {
@@ -418,6 +425,7 @@ struct Semiring {
       case REF_MINPLUS: t.v = a.v + b.v; break;
       case REF_ADDMULT:
       case REF_DIFF_ADDMULT: t.v = a.v * b.v; break;
+      case REF_DIFF_MAXMIN: t = pick(a, b, false); break;
       default: {
         std::vector<uint64_t> cand;
         for (int i = 0; i < a.cnt; ++i)
@@ -435,6 +443,7 @@ struct Semiring {
       case REF_MINPLUS: t.v = std::min(a.v, b.v); break;
       case REF_ADDMULT:
       case REF_DIFF_ADDMULT: t.v = std::min(1.0, a.v + b.v); break;
+      case REF_DIFF_MAXMIN: t = pick(a, b, true); break;
       default: {
         std::vector<uint64_t> cand;
         for (int i = 0; i < a.cnt; ++i) cand.push_back(a.bits[i]);
@@ -446,6 +455,7 @@ struct Semiring {
   }
   bool same(const Tag& a, const Tag& b) const {
     if (kind == REF_BOOL) return true;
+    if (kind == REF_DIFF_MAXMIN) return a.v == b.v && a.fid == b.fid;
     if (!topk()) return a.v == b.v;
     if (a.cnt != b.cnt) return false;
     for (int i = 0; i < a.cnt; ++i)
@@ -512,6 +522,7 @@ struct ref_engine {
   std::vector<long> nfacts;                       // per relation
   std::vector<std::vector<double>> grad;          // per relation, per fact
   std::vector<std::vector<uint32_t>> fact_sample; // per relation, per fact
+  std::vector<std::pair<int, long>> fact_of_fid;  // differentiable max-min: fact number -> (relation, fact)
   std::string err;
 };
 
@@ -714,7 +725,7 @@ extern "C" {
 int ref_create(const char* program, int semiring, int k, int batched, ref_engine** out, char* err,
                size_t errlen) {
   *out = nullptr;
-  if (semiring < REF_BOOL || semiring > REF_DIFF_TOPK || k < 1 || k > KMAX) {
+  if (semiring < REF_BOOL || semiring > REF_DIFF_MAXMIN || k < 1 || k > KMAX) {
     if (err && errlen) std::snprintf(err, errlen, "bad semiring or k");
     return 1;
   }
@@ -778,6 +789,10 @@ int ref_add_facts(ref_engine* e, const char* rel, size_t n, const uint32_t* samp
       t.p[0] = tags[i];
       db.q.push_back(tags[i]);
       db.fact_of_bit.push_back({r, f});
+    } else if (e->sr.kind == REF_DIFF_MAXMIN) {
+      t.v = (double)tags[i];
+      t.fid = (uint32_t)e->fact_of_fid.size();
+      e->fact_of_fid.push_back({r, f});
     } else if (e->sr.kind != REF_BOOL) {
       t.v = (double)tags[i];
     } else {
@@ -861,13 +876,21 @@ int ref_backward(ref_engine* e, const char* out_rel, const double* grad_out) {
   int r = e->prog.find(out_rel);
   if (r < 0 || !e->ran) return 1;
   int kind = e->sr.kind;
-  if (kind != REF_DIFF_ADDMULT && kind != REF_DIFF_TOPK) {
+  if (kind != REF_DIFF_ADDMULT && kind != REF_DIFF_TOPK && kind != REF_DIFF_MAXMIN) {
     e->err = "backward needs a differentiable semiring";
     return 1;
   }
   size_t i = 0;
   for (auto& kv : e->samples) {
     SampleDB& db = kv.second;
+    if (kind == REF_DIFF_MAXMIN) {
+      // the tag is the probability of one input fact: derivative 1 there
+      for (auto& t : db.rel[r]) {
+        const auto fr = e->fact_of_fid[t.second.tag.fid];
+        e->grad[fr.first][fr.second] += grad_out[i++];
+      }
+      continue;
+    }
     if (kind == REF_DIFF_TOPK) {
       // dP/dq_j of the inclusion-exclusion probability, proofs held fixed.
       for (auto& t : db.rel[r]) {
@@ -926,6 +949,27 @@ int ref_backward(ref_engine* e, const char* out_rel, const double* grad_out) {
       }
     }
   }
+  return 0;
+}
+
+int ref_read_fid(ref_engine* e, const char* rel, uint32_t* fid) {
+  int r = e->prog.find(rel);
+  if (r < 0) return 1;
+  size_t i = 0;
+  for (auto& kv : e->samples)
+    for (auto& t : kv.second.rel[r]) fid[i++] = t.second.tag.fid;
+  return 0;
+}
+
+int ref_vid_op(int op, double av, uint32_t aid, double bv, uint32_t bid, double* ov, uint32_t* oid) {
+  Tag a, b;
+  a.v = av;
+  a.fid = aid;
+  b.v = bv;
+  b.fid = bid;
+  const Tag t = Semiring::pick(a, b, op == 0);
+  *ov = t.v;
+  *oid = t.fid;
   return 0;
 }
 

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libdlref.so")
 SOURCES = ["naive.cpp", "special.cpp"]
 
 SEMIRINGS = {"bool": 0, "maxmin": 1, "minplus": 2, "addmult": 3,
-             "diff_addmult": 4, "topk": 5, "diff_topk": 6}
+             "diff_addmult": 4, "topk": 5, "diff_topk": 6, "diff_maxmin": 7}
 
 
 def build(force: bool = False) -> str:
@@ -55,6 +55,9 @@ def lib():
         L.ref_num_strata.argtypes = [vp]
         L.ref_read.argtypes = [vp, C.c_char_p] + [vp] * 8
         L.ref_backward.argtypes = [vp, C.c_char_p, vp]
+        L.ref_read_fid.argtypes = [vp, C.c_char_p, vp]
+        L.ref_vid_op.argtypes = [C.c_int, C.c_double, C.c_uint32, C.c_double, C.c_uint32,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_uint32)]
         L.ref_read_grad.argtypes = [vp, C.c_char_p, vp]
         L.ref_zero_grad.argtypes = [vp]
         L.ref_error.argtypes = [vp]
@@ -150,6 +153,13 @@ class Oracle:
         return dict(sample=s, cols=cols, value=val, cnt=cnt, bits=bits, p=p,
                     prob=prob, round=rf)
 
+    def fid(self, rel: str) -> np.ndarray:
+        """Differentiable max-min: the input fact number each tuple's tag comes from."""
+        out = np.zeros(self.size(rel), np.uint32)
+        if lib().ref_read_fid(self.h, rel.encode(), _p(out)):
+            self._err("read_fid")
+        return out
+
     def backward(self, out_rel: str, grad_out):
         g = np.ascontiguousarray(np.asarray(grad_out, np.float64))
         if lib().ref_backward(self.h, out_rel.encode(), _p(g)):
@@ -163,6 +173,14 @@ class Oracle:
 
     def zero_grad(self):
         lib().ref_zero_grad(self.h)
+
+
+def vid_op(op: str, a, b):
+    """Differentiable max-min pair operation ('plus' or 'times') on (value, fact) pairs."""
+    ov, oid = C.c_double(), C.c_uint32()
+    lib().ref_vid_op(0 if op == "plus" else 1, float(a[0]), int(a[1]), float(b[0]), int(b[1]), C.byref(ov),
+                     C.byref(oid))
+    return ov.value, oid.value
 
 
 def tc_column(n: int, src, dst, w, semiring: str, z: int, grad_col=None):
