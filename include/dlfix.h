@@ -57,7 +57,14 @@ typedef enum {
  *                proofs (ties: smaller bitset first).
  *  DIFF_TOPK     TOPK with the gradient of the inclusion-exclusion
  *                probability of the kept proofs.
- * BOOL, MAXMIN, MINPLUS and the TOPK forms have an idempotent + and are
+ *  DIFF_MAXMIN   MAXMIN with gradients (Sec. 3.5): a tag is a pair (value,
+ *                fact number), the value being the probability of one input
+ *                fact, numbered over all relations in dl_add_facts order from
+ *                0 (since the last dl_clear_facts).  x keeps the smaller value,
+ *                + the larger; equal values keep the smaller fact number, so
+ *                the result does not depend on evaluation order.  The
+ *                derivative of a tag is 1 for its fact and 0 for all others.
+ * BOOL, MAXMIN, MINPLUS, DIFF_MAXMIN and the TOPK forms have an idempotent + and are
  * iterated until no tag changes; the ADDMULT forms fix a fact's tag in the
  * iteration that first derives it (later derivations do not change it). */
 typedef enum {
@@ -67,7 +74,8 @@ typedef enum {
   DL_ADDMULT = 3,
   DL_DIFF_ADDMULT = 4,
   DL_TOPK = 5,
-  DL_DIFF_TOPK = 6
+  DL_DIFF_TOPK = 6,
+  DL_DIFF_MAXMIN = 7
 } dl_semiring;
 
 typedef struct {
@@ -77,10 +85,13 @@ typedef struct {
   void* stream;       /* hipStream_t to run on; NULL: the engine creates its own stream */
   int dedup;          /* per-round deduplication of derived relations:
                          0 = automatic (dense-domain when the packed key domain of the relation
-                             is at most 2^30 and the semiring is not top-k, else sort-based),
+                             is at most 2^30 and the semiring is not a top-k form or DIFF_MAXMIN,
+                             else sort-based),
                          1 = always sort-based (radix sort, unique, difference, merge),
                          2 = dense-domain wherever possible */
   int no_graphs;      /* 1: never replay round bodies as captured HIP graphs (0: replay where eligible) */
+  int no_fused;       /* 1: never run a round as one fused launch (0: where the stratum has one
+                         static-driven join whose derivations fall into per-group windows) */
   int lineage;        /* DIFF_ADDMULT derivation lineage for dl_backward:
                          0 = automatic (recorded during the run; dropped and recomputed round by
                              round in dl_backward once it would exceed lineage_budget),
@@ -97,6 +108,11 @@ typedef struct {
                              stream.  Its contents on entry do not matter.  NULL: the engine makes
                              its own hipMalloc allocations. */
   size_t workspace_bytes; /* size of `workspace` in bytes (at least 256) */
+  uint64_t max_join_outputs; /* outputs of one join launch before its probe rows are split into chunks
+                                (0: 2^32 - 1, the reach of the 32-bit offsets); smaller values only serve
+                                to test the chunked path */
+  int exact_growth;       /* 1: buffers grow to exactly the size asked (no 25% margin), so that they are
+                             regrown more often (tests of the regrowth paths) */
 } dl_options;
 
 /* Result columns of dl_read_relation.  Any pointer may be NULL (not written).
@@ -109,6 +125,8 @@ typedef struct {
   uint8_t* topk_count;    /* [n]   number of kept proofs (TOPK) */
   uint64_t* topk_bits;    /* [k*n] proof j of row i at [j*n + i]; bit f = fact f of the row's sample */
   float* topk_prob;       /* [k*n] binary32 proof probabilities, same layout */
+  uint32_t* fact_ids;     /* [n] DIFF_MAXMIN: the number of the input fact each tag comes from
+                             (not written for the other semirings) */
 } dl_relation_out;
 
 typedef struct {
@@ -252,13 +270,13 @@ dl_status dl_read_relation(dl_engine* e, const char* relation, size_t capacity,
 dl_status dl_lookup(dl_engine* e, const char* relation, size_t n, const uint32_t* sample_ids,
                     const uint32_t* const* columns, int64_t* rows, float* tags, int on_device);
 
-/* Reverse mode seeded on selected rows (e.g. from dl_lookup; rows < 0 are
- * skipped): d(loss)/d(tag of row rows[i]) = grad[i].  Same accumulation as
+/* Reverse mode seeded on selected rows (e.g. from dl_lookup; rows < 0 or at
+ * least the relation's size are skipped): d(loss)/d(tag of row rows[i]) = grad[i].  Same accumulation as
  * dl_backward (Sec. 3.5, differentiable semirings). */
 dl_status dl_backward_rows(dl_engine* e, const char* relation, size_t n, const int64_t* rows, const float* grad,
                            int on_device);
 
-/* Reverse mode for DIFF_ADDMULT and DIFF_TOPK (Sec. 3.5: differentiable
+/* Reverse mode for DIFF_ADDMULT, DIFF_TOPK and DIFF_MAXMIN (Sec. 3.5: differentiable
  * provenance semirings, whose tags carry derivatives with respect to the input
  * facts' probabilities; computed here in reverse mode over the recorded or
  * recomputed derivations): grad_out[i] is d(loss)/d(tag)
@@ -267,7 +285,8 @@ dl_status dl_backward_rows(dl_engine* e, const char* relation, size_t n, const i
  * DIFF_ADDMULT sweeps the discovery derivations round by round in reverse
  * (a tuple's tag is the clamped sum over the derivations of the round that
  * found it); without recorded lineage (dl_options.lineage) each round's
- * derivations are recomputed first, which costs about one forward join pass. */
+ * derivations are recomputed first, which costs about one forward join pass.
+ * DIFF_MAXMIN adds grad_out[i] to the fact that row i's tag comes from. */
 dl_status dl_backward(dl_engine* e, const char* out_relation, const float* grad_out, int on_device);
 
 /* Accumulated input gradients of an input relation, in dl_add_facts order

@@ -139,7 +139,19 @@ struct TopK {
   uint32_t cnt;
 };
 
-enum SemiringKind : int { SR_BOOL = 0, SR_MAXMIN = 1, SR_MINPLUS = 2, SR_ADDMULT = 3, SR_DIFF_ADDMULT = 4, SR_TOPK = 5, SR_DIFF_TOPK = 6 };
+// Differentiable max-min: a probability and the input fact it comes from.
+struct VTag {
+  float v;
+  uint32_t f;
+};
+// x keeps the smaller value, + the larger one; equal values keep the
+// smaller fact number (order independent, so atomics and any + order agree)
+__device__ __forceinline__ VTag vtag_pick(VTag a, VTag b, bool larger) {
+  if (a.v != b.v) return (a.v > b.v) == larger ? a : b;
+  return a.f <= b.f ? a : b;
+}
+
+enum SemiringKind : int { SR_BOOL = 0, SR_MAXMIN = 1, SR_MINPLUS = 2, SR_ADDMULT = 3, SR_DIFF_ADDMULT = 4, SR_TOPK = 5, SR_DIFF_TOPK = 6, SR_DIFF_MAXMIN = 7 };
 
 // x for binary32 semirings (`sr` is uniform across the launch).
 __device__ __forceinline__ float f_otimes(int sr, float a, float b) {

@@ -64,7 +64,8 @@ struct Table {
 struct RelState {
   // input relations: facts staged as they arrive, packed at the next run
   std::vector<DevBuf> raw_cols;
-  DevBuf raw_sample, raw_tags, raw_local;  // raw_local: top-k fact id inside its sample
+  DevBuf raw_sample, raw_tags, raw_local;  // raw_local: top-k: fact id inside its sample;
+                                           // differentiable max-min: fact number over all relations
   size_t nraw = 0;
   Table full, full_alt, recent;
   DevBuf cand_keys, cand_tags, cand_l, cand_r;  // this round's derivations (head rows)
@@ -113,6 +114,7 @@ struct ExecConfig {
   int orient = 0;  // delta plans of 2-atom rules: 0 auto, 1 recent-driven, 2 static-driven
   int graph = 1;   // replay eligible round bodies as a captured HIP graph
   int rows = 1;    // row-window variant of the dense join where it applies
+  int fused = 1;   // one launch per round (window_round) where the shape allows
 };
 
 struct Engine {
@@ -154,6 +156,7 @@ struct Engine {
   // top-k: fact probabilities per sample [sample][64] and counters
   std::vector<float> qtab_h;
   std::vector<uint32_t> topk_next;
+  uint32_t nfacts = 0;  // facts added since the last clear, over all relations (max-min fact numbers)
   DevBuf qtab, grad_fact;
 
   // lineage log (diff add-mult) and per-id tags.  Ids are handed out in
@@ -172,13 +175,15 @@ struct Engine {
   DevBuf counts, offs, istart, alt_keys, alt_vals, vals, flags, pos, ukeys, utags,
       status, nflags, newpos, rflags, rpos, lf, lpos, nkeys, ntags, nids, tmpA_keys, tmpA_tags, tmpB_keys, tmpB_tags,
       work, unpack, qbuf,  // work: scan and radix-sort partials
-      ev_keys, ev_tags, ev_l, ev_r;  // output rows of a plan with evaluation, before the condition compacts them
+      ev_keys, ev_tags, ev_l, ev_r,  // output rows of a plan with evaluation, before the condition compacts them
+      wr_keys0, wr_keys1, wr_tags0, wr_tags1, wr_cnt0, wr_cnt1, wr_part;  // fused rounds: two window-layout recent sets
   uint64_t* host = nullptr;  // pinned readback words
   DevBuf dtotal;             // device words for totals
   DevBuf cs_state;           // single-pass count+scan: tile sums and flags (kept zeroed between launches)
 
   dl_stats stats{};
   uint64_t deferred_units = 0;  // derivations of joins whose totals stayed on the device (last run)
+  uint64_t fused_units = 0;     // derivations of fused rounds (this run, added up on the host)
   uint32_t prof_mask = 0;
   dl_kernel_timing kstats[DL_K_FAMILIES]{};
   size_t device_bytes = 0;
@@ -237,7 +242,8 @@ void Engine::for_each_buf(F&& f) {
   for (DevBuf* b : {&d_sn, &d_snp, &qtab, &grad_fact, &lin_owner, &lin_l, &lin_r, &tag_by_id, &adj, &counts, &offs,
                     &istart, &alt_keys, &alt_vals, &vals, &flags, &pos, &ukeys, &utags, &status, &nflags, &newpos,
                     &rflags, &rpos, &lf, &lpos, &nkeys, &ntags, &nids, &tmpA_keys, &tmpA_tags, &tmpB_keys,
-                    &tmpB_tags, &work, &unpack, &qbuf, &dtotal, &cs_state, &ev_keys, &ev_tags, &ev_l, &ev_r})
+                    &tmpB_tags, &work, &unpack, &qbuf, &dtotal, &cs_state, &ev_keys, &ev_tags, &ev_l, &ev_r,
+                    &wr_keys0, &wr_keys1, &wr_tags0, &wr_tags1, &wr_cnt0, &wr_cnt1, &wr_part})
     f(*b);
 }
 

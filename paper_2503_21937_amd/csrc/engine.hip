@@ -119,7 +119,7 @@ size_t Arena::largest_free() const {
 
 void Engine::grow(DevBuf& b, size_t bytes, bool keep, size_t used) {
   if (bytes <= b.cap) return;
-  size_t cap = std::max<size_t>(bytes + bytes / 4, 256);
+  size_t cap = std::max<size_t>(opts.exact_growth ? bytes : bytes + bytes / 4, 256);
   void* p = nullptr;
   if (use_arena) {
     cap = align_up(cap);
@@ -256,14 +256,17 @@ void Engine::init(const char* program_text, const dl_options* o) {
   text = program_text;
   opts = *o;
   sr = o->semiring;
-  if (sr < DL_BOOL || sr > DL_DIFF_TOPK) throw Error{DL_ERR_ARG, "unknown semiring"};
+  if (sr < DL_BOOL || sr > DL_DIFF_MAXMIN) throw Error{DL_ERR_ARG, "unknown semiring"};
   k = o->k == 0 ? 3 : o->k;
   if ((sr == DL_TOPK || sr == DL_DIFF_TOPK) && (k < 1 || k > 3)) throw Error{DL_ERR_ARG, "k must be 1..3"};
   batched = o->batched != 0;
   converge = !(sr == DL_ADDMULT || sr == DL_DIFF_ADDMULT);
   lineage = sr == DL_DIFF_ADDMULT;
-  tag_kind = sr == DL_BOOL ? TAG_NONE : (sr == DL_TOPK || sr == DL_DIFF_TOPK) ? TAG_TOPK : TAG_F32;
-  tag_bytes = tag_kind == TAG_NONE ? 0 : tag_kind == TAG_F32 ? 4 : sizeof(TopK);
+  tag_kind = sr == DL_BOOL                       ? TAG_NONE
+             : (sr == DL_TOPK || sr == DL_DIFF_TOPK) ? TAG_TOPK
+             : sr == DL_DIFF_MAXMIN                  ? TAG_VID
+                                                     : TAG_F32;
+  tag_bytes = tag_kind == TAG_NONE ? 0 : tag_kind == TAG_F32 ? 4 : tag_kind == TAG_VID ? sizeof(VTag) : sizeof(TopK);
   std::string perr;
   int rc = parse_and_plan(program_text, !converge, lineage, prog, perr);
   if (rc) throw Error{(dl_status)rc, perr};
@@ -272,6 +275,7 @@ void Engine::init(const char* program_text, const dl_options* o) {
   idx.assign(prog.indexes.size(), IndexState{});
   if (o->dedup < 0 || o->dedup > 2) throw Error{DL_ERR_ARG, "dedup must be 0, 1 or 2"};
   cfg.graph = o->no_graphs ? 0 : 1;
+  cfg.fused = o->no_fused ? 0 : 1;
   for (const Plan& pl : prog.plans)
     for (const Step& st : pl.steps) {
       const IndexSpec& ix = prog.indexes[st.index];
@@ -320,6 +324,7 @@ void Engine::clear_facts() {
   for (auto& x : idx) x.built = false;
   qtab_h.clear();
   topk_next.clear();
+  nfacts = 0;
   ingested = false;
   ran = false;
 }
@@ -335,6 +340,8 @@ void Engine::add_facts(const char* relation, size_t n, const uint32_t* sample_id
     if (!columns[c]) throw Error{DL_ERR_ARG, "a column pointer is NULL"};
   if (batched && !sample_ids) throw Error{DL_ERR_ARG, "batched engine needs sample ids"};
   if (sr != DL_BOOL && !tags) throw Error{DL_ERR_ARG, "this semiring needs tags"};
+  if (tag_kind == TAG_VID && n >= (size_t)UINT32_MAX - nfacts)  // UINT32_MAX: the fact number of x's identity
+    throw Error{DL_ERR_CAPACITY, "more than 2^32 - 2 facts"};
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   RelState& R = rel[r];
   const bool topk = tag_kind == TAG_TOPK;
@@ -378,6 +385,10 @@ void Engine::add_facts(const char* relation, size_t n, const uint32_t* sample_id
   if (topk) {
     grow(R.raw_local, (old + n) * 4, true, old * 4);
     DL_HIP(hipMemcpyAsync(R.raw_local.as<uint32_t>() + old, local_h.data(), n * 4, hipMemcpyHostToDevice, stream));
+  } else if (tag_kind == TAG_VID) {  // fact numbers continue over calls and relations
+    grow(R.raw_local, (old + n) * 4, true, old * 4);
+    iota_u32(R.raw_local.as<uint32_t>() + old, n, nfacts, stream);
+    nfacts += (uint32_t)n;
   }
   R.nraw = old + n;
   sync();  // host staging vectors go out of scope
@@ -475,8 +486,8 @@ size_t Engine::read_relation(const char* relation, size_t capacity, const dl_rel
 void Engine::backward(const char* out_relation, const float* grad_out, int on_device) {
   int r = relation_id(out_relation);
   if (!ran) throw Error{DL_ERR_STATE, "run the fixpoint first"};
-  if (sr != DL_DIFF_ADDMULT && sr != DL_DIFF_TOPK)
-    throw Error{DL_ERR_STATE, "backward needs DL_DIFF_ADDMULT or DL_DIFF_TOPK"};
+  if (sr != DL_DIFF_ADDMULT && sr != DL_DIFF_TOPK && sr != DL_DIFF_MAXMIN)
+    throw Error{DL_ERR_STATE, "backward needs a differentiable semiring"};
   const size_t n = rel[r].full.n;
   if (n && !grad_out) throw Error{DL_ERR_ARG, "grad_out is NULL"};
   grow(unpack, n * 4 + 4);
@@ -493,8 +504,8 @@ void Engine::backward(const char* out_relation, const float* grad_out, int on_de
 void Engine::backward_rows(const char* relation, size_t n, const int64_t* rows, const float* grad, int on_device) {
   int r = relation_id(relation);
   if (!ran) throw Error{DL_ERR_STATE, "run the fixpoint first"};
-  if (sr != DL_DIFF_ADDMULT && sr != DL_DIFF_TOPK)
-    throw Error{DL_ERR_STATE, "backward needs DL_DIFF_ADDMULT or DL_DIFF_TOPK"};
+  if (sr != DL_DIFF_ADDMULT && sr != DL_DIFF_TOPK && sr != DL_DIFF_MAXMIN)
+    throw Error{DL_ERR_STATE, "backward needs a differentiable semiring"};
   if (n && (!rows || !grad)) throw Error{DL_ERR_ARG, "rows or grad is NULL"};
   const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   grow(qbuf, n * 12 + 16);
@@ -559,6 +570,8 @@ void Engine::read_grad(const char* in_relation, float* grad_in, int on_device) {
     grow(R.fact_slot_d, R.nraw * 4);
     DL_HIP(hipMemcpyAsync(R.fact_slot_d.p, R.fact_slot.data(), R.nraw * 4, hipMemcpyHostToDevice, stream));
     gather(grad_fact.p, R.fact_slot_d.as<uint32_t>(), R.grad.p, R.nraw, 4, stream);
+  } else if (tag_kind == TAG_VID) {  // grad_fact is indexed by fact number
+    gather(grad_fact.p, R.raw_local.as<uint32_t>(), R.grad.p, R.nraw, 4, stream);
   }
   DL_HIP(hipMemcpyAsync(grad_in, R.grad.p, R.nraw * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                         stream));

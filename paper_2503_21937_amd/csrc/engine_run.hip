@@ -13,6 +13,7 @@
 // stratum ends after the first round that changes nothing.
 #include <algorithm>
 #include <cstring>
+#include <functional>
 
 #include "dl_device.h"
 #include "engine.h"
@@ -171,7 +172,7 @@ void setup_dense(Engine& e) {
     const uint64_t dom = dense_domain(e, e.prog.rels[r].arity);
     const size_t keys = (size_t)std::min<uint64_t>(dom, (uint64_t)1 << 40);
     const size_t bytes = 2 * bitmap_words(keys) * 4 + (e.tag_kind == TAG_F32 ? keys * 4 : 0) + (e.lineage ? keys * 4 : 0);
-    const bool fits = e.tag_kind != TAG_TOPK && dom <= ((uint64_t)1 << 31) && bytes <= budget;
+    const bool fits = (e.tag_kind == TAG_NONE || e.tag_kind == TAG_F32) && dom <= ((uint64_t)1 << 31) && bytes <= budget;
     if (e.opts.dedup == 2 && !fits)
       throw Error{DL_ERR_UNSUPPORTED, "dense-domain deduplication does not fit relation " + e.prog.rels[r].name};
     R.dense = fits && e.opts.dedup != 1;
@@ -474,7 +475,13 @@ void run_plan(Engine& e, const Plan& pl) {
 
   DevBuf* tmp_keys[2] = {&e.tmpA_keys, &e.tmpB_keys};
   DevBuf* tmp_tags[2] = {&e.tmpA_tags, &e.tmpB_tags};
-  for (size_t si = 0; si < pl.steps.size(); ++si) {
+  // Joins whose outputs exceed the 32-bit offsets (or the max_join_outputs
+  // option) run in chunks of probe rows, each chunk through the remaining
+  // steps before the next one starts (depth first: the step buffers are
+  // reused).  A chunk is cut from the per-row match counts read back once.
+  const uint64_t limit = e.opts.max_join_outputs ? std::min<uint64_t>(e.opts.max_join_outputs, 0xffffffffull)
+                                                 : 0xffffffffull;
+  std::function<void(size_t, Cur)> steps_from = [&](size_t si, Cur cur) {
     const Step& step = pl.steps[si];
     a.ev = si + 1 == pl.steps.size() ? ev_out : EvalCode{};
     a.keep = nullptr;
@@ -504,7 +511,11 @@ void run_plan(Engine& e, const Plan& pl) {
     e.grow(e.offs, (cur.n + 1) * 4);
     e.grow(e.istart, cur.n * 4 + 4);
     a.istart = e.istart.as<uint32_t>();
-    const bool nosync = si + 1 == pl.steps.size() && H.dense && !e.record;
+    const bool last = si + 1 == pl.steps.size();
+    // the total stays on the device only when it cannot pass the limit
+    const size_t in = std::max<size_t>(ix.t.n, 1);
+    const uint64_t bound = cur.n > ((size_t)1 << 40) / in ? ((uint64_t)1 << 40) : (uint64_t)cur.n * in;
+    const bool nosync = last && H.dense && !e.record && bound <= limit;
     // without a host readback the scan also adds its total to the run's
     // candidate count (collected at round end)
     if (!join_count_scan<K>(a, e.offs.as<uint32_t>(), e.cs_state.as<uint64_t>(), total_slot(e, S_SCAN),
@@ -515,10 +526,7 @@ void run_plan(Engine& e, const Plan& pl) {
     }
     if (nosync) {
       // no host readback: the expand reads the total on the device; the
-      // candidate count and any 32-bit overflow are collected at round end
-      const IndexState& ixs = e.idx[step.index];
-      const size_t in = std::max<size_t>(ixs.t.n, 1);
-      const size_t bound = cur.n > ((size_t)1 << 40) / in ? ((size_t)1 << 40) : cur.n * in;
+      // candidate count is collected at round end
       const DenseArgs d = dense_room(0, a.items);
       RowWindows rw{};
       const bool rows = e.cfg.rows && row_windows<K>(e, pl, &rw);
@@ -527,9 +535,30 @@ void run_plan(Engine& e, const Plan& pl) {
       return;
     }
     const uint64_t total = e.read_total(S_SCAN);
-    if (total > 0xffffffffull) throw Error{DL_ERR_CAPACITY, "more than 2^32 join outputs in one step"};
     if (total == 0) return;
-    const bool last = si + 1 == pl.steps.size();
+    if (total > limit) {
+      // per-row match counts -> chunks of rows with at most `limit` outputs
+      join_count<K>(a, e.counts.as<uint32_t>(), e.stream);
+      std::vector<uint32_t> cnt(cur.n);
+      DL_HIP(hipMemcpyAsync(cnt.data(), e.counts.p, cur.n * 4, hipMemcpyDeviceToHost, e.stream));
+      e.sync();
+      size_t r0 = 0;
+      while (r0 < cur.n) {
+        uint64_t acc = 0;
+        size_t r1 = r0;
+        while (r1 < cur.n && acc + cnt[r1] <= limit) acc += cnt[r1++];
+        if (r1 == r0)
+          throw Error{DL_ERR_CAPACITY, "one probe row has more than " + std::to_string(limit) + " join outputs"};
+        Cur part = cur;
+        part.keys = static_cast<const K*>(cur.keys) + r0;
+        part.tags = cur.tags ? static_cast<const uint8_t*>(cur.tags) + r0 * e.tag_bytes : nullptr;
+        part.ids = cur.ids ? cur.ids + r0 : nullptr;
+        part.n = r1 - r0;
+        steps_from(si, part);
+        r0 = r1;
+      }
+      return;
+    }
     if (last && H.dense) {
       const DenseArgs d = dense_room(total, a.items);
       RowWindows rw{};
@@ -538,6 +567,8 @@ void run_plan(Engine& e, const Plan& pl) {
                            rows ? &rw : nullptr);
       return;
     }
+    if (last && H.ncand + total > 0xffffffffull)
+      throw Error{DL_ERR_CAPACITY, "more than 2^32 candidate tuples in one round (sort-based deduplication)"};
     void *ok, *ot;
     uint32_t *ol = nullptr, *orr = nullptr;
     if (last && a.ev.n) {
@@ -559,9 +590,10 @@ void run_plan(Engine& e, const Plan& pl) {
     } else if (last) {
       H.ncand += total;
     } else {
-      cur = Cur{ok, ot, nullptr, total, ocols, std::min(cur.minpos, step.body_pos)};
+      steps_from(si + 1, Cur{ok, ot, nullptr, total, ocols, std::min(cur.minpos, step.body_pos)});
     }
-  }
+  };
+  steps_from(0, cur);
 }
 
 // Dense-domain round end: the touched keys are exactly the new and changed
@@ -675,7 +707,7 @@ size_t absorb_sorted(Engine& e, int r) {
   e.stats.candidates += C;
   const int ar = e.prog.rels[r].arity;
   const size_t kb = sizeof(K), tb = e.tag_bytes;
-  const bool use_perm = e.tag_kind == TAG_TOPK || e.record;
+  const bool use_perm = e.tag_kind == TAG_TOPK || e.tag_kind == TAG_VID || e.record;
   hipStream_t st = e.stream;
 
   // 1. sort the candidates by packed key (stable: derivation order kept)
@@ -903,12 +935,137 @@ void enqueue_round_body(Engine& e, int r, const std::vector<const Plan*>& plans,
                     st, total_slot(e, S_LOG), false, fin_csr ? &csr : nullptr, R.lb_state.as<uint64_t>());
 }
 
+// Whether the rounds of a batched stratum can each run as one fused launch
+// (window_round): one static-driven plan with the row-window shape whose
+// index is the recent relation on its first column.  Fills rw (and builds
+// the driver's prefix CSR) when they can.
+template <typename K>
+bool fused_eligible(Engine& e, int r, const std::vector<const Plan*>& plans, RowWindows* rw) {
+  if (!e.cfg.fused || plans.size() != 1 || e.prog.rels[r].arity < 2) return false;
+  const Plan& tw = *plans[0];
+  const IndexSpec& spec = e.prog.indexes[tw.steps[0].index];
+  if (!(spec.rel == r && spec.w == 1 && spec.identity() && spec.recent)) return false;
+  if (!row_windows<K>(e, tw, rw)) return false;
+  return window_round_fits(rw->wkeys);
+}
+
+// Rounds 2.. as fused launches over a window-layout recent relation (see
+// k_window_round); four rounds per host synchronisation, as one captured
+// HIP graph where allowed.  Returns the number of rounds run.
+template <typename K>
+int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows& rw) {
+  const int r = st.rels[0];
+  RelState& R = e.rel[r];
+  const int ar = e.prog.rels[r].arity;
+  const size_t keys = R.dense_keys;
+  const uint32_t ng = (uint32_t)rw.ngroups;
+  const bool f32 = e.tag_kind == TAG_F32;
+  DevBuf* rk[2] = {&e.wr_keys0, &e.wr_keys1};
+  DevBuf* rt[2] = {&e.wr_tags0, &e.wr_tags1};
+  DevBuf* rc[2] = {&e.wr_cnt0, &e.wr_cnt1};
+  for (int i = 0; i < 2; ++i) {
+    e.grow(*rk[i], keys * sizeof(K) + 8);
+    if (f32) e.grow(*rt[i], keys * 4 + 8);
+    e.grow(*rc[i], (size_t)ng * 4 + 4);
+  }
+  const unsigned nb = window_round_grid(ng);
+  e.grow(e.wr_part, (size_t)BATCH_ROUNDS * nb * 2 * 4);
+  // round 1's recent tuples (sorted) into window layout, through their CSR
+  // over (sample, first column)
+  const int ir = tw.steps[0].index;
+  IndexState& ix = e.idx[ir];
+  e.grow(ix.off, ((size_t)ng + 1) * 4);
+  csr_build<K>(R.recent.keys.as<K>(), R.recent.n, e.key_width(ar), e.sbits + e.cbits, ix.off.as<uint32_t>(), e.stream);
+  const DenseArgs d = dense_args(e, R);
+  WindowRecent w[2];
+  for (int i = 0; i < 2; ++i)
+    w[i] = WindowRecent{rc[i]->as<uint32_t>(), rk[i]->p, f32 ? rt[i]->as<float>() : nullptr};
+  to_windows<K>(R.recent.keys.as<K>(), f32 ? R.recent.tags.as<float>() : nullptr, R.recent.n, ix.off.as<uint32_t>(), ng,
+                d, w[0], e.stream);
+  const JoinArgs a = batch_join_args<K>(e, tw, R, ar);
+  RoundArgs ra{};
+  ra.goff = rw.goff;
+  ra.ngroups = ng;
+  ra.win_per_key = e.cfg.rows == 0 ? ~0u : e.cfg.rows == 2 ? 0u : 12u;
+  e.sync();
+  // Every round writes its workgroups' counts to its own part of wr_part;
+  // the host adds them up after the batch.  BATCH_ROUNDS is even: a batch
+  // ends with the recent tuples back in set 0.
+  std::vector<uint32_t> part((size_t)BATCH_ROUNDS * nb * 2);
+  auto enqueue_batch = [&] {
+    for (int i = 0; i < BATCH_ROUNDS; ++i) {
+      ra.cur = w[i & 1];
+      ra.next = w[(i + 1) & 1];
+      ra.part = e.wr_part.as<uint32_t>() + (size_t)i * nb * 2;
+      window_round<K>(a, e.tag_kind, d, ra, e.stream);
+    }
+    DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, e.stream));
+    DL_HIP(hipMemcpyAsync(part.data(), e.wr_part.p, part.size() * 4, hipMemcpyDeviceToHost, e.stream));
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto release = [&] {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  };
+  if (e.cfg.graph && !g_prof && hipStreamBeginCapture(e.stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
+    bool ok = true;
+    try {
+      enqueue_batch();
+    } catch (...) {
+      ok = false;
+    }
+    if (hipStreamEndCapture(e.stream, &graph) != hipSuccess || !graph) ok = false;
+    if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
+    if (!ok) {
+      release();
+      (void)hipGetLastError();
+    }
+  } else {
+    (void)hipGetLastError();
+  }
+  int rounds = 0;
+  bool done = false;
+  while (!done) {
+    if (exec) DL_HIP(hipGraphLaunch(exec, e.stream));
+    else enqueue_batch();
+    e.sync();
+    if (e.host[S_OVF]) {
+      release();
+      check_overflow(e);
+    }
+    for (int i = 0; i < BATCH_ROUNDS && !done; ++i) {
+      uint64_t U = 0, C = 0;
+      for (unsigned b = 0; b < nb; ++b) {
+        U += part[((size_t)i * nb + b) * 2];
+        C += part[((size_t)i * nb + b) * 2 + 1];
+      }
+      ++rounds;
+      ++R.version;
+      ++R.rversion;
+      e.stats.unique += U;
+      e.fused_units += C;
+      done = U == 0;
+    }
+  }
+  R.recent.n = 0;
+  release();
+  ix.built = false;
+  return rounds;
+}
+
 // Rounds 2.. of an eligible stratum in batches of device-sized round bodies;
 // returns the number of rounds run (the last one changed nothing).
 template <typename K>
 int batch_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& plans) {
   const int r = st.rels[0];
   RelState& R = e.rel[r];
+  {
+    RowWindows frw{};
+    if (fused_eligible<K>(e, r, plans, &frw)) return fused_rounds<K>(e, st, *plans[0], frw);
+  }
   // every buffer the body touches at its final size, before any batch (and capture)
   const size_t keys = R.dense_keys;
   e.grow(R.recent.keys, keys * sizeof(K) + 8, true, R.recent.n * sizeof(K));
@@ -1012,6 +1169,10 @@ void ingest(Engine& e) {
       DL_HIP(hipMemcpyAsync(e.qtab.p, e.qtab_h.data(), e.qtab_h.size() * 4, hipMemcpyHostToDevice, st));
     e.grow(e.grad_fact, q * 4);
     DL_HIP(hipMemsetAsync(e.grad_fact.p, 0, q * 4, st));
+  } else if (e.tag_kind == TAG_VID) {  // input gradients by fact number
+    const size_t q = (size_t)e.nfacts + 1;
+    e.grow(e.grad_fact, q * 4);
+    DL_HIP(hipMemsetAsync(e.grad_fact.p, 0, q * 4, st));
   }
   uint32_t id = 0;
   for (size_t r = 0; r < e.rel.size(); ++r) {
@@ -1046,6 +1207,10 @@ void ingest(Engine& e) {
     } else if (e.tag_kind == TAG_TOPK) {
       e.grow(R.cand_tags, n * sizeof(TopK));
       topk_from_facts(R.raw_tags.as<float>(), R.raw_local.as<uint32_t>(), n, R.cand_tags.as<TopK>(), st);
+      ftags = R.cand_tags.p;
+    } else if (e.tag_kind == TAG_VID) {
+      e.grow(R.cand_tags, n * sizeof(VTag));
+      vtags_from_facts(R.raw_tags.as<float>(), R.raw_local.as<uint32_t>(), n, R.cand_tags.as<VTag>(), st);
       ftags = R.cand_tags.p;
     }
     e.grow(R.full.keys, U * sizeof(K) + 8);
@@ -1101,6 +1266,7 @@ void run_fixpoint(Engine& e) {
     }
   }
   e.next_id = edb;
+  e.fused_units = 0;
   e.lin_n = 0;
   e.lin_segs.clear();
   e.record = e.lineage && e.lin_budget > 0;
@@ -1149,8 +1315,8 @@ void run_fixpoint(Engine& e) {
     if (e.prog.rels[r].derived) e.stats.derived += e.rel[r].full.n;
   e.read_totals();
   check_overflow(e);
-  e.stats.candidates += e.host[S_CAND];
-  e.deferred_units = e.host[S_CAND];
+  e.stats.candidates += e.host[S_CAND] + e.fused_units;
+  e.deferred_units = e.host[S_CAND] + e.fused_units;
   e.stats.lineage_mode = !e.lineage ? 0 : e.record ? 1 : 2;
 }
 
@@ -1163,14 +1329,15 @@ size_t read_relation_t(Engine& e, int r, size_t capacity, const dl_relation_out*
   hipStream_t st = e.stream;
   const int ar = e.prog.rels[r].arity;
   const KeyLayout lay = e.layout(ar);
-  // device staging: columns + sample (u32 each), tags (f32), top-k parts
-  const size_t words = (size_t)(ar + 1) * n + n + (size_t)e.k * n * 3 + n;
+  // device staging: columns + sample (u32 each), tags (f32), fact numbers, top-k parts
+  const size_t words = (size_t)(ar + 1) * n + 2 * n + (size_t)e.k * n * 3 + n;
   e.grow(e.unpack, words * 4 + 64);
   uint32_t* base = e.unpack.as<uint32_t>();
   uint32_t* dcols[4] = {nullptr, nullptr, nullptr, nullptr};
   uint32_t* dsample = base + (size_t)ar * n;
   float* dtag = reinterpret_cast<float*>(dsample + n);
-  uint64_t* dbits = reinterpret_cast<uint64_t*>(((uintptr_t)(dtag + n) + 7) & ~(uintptr_t)7);
+  uint32_t* dfid = reinterpret_cast<uint32_t*>(dtag + n);
+  uint64_t* dbits = reinterpret_cast<uint64_t*>(((uintptr_t)(dfid + n) + 7) & ~(uintptr_t)7);
   float* dprob = reinterpret_cast<float*>(dbits + (size_t)e.k * n);
   uint8_t* dcnt = reinterpret_cast<uint8_t*>(dprob + (size_t)e.k * n);
   for (int c = 0; c < ar; ++c) dcols[c] = on_device ? out->columns[c] : (out->columns[c] ? base + (size_t)c * n : nullptr);
@@ -1180,9 +1347,12 @@ size_t read_relation_t(Engine& e, int r, size_t capacity, const dl_relation_out*
   unpack_rows<K>(R.full.keys.as<K>(), n, lay, dcols, e.batched ? samp_k : nullptr, st);
   if (!e.batched && samp) DL_HIP(hipMemsetAsync(samp, 0, n * 4, st));
   float* tg = out->tags ? (on_device ? out->tags : dtag) : nullptr;
+  uint32_t* fi = e.tag_kind == TAG_VID && out->fact_ids ? (on_device ? out->fact_ids : dfid) : nullptr;
+  if (fi) vtag_split(R.full.tags.as<VTag>(), n, nullptr, fi, st);
   if (tg) {
     if (e.tag_kind == TAG_F32) DL_HIP(hipMemcpyAsync(tg, R.full.tags.p, n * 4, hipMemcpyDeviceToDevice, st));
     else if (e.tag_kind == TAG_NONE) fill_f32(tg, n, 1.0f, st);
+    else if (e.tag_kind == TAG_VID) vtag_split(R.full.tags.as<VTag>(), n, tg, nullptr, st);
     else topk_probability(R.full.tags.as<TopK>(), e.batched ? samp_k : nullptr, n, e.qtab.as<float>(), tg, st);
   }
   uint8_t* oc = nullptr;
@@ -1204,6 +1374,7 @@ size_t read_relation_t(Engine& e, int r, size_t capacity, const dl_relation_out*
       else std::memset(out->sample_ids, 0, n * 4);
     }
     d2h(out->tags, dtag, n * 4);
+    if (fi) d2h(out->fact_ids, dfid, n * 4);
     if (e.tag_kind == TAG_TOPK) {
       d2h(out->topk_count, dcnt, n);
       d2h(out->topk_bits, dbits, (size_t)e.k * n * 8);
@@ -1324,7 +1495,11 @@ void backward_t(Engine& e, int r, const float* gout, const int64_t* rows, size_t
   hipStream_t st = e.stream;
   if (e.sr == DL_DIFF_TOPK && rows) {
     topk_backward_rows<K>(R.full.tags.as<TopK>(), R.full.keys.as<K>(), e.layout(e.prog.rels[r].arity), rows, gout,
-                          nrows, e.qtab.as<float>(), e.grad_fact.as<float>(), st);
+                          nrows, n, e.qtab.as<float>(), e.grad_fact.as<float>(), st);
+    return;
+  }
+  if (e.sr == DL_DIFF_MAXMIN) {  // the gradient of a row goes to the fact its tag comes from
+    vtag_backward(R.full.tags.as<VTag>(), rows, gout, rows ? nrows : n, n, e.grad_fact.as<float>(), st);
     return;
   }
   if (e.sr == DL_DIFF_TOPK) {
@@ -1342,7 +1517,7 @@ void backward_t(Engine& e, int r, const float* gout, const int64_t* rows, size_t
   const size_t ids = e.next_id;
   e.grow(e.adj, ids * 4 + 4);
   DL_HIP(hipMemsetAsync(e.adj.p, 0, ids * 4 + 4, st));
-  if (rows) scatter_add_rows(R.full.ids.as<uint32_t>(), rows, gout, nrows, e.adj.as<float>(), st);
+  if (rows) scatter_add_rows(R.full.ids.as<uint32_t>(), rows, gout, nrows, n, e.adj.as<float>(), st);
   else scatter_add(R.full.ids.as<uint32_t>(), gout, n, e.adj.as<float>(), st);
   if (e.record) {
     for (size_t i = e.lin_segs.size(); i-- > 0;) {

@@ -1327,6 +1327,520 @@ void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, bool 
   DL_PROF_END(6, st, words * 4.0);
 }
 
+// ------------------------------------------------------------ fused rounds
+// One launch per round (count, join and round-end compaction together) for a
+// one-plan stratum whose delta join is static-driven with the row-window
+// shape -- the head key starts with the driver's (sample, first column)
+// prefix g -- and joins the recent tuples on their first column.  All
+// derivations of the driver rows of group g land in window g of the head,
+// which therefore belongs to whichever workgroup takes g: no other workgroup
+// reads or writes it during the round.  The recent relation lives in window
+// layout (WindowRecent), written by the previous round, so a driver row's
+// matches are read straight from its recent group; the counts and offsets a
+// group needs come from those group counts (no global scan).  A group with
+// many derivations for its window's size folds them in LDS over the staged
+// window (as k_join_expand_rows); a sparse one folds them with global
+// atomics on its window without staging it.  The workgroup then writes the
+// window's new or changed tuples as the group's recent tuples for the next
+// round (in key order), makes them present and adds their count to the
+// round total, which the last workgroup appends to the round log.  Every
+// read of a round is of the previous round's recent tuples or of the group's
+// own window (Jacobi order), and two window-layout buffers alternate.
+//
+// Workgroups take batches of RW_WAVES groups from a counter; each wave sums
+// one group's derivation count, and only groups with derivations are then
+// processed by the whole workgroup.
+
+// Window of group g (first dense index, keys) of the relation of DenseArgs.
+__device__ __forceinline__ uint32_t group_window(const DenseArgs& d, uint32_t g, uint32_t* W) {
+  const uint32_t s = g >> d.dcbits, c0 = g & ((1u << d.dcbits) - 1u);
+  uint32_t n = d.dn, np = d.dnp, base = 0;
+  if (d.nsamp > 1) {
+    base = d.sbase[s];
+    n = d.sn[s];
+    np = d.snp[s];
+  }
+  uint32_t w = np;
+  for (int c = 2; c < d.dcols; ++c) w *= n;
+  *W = w;
+  return base + c0 * w;
+}
+
+bool window_round_fits(uint32_t wkeys) { return wkeys <= (uint32_t)RW_KEYS; }
+
+// Workgroups of a fused round: one per batch of RW_WAVES groups (up to
+// 16384; beyond, each takes every grid-th batch), so that the dispatcher
+// hands batches to CUs as they free up.
+unsigned window_round_grid(uint32_t ngroups) {
+  return (unsigned)std::min<size_t>(16384, ((size_t)ngroups + RW_WAVES - 1) / RW_WAVES);
+}
+
+template <typename K, int TK, int RX_ITEMS, int FM>
+__global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseArgs d, RoundArgs ra) {
+  constexpr bool FAST = FM >= 0;
+  constexpr int WAVE_MARKS = RW_KEYS / RW_WAVES;  // per-wave mark words in s_tag (>= RW_KEYS / 32)
+  __shared__ uint32_t s_tag[RW_KEYS];  // dense group: its window's tags; sparse groups: per-wave marks
+  __shared__ uint32_t s_pres[RW_KEYS / 32];
+  __shared__ uint32_t s_new[RW_KEYS / 32];
+  __shared__ uint32_t s_offs[RW_ROWS + 1];  // per chunk row: first local output slot
+  __shared__ uint32_t s_ibase[RW_ROWS];     // recent position of the row's first match minus that slot
+  __shared__ K s_dkey[RW_ROWS];
+  __shared__ float s_dtag[TK == TAG_F32 ? RW_ROWS : 1];
+  __shared__ __align__(8) uint32_t s_cpre[RW_ROWS + 1];  // 64-output chunks before each row
+  __shared__ uint32_t s_gd[RW_WAVES];  // derivations of the batch's dense groups (0: none)
+  __shared__ uint32_t s_ws[RW_WAVES];
+  __shared__ uint32_t s_sum[2];         // the workgroup's new/changed tuples and derivations
+  // rows of each wave's group as the wave phase read them (groups of at
+  // most WAVE driver rows): key, tag, recent count and recent base
+  __shared__ K s_ck[RW_WAVES][WAVE];
+  __shared__ float s_ct[RW_WAVES][TK == TAG_F32 ? WAVE : 1];
+  __shared__ uint32_t s_cc[RW_WAVES][WAVE], s_cb[RW_WAVES][WAVE];
+  static_assert(WAVE_MARKS >= RW_KEYS / 32, "a wave's marks must cover a window");
+  const K* dk = (const K*)a.dkeys;
+  const float* dt = (const float*)a.dtags;
+  const K* ik = (const K*)ra.cur.rk;
+  const float* it = ra.cur.rt;
+  const uint32_t lane = (uint32_t)lane_id();
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+  auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
+  // head columns 1..: which key holds each, at which shift (fixed per launch)
+  const int nc = FAST ? 2 : a.olay.ncols;
+  bool from_index[4];
+  uint32_t shf[4], msk[4];
+#pragma unroll
+  for (int c = 1; c < (FAST ? 2 : 4); ++c) {
+    const int s = c < nc ? a.osrc[c] : 0;
+    from_index[c] = s < 0;
+    const KeyLayout& l = s < 0 ? a.ilay : a.dlay;
+    shf[c] = (uint32_t)((l.ncols - 1 - (s < 0 ? -1 - s : s)) * l.cbits);
+    msk[c] = cmask(l.cbits);
+  }
+  // recent group of a driver row: (sample, joined column)
+  const uint32_t jshift = (uint32_t)((a.dlay.ncols - 1 - a.jsrc[0]) * a.dlay.cbits), jmask = cmask(a.dlay.cbits);
+  auto recent_group = [&](K dkey) -> uint32_t {
+    const uint32_t y = (uint32_t)((uint64_t)dkey >> jshift) & jmask;
+    return a.dlay.sbits ? (key_sample(dkey, a.dlay) << d.dcbits) | y : y;
+  };
+  const int mode = FAST ? FM : d.mode;
+  const uint32_t zero = dense_init_word_dev(mode);
+  // offset of a derivation's head key in its window (the head key's columns
+  // after the first, in the window's mixed radix)
+  auto head_loc = [&](K dkey, K ikey) -> uint32_t {
+    if constexpr (FAST) {
+      return (uint32_t)((uint64_t)ikey >> shf[1]) & msk[1];
+    } else {
+      const uint32_t s = key_sample(dkey, a.dlay);
+      const uint32_t gn = d.nsamp > 1 ? d.sn[s] : d.dn, gnp = d.nsamp > 1 ? d.snp[s] : d.dnp;
+      uint32_t loc = 0;
+#pragma unroll
+      for (int c = 1; c < 4; ++c)
+        if (c < nc)
+          loc = loc * (c + 1 < nc ? gn : gnp) + ((uint32_t)((uint64_t)(from_index[c] ? ikey : dkey) >> shf[c]) & msk[c]);
+      return loc;
+    }
+  };
+  // the derivation's tag: the product of the body tags in body order
+  auto product = [&](float x, float y) -> float {
+    const float p = a.index_first ? y : x, r = a.index_first ? x : y;
+    if constexpr (FAST) return FM == DENSE_ADD ? __fmul_rn(p, r) : FM == DENSE_MAX ? fminf(p, r) : __fadd_rn(p, r);
+    else return f_otimes(a.sr, p, r);
+  };
+  // One derivation folded into its window: `tw` the key's tag word and
+  // `pres` its presence (LDS in a staged window, global memory otherwise);
+  // true when it makes the key present or improves its tag.
+  auto fold_word = [&](uint32_t* tw, bool pres, float t) -> bool {
+    if (mode == DENSE_ADD) {
+      if (!pres) atomicAdd(reinterpret_cast<float*>(tw), t);
+      return !pres;
+    }
+    const uint32_t o = to_ordered(t), cur = *tw;
+    if (mode == DENSE_MAX) {
+      if (o > cur) {
+        atomicMax(tw, o);
+        return true;
+      }
+      return o <= zero && !pres;  // does not beat the zero: new only if absent
+    }
+    if (o < cur) {
+      atomicMin(tw, o);
+      return true;
+    }
+    return o >= zero && !pres;
+  };
+  // A window's marked keys become group g's recent tuples of the next round
+  // (in key order): emitted by one wave over words [w0, w1) of `marks`
+  // (64 at a time, coalesced writes) starting at slot `base`; returns the
+  // number emitted.  Tags come from the staged window (`win`) or from the
+  // dense tag words; frozen sums are clamped.
+  auto emit = [&](uint32_t g, uint32_t kb, const uint32_t* marks, uint32_t w0, uint32_t w1, uint32_t base,
+                  bool win) -> uint32_t {
+    K* nk = reinterpret_cast<K*>(ra.next.rk) + kb;
+    float* nt = ra.next.rt ? ra.next.rt + kb : nullptr;
+    const uint32_t c0 = g & ((1u << d.dcbits) - 1u);
+    const size_t wb = kb >> 5;
+    uint32_t run = base;
+    for (uint32_t q0 = w0; q0 < w1; q0 += WAVE) {  // uniform
+      const uint32_t wi = q0 + lane;
+      const uint32_t xw = wi < w1 ? marks[wi] : 0u;
+      if (xw) d.present[wb + wi] |= xw;
+      run += wave_expand_bits(xw, wb + q0, run, 0ull, [&](uint32_t slot, uint64_t kk, uint64_t, uint32_t) {
+        const uint32_t loc = (uint32_t)kk - kb;
+        if constexpr (FAST) nk[slot] = (K)(((uint64_t)c0 << a.olay.cbits) | loc);
+        else nk[slot] = dense_key<K>(d, (uint32_t)kk);
+        if constexpr (TK == TAG_F32) {
+          const uint32_t v = win ? s_tag[loc] : __hip_atomic_load(d.dtag + kk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          float t;
+          if (mode == DENSE_ADD) {
+            t = fminf(1.0f, __uint_as_float(v));  // the frozen tag: the clamped sum of the round
+            if (!win) d.dtag[kk] = __float_as_uint(t);
+          } else {
+            t = from_ordered(v);
+          }
+          nt[slot] = t;
+        }
+      });
+    }
+    return run - base;
+  };
+
+  if (threadIdx.x < 2) s_sum[threadIdx.x] = 0u;
+  // batches of RW_WAVES groups, every gridDim.x-th to this workgroup (no
+  // shared counter: same-address atomics from every CU serialise)
+  for (uint32_t g0 = blockIdx.x * RW_WAVES; g0 < ra.ngroups; g0 += gridDim.x * RW_WAVES) {
+    __syncthreads();  // s_gd and the wave marks of the previous batch are no longer read
+    {
+      // Wave phase: wave wv takes group g0 + wv.  It counts the group's
+      // derivations; a sparse group is done by the wave alone (global
+      // atomics on its window, marks in the wave's LDS words, emission), a
+      // dense one is left for the whole workgroup.
+      const uint32_t g = g0 + wv;
+      uint32_t D = 0, r0 = 0, r1 = 0;
+      // the lane's row (the first WAVE rows of the group): key, tag,
+      // recent group count and base, kept for the folds below
+      K rkey = 0;
+      float rtag = 0.0f;
+      uint32_t rcnt = 0, rbase = 0;
+      if (g < ra.ngroups) {
+        r0 = uni(ra.goff[g]);
+        r1 = uni(ra.goff[g + 1]);
+        if (r0 + lane < r1) {
+          rkey = dk[r0 + lane];
+          if constexpr (TK == TAG_F32) rtag = dt[r0 + lane];
+          const uint32_t gy = recent_group(rkey);
+          uint32_t wy;
+          rcnt = ra.cur.rc[gy];
+          rbase = group_window(d, gy, &wy);
+        }
+        D = rcnt;
+        for (uint32_t r = r0 + WAVE + lane; r < r1; r += WAVE) D += ra.cur.rc[recent_group(dk[r])];
+        D = uni(wave_sum(D));
+      }
+      uint32_t dense = 0;
+      if (g < ra.ngroups && D == 0) {
+        if (lane == 0) ra.next.rc[g] = 0u;
+      } else if (g < ra.ngroups) {
+        uint32_t W;
+        const uint32_t kb = group_window(d, g, &W);
+        if (ra.win_per_key != ~0u && (uint64_t)D * ra.win_per_key >= W) {
+          dense = D;
+          s_ck[wv][lane] = rkey;  // the workgroup phase takes the rows from here
+          if constexpr (TK == TAG_F32) s_ct[wv][lane] = rtag;
+          s_cc[wv][lane] = rcnt;
+          s_cb[wv][lane] = rbase;
+        } else {
+          uint32_t* marks = s_tag + wv * WAVE_MARKS;
+          const uint32_t NWD = W / 32;
+          const size_t wb = kb >> 5;
+          for (uint32_t i = lane; i < NWD; i += WAVE) marks[i] = 0u;
+          for (uint32_t r = r0; r < r1; ++r) {  // uniform: one driver row at a time
+            K dkey;
+            float x = 0.0f;
+            uint32_t cnt, base;
+            if (r - r0 < (uint32_t)WAVE) {  // read by the wave phase: a shuffle away
+              const int src = (int)(r - r0);
+              if constexpr (sizeof(K) == 8)
+                dkey = ((K)uni(__shfl((uint32_t)(rkey >> 32), src, WAVE)) << 32) | (K)uni(__shfl((uint32_t)rkey, src, WAVE));
+              else
+                dkey = (K)uni(__shfl((uint32_t)rkey, src, WAVE));
+              if constexpr (TK == TAG_F32) x = __shfl(rtag, src, WAVE);
+              cnt = uni(__shfl(rcnt, src, WAVE));
+              base = uni(__shfl(rbase, src, WAVE));
+            } else {
+              dkey = dk[r];
+              if constexpr (TK == TAG_F32) x = dt[r];
+              const uint32_t gy = recent_group(dkey);
+              uint32_t wy;
+              cnt = uni(ra.cur.rc[gy]);
+              base = group_window(d, gy, &wy);
+            }
+            for (uint32_t i = lane; i < cnt; i += WAVE) {
+              const K ikey = ik[base + i];
+              const uint32_t loc = head_loc(dkey, ikey);
+              if (loc >= W) {  // the host only picks this kernel when every key lies in its window
+                if (d.overflow) *d.overflow = 2;
+                continue;
+              }
+              const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
+              const bool pres = (d.present[wb + wi] & bit) != 0u;
+              bool mark;
+              if constexpr (TK == TAG_F32) mark = fold_word(d.dtag + kb + loc, pres, product(x, it[base + i]));
+              else mark = !pres;
+              if (mark) atomicOr(marks + wi, bit);
+            }
+          }
+          const uint32_t total = emit(g, kb, marks, 0, NWD, 0, false);
+          if (lane == 0) {
+            ra.next.rc[g] = total;
+            atomicAdd(s_sum, total);
+            atomicAdd(s_sum + 1, D);
+          }
+        }
+      }
+      if (lane == 0) s_gd[wv] = dense;
+    }
+    __syncthreads();
+    // Workgroup phase: the batch's dense groups, one at a time, folded in
+    // LDS over the staged window.
+    for (uint32_t w = 0; w < (uint32_t)RW_WAVES; ++w) {
+      const uint32_t D = s_gd[w];
+      if (!D) continue;  // uniform
+      const uint32_t g = g0 + w;
+      uint32_t W;
+      const uint32_t kb = group_window(d, g, &W);
+      const uint32_t NWD = W / 32;
+      const size_t wb = kb >> 5;
+      for (uint32_t i = threadIdx.x; i < NWD; i += RW_BLOCK) {
+        s_new[i] = 0u;
+        s_pres[i] = d.present[wb + i];
+      }
+      if constexpr (TK == TAG_F32) {  // 16-byte loads (a window is W-aligned, W a multiple of 32)
+        const uint4* src = reinterpret_cast<const uint4*>(d.dtag + kb);
+        uint4* dst = reinterpret_cast<uint4*>(s_tag);
+#pragma unroll 4
+        for (uint32_t i = threadIdx.x; i < W / 4; i += RW_BLOCK) dst[i] = src[i];
+      }
+      const uint32_t r0 = uni(ra.goff[g]), r1 = uni(ra.goff[g + 1]);
+      for (uint32_t q0 = r0; q0 < r1; q0 += RW_ROWS) {  // uniform
+        const uint32_t nr = r1 - q0 < (uint32_t)RW_ROWS ? r1 - q0 : (uint32_t)RW_ROWS;
+        __syncthreads();  // the window is staged; the previous chunk's rows are no longer read
+        if (threadIdx.x < WAVE) {
+          // the chunk's rows (4 per lane): recent group counts, their local
+          // output offsets and 64-output chunk counts, scanned by one wave;
+          // a group of at most WAVE rows comes from the wave phase's copy
+          uint32_t cnt[4], base[4], sum = 0, csum = 0;
+          const bool cached = r1 - r0 <= (uint32_t)WAVE;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t i = lane * 4 + k;
+            cnt[k] = base[k] = 0;
+            if (i < nr) {
+              K key;
+              if (cached) {
+                key = s_ck[w][i];
+                cnt[k] = s_cc[w][i];
+                base[k] = s_cb[w][i];
+                if constexpr (TK == TAG_F32) s_dtag[i] = s_ct[w][i];
+              } else {
+                key = dk[q0 + i];
+                const uint32_t gy = recent_group(key);
+                uint32_t wy;
+                cnt[k] = ra.cur.rc[gy];
+                base[k] = group_window(d, gy, &wy);
+                if constexpr (TK == TAG_F32) s_dtag[i] = dt[q0 + i];
+              }
+              s_dkey[i] = key;
+            }
+            sum += cnt[k];
+            csum += (cnt[k] + WAVE - 1) / WAVE;
+          }
+          uint32_t run = wave_inclusive_scan(sum) - sum, crun = wave_inclusive_scan(csum) - csum;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t i = lane * 4 + k;
+            if (i <= nr) {
+              s_offs[i] = run;
+              s_cpre[i] = crun;
+            }
+            if (i < nr) s_ibase[i] = base[k] - run;
+            run += cnt[k];
+            crun += (cnt[k] + WAVE - 1) / WAVE;
+          }
+        }
+        __syncthreads();
+        // every wave takes a contiguous range of 64-output chunks and walks
+        // the rows along it (row state uniform per wave)
+        const uint32_t nch = uni(s_cpre[nr]);
+        const uint32_t per = (nch + RW_WAVES - 1) / RW_WAVES;
+        uint32_t c = wv * per;
+        const uint32_t ce = c + per < nch ? c + per : nch;
+        uint32_t lo = 0;
+        if (c < ce) {  // the row of chunk c: s_cpre[lo] <= c < s_cpre[lo + 1]
+          uint32_t hi = nr;
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (uni(s_cpre[mid]) <= c) lo = mid;
+            else hi = mid;
+          }
+        }
+        for (; c < ce; c += RX_ITEMS) {  // uniform per wave
+          bool act[RX_ITEMS];
+          uint32_t irow[RX_ITEMS];
+          K dkey[RX_ITEMS], ikey[RX_ITEMS];
+          float x[RX_ITEMS], y[RX_ITEMS];
+#pragma unroll
+          for (int q = 0; q < RX_ITEMS; ++q) {
+            const uint32_t cq = c + (uint32_t)q;
+            if (cq < ce)
+              while (uni(s_cpre[lo + 1]) <= cq) ++lo;  // empty rows own no chunk
+            const uint32_t j = uni(s_offs[lo]) + (cq - uni(s_cpre[lo])) * WAVE + lane;
+            act[q] = cq < ce && j < uni(s_offs[lo + 1]);
+            if constexpr (sizeof(K) == 8)
+              dkey[q] = ((K)uni((uint32_t)(s_dkey[lo] >> 32)) << 32) | (K)uni((uint32_t)s_dkey[lo]);
+            else
+              dkey[q] = (K)uni((uint32_t)s_dkey[lo]);
+            irow[q] = uni(s_ibase[lo]) + j;
+            x[q] = 0.0f;
+            if constexpr (TK == TAG_F32) x[q] = __uint_as_float(uni(__float_as_uint(s_dtag[lo])));
+          }
+#pragma unroll
+          for (int q = 0; q < RX_ITEMS; ++q) {
+            ikey[q] = act[q] ? ik[irow[q]] : (K)0;
+            y[q] = 0.0f;
+            if constexpr (TK == TAG_F32) y[q] = act[q] ? it[irow[q]] : 0.0f;
+          }
+#pragma unroll
+          for (int q = 0; q < RX_ITEMS; ++q) {
+            if (!act[q]) continue;
+            const uint32_t loc = head_loc(dkey[q], ikey[q]);
+            if (loc >= W) {
+              if (d.overflow) *d.overflow = 2;
+              continue;
+            }
+            const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
+            const bool pres = (s_pres[wi] & bit) != 0u;
+            bool mark;
+            if constexpr (TK == TAG_F32) mark = fold_word(s_tag + loc, pres, product(x[q], y[q]));
+            else mark = !pres;
+            if (mark) atomicOr(s_new + wi, bit);
+          }
+        }
+      }
+      __syncthreads();
+      // the window's marked keys: per-wave word counts -> slots, emission
+      // by every wave over its 64 words, tags written back where changed
+      const uint32_t xw = threadIdx.x < NWD ? s_new[threadIdx.x] : 0u;
+      const uint32_t incl = wave_inclusive_scan((uint32_t)__popc(xw));
+      if (lane == WAVE - 1) s_ws[wv] = incl;
+      __syncthreads();
+      uint32_t before = 0, total = 0;
+#pragma unroll
+      for (int i = 0; i < RW_WAVES; ++i) {
+        const uint32_t t = s_ws[i];
+        before += (uint32_t)i < wv ? t : 0u;
+        total += t;
+      }
+      if (wv * WAVE < NWD) (void)emit(g, kb, s_new, wv * WAVE, min(wv * WAVE + WAVE, NWD), before, true);
+      if constexpr (TK == TAG_F32) {
+        // write the window back four keys at a time where any changed (an
+        // unchanged key gets the value it had: nothing else writes it);
+        // frozen sums are clamped here
+        uint4* dst = reinterpret_cast<uint4*>(d.dtag + kb);
+        const uint4* src = reinterpret_cast<const uint4*>(s_tag);
+        for (uint32_t i = threadIdx.x; i < W / 4; i += RW_BLOCK) {
+          const uint32_t nb = (s_new[i >> 3] >> ((i & 7) * 4)) & 0xfu;
+          if (!nb) continue;
+          uint4 v = src[i];
+          if (mode == DENSE_ADD) {
+            if (nb & 1u) v.x = __float_as_uint(fminf(1.0f, __uint_as_float(v.x)));
+            if (nb & 2u) v.y = __float_as_uint(fminf(1.0f, __uint_as_float(v.y)));
+            if (nb & 4u) v.z = __float_as_uint(fminf(1.0f, __uint_as_float(v.z)));
+            if (nb & 8u) v.w = __float_as_uint(fminf(1.0f, __uint_as_float(v.w)));
+          }
+          dst[i] = v;
+        }
+      }
+      if (threadIdx.x == 0) {
+        ra.next.rc[g] = total;
+        atomicAdd(s_sum, total);
+        atomicAdd(s_sum + 1, D);
+      }
+      __syncthreads();  // the window's LDS is reused by the next group
+    }
+  }
+  // the workgroup's counts of the round (the host adds them up)
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ra.part[2 * blockIdx.x] = s_sum[0];
+    ra.part[2 * blockIdx.x + 1] = s_sum[1];
+  }
+}
+
+template <typename K>
+void window_round(const JoinArgs& a, int tk, const DenseArgs& d, const RoundArgs& ra, hipStream_t st) {
+  const unsigned nb = window_round_grid(ra.ngroups);
+  int fm = -1;
+  if (sizeof(K) == 4 && d.nsamp <= 1 && a.olay.ncols == 2 && a.osrc[0] >= 0 && a.osrc[1] < 0) {
+    if (tk == TAG_NONE && d.mode == DENSE_BOOL) fm = DENSE_BOOL;
+    else if (tk == TAG_F32 && d.mode == DENSE_ADD && (a.sr == SR_ADDMULT || a.sr == SR_DIFF_ADDMULT)) fm = DENSE_ADD;
+    else if (tk == TAG_F32 && d.mode == DENSE_MAX && a.sr == SR_MAXMIN) fm = DENSE_MAX;
+    else if (tk == TAG_F32 && d.mode == DENSE_MIN && a.sr == SR_MINPLUS) fm = DENSE_MIN;
+  }
+  const int items = a.items >= 4 ? 4 : a.items >= 2 ? 2 : 1;
+#define DL_WR(TK, IT, FM) k_window_round<K, TK, IT, FM><<<nb, RW_BLOCK, 0, st>>>(a, d, ra)
+#define DL_WR_ITEMS(TK, FM)               \
+  if (items == 1) DL_WR(TK, 1, FM);       \
+  else if (items == 2) DL_WR(TK, 2, FM);  \
+  else DL_WR(TK, 4, FM);
+  DL_PROF_BEGIN(1, st);
+  if (tk == TAG_F32) {
+    if constexpr (sizeof(K) == 4) {
+      if (fm == DENSE_MAX) { DL_WR_ITEMS(TAG_F32, DENSE_MAX) }
+      else if (fm == DENSE_MIN) { DL_WR_ITEMS(TAG_F32, DENSE_MIN) }
+      else if (fm == DENSE_ADD) { DL_WR_ITEMS(TAG_F32, DENSE_ADD) }
+      else { DL_WR_ITEMS(TAG_F32, -1) }
+    } else {
+      DL_WR_ITEMS(TAG_F32, -1)
+    }
+  } else {
+    if constexpr (sizeof(K) == 4) {
+      if (fm == DENSE_BOOL) { DL_WR_ITEMS(TAG_NONE, DENSE_BOOL) }
+      else { DL_WR_ITEMS(TAG_NONE, -1) }
+    } else {
+      DL_WR_ITEMS(TAG_NONE, -1)
+    }
+  }
+#undef DL_WR_ITEMS
+#undef DL_WR
+  // algorithmic bytes: every driver row read once (key + tag), every
+  // derivation once (its recent row's key + tag; counted on the device)
+  const double per = sizeof(K) + (tk == TAG_F32 ? 4.0 : 0.0);
+  DL_PROF_END(1, st, a.n * per);
+  DL_PROF_DEFER(1, per);
+}
+
+// Window layout of a sorted relation: group g's rows (off[g] .. off[g+1])
+// go to its window's first dense indexes; every group's count is written.
+template <typename K>
+__global__ void k_to_windows(const K* __restrict__ keys, const float* __restrict__ tags, size_t n,
+                             const uint32_t* __restrict__ off, uint32_t ngroups, DenseArgs d, WindowRecent w) {
+  GRID_STRIDE(i, (size_t)ngroups) w.rc[i] = off[i + 1] - off[i];
+  const int shift = (d.dcols - 1) * d.dcbits;
+  GRID_STRIDE(i, n) {
+    const K k = keys[i];
+    const uint32_t g = (uint32_t)((uint64_t)k >> shift);  // (sample, first column)
+    uint32_t W;
+    const uint32_t dst = group_window(d, g, &W) + (uint32_t)i - off[g];
+    reinterpret_cast<K*>(w.rk)[dst] = k;
+    if (tags) w.rt[dst] = tags[i];
+  }
+}
+
+template <typename K>
+void to_windows(const K* keys, const float* tags, size_t n, const uint32_t* off, uint32_t ngroups,
+                const DenseArgs& d, WindowRecent w, hipStream_t st) {
+  k_to_windows<K><<<grid_for(std::max<size_t>(n, ngroups)), BLOCK, 0, st>>>(keys, tags, n, off, ngroups, d, w);
+}
+
 #define INST(K)                                                                                                       \
   template void join_expand_dense<K>(const JoinArgs&, int, const uint32_t*, size_t, const uint64_t*, size_t,     \
                                      const DenseArgs&, bool, hipStream_t, const RowWindows*);                                                \
@@ -1335,7 +1849,10 @@ void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, bool 
                                   hipStream_t, uint64_t*, bool, const DenseCsr*, uint64_t*);                                \
   template void segments_lineage<K>(const DenseArgs&, const uint32_t*, size_t, uint32_t*, uint32_t*, uint32_t*,            \
                                     hipStream_t);                                                                          \
-  template void bitmap_keys<K>(const DenseArgs&, size_t, const uint32_t*, bool, K*, float*, uint32_t*, hipStream_t);
+  template void bitmap_keys<K>(const DenseArgs&, size_t, const uint32_t*, bool, K*, float*, uint32_t*, hipStream_t); \
+  template void window_round<K>(const JoinArgs&, int, const DenseArgs&, const RoundArgs&, hipStream_t);               \
+  template void to_windows<K>(const K*, const float*, size_t, const uint32_t*, uint32_t, const DenseArgs&,             \
+                              WindowRecent, hipStream_t);
 
 INST(uint32_t)
 INST(uint64_t)

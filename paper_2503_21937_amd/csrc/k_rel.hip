@@ -289,7 +289,7 @@ void join_expand(const JoinArgs& a, int tk, const uint32_t* offs, size_t total, 
   if (!total) return;
   const int items = a.items == 1 || a.items == 2 || a.items == 8 ? a.items : 4;
   const size_t nb = (total + (size_t)BLOCK * items - 1) / ((size_t)BLOCK * items);
-  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : (double)sizeof(TopK);
+  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : tk == TAG_VID ? 8.0 : (double)sizeof(TopK);
   // algorithmic bytes of a join: probe rows read once (key + tag), every
   // derivation once (key + tag, plus its two lineage ids when recorded)
   const double bytes = total * (sizeof(K) + tb + (ol ? 8.0 : 0.0)) + a.n * (sizeof(K) + tb);
@@ -298,6 +298,8 @@ void join_expand(const JoinArgs& a, int tk, const uint32_t* offs, size_t total, 
     k_join_expand<K, TAG_NONE, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (NoTag*)otags, ol, orr);  \
   else if (tk == TAG_F32)                                                                                      \
     k_join_expand<K, TAG_F32, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (float*)otags, ol, orr);   \
+  else if (tk == TAG_VID)                                                                                      \
+    k_join_expand<K, TAG_VID, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (VTag*)otags, ol, orr);    \
   else                                                                                                         \
     k_join_expand<K, TAG_TOPK, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (TopK*)otags, ol, orr);
   DL_PROF_BEGIN(1, st);
@@ -337,6 +339,8 @@ void project_rows(const JoinArgs& a, int tk, void* okeys, void* otags, uint32_t*
     k_project<K, TAG_NONE><<<grid_for(a.n), BLOCK, 0, st>>>(a, (K*)okeys, (NoTag*)otags, ol, orr);
   else if (tk == TAG_F32)
     k_project<K, TAG_F32><<<grid_for(a.n), BLOCK, 0, st>>>(a, (K*)okeys, (float*)otags, ol, orr);
+  else if (tk == TAG_VID)
+    k_project<K, TAG_VID><<<grid_for(a.n), BLOCK, 0, st>>>(a, (K*)okeys, (VTag*)otags, ol, orr);
   else
     k_project<K, TAG_TOPK><<<grid_for(a.n), BLOCK, 0, st>>>(a, (K*)okeys, (TopK*)otags, ol, orr);
 }
@@ -370,6 +374,7 @@ __global__ void k_segment_reduce(const K* __restrict__ keys, const uint32_t* __r
       for (size_t j = i + 1; j < n && !flags[j]; ++j) {
         T x = tags[perm ? perm[j] : j];
         if constexpr (TK == TAG_F32) acc = f_oplus(sr, acc, x);
+        else if constexpr (TK == TAG_VID) acc = vtag_pick(acc, x, true);
         else acc = topk_oplus(acc, x, k);
       }
       tout[s] = acc;
@@ -381,7 +386,7 @@ template <typename K>
 void segment_reduce(const K* keys, const uint32_t* pos, const uint32_t* flags, size_t n, int tk, int sr, int k,
                     const void* tags, const uint32_t* perm, K* kout, void* tout, size_t nout, hipStream_t st) {
   if (!n) return;
-  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : (double)sizeof(TopK);
+  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : tk == TAG_VID ? 8.0 : (double)sizeof(TopK);
   DL_PROF_BEGIN(5, st);
   if (tk == TAG_NONE)
     k_segment_reduce<K, TAG_NONE><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const NoTag*)tags, perm,
@@ -389,6 +394,9 @@ void segment_reduce(const K* keys, const uint32_t* pos, const uint32_t* flags, s
   else if (tk == TAG_F32)
     k_segment_reduce<K, TAG_F32><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const float*)tags, perm,
                                                                 kout, (float*)tout);
+  else if (tk == TAG_VID)
+    k_segment_reduce<K, TAG_VID><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const VTag*)tags, perm,
+                                                                kout, (VTag*)tout);
   else
     k_segment_reduce<K, TAG_TOPK><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const TopK*)tags, perm,
                                                                  kout, (TopK*)tout);
@@ -456,6 +464,9 @@ __global__ __launch_bounds__(BLOCK) void k_diff(const K* __restrict__ uk, typena
         if constexpr (TK == TAG_F32) {
           nw = f_oplus(sr, old, ut[i]);
           if (__float_as_uint(nw) != __float_as_uint(old)) s = 2u;
+        } else if constexpr (TK == TAG_VID) {
+          nw = vtag_pick(old, ut[i], true);
+          if (__float_as_uint(nw.v) != __float_as_uint(old.v) || nw.f != old.f) s = 2u;
         } else {
           nw = topk_oplus(old, ut[i], k);
           if (!topk_same(nw, old)) s = 2u;
@@ -475,12 +486,14 @@ void diff_merge(const K* uk, const void* ut, size_t nu, const K* fk, void* ft, s
                 bool converge, uint32_t* status, uint32_t* fpos, hipStream_t st) {
   if (!nu) return;
   size_t nb = (nu + DIFF_TILE - 1) / DIFF_TILE;
-  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : (double)sizeof(TopK);
+  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : tk == TAG_VID ? 8.0 : (double)sizeof(TopK);
   DL_PROF_BEGIN(6, st);
   if (tk == TAG_NONE)
     k_diff<K, TAG_NONE><<<nb, BLOCK, 0, st>>>(uk, (NoTag*)ut, nu, fk, (NoTag*)ft, nf, sr, k, converge, status, fpos);
   else if (tk == TAG_F32)
     k_diff<K, TAG_F32><<<nb, BLOCK, 0, st>>>(uk, (float*)ut, nu, fk, (float*)ft, nf, sr, k, converge, status, fpos);
+  else if (tk == TAG_VID)
+    k_diff<K, TAG_VID><<<nb, BLOCK, 0, st>>>(uk, (VTag*)ut, nu, fk, (VTag*)ft, nf, sr, k, converge, status, fpos);
   else
     k_diff<K, TAG_TOPK><<<nb, BLOCK, 0, st>>>(uk, (TopK*)ut, nu, fk, (TopK*)ft, nf, sr, k, converge, status, fpos);
   DL_PROF_END(6, st, nu * (sizeof(K) + tb + 4.0) + (double)nf * sizeof(K));
@@ -567,6 +580,8 @@ __global__ __launch_bounds__(BLOCK) void k_merge(const K* __restrict__ ak, const
     if (oid) oid[o] = fromA ? aid[g] : bid[g];
     if (tag_bytes == 4) {
       reinterpret_cast<uint32_t*>(ot)[o] = reinterpret_cast<const uint32_t*>(fromA ? at : bt)[g];
+    } else if (tag_bytes == 8) {
+      reinterpret_cast<uint64_t*>(ot)[o] = reinterpret_cast<const uint64_t*>(fromA ? at : bt)[g];
     } else if (tag_bytes == (int)sizeof(TopK)) {
       reinterpret_cast<TopK*>(ot)[o] = reinterpret_cast<const TopK*>(fromA ? at : bt)[g];
     }
@@ -804,6 +819,7 @@ __global__ void k_lookup(const K* __restrict__ keys, size_t n, QCols qc, size_t 
       float t = 0.0f;
       if (found) {
         if (tk == TAG_F32) t = ((const float*)tags)[lo];
+        else if (tk == TAG_VID) t = ((const VTag*)tags)[lo].v;
         else if (tk == TAG_NONE) t = 1.0f;
         else t = (float)incl_excl(((const TopK*)tags)[lo], qtab + (size_t)key_sample(q, lay) * 64, -1, nullptr);
       }
@@ -856,23 +872,24 @@ template void match_owner<uint64_t>(const uint64_t*, size_t, const uint64_t*, co
                                     uint32_t, uint32_t*, hipStream_t);
 
 __global__ void k_scatter_add_rows(const uint32_t* __restrict__ ids, const int64_t* __restrict__ rows,
-                                   const float* __restrict__ g, size_t n, float* adj) {
+                                   const float* __restrict__ g, size_t n, size_t nrel, float* adj) {
   GRID_STRIDE(i, n) {
-    if (rows[i] >= 0) atomicAdd(&adj[ids[rows[i]]], g[i]);
+    if (rows[i] >= 0 && (uint64_t)rows[i] < nrel) atomicAdd(&adj[ids[rows[i]]], g[i]);
   }
 }
 
-void scatter_add_rows(const uint32_t* ids, const int64_t* rows, const float* g, size_t n, float* adj, hipStream_t st) {
-  if (n) k_scatter_add_rows<<<grid_for(n), BLOCK, 0, st>>>(ids, rows, g, n, adj);
+void scatter_add_rows(const uint32_t* ids, const int64_t* rows, const float* g, size_t n, size_t nrel, float* adj,
+                      hipStream_t st) {
+  if (n) k_scatter_add_rows<<<grid_for(n), BLOCK, 0, st>>>(ids, rows, g, n, nrel, adj);
 }
 
 template <typename K>
 __global__ void k_topk_backward_rows(const TopK* __restrict__ t, const K* __restrict__ keys, KeyLayout lay,
                                      const int64_t* __restrict__ rows, const float* __restrict__ gout, size_t n,
-                                     const float* __restrict__ qtab, float* grad) {
+                                     size_t nrel, const float* __restrict__ qtab, float* grad) {
   GRID_STRIDE(i, n) {
     const float g = gout[i];
-    if (g == 0.0f || rows[i] < 0) continue;
+    if (g == 0.0f || rows[i] < 0 || (uint64_t)rows[i] >= nrel) continue;
     const size_t r = (size_t)rows[i];
     const TopK x = t[r];
     const uint32_t s = key_sample(keys[r], lay);
@@ -891,8 +908,48 @@ __global__ void k_topk_backward_rows(const TopK* __restrict__ t, const K* __rest
 
 template <typename K>
 void topk_backward_rows(const TopK* t, const K* keys, KeyLayout lay, const int64_t* rows, const float* g, size_t n,
-                        const float* qtab, float* grad_fact, hipStream_t st) {
-  if (n) k_topk_backward_rows<K><<<grid_for(n), BLOCK, 0, st>>>(t, keys, lay, rows, g, n, qtab, grad_fact);
+                        size_t nrel, const float* qtab, float* grad_fact, hipStream_t st) {
+  if (n) k_topk_backward_rows<K><<<grid_for(n), BLOCK, 0, st>>>(t, keys, lay, rows, g, n, nrel, qtab, grad_fact);
+}
+
+// -------------------------------------------------- differentiable max-min
+// Input facts' tags: (probability, fact number).
+__global__ void k_vtags_from_facts(const float* __restrict__ q, const uint32_t* __restrict__ fid, size_t n,
+                                   VTag* __restrict__ out) {
+  GRID_STRIDE(i, n) out[i] = VTag{q[i], fid[i]};
+}
+void vtags_from_facts(const float* q, const uint32_t* fid, size_t n, VTag* out, hipStream_t st) {
+  if (n) k_vtags_from_facts<<<grid_for(n), BLOCK, 0, st>>>(q, fid, n, out);
+}
+
+// The values and the fact numbers of n tags (either output may be NULL).
+__global__ void k_vtag_split(const VTag* __restrict__ t, size_t n, float* __restrict__ v, uint32_t* __restrict__ f) {
+  GRID_STRIDE(i, n) {
+    const VTag x = t[i];
+    if (v) v[i] = x.v;
+    if (f) f[i] = x.f;
+  }
+}
+void vtag_split(const VTag* t, size_t n, float* v, uint32_t* f, hipStream_t st) {
+  if (n && (v || f)) k_vtag_split<<<grid_for(n), BLOCK, 0, st>>>(t, n, v, f);
+}
+
+// Reverse mode: a tag equals the probability of its fact, so the gradient
+// of row i (rows[i] when given, else i; rows outside [0, nrel) are skipped)
+// goes to that fact.
+__global__ void k_vtag_backward(const VTag* __restrict__ t, const int64_t* __restrict__ rows,
+                                const float* __restrict__ g, size_t n, size_t nrel, float* __restrict__ grad_fact) {
+  GRID_STRIDE(i, n) {
+    const int64_t r = rows ? rows[i] : (int64_t)i;
+    if (r >= 0 && (uint64_t)r < nrel) atomicAdd(grad_fact + t[r].f, g[i]);
+  }
+}
+void vtag_backward(const VTag* t, const int64_t* rows, const float* g, size_t n, size_t nrel, float* grad_fact,
+                   hipStream_t st) {
+  if (!n) return;
+  DL_PROF_BEGIN(10, st);
+  k_vtag_backward<<<grid_for(n), BLOCK, 0, st>>>(t, rows, g, n, nrel, grad_fact);
+  DL_PROF_END(10, st, n * 16.0);
 }
 
 // ------------------------------------------------------- instantiations
@@ -919,6 +976,7 @@ void topk_backward_rows(const TopK* t, const K* keys, KeyLayout lay, const int64
   template void lookup_rows<K>(const K*, size_t, const uint32_t* const*, const uint32_t*, size_t, int,           \
                                const void*, KeyLayout, const float*, int64_t*, float*, hipStream_t);                                                    \
   template void topk_backward_rows<K>(const TopK*, const K*, KeyLayout, const int64_t*, const float*, size_t,     \
+                                      size_t,                                                                      \
                                       const float*, float*, hipStream_t);
 
 INST(uint32_t)

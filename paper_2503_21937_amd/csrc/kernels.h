@@ -65,7 +65,7 @@ template <typename K>
 void csr_build_dn(const K* keys, const uint64_t* dn, int total_bits, int prefix_bits, uint32_t* off, hipStream_t st);
 
 // Tag payload kinds of the relational kernels.
-enum TagKind : int { TAG_NONE = 0, TAG_F32 = 1, TAG_TOPK = 2 };
+enum TagKind : int { TAG_NONE = 0, TAG_F32 = 1, TAG_TOPK = 2, TAG_VID = 3 };  // TAG_VID: VTag (value, fact)
 
 // Expression evaluation at a plan's output (Sec. 5: a bytecode program for a
 // small stack machine run by each thread on one output row; Sec. 3.3
@@ -117,6 +117,15 @@ struct JoinArgs {
   uint32_t* keep;    // sort path with evaluation: per output row, 1 if it survives (else NULL)
   uint64_t* err;     // evaluation errors: a computed value outside the ids in use sets 4
 };
+
+// Differentiable max-min tags (VTag: value, fact): from the input facts'
+// probabilities and numbers, their values, and the reverse pass (the gradient
+// of row rows[i] -- or i -- goes to the row's fact).
+struct VTag;
+void vtags_from_facts(const float* q, const uint32_t* fid, size_t n, VTag* out, hipStream_t st);
+void vtag_split(const VTag* t, size_t n, float* v, uint32_t* f, hipStream_t st);
+void vtag_backward(const VTag* t, const int64_t* rows, const float* g, size_t n, size_t nrel, float* grad_fact,
+                   hipStream_t st);
 
 // Dense-domain deduplication state of one derived relation (key < 2^w):
 // presence and "touched this round" bitmaps, a dense tag word per key and the
@@ -207,6 +216,35 @@ void join_expand_dense(const JoinArgs& a, int tag_kind, const uint32_t* offs, si
                        const RowWindows* rw = nullptr);
 template <typename K>
 void project_dense(const JoinArgs& a, int tag_kind, const DenseArgs& d, bool lineage, hipStream_t st);
+
+// Fused rounds: one launch per round for a one-plan stratum whose delta join
+// is static-driven with the row-window shape and joins the recent tuples on
+// their first column (see k_window_round).  The recent relation is kept in
+// window layout: the rc[g] recent tuples of group g = (sample, first column)
+// sit from the window's first dense index on.
+struct WindowRecent {
+  uint32_t* rc;  // per group: recent tuples of its window
+  void* rk;      // packed keys, window g's from its first dense index on
+  float* rt;     // tags (f32 semirings, else NULL), same positions
+};
+struct RoundArgs {
+  WindowRecent cur, next;  // read in this round / written for the next one
+  const uint32_t* goff;    // driver CSR over its (sample, first column) prefix
+  uint32_t ngroups;        // groups (2^(sample bits + column bits))
+  uint32_t win_per_key;    // a group folds in LDS when derivations * win_per_key >= window keys
+                           // (0: always; ~0u: never)
+  uint32_t* part;          // per workgroup: [2b] new/changed tuples, [2b + 1] derivations of the round
+};
+// Whether the fused round kernel takes this shape (window of at most 8192 keys),
+// and its grid (the entries of `part` it writes: 2 per workgroup).
+bool window_round_fits(uint32_t wkeys);
+unsigned window_round_grid(uint32_t ngroups);
+template <typename K>
+void window_round(const JoinArgs& a, int tag_kind, const DenseArgs& d, const RoundArgs& ra, hipStream_t st);
+// Sorted recent tuples with a CSR over (sample, first column) -> window layout.
+template <typename K>
+void to_windows(const K* keys, const float* tags, size_t n, const uint32_t* off, uint32_t ngroups,
+                const DenseArgs& d, WindowRecent w, hipStream_t st);
 // Pass 1 of a bitmap compaction: set-bit count of every block of a bitmap
 // over `keys` dense indexes (dense_count_blocks(keys) entries).
 size_t dense_count_blocks(size_t keys);
@@ -311,12 +349,13 @@ template <typename K>
 void lookup_rows(const K* keys, size_t n, const uint32_t* const* qcols, const uint32_t* qsample, size_t nq,
                  int tag_kind, const void* tags, KeyLayout lay, const float* qtab, int64_t* rows, float* qtag,
                  hipStream_t st);
-// adj[ids[rows[i]]] += g[i] for rows[i] >= 0
-void scatter_add_rows(const uint32_t* ids, const int64_t* rows, const float* g, size_t n, float* adj, hipStream_t st);
-// top-k gradient seeded on selected rows of a relation
+// adj[ids[rows[i]]] += g[i] for 0 <= rows[i] < nrel
+void scatter_add_rows(const uint32_t* ids, const int64_t* rows, const float* g, size_t n, size_t nrel, float* adj,
+                      hipStream_t st);
+// top-k gradient seeded on selected rows of a relation of nrel rows
 template <typename K>
 void topk_backward_rows(const TopK* t, const K* keys, KeyLayout lay, const int64_t* rows, const float* g, size_t n,
-                        const float* qtab, float* grad_fact, hipStream_t st);
+                        size_t nrel, const float* qtab, float* grad_fact, hipStream_t st);
 
 // ---------------------------------------------------------- tags & grads
 // Input facts -> tags: f32 copy (bool: none); top-k: [(1 << local_id, q)].

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libdlfix.so")
 
 SEMIRINGS = {"bool": 0, "maxmin": 1, "minplus": 2, "addmult": 3,
-             "diff_addmult": 4, "topk": 5, "diff_topk": 6}
+             "diff_addmult": 4, "topk": 5, "diff_topk": 6, "diff_maxmin": 7}
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_PARSE", 3: "ERR_UNSUPPORTED", 4: "ERR_STATE",
           5: "ERR_NOMEM", 6: "ERR_CAPACITY", 7: "ERR_PROOF_OVERFLOW", 8: "ERR_HIP"}
 EXPORTS = ["dl_load_program", "dl_load_program_static", "dl_clear_facts", "dl_add_facts", "dl_run_fixpoint", "dl_set_workspace",
@@ -35,14 +35,16 @@ class DLError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("semiring", C.c_int), ("k", C.c_int), ("batched", C.c_int),
-                ("stream", C.c_void_p), ("dedup", C.c_int), ("no_graphs", C.c_int),
+                ("stream", C.c_void_p), ("dedup", C.c_int), ("no_graphs", C.c_int), ("no_fused", C.c_int),
                 ("lineage", C.c_int), ("lineage_budget", C.c_size_t),
-                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("max_join_outputs", C.c_uint64), ("exact_growth", C.c_int)]
 
 
 class RelationOut(C.Structure):
     _fields_ = [("sample_ids", C.c_void_p), ("columns", C.c_void_p * 4), ("tags", C.c_void_p),
-                ("topk_count", C.c_void_p), ("topk_bits", C.c_void_p), ("topk_prob", C.c_void_p)]
+                ("topk_count", C.c_void_p), ("topk_bits", C.c_void_p), ("topk_prob", C.c_void_p),
+                ("fact_ids", C.c_void_p)]
 
 
 class KernelStats(C.Structure):
@@ -151,7 +153,8 @@ class Engine:
     def __init__(self, program: str, semiring: str = "bool", k: int = 3,
                  batched: bool = False, stream: int | None = None, use_torch_stream: bool = True,
                  dedup: str = "auto", graphs: bool = True, lineage: str = "auto",
-                 lineage_budget: int = 0, workspace=None, static: bool = False):
+                 lineage_budget: int = 0, workspace=None, static: bool = False, fused: bool = True,
+                 max_join_outputs: int = 0, exact_growth: bool = False):
         """workspace: None (the library allocates), a byte count (a torch
         uint8 tensor of that size is allocated here and kept), or a device
         tensor whose storage the engine keeps all its buffers in.
@@ -175,7 +178,8 @@ class Engine:
         self.workspace = _workspace(workspace)
         wp, wn = (None, 0) if self.workspace is None else (self.workspace.data_ptr(), self.workspace.nbytes)
         opts = Options(SEMIRINGS[semiring], k, int(batched), stream, self.DEDUP[dedup], int(not graphs),
-                       self.LINEAGE[lineage], lineage_budget, wp, wn)
+                       int(not fused), self.LINEAGE[lineage], lineage_budget, wp, wn, max_join_outputs,
+                       int(exact_growth))
         h = C.c_void_p()
         load = lib().dl_load_program_static if static else lib().dl_load_program
         rc = load(program.encode(), C.byref(opts), C.byref(h))
@@ -235,7 +239,8 @@ class Engine:
 
     def read(self, rel: str, device: bool = False) -> dict:
         """Relation in canonical order: dict(sample, cols (n x arity), tags,
-        and for top-k cnt (n), bits (n x k), p (n x k))."""
+        for top-k cnt (n), bits (n x k), p (n x k), and for differentiable
+        max-min fid (n): the number of the input fact each tag comes from)."""
         n = self.size(rel)
         ar = self.arity[rel]
         topk = self.semiring in ("topk", "diff_topk")
@@ -248,8 +253,11 @@ class Engine:
             mk = lambda shape, dt: np.zeros(shape, dt)
             u32, f32, u8, u64 = np.uint32, np.float32, np.uint8, np.uint64
         out = dict(sample=mk(n, u32), cols=[mk(n, u32) for _ in range(ar)], tags=mk(n, f32))
+        vid = self.semiring == "diff_maxmin"
         if topk:
             out.update(cnt=mk(n, u8), bits=mk((self.k, n), u64), p=mk((self.k, n), f32))
+        if vid:
+            out["fid"] = mk(n, u32)
         ro = RelationOut()
         ptr = (lambda t: t.data_ptr()) if device else (lambda a: a.ctypes.data)
         if n:
@@ -261,6 +269,8 @@ class Engine:
                 ro.topk_count = ptr(out["cnt"])
                 ro.topk_bits = ptr(out["bits"])
                 ro.topk_prob = ptr(out["p"])
+            if vid:
+                ro.fact_ids = ptr(out["fid"])
         w = C.c_size_t()
         self._check(lib().dl_read_relation(self.h, rel.encode(), n, C.byref(ro), int(device),
                                            C.byref(w)))

@@ -1,0 +1,76 @@
+"""GPU parity of the fused rounds (one launch per round over a window-layout
+recent relation) against the CPU oracle and against the same engine with
+fused rounds switched off: batched samples (the general, multi-sample form
+of the kernel), a three-column head, and the window / scatter choices
+forced both ways."""
+import json
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_tags_close, engine, oracle_run, same_rows, tune_key
+
+pytestmark = pytest.mark.gpu
+
+
+def check(g, o, rel, sr, batched=False):
+    gr, orr = g.read(rel), o.read(rel)
+    same_rows(gr, orr, batched)
+    if sr == "maxmin":
+        assert np.array_equal(gr["tags"].astype(np.float64), orr["value"])
+    elif sr != "bool":
+        assert_tags_close(gr["tags"], orr["value"], what=sr)
+
+
+@pytest.mark.parametrize("sr", ["bool", "maxmin", "minplus", "addmult"])
+def test_batched_samples(oracle, synth, sr):
+    """Grids of several sizes in one engine: per-sample windows and groups."""
+    g = synth.grid_batch(9, samples=24, kmin=3, kmax=12)
+    facts = {"edge": ([g["src"], g["dst"]], None if sr == "bool" else g["p"], g["sample"])}
+    o = oracle_run(oracle, synth.TC_PROGRAM, sr, facts, batched=True)
+    for fused in (True, False):
+        e = engine(synth.TC_PROGRAM, sr, facts, batched=True, dedup="dense", fused=fused)
+        check(e, o, "path", sr, batched=True)
+        if sr != "minplus":
+            assert e.stats()["max_rounds"] == o.rounds()
+
+
+THREE = """
+.input e/2
+.input f/3
+r(x, z, w) :- f(x, z, w).
+r(x, z, w) :- e(x, y), r(y, z, w).
+"""
+
+
+@pytest.mark.parametrize("sr", ["bool", "maxmin", "addmult"])
+def test_three_column_head(oracle, synth, sr):
+    rng = np.random.default_rng(3)
+    src, dst, p = synth.er_graph(2, 60, 150, weights=True)
+    n = 80
+    f = [rng.integers(0, 60, n).astype(np.uint32), rng.integers(0, 60, n).astype(np.uint32),
+         rng.integers(0, 60, n).astype(np.uint32)]
+    fp = synth.unit_prob(rng, n)
+    facts = {"e": ([src, dst], None if sr == "bool" else p, None), "f": (f, None if sr == "bool" else fp, None)}
+    o = oracle_run(oracle, THREE, sr, facts)
+    for fused in (True, False):
+        e = engine(THREE, sr, facts, dedup="dense", fused=fused)
+        check(e, o, "r", sr)
+
+
+@pytest.mark.parametrize("rows", [0, 2])
+@pytest.mark.parametrize("sr", ["maxmin", "addmult", "bool"])
+def test_window_and_scatter_forced(oracle, synth, sr, rows, tmp_path):
+    """Every group folded in LDS (rows = 2) or every group scattered with
+    global atomics (rows = 0), forced through the autotuner's cache."""
+    from gpu_util import tc_closure, check_closure
+    from paper_2503_21937_amd import dlfix
+    n, m = 1500, 6000
+    src, dst, p = synth.er_graph(4, n, m, weights=True)
+    e = dlfix.Engine(synth.TC_PROGRAM, sr)
+    e.add_facts("edge", [src, dst], None if sr == "bool" else p)
+    key = tune_key(e)
+    cache = tmp_path / "force.jsonl"
+    cache.write_text(json.dumps({"key": key, "dedup": 2, "orient": 2, "items": 2, "rows": rows, "ms": 1.0}) + "\n")
+    e.autotune(1, str(cache))
+    check_closure(e.read("path"), tc_closure(oracle, n, src, dst, p, sr), sr, f"rows={rows}")

@@ -1,20 +1,21 @@
 """Kernel timing (dl_profile): a timed run gives the same relation as an
 untimed one, and engines built with and without round graphs (timed rounds
 are launched directly) report the same launches and algorithmic bytes per
-family."""
+family (with rounds fused into one launch and without)."""
 import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("sr", ["maxmin", "addmult"])
-def test_profiled_graphs_match_direct_launches(synth, sr):
+def test_profiled_graphs_match_direct_launches(synth, sr, fused):
     from paper_2503_21937_amd import dlfix
     src, dst, p = synth.er_graph(3, 1500, 6000, weights=True)
     runs = {}
     for graphs in (True, False):
-        e = dlfix.Engine(synth.TC_PROGRAM, sr, dedup="dense", graphs=graphs)
+        e = dlfix.Engine(synth.TC_PROGRAM, sr, dedup="dense", graphs=graphs, fused=fused)
         e.add_facts("edge", [src, dst], p)
         plain = e.run().read("path")
         e.profile(["join_expand", "join_count"])
@@ -25,7 +26,11 @@ def test_profiled_graphs_match_direct_launches(synth, sr):
         runs[graphs] = (timed, ks)
     (g, kg), (d, kd) = runs[True], runs[False]
     assert np.array_equal(g["cols"], d["cols"])
-    for fam in ("join_expand", "join_count"):
+    # fused rounds count the matches inside the join launch
+    fams = ("join_expand",) if fused else ("join_expand", "join_count")
+    for fam in fams:
         assert kg[fam]["launches"] == kd[fam]["launches"] > 0, fam
         assert kg[fam]["ms"] > 0 and kd[fam]["ms"] > 0, fam
         assert kg[fam]["bytes"] == pytest.approx(kd[fam]["bytes"], rel=1e-9), fam
+    if fused:
+        assert kg["join_count"]["launches"] == kd["join_count"]["launches"] == 0
