@@ -31,18 +31,7 @@ struct ProfScope {
     on = false;
     e.sync();
     if (p.deferred_fam >= 0) e.kstats[p.deferred_fam].bytes += p.deferred_per * (double)e.deferred_units;
-
-    for (auto& r : p.recs) {
-      float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
-        (void)hipGetLastError();  // do not leave the error for the next caller
-        continue;
-      }
-      dl_kernel_timing& k = e.kstats[r.fam];
-      k.launches += 1;
-      k.ms += ms;
-      k.bytes += r.bytes;
-    }
+    Profiler::fold(p.recs, e.kstats);
   }
   ~ProfScope() {
     if (on) g_prof = nullptr;
@@ -57,6 +46,7 @@ Engine::~Engine() {
       b.p = nullptr;
     });
   if (host && host != host_words) (void)hipHostFree(host);
+  if (host_part) (void)hipHostFree(host_part);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 

@@ -951,14 +951,22 @@ bool fused_eligible(Engine& e, int r, const std::vector<const Plan*>& plans, Row
 
 // Rounds 2.. as fused launches over a window-layout recent relation (see
 // k_window_round); four rounds per host synchronisation, as one captured
-// HIP graph where allowed.  Returns the number of rounds run.
+// HIP graph where allowed (timing events, when profiling, inside it).  Each
+// batch of rounds takes the wide group batch (a wave per group) or one group
+// per workgroup, from the size of the last round seen: one group per
+// workgroup once the average group has four times the derivations of the
+// dense threshold (estimated as the last round's new or changed tuples
+// times the drivers per group over the groups; below that, one group per
+// workgroup measured slower).  Returns the number of rounds run.
 template <typename K>
 int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows& rw) {
   const int r = st.rels[0];
   RelState& R = e.rel[r];
   const int ar = e.prog.rels[r].arity;
   const size_t keys = R.dense_keys;
-  const uint32_t ng = (uint32_t)rw.ngroups;
+  // groups of the rounds: one engine's ids in use (groups past the largest
+  // id have no driver rows), a batched engine's whole (sample, id) prefix
+  const uint32_t ng = e.batched ? (uint32_t)rw.ngroups : (uint32_t)std::min<uint64_t>(rw.ngroups, (uint64_t)e.max_id + 1);
   const bool f32 = e.tag_kind == TAG_F32;
   DevBuf* rk[2] = {&e.wr_keys0, &e.wr_keys1};
   DevBuf* rt[2] = {&e.wr_tags0, &e.wr_tags1};
@@ -968,13 +976,14 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     if (f32) e.grow(*rt[i], keys * 4 + 8);
     e.grow(*rc[i], (size_t)ng * 4 + 4);
   }
-  const unsigned nb = window_round_grid(ng);
-  e.grow(e.wr_part, (size_t)BATCH_ROUNDS * nb * 2 * 4);
+  const unsigned nbw[2] = {window_round_grid(ng, WINDOW_ROUND_WIDE), window_round_grid(ng, 1)};
+  const unsigned nbmax = std::max(nbw[0], nbw[1]);
+  e.grow(e.wr_part, (size_t)BATCH_ROUNDS * nbmax * 2 * 4);
   // round 1's recent tuples (sorted) into window layout, through their CSR
   // over (sample, first column)
   const int ir = tw.steps[0].index;
   IndexState& ix = e.idx[ir];
-  e.grow(ix.off, ((size_t)ng + 1) * 4);
+  e.grow(ix.off, (rw.ngroups + 1) * 4);
   csr_build<K>(R.recent.keys.as<K>(), R.recent.n, e.key_width(ar), e.sbits + e.cbits, ix.off.as<uint32_t>(), e.stream);
   const DenseArgs d = dense_args(e, R);
   WindowRecent w[2];
@@ -989,53 +998,115 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
   ra.win_per_key = e.cfg.rows == 0 ? ~0u : e.cfg.rows == 2 ? 0u : 12u;
   e.sync();
   // Every round writes its workgroups' counts to its own part of wr_part;
-  // the host adds them up after the batch.  BATCH_ROUNDS is even: a batch
-  // ends with the recent tuples back in set 0.
-  std::vector<uint32_t> part((size_t)BATCH_ROUNDS * nb * 2);
-  auto enqueue_batch = [&] {
+  // the host adds them up after the batch (pinned readback where the engine
+  // may allocate).  BATCH_ROUNDS is even: a batch ends with the recent
+  // tuples back in set 0.
+  const size_t part_words = (size_t)BATCH_ROUNDS * nbmax * 2;
+  std::vector<uint32_t> part_pageable;
+  uint32_t* part = nullptr;
+  if (e.static_dev >= 0) {
+    part_pageable.resize(part_words);
+    part = part_pageable.data();
+  } else {
+    if (e.host_part_cap < part_words) {
+      if (e.host_part) DL_HIP(hipHostFree(e.host_part));
+      e.host_part = nullptr;
+      e.host_part_cap = 0;
+      DL_HIP(hipHostMalloc((void**)&e.host_part, part_words * 4, hipHostMallocDefault));
+      e.host_part_cap = part_words;
+    }
+    part = e.host_part;
+  }
+  auto enqueue_rounds = [&](int narrow) {
+    ra.batch = narrow ? 1u : WINDOW_ROUND_WIDE;
     for (int i = 0; i < BATCH_ROUNDS; ++i) {
       ra.cur = w[i & 1];
       ra.next = w[(i + 1) & 1];
-      ra.part = e.wr_part.as<uint32_t>() + (size_t)i * nb * 2;
+      ra.part = e.wr_part.as<uint32_t>() + (size_t)i * nbw[narrow] * 2;
       window_round<K>(a, e.tag_kind, d, ra, e.stream);
     }
+  };
+  auto enqueue_readback = [&](int narrow) {
     DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, e.stream));
-    DL_HIP(hipMemcpyAsync(part.data(), e.wr_part.p, part.size() * 4, hipMemcpyDeviceToHost, e.stream));
+    DL_HIP(hipMemcpyAsync(part, e.wr_part.p, (size_t)BATCH_ROUNDS * nbw[narrow] * 2 * 4, hipMemcpyDeviceToHost,
+                          e.stream));
   };
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // The graph holds the rounds' launches only, so that two events around a
+  // replay time exactly them when profiling (events recorded inside a graph
+  // carry no time): the launches' records (family, bytes) are kept from the
+  // capture and counted once per replay.
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  bool tried[2] = {false, false};
+  std::vector<Profiler::Rec> graph_recs[2];
+  hipEvent_t span[2] = {nullptr, nullptr};
+  if (g_prof) {
+    span[0] = g_prof->get();
+    span[1] = g_prof->get();
+  }
   auto release = [&] {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    exec = nullptr;
-    graph = nullptr;
+    for (int m = 0; m < 2; ++m) {
+      if (exec[m]) (void)hipGraphExecDestroy(exec[m]);
+      if (graph[m]) (void)hipGraphDestroy(graph[m]);
+      exec[m] = nullptr;
+      graph[m] = nullptr;
+    }
   };
-  if (e.cfg.graph && !g_prof && hipStreamBeginCapture(e.stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
+  auto capture = [&](int m) {  // the batch body of width m as a graph, once
+    tried[m] = true;
+    if (!e.cfg.graph) return;
+    if (hipStreamBeginCapture(e.stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      (void)hipGetLastError();
+      return;
+    }
+    const size_t m0 = g_prof ? g_prof->recs.size() : 0;
     bool ok = true;
     try {
-      enqueue_batch();
+      enqueue_rounds(m);
     } catch (...) {
       ok = false;
     }
-    if (hipStreamEndCapture(e.stream, &graph) != hipSuccess || !graph) ok = false;
-    if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
+    if (hipStreamEndCapture(e.stream, &graph[m]) != hipSuccess || !graph[m]) ok = false;
+    if (ok && hipGraphInstantiate(&exec[m], graph[m], nullptr, nullptr, 0) != hipSuccess) ok = false;
+    if (g_prof) {  // the launches' records, without their (captured) events' times
+      if (ok) graph_recs[m].assign(g_prof->recs.begin() + (std::ptrdiff_t)m0, g_prof->recs.end());
+      g_prof->recs.resize(m0);
+    }
     if (!ok) {
-      release();
+      if (exec[m]) (void)hipGraphExecDestroy(exec[m]);
+      if (graph[m]) (void)hipGraphDestroy(graph[m]);
+      exec[m] = nullptr;
+      graph[m] = nullptr;
       (void)hipGetLastError();
     }
-  } else {
-    (void)hipGetLastError();
-  }
+  };
+  // four times the dense threshold of a group (derivations); the forced
+  // settings take one width throughout
+  const double per_group = (double)a.n / std::max<uint32_t>(ng, 1u);
+  const double big = ra.win_per_key == ~0u ? -1.0 : 4.0 * (double)rw.wkeys / std::max(ra.win_per_key, 1u);
+  uint64_t last = R.recent.n;
   int rounds = 0;
   bool done = false;
   while (!done) {
-    if (exec) DL_HIP(hipGraphLaunch(exec, e.stream));
-    else enqueue_batch();
+    const int m = big < 0 ? 0 : ra.win_per_key == 0 ? 1 : (double)last * per_group / ng >= big;
+    if (!tried[m]) capture(m);
+    const bool timed = exec[m] && span[0] && span[1];
+    if (timed) DL_HIP(hipEventRecord(span[0], e.stream));
+    if (exec[m]) DL_HIP(hipGraphLaunch(exec[m], e.stream));
+    else enqueue_rounds(m);
+    if (timed) DL_HIP(hipEventRecord(span[1], e.stream));
+    enqueue_readback(m);
     e.sync();
+    if (timed) {
+      float ms = 0.0f;
+      DL_HIP(hipEventElapsedTime(&ms, span[0], span[1]));
+      Profiler::fold_span(graph_recs[m], ms, e.kstats);
+    }
     if (e.host[S_OVF]) {
       release();
       check_overflow(e);
     }
+    const unsigned nb = nbw[m];
     for (int i = 0; i < BATCH_ROUNDS && !done; ++i) {
       uint64_t U = 0, C = 0;
       for (unsigned b = 0; b < nb; ++b) {
@@ -1048,6 +1119,7 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
       e.stats.unique += U;
       e.fused_units += C;
       done = U == 0;
+      last = U;
     }
   }
   R.recent.n = 0;

@@ -1347,9 +1347,12 @@ void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, bool 
 // read of a round is of the previous round's recent tuples or of the group's
 // own window (Jacobi order), and two window-layout buffers alternate.
 //
-// Workgroups take batches of RW_WAVES groups from a counter; each wave sums
-// one group's derivation count, and only groups with derivations are then
-// processed by the whole workgroup.
+// Workgroups take batches of groups (every grid-th batch): in a batch of
+// RW_WAVES groups each wave sums one group's derivation count and does a
+// sparse group alone, and the dense groups are then processed by the whole
+// workgroup one after the other; in a batch of one group (large rounds, where
+// most groups are dense) the first wave counts and the dense groups spread
+// over all workgroups.
 
 // Window of group g (first dense index, keys) of the relation of DenseArgs.
 __device__ __forceinline__ uint32_t group_window(const DenseArgs& d, uint32_t g, uint32_t* W) {
@@ -1368,12 +1371,13 @@ __device__ __forceinline__ uint32_t group_window(const DenseArgs& d, uint32_t g,
 
 bool window_round_fits(uint32_t wkeys) { return wkeys <= (uint32_t)RW_KEYS; }
 
-// Workgroups of a fused round: one per batch of RW_WAVES groups (up to
+// Workgroups of a fused round: one per batch of `batch` groups (up to
 // 16384; beyond, each takes every grid-th batch), so that the dispatcher
 // hands batches to CUs as they free up.
-unsigned window_round_grid(uint32_t ngroups) {
-  return (unsigned)std::min<size_t>(16384, ((size_t)ngroups + RW_WAVES - 1) / RW_WAVES);
+unsigned window_round_grid(uint32_t ngroups, uint32_t batch) {
+  return (unsigned)std::min<size_t>(16384, ((size_t)ngroups + batch - 1) / batch);
 }
+static_assert(WINDOW_ROUND_WIDE == (uint32_t)RW_WAVES, "the wide batch is one group per wave");
 
 template <typename K, int TK, int RX_ITEMS, int FM>
 __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseArgs d, RoundArgs ra) {
@@ -1474,6 +1478,8 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
   // dense tag words; frozen sums are clamped.
   auto emit = [&](uint32_t g, uint32_t kb, const uint32_t* marks, uint32_t w0, uint32_t w1, uint32_t base,
                   bool win) -> uint32_t {
+    // presence: a staged window's words are in s_pres (only this workgroup
+    // writes them during the round), so they are stored, not read again
     K* nk = reinterpret_cast<K*>(ra.next.rk) + kb;
     float* nt = ra.next.rt ? ra.next.rt + kb : nullptr;
     const uint32_t c0 = g & ((1u << d.dcbits) - 1u);
@@ -1482,7 +1488,10 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
     for (uint32_t q0 = w0; q0 < w1; q0 += WAVE) {  // uniform
       const uint32_t wi = q0 + lane;
       const uint32_t xw = wi < w1 ? marks[wi] : 0u;
-      if (xw) d.present[wb + wi] |= xw;
+      if (xw) {
+        if (win) d.present[wb + wi] = s_pres[wi] | xw;
+        else d.present[wb + wi] |= xw;
+      }
       run += wave_expand_bits(xw, wb + q0, run, 0ull, [&](uint32_t slot, uint64_t kk, uint64_t, uint32_t) {
         const uint32_t loc = (uint32_t)kk - kb;
         if constexpr (FAST) nk[slot] = (K)(((uint64_t)c0 << a.olay.cbits) | loc);
@@ -1503,17 +1512,40 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
     return run - base;
   };
 
+  // A dense group's window into LDS: presence words and (float tags) the
+  // tag words, by threads t0, t0 + nt, ... (16-byte loads: a window is
+  // W-aligned, W a multiple of 32)
+  auto stage = [&](uint32_t kb, uint32_t W, uint32_t t0, uint32_t nt) {
+    const uint32_t NWD = W / 32;
+    const size_t wb = kb >> 5;
+    for (uint32_t i = t0; i < NWD; i += nt) s_pres[i] = d.present[wb + i];
+    if constexpr (TK == TAG_F32) {
+      const uint4* src = reinterpret_cast<const uint4*>(d.dtag + kb);
+      uint4* dst = reinterpret_cast<uint4*>(s_tag);
+#pragma unroll 4
+      for (uint32_t i = t0; i < W / 4; i += nt) dst[i] = src[i];
+    }
+  };
+
   if (threadIdx.x < 2) s_sum[threadIdx.x] = 0u;
-  // batches of RW_WAVES groups, every gridDim.x-th to this workgroup (no
-  // shared counter: same-address atomics from every CU serialise)
-  for (uint32_t g0 = blockIdx.x * RW_WAVES; g0 < ra.ngroups; g0 += gridDim.x * RW_WAVES) {
+  // batches of B groups, every gridDim.x-th to this workgroup (no shared
+  // counter: same-address atomics from every CU serialise)
+  const uint32_t B = ra.batch;  // 1 or RW_WAVES
+  for (uint32_t g0 = blockIdx.x * B; g0 < ra.ngroups; g0 += gridDim.x * B) {
     __syncthreads();  // s_gd and the wave marks of the previous batch are no longer read
+    if (B == 1 && wv != 0) {
+      // one group per batch (large rounds: most groups are dense): the
+      // other waves stage its window while the first wave counts
+      uint32_t W;
+      const uint32_t kb = group_window(d, g0, &W);
+      stage(kb, W, threadIdx.x - WAVE, RW_BLOCK - WAVE);
+    }
     {
-      // Wave phase: wave wv takes group g0 + wv.  It counts the group's
+      // Wave phase: wave wv (< B) takes group g0 + wv.  It counts the group's
       // derivations; a sparse group is done by the wave alone (global
       // atomics on its window, marks in the wave's LDS words, emission), a
       // dense one is left for the whole workgroup.
-      const uint32_t g = g0 + wv;
+      const uint32_t g = wv < B ? g0 + wv : ra.ngroups;
       uint32_t D = 0, r0 = 0, r1 = 0;
       // the lane's row (the first WAVE rows of the group): key, tag,
       // recent group count and base, kept for the folds below
@@ -1548,7 +1580,9 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
           s_cc[wv][lane] = rcnt;
           s_cb[wv][lane] = rbase;
         } else {
-          uint32_t* marks = s_tag + wv * WAVE_MARKS;
+          // the wave's mark words (the first wave of a one-group batch marks
+          // in s_new: the other waves are staging s_tag)
+          uint32_t* marks = B == 1 ? s_new : s_tag + wv * WAVE_MARKS;
           const uint32_t NWD = W / 32;
           const size_t wb = kb >> 5;
           for (uint32_t i = lane; i < NWD; i += WAVE) marks[i] = 0u;
@@ -1608,17 +1642,8 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
       uint32_t W;
       const uint32_t kb = group_window(d, g, &W);
       const uint32_t NWD = W / 32;
-      const size_t wb = kb >> 5;
-      for (uint32_t i = threadIdx.x; i < NWD; i += RW_BLOCK) {
-        s_new[i] = 0u;
-        s_pres[i] = d.present[wb + i];
-      }
-      if constexpr (TK == TAG_F32) {  // 16-byte loads (a window is W-aligned, W a multiple of 32)
-        const uint4* src = reinterpret_cast<const uint4*>(d.dtag + kb);
-        uint4* dst = reinterpret_cast<uint4*>(s_tag);
-#pragma unroll 4
-        for (uint32_t i = threadIdx.x; i < W / 4; i += RW_BLOCK) dst[i] = src[i];
-      }
+      for (uint32_t i = threadIdx.x; i < NWD; i += RW_BLOCK) s_new[i] = 0u;
+      if (B != 1) stage(kb, W, threadIdx.x, RW_BLOCK);  // else staged during the wave phase
       const uint32_t r0 = uni(ra.goff[g]), r1 = uni(ra.goff[g + 1]);
       for (uint32_t q0 = r0; q0 < r1; q0 += RW_ROWS) {  // uniform
         const uint32_t nr = r1 - q0 < (uint32_t)RW_ROWS ? r1 - q0 : (uint32_t)RW_ROWS;
@@ -1777,7 +1802,7 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
 
 template <typename K>
 void window_round(const JoinArgs& a, int tk, const DenseArgs& d, const RoundArgs& ra, hipStream_t st) {
-  const unsigned nb = window_round_grid(ra.ngroups);
+  const unsigned nb = window_round_grid(ra.ngroups, ra.batch);
   int fm = -1;
   if (sizeof(K) == 4 && d.nsamp <= 1 && a.olay.ncols == 2 && a.osrc[0] >= 0 && a.osrc[1] < 0) {
     if (tk == TAG_NONE && d.mode == DENSE_BOOL) fm = DENSE_BOOL;

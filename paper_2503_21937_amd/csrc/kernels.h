@@ -234,11 +234,16 @@ struct RoundArgs {
   uint32_t win_per_key;    // a group folds in LDS when derivations * win_per_key >= window keys
                            // (0: always; ~0u: never)
   uint32_t* part;          // per workgroup: [2b] new/changed tuples, [2b + 1] derivations of the round
+  uint32_t batch;          // groups per workgroup batch: RW_WAVES (one wave counts each group and does a
+                           // sparse one alone) or 1 (one group per workgroup: the dense groups of large
+                           // rounds spread over all workgroups instead of queueing in batches)
 };
 // Whether the fused round kernel takes this shape (window of at most 8192 keys),
-// and its grid (the entries of `part` it writes: 2 per workgroup).
+// and its grid for `batch` groups per workgroup batch (the entries of `part`
+// it writes: 2 per workgroup).
 bool window_round_fits(uint32_t wkeys);
-unsigned window_round_grid(uint32_t ngroups);
+unsigned window_round_grid(uint32_t ngroups, uint32_t batch);
+constexpr uint32_t WINDOW_ROUND_WIDE = 8;  // the wider batch (waves of the fused round's workgroup)
 template <typename K>
 void window_round(const JoinArgs& a, int tag_kind, const DenseArgs& d, const RoundArgs& ra, hipStream_t st);
 // Sorted recent tuples with a CSR over (sample, first column) -> window layout.

@@ -46,6 +46,34 @@ struct Profiler {
     recs.back().bytes = bytes;
     (void)hipEventRecord(recs.back().b, st);
   }
+  // Elapsed times and bytes of records into per-family totals k[fam]
+  // (launches, ms, bytes).
+  template <typename Timing>
+  static void fold(const std::vector<Rec>& rs, Timing* k) {
+    for (const Rec& r : rs) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+        (void)hipGetLastError();  // do not leave the error for the next caller
+        continue;
+      }
+      k[r.fam].launches += 1;
+      k[r.fam].ms += ms;
+      k[r.fam].bytes += r.bytes;
+    }
+  }
+  // Records launched together inside a graph, timed as one span of `ms`
+  // by events around the graph launch: every record counts as a launch and
+  // adds its bytes; the span's time goes to the first record's family (the
+  // graphs timed this way hold one family).
+  template <typename Timing>
+  static void fold_span(const std::vector<Rec>& rs, float ms, Timing* k) {
+    if (rs.empty()) return;
+    for (const Rec& r : rs) {
+      k[r.fam].launches += 1;
+      k[r.fam].bytes += r.bytes;
+    }
+    k[rs.front().fam].ms += ms;
+  }
   void defer(int fam, double per_unit) {
     if (!(mask >> fam & 1u)) return;
     deferred_fam = fam;
