@@ -37,10 +37,10 @@ sys.path.insert(0, ROOT)
 
 SEMIRINGS = ("addmult", "maxmin", "minplus")
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-# sources of the join_expand family (row-window and scattered dense joins)
+# sources of the join_expand family (fused rounds, row-window and scattered dense joins)
 EXPAND_SOURCES = ("paper_2503_21937_amd/csrc/k_dense.hip", "paper_2503_21937_amd/csrc/rel_device.h",
                   "paper_2503_21937_amd/csrc/dl_device.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "join_expand_er5000_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "window_round_er5000_traffic.txt")
 
 
 def expand_source_hash() -> str:
@@ -431,6 +431,9 @@ def main() -> int:
     ap.add_argument("--tune-cache", default=None, metavar="PATH",
                     help="autotuner cache to read and extend (default: a fresh temporary file); a profiled "
                          "run that reuses the cache of an earlier run executes no tuning trials")
+    ap.add_argument("--round-log", default=None, metavar="PATH",
+                    help="write each engine's fused-round launch sizes of the last timed step (JSON lines), "
+                         "to relate a kernel trace's launches to their work")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -486,6 +489,12 @@ def main() -> int:
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     derived = sum(e.size("path") for e in engines)
+    if args.round_log:
+        with open(args.round_log, "w") as f:
+            for sr, e in zip(SEMIRINGS, engines):
+                new, der = e.round_log()
+                f.write(json.dumps({"semiring": sr, "driver_rows": int(len(src)), "bytes_per_unit": 8,
+                                    "new": new.tolist(), "derivations": der.tolist()}) + "\n")
     launches = ms = nbytes = 0.0
     for e in engines:
         ks = e.kernel_stats()[dominant]

@@ -314,12 +314,24 @@ dl_status dl_get_stats(const dl_engine* e, dl_stats* out);
 dl_status dl_autotune(dl_engine* e, int trials, const char* cache_path);
 
 /* Time the kernel families in `family_mask` with HIP events recorded on the
- * engine's stream around each launch (0 switches timing off).  Resets the
- * totals; later dl_run_fixpoint and dl_backward calls add to them. */
+ * engine's stream around each launch (0 switches timing off); fused rounds
+ * replayed as a graph are timed by events around each replay, which count as
+ * its launches.  Resets the totals; later dl_run_fixpoint and dl_backward
+ * calls add to them. */
 dl_status dl_profile(dl_engine* e, uint32_t family_mask);
 
 /* Totals of one kernel family since the last dl_profile call. */
 dl_status dl_get_kernel_timing(const dl_engine* e, int family, dl_kernel_timing* out);
+
+/* Sizes of the fused-round launches of the last dl_run_fixpoint (one entry
+ * per launch of the fused round kernel, in launch order, including the
+ * launches of a final batch after the stratum's last round, which find
+ * nothing): tuples new or changed by the round and its derivations (join
+ * outputs).  For relating a kernel trace's launches to their work (Alg. 1:
+ * one entry per iteration).  Writes min(capacity, entries) entries to either
+ * array (NULL: not written) and the entry count to *n. */
+dl_status dl_get_round_log(const dl_engine* e, size_t capacity, uint64_t* new_or_changed, uint64_t* derivations,
+                           size_t* n);
 
 /* Owned by the engine; valid until the next call on it.  Never NULL. */
 const char* dl_last_error(const dl_engine* e);

@@ -186,6 +186,7 @@ struct Engine {
   dl_stats stats{};
   uint64_t deferred_units = 0;  // derivations of joins whose totals stayed on the device (last run)
   uint64_t fused_units = 0;     // derivations of fused rounds (this run, added up on the host)
+  std::vector<uint64_t> round_log;  // fused round launches of the last run: (new or changed, derivations) pairs
   uint32_t prof_mask = 0;
   dl_kernel_timing kstats[DL_K_FAMILIES]{};
   size_t device_bytes = 0;

@@ -1107,12 +1107,15 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
       check_overflow(e);
     }
     const unsigned nb = nbw[m];
-    for (int i = 0; i < BATCH_ROUNDS && !done; ++i) {
+    for (int i = 0; i < BATCH_ROUNDS; ++i) {
       uint64_t U = 0, C = 0;
       for (unsigned b = 0; b < nb; ++b) {
         U += part[((size_t)i * nb + b) * 2];
         C += part[((size_t)i * nb + b) * 2 + 1];
       }
+      e.round_log.push_back(U);
+      e.round_log.push_back(C);
+      if (done) continue;  // launched after the last round: found nothing
       ++rounds;
       ++R.version;
       ++R.rversion;
@@ -1339,6 +1342,7 @@ void run_fixpoint(Engine& e) {
   }
   e.next_id = edb;
   e.fused_units = 0;
+  e.round_log.clear();
   e.lin_n = 0;
   e.lin_segs.clear();
   e.record = e.lineage && e.lin_budget > 0;

@@ -21,7 +21,7 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_PARSE", 3: "ERR_UNSUPPORTED", 4: "ERR_S
           5: "ERR_NOMEM", 6: "ERR_CAPACITY", 7: "ERR_PROOF_OVERFLOW", 8: "ERR_HIP"}
 EXPORTS = ["dl_load_program", "dl_load_program_static", "dl_clear_facts", "dl_add_facts", "dl_run_fixpoint", "dl_set_workspace",
            "dl_relation_size", "dl_read_relation", "dl_lookup", "dl_backward_rows", "dl_backward", "dl_read_grad",
-           "dl_zero_grad", "dl_get_stats", "dl_autotune", "dl_profile", "dl_get_kernel_timing",
+           "dl_zero_grad", "dl_get_stats", "dl_autotune", "dl_profile", "dl_get_kernel_timing", "dl_get_round_log",
            "dl_last_error", "dl_free"]
 KERNEL_FAMILIES = ["join_count", "join_expand", "sort_hist", "sort_scatter", "scan", "reduce",
                    "diff", "merge", "compact", "index", "backward"]
@@ -97,6 +97,7 @@ def lib():
         L.dl_autotune.argtypes = [vp, C.c_int, C.c_char_p]
         L.dl_profile.argtypes = [vp, C.c_uint32]
         L.dl_get_kernel_timing.argtypes = [vp, C.c_int, C.POINTER(KernelStats)]
+        L.dl_get_round_log.argtypes = [vp, sz, vp, vp, C.POINTER(sz)]
         L.dl_last_error.argtypes = [vp]
         L.dl_last_error.restype = C.c_char_p
         L.dl_free.argtypes = [vp]
@@ -348,6 +349,17 @@ class Engine:
             self._check(lib().dl_get_kernel_timing(self.h, i, C.byref(ks)))
             out[name] = dict(launches=ks.launches, ms=ks.ms, bytes=ks.bytes)
         return out
+
+    def round_log(self):
+        """(new or changed, derivations) per fused-round launch of the last
+        run, in launch order (numpy uint64 arrays)."""
+        n = C.c_size_t()
+        self._check(lib().dl_get_round_log(self.h, 0, None, None, C.byref(n)))
+        new = np.zeros(n.value, np.uint64)
+        der = np.zeros(n.value, np.uint64)
+        if n.value:
+            self._check(lib().dl_get_round_log(self.h, n.value, new.ctypes.data, der.ctypes.data, C.byref(n)))
+        return new, der
 
     def stats(self) -> dict:
         s = Stats()

@@ -74,3 +74,28 @@ def test_window_and_scatter_forced(oracle, synth, sr, rows, tmp_path):
     cache.write_text(json.dumps({"key": key, "dedup": 2, "orient": 2, "items": 2, "rows": rows, "ms": 1.0}) + "\n")
     e.autotune(1, str(cache))
     check_closure(e.read("path"), tc_closure(oracle, n, src, dst, p, sr), sr, f"rows={rows}")
+
+
+@pytest.mark.parametrize("sr", ["maxmin", "addmult"])
+def test_round_log(synth, sr):
+    """One log entry per fused launch: the rounds after the first come in
+    order until one finds nothing (later launches of that batch find nothing
+    too), and their derivations add up to the fused part of the candidates."""
+    from paper_2503_21937_amd import dlfix
+    src, dst, p = synth.er_graph(5, 2000, 8000, weights=True)
+    on = dlfix.Engine(synth.TC_PROGRAM, sr, dedup="dense")
+    on.add_facts("edge", [src, dst], p)
+    on.run()
+    new, der = on.round_log()
+    st = on.stats()
+    first_empty = int(np.argmax(new == 0))
+    assert new[first_empty] == 0 and np.all(new[first_empty:] == 0) and np.all(der[first_empty + 1:] == 0)
+    assert first_empty + 1 == st["max_rounds"] - 1  # round 1 is not fused; its last round finds nothing
+    off = dlfix.Engine(synth.TC_PROGRAM, sr, dedup="dense", fused=False)
+    off.add_facts("edge", [src, dst], p)
+    off.run()
+    assert off.round_log()[0].size == 0
+    # the same derivations either way; round 1 (the base rule) derives one
+    # candidate per edge
+    assert st["candidates"] == off.stats()["candidates"]
+    assert int(der.sum()) + src.size == st["candidates"]
