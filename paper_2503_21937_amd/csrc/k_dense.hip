@@ -1369,6 +1369,15 @@ __device__ __forceinline__ uint32_t group_window(const DenseArgs& d, uint32_t g,
   return base + c0 * w;
 }
 
+// Whether group g is a (sample, id) prefix of the dense domain: the groups
+// of a round cover whole powers of two of samples and ids, and only these
+// have a window (a group with driver rows always has one).
+__device__ __forceinline__ bool group_in_domain(const DenseArgs& d, uint32_t g) {
+  const uint32_t s = g >> d.dcbits, c0 = g & ((1u << d.dcbits) - 1u);
+  if (d.nsamp > 1) return s < d.nsamp && c0 < d.sn[s];
+  return s == 0 && c0 < d.dn;
+}
+
 bool window_round_fits(uint32_t wkeys) { return wkeys <= (uint32_t)RW_KEYS; }
 
 // Workgroups of a fused round: one per batch of `batch` groups (up to
@@ -1533,9 +1542,10 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
   const uint32_t B = ra.batch;  // 1 or RW_WAVES
   for (uint32_t g0 = blockIdx.x * B; g0 < ra.ngroups; g0 += gridDim.x * B) {
     __syncthreads();  // s_gd and the wave marks of the previous batch are no longer read
-    if (B == 1 && wv != 0) {
+    if (B == 1 && wv != 0 && group_in_domain(d, g0)) {
       // one group per batch (large rounds: most groups are dense): the
-      // other waves stage its window while the first wave counts
+      // other waves stage its window while the first wave counts (only a
+      // group of the domain has one)
       uint32_t W;
       const uint32_t kb = group_window(d, g0, &W);
       stage(kb, W, threadIdx.x - WAVE, RW_BLOCK - WAVE);
