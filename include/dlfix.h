@@ -152,6 +152,8 @@ typedef struct {
                              per window (default), 2 wherever they apply */
   uint64_t device_allocs; /* hipMalloc calls the engine has made since creation (0 with a workspace) */
   uint64_t workspace_peak;/* largest number of workspace bytes in use at once (0 without a workspace) */
+  int index;              /* join indexes in force: 0 CSR offsets over the prefix domain (a hash index
+                             where that domain passes 2^30), 1 hash indexes (Sec. 5) */
 } dl_stats;
 
 /* Kernel families timed by dl_profile (bit i of the mask = family i). */
@@ -302,9 +304,10 @@ dl_status dl_get_stats(const dl_engine* e, dl_stats* out);
  * candidate execution configuration -- deduplication (sort-based or
  * dense-domain), orientation of the delta joins of 2-atom rules (recent
  * tuples probe the static side, or the static side probes an index over the
- * recent tuples), the join expand tile (1, 2, 4 or 8 outputs per thread) and,
- * for dense heads of static-driven joins, whether derivations are folded per
- * head-key window in LDS (row windows) or scattered with global atomics --
+ * recent tuples), the join expand tile (1, 2, 4 or 8 outputs per thread),
+ * for dense heads of static-driven joins whether derivations are folded per
+ * head-key window in LDS (row windows) or scattered with global atomics, and
+ * (for the fastest of those) CSR offsets or hash indexes for the joins --
  * and keeps the fastest (median of `trials` runs after a warm-up run) for
  * later runs.  All candidates compute the same relations.  If cache_path is
  * not NULL the choice is first looked up there, keyed by a hash of the program

@@ -99,6 +99,9 @@ struct RelState {
 struct IndexState {
   Table t;           // keys permuted, tags, ids
   DevBuf off;        // CSR over the prefix
+  DevBuf hash;       // or a hash index over it (HSlot[hmask + 1])
+  uint32_t hmask = 0;
+  bool use_hash = false;
   bool built = false;
   bool borrowed = false;  // identity permutation: t aliases the relation
   uint64_t version = ~0ull;  // relation version it was built from
@@ -112,6 +115,7 @@ struct LineageSeg {
 struct ExecConfig {
   int items = 2;   // join expand tile: outputs per thread (1, 2, 4, 8)
   int orient = 0;  // delta plans of 2-atom rules: 0 auto, 1 recent-driven, 2 static-driven
+  int index = 0;   // indexes built for joins: 0 CSR offsets (hash above a 2^30 prefix domain), 1 hash
   int graph = 1;   // replay eligible round bodies as a captured HIP graph
   int rows = 1;    // row-window variant of the dense join where it applies
   int fused = 1;   // one launch per round (window_round) where the shape allows
@@ -241,6 +245,7 @@ void Engine::for_each_buf(F&& f) {
   for (auto& x : idx) {
     if (!x.borrowed) f(x.t.keys), f(x.t.tags), f(x.t.ids);
     f(x.off);
+    f(x.hash);
   }
   for (DevBuf* b : {&d_sn, &d_snp, &qtab, &grad_fact, &lin_owner, &lin_l, &lin_r, &tag_by_id, &adj, &counts, &offs,
                     &istart, &alt_keys, &alt_vals, &vals, &flags, &pos, &ukeys, &utags, &status, &nflags, &newpos,

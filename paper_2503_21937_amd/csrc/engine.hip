@@ -456,6 +456,7 @@ void Engine::run() {
   stats.orient = cfg.orient;
   stats.items = cfg.items;
   stats.rows = cfg.rows;
+  stats.index = cfg.index;
 }
 
 size_t Engine::relation_size(const char* relation) {
@@ -593,7 +594,7 @@ std::string Engine::tune_key() const {
 
 namespace {
 struct Tuned {
-  int dedup, orient, items, rows;
+  int dedup, orient, items, rows, index;
   double ms;
 };
 
@@ -606,7 +607,12 @@ bool cache_lookup(const char* path, const std::string& key, Tuned* t) {
     char k[200];
     Tuned x{};
     x.rows = 1;
+    x.index = 0;
     const bool ok =
+        std::sscanf(line,
+                    "{\"key\": \"%199[^\"]\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"rows\": %d, \"index\": %d, "
+                    "\"ms\": %lf",
+                    k, &x.dedup, &x.orient, &x.items, &x.rows, &x.index, &x.ms) == 7 ||
         std::sscanf(line, "{\"key\": \"%199[^\"]\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"rows\": %d, \"ms\": %lf",
                     k, &x.dedup, &x.orient, &x.items, &x.rows, &x.ms) == 6 ||
         std::sscanf(line, "{\"key\": \"%199[^\"]\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"ms\": %lf",
@@ -623,8 +629,10 @@ bool cache_lookup(const char* path, const std::string& key, Tuned* t) {
 void cache_store(const char* path, const std::string& key, const Tuned& t) {
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "{\"key\": \"%s\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"rows\": %d, \"ms\": %.4f}\n",
-               key.c_str(), t.dedup, t.orient, t.items, t.rows, t.ms);
+  std::fprintf(f,
+               "{\"key\": \"%s\", \"dedup\": %d, \"orient\": %d, \"items\": %d, \"rows\": %d, \"index\": %d, "
+               "\"ms\": %.4f}\n",
+               key.c_str(), t.dedup, t.orient, t.items, t.rows, t.index, t.ms);
   std::fclose(f);
 }
 }  // namespace
@@ -635,12 +643,13 @@ void Engine::autotune(int trials, const char* cache_path) {
   if (trials < 1) trials = 1;
   if (!ingested) run();  // fixes the key layout the decision is keyed on
   const std::string key = tune_key();
-  Tuned best{opts.dedup, cfg.orient, cfg.items, cfg.rows, 1e300};
+  Tuned best{opts.dedup, cfg.orient, cfg.items, cfg.rows, cfg.index, 1e300};
   if (cache_path && cache_lookup(cache_path, key, &best)) {
     opts.dedup = best.dedup;
     cfg.orient = best.orient;
     cfg.items = best.items;
     cfg.rows = best.rows;
+    cfg.index = best.index;
     stats.tuned_ms = best.ms;
     run();  // results of the cached configuration
     return;
@@ -649,6 +658,27 @@ void Engine::autotune(int trials, const char* cache_path) {
   for (const Plan& pl : prog.plans) twins = twins || pl.alt >= 0;
   const int saved_dedup = opts.dedup;
   const ExecConfig saved = cfg;
+  cfg.index = 0;
+  // median of `trials` runs after a warm-up run; false when the
+  // configuration does not apply (e.g. no dense domain)
+  auto time_config = [&](double* med) {
+    std::vector<double> ms;
+    try {
+      run();
+      for (int t = 0; t < trials; ++t) {
+        run();
+        ms.push_back(stats.run_ms);
+      }
+    } catch (const Error& x) {
+      if (x.code == DL_ERR_UNSUPPORTED) return false;
+      opts.dedup = saved_dedup;
+      cfg = saved;
+      throw;
+    }
+    std::sort(ms.begin(), ms.end());
+    *med = ms[ms.size() / 2];
+    return true;
+  };
   for (int dedup : {1, 2}) {
     for (int orient : {1, 2}) {
       if (orient == 2 && !twins) continue;
@@ -660,30 +690,31 @@ void Engine::autotune(int trials, const char* cache_path) {
           cfg.orient = orient;
           cfg.items = items;
           cfg.rows = rows;
-          std::vector<double> ms;
-          try {
-            run();
-            for (int t = 0; t < trials; ++t) {
-              run();
-              ms.push_back(stats.run_ms);
-            }
-          } catch (const Error& x) {
-            if (x.code == DL_ERR_UNSUPPORTED) break;  // e.g. no dense domain
-            opts.dedup = saved_dedup;
-            cfg = saved;
-            throw;
-          }
-          std::sort(ms.begin(), ms.end());
-          const double med = ms[ms.size() / 2];
-          if (med < best.ms) best = Tuned{dedup, orient, items, rows, med};
+          double med;
+          if (!time_config(&med)) break;  // e.g. no dense domain
+          if (med < best.ms) best = Tuned{dedup, orient, items, rows, 0, med};
         }
       }
+    }
+  }
+  // the fastest configuration with hash indexes instead of CSR offsets
+  if (best.ms < 1e300) {
+    opts.dedup = best.dedup;
+    cfg.orient = best.orient;
+    cfg.items = best.items;
+    cfg.rows = best.rows;
+    cfg.index = 1;
+    double med;
+    if (time_config(&med) && med < best.ms) {
+      best.index = 1;
+      best.ms = med;
     }
   }
   opts.dedup = best.dedup;
   cfg.orient = best.orient;
   cfg.items = best.items;
   cfg.rows = best.rows;
+  cfg.index = best.index;
   stats.tuned_ms = best.ms;
   if (cache_path) cache_store(cache_path, key, best);
   run();  // leave the results of the chosen configuration in place

@@ -249,7 +249,10 @@ void build_index(Engine& e, int i) {
   const KeyLayout lay = e.layout(ar);
   const size_t n = src.n;
   const int pbits = e.sbits + spec.w * e.cbits;
-  if (pbits > 30) throw Error{DL_ERR_UNSUPPORTED, "join key domain above 2^30 (index on " + e.prog.rels[spec.rel].name + ")"};
+  // CSR offsets need 4 bytes per prefix of the domain; a hash index 32
+  // bytes per row, whatever the domain
+  ix.use_hash = e.cfg.index == 1 || pbits > 30;
+  if (ix.use_hash && pbits > 62) throw Error{DL_ERR_UNSUPPORTED, "join prefix wider than 62 bits (index on " + e.prog.rels[spec.rel].name + ")"};
   if (spec.identity()) {
     if (!ix.borrowed) {
       e.release(ix.t.keys), e.release(ix.t.tags), e.release(ix.t.ids);
@@ -282,8 +285,17 @@ void build_index(Engine& e, int i) {
     }
   }
   ix.t.n = n;
-  e.grow(ix.off, (((size_t)1 << pbits) + 1) * 4);
-  csr_build<K>(ix.t.keys.as<K>(), n, e.key_width(ar), pbits, ix.off.as<uint32_t>(), e.stream);
+  if (ix.use_hash) {
+    size_t slots = 64;
+    while (slots < 2 * n) slots *= 2;
+    if (slots > ((size_t)1 << 32)) throw Error{DL_ERR_CAPACITY, "hash index above 2^32 slots"};
+    e.grow(ix.hash, slots * sizeof(HSlot));
+    ix.hmask = (uint32_t)(slots - 1);
+    hash_build<K>(ix.t.keys.as<K>(), n, e.key_width(ar), pbits, ix.hash.as<HSlot>(), ix.hmask, e.stream);
+  } else {
+    e.grow(ix.off, (((size_t)1 << pbits) + 1) * 4);
+    csr_build<K>(ix.t.keys.as<K>(), n, e.key_width(ar), pbits, ix.off.as<uint32_t>(), e.stream);
+  }
   ix.built = true;
   ix.version = index_version(R, spec);
 }
@@ -496,7 +508,9 @@ void run_plan(Engine& e, const Plan& pl) {
     a.dlay = e.layout(cur.ncols);
     a.w = spec.w;
     for (int j = 0; j < spec.w; ++j) a.jsrc[j] = step.join_src[j];
-    a.off = ix.off.as<uint32_t>();
+    a.off = ix.use_hash ? nullptr : ix.off.as<uint32_t>();
+    a.hslots = ix.use_hash ? ix.hash.as<HSlot>() : nullptr;
+    a.hmask = ix.hmask;
     a.ikeys = ix.t.keys.p;
     a.itags = ix.t.tags.p;
     a.iids = ix.t.ids.as<uint32_t>();

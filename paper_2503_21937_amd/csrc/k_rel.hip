@@ -145,14 +145,63 @@ void csr_build_dn(const K* keys, const uint64_t* dn, int total_bits, int prefix_
   csr_launch<K>(keys, 0, dn, total_bits - prefix_bits, domain, off, st);
 }
 
+// Hash index build in two launches over the sorted keys: the first row of
+// every prefix run claims a slot (compare-and-swap on the empty key, then
+// the next slot on a collision) and records itself as the run's start; the
+// last row of the run then finds that slot and writes the row count.
+template <typename K>
+__global__ void k_hash_insert(const K* __restrict__ keys, size_t n, int shift, HSlot* __restrict__ slots,
+                              uint32_t mask) {
+  GRID_STRIDE(i, n) {
+    const uint64_t p = (uint64_t)keys[i] >> shift;
+    if (i > 0 && ((uint64_t)keys[i - 1] >> shift) == p) continue;
+    for (uint32_t h = hash_slot(p, mask);; h = (h + 1) & mask) {
+      const unsigned long long old =
+          atomicCAS(reinterpret_cast<unsigned long long*>(&slots[h].key), (unsigned long long)HSLOT_EMPTY,
+                    (unsigned long long)p);
+      if (old == HSLOT_EMPTY) {
+        slots[h].start = (uint32_t)i;
+        break;
+      }
+    }
+  }
+}
+
+template <typename K>
+__global__ void k_hash_count(const K* __restrict__ keys, size_t n, int shift, HSlot* __restrict__ slots,
+                             uint32_t mask) {
+  GRID_STRIDE(i, n) {
+    const uint64_t p = (uint64_t)keys[i] >> shift;
+    if (i + 1 < n && ((uint64_t)keys[i + 1] >> shift) == p) continue;
+    for (uint32_t h = hash_slot(p, mask);; h = (h + 1) & mask) {
+      if (slots[h].key == p) {
+        slots[h].count = (uint32_t)i + 1u - slots[h].start;
+        break;
+      }
+    }
+  }
+}
+
+template <typename K>
+void hash_build(const K* keys, size_t n, int total_bits, int prefix_bits, HSlot* slots, uint32_t mask,
+                hipStream_t st) {
+  fill_u32(reinterpret_cast<uint32_t*>(slots), ((size_t)mask + 1) * 4, 0xffffffffu, st);  // every key empty
+  if (!n) return;
+  const int shift = total_bits - prefix_bits;
+  DL_PROF_BEGIN(9, st);
+  k_hash_insert<K><<<grid_for(n), BLOCK, 0, st>>>(keys, n, shift, slots, mask);
+  k_hash_count<K><<<grid_for(n), BLOCK, 0, st>>>(keys, n, shift, slots, mask);
+  DL_PROF_END(9, st, ((double)mask + 1) * 16.0 + 2.0 * (double)n * sizeof(K));
+}
+
 // ------------------------------------------------------------------ joins
 template <typename K>
 __global__ void k_join_count(JoinArgs a, uint32_t* __restrict__ counts) {
   const K* dk = (const K*)a.dkeys;
   GRID_STRIDE(i, a.n) {
-    uint64_t p = join_prefix(dk[i], a);
-    const uint32_t b = a.off[p];
-    counts[i] = a.off[p + 1] - b;
+    uint32_t b, c;
+    index_range(a, join_prefix(dk[i], a), &b, &c);
+    counts[i] = c;
     if (a.istart) a.istart[i] = b;
   }
 }
@@ -197,11 +246,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_count_scan(JoinArgs a, uint32_t*
     const size_t i = base + q;
     c[q] = 0;
     st[q] = 0;
-    if (i < a.n) {
-      const uint64_t p = join_prefix(dk[i], a);
-      st[q] = a.off[p];
-      c[q] = a.off[p + 1] - st[q];
-    }
+    if (i < a.n) index_range(a, join_prefix(dk[i], a), &st[q], &c[q]);
     s += c[q];
   }
   uint64_t tot;
@@ -264,8 +309,10 @@ __global__ __launch_bounds__(BLOCK) void k_join_expand(JoinArgs a, const uint32_
     const size_t row = s_row[j - s0];
     const uint32_t base = offs[row];
     const K dkey = dk[row];
-    const uint64_t p = join_prefix(dkey, a);
-    const uint32_t irow = a.off[p] + ((uint32_t)j - base);
+    uint32_t first, cnt;
+    if (a.istart) first = a.istart[row];  // written by the count
+    else index_range(a, join_prefix(dkey, a), &first, &cnt);
+    const uint32_t irow = first + ((uint32_t)j - base);
     const K ikey = ik[irow];
     uint32_t v[4];
     const bool ok = out_cols<K>(a, dkey, ikey, v);
@@ -959,6 +1006,7 @@ void vtag_backward(const VTag* t, const int64_t* rows, const float* g, size_t n,
   template void permute_keys<K>(const K*, size_t, KeyLayout, const int*, K*, hipStream_t);                        \
   template void csr_build<K>(const K*, size_t, int, int, uint32_t*, hipStream_t);                                   \
   template void csr_build_dn<K>(const K*, const uint64_t*, int, int, uint32_t*, hipStream_t);                       \
+  template void hash_build<K>(const K*, size_t, int, int, HSlot*, uint32_t, hipStream_t);                          \
   template void join_count<K>(const JoinArgs&, uint32_t*, hipStream_t);                                             \
   template bool join_count_scan<K>(const JoinArgs&, uint32_t*, uint64_t*, uint64_t*, uint64_t*, uint64_t*, hipStream_t);                                             \
   template void join_expand<K>(const JoinArgs&, int, const uint32_t*, size_t, void*, void*, uint32_t*, uint32_t*,   \

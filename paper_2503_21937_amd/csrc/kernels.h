@@ -64,6 +64,22 @@ void csr_build(const K* keys, size_t n, int total_bits, int prefix_bits, uint32_
 template <typename K>
 void csr_build_dn(const K* keys, const uint64_t* dn, int total_bits, int prefix_bits, uint32_t* off, hipStream_t st);
 
+// Hash index over the same prefix (Sec. 5, hash table design: open
+// addressing with linear probing, row positions as the payload): one slot
+// per distinct prefix of the sorted keys with its first row and row count
+// (a prefix's rows are contiguous).  Memory follows the distinct prefixes,
+// not the prefix domain, so any prefix width up to 62 bits is indexable.
+// `mask` + 1 slots (a power of two, at least twice the rows: a probe always
+// meets an empty slot).
+struct alignas(16) HSlot {
+  uint64_t key;  // prefix, or HSLOT_EMPTY
+  uint32_t start, count;
+};
+constexpr uint64_t HSLOT_EMPTY = ~0ull;
+template <typename K>
+void hash_build(const K* keys, size_t n, int total_bits, int prefix_bits, HSlot* slots, uint32_t mask,
+                hipStream_t st);
+
 // Tag payload kinds of the relational kernels.
 enum TagKind : int { TAG_NONE = 0, TAG_F32 = 1, TAG_TOPK = 2, TAG_VID = 3 };  // TAG_VID: VTag (value, fact)
 
@@ -97,8 +113,11 @@ struct JoinArgs {
   // join prefix: driver columns forming the index prefix, in index key order
   int w;
   int jsrc[4];
-  // index
+  // index: CSR offsets over the prefix domain, or (hslots != NULL) a hash
+  // index of hmask + 1 slots
   const uint32_t* off;
+  const HSlot* hslots;
+  uint32_t hmask;
   const void* ikeys;
   const void* itags;
   const uint32_t* iids;

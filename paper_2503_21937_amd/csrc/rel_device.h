@@ -107,6 +107,40 @@ __device__ __forceinline__ bool out_cols(const JoinArgs& a, K dkey, K ikey, uint
   return true;
 }
 
+// Slot of a prefix in a hash index: the 64-bit finaliser of MurmurHash3
+// (public domain: xor-shift, multiply, twice), masked.
+__device__ __forceinline__ uint32_t hash_slot(uint64_t p, uint32_t mask) {
+  p ^= p >> 33;
+  p *= 0xff51afd7ed558ccdull;
+  p ^= p >> 33;
+  p *= 0xc4ceb9fe1a85ec53ull;
+  p ^= p >> 33;
+  return (uint32_t)p & mask;
+}
+
+// First index row and row count of join prefix p: CSR offsets, or a probe
+// of the hash index (linear from the prefix's slot to its slot or an empty
+// one; the table is at most half full).
+__device__ __forceinline__ void index_range(const JoinArgs& a, uint64_t p, uint32_t* start, uint32_t* count) {
+  if (a.hslots) {
+    for (uint32_t h = hash_slot(p, a.hmask);; h = (h + 1) & a.hmask) {
+      const HSlot s = a.hslots[h];
+      if (s.key == p) {
+        *start = s.start;
+        *count = s.count;
+        return;
+      }
+      if (s.key == HSLOT_EMPTY) {
+        *start = 0;
+        *count = 0;
+        return;
+      }
+    }
+  }
+  *start = a.off[p];
+  *count = a.off[p + 1] - *start;
+}
+
 template <typename K>
 __device__ __forceinline__ uint64_t join_prefix(K dkey, const JoinArgs& a) {
   uint64_t p = a.ilay.sbits ? (uint64_t)key_sample(dkey, a.dlay) << (a.w * a.ilay.cbits) : 0ull;

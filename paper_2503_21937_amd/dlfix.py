@@ -58,7 +58,7 @@ class Stats(C.Structure):
                 ("key_bits", C.c_uint32), ("id_bits", C.c_uint32), ("sample_bits", C.c_uint32),
                 ("dedup", C.c_int), ("orient", C.c_int), ("items", C.c_int), ("tuned_ms", C.c_double),
                 ("lineage_mode", C.c_int), ("rows", C.c_int),
-                ("device_allocs", C.c_uint64), ("workspace_peak", C.c_uint64)]
+                ("device_allocs", C.c_uint64), ("workspace_peak", C.c_uint64), ("index", C.c_int)]
 
 
 _lib = None
