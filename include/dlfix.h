@@ -88,7 +88,10 @@ typedef struct {
                              is at most 2^30 and the semiring is not a top-k form or DIFF_MAXMIN,
                              else sort-based),
                          1 = always sort-based (radix sort, unique, difference, merge),
-                         2 = dense-domain wherever possible */
+                         2 = dense-domain wherever possible,
+                         3 = hash-set (Sec. 5): each round's candidates go into a hash set that
+                             folds their tags, then only the distinct keys are sorted; f32 tags
+                             or none, without recorded lineage (otherwise sort-based) */
   int no_graphs;      /* 1: never replay round bodies as captured HIP graphs (0: replay where eligible) */
   int no_fused;       /* 1: never run a round as one fused launch (0: where the stratum has one
                          static-driven join whose derivations fall into per-group windows) */
@@ -302,7 +305,7 @@ dl_status dl_get_stats(const dl_engine* e, dl_stats* out);
 
 /* Autotuner.  Times dl_run_fixpoint on the current facts under every
  * candidate execution configuration -- deduplication (sort-based or
- * dense-domain), orientation of the delta joins of 2-atom rules (recent
+ * dense-domain; hash-set for the fastest sort-based one), orientation of the delta joins of 2-atom rules (recent
  * tuples probe the static side, or the static side probes an index over the
  * recent tuples), the join expand tile (1, 2, 4 or 8 outputs per thread),
  * for dense heads of static-driven joins whether derivations are folded per

@@ -263,7 +263,7 @@ void Engine::init(const char* program_text, const dl_options* o) {
   rel.assign(prog.rels.size(), RelState{});
   for (size_t r = 0; r < prog.rels.size(); ++r) rel[r].raw_cols.assign(prog.rels[r].arity, DevBuf{});
   idx.assign(prog.indexes.size(), IndexState{});
-  if (o->dedup < 0 || o->dedup > 2) throw Error{DL_ERR_ARG, "dedup must be 0, 1 or 2"};
+  if (o->dedup < 0 || o->dedup > 3) throw Error{DL_ERR_ARG, "dedup must be 0, 1, 2 or 3"};
   cfg.graph = o->no_graphs ? 0 : 1;
   cfg.fused = o->no_fused ? 0 : 1;
   for (const Plan& pl : prog.plans)
@@ -659,6 +659,7 @@ void Engine::autotune(int trials, const char* cache_path) {
   const int saved_dedup = opts.dedup;
   const ExecConfig saved = cfg;
   cfg.index = 0;
+  Tuned best1{1, 0, 2, 1, 0, 1e300};  // the fastest sort-based configuration
   // median of `trials` runs after a warm-up run; false when the
   // configuration does not apply (e.g. no dense domain)
   auto time_config = [&](double* med) {
@@ -693,9 +694,19 @@ void Engine::autotune(int trials, const char* cache_path) {
           double med;
           if (!time_config(&med)) break;  // e.g. no dense domain
           if (med < best.ms) best = Tuned{dedup, orient, items, rows, 0, med};
+          if (dedup == 1 && med < best1.ms) best1 = Tuned{dedup, orient, items, rows, 0, med};
         }
       }
     }
+  }
+  // the fastest sort-based configuration with hash-set deduplication
+  if (best1.ms < 1e300) {
+    opts.dedup = 3;
+    cfg.orient = best1.orient;
+    cfg.items = best1.items;
+    cfg.rows = best1.rows;
+    double med;
+    if (time_config(&med) && med < best.ms) best = Tuned{3, best1.orient, best1.items, best1.rows, 0, med};
   }
   // the fastest configuration with hash indexes instead of CSR offsets
   if (best.ms < 1e300) {

@@ -175,7 +175,7 @@ void setup_dense(Engine& e) {
     const bool fits = (e.tag_kind == TAG_NONE || e.tag_kind == TAG_F32) && dom <= ((uint64_t)1 << 31) && bytes <= budget;
     if (e.opts.dedup == 2 && !fits)
       throw Error{DL_ERR_UNSUPPORTED, "dense-domain deduplication does not fit relation " + e.prog.rels[r].name};
-    R.dense = fits && e.opts.dedup != 1;
+    R.dense = fits && e.opts.dedup != 1 && e.opts.dedup != 3;
     if (!R.dense) continue;
     R.dense_keys = keys;
     R.dense_cols = e.prog.rels[r].arity;
@@ -724,35 +724,71 @@ size_t absorb_sorted(Engine& e, int r) {
   const bool use_perm = e.tag_kind == TAG_TOPK || e.tag_kind == TAG_VID || e.record;
   hipStream_t st = e.stream;
 
-  // 1. sort the candidates by packed key (stable: derivation order kept)
   K* kp = R.cand_keys.as<K>();
   uint32_t* vp = nullptr;
-  if (use_perm) {
-    e.grow(e.vals, C * 4);
-    iota_u32(e.vals.as<uint32_t>(), C, 0, st);
-    vp = e.vals.as<uint32_t>();
-  } else if (e.tag_kind == TAG_F32) {
-    vp = R.cand_tags.as<uint32_t>();
-  }
-  sort_pairs<K>(e, &kp, &vp, C, e.key_width(ar));
+  K* uk;     // the round's distinct keys, sorted, and their +-folded tags
+  void* ut;
+  size_t U;
+  // hash-set deduplication (f32 or no tags, no lineage record, keys below
+  // the full width of K so that all ones marks an empty slot)
+  const bool hset = e.opts.dedup == 3 && !use_perm && e.key_width(ar) < (int)(8 * sizeof(K));
+  if (hset) {
+    // 1'. candidates into a hash set at most half full, tags folded per key
+    const int mode = e.tag_kind == TAG_NONE ? DENSE_BOOL
+                     : e.sr == DL_MAXMIN    ? DENSE_MAX
+                     : e.sr == DL_MINPLUS   ? DENSE_MIN
+                                            : DENSE_ADD;
+    size_t slots = 64;
+    while (slots < 2 * C) slots *= 2;
+    if (slots > ((size_t)1 << 32)) throw Error{DL_ERR_CAPACITY, "hash set above 2^32 slots"};
+    e.grow(e.alt_keys, slots * kb);
+    if (tb) e.grow(e.alt_vals, slots * 4);
+    K* hk = e.alt_keys.as<K>();
+    uint32_t* ht = tb ? e.alt_vals.as<uint32_t>() : nullptr;
+    hset_prepare<K>(hk, ht, slots, mode, st);
+    hset_insert<K>(kp, tb ? R.cand_tags.as<float>() : nullptr, C, hk, ht, (uint32_t)(slots - 1), mode, st);
+    // 2'. occupied slots -> distinct keys (into the candidate buffers), sorted
+    e.grow(e.flags, slots * 4);
+    e.grow(e.pos, (slots + 1) * 4);
+    hset_flags<K>(hk, slots, e.flags.as<uint32_t>(), st);
+    scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), slots, S_UNIQUE, true);
+    U = e.read_total(S_UNIQUE);
+    hset_compact<K>(hk, ht, e.pos.as<uint32_t>(), slots, mode, kp, tb ? R.cand_tags.as<float>() : nullptr, st);
+    vp = tb ? R.cand_tags.as<uint32_t>() : nullptr;
+    sort_pairs<K>(e, &kp, &vp, U, e.key_width(ar));
+    uk = kp;
+    ut = vp;
+  } else {
+    // 1. sort the candidates by packed key (stable: derivation order kept)
+    if (use_perm) {
+      e.grow(e.vals, C * 4);
+      iota_u32(e.vals.as<uint32_t>(), C, 0, st);
+      vp = e.vals.as<uint32_t>();
+    } else if (e.tag_kind == TAG_F32) {
+      vp = R.cand_tags.as<uint32_t>();
+    }
+    sort_pairs<K>(e, &kp, &vp, C, e.key_width(ar));
 
-  // 2. runs of equal keys -> one row each, tags +-folded in sorted order
-  e.grow(e.flags, C * 4);
-  e.grow(e.pos, (C + 1) * 4);
-  head_flags<K>(kp, C, e.flags.as<uint32_t>(), st);
-  scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), C, S_UNIQUE, true);
-  const size_t U = e.read_total(S_UNIQUE);
+    // 2. runs of equal keys -> one row each, tags +-folded in sorted order
+    e.grow(e.flags, C * 4);
+    e.grow(e.pos, (C + 1) * 4);
+    head_flags<K>(kp, C, e.flags.as<uint32_t>(), st);
+    scan(e, e.flags.as<uint32_t>(), e.pos.as<uint32_t>(), C, S_UNIQUE, true);
+    U = e.read_total(S_UNIQUE);
+    e.grow(e.ukeys, U * kb);
+    if (tb) e.grow(e.utags, U * tb);
+    const void* tsrc = use_perm ? R.cand_tags.p : (const void*)vp;
+    segment_reduce<K>(kp, e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), C, e.tag_kind, e.sr, e.k, tsrc,
+                      use_perm ? vp : nullptr, e.ukeys.as<K>(), e.utags.p, U, st);
+    uk = e.ukeys.as<K>();
+    ut = e.utags.p;
+  }
   e.stats.unique += U;
-  e.grow(e.ukeys, U * kb);
-  if (tb) e.grow(e.utags, U * tb);
-  const void* tsrc = use_perm ? R.cand_tags.p : (const void*)vp;
-  segment_reduce<K>(kp, e.pos.as<uint32_t>(), e.flags.as<uint32_t>(), C, e.tag_kind, e.sr, e.k, tsrc,
-                    use_perm ? vp : nullptr, e.ukeys.as<K>(), e.utags.p, U, st);
 
   // 3. difference / +-merge against the full relation
   e.grow(e.status, U * 4);
-  diff_merge<K>(e.ukeys.as<K>(), e.utags.p, U, R.full.keys.as<K>(), R.full.tags.p, R.full.n, e.tag_kind, e.sr, e.k,
-                e.converge, e.status.as<uint32_t>(), nullptr, st);
+  diff_merge<K>(uk, ut, U, R.full.keys.as<K>(), R.full.tags.p, R.full.n, e.tag_kind, e.sr, e.k, e.converge,
+                e.status.as<uint32_t>(), nullptr, st);
   e.grow(e.nflags, U * 4);
   e.grow(e.newpos, (U + 1) * 4);
   status_flags(e.status.as<uint32_t>(), U, 1u, e.nflags.as<uint32_t>(), st);
@@ -771,10 +807,10 @@ size_t absorb_sorted(Engine& e, int r) {
 
   // 4. next recent relation = new (and, converging, changed) tuples, sorted
   e.grow(R.recent.keys, Rn * kb + 8);
-  compact(e.ukeys.p, rfl, rps, U, kb, R.recent.keys.p, st);
+  compact(uk, rfl, rps, U, kb, R.recent.keys.p, st);
   if (tb) {
     e.grow(R.recent.tags, Rn * tb + 8);
-    compact(e.utags.p, rfl, rps, U, tb, R.recent.tags.p, st);
+    compact(ut, rfl, rps, U, tb, R.recent.tags.p, st);
   }
   R.recent.n = Rn;
   ++R.rversion;
@@ -787,10 +823,10 @@ size_t absorb_sorted(Engine& e, int r) {
   const uint32_t* nid = nullptr;
   if (e.converge) {
     e.grow(e.nkeys, N * kb);
-    compact(e.ukeys.p, e.nflags.as<uint32_t>(), e.newpos.as<uint32_t>(), U, kb, e.nkeys.p, st);
+    compact(uk, e.nflags.as<uint32_t>(), e.newpos.as<uint32_t>(), U, kb, e.nkeys.p, st);
     if (tb) {
       e.grow(e.ntags, N * tb);
-      compact(e.utags.p, e.nflags.as<uint32_t>(), e.newpos.as<uint32_t>(), U, tb, e.ntags.p, st);
+      compact(ut, e.nflags.as<uint32_t>(), e.newpos.as<uint32_t>(), U, tb, e.ntags.p, st);
     }
     nk = e.nkeys.p;
     nt = e.ntags.p;

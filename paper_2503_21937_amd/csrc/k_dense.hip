@@ -6,6 +6,8 @@
 // encoding of binary32, or float add for frozen add-mult sums), and appends
 // each key the first time it is touched in the round (wave-aggregated
 // append).  Only the touched keys are sorted afterwards.
+#include <type_traits>
+
 #include "prof.h"
 #include "rel_device.h"
 
@@ -1876,6 +1878,76 @@ void to_windows(const K* keys, const float* tags, size_t n, const uint32_t* off,
   k_to_windows<K><<<grid_for(std::max<size_t>(n, ngroups)), BLOCK, 0, st>>>(keys, tags, n, off, ngroups, d, w);
 }
 
+// ------------------------------------------------- hash-set deduplication
+template <typename K>
+void hset_prepare(K* hkeys, uint32_t* htags, size_t slots, int mode, hipStream_t st) {
+  fill_u32(reinterpret_cast<uint32_t*>(hkeys), slots * (sizeof(K) / 4), 0xffffffffu, st);
+  if (htags) fill_u32(htags, slots, dense_init_word(mode), st);
+}
+
+template <typename K>
+__global__ void k_hset_insert(const K* __restrict__ keys, const float* __restrict__ tags, size_t n,
+                              K* __restrict__ hkeys, uint32_t* __restrict__ htags, uint32_t mask, int mode) {
+  using U = std::conditional_t<sizeof(K) == 8, unsigned long long, unsigned int>;
+  const K empty = (K)~(K)0;
+  GRID_STRIDE(i, n) {
+    const K k = keys[i];
+    uint32_t h = hash_slot((uint64_t)k, mask);
+    for (;; h = (h + 1) & mask) {
+      K cur = hkeys[h];
+      if (cur == empty) cur = (K)atomicCAS(reinterpret_cast<U*>(hkeys + h), (U)empty, (U)k);
+      if (cur == empty || cur == k) break;  // claimed, or the key's slot
+    }
+    if (!htags) continue;
+    const float t = tags[i];
+    if (mode == DENSE_ADD) atomicAdd(reinterpret_cast<float*>(htags + h), t);
+    else if (mode == DENSE_MAX) atomicMax(htags + h, to_ordered(t));
+    else atomicMin(htags + h, to_ordered(t));
+  }
+}
+
+template <typename K>
+void hset_insert(const K* keys, const float* tags, size_t n, K* hkeys, uint32_t* htags, uint32_t mask, int mode,
+                 hipStream_t st) {
+  if (!n) return;
+  DL_PROF_BEGIN(5, st);
+  k_hset_insert<K><<<grid_for(n), BLOCK, 0, st>>>(keys, tags, n, hkeys, htags, mask, mode);
+  DL_PROF_END(5, st, (double)n * (sizeof(K) + (htags ? 4.0 : 0.0)));
+}
+
+template <typename K>
+__global__ void k_hset_flags(const K* __restrict__ hkeys, size_t slots, uint32_t* __restrict__ flags) {
+  GRID_STRIDE(i, slots) flags[i] = hkeys[i] != (K)~(K)0 ? 1u : 0u;
+}
+
+template <typename K>
+void hset_flags(const K* hkeys, size_t slots, uint32_t* flags, hipStream_t st) {
+  k_hset_flags<K><<<grid_for(slots), BLOCK, 0, st>>>(hkeys, slots, flags);
+}
+
+template <typename K>
+__global__ void k_hset_compact(const K* __restrict__ hkeys, const uint32_t* __restrict__ htags,
+                               const uint32_t* __restrict__ pos, size_t slots, int mode, K* __restrict__ okeys,
+                               float* __restrict__ otags) {
+  GRID_STRIDE(i, slots) {
+    if (pos[i + 1] == pos[i]) continue;  // empty slot
+    const uint32_t o = pos[i];
+    okeys[o] = hkeys[i];
+    if (otags) {
+      const uint32_t w = htags[i];
+      otags[o] = mode == DENSE_ADD ? fminf(1.0f, __uint_as_float(w)) : from_ordered(w);
+    }
+  }
+}
+
+template <typename K>
+void hset_compact(const K* hkeys, const uint32_t* htags, const uint32_t* pos, size_t slots, int mode, K* okeys,
+                  float* otags, hipStream_t st) {
+  DL_PROF_BEGIN(8, st);
+  k_hset_compact<K><<<grid_for(slots), BLOCK, 0, st>>>(hkeys, htags, pos, slots, mode, okeys, otags);
+  DL_PROF_END(8, st, (double)slots * (sizeof(K) + 4.0));
+}
+
 #define INST(K)                                                                                                       \
   template void join_expand_dense<K>(const JoinArgs&, int, const uint32_t*, size_t, const uint64_t*, size_t,     \
                                      const DenseArgs&, bool, hipStream_t, const RowWindows*);                                                \
@@ -1887,7 +1959,11 @@ void to_windows(const K* keys, const float* tags, size_t n, const uint32_t* off,
   template void bitmap_keys<K>(const DenseArgs&, size_t, const uint32_t*, bool, K*, float*, uint32_t*, hipStream_t); \
   template void window_round<K>(const JoinArgs&, int, const DenseArgs&, const RoundArgs&, hipStream_t);               \
   template void to_windows<K>(const K*, const float*, size_t, const uint32_t*, uint32_t, const DenseArgs&,             \
-                              WindowRecent, hipStream_t);
+                              WindowRecent, hipStream_t);                                                              \
+  template void hset_prepare<K>(K*, uint32_t*, size_t, int, hipStream_t);                                              \
+  template void hset_insert<K>(const K*, const float*, size_t, K*, uint32_t*, uint32_t, int, hipStream_t);             \
+  template void hset_flags<K>(const K*, size_t, uint32_t*, hipStream_t);                                                \
+  template void hset_compact<K>(const K*, const uint32_t*, const uint32_t*, size_t, int, K*, float*, hipStream_t);
 
 INST(uint32_t)
 INST(uint64_t)

@@ -195,6 +195,24 @@ size_t dense_segments(size_t n, int items);
 // Initial dense tag word (semiring zero) for a mode.
 uint32_t dense_init_word(int mode);
 
+// Hash-set deduplication of a round's candidates (Sec. 5, GPU hash table;
+// the alternative to sorting them): every candidate is inserted into a table
+// of mask + 1 slots (open addressing, linear probing; an empty slot's key is
+// all ones, which no packed key narrower than K can be) and its tag folded
+// into the slot's word as the dense path folds (mode: DenseMode; f32 tags or
+// none).  The occupied slots then give the distinct keys, unsorted, with
+// their +-folded tags (frozen sums clamped).  hset_prepare empties the table.
+template <typename K>
+void hset_prepare(K* hkeys, uint32_t* htags, size_t slots, int mode, hipStream_t st);
+template <typename K>
+void hset_insert(const K* keys, const float* tags, size_t n, K* hkeys, uint32_t* htags, uint32_t mask, int mode,
+                 hipStream_t st);
+template <typename K>
+void hset_flags(const K* hkeys, size_t slots, uint32_t* flags, hipStream_t st);
+template <typename K>
+void hset_compact(const K* hkeys, const uint32_t* htags, const uint32_t* pos, size_t slots, int mode, K* okeys,
+                  float* otags, hipStream_t st);
+
 // counts[i] = number of index rows matching driver row i.
 template <typename K>
 void join_count(const JoinArgs& a, uint32_t* counts, hipStream_t st);  // also fills a.istart if set

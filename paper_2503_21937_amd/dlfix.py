@@ -148,7 +148,7 @@ def _workspace(ws):
 class Engine:
     """One fixpoint engine: a program under one semiring (dlfix.h)."""
 
-    DEDUP = {"auto": 0, "sort": 1, "dense": 2}
+    DEDUP = {"auto": 0, "sort": 1, "dense": 2, "hash": 3}
     LINEAGE = {"auto": 0, "store": 1, "recompute": 2}
 
     def __init__(self, program: str, semiring: str = "bool", k: int = 3,

@@ -88,3 +88,58 @@ def test_autotuner_records_index(synth, tmp_path):
     e.autotune(1, str(cache))
     rec = json.loads(cache.read_text().splitlines()[-1])
     assert rec["index"] in (0, 1) and rec["index"] == e.stats()["index"]
+
+
+# ------------------------------------------------ hash-set deduplication
+
+@pytest.mark.parametrize("sr", ["bool", "maxmin", "minplus", "addmult"])
+def test_tc_hash_set(oracle, synth, sr):
+    """Each round's candidates deduplicated in a hash set (tags folded per
+    key with atomics), then only the distinct keys sorted."""
+    from paper_2503_21937_amd import dlfix
+    n, m = 900, 3600
+    src, dst, p = synth.er_graph(8, n, m, weights=True)
+    e = dlfix.Engine(synth.TC_PROGRAM, sr, dedup="hash")
+    e.add_facts("edge", [src, dst], None if sr == "bool" else p)
+    e.run()
+    assert e.stats()["dedup"] == 3
+    check_closure(e.read("path"), tc_closure(oracle, n, src, dst, p, sr), sr, "hash set")
+
+
+NONLINEAR = ".input edge/2\npath(x, y) :- edge(x, y).\npath(x, z) :- path(x, y), path(y, z).\n"
+
+
+@pytest.mark.parametrize("sr", ["maxmin", "addmult"])
+def test_nonlinear_and_batched_hash_set(oracle, synth, sr):
+    src, dst, p = synth.er_graph(3, 300, 900, weights=True)
+    facts = {"edge": ([src, dst], p, None)}
+    g = engine(NONLINEAR, sr, facts, dedup="hash")
+    o = oracle_run(oracle, NONLINEAR, sr, facts)
+    gr, orr = g.read("path"), o.read("path")
+    same_rows(gr, orr)
+    assert_tags_close(gr["tags"], orr["value"])
+    gb = synth.grid_batch(6, samples=12, kmin=3, kmax=9)
+    facts = {"edge": ([gb["src"], gb["dst"]], gb["p"], gb["sample"])}
+    g = engine(synth.TC_PROGRAM, sr, facts, batched=True, dedup="hash")
+    o = oracle_run(oracle, synth.TC_PROGRAM, sr, facts, batched=True)
+    gr, orr = g.read("path"), o.read("path")
+    same_rows(gr, orr, batched=True)
+    assert_tags_close(gr["tags"], orr["value"])
+    assert g.stats()["max_rounds"] == o.rounds()
+
+
+def test_hash_set_with_wide_keys_and_points_to(oracle, synth):
+    """64-bit packed keys (three 17-bit columns) and three-atom rules."""
+    rng = np.random.default_rng(12)
+    pool = rng.choice(1 << 17, 120, replace=False).astype(np.uint32)
+    facts = {"e": ([pool[rng.integers(0, 120, 300)] for _ in range(3)], None, None),
+             "f": ([pool[rng.integers(0, 120, 1200)] for _ in range(3)], None, None)}
+    g = engine(WIDE, "bool", facts, dedup="hash")
+    assert g.stats()["key_bits"] == 64
+    o = oracle_run(oracle, WIDE, "bool", facts)
+    same_rows(g.read("r"), o.read("r"))
+    rels = synth.andersen(4, v=500, n_addr=250, n_assign=1500, n_load=200, n_store=200)
+    facts = {name: ([a, b], None, None) for name, (a, b) in rels.items()}
+    g = engine(synth.ANDERSEN_PROGRAM, "bool", facts, dedup="hash")
+    o = oracle_run(oracle, synth.ANDERSEN_PROGRAM, "bool", facts)
+    assert np.array_equal(g.read("pt")["cols"], o.read("pt")["cols"])
