@@ -1001,13 +1001,14 @@ bool fused_eligible(Engine& e, int r, const std::vector<const Plan*>& plans, Row
 
 // Rounds 2.. as fused launches over a window-layout recent relation (see
 // k_window_round); four rounds per host synchronisation, as one captured
-// HIP graph where allowed (timing events, when profiling, inside it).  Each
-// batch of rounds takes the wide group batch (a wave per group) or one group
-// per workgroup, from the size of the last round seen: one group per
-// workgroup once the average group has four times the derivations of the
-// dense threshold (estimated as the last round's new or changed tuples
-// times the drivers per group over the groups; below that, one group per
-// workgroup measured slower).  Returns the number of rounds run.
+// HIP graph where allowed (timed, when profiling, by events around each
+// replay).  Each batch of rounds takes a group batch width from the size of
+// the last round seen, as the ratio r of the average group's derivations
+// (the last round's new or changed tuples times the drivers per group, over
+// the groups) to the dense threshold: 8 groups per workgroup (a wave per
+// group) below r = 1, then 4, 2 and, from r = 4, one group per workgroup --
+// fewer groups queue behind one workgroup's dense ones as more of them are
+// dense.  Returns the number of rounds run.
 template <typename K>
 int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows& rw) {
   const int r = st.rels[0];
@@ -1026,8 +1027,11 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     if (f32) e.grow(*rt[i], keys * 4 + 8);
     e.grow(*rc[i], (size_t)ng * 4 + 4);
   }
-  const unsigned nbw[2] = {window_round_grid(ng, WINDOW_ROUND_WIDE), window_round_grid(ng, 1)};
-  const unsigned nbmax = std::max(nbw[0], nbw[1]);
+  // group batch widths (groups per workgroup batch) a batch of rounds can take
+  constexpr int NW = 4;
+  const uint32_t widths[NW] = {WINDOW_ROUND_WIDE, WINDOW_ROUND_WIDE / 2, WINDOW_ROUND_WIDE / 4, 1};
+  unsigned nbw[NW], nbmax = 0;
+  for (int m = 0; m < NW; ++m) nbmax = std::max(nbmax, nbw[m] = window_round_grid(ng, widths[m]));
   e.grow(e.wr_part, (size_t)BATCH_ROUNDS * nbmax * 2 * 4);
   // round 1's recent tuples (sorted) into window layout, through their CSR
   // over (sample, first column)
@@ -1067,35 +1071,35 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     }
     part = e.host_part;
   }
-  auto enqueue_rounds = [&](int narrow) {
-    ra.batch = narrow ? 1u : WINDOW_ROUND_WIDE;
+  auto enqueue_rounds = [&](int m) {
+    ra.batch = widths[m];
     for (int i = 0; i < BATCH_ROUNDS; ++i) {
       ra.cur = w[i & 1];
       ra.next = w[(i + 1) & 1];
-      ra.part = e.wr_part.as<uint32_t>() + (size_t)i * nbw[narrow] * 2;
+      ra.part = e.wr_part.as<uint32_t>() + (size_t)i * nbw[m] * 2;
       window_round<K>(a, e.tag_kind, d, ra, e.stream);
     }
   };
-  auto enqueue_readback = [&](int narrow) {
+  auto enqueue_readback = [&](int m) {
     DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, e.stream));
-    DL_HIP(hipMemcpyAsync(part, e.wr_part.p, (size_t)BATCH_ROUNDS * nbw[narrow] * 2 * 4, hipMemcpyDeviceToHost,
+    DL_HIP(hipMemcpyAsync(part, e.wr_part.p, (size_t)BATCH_ROUNDS * nbw[m] * 2 * 4, hipMemcpyDeviceToHost,
                           e.stream));
   };
   // The graph holds the rounds' launches only, so that two events around a
   // replay time exactly them when profiling (events recorded inside a graph
   // carry no time): the launches' records (family, bytes) are kept from the
   // capture and counted once per replay.
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
-  bool tried[2] = {false, false};
-  std::vector<Profiler::Rec> graph_recs[2];
+  hipGraph_t graph[NW] = {};
+  hipGraphExec_t exec[NW] = {};
+  bool tried[NW] = {};
+  std::vector<Profiler::Rec> graph_recs[NW];
   hipEvent_t span[2] = {nullptr, nullptr};
   if (g_prof) {
     span[0] = g_prof->get();
     span[1] = g_prof->get();
   }
   auto release = [&] {
-    for (int m = 0; m < 2; ++m) {
+    for (int m = 0; m < NW; ++m) {
       if (exec[m]) (void)hipGraphExecDestroy(exec[m]);
       if (graph[m]) (void)hipGraphDestroy(graph[m]);
       exec[m] = nullptr;
@@ -1133,12 +1137,18 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
   // four times the dense threshold of a group (derivations); the forced
   // settings take one width throughout
   const double per_group = (double)a.n / std::max<uint32_t>(ng, 1u);
-  const double big = ra.win_per_key == ~0u ? -1.0 : 4.0 * (double)rw.wkeys / std::max(ra.win_per_key, 1u);
+  const double dense = ra.win_per_key == ~0u ? -1.0 : (double)rw.wkeys / std::max(ra.win_per_key, 1u);
   uint64_t last = R.recent.n;
   int rounds = 0;
   bool done = false;
   while (!done) {
-    const int m = big < 0 ? 0 : ra.win_per_key == 0 ? 1 : (double)last * per_group / ng >= big;
+    int m = 0;
+    if (dense >= 0 && ra.win_per_key == 0) {
+      m = NW - 1;
+    } else if (dense >= 0) {
+      const double r = (double)last * per_group / ng / dense;
+      m = r < 1.0 ? 0 : r < 2.0 ? 1 : r < 4.0 ? 2 : 3;
+    }
     if (!tried[m]) capture(m);
     const bool timed = exec[m] && span[0] && span[1];
     if (timed) DL_HIP(hipEventRecord(span[0], e.stream));
