@@ -64,6 +64,11 @@ int ref_num_strata(ref_engine*);
 int ref_read(ref_engine*, const char* rel, uint32_t* sample_ids, uint32_t* cols,
              double* value, int32_t* cnt, uint64_t* bits, float* p,
              double* prob, int32_t* round_found);
+/* Top-k proofs as full fact sets (up to 256 probabilistic facts per sample,
+ * Sec. 3.5 top-k proofs): word w of proof j of tuple i at
+ * bits[(i*3 + j)*4 + w], fact f at bit f % 64 of word f / 64 (ref_read's
+ * `bits` holds word 0 only). */
+int ref_read_bits(ref_engine*, const char* rel, uint64_t* bits);
 /* Differentiable max-min: the input fact (numbered 0, 1, ... over all
  * ref_add_facts calls in order) whose probability each tuple's tag equals;
  * its derivative with respect to that probability is 1, to all others 0.

@@ -364,11 +364,35 @@ struct Parser {
 
 // ----------------------------------------------------------------- semiring
 const int KMAX = 3;
+const int WMAX = 4;  // words of a proof's fact set: up to 256 probabilistic facts per sample
+// A proof: the set of its facts, fact f at bit f % 64 of word f / 64.  Sets
+// are ordered as the unsigned integers they spell (highest word first).
+struct Bits {
+  uint64_t w[WMAX] = {0, 0, 0, 0};
+  bool test(int f) const { return (w[f >> 6] >> (f & 63)) & 1ull; }
+  void set(int f) { w[f >> 6] |= 1ull << (f & 63); }
+  Bits operator|(const Bits& o) const {
+    Bits r;
+    for (int i = 0; i < WMAX; ++i) r.w[i] = w[i] | o.w[i];
+    return r;
+  }
+  bool operator==(const Bits& o) const {
+    for (int i = 0; i < WMAX; ++i)
+      if (w[i] != o.w[i]) return false;
+    return true;
+  }
+  bool operator!=(const Bits& o) const { return !(*this == o); }
+  bool operator<(const Bits& o) const {
+    for (int i = WMAX - 1; i >= 0; --i)
+      if (w[i] != o.w[i]) return w[i] < o.w[i];
+    return false;
+  }
+};
 struct Tag {
   double v = 0;
   uint32_t fid = 0;  // differentiable max-min: the input fact the value comes from
   int cnt = 0;
-  uint64_t bits[KMAX] = {0, 0, 0};
+  Bits bits[KMAX];
   float p[KMAX] = {0, 0, 0};
 };
 
@@ -381,20 +405,20 @@ struct Semiring {
   // Probability of a proof (conjunction of the facts whose bits are set):
   // product of their probabilities in binary32, facts in ascending id order,
   // starting from 1.
-  static float proof_prob(uint64_t b, const std::vector<float>& q) {
+  static float proof_prob(const Bits& b, const std::vector<float>& q) {
     float acc = 1.0f;
-    for (int i = 0; i < 64; ++i)
-      if ((b >> i) & 1ull) acc = acc * q[i];
+    for (int i = 0; i < 64 * WMAX; ++i)
+      if (b.test(i)) acc = acc * q[i];
     return acc;
   }
   // Keep the k best distinct proofs: probability descending, then the bitset
   // as an unsigned integer ascending.
-  Tag best(std::vector<uint64_t> cand, const std::vector<float>& q) const {
+  Tag best(std::vector<Bits> cand, const std::vector<float>& q) const {
     std::sort(cand.begin(), cand.end());
     cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-    std::vector<std::pair<float, uint64_t>> ranked;
-    for (uint64_t b : cand) ranked.push_back({proof_prob(b, q), b});
-    std::sort(ranked.begin(), ranked.end(), [](const std::pair<float, uint64_t>& a, const std::pair<float, uint64_t>& b) {
+    std::vector<std::pair<float, Bits>> ranked;
+    for (const Bits& b : cand) ranked.push_back({proof_prob(b, q), b});
+    std::sort(ranked.begin(), ranked.end(), [](const std::pair<float, Bits>& a, const std::pair<float, Bits>& b) {
       if (a.first != b.first) return a.first > b.first;
       return a.second < b.second;
     });
@@ -427,7 +451,7 @@ struct Semiring {
       case REF_DIFF_ADDMULT: t.v = a.v * b.v; break;
       case REF_DIFF_MAXMIN: t = pick(a, b, false); break;
       default: {
-        std::vector<uint64_t> cand;
+        std::vector<Bits> cand;
         for (int i = 0; i < a.cnt; ++i)
           for (int j = 0; j < b.cnt; ++j) cand.push_back(a.bits[i] | b.bits[j]);
         t = best(cand, q);
@@ -445,7 +469,7 @@ struct Semiring {
       case REF_DIFF_ADDMULT: t.v = std::min(1.0, a.v + b.v); break;
       case REF_DIFF_MAXMIN: t = pick(a, b, true); break;
       default: {
-        std::vector<uint64_t> cand;
+        std::vector<Bits> cand;
         for (int i = 0; i < a.cnt; ++i) cand.push_back(a.bits[i]);
         for (int j = 0; j < b.cnt; ++j) cand.push_back(b.bits[j]);
         t = best(cand, q);
@@ -469,16 +493,16 @@ struct Semiring {
 double incl_excl(const Tag& t, const std::vector<float>& q) {
   double P = 0;
   for (int S = 1; S < (1 << t.cnt); ++S) {
-    uint64_t u = 0;
+    Bits u;
     int sz = 0;
     for (int i = 0; i < t.cnt; ++i)
       if (S >> i & 1) {
-        u |= t.bits[i];
+        u = u | t.bits[i];
         ++sz;
       }
     double prod = 1;
-    for (int b = 0; b < 64; ++b)
-      if (u >> b & 1ull) prod *= (double)q[b];
+    for (int b = 0; b < 64 * WMAX; ++b)
+      if (u.test(b)) prod *= (double)q[b];
     P += (sz % 2 ? 1.0 : -1.0) * prod;
   }
   return P;
@@ -780,12 +804,12 @@ int ref_add_facts(ref_engine* e, const char* rel, size_t n, const uint32_t* samp
     Key key(cols + i * ar, cols + (i + 1) * ar);
     Tag t;
     if (e->sr.topk()) {
-      if (db.q.size() >= 64) {
-        e->err = "more than 64 probabilistic facts in one sample";
+      if (db.q.size() >= 64 * WMAX) {
+        e->err = "more than 256 probabilistic facts in one sample";
         return 2;
       }
       t.cnt = 1;
-      t.bits[0] = 1ull << db.q.size();
+      t.bits[0].set((int)db.q.size());
       t.p[0] = tags[i];
       db.q.push_back(tags[i]);
       db.fact_of_bit.push_back({r, f});
@@ -857,7 +881,7 @@ int ref_read(ref_engine* e, const char* rel, uint32_t* sample_ids, uint32_t* col
       if (value) value[i] = e->sr.kind == REF_BOOL ? 1.0 : t.second.tag.v;
       if (cnt) cnt[i] = t.second.tag.cnt;
       for (int j = 0; j < KMAX; ++j) {
-        if (bits) bits[i * KMAX + j] = j < t.second.tag.cnt ? t.second.tag.bits[j] : 0;
+        if (bits) bits[i * KMAX + j] = j < t.second.tag.cnt ? t.second.tag.bits[j].w[0] : 0;
         if (p) p[i * KMAX + j] = j < t.second.tag.cnt ? t.second.tag.p[j] : 0.0f;
       }
       if (prob) prob[i] = e->sr.topk() ? incl_excl(t.second.tag, kv.second.q) : t.second.tag.v;
@@ -865,6 +889,20 @@ int ref_read(ref_engine* e, const char* rel, uint32_t* sample_ids, uint32_t* col
       ++i;
     }
   }
+  return 0;
+}
+
+int ref_read_bits(ref_engine* e, const char* rel, uint64_t* bits) {
+  int r = e->prog.find(rel);
+  if (r < 0) return 1;
+  size_t i = 0;
+  for (auto& kv : e->samples)
+    for (auto& t : kv.second.rel[r]) {
+      for (int j = 0; j < KMAX; ++j)
+        for (int w = 0; w < WMAX; ++w)
+          bits[(i * KMAX + j) * WMAX + w] = j < t.second.tag.cnt ? t.second.tag.bits[j].w[w] : 0;
+      ++i;
+    }
   return 0;
 }
 
@@ -897,19 +935,19 @@ int ref_backward(ref_engine* e, const char* out_rel, const double* grad_out) {
         double g = grad_out[i++];
         const Tag& tg = t.second.tag;
         for (int S = 1; S < (1 << tg.cnt); ++S) {
-          uint64_t u = 0;
+          Bits u;
           int sz = 0;
           for (int a = 0; a < tg.cnt; ++a)
             if (S >> a & 1) {
-              u |= tg.bits[a];
+              u = u | tg.bits[a];
               ++sz;
             }
           double sign = sz % 2 ? 1.0 : -1.0;
-          for (int j = 0; j < 64; ++j) {
-            if (!(u >> j & 1ull)) continue;
+          for (int j = 0; j < 64 * WMAX; ++j) {
+            if (!u.test(j)) continue;
             double prod = 1;
-            for (int b = 0; b < 64; ++b)
-              if (b != j && (u >> b & 1ull)) prod *= (double)db.q[b];
+            for (int b = 0; b < 64 * WMAX; ++b)
+              if (b != j && u.test(b)) prod *= (double)db.q[b];
             auto fr = db.fact_of_bit[j];
             e->grad[fr.first][fr.second] += g * sign * prod;
           }
@@ -1012,17 +1050,17 @@ int ref_topk_op(int k, int op, int acnt, const uint64_t* abits, int bcnt, const 
   a.cnt = acnt;
   b.cnt = bcnt;
   for (int i = 0; i < acnt; ++i) {
-    a.bits[i] = abits[i];
-    a.p[i] = Semiring::proof_prob(abits[i], qv);
+    a.bits[i].w[0] = abits[i];
+    a.p[i] = Semiring::proof_prob(a.bits[i], qv);
   }
   for (int i = 0; i < bcnt; ++i) {
-    b.bits[i] = bbits[i];
-    b.p[i] = Semiring::proof_prob(bbits[i], qv);
+    b.bits[i].w[0] = bbits[i];
+    b.p[i] = Semiring::proof_prob(b.bits[i], qv);
   }
   Tag t = op ? sr.otimes(a, b, qv) : sr.oplus(a, b, qv);
   *ocnt = t.cnt;
   for (int i = 0; i < KMAX; ++i) {
-    obits[i] = i < t.cnt ? t.bits[i] : 0;
+    obits[i] = i < t.cnt ? t.bits[i].w[0] : 0;
     oprob[i] = i < t.cnt ? t.p[i] : 0.0f;
   }
   return 0;

@@ -56,6 +56,7 @@ def lib():
         L.ref_read.argtypes = [vp, C.c_char_p] + [vp] * 8
         L.ref_backward.argtypes = [vp, C.c_char_p, vp]
         L.ref_read_fid.argtypes = [vp, C.c_char_p, vp]
+        L.ref_read_bits.argtypes = [vp, C.c_char_p, vp]
         L.ref_vid_op.argtypes = [C.c_int, C.c_double, C.c_uint32, C.c_double, C.c_uint32,
                                  C.POINTER(C.c_double), C.POINTER(C.c_uint32)]
         L.ref_read_grad.argtypes = [vp, C.c_char_p, vp]
@@ -150,8 +151,10 @@ class Oracle:
         rf = np.zeros(n, np.int32)
         lib().ref_read(self.h, rel.encode(), _p(s), _p(cols), _p(val), _p(cnt),
                        _p(bits), _p(p), _p(prob), _p(rf))
+        wide = np.zeros((n, 3, 4), np.uint64)
+        lib().ref_read_bits(self.h, rel.encode(), _p(wide))
         return dict(sample=s, cols=cols, value=val, cnt=cnt, bits=bits, p=p,
-                    prob=prob, round=rf)
+                    prob=prob, round=rf, bits_wide=wide)
 
     def fid(self, rel: str) -> np.ndarray:
         """Differentiable max-min: the input fact number each tuple's tag comes from."""
