@@ -39,7 +39,7 @@ typedef enum {
   DL_ERR_NOMEM = 5,           /* device allocation failed or the workspace is full; the engine and its
                                  facts stay valid: rerun after dl_set_workspace with a larger block */
   DL_ERR_CAPACITY = 6,        /* a size exceeds an index width (e.g. > 2^32 join outputs in one round) */
-  DL_ERR_PROOF_OVERFLOW = 7,  /* top-k: more than 64 probabilistic facts in one sample */
+  DL_ERR_PROOF_OVERFLOW = 7,  /* top-k: more than 256 probabilistic facts in one sample */
   DL_ERR_HIP = 8              /* a HIP runtime call failed */
 } dl_status;
 
@@ -50,7 +50,8 @@ typedef enum {
  *  ADDMULT       [0,1], +: min(1, a+b), x: a*b.
  *  DIFF_ADDMULT  ADDMULT with reverse-mode gradients (dl_backward).
  *  TOPK          up to k <= 3 proofs per fact; a proof is a set of input facts
- *                (bitset over the <= 64 probabilistic facts of its sample),
+ *                (bitset over the <= 256 probabilistic facts of its sample: one
+ *                64-bit word while every sample has <= 64, else four),
  *                its probability the binary32 product of those facts'
  *                probabilities in ascending fact order.  x: pairwise unions,
  *                + : union of the lists; both keep the k most likely distinct
@@ -126,7 +127,8 @@ typedef struct {
   float* tags;            /* [n]: the tag (f32 semirings), 1.0 (BOOL), or the
                              inclusion-exclusion probability of the kept proofs (TOPK) */
   uint8_t* topk_count;    /* [n]   number of kept proofs (TOPK) */
-  uint64_t* topk_bits;    /* [k*n] proof j of row i at [j*n + i]; bit f = fact f of the row's sample */
+  uint64_t* topk_bits;    /* [k*n*W], W = dl_stats.topk_words: word w of proof j of row i at
+                             [(j*n + i)*W + w]; fact f of the row's sample is bit f % 64 of word f / 64 */
   float* topk_prob;       /* [k*n] binary32 proof probabilities, same layout */
   uint32_t* fact_ids;     /* [n] DIFF_MAXMIN: the number of the input fact each tag comes from
                              (not written for the other semirings) */
@@ -157,6 +159,8 @@ typedef struct {
   uint64_t workspace_peak;/* largest number of workspace bytes in use at once (0 without a workspace) */
   int index;              /* join indexes in force: 0 CSR offsets over the prefix domain (a hash index
                              where that domain passes 2^30), 1 hash indexes (Sec. 5) */
+  int topk_words;         /* top-k forms: 64-bit words per proof set in the last run (1 while every
+                             sample has at most 64 probabilistic facts, else 4: up to 256); 0 otherwise */
 } dl_stats;
 
 /* Kernel families timed by dl_profile (bit i of the mask = family i). */

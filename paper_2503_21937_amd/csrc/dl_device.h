@@ -131,13 +131,19 @@ __device__ __forceinline__ uint64_t block_lookback(uint64_t* stat, uint64_t agg,
 // Bool: presence is the tag (nothing stored).
 struct NoTag {};
 
-// Top-k proofs, k <= 3: bitsets over the sample's probabilistic facts with
-// their binary32 probabilities, best first.
-struct TopK {
-  uint64_t b[3];
+// Top-k proofs, k <= 3: sets of the sample's probabilistic facts (W 64-bit
+// words each, fact f at bit f % 64 of word f / 64; proof i's words at
+// b[i*W .. i*W + W - 1]) with their binary32 probabilities, best first.
+// W = 1 covers 64 facts per sample, W = 4 covers 256.
+template <int W>
+struct TopKW {
+  static constexpr int WORDS = W;
+  uint64_t b[3 * W];
   float p[3];
   uint32_t cnt;
 };
+using TopK = TopKW<1>;
+using TopK4 = TopKW<4>;
 
 // Differentiable max-min: a probability and the input fact it comes from.
 struct VTag {
@@ -172,68 +178,101 @@ __device__ __forceinline__ float f_oplus(int sr, float a, float b) {
 
 // Probability of a proof: product of its facts' probabilities in binary32,
 // ascending fact id, starting from 1 (multiplications only: no contraction).
-__device__ __forceinline__ float proof_prob(uint64_t bits, const float* __restrict__ q) {
+template <int W>
+__device__ __forceinline__ float proof_prob(const uint64_t* bits, const float* __restrict__ q) {
   float acc = 1.0f;
-  while (bits) {
-    int i = __builtin_ctzll(bits);
-    acc = __fmul_rn(acc, q[i]);
-    bits &= bits - 1;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    uint64_t x = bits[w];
+    while (x) {
+      const int i = __builtin_ctzll(x);
+      acc = __fmul_rn(acc, q[w * 64 + i]);
+      x &= x - 1;
+    }
   }
   return acc;
 }
 
-// Ranking of proofs: higher probability first, then smaller bitset.
-__device__ __forceinline__ bool proof_before(float pa, uint64_t ba, float pb, uint64_t bb) {
-  return pa > pb || (pa == pb && ba < bb);
+// Proof sets as the unsigned integers they spell: a < b.
+template <int W>
+__device__ __forceinline__ bool bits_less(const uint64_t* a, const uint64_t* b) {
+#pragma unroll
+  for (int w = W - 1; w >= 0; --w)
+    if (a[w] != b[w]) return a[w] < b[w];
+  return false;
+}
+template <int W>
+__device__ __forceinline__ bool bits_equal(const uint64_t* a, const uint64_t* b) {
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+    if (a[w] != b[w]) return false;
+  return true;
 }
 
-// Offer one proof to a best-k list (kept sorted, distinct bitsets).
-__device__ __forceinline__ void topk_offer(TopK& t, int k, uint64_t b, float p) {
+// Ranking of proofs: higher probability first, then smaller set.
+template <int W>
+__device__ __forceinline__ bool proof_before(float pa, const uint64_t* ba, float pb, const uint64_t* bb) {
+  return pa > pb || (pa == pb && bits_less<W>(ba, bb));
+}
+
+// Offer one proof to a best-k list (kept sorted, distinct sets).
+template <int W>
+__device__ __forceinline__ void topk_offer(TopKW<W>& t, int k, const uint64_t* b, float p) {
   for (uint32_t i = 0; i < t.cnt; ++i)
-    if (t.b[i] == b) return;
+    if (bits_equal<W>(t.b + i * W, b)) return;
   int pos = (int)t.cnt;
-  while (pos > 0 && proof_before(p, b, t.p[pos - 1], t.b[pos - 1])) --pos;
+  while (pos > 0 && proof_before<W>(p, b, t.p[pos - 1], t.b + (pos - 1) * W)) --pos;
   if (pos >= k) return;
   int last = (int)t.cnt < k ? (int)t.cnt : k - 1;
   for (int i = last; i > pos; --i) {
-    t.b[i] = t.b[i - 1];
+#pragma unroll
+    for (int w = 0; w < W; ++w) t.b[i * W + w] = t.b[(i - 1) * W + w];
     t.p[i] = t.p[i - 1];
   }
-  t.b[pos] = b;
+#pragma unroll
+  for (int w = 0; w < W; ++w) t.b[pos * W + w] = b[w];
   t.p[pos] = p;
   if ((int)t.cnt < k) ++t.cnt;
 }
 
-__device__ __forceinline__ TopK topk_empty() {
-  TopK t;
+template <int W>
+__device__ __forceinline__ TopKW<W> topk_empty() {
+  TopKW<W> t;
   t.cnt = 0;
-  t.b[0] = t.b[1] = t.b[2] = 0;
+#pragma unroll
+  for (int i = 0; i < 3 * W; ++i) t.b[i] = 0;
   t.p[0] = t.p[1] = t.p[2] = 0.0f;
   return t;
 }
 
 // a x b: the k best distinct unions of one proof of a with one of b.
-__device__ __forceinline__ TopK topk_otimes(const TopK& a, const TopK& b, int k, const float* __restrict__ q) {
-  TopK t = topk_empty();
+template <int W>
+__device__ __forceinline__ TopKW<W> topk_otimes(const TopKW<W>& a, const TopKW<W>& b, int k,
+                                                const float* __restrict__ q) {
+  TopKW<W> t = topk_empty<W>();
   for (uint32_t i = 0; i < a.cnt; ++i)
     for (uint32_t j = 0; j < b.cnt; ++j) {
-      uint64_t u = a.b[i] | b.b[j];
-      topk_offer(t, k, u, proof_prob(u, q));
+      uint64_t u[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) u[w] = a.b[i * W + w] | b.b[j * W + w];
+      topk_offer<W>(t, k, u, proof_prob<W>(u, q));
     }
   return t;
 }
 
 // a + b: the k best distinct proofs of the two lists.
-__device__ __forceinline__ TopK topk_oplus(const TopK& a, const TopK& b, int k) {
-  TopK t = a;
-  for (uint32_t j = 0; j < b.cnt; ++j) topk_offer(t, k, b.b[j], b.p[j]);
+template <int W>
+__device__ __forceinline__ TopKW<W> topk_oplus(const TopKW<W>& a, const TopKW<W>& b, int k) {
+  TopKW<W> t = a;
+  for (uint32_t j = 0; j < b.cnt; ++j) topk_offer<W>(t, k, b.b + j * W, b.p[j]);
   return t;
 }
 
-__device__ __forceinline__ bool topk_same(const TopK& a, const TopK& b) {
+template <int W>
+__device__ __forceinline__ bool topk_same(const TopKW<W>& a, const TopKW<W>& b) {
   if (a.cnt != b.cnt) return false;
   for (uint32_t i = 0; i < a.cnt; ++i)
-    if (a.b[i] != b.b[i]) return false;
+    if (!bits_equal<W>(a.b + i * W, b.b + i * W)) return false;
   return true;
 }
 

@@ -158,8 +158,10 @@ struct Engine {
   std::vector<IndexState> idx;
 
   // top-k: fact probabilities per sample [sample][64] and counters
-  std::vector<float> qtab_h;
+  std::vector<float> qtab_h;        // top-k fact probabilities, [sample][256] (host)
+  std::vector<float> qtab_up;       // the same at the stride in force, as uploaded
   std::vector<uint32_t> topk_next;
+  int topk_words = 1;               // u64 words per top-k proof set in force (1: <= 64 facts per sample, 4: <= 256)
   uint32_t nfacts = 0;  // facts added since the last clear, over all relations (max-min fact numbers)
   DevBuf qtab, grad_fact;
 

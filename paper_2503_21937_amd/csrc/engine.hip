@@ -334,7 +334,7 @@ void Engine::add_facts(const char* relation, size_t n, const uint32_t* sample_id
     throw Error{DL_ERR_CAPACITY, "more than 2^32 - 2 facts"};
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   RelState& R = rel[r];
-  const bool topk = tag_kind == TAG_TOPK;
+  const bool topk = sr == DL_TOPK || sr == DL_DIFF_TOPK;
   std::vector<uint32_t> samp_h;
   std::vector<float> q_h;
   std::vector<uint32_t> local_h;
@@ -348,15 +348,15 @@ void Engine::add_facts(const char* relation, size_t n, const uint32_t* sample_id
     for (size_t i = 0; i < n; ++i) {
       uint32_t s = samp_h[i];
       if (s >= next.size()) next.resize((size_t)s + 1, 0);
-      if (next[s] >= 64)
-        throw Error{DL_ERR_PROOF_OVERFLOW, "sample " + std::to_string(s) + " has more than 64 probabilistic facts"};
+      if (next[s] >= 256)
+        throw Error{DL_ERR_PROOF_OVERFLOW, "sample " + std::to_string(s) + " has more than 256 probabilistic facts"};
       local_h[i] = next[s]++;
     }
     topk_next = next;
-    if (qtab_h.size() < topk_next.size() * 64) qtab_h.resize(topk_next.size() * 64, 0.0f);
+    if (qtab_h.size() < topk_next.size() * 256) qtab_h.resize(topk_next.size() * 256, 0.0f);
     for (size_t i = 0; i < n; ++i) {
-      qtab_h[(size_t)samp_h[i] * 64 + local_h[i]] = q_h[i];
-      R.fact_slot.push_back(samp_h[i] * 64 + local_h[i]);
+      qtab_h[(size_t)samp_h[i] * 256 + local_h[i]] = q_h[i];
+      R.fact_slot.push_back(samp_h[i] * 256 + local_h[i]);  // at the stride in force when read
     }
   }
   const size_t old = R.nraw;
@@ -457,6 +457,7 @@ void Engine::run() {
   stats.items = cfg.items;
   stats.rows = cfg.rows;
   stats.index = cfg.index;
+  stats.topk_words = (sr == DL_TOPK || sr == DL_DIFF_TOPK) ? topk_words : 0;
 }
 
 size_t Engine::relation_size(const char* relation) {
@@ -556,10 +557,14 @@ void Engine::read_grad(const char* in_relation, float* grad_in, int on_device) {
   if (!R.nraw) return;
   if (!grad_in) throw Error{DL_ERR_ARG, "grad_in is NULL"};
   grow(R.grad, R.nraw * 4);
-  if (tag_kind == TAG_TOPK) {
-    // grad_fact is [sample][64]; gather the slots of this relation's facts
+  std::vector<uint32_t> slots;
+  if (sr == DL_TOPK || sr == DL_DIFF_TOPK) {
+    // grad_fact is [sample][64 * W]; gather the slots of this relation's facts
+    const uint32_t qs = 64u * (uint32_t)topk_words;
+    slots.resize(R.nraw);
+    for (size_t i = 0; i < R.nraw; ++i) slots[i] = (R.fact_slot[i] >> 8) * qs + (R.fact_slot[i] & 255u);
     grow(R.fact_slot_d, R.nraw * 4);
-    DL_HIP(hipMemcpyAsync(R.fact_slot_d.p, R.fact_slot.data(), R.nraw * 4, hipMemcpyHostToDevice, stream));
+    DL_HIP(hipMemcpyAsync(R.fact_slot_d.p, slots.data(), R.nraw * 4, hipMemcpyHostToDevice, stream));
     gather(grad_fact.p, R.fact_slot_d.as<uint32_t>(), R.grad.p, R.nraw, 4, stream);
   } else if (tag_kind == TAG_VID) {  // grad_fact is indexed by fact number
     gather(grad_fact.p, R.raw_local.as<uint32_t>(), R.grad.p, R.nraw, 4, stream);

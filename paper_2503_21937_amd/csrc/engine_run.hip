@@ -721,7 +721,7 @@ size_t absorb_sorted(Engine& e, int r) {
   e.stats.candidates += C;
   const int ar = e.prog.rels[r].arity;
   const size_t kb = sizeof(K), tb = e.tag_bytes;
-  const bool use_perm = e.tag_kind == TAG_TOPK || e.tag_kind == TAG_VID || e.record;
+  const bool use_perm = e.tag_kind == TAG_TOPK || e.tag_kind == TAG_TOPK4 || e.tag_kind == TAG_VID || e.record;
   hipStream_t st = e.stream;
 
   K* kp = R.cand_keys.as<K>();
@@ -1296,14 +1296,23 @@ int batch_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
 template <typename K>
 void ingest(Engine& e) {
   hipStream_t st = e.stream;
-  if (e.tag_kind == TAG_TOPK) {
-    size_t q = std::max<size_t>(e.qtab_h.size(), 64);
-    e.grow(e.qtab, q * 4);
-    DL_HIP(hipMemsetAsync(e.qtab.p, 0, q * 4, st));
-    if (!e.qtab_h.empty())
-      DL_HIP(hipMemcpyAsync(e.qtab.p, e.qtab_h.data(), e.qtab_h.size() * 4, hipMemcpyHostToDevice, st));
-    e.grow(e.grad_fact, q * 4);
-    DL_HIP(hipMemsetAsync(e.grad_fact.p, 0, q * 4, st));
+  if (e.sr == DL_TOPK || e.sr == DL_DIFF_TOPK) {
+    // proof sets of one word while every sample has at most 64 probabilistic
+    // facts, else of four (256)
+    uint32_t most = 0;
+    for (uint32_t c : e.topk_next) most = std::max(most, c);
+    const int W = most > 64 ? 4 : 1;
+    e.topk_words = W;
+    e.tag_kind = W == 4 ? TAG_TOPK4 : TAG_TOPK;
+    e.tag_bytes = W == 4 ? sizeof(TopK4) : sizeof(TopK);
+    const size_t ns = std::max<size_t>(e.topk_next.size(), 1), qs = 64 * (size_t)W;
+    e.qtab_up.assign(ns * qs, 0.0f);
+    for (size_t s = 0; s < e.topk_next.size(); ++s)
+      for (size_t i = 0; i < qs; ++i) e.qtab_up[s * qs + i] = e.qtab_h[s * 256 + i];
+    e.grow(e.qtab, ns * qs * 4);
+    DL_HIP(hipMemcpyAsync(e.qtab.p, e.qtab_up.data(), ns * qs * 4, hipMemcpyHostToDevice, st));
+    e.grow(e.grad_fact, ns * qs * 4);
+    DL_HIP(hipMemsetAsync(e.grad_fact.p, 0, ns * qs * 4, st));
   } else if (e.tag_kind == TAG_VID) {  // input gradients by fact number
     const size_t q = (size_t)e.nfacts + 1;
     e.grow(e.grad_fact, q * 4);
@@ -1341,7 +1350,11 @@ void ingest(Engine& e) {
       ftags = R.raw_tags.p;
     } else if (e.tag_kind == TAG_TOPK) {
       e.grow(R.cand_tags, n * sizeof(TopK));
-      topk_from_facts(R.raw_tags.as<float>(), R.raw_local.as<uint32_t>(), n, R.cand_tags.as<TopK>(), st);
+      topk_from_facts<1>(R.raw_tags.as<float>(), R.raw_local.as<uint32_t>(), n, R.cand_tags.as<TopK>(), st);
+      ftags = R.cand_tags.p;
+    } else if (e.tag_kind == TAG_TOPK4) {
+      e.grow(R.cand_tags, n * sizeof(TopK4));
+      topk_from_facts<4>(R.raw_tags.as<float>(), R.raw_local.as<uint32_t>(), n, R.cand_tags.as<TopK4>(), st);
       ftags = R.cand_tags.p;
     } else if (e.tag_kind == TAG_VID) {
       e.grow(R.cand_tags, n * sizeof(VTag));
@@ -1466,7 +1479,9 @@ size_t read_relation_t(Engine& e, int r, size_t capacity, const dl_relation_out*
   const int ar = e.prog.rels[r].arity;
   const KeyLayout lay = e.layout(ar);
   // device staging: columns + sample (u32 each), tags (f32), fact numbers, top-k parts
-  const size_t words = (size_t)(ar + 1) * n + 2 * n + (size_t)e.k * n * 3 + n;
+  const bool topk = e.tag_kind == TAG_TOPK || e.tag_kind == TAG_TOPK4;
+  const size_t W = topk ? (size_t)e.topk_words : 1;
+  const size_t words = (size_t)(ar + 1) * n + 2 * n + (size_t)e.k * n * (2 * W + 1) + n;
   e.grow(e.unpack, words * 4 + 64);
   uint32_t* base = e.unpack.as<uint32_t>();
   uint32_t* dcols[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -1474,11 +1489,11 @@ size_t read_relation_t(Engine& e, int r, size_t capacity, const dl_relation_out*
   float* dtag = reinterpret_cast<float*>(dsample + n);
   uint32_t* dfid = reinterpret_cast<uint32_t*>(dtag + n);
   uint64_t* dbits = reinterpret_cast<uint64_t*>(((uintptr_t)(dfid + n) + 7) & ~(uintptr_t)7);
-  float* dprob = reinterpret_cast<float*>(dbits + (size_t)e.k * n);
+  float* dprob = reinterpret_cast<float*>(dbits + (size_t)e.k * n * W);
   uint8_t* dcnt = reinterpret_cast<uint8_t*>(dprob + (size_t)e.k * n);
   for (int c = 0; c < ar; ++c) dcols[c] = on_device ? out->columns[c] : (out->columns[c] ? base + (size_t)c * n : nullptr);
   uint32_t* samp = on_device ? out->sample_ids : (out->sample_ids ? dsample : nullptr);
-  const bool need_sample = e.tag_kind == TAG_TOPK && e.batched;
+  const bool need_sample = topk && e.batched;
   uint32_t* samp_k = samp ? samp : (need_sample ? dsample : nullptr);
   unpack_rows<K>(R.full.keys.as<K>(), n, lay, dcols, e.batched ? samp_k : nullptr, st);
   if (!e.batched && samp) DL_HIP(hipMemsetAsync(samp, 0, n * 4, st));
@@ -1489,16 +1504,20 @@ size_t read_relation_t(Engine& e, int r, size_t capacity, const dl_relation_out*
     if (e.tag_kind == TAG_F32) DL_HIP(hipMemcpyAsync(tg, R.full.tags.p, n * 4, hipMemcpyDeviceToDevice, st));
     else if (e.tag_kind == TAG_NONE) fill_f32(tg, n, 1.0f, st);
     else if (e.tag_kind == TAG_VID) vtag_split(R.full.tags.as<VTag>(), n, tg, nullptr, st);
-    else topk_probability(R.full.tags.as<TopK>(), e.batched ? samp_k : nullptr, n, e.qtab.as<float>(), tg, st);
+    else if (e.tag_kind == TAG_TOPK)
+      topk_probability<1>(R.full.tags.as<TopK>(), e.batched ? samp_k : nullptr, n, e.qtab.as<float>(), tg, st);
+    else
+      topk_probability<4>(R.full.tags.as<TopK4>(), e.batched ? samp_k : nullptr, n, e.qtab.as<float>(), tg, st);
   }
   uint8_t* oc = nullptr;
   uint64_t* ob = nullptr;
   float* op = nullptr;
-  if (e.tag_kind == TAG_TOPK) {
+  if (topk) {
     oc = out->topk_count ? (on_device ? out->topk_count : dcnt) : nullptr;
     ob = out->topk_bits ? (on_device ? out->topk_bits : dbits) : nullptr;
     op = out->topk_prob ? (on_device ? out->topk_prob : dprob) : nullptr;
-    if (oc || ob || op) topk_split(R.full.tags.as<TopK>(), n, e.k, oc, ob, op, st);
+    if ((oc || ob || op) && W == 1) topk_split<1>(R.full.tags.as<TopK>(), n, e.k, oc, ob, op, st);
+    else if (oc || ob || op) topk_split<4>(R.full.tags.as<TopK4>(), n, e.k, oc, ob, op, st);
   }
   if (!on_device) {
     auto d2h = [&](void* dst, const void* src, size_t bytes) {
@@ -1511,9 +1530,9 @@ size_t read_relation_t(Engine& e, int r, size_t capacity, const dl_relation_out*
     }
     d2h(out->tags, dtag, n * 4);
     if (fi) d2h(out->fact_ids, dfid, n * 4);
-    if (e.tag_kind == TAG_TOPK) {
+    if (topk) {
       d2h(out->topk_count, dcnt, n);
-      d2h(out->topk_bits, dbits, (size_t)e.k * n * 8);
+      d2h(out->topk_bits, dbits, (size_t)e.k * n * W * 8);
       d2h(out->topk_prob, dprob, (size_t)e.k * n * 4);
     }
   }
@@ -1630,8 +1649,12 @@ void backward_t(Engine& e, int r, const float* gout, const int64_t* rows, size_t
   const size_t n = R.full.n;
   hipStream_t st = e.stream;
   if (e.sr == DL_DIFF_TOPK && rows) {
-    topk_backward_rows<K>(R.full.tags.as<TopK>(), R.full.keys.as<K>(), e.layout(e.prog.rels[r].arity), rows, gout,
-                          nrows, n, e.qtab.as<float>(), e.grad_fact.as<float>(), st);
+    if (e.topk_words == 1)
+      topk_backward_rows<K, 1>(R.full.tags.as<TopK>(), R.full.keys.as<K>(), e.layout(e.prog.rels[r].arity), rows,
+                               gout, nrows, n, e.qtab.as<float>(), e.grad_fact.as<float>(), st);
+    else
+      topk_backward_rows<K, 4>(R.full.tags.as<TopK4>(), R.full.keys.as<K>(), e.layout(e.prog.rels[r].arity), rows,
+                               gout, nrows, n, e.qtab.as<float>(), e.grad_fact.as<float>(), st);
     return;
   }
   if (e.sr == DL_DIFF_MAXMIN) {  // the gradient of a row goes to the fact its tag comes from
@@ -1646,7 +1669,10 @@ void backward_t(Engine& e, int r, const float* gout, const int64_t* rows, size_t
       uint32_t* cols[4] = {nullptr, nullptr, nullptr, nullptr};
       unpack_rows<K>(R.full.keys.as<K>(), n, e.layout(e.prog.rels[r].arity), cols, samp, st);
     }
-    topk_backward(R.full.tags.as<TopK>(), samp, gout, n, e.qtab.as<float>(), e.grad_fact.as<float>(), st);
+    if (e.topk_words == 1)
+      topk_backward<1>(R.full.tags.as<TopK>(), samp, gout, n, e.qtab.as<float>(), e.grad_fact.as<float>(), st);
+    else
+      topk_backward<4>(R.full.tags.as<TopK4>(), samp, gout, n, e.qtab.as<float>(), e.grad_fact.as<float>(), st);
     return;
   }
   // diff add-mult: seed, sweep the recorded derivations in reverse, collect

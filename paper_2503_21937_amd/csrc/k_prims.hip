@@ -356,8 +356,10 @@ void gather(const void* in, const uint32_t* idx, void* out, size_t n, size_t byt
     k_gather<uint32_t><<<grid_for(n), BLOCK, 0, st>>>((const uint32_t*)in, idx, (uint32_t*)out, n);
   else if (bytes == 8)
     k_gather<uint64_t><<<grid_for(n), BLOCK, 0, st>>>((const uint64_t*)in, idx, (uint64_t*)out, n);
-  else
+  else if (bytes == sizeof(TopK))
     k_gather<TopK><<<grid_for(n), BLOCK, 0, st>>>((const TopK*)in, idx, (TopK*)out, n);
+  else
+    k_gather<TopK4><<<grid_for(n), BLOCK, 0, st>>>((const TopK4*)in, idx, (TopK4*)out, n);
 }
 
 __global__ void k_max(const uint32_t* __restrict__ in, size_t n, uint32_t* out) {
@@ -432,8 +434,10 @@ void compact(const void* in, const uint32_t* flags, const uint32_t* pos, size_t 
     k_compact<uint32_t><<<grid_for(n), BLOCK, 0, st>>>((const uint32_t*)in, flags, pos, n, (uint32_t*)out);
   else if (bytes == 8)
     k_compact<uint64_t><<<grid_for(n), BLOCK, 0, st>>>((const uint64_t*)in, flags, pos, n, (uint64_t*)out);
-  else
+  else if (bytes == sizeof(TopK))
     k_compact<TopK><<<grid_for(n), BLOCK, 0, st>>>((const TopK*)in, flags, pos, n, (TopK*)out);
+  else
+    k_compact<TopK4><<<grid_for(n), BLOCK, 0, st>>>((const TopK4*)in, flags, pos, n, (TopK4*)out);
 }
 
 __global__ void k_status_flags(const uint32_t* __restrict__ status, size_t n, uint32_t mask,

@@ -8,6 +8,17 @@
 
 namespace dlfix {
 
+// Bytes of one tag of a kind (algorithmic byte counts of the kernels).
+static double tag_size(int tk) {
+  switch (tk) {
+    case TAG_NONE: return 0.0;
+    case TAG_F32: return 4.0;
+    case TAG_VID: return (double)sizeof(VTag);
+    case TAG_TOPK: return (double)sizeof(TopK);
+    default: return (double)sizeof(TopK4);
+  }
+}
+
 template <typename K>
 __global__ void k_pack(const uint32_t* c0, const uint32_t* c1, const uint32_t* c2, const uint32_t* c3,
                        const uint32_t* sample, size_t n, KeyLayout l, K* keys) {
@@ -336,7 +347,7 @@ void join_expand(const JoinArgs& a, int tk, const uint32_t* offs, size_t total, 
   if (!total) return;
   const int items = a.items == 1 || a.items == 2 || a.items == 8 ? a.items : 4;
   const size_t nb = (total + (size_t)BLOCK * items - 1) / ((size_t)BLOCK * items);
-  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : tk == TAG_VID ? 8.0 : (double)sizeof(TopK);
+  const double tb = tag_size(tk);
   // algorithmic bytes of a join: probe rows read once (key + tag), every
   // derivation once (key + tag, plus its two lineage ids when recorded)
   const double bytes = total * (sizeof(K) + tb + (ol ? 8.0 : 0.0)) + a.n * (sizeof(K) + tb);
@@ -347,8 +358,10 @@ void join_expand(const JoinArgs& a, int tk, const uint32_t* offs, size_t total, 
     k_join_expand<K, TAG_F32, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (float*)otags, ol, orr);   \
   else if (tk == TAG_VID)                                                                                      \
     k_join_expand<K, TAG_VID, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (VTag*)otags, ol, orr);    \
+  else if (tk == TAG_TOPK)                                                                                     \
+    k_join_expand<K, TAG_TOPK, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (TopK*)otags, ol, orr);   \
   else                                                                                                         \
-    k_join_expand<K, TAG_TOPK, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (TopK*)otags, ol, orr);
+    k_join_expand<K, TAG_TOPK4, IT><<<nb, BLOCK, 0, st>>>(a, offs, total, (K*)okeys, (TopK4*)otags, ol, orr);
   DL_PROF_BEGIN(1, st);
   switch (items) {
     case 1: DL_EXPAND(1) break;
@@ -388,8 +401,10 @@ void project_rows(const JoinArgs& a, int tk, void* okeys, void* otags, uint32_t*
     k_project<K, TAG_F32><<<grid_for(a.n), BLOCK, 0, st>>>(a, (K*)okeys, (float*)otags, ol, orr);
   else if (tk == TAG_VID)
     k_project<K, TAG_VID><<<grid_for(a.n), BLOCK, 0, st>>>(a, (K*)okeys, (VTag*)otags, ol, orr);
-  else
+  else if (tk == TAG_TOPK)
     k_project<K, TAG_TOPK><<<grid_for(a.n), BLOCK, 0, st>>>(a, (K*)okeys, (TopK*)otags, ol, orr);
+  else
+    k_project<K, TAG_TOPK4><<<grid_for(a.n), BLOCK, 0, st>>>(a, (K*)okeys, (TopK4*)otags, ol, orr);
 }
 
 // ------------------------------------------------------------- reduction
@@ -433,7 +448,7 @@ template <typename K>
 void segment_reduce(const K* keys, const uint32_t* pos, const uint32_t* flags, size_t n, int tk, int sr, int k,
                     const void* tags, const uint32_t* perm, K* kout, void* tout, size_t nout, hipStream_t st) {
   if (!n) return;
-  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : tk == TAG_VID ? 8.0 : (double)sizeof(TopK);
+  const double tb = tag_size(tk);
   DL_PROF_BEGIN(5, st);
   if (tk == TAG_NONE)
     k_segment_reduce<K, TAG_NONE><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const NoTag*)tags, perm,
@@ -444,9 +459,12 @@ void segment_reduce(const K* keys, const uint32_t* pos, const uint32_t* flags, s
   else if (tk == TAG_VID)
     k_segment_reduce<K, TAG_VID><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const VTag*)tags, perm,
                                                                 kout, (VTag*)tout);
-  else
+  else if (tk == TAG_TOPK)
     k_segment_reduce<K, TAG_TOPK><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const TopK*)tags, perm,
                                                                  kout, (TopK*)tout);
+  else
+    k_segment_reduce<K, TAG_TOPK4><<<grid_for(n), BLOCK, 0, st>>>(keys, pos, flags, n, sr, k, (const TopK4*)tags,
+                                                                  perm, kout, (TopK4*)tout);
   DL_PROF_END(5, st, n * (sizeof(K) + 8.0 + tb + (perm ? 4.0 : 0.0)) + nout * (sizeof(K) + tb));
 }
 
@@ -533,7 +551,7 @@ void diff_merge(const K* uk, const void* ut, size_t nu, const K* fk, void* ft, s
                 bool converge, uint32_t* status, uint32_t* fpos, hipStream_t st) {
   if (!nu) return;
   size_t nb = (nu + DIFF_TILE - 1) / DIFF_TILE;
-  const double tb = tk == TAG_NONE ? 0.0 : tk == TAG_F32 ? 4.0 : tk == TAG_VID ? 8.0 : (double)sizeof(TopK);
+  const double tb = tag_size(tk);
   DL_PROF_BEGIN(6, st);
   if (tk == TAG_NONE)
     k_diff<K, TAG_NONE><<<nb, BLOCK, 0, st>>>(uk, (NoTag*)ut, nu, fk, (NoTag*)ft, nf, sr, k, converge, status, fpos);
@@ -541,8 +559,10 @@ void diff_merge(const K* uk, const void* ut, size_t nu, const K* fk, void* ft, s
     k_diff<K, TAG_F32><<<nb, BLOCK, 0, st>>>(uk, (float*)ut, nu, fk, (float*)ft, nf, sr, k, converge, status, fpos);
   else if (tk == TAG_VID)
     k_diff<K, TAG_VID><<<nb, BLOCK, 0, st>>>(uk, (VTag*)ut, nu, fk, (VTag*)ft, nf, sr, k, converge, status, fpos);
-  else
+  else if (tk == TAG_TOPK)
     k_diff<K, TAG_TOPK><<<nb, BLOCK, 0, st>>>(uk, (TopK*)ut, nu, fk, (TopK*)ft, nf, sr, k, converge, status, fpos);
+  else
+    k_diff<K, TAG_TOPK4><<<nb, BLOCK, 0, st>>>(uk, (TopK4*)ut, nu, fk, (TopK4*)ft, nf, sr, k, converge, status, fpos);
   DL_PROF_END(6, st, nu * (sizeof(K) + tb + 4.0) + (double)nf * sizeof(K));
 }
 
@@ -631,6 +651,8 @@ __global__ __launch_bounds__(BLOCK) void k_merge(const K* __restrict__ ak, const
       reinterpret_cast<uint64_t*>(ot)[o] = reinterpret_cast<const uint64_t*>(fromA ? at : bt)[g];
     } else if (tag_bytes == (int)sizeof(TopK)) {
       reinterpret_cast<TopK*>(ot)[o] = reinterpret_cast<const TopK*>(fromA ? at : bt)[g];
+    } else if (tag_bytes == (int)sizeof(TopK4)) {
+      reinterpret_cast<TopK4*>(ot)[o] = reinterpret_cast<const TopK4*>(fromA ? at : bt)[g];
     }
   }
 }
@@ -743,95 +765,126 @@ void gather_add_clamped(const uint32_t* ids, const float* adj, const float* tag,
 }
 
 // ------------------------------------------------------------------ top-k
+// W 64-bit words per proof set; a sample's fact probabilities are the 64 * W
+// floats at qtab + sample * 64 * W.
+template <int W>
 __global__ void k_topk_from_facts(const float* __restrict__ q, const uint32_t* __restrict__ local, size_t n,
-                                  TopK* __restrict__ out) {
+                                  TopKW<W>* __restrict__ out) {
   GRID_STRIDE(i, n) {
-    TopK t = topk_empty();
+    TopKW<W> t = topk_empty<W>();
     t.cnt = 1;
-    t.b[0] = 1ull << local[i];
+    t.b[local[i] >> 6] = 1ull << (local[i] & 63u);
     t.p[0] = q[i];
     out[i] = t;
   }
 }
 
-void topk_from_facts(const float* q, const uint32_t* local, size_t n, TopK* out, hipStream_t st) {
-  if (n) k_topk_from_facts<<<grid_for(n), BLOCK, 0, st>>>(q, local, n, out);
+template <int W>
+void topk_from_facts(const float* q, const uint32_t* local, size_t n, TopKW<W>* out, hipStream_t st) {
+  if (n) k_topk_from_facts<W><<<grid_for(n), BLOCK, 0, st>>>(q, local, n, out);
 }
 
 // P = sum over non-empty subsets S of the kept proofs of (-1)^(|S|+1) times
-// the product of the probabilities of the facts in their union.
-__device__ double incl_excl(const TopK& t, const float* q, int skip_bit, double* dP) {
+// the product of the probabilities of the facts in their union.  With
+// skip_bit >= 0: adds to *dP the derivative of P by that fact's probability.
+template <int W>
+__device__ double incl_excl(const TopKW<W>& t, const float* q, int skip_bit, double* dP) {
   double P = 0;
   for (uint32_t S = 1; S < (1u << t.cnt); ++S) {
-    uint64_t u = 0;
-    for (uint32_t i = 0; i < t.cnt; ++i)
-      if (S >> i & 1u) u |= t.b[i];
+    uint64_t u[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      u[w] = 0;
+      for (uint32_t i = 0; i < t.cnt; ++i)
+        if (S >> i & 1u) u[w] |= t.b[i * W + w];
+    }
     double prod = 1.0;
-    uint64_t b = u;
-    while (b) {
-      int i = __builtin_ctzll(b);
-      if (i != skip_bit) prod *= (double)q[i];
-      b &= b - 1;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      uint64_t b = u[w];
+      while (b) {
+        const int i = w * 64 + __builtin_ctzll(b);
+        if (i != skip_bit) prod *= (double)q[i];
+        b &= b - 1;
+      }
     }
     double sign = (__popc(S) & 1) ? 1.0 : -1.0;
     if (skip_bit < 0) P += sign * prod;
-    else if (u >> skip_bit & 1ull) *dP += sign * prod;
+    else if (u[skip_bit >> 6] >> (skip_bit & 63) & 1ull) *dP += sign * prod;
   }
   return P;
 }
 
-__global__ void k_topk_prob(const TopK* __restrict__ t, const uint32_t* __restrict__ sample, size_t n,
+template <int W>
+__global__ void k_topk_prob(const TopKW<W>* __restrict__ t, const uint32_t* __restrict__ sample, size_t n,
                             const float* __restrict__ qtab, float* __restrict__ prob) {
   GRID_STRIDE(i, n) {
-    const float* q = qtab + (size_t)(sample ? sample[i] : 0u) * 64;
-    prob[i] = (float)incl_excl(t[i], q, -1, nullptr);
+    const float* q = qtab + (size_t)(sample ? sample[i] : 0u) * 64 * W;
+    prob[i] = (float)incl_excl<W>(t[i], q, -1, nullptr);
   }
 }
 
-void topk_probability(const TopK* t, const uint32_t* sample, size_t n, const float* qtab, float* prob,
+template <int W>
+void topk_probability(const TopKW<W>* t, const uint32_t* sample, size_t n, const float* qtab, float* prob,
                       hipStream_t st) {
-  if (n) k_topk_prob<<<grid_for(n), BLOCK, 0, st>>>(t, sample, n, qtab, prob);
+  if (n) k_topk_prob<W><<<grid_for(n), BLOCK, 0, st>>>(t, sample, n, qtab, prob);
 }
 
-__global__ void k_topk_split(const TopK* __restrict__ t, size_t n, int k, uint8_t* cnt, uint64_t* bits, float* prob) {
+// word w of proof j of row i at bits[(j * n + i) * W + w]
+template <int W>
+__global__ void k_topk_split(const TopKW<W>* __restrict__ t, size_t n, int k, uint8_t* cnt, uint64_t* bits,
+                             float* prob) {
   GRID_STRIDE(i, n) {
-    TopK x = t[i];
+    const TopKW<W> x = t[i];
     if (cnt) cnt[i] = (uint8_t)x.cnt;
     for (int j = 0; j < k; ++j) {
-      if (bits) bits[(size_t)j * n + i] = (uint32_t)j < x.cnt ? x.b[j] : 0ull;
+      if (bits)
+        for (int w = 0; w < W; ++w) bits[((size_t)j * n + i) * W + w] = (uint32_t)j < x.cnt ? x.b[j * W + w] : 0ull;
       if (prob) prob[(size_t)j * n + i] = (uint32_t)j < x.cnt ? x.p[j] : 0.0f;
     }
   }
 }
 
-void topk_split(const TopK* t, size_t n, int k, uint8_t* cnt, uint64_t* bits, float* prob, hipStream_t st) {
-  if (n) k_topk_split<<<grid_for(n), BLOCK, 0, st>>>(t, n, k, cnt, bits, prob);
+template <int W>
+void topk_split(const TopKW<W>* t, size_t n, int k, uint8_t* cnt, uint64_t* bits, float* prob, hipStream_t st) {
+  if (n) k_topk_split<W><<<grid_for(n), BLOCK, 0, st>>>(t, n, k, cnt, bits, prob);
 }
 
-__global__ void k_topk_backward(const TopK* __restrict__ t, const uint32_t* __restrict__ sample,
+// The gradient of one row's probability: every fact of its kept proofs
+// gets g * dP/dq (proofs held fixed); grad is [sample][64 * W].
+template <int W>
+__device__ void topk_row_backward(const TopKW<W>& x, uint32_t s, float g, const float* __restrict__ qtab,
+                                  float* grad) {
+  const float* q = qtab + (size_t)s * 64 * W;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    uint64_t all = 0;
+    for (uint32_t j = 0; j < x.cnt; ++j) all |= x.b[j * W + w];
+    while (all) {
+      const int bit = w * 64 + __builtin_ctzll(all);
+      all &= all - 1;
+      double d = 0;
+      incl_excl<W>(x, q, bit, &d);
+      atomicAdd(&grad[(size_t)s * 64 * W + bit], (float)((double)g * d));
+    }
+  }
+}
+
+template <int W>
+__global__ void k_topk_backward(const TopKW<W>* __restrict__ t, const uint32_t* __restrict__ sample,
                                 const float* __restrict__ gout, size_t n, const float* __restrict__ qtab,
                                 float* grad) {
   GRID_STRIDE(i, n) {
     const float g = gout[i];
     if (g == 0.0f) continue;
-    const TopK x = t[i];
-    const uint32_t s = sample ? sample[i] : 0u;
-    const float* q = qtab + (size_t)s * 64;
-    uint64_t all = 0;
-    for (uint32_t j = 0; j < x.cnt; ++j) all |= x.b[j];
-    while (all) {
-      int bit = __builtin_ctzll(all);
-      all &= all - 1;
-      double d = 0;
-      incl_excl(x, q, bit, &d);
-      atomicAdd(&grad[(size_t)s * 64 + bit], (float)((double)g * d));
-    }
+    topk_row_backward<W>(t[i], sample ? sample[i] : 0u, g, qtab, grad);
   }
 }
 
-void topk_backward(const TopK* t, const uint32_t* sample, const float* gout, size_t n, const float* qtab,
+template <int W>
+void topk_backward(const TopKW<W>* t, const uint32_t* sample, const float* gout, size_t n, const float* qtab,
                    float* grad, hipStream_t st) {
-  if (n) k_topk_backward<<<grid_for(n), BLOCK, 0, st>>>(t, sample, gout, n, qtab, grad);
+  if (n) k_topk_backward<W><<<grid_for(n), BLOCK, 0, st>>>(t, sample, gout, n, qtab, grad);
 }
 
 // ------------------------------------------------------------ point queries
@@ -868,7 +921,10 @@ __global__ void k_lookup(const K* __restrict__ keys, size_t n, QCols qc, size_t 
         if (tk == TAG_F32) t = ((const float*)tags)[lo];
         else if (tk == TAG_VID) t = ((const VTag*)tags)[lo].v;
         else if (tk == TAG_NONE) t = 1.0f;
-        else t = (float)incl_excl(((const TopK*)tags)[lo], qtab + (size_t)key_sample(q, lay) * 64, -1, nullptr);
+        else if (tk == TAG_TOPK)
+          t = (float)incl_excl<1>(((const TopK*)tags)[lo], qtab + (size_t)key_sample(q, lay) * 64, -1, nullptr);
+        else
+          t = (float)incl_excl<4>(((const TopK4*)tags)[lo], qtab + (size_t)key_sample(q, lay) * 256, -1, nullptr);
       }
       qtag[i] = t;
     }
@@ -930,33 +986,22 @@ void scatter_add_rows(const uint32_t* ids, const int64_t* rows, const float* g, 
   if (n) k_scatter_add_rows<<<grid_for(n), BLOCK, 0, st>>>(ids, rows, g, n, nrel, adj);
 }
 
-template <typename K>
-__global__ void k_topk_backward_rows(const TopK* __restrict__ t, const K* __restrict__ keys, KeyLayout lay,
+template <typename K, int W>
+__global__ void k_topk_backward_rows(const TopKW<W>* __restrict__ t, const K* __restrict__ keys, KeyLayout lay,
                                      const int64_t* __restrict__ rows, const float* __restrict__ gout, size_t n,
                                      size_t nrel, const float* __restrict__ qtab, float* grad) {
   GRID_STRIDE(i, n) {
     const float g = gout[i];
     if (g == 0.0f || rows[i] < 0 || (uint64_t)rows[i] >= nrel) continue;
     const size_t r = (size_t)rows[i];
-    const TopK x = t[r];
-    const uint32_t s = key_sample(keys[r], lay);
-    const float* q = qtab + (size_t)s * 64;
-    uint64_t all = 0;
-    for (uint32_t j = 0; j < x.cnt; ++j) all |= x.b[j];
-    while (all) {
-      int bit = __builtin_ctzll(all);
-      all &= all - 1;
-      double d = 0;
-      incl_excl(x, q, bit, &d);
-      atomicAdd(&grad[(size_t)s * 64 + bit], (float)((double)g * d));
-    }
+    topk_row_backward<W>(t[r], key_sample(keys[r], lay), g, qtab, grad);
   }
 }
 
-template <typename K>
-void topk_backward_rows(const TopK* t, const K* keys, KeyLayout lay, const int64_t* rows, const float* g, size_t n,
-                        size_t nrel, const float* qtab, float* grad_fact, hipStream_t st) {
-  if (n) k_topk_backward_rows<K><<<grid_for(n), BLOCK, 0, st>>>(t, keys, lay, rows, g, n, nrel, qtab, grad_fact);
+template <typename K, int W>
+void topk_backward_rows(const TopKW<W>* t, const K* keys, KeyLayout lay, const int64_t* rows, const float* g,
+                        size_t n, size_t nrel, const float* qtab, float* grad_fact, hipStream_t st) {
+  if (n) k_topk_backward_rows<K, W><<<grid_for(n), BLOCK, 0, st>>>(t, keys, lay, rows, g, n, nrel, qtab, grad_fact);
 }
 
 // -------------------------------------------------- differentiable max-min
@@ -1023,10 +1068,20 @@ void vtag_backward(const VTag* t, const int64_t* rows, const float* g, size_t n,
 #define INST2(K)                                                                                                 \
   template void lookup_rows<K>(const K*, size_t, const uint32_t* const*, const uint32_t*, size_t, int,           \
                                const void*, KeyLayout, const float*, int64_t*, float*, hipStream_t);                                                    \
-  template void topk_backward_rows<K>(const TopK*, const K*, KeyLayout, const int64_t*, const float*, size_t,     \
-                                      size_t,                                                                      \
-                                      const float*, float*, hipStream_t);
+  template void topk_backward_rows<K, 1>(const TopK*, const K*, KeyLayout, const int64_t*, const float*, size_t,  \
+                                         size_t, const float*, float*, hipStream_t);                               \
+  template void topk_backward_rows<K, 4>(const TopK4*, const K*, KeyLayout, const int64_t*, const float*, size_t, \
+                                         size_t, const float*, float*, hipStream_t);
 
+#define INST_W(W)                                                                                                \
+  template void topk_from_facts<W>(const float*, const uint32_t*, size_t, TopKW<W>*, hipStream_t);                \
+  template void topk_probability<W>(const TopKW<W>*, const uint32_t*, size_t, const float*, float*, hipStream_t);  \
+  template void topk_split<W>(const TopKW<W>*, size_t, int, uint8_t*, uint64_t*, float*, hipStream_t);            \
+  template void topk_backward<W>(const TopKW<W>*, const uint32_t*, const float*, size_t, const float*, float*,    \
+                                 hipStream_t);
+
+INST_W(1)
+INST_W(4)
 INST(uint32_t)
 INST(uint64_t)
 INST2(uint32_t)

@@ -7,7 +7,10 @@
 
 namespace dlfix {
 
-struct TopK;
+template <int W>
+struct TopKW;
+using TopK = TopKW<1>;   // top-k proofs over up to 64 facts per sample
+using TopK4 = TopKW<4>;  // over up to 256
 
 // ------------------------------------------------------------- primitives
 // Scratch words a scan of n values needs (u64 units).
@@ -30,7 +33,7 @@ void radix_sort(K** keys, uint32_t** vals, K** keys_alt, uint32_t** vals_alt, si
 void iota_u32(uint32_t* out, size_t n, uint32_t start, hipStream_t st);
 void fill_u32(uint32_t* out, size_t n, uint32_t v, hipStream_t st);
 void fill_f32(float* out, size_t n, float v, hipStream_t st);
-// out[i] = in[idx[i]] for element size `bytes` in {4, 8, sizeof(TopK)}.
+// out[i] = in[idx[i]] for element size `bytes` in {4, 8, sizeof(TopK), sizeof(TopK4)}.
 void gather(const void* in, const uint32_t* idx, void* out, size_t n, size_t bytes, hipStream_t st);
 // Max over n u32 values into *d_out (atomic max; *d_out must be initialised).
 void max_u32(const uint32_t* in, size_t n, uint32_t* d_out, hipStream_t st);
@@ -81,7 +84,8 @@ void hash_build(const K* keys, size_t n, int total_bits, int prefix_bits, HSlot*
                 hipStream_t st);
 
 // Tag payload kinds of the relational kernels.
-enum TagKind : int { TAG_NONE = 0, TAG_F32 = 1, TAG_TOPK = 2, TAG_VID = 3 };  // TAG_VID: VTag (value, fact)
+// TAG_VID: VTag (value, fact); TAG_TOPK4: top-k over up to 256 facts per sample
+enum TagKind : int { TAG_NONE = 0, TAG_F32 = 1, TAG_TOPK = 2, TAG_VID = 3, TAG_TOPK4 = 4 };
 
 // Expression evaluation at a plan's output (Sec. 5: a bytecode program for a
 // small stack machine run by each thread on one output row; Sec. 3.3
@@ -395,20 +399,27 @@ void lookup_rows(const K* keys, size_t n, const uint32_t* const* qcols, const ui
 void scatter_add_rows(const uint32_t* ids, const int64_t* rows, const float* g, size_t n, size_t nrel, float* adj,
                       hipStream_t st);
 // top-k gradient seeded on selected rows of a relation of nrel rows
-template <typename K>
-void topk_backward_rows(const TopK* t, const K* keys, KeyLayout lay, const int64_t* rows, const float* g, size_t n,
-                        size_t nrel, const float* qtab, float* grad_fact, hipStream_t st);
+template <typename K, int W>
+void topk_backward_rows(const TopKW<W>* t, const K* keys, KeyLayout lay, const int64_t* rows, const float* g,
+                        size_t n, size_t nrel, const float* qtab, float* grad_fact, hipStream_t st);
 
 // ---------------------------------------------------------- tags & grads
-// Input facts -> tags: f32 copy (bool: none); top-k: [(1 << local_id, q)].
-void topk_from_facts(const float* q, const uint32_t* local_id, size_t n, TopK* out, hipStream_t st);
+// Top-k with W words per proof set; qtab and grad_fact are [sample][64 * W].
+// Input facts -> tags: [({local_id}, q)].
+template <int W>
+void topk_from_facts(const float* q, const uint32_t* local_id, size_t n, TopKW<W>* out, hipStream_t st);
 // Inclusion-exclusion probability of each row's kept proofs (binary64).
-void topk_probability(const TopK* t, const uint32_t* sample, size_t n, const float* qtab, float* prob,
+template <int W>
+void topk_probability(const TopKW<W>* t, const uint32_t* sample, size_t n, const float* qtab, float* prob,
                       hipStream_t st);
-void topk_split(const TopK* t, size_t n, int k, uint8_t* cnt, uint64_t* bits, float* prob, hipStream_t st);
+// Proof counts, sets (word w of proof j of row i at bits[(j*n + i)*W + w])
+// and probabilities.
+template <int W>
+void topk_split(const TopKW<W>* t, size_t n, int k, uint8_t* cnt, uint64_t* bits, float* prob, hipStream_t st);
 // grad of the inclusion-exclusion probability w.r.t. fact probabilities,
-// scattered into grad_fact[sample*64 + bit].
-void topk_backward(const TopK* t, const uint32_t* sample, const float* gout, size_t n, const float* qtab,
+// scattered into grad_fact[sample * 64 * W + fact].
+template <int W>
+void topk_backward(const TopKW<W>* t, const uint32_t* sample, const float* gout, size_t n, const float* qtab,
                    float* grad_fact, hipStream_t st);
 
 // Add-mult lineage: for derivation i of tuple owner[i] with body tuples

@@ -164,6 +164,10 @@ template <>
 struct TagOf<TAG_VID> {
   using T = VTag;
 };
+template <>
+struct TagOf<TAG_TOPK4> {
+  using T = TopK4;
+};
 
 template <int TK>
 __device__ __forceinline__ typename TagOf<TK>::T tag_otimes(const typename TagOf<TK>::T& x,
@@ -173,6 +177,8 @@ __device__ __forceinline__ typename TagOf<TK>::T tag_otimes(const typename TagOf
     return f_otimes(a.sr, x, y);
   } else if constexpr (TK == TAG_TOPK) {
     return topk_otimes(x, y, a.k, a.q + (size_t)sample * 64);
+  } else if constexpr (TK == TAG_TOPK4) {
+    return topk_otimes(x, y, a.k, a.q + (size_t)sample * 256);
   } else if constexpr (TK == TAG_VID) {
     return vtag_pick(x, y, false);
   } else {

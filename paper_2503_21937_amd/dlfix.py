@@ -58,7 +58,8 @@ class Stats(C.Structure):
                 ("key_bits", C.c_uint32), ("id_bits", C.c_uint32), ("sample_bits", C.c_uint32),
                 ("dedup", C.c_int), ("orient", C.c_int), ("items", C.c_int), ("tuned_ms", C.c_double),
                 ("lineage_mode", C.c_int), ("rows", C.c_int),
-                ("device_allocs", C.c_uint64), ("workspace_peak", C.c_uint64), ("index", C.c_int)]
+                ("device_allocs", C.c_uint64), ("workspace_peak", C.c_uint64), ("index", C.c_int),
+                ("topk_words", C.c_int)]
 
 
 _lib = None
@@ -240,7 +241,8 @@ class Engine:
 
     def read(self, rel: str, device: bool = False) -> dict:
         """Relation in canonical order: dict(sample, cols (n x arity), tags,
-        for top-k cnt (n), bits (n x k), p (n x k), and for differentiable
+        for top-k cnt (n), bits (n x k; n x k x 4 when a sample has more than
+        64 probabilistic facts: word w of each proof set), p (n x k), and for differentiable
         max-min fid (n): the number of the input fact each tag comes from)."""
         n = self.size(rel)
         ar = self.arity[rel]
@@ -255,8 +257,10 @@ class Engine:
             u32, f32, u8, u64 = np.uint32, np.float32, np.uint8, np.uint64
         out = dict(sample=mk(n, u32), cols=[mk(n, u32) for _ in range(ar)], tags=mk(n, f32))
         vid = self.semiring == "diff_maxmin"
+        words = self.stats()["topk_words"] if topk else 1
         if topk:
-            out.update(cnt=mk(n, u8), bits=mk((self.k, n), u64), p=mk((self.k, n), f32))
+            shape = (self.k, n) if words == 1 else (self.k, n, words)
+            out.update(cnt=mk(n, u8), bits=mk(shape, u64), p=mk((self.k, n), f32))
         if vid:
             out["fid"] = mk(n, u32)
         ro = RelationOut()
@@ -278,7 +282,7 @@ class Engine:
         if not device:
             out["cols"] = np.stack(out["cols"], 1) if ar else np.zeros((n, 0), np.uint32)
             if topk:
-                out["bits"] = out["bits"].T.copy()
+                out["bits"] = (out["bits"].T if words == 1 else out["bits"].transpose(1, 0, 2)).copy()
                 out["p"] = out["p"].T.copy()
         return out
 

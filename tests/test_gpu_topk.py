@@ -48,9 +48,11 @@ def test_topk_scenes(oracle, synth, k, samples):
 
 
 def test_proof_overflow(synth):
+    """A sample may hold 256 probabilistic facts (four-word proof sets), not 257."""
     from paper_2503_21937_amd import dlfix
     e = dlfix.Engine(synth.TC_PROGRAM, "topk")
-    src = np.arange(65, dtype=np.uint32)
+    src = np.arange(257, dtype=np.uint32)
+    e.add_facts("edge", [src[:256], src[:256] + 1], np.full(256, 0.5, np.float32))
     with pytest.raises(dlfix.DLError) as ex:
-        e.add_facts("edge", [src, src + 1], np.full(65, 0.5, np.float32))
+        e.add_facts("edge", [src[256:], src[256:] + 1], np.full(1, 0.5, np.float32))
     assert ex.value.status == 7
