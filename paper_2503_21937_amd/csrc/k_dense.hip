@@ -387,6 +387,7 @@ constexpr int RW_KEYS = 1 << RW_BITS;
 constexpr int RW_ROWS = 255;   // driver rows of a group staged in LDS (4 workgroups fit a CU)
 constexpr int RW_BLOCK = 512;  // 8 waves: the window's LDS is shared by more waves
 constexpr int RW_WAVES = RW_BLOCK / WAVE;
+constexpr int SPARSE_ITEMS = 2;  // fused rounds: derivations per lane in flight in a sparse group
 
 // FM >= 0 selects the specialised variant for the most common shape: 32-bit
 // keys, one sample, a binary head whose second column comes from the index
@@ -1598,40 +1599,74 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
           const uint32_t NWD = W / 32;
           const size_t wb = kb >> 5;
           for (uint32_t i = lane; i < NWD; i += WAVE) marks[i] = 0u;
-          for (uint32_t r = r0; r < r1; ++r) {  // uniform: one driver row at a time
-            K dkey;
-            float x = 0.0f;
-            uint32_t cnt, base;
-            if (r - r0 < (uint32_t)WAVE) {  // read by the wave phase: a shuffle away
-              const int src = (int)(r - r0);
-              if constexpr (sizeof(K) == 8)
-                dkey = ((K)uni(__shfl((uint32_t)(rkey >> 32), src, WAVE)) << 32) | (K)uni(__shfl((uint32_t)rkey, src, WAVE));
-              else
-                dkey = (K)uni(__shfl((uint32_t)rkey, src, WAVE));
-              if constexpr (TK == TAG_F32) x = __shfl(rtag, src, WAVE);
-              cnt = uni(__shfl(rcnt, src, WAVE));
-              base = uni(__shfl(rbase, src, WAVE));
-            } else {
-              dkey = dk[r];
-              if constexpr (TK == TAG_F32) x = dt[r];
-              const uint32_t gy = recent_group(dkey);
-              uint32_t wy;
-              cnt = uni(ra.cur.rc[gy]);
-              base = group_window(d, gy, &wy);
+          // One derivation folded into the group's window in global memory.
+          auto fold_sparse = [&](K dkey, float x, K ikey, float y) {
+            const uint32_t loc = head_loc(dkey, ikey);
+            if (loc >= W) {  // the host only picks this kernel when every key lies in its window
+              if (d.overflow) *d.overflow = 2;
+              return;
             }
-            for (uint32_t i = lane; i < cnt; i += WAVE) {
-              const K ikey = ik[base + i];
-              const uint32_t loc = head_loc(dkey, ikey);
-              if (loc >= W) {  // the host only picks this kernel when every key lies in its window
-                if (d.overflow) *d.overflow = 2;
-                continue;
+            const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
+            const bool pres = (d.present[wb + wi] & bit) != 0u;
+            bool mark;
+            if constexpr (TK == TAG_F32) mark = fold_word(d.dtag + kb + loc, pres, product(x, y));
+            else mark = !pres;
+            if (mark) atomicOr(marks + wi, bit);
+          };
+          // The derivations of the first WAVE rows (held by the lanes since
+          // the count) spread over the lanes as one list, SPARSE_ITEMS per
+          // lane at a time, whatever the rows' sizes: each lane finds its
+          // derivation's row by a binary search over the rows' running
+          // counts, so all loads of a step are in flight together.
+          {
+            const uint32_t incl = wave_inclusive_scan(rcnt);  // rcnt is 0 past the group's rows
+            const uint32_t excl = incl - rcnt;
+            const uint32_t D64 = uni(__shfl(incl, WAVE - 1, WAVE));
+            for (uint32_t j0 = 0; j0 < D64; j0 += WAVE * SPARSE_ITEMS) {  // uniform
+              uint32_t row[SPARSE_ITEMS];
+              K ikey[SPARSE_ITEMS];
+              float y[SPARSE_ITEMS];
+#pragma unroll
+              for (int q = 0; q < SPARSE_ITEMS; ++q) {
+                const uint32_t j = j0 + (uint32_t)q * WAVE + lane;
+                uint32_t lo = 0;  // rows whose running count is <= j
+#pragma unroll
+                for (uint32_t step = WAVE / 2; step >= 1; step >>= 1)
+                  if (__shfl(incl, (int)(lo + step - 1), WAVE) <= j) lo += step;
+                row[q] = lo;
+                const uint32_t idx = __shfl(rbase, (int)(lo & (WAVE - 1)), WAVE) + j -
+                                     __shfl(excl, (int)(lo & (WAVE - 1)), WAVE);
+                const bool act = j < D64;
+                ikey[q] = act ? ik[idx] : (K)0;
+                y[q] = 0.0f;
+                if constexpr (TK == TAG_F32) y[q] = act ? it[idx] : 0.0f;
               }
-              const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
-              const bool pres = (d.present[wb + wi] & bit) != 0u;
-              bool mark;
-              if constexpr (TK == TAG_F32) mark = fold_word(d.dtag + kb + loc, pres, product(x, it[base + i]));
-              else mark = !pres;
-              if (mark) atomicOr(marks + wi, bit);
+#pragma unroll
+              for (int q = 0; q < SPARSE_ITEMS; ++q) {
+                const int src = (int)(row[q] & (WAVE - 1));
+                K dkey;
+                if constexpr (sizeof(K) == 8)
+                  dkey = ((K)__shfl((uint32_t)(rkey >> 32), src, WAVE) << 32) | (K)__shfl((uint32_t)rkey, src, WAVE);
+                else
+                  dkey = (K)__shfl((uint32_t)rkey, src, WAVE);
+                float x = 0.0f;
+                if constexpr (TK == TAG_F32) x = __shfl(rtag, src, WAVE);
+                if (j0 + (uint32_t)q * WAVE + lane < D64) fold_sparse(dkey, x, ikey[q], y[q]);
+              }
+            }
+          }
+          for (uint32_t r = r0 + WAVE; r < r1; ++r) {  // rows past the first WAVE: one at a time
+            const K dkey = dk[r];
+            float x = 0.0f;
+            if constexpr (TK == TAG_F32) x = dt[r];
+            const uint32_t gy = recent_group(dkey);
+            uint32_t wy;
+            const uint32_t cnt = uni(ra.cur.rc[gy]);
+            const uint32_t base = group_window(d, gy, &wy);
+            for (uint32_t i = lane; i < cnt; i += WAVE) {
+              float y = 0.0f;
+              if constexpr (TK == TAG_F32) y = it[base + i];
+              fold_sparse(dkey, x, ik[base + i], y);
             }
           }
           const uint32_t total = emit(g, kb, marks, 0, NWD, 0, false);
