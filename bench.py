@@ -492,9 +492,11 @@ def main() -> int:
     if args.round_log:
         with open(args.round_log, "w") as f:
             for sr, e in zip(SEMIRINGS, engines):
-                new, der = e.round_log()
+                log = e.round_log()
+                fused = log["kind"] == 3
                 f.write(json.dumps({"semiring": sr, "driver_rows": int(len(src)), "bytes_per_unit": 8,
-                                    "new": new.tolist(), "derivations": der.tolist()}) + "\n")
+                                    "new": log["new"][fused].tolist(),
+                                    "derivations": log["derivations"][fused].tolist()}) + "\n")
     launches = ms = nbytes = 0.0
     for e in engines:
         ks = e.kernel_stats()[dominant]

@@ -333,15 +333,23 @@ dl_status dl_profile(dl_engine* e, uint32_t family_mask);
 /* Totals of one kernel family since the last dl_profile call. */
 dl_status dl_get_kernel_timing(const dl_engine* e, int family, dl_kernel_timing* out);
 
-/* Sizes of the fused-round launches of the last dl_run_fixpoint (one entry
- * per launch of the fused round kernel, in launch order, including the
- * launches of a final batch after the stratum's last round, which find
- * nothing): tuples new or changed by the round and its derivations (join
- * outputs).  For relating a kernel trace's launches to their work (Alg. 1:
- * one entry per iteration).  Writes min(capacity, entries) entries to either
- * array (NULL: not written) and the entry count to *n. */
+/* Per-round sizes of the last dl_run_fixpoint (Alg. 1: one entry per
+ * iteration), in order over the strata: tuples new or changed by the round,
+ * its derivations (join outputs; UINT64_MAX where they were only counted in
+ * total on the device: batched rounds) and info = stratum << 8 | kind, kind
+ * DL_ROUND_FIRST (a stratum's first round), DL_ROUND_PLAIN (a later round of
+ * separate launches), DL_ROUND_FUSED (one launch of the fused round kernel;
+ * the launches of a final batch after the stratum's last round are listed
+ * too and find nothing) or DL_ROUND_BATCHED (a round of a device-sized
+ * batch).  For relating a kernel trace's launches to their work.  Writes
+ * min(capacity, entries) entries to each array given (NULL: not written) and
+ * the entry count to *n. */
+#define DL_ROUND_FIRST 1
+#define DL_ROUND_PLAIN 2
+#define DL_ROUND_FUSED 3
+#define DL_ROUND_BATCHED 4
 dl_status dl_get_round_log(const dl_engine* e, size_t capacity, uint64_t* new_or_changed, uint64_t* derivations,
-                           size_t* n);
+                           uint32_t* info, size_t* n);
 
 /* Owned by the engine; valid until the next call on it.  Never NULL. */
 const char* dl_last_error(const dl_engine* e);

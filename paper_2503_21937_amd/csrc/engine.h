@@ -192,7 +192,13 @@ struct Engine {
   dl_stats stats{};
   uint64_t deferred_units = 0;  // derivations of joins whose totals stayed on the device (last run)
   uint64_t fused_units = 0;     // derivations of fused rounds (this run, added up on the host)
-  std::vector<uint64_t> round_log;  // fused round launches of the last run: (new or changed, derivations) pairs
+  std::vector<uint64_t> round_log;  // rounds of the last run: (new or changed, derivations, info) triples
+  void log_round(uint64_t u, uint64_t c, int stratum, int kind) {
+    round_log.push_back(u);
+    round_log.push_back(c);
+    round_log.push_back((uint64_t)stratum << 8 | (uint64_t)kind);
+  }
+  int cur_stratum = 0;  // the stratum being evaluated (round log)
   uint32_t prof_mask = 0;
   dl_kernel_timing kstats[DL_K_FAMILIES]{};
   size_t device_bytes = 0;

@@ -954,13 +954,14 @@ dl_status dl_get_kernel_timing(const dl_engine* h, int family, dl_kernel_timing*
 }
 
 dl_status dl_get_round_log(const dl_engine* h, size_t capacity, uint64_t* new_or_changed, uint64_t* derivations,
-                           size_t* n) {
+                           uint32_t* info, size_t* n) {
   if (!h || !n) return DL_ERR_ARG;
   const std::vector<uint64_t>& log = h->e.round_log;
-  *n = log.size() / 2;
+  *n = log.size() / 3;
   for (size_t i = 0; i < std::min(capacity, *n); ++i) {
-    if (new_or_changed) new_or_changed[i] = log[2 * i];
-    if (derivations) derivations[i] = log[2 * i + 1];
+    if (new_or_changed) new_or_changed[i] = log[3 * i];
+    if (derivations) derivations[i] = log[3 * i + 1];
+    if (info) info[i] = (uint32_t)log[3 * i + 2];
   }
   return DL_OK;
 }

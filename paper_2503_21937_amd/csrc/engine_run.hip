@@ -1173,8 +1173,7 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
         U += part[((size_t)i * nb + b) * 2];
         C += part[((size_t)i * nb + b) * 2 + 1];
       }
-      e.round_log.push_back(U);
-      e.round_log.push_back(C);
+      e.log_round(U, C, e.cur_stratum, DL_ROUND_FUSED);
       if (done) continue;  // launched after the last round: found nothing
       ++rounds;
       ++R.version;
@@ -1278,6 +1277,7 @@ int batch_rounds(Engine& e, const Stratum& st, const std::vector<const Plan*>& p
     const uint64_t* log = e.host + S_LOG;
     for (uint64_t i = 0; i < log[0] && !done; ++i) {
       const size_t U = log[1 + i];
+      e.log_round(U, ~0ull, e.cur_stratum, DL_ROUND_BATCHED);
       ++rounds;
       ++R.version;
       ++R.rversion;
@@ -1422,12 +1422,19 @@ void run_fixpoint(Engine& e) {
   e.round_ids.clear();
   DL_HIP(hipMemsetAsync(e.dtotal.p, 0, 32 * sizeof(uint64_t), e.stream));
   setup_dense(e);
+  // derivations so far: counted on the host, on the device (read with the
+  // totals every round reads) and in fused rounds
+  e.host[S_CAND] = 0;
+  auto derivations = [&] { return e.stats.candidates + e.host[S_CAND] + e.fused_units; };
+  e.cur_stratum = 0;
   for (const Stratum& st : e.prog.strata) {
     int rounds = 1;
     std::vector<uint32_t> ids{e.next_id};
+    uint64_t d0 = derivations();
     for (int p : st.base_plans) run_plan<K>(e, e.prog.plans[p]);
     size_t changed = 0;
     for (int r : st.rels) changed += absorb<K>(e, r);
+    e.log_round(changed, derivations() - d0, e.cur_stratum, DL_ROUND_FIRST);
     if (changed) {
       const std::vector<const Plan*> gp = batch_plans(e, st);
       const int gr = gp.empty() ? 0 : batch_rounds<K>(e, st, gp);
@@ -1438,6 +1445,7 @@ void run_fixpoint(Engine& e) {
     }
     while (changed && !st.delta_plans.empty()) {
       ++rounds;
+      d0 = derivations();
       for (int p : st.delta_plans) {
         const Plan& pl = e.prog.plans[p];
         // orientation: by default dense heads take the static-driven twin
@@ -1448,6 +1456,7 @@ void run_fixpoint(Engine& e) {
       changed = 0;
       ids.push_back(e.next_id);
       for (int r : st.rels) changed += absorb<K>(e, r);
+      e.log_round(changed, derivations() - d0, e.cur_stratum, DL_ROUND_PLAIN);
     }
     ids.push_back(e.next_id);
     if (e.lineage) e.round_ids.push_back(std::move(ids));
@@ -1459,6 +1468,7 @@ void run_fixpoint(Engine& e) {
     e.stats.strata += 1;
     e.stats.rounds += rounds;
     e.stats.max_rounds = std::max(e.stats.max_rounds, rounds);
+    ++e.cur_stratum;
   }
   for (size_t r = 0; r < e.rel.size(); ++r)
     if (e.prog.rels[r].derived) e.stats.derived += e.rel[r].full.n;

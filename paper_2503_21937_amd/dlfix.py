@@ -98,7 +98,7 @@ def lib():
         L.dl_autotune.argtypes = [vp, C.c_int, C.c_char_p]
         L.dl_profile.argtypes = [vp, C.c_uint32]
         L.dl_get_kernel_timing.argtypes = [vp, C.c_int, C.POINTER(KernelStats)]
-        L.dl_get_round_log.argtypes = [vp, sz, vp, vp, C.POINTER(sz)]
+        L.dl_get_round_log.argtypes = [vp, sz, vp, vp, vp, C.POINTER(sz)]
         L.dl_last_error.argtypes = [vp]
         L.dl_last_error.restype = C.c_char_p
         L.dl_free.argtypes = [vp]
@@ -354,16 +354,21 @@ class Engine:
             out[name] = dict(launches=ks.launches, ms=ks.ms, bytes=ks.bytes)
         return out
 
-    def round_log(self):
-        """(new or changed, derivations) per fused-round launch of the last
-        run, in launch order (numpy uint64 arrays)."""
+    ROUND_KINDS = {1: "first", 2: "plain", 3: "fused", 4: "batched"}
+
+    def round_log(self) -> dict:
+        """Per-round sizes of the last run: dict(new, derivations (2^64 - 1
+        where only the device's total is known), stratum, kind: 1 first
+        round, 2 later round, 3 fused-round launch, 4 batched round)."""
         n = C.c_size_t()
-        self._check(lib().dl_get_round_log(self.h, 0, None, None, C.byref(n)))
+        self._check(lib().dl_get_round_log(self.h, 0, None, None, None, C.byref(n)))
         new = np.zeros(n.value, np.uint64)
         der = np.zeros(n.value, np.uint64)
+        info = np.zeros(n.value, np.uint32)
         if n.value:
-            self._check(lib().dl_get_round_log(self.h, n.value, new.ctypes.data, der.ctypes.data, C.byref(n)))
-        return new, der
+            self._check(lib().dl_get_round_log(self.h, n.value, new.ctypes.data, der.ctypes.data, info.ctypes.data,
+                                               C.byref(n)))
+        return dict(new=new, derivations=der, stratum=info >> 8, kind=info & 0xff)
 
     def stats(self) -> dict:
         s = Stats()

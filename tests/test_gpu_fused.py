@@ -86,7 +86,11 @@ def test_round_log(synth, sr):
     on = dlfix.Engine(synth.TC_PROGRAM, sr, dedup="dense")
     on.add_facts("edge", [src, dst], p)
     on.run()
-    new, der = on.round_log()
+    log = on.round_log()
+    kinds = log["kind"]
+    assert kinds[0] == 1 and np.all(kinds[1:] == 3)  # round 1, then fused launches
+    new, der = log["new"][1:], log["derivations"][1:]
+    assert int(log["derivations"][0]) == src.size  # round 1 derives one candidate per edge
     st = on.stats()
     first_empty = int(np.argmax(new == 0))
     assert new[first_empty] == 0 and np.all(new[first_empty:] == 0) and np.all(der[first_empty + 1:] == 0)
@@ -94,7 +98,11 @@ def test_round_log(synth, sr):
     off = dlfix.Engine(synth.TC_PROGRAM, sr, dedup="dense", fused=False)
     off.add_facts("edge", [src, dst], p)
     off.run()
-    assert off.round_log()[0].size == 0
+    olog = off.round_log()
+    assert olog["kind"][0] == 1 and set(olog["kind"][1:].tolist()) <= {2, 4}
+    # the same rounds and new or changed tuples either way
+    assert int(olog["new"].sum()) == int(log["new"].sum())
+    assert olog["kind"].size == st["max_rounds"]  # one entry per round, the last finding nothing
     # the same derivations either way; round 1 (the base rule) derives one
     # candidate per edge
     assert st["candidates"] == off.stats()["candidates"]

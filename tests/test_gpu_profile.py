@@ -34,3 +34,21 @@ def test_profiled_graphs_match_direct_launches(synth, sr, fused):
         assert kg[fam]["bytes"] == pytest.approx(kd[fam]["bytes"], rel=1e-9), fam
     if fused:
         assert kg["join_count"]["launches"] == kd["join_count"]["launches"] == 0
+
+
+@pytest.mark.parametrize("dedup", ["sort", "hash"])
+def test_round_log_sort_path(oracle, synth, dedup):
+    """Every round of the sort path is logged with its derivations (counted
+    on the host), and the new tuples add up to the relation."""
+    from paper_2503_21937_amd import dlfix
+    src, dst, p = synth.er_graph(6, 400, 1200, weights=True)
+    e = dlfix.Engine(synth.TC_PROGRAM, "addmult", dedup=dedup)
+    e.add_facts("edge", [src, dst], p)
+    e.run()
+    log = e.round_log()
+    st = e.stats()
+    assert log["kind"].size == st["max_rounds"]
+    assert log["kind"][0] == 1 and np.all(log["kind"][1:] == 2)
+    assert int(log["derivations"].sum()) == st["candidates"]
+    assert int(log["new"].sum()) == e.size("path")  # frozen tags: every tuple is new once
+    assert log["new"][-1] == 0
