@@ -1053,12 +1053,12 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
   e.sync();
   // Every round writes its workgroups' counts to its own part of wr_part;
   // the host adds them up after the batch (pinned readback where the engine
-  // may allocate).  BATCH_ROUNDS is even: a batch ends with the recent
+  // allocates its own memory).  BATCH_ROUNDS is even: a batch ends with the recent
   // tuples back in set 0.
   const size_t part_words = (size_t)BATCH_ROUNDS * nbmax * 2;
   std::vector<uint32_t> part_pageable;
   uint32_t* part = nullptr;
-  if (e.static_dev >= 0) {
+  if (e.static_dev >= 0 || e.use_arena) {  // engines that allocate nothing while they run
     part_pageable.resize(part_words);
     part = part_pageable.data();
   } else {
