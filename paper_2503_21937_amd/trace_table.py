@@ -1,6 +1,7 @@
 """Launch sizes against launch times: joins a rocprofv3 kernel trace
-(``*_kernel_trace.csv``) with the fused-round log that ``bench.py
---round-log`` writes, and prints a markdown table per size class of the fused
+(``*_kernel_trace.csv``) with the fused-round launches of the engines'
+round logs (``dl_get_round_log``) that ``bench.py --round-log`` writes, and
+prints a markdown table per size class of the fused
 round kernel (derivations per launch): launches, average duration,
 algorithmic bytes (driver rows plus derivations, key and tag each) and the
 rate they imply.
