@@ -1528,6 +1528,10 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
   // tag words, by threads t0, t0 + nt, ... (16-byte loads: a window is
   // W-aligned, W a multiple of 32)
   auto stage = [&](uint32_t kb, uint32_t W, uint32_t t0, uint32_t nt) {
+    // t0 made opaque here: otherwise the per-thread addresses are hoisted
+    // out of the batch loop and spilled to scratch memory (HBM traffic in
+    // every workgroup), for want of registers
+    asm volatile("" : "+v"(t0));
     const uint32_t NWD = W / 32;
     const size_t wb = kb >> 5;
     for (uint32_t i = t0; i < NWD; i += nt) s_pres[i] = d.present[wb + i];
