@@ -1462,12 +1462,15 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
     else return f_otimes(a.sr, p, r);
   };
   // One derivation folded into its window: `tw` the key's tag word and
-  // `pres` its presence (LDS in a staged window, global memory otherwise);
-  // true when it makes the key present or improves its tag.
-  auto fold_word = [&](uint32_t* tw, bool pres, float t) -> bool {
+  // `pres()` its presence (LDS in a staged window, global memory otherwise),
+  // read only where the outcome depends on it (max / min: a tag that does
+  // not beat the current one); true when it makes the key present or
+  // improves its tag.
+  auto fold_word = [&](uint32_t* tw, auto&& pres, float t) -> bool {
     if (mode == DENSE_ADD) {
-      if (!pres) atomicAdd(reinterpret_cast<float*>(tw), t);
-      return !pres;
+      const bool p = pres();
+      if (!p) atomicAdd(reinterpret_cast<float*>(tw), t);
+      return !p;
     }
     const uint32_t o = to_ordered(t), cur = *tw;
     if (mode == DENSE_MAX) {
@@ -1475,13 +1478,13 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
         atomicMax(tw, o);
         return true;
       }
-      return o <= zero && !pres;  // does not beat the zero: new only if absent
+      return o <= zero && !pres();  // does not beat the zero: new only if absent
     }
     if (o < cur) {
       atomicMin(tw, o);
       return true;
     }
-    return o >= zero && !pres;
+    return o >= zero && !pres();
   };
   // A window's marked keys become group g's recent tuples of the next round
   // (in key order): emitted by one wave over words [w0, w1) of `marks`
@@ -1611,10 +1614,10 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
               return;
             }
             const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
-            const bool pres = (d.present[wb + wi] & bit) != 0u;
+            auto pres = [&] { return (d.present[wb + wi] & bit) != 0u; };
             bool mark;
             if constexpr (TK == TAG_F32) mark = fold_word(d.dtag + kb + loc, pres, product(x, y));
-            else mark = !pres;
+            else mark = !pres();
             if (mark) atomicOr(marks + wi, bit);
           };
           // The derivations of the first WAVE rows (held by the lanes since
@@ -1758,6 +1761,24 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
             else hi = mid;
           }
         }
+        // the current row's chunk and output ranges, recent base, key and
+        // tag, held in scalar registers until a chunk past its end
+        uint32_t r_c0 = 0, r_cend = 0, r_off = 0, r_oend = 0, r_ib = 0;
+        K r_key = 0;
+        float r_tag = 0.0f;
+        auto load_row = [&](uint32_t l) {
+          r_c0 = uni(s_cpre[l]);
+          r_cend = uni(s_cpre[l + 1]);
+          r_off = uni(s_offs[l]);
+          r_oend = uni(s_offs[l + 1]);
+          r_ib = uni(s_ibase[l]);
+          if constexpr (sizeof(K) == 8)
+            r_key = ((K)uni((uint32_t)(s_dkey[l] >> 32)) << 32) | (K)uni((uint32_t)s_dkey[l]);
+          else
+            r_key = (K)uni((uint32_t)s_dkey[l]);
+          if constexpr (TK == TAG_F32) r_tag = __uint_as_float(uni(__float_as_uint(s_dtag[l])));
+        };
+        if (c < ce) load_row(lo);
         for (; c < ce; c += RX_ITEMS) {  // uniform per wave
           bool act[RX_ITEMS];
           uint32_t irow[RX_ITEMS];
@@ -1766,17 +1787,16 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
 #pragma unroll
           for (int q = 0; q < RX_ITEMS; ++q) {
             const uint32_t cq = c + (uint32_t)q;
-            if (cq < ce)
-              while (uni(s_cpre[lo + 1]) <= cq) ++lo;  // empty rows own no chunk
-            const uint32_t j = uni(s_offs[lo]) + (cq - uni(s_cpre[lo])) * WAVE + lane;
-            act[q] = cq < ce && j < uni(s_offs[lo + 1]);
-            if constexpr (sizeof(K) == 8)
-              dkey[q] = ((K)uni((uint32_t)(s_dkey[lo] >> 32)) << 32) | (K)uni((uint32_t)s_dkey[lo]);
-            else
-              dkey[q] = (K)uni((uint32_t)s_dkey[lo]);
-            irow[q] = uni(s_ibase[lo]) + j;
-            x[q] = 0.0f;
-            if constexpr (TK == TAG_F32) x[q] = __uint_as_float(uni(__float_as_uint(s_dtag[lo])));
+            if (cq < ce && cq >= r_cend) {
+              do ++lo;
+              while (uni(s_cpre[lo + 1]) <= cq);  // empty rows own no chunk
+              load_row(lo);
+            }
+            const uint32_t j = r_off + (cq - r_c0) * WAVE + lane;
+            act[q] = cq < ce && j < r_oend;
+            dkey[q] = r_key;
+            irow[q] = r_ib + j;
+            x[q] = r_tag;
           }
 #pragma unroll
           for (int q = 0; q < RX_ITEMS; ++q) {
@@ -1793,10 +1813,17 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
               continue;
             }
             const uint32_t wi = loc >> 5, bit = 1u << (loc & 31);
-            const bool pres = (s_pres[wi] & bit) != 0u;
+            auto pres = [&] { return (s_pres[wi] & bit) != 0u; };
             bool mark;
-            if constexpr (TK == TAG_F32) mark = fold_word(s_tag + loc, pres, product(x[q], y[q]));
-            else mark = !pres;
+            if constexpr (TK == TAG_F32 && (FM == DENSE_MAX || FM == DENSE_MIN)) {
+              const uint32_t o = to_ordered(product(x[q], y[q]));
+              if constexpr (FM == DENSE_MAX) mark = o > atomicMax(s_tag + loc, o) || (o <= zero && !pres());
+              else mark = o < atomicMin(s_tag + loc, o) || (o >= zero && !pres());
+            } else if constexpr (TK == TAG_F32) {
+              mark = fold_word(s_tag + loc, pres, product(x[q], y[q]));
+            } else {
+              mark = !pres();
+            }
             if (mark) atomicOr(s_new + wi, bit);
           }
         }
