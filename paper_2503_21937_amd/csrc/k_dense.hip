@@ -1395,7 +1395,7 @@ template <typename K, int TK, int RX_ITEMS, int FM>
 __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseArgs d, RoundArgs ra) {
   constexpr bool FAST = FM >= 0;
   constexpr int WAVE_MARKS = RW_KEYS / RW_WAVES;  // per-wave mark words in s_tag (>= RW_KEYS / 32)
-  __shared__ uint32_t s_tag[RW_KEYS];  // dense group: its window's tags; sparse groups: per-wave marks
+  __shared__ __align__(16) uint32_t s_tag[RW_KEYS];  // dense group: its window's tags; sparse groups: per-wave marks
   __shared__ uint32_t s_pres[RW_KEYS / 32];
   __shared__ uint32_t s_new[RW_KEYS / 32];
   __shared__ uint32_t s_offs[RW_ROWS + 1];  // per chunk row: first local output slot
@@ -1527,22 +1527,34 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
     return run - base;
   };
 
-  // A dense group's window into LDS: presence words and (float tags) the
-  // tag words, by threads t0, t0 + nt, ... (16-byte loads: a window is
-  // W-aligned, W a multiple of 32)
-  auto stage = [&](uint32_t kb, uint32_t W, uint32_t t0, uint32_t nt) {
-    // t0 made opaque here: otherwise the per-thread addresses are hoisted
-    // out of the batch loop and spilled to scratch memory (HBM traffic in
-    // every workgroup), for want of registers
-    asm volatile("" : "+v"(t0));
+  // A dense group's window into LDS by waves w0 .. w0 + nw - 1 (uniform):
+  // its presence words in 256-byte pieces and (float tags) its tag words in
+  // 1 KB pieces, each piece a wave's loads written straight into LDS (lane
+  // l's 4 or 16 bytes at the piece's LDS base + 4 l or 16 l), so that no
+  // registers hold the data and all of a wave's pieces are in flight
+  // together.  A window is W-aligned, W a multiple of 32; the barrier after
+  // staging waits for the loads.
+  auto stage = [&](uint32_t kb, uint32_t W, uint32_t w0, uint32_t nw) {
+    uint32_t l = lane;
+    // made opaque here: otherwise the per-lane addresses are hoisted out of
+    // the batch loop and spilled to scratch memory, for want of registers
+    asm volatile("" : "+v"(l));
     const uint32_t NWD = W / 32;
-    const size_t wb = kb >> 5;
-    for (uint32_t i = t0; i < NWD; i += nt) s_pres[i] = d.present[wb + i];
+    for (uint32_t c = wv - w0; c * WAVE < NWD; c += nw) {  // uniform
+      const uint32_t q = c * WAVE + l;
+      if (q < NWD)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(d.present + (kb >> 5) + q),
+                                         (__attribute__((address_space(3))) void*)(s_pres + c * WAVE), 4, 0, 0);
+    }
     if constexpr (TK == TAG_F32) {
       const uint4* src = reinterpret_cast<const uint4*>(d.dtag + kb);
-      uint4* dst = reinterpret_cast<uint4*>(s_tag);
-#pragma unroll 4
-      for (uint32_t i = t0; i < W / 4; i += nt) dst[i] = src[i];
+      const uint32_t NQ = W / 4;
+      for (uint32_t c = wv - w0; c * WAVE < NQ; c += nw) {  // uniform
+        const uint32_t q = c * WAVE + l;
+        if (q < NQ)
+          __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + q),
+                                           (__attribute__((address_space(3))) void*)(s_tag + c * WAVE * 4), 16, 0, 0);
+      }
     }
   };
 
@@ -1558,7 +1570,7 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
       // group of the domain has one)
       uint32_t W;
       const uint32_t kb = group_window(d, g0, &W);
-      stage(kb, W, threadIdx.x - WAVE, RW_BLOCK - WAVE);
+      stage(kb, W, 1, RW_WAVES - 1);
     }
     {
       // Wave phase: wave wv (< B) takes group g0 + wv.  It counts the group's
@@ -1697,7 +1709,7 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
       const uint32_t kb = group_window(d, g, &W);
       const uint32_t NWD = W / 32;
       for (uint32_t i = threadIdx.x; i < NWD; i += RW_BLOCK) s_new[i] = 0u;
-      if (B != 1) stage(kb, W, threadIdx.x, RW_BLOCK);  // else staged during the wave phase
+      if (B != 1) stage(kb, W, 0, RW_WAVES);  // else staged during the wave phase
       const uint32_t r0 = uni(ra.goff[g]), r1 = uni(ra.goff[g + 1]);
       for (uint32_t q0 = r0; q0 < r1; q0 += RW_ROWS) {  // uniform
         const uint32_t nr = r1 - q0 < (uint32_t)RW_ROWS ? r1 - q0 : (uint32_t)RW_ROWS;
