@@ -1346,7 +1346,7 @@ void bitmap_keys(const DenseArgs& d, size_t nkeys, const uint32_t* counts, bool 
 // atomics on its window without staging it.  The workgroup then writes the
 // window's new or changed tuples as the group's recent tuples for the next
 // round (in key order), makes them present and adds their count to the
-// round total, which the last workgroup appends to the round log.  Every
+// workgroup's own slot of the round's counts (the host adds them up).  Every
 // read of a round is of the previous round's recent tuples or of the group's
 // own window (Jacobi order), and two window-layout buffers alternate.
 //
