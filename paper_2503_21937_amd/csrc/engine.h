@@ -184,8 +184,6 @@ struct Engine {
       ev_keys, ev_tags, ev_l, ev_r,  // output rows of a plan with evaluation, before the condition compacts them
       wr_keys0, wr_keys1, wr_tags0, wr_tags1, wr_cnt0, wr_cnt1, wr_part;  // fused rounds: two window-layout recent sets
   uint64_t* host = nullptr;  // pinned readback words
-  uint32_t* host_part = nullptr;  // pinned readback of fused rounds' per-workgroup counts
-  size_t host_part_cap = 0;       // (words; static engines read into a pageable vector instead)
   DevBuf dtotal;             // device words for totals
   DevBuf cs_state;           // single-pass count+scan: tile sums and flags (kept zeroed between launches)
 

@@ -46,7 +46,6 @@ Engine::~Engine() {
       b.p = nullptr;
     });
   if (host && host != host_words) (void)hipHostFree(host);
-  if (host_part) (void)hipHostFree(host_part);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 

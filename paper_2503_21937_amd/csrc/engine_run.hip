@@ -23,9 +23,10 @@ namespace dlfix {
 
 namespace {
 
-// Device words of totals (64 x u64): slots 0..6 below, 30 = id / sample
-// maxima at ingest, 32.. = round log of a graph batch (count, then totals).
-enum Slot { S_SCAN = 0, S_UNIQUE = 1, S_NEW = 2, S_RECENT = 3, S_LIN = 4, S_OVF = 5, S_CAND = 6, S_LOG = 32 };
+// Device words of totals (64 x u64): slots 0..6 below, 8..15 = totals of a
+// batch of fused rounds, 30 = id / sample maxima at ingest, 32.. = round log
+// of a graph batch (count, then totals).
+enum Slot { S_SCAN = 0, S_UNIQUE = 1, S_NEW = 2, S_RECENT = 3, S_LIN = 4, S_OVF = 5, S_CAND = 6, S_PART = 8, S_LOG = 32 };
 constexpr int BATCH_ROUNDS = 4;  // round bodies per host synchronisation (one graph)
 
 uint64_t* total_slot(Engine& e, int s) { return e.dtotal.as<uint64_t>() + s; }
@@ -1052,25 +1053,9 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
   ra.win_per_key = e.cfg.rows == 0 ? ~0u : e.cfg.rows == 2 ? 0u : 12u;
   e.sync();
   // Every round writes its workgroups' counts to its own part of wr_part;
-  // the host adds them up after the batch (pinned readback where the engine
-  // allocates its own memory).  BATCH_ROUNDS is even: a batch ends with the recent
-  // tuples back in set 0.
-  const size_t part_words = (size_t)BATCH_ROUNDS * nbmax * 2;
-  std::vector<uint32_t> part_pageable;
-  uint32_t* part = nullptr;
-  if (e.static_dev >= 0 || e.use_arena) {  // engines that allocate nothing while they run
-    part_pageable.resize(part_words);
-    part = part_pageable.data();
-  } else {
-    if (e.host_part_cap < part_words) {
-      if (e.host_part) DL_HIP(hipHostFree(e.host_part));
-      e.host_part = nullptr;
-      e.host_part_cap = 0;
-      DL_HIP(hipHostMalloc((void**)&e.host_part, part_words * 4, hipHostMallocDefault));
-      e.host_part_cap = part_words;
-    }
-    part = e.host_part;
-  }
+  // after a batch one small launch adds them up per round into the total
+  // slots, which the host reads back with the others.
+  static_assert(S_PART + 2 * BATCH_ROUNDS <= 30, "batch totals overlap other slots");
   auto enqueue_rounds = [&](int m) {
     ra.batch = widths[m];
     for (int i = 0; i < BATCH_ROUNDS; ++i) {
@@ -1081,9 +1066,8 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     }
   };
   auto enqueue_readback = [&](int m) {
+    sum_parts(e.wr_part.as<uint32_t>(), nbw[m], BATCH_ROUNDS, total_slot(e, S_PART), e.stream);
     DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, e.stream));
-    DL_HIP(hipMemcpyAsync(part, e.wr_part.p, (size_t)BATCH_ROUNDS * nbw[m] * 2 * 4, hipMemcpyDeviceToHost,
-                          e.stream));
   };
   // The graph holds the rounds' launches only, so that two events around a
   // replay time exactly them when profiling (events recorded inside a graph
@@ -1166,13 +1150,8 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
       release();
       check_overflow(e);
     }
-    const unsigned nb = nbw[m];
     for (int i = 0; i < BATCH_ROUNDS; ++i) {
-      uint64_t U = 0, C = 0;
-      for (unsigned b = 0; b < nb; ++b) {
-        U += part[((size_t)i * nb + b) * 2];
-        C += part[((size_t)i * nb + b) * 2 + 1];
-      }
+      const uint64_t U = e.host[S_PART + 2 * i], C = e.host[S_PART + 2 * i + 1];
       e.log_round(U, C, e.cur_stratum, DL_ROUND_FUSED);
       if (done) continue;  // launched after the last round: found nothing
       ++rounds;

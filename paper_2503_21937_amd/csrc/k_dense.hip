@@ -1933,6 +1933,42 @@ void window_round(const JoinArgs& a, int tk, const DenseArgs& d, const RoundArgs
   DL_PROF_DEFER(1, per);
 }
 
+// Totals of a batch of fused rounds: workgroup i adds up round i's
+// per-workgroup (new or changed, derivations) pairs (nb of them, from
+// part + 2 nb i) into out[2i] and out[2i + 1].
+__global__ __launch_bounds__(BLOCK) void k_sum_parts(const uint32_t* __restrict__ part, unsigned nb,
+                                                     uint64_t* __restrict__ out) {
+  __shared__ uint64_t s_u[NWAVES], s_c[NWAVES];
+  const uint2* p = reinterpret_cast<const uint2*>(part) + (size_t)blockIdx.x * nb;
+  uint64_t u = 0, c = 0;
+  for (unsigned b = threadIdx.x; b < nb; b += BLOCK) {
+    const uint2 v = p[b];
+    u += v.x;
+    c += v.y;
+  }
+  u = wave_sum<uint64_t>(u);
+  c = wave_sum<uint64_t>(c);
+  const int wv = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    s_u[wv] = u;
+    s_c[wv] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t tu = 0, tc = 0;
+    for (int i = 0; i < NWAVES; ++i) {
+      tu += s_u[i];
+      tc += s_c[i];
+    }
+    out[2 * blockIdx.x] = tu;
+    out[2 * blockIdx.x + 1] = tc;
+  }
+}
+
+void sum_parts(const uint32_t* part, unsigned nb, unsigned rounds, uint64_t* out, hipStream_t st) {
+  k_sum_parts<<<rounds, BLOCK, 0, st>>>(part, nb, out);
+}
+
 // Window layout of a sorted relation: group g's rows (off[g] .. off[g+1])
 // go to its window's first dense indexes; every group's count is written.
 template <typename K>

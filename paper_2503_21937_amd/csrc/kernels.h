@@ -284,6 +284,10 @@ struct RoundArgs {
 // it writes: 2 per workgroup).
 bool window_round_fits(uint32_t wkeys);
 unsigned window_round_grid(uint32_t ngroups, uint32_t batch);
+// Per-round totals of `rounds` fused rounds from their per-workgroup pairs
+// (nb pairs a round, rounds one after the other in `part`): out[2i] = new or
+// changed tuples of round i, out[2i + 1] = its derivations.
+void sum_parts(const uint32_t* part, unsigned nb, unsigned rounds, uint64_t* out, hipStream_t st);
 constexpr uint32_t WINDOW_ROUND_WIDE = 8;  // the wider batch (waves of the fused round's workgroup)
 template <typename K>
 void window_round(const JoinArgs& a, int tag_kind, const DenseArgs& d, const RoundArgs& ra, hipStream_t st);
