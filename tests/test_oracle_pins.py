@@ -167,6 +167,33 @@ def test_addmult_grid_closed_form(oracle, synth, k):
         assert got[key] == pytest.approx(v, rel=1e-12), key
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_addmult_general_graph_matrix_power(oracle, synth, seed):
+    """Frozen add-mult on a general graph.  A pair first derived in round d
+    (its hop distance, at least one edge) keeps the sum, over the walks of d
+    edges from x to z, of their edge products: every such walk is a shortest
+    one and so are its suffixes, which are what the earlier rounds summed.
+    That is entry (x, z) of A^d for the weighted adjacency A, as long as no
+    sum reaches the clamp at 1 (asserted for these tags)."""
+    n = 256
+    src, dst, _ = synth.er_graph(seed, n, 1024)
+    p = np.random.default_rng(100 + seed).uniform(0.02, 0.3, src.size).astype(np.float32)
+    A = np.zeros((n, n))
+    A[src, dst] = p.astype(np.float64)
+    d1 = hop_matrix(n, src, dst)
+    want = np.zeros((n, n))
+    P = np.eye(n)
+    for d in range(1, int(d1[np.isfinite(d1)].max()) + 1):
+        P = P @ A
+        want[d1 == d] = P[d1 == d]
+    pairs = np.argwhere(np.isfinite(d1))
+    vals = want[pairs[:, 0], pairs[:, 1]]
+    assert vals.min() > 0 and vals.max() < 1.0  # no clamp in this regime
+    res = tc(oracle, synth, src, dst, p, "addmult").read("path")
+    assert np.array_equal(res["cols"], pairs.astype(np.uint32))
+    np.testing.assert_allclose(res["value"], vals, rtol=1e-12)
+
+
 def test_addmult_out_tree_products(oracle, synth):
     """On an out-tree every pair has one walk: the tag is its edge product."""
     rng = np.random.default_rng(7)
