@@ -7,6 +7,11 @@
 // lookup table on the positions already bound), floating point is binary64
 // except the top-k proof probabilities, which the semiring defines in
 // binary32 (they decide which proofs are kept).
+//
+// Pinned by tests/test_oracle_*.py against closed forms, textbook
+// algorithms and brute force.  Parity unpinned in two regimes: add-mult sums
+// that reach the clamp at 1 on general graphs (pinned on grids, which clamp,
+// and trees), and top-k selection on instances beyond brute-force size.
 #include "dlref.h"
 
 #include <algorithm>
