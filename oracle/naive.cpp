@@ -9,9 +9,8 @@
 // binary32 (they decide which proofs are kept).
 //
 // Pinned by tests/test_oracle_*.py against closed forms, textbook
-// algorithms and brute force.  Parity unpinned in two regimes: add-mult sums
-// that reach the clamp at 1 on general graphs (pinned on grids, which clamp,
-// and trees), and top-k selection on instances beyond brute-force size.
+// algorithms and brute force.  Parity unpinned in one regime: top-k
+// selection on instances beyond brute-force size.
 #include "dlref.h"
 
 #include <algorithm>

@@ -194,6 +194,41 @@ def test_addmult_general_graph_matrix_power(oracle, synth, seed):
     np.testing.assert_allclose(res["value"], vals, rtol=1e-12)
 
 
+@pytest.mark.parametrize("seed", [4, 5])
+def test_addmult_general_graph_clamped_layers(oracle, synth, seed):
+    """Frozen add-mult with the clamp at work, per target t by hop layers
+    (scipy's distances): f(x, t) = p(x, t) at distance 1, else
+    min(1, sum over successors y one layer closer of p(x, y) f(y, t)),
+    evaluated target by target in increasing distance -- another order than
+    the oracle's rounds over all pairs at once."""
+    n = 128
+    src, dst, _ = synth.er_graph(seed, n, 640)
+    p = np.random.default_rng(200 + seed).uniform(0.5, 0.95, src.size).astype(np.float32)
+    w = {(int(a), int(b)): float(q) for a, b, q in zip(src, dst, p)}
+    succ = {}
+    for a, b in w:
+        succ.setdefault(a, []).append(b)
+    d1 = hop_matrix(n, src, dst)
+    want, clamped = {}, 0
+    for t in range(n):
+        f = {}
+        for x in sorted(np.flatnonzero(np.isfinite(d1[:, t])).tolist(), key=lambda x: d1[x, t]):
+            d = d1[x, t]
+            if d == 1:
+                f[x] = w[(x, t)]
+            else:
+                s = sum(w[(x, y)] * f[y] for y in succ[x] if d1[y, t] == d - 1)
+                clamped += s >= 1.0
+                f[x] = min(1.0, s)
+            want[(x, t)] = f[x]
+    assert clamped > 100  # the clamp decides many tags here
+    res = tc(oracle, synth, src, dst, p, "addmult").read("path")
+    got = {(int(a), int(b)): v for (a, b), v in zip(res["cols"], res["value"])}
+    assert sorted(got) == sorted(want)
+    for key, v in want.items():
+        assert got[key] == pytest.approx(v, rel=1e-12), key
+
+
 def test_addmult_out_tree_products(oracle, synth):
     """On an out-tree every pair has one walk: the tag is its edge product."""
     rng = np.random.default_rng(7)
