@@ -9,8 +9,8 @@
 // binary32 (they decide which proofs are kept).
 //
 // Pinned by tests/test_oracle_*.py against closed forms, textbook
-// algorithms and brute force.  Parity unpinned in one regime: top-k
-// selection on instances beyond brute-force size.
+// algorithms and brute force.  Parity unpinned in one regime: top-k on
+// cyclic graphs beyond brute-force size (on DAGs, against path enumeration).
 #include "dlref.h"
 
 #include <algorithm>

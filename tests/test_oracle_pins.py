@@ -323,6 +323,62 @@ def count_paths(n, src, dst):
     return total
 
 
+def dag_paths(n, src, dst):
+    """Every path of a DAG as its edge (fact) numbers, by pair."""
+    out = {}
+    succ = {}
+    for e, (a, b) in enumerate(zip(src.tolist(), dst.tolist())):
+        succ.setdefault(a, []).append((b, e))
+
+    def walk(x, node, facts):
+        for b, e in succ.get(node, []):
+            f = facts + [e]
+            out.setdefault((x, b), []).append(sorted(f))
+            walk(x, b, f)
+
+    for x in range(n):
+        walk(x, x, [])
+    return out
+
+
+@pytest.mark.parametrize("seed", [31, 32, 33])
+def test_topk_selection_vs_path_enumeration(oracle, synth, seed):
+    """Top-3 proofs on DAGs with up to a few hundred paths per pair: each
+    path is a proof (its edges), of binary32 probability the product of its
+    facts in ascending order; the kept proofs are paths with exactly those
+    probabilities, as many as min(3, paths), and no path is more probable
+    than the third kept one beyond binary32 rounding."""
+    rng = np.random.default_rng(seed)
+    n, m = 18, 64
+    src, dst = random_dag(rng, n, m)
+    p = rng.uniform(0.3, 0.95, m).astype(np.float32)
+    paths = dag_paths(n, src, dst)
+    assert max(len(v) for v in paths.values()) > 30
+
+    def prob32(facts):
+        acc = np.float32(1.0)
+        for f in facts:
+            acc = np.float32(acc * p[f])
+        return acc
+
+    res = tc(oracle, synth, src, dst, p, "topk", k=3).read("path")
+    assert sorted(map(tuple, res["cols"].tolist())) == sorted(paths)
+    for (x, z), cnt, bits, pp in zip(res["cols"].tolist(), res["cnt"], res["bits"], res["p"]):
+        cands = paths[(x, z)]
+        assert cnt == min(3, len(cands))
+        sets = {sum(1 << f for f in c): prob32(c) for c in cands}
+        kept = []
+        for j in range(cnt):
+            b = int(bits[j])
+            assert b in sets, (x, z)  # a kept proof is a path
+            assert pp[j] == sets[b]
+            kept.append(b)
+        assert len(set(kept)) == cnt
+        best = sorted(sets.values(), reverse=True)
+        np.testing.assert_allclose(sorted(pp[:cnt], reverse=True), best[:cnt], rtol=1e-6)
+        assert best[cnt] <= pp[cnt - 1] * (1 + 1e-6) if len(best) > cnt else True
+
+
 @pytest.mark.parametrize("seed", [11, 12, 13, 14])
 def test_topk_vs_possible_worlds(oracle, synth, seed):
     rng = np.random.default_rng(seed)
