@@ -10,6 +10,7 @@
 
 #include "../../include/dlfix.h"
 #include "kernels.h"
+#include "prof.h"
 #include "program.h"
 
 namespace dlfix {
@@ -190,6 +191,22 @@ struct Engine {
   dl_stats stats{};
   uint64_t deferred_units = 0;  // derivations of joins whose totals stayed on the device (last run)
   uint64_t fused_units = 0;     // derivations of fused rounds (this run, added up on the host)
+  // The fused rounds' graphs, one per group batch width, kept from run to
+  // run while their launches' arguments stay the same (key: those bytes);
+  // recs are the launches' profiling records when captured while profiling.
+  struct FusedGraph {
+    std::vector<unsigned char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<Profiler::Rec> recs;
+    bool profiled = false;
+  };
+  FusedGraph fused_graph[4];
+  void drop_fused_graph(FusedGraph& g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = FusedGraph{};
+  }
   std::vector<uint64_t> round_log;  // rounds of the last run: (new or changed, derivations, info) triples
   void log_round(uint64_t u, uint64_t c, int stratum, int kind) {
     round_log.push_back(u);

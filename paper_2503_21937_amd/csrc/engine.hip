@@ -40,6 +40,7 @@ struct ProfScope {
 }  // namespace
 
 Engine::~Engine() {
+  for (FusedGraph& g : fused_graph) drop_fused_graph(g);
   // arena ranges belong to the caller's workspace (or the static array)
   if (!use_arena) for_each_buf([](DevBuf& b) {
       if (b.p) (void)hipFree(b.p);

@@ -1072,27 +1072,48 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
   // The graph holds the rounds' launches only, so that two events around a
   // replay time exactly them when profiling (events recorded inside a graph
   // carry no time): the launches' records (family, bytes) are kept from the
-  // capture and counted once per replay.
-  hipGraph_t graph[NW] = {};
-  hipGraphExec_t exec[NW] = {};
+  // capture and counted once per replay.  A graph is captured once per width
+  // and kept in the engine for later runs while every argument of its
+  // launches is the same.
+  static_assert(NW <= (int)(sizeof(e.fused_graph) / sizeof(e.fused_graph[0])), "a cached graph per width");
   bool tried[NW] = {};
-  std::vector<Profiler::Rec> graph_recs[NW];
   hipEvent_t span[2] = {nullptr, nullptr};
   if (g_prof) {
     span[0] = g_prof->get();
     span[1] = g_prof->get();
   }
+  auto graph_key = [&](int m) {
+    std::vector<unsigned char> k;
+    auto put = [&](const void* p, size_t n) {
+      const unsigned char* c = static_cast<const unsigned char*>(p);
+      k.insert(k.end(), c, c + n);
+    };
+    RoundArgs rk = ra;  // what enqueue_rounds sets per round: from w, wr_part and the width
+    rk.cur = rk.next = WindowRecent{};
+    rk.part = nullptr;
+    rk.batch = widths[m];
+    const void* part = e.wr_part.p;
+    const int tk = e.tag_kind;
+    put(&a, sizeof a);
+    put(&d, sizeof d);
+    put(&rk, sizeof rk);
+    put(w, sizeof w);
+    put(&part, sizeof part);
+    put(&nbw[m], sizeof nbw[m]);
+    put(&tk, sizeof tk);
+    put(&e.stream, sizeof e.stream);
+    return k;
+  };
   auto release = [&] {
-    for (int m = 0; m < NW; ++m) {
-      if (exec[m]) (void)hipGraphExecDestroy(exec[m]);
-      if (graph[m]) (void)hipGraphDestroy(graph[m]);
-      exec[m] = nullptr;
-      graph[m] = nullptr;
-    }
+    for (int m = 0; m < NW; ++m) e.drop_fused_graph(e.fused_graph[m]);
   };
   auto capture = [&](int m) {  // the batch body of width m as a graph, once
     tried[m] = true;
     if (!e.cfg.graph) return;
+    Engine::FusedGraph& G = e.fused_graph[m];
+    std::vector<unsigned char> key = graph_key(m);
+    if (G.exec && G.key == key && (!g_prof || G.profiled)) return;  // the last run's graph fits
+    e.drop_fused_graph(G);
     if (hipStreamBeginCapture(e.stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
       (void)hipGetLastError();
       return;
@@ -1104,19 +1125,19 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     } catch (...) {
       ok = false;
     }
-    if (hipStreamEndCapture(e.stream, &graph[m]) != hipSuccess || !graph[m]) ok = false;
-    if (ok && hipGraphInstantiate(&exec[m], graph[m], nullptr, nullptr, 0) != hipSuccess) ok = false;
+    if (hipStreamEndCapture(e.stream, &G.graph) != hipSuccess || !G.graph) ok = false;
+    if (ok && hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
     if (g_prof) {  // the launches' records, without their (captured) events' times
-      if (ok) graph_recs[m].assign(g_prof->recs.begin() + (std::ptrdiff_t)m0, g_prof->recs.end());
+      if (ok) G.recs.assign(g_prof->recs.begin() + (std::ptrdiff_t)m0, g_prof->recs.end());
       g_prof->recs.resize(m0);
     }
     if (!ok) {
-      if (exec[m]) (void)hipGraphExecDestroy(exec[m]);
-      if (graph[m]) (void)hipGraphDestroy(graph[m]);
-      exec[m] = nullptr;
-      graph[m] = nullptr;
+      e.drop_fused_graph(G);
       (void)hipGetLastError();
+      return;
     }
+    G.key = std::move(key);
+    G.profiled = g_prof != nullptr;
   };
   // four times the dense threshold of a group (derivations); the forced
   // settings take one width throughout
@@ -1134,9 +1155,10 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
       m = r < 1.0 ? 0 : r < 2.0 ? 1 : r < 4.0 ? 2 : 3;
     }
     if (!tried[m]) capture(m);
-    const bool timed = exec[m] && span[0] && span[1];
+    hipGraphExec_t exec = e.cfg.graph ? e.fused_graph[m].exec : nullptr;
+    const bool timed = exec && span[0] && span[1];
     if (timed) DL_HIP(hipEventRecord(span[0], e.stream));
-    if (exec[m]) DL_HIP(hipGraphLaunch(exec[m], e.stream));
+    if (exec) DL_HIP(hipGraphLaunch(exec, e.stream));
     else enqueue_rounds(m);
     if (timed) DL_HIP(hipEventRecord(span[1], e.stream));
     enqueue_readback(m);
@@ -1144,7 +1166,7 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     if (timed) {
       float ms = 0.0f;
       DL_HIP(hipEventElapsedTime(&ms, span[0], span[1]));
-      Profiler::fold_span(graph_recs[m], ms, e.kstats);
+      Profiler::fold_span(e.fused_graph[m].recs, ms, e.kstats);
     }
     if (e.host[S_OVF]) {
       release();
@@ -1164,9 +1186,8 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     }
   }
   R.recent.n = 0;
-  release();
   ix.built = false;
-  return rounds;
+  return rounds;  // the graphs stay for the next run
 }
 
 // Rounds 2.. of an eligible stratum in batches of device-sized round bodies;

@@ -107,3 +107,24 @@ def test_round_log(synth, sr):
     # candidate per edge
     assert st["candidates"] == off.stats()["candidates"]
     assert int(der.sum()) + src.size == st["candidates"]
+
+
+@pytest.mark.parametrize("sr", ["maxmin", "addmult"])
+def test_graphs_kept_across_runs(oracle, synth, sr):
+    """The fused rounds' graphs stay in the engine from run to run while
+    their launches' arguments are the same: new facts of the same shape
+    reuse them (the graphs read the buffers' new contents), facts of another
+    shape make new ones; every run agrees with the oracle."""
+    from paper_2503_21937_amd import dlfix
+    e = dlfix.Engine(synth.TC_PROGRAM, sr, dedup="dense")
+    ref = {}
+    for seed, n, m in [(11, 200, 800), (11, 200, 800), (12, 200, 800), (13, 260, 1000), (12, 200, 800)]:
+        src, dst, p = synth.er_graph(seed, n, m, weights=True)
+        e.clear_facts()
+        e.add_facts("edge", [src, dst], p)
+        e.run()
+        if seed not in ref:
+            ref[seed] = oracle_run(oracle, synth.TC_PROGRAM, sr, {"edge": ([src, dst], p, None)})
+        o = ref[seed]
+        check(e, o, "path", sr)
+        assert e.stats()["max_rounds"] == o.rounds()
