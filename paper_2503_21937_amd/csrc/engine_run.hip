@@ -1007,9 +1007,10 @@ bool fused_eligible(Engine& e, int r, const std::vector<const Plan*>& plans, Row
 // the last round seen, as the ratio r of the average group's derivations
 // (the last round's new or changed tuples times the drivers per group, over
 // the groups) to the dense threshold: 8 groups per workgroup (a wave per
-// group) below r = 1, then 4, 2 and, from r = 4, one group per workgroup --
-// fewer groups queue behind one workgroup's dense ones as more of them are
-// dense.  Returns the number of rounds run.
+// group) below r = 2, then 4 (below 4), 2 (below 16) and one group per
+// workgroup -- fewer groups queue behind one workgroup's dense ones as more
+// of them are dense (thresholds measured on ER graphs).  Returns the number
+// of rounds run.
 template <typename K>
 int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows& rw) {
   const int r = st.rels[0];
@@ -1139,8 +1140,8 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     G.key = std::move(key);
     G.profiled = g_prof != nullptr;
   };
-  // four times the dense threshold of a group (derivations); the forced
-  // settings take one width throughout
+  // the dense threshold of a group (derivations); the forced settings take
+  // one width throughout
   const double per_group = (double)a.n / std::max<uint32_t>(ng, 1u);
   const double dense = ra.win_per_key == ~0u ? -1.0 : (double)rw.wkeys / std::max(ra.win_per_key, 1u);
   uint64_t last = R.recent.n;
@@ -1152,7 +1153,7 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
       m = NW - 1;
     } else if (dense >= 0) {
       const double r = (double)last * per_group / ng / dense;
-      m = r < 1.0 ? 0 : r < 2.0 ? 1 : r < 4.0 ? 2 : 3;
+      m = r < 2.0 ? 0 : r < 4.0 ? 1 : r < 16.0 ? 2 : 3;
     }
     if (!tried[m]) capture(m);
     hipGraphExec_t exec = e.cfg.graph ? e.fused_graph[m].exec : nullptr;
