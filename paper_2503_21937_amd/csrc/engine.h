@@ -200,6 +200,8 @@ struct Engine {
     hipGraphExec_t exec = nullptr;
     std::vector<Profiler::Rec> recs;
     bool profiled = false;
+    int defer_fam = -1;  // the launches' bytes per device-counted unit (Profiler::defer)
+    double defer_per = 0.0;
   };
   FusedGraph fused_graph[4];
   void drop_fused_graph(FusedGraph& g) {

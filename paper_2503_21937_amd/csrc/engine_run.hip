@@ -1113,7 +1113,10 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     if (!e.cfg.graph) return;
     Engine::FusedGraph& G = e.fused_graph[m];
     std::vector<unsigned char> key = graph_key(m);
-    if (G.exec && G.key == key && (!g_prof || G.profiled)) return;  // the last run's graph fits
+    if (G.exec && G.key == key && (!g_prof || G.profiled)) {  // the last run's graph fits
+      if (g_prof && G.defer_fam >= 0) g_prof->defer(G.defer_fam, G.defer_per);  // as its launchers did
+      return;
+    }
     e.drop_fused_graph(G);
     if (hipStreamBeginCapture(e.stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
       (void)hipGetLastError();
@@ -1139,6 +1142,10 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     }
     G.key = std::move(key);
     G.profiled = g_prof != nullptr;
+    if (g_prof) {
+      G.defer_fam = g_prof->deferred_fam;
+      G.defer_per = g_prof->deferred_per;
+    }
   };
   // the dense threshold of a group (derivations); the forced settings take
   // one width throughout

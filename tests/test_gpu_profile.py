@@ -1,7 +1,8 @@
 """Kernel timing (dl_profile): a timed run gives the same relation as an
 untimed one, and engines built with and without round graphs (timed rounds
 are launched directly) report the same launches and algorithmic bytes per
-family (with rounds fused into one launch and without)."""
+family (with rounds fused into one launch and without), and so does a second
+timed run of the same engine."""
 import numpy as np
 import pytest
 
@@ -24,6 +25,13 @@ def test_profiled_graphs_match_direct_launches(synth, sr, fused):
         assert np.array_equal(plain["cols"], timed["cols"])
         assert np.array_equal(plain["tags"], timed["tags"]) or sr == "addmult"
         runs[graphs] = (timed, ks)
+        # a second timed run (round graphs kept from the first) counts the same
+        e.profile(["join_expand", "join_count"])
+        e.run()
+        ks2 = e.kernel_stats()
+        for fam in ("join_expand", "join_count"):
+            assert ks2[fam]["launches"] == ks[fam]["launches"], fam
+            assert ks2[fam]["bytes"] == pytest.approx(ks[fam]["bytes"], rel=1e-9), fam
     (g, kg), (d, kd) = runs[True], runs[False]
     assert np.array_equal(g["cols"], d["cols"])
     # fused rounds count the matches inside the join launch
