@@ -191,7 +191,7 @@ struct Engine {
   dl_stats stats{};
   uint64_t deferred_units = 0;  // derivations of joins whose totals stayed on the device (last run)
   uint64_t fused_units = 0;     // derivations of fused rounds (this run, added up on the host)
-  // The fused rounds' graphs, one per group batch width, kept from run to
+  // The fused rounds' graphs, one per group batch width and batch length, kept from run to
   // run while their launches' arguments stay the same (key: those bytes);
   // recs are the launches' profiling records when captured while profiling.
   struct FusedGraph {
@@ -203,7 +203,7 @@ struct Engine {
     int defer_fam = -1;  // the launches' bytes per device-counted unit (Profiler::defer)
     double defer_per = 0.0;
   };
-  FusedGraph fused_graph[4];
+  FusedGraph fused_graph[8];
   void drop_fused_graph(FusedGraph& g) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (g.graph) (void)hipGraphDestroy(g.graph);

@@ -1001,7 +1001,8 @@ bool fused_eligible(Engine& e, int r, const std::vector<const Plan*>& plans, Row
 }
 
 // Rounds 2.. as fused launches over a window-layout recent relation (see
-// k_window_round); four rounds per host synchronisation, as one captured
+// k_window_round); four rounds per host synchronisation (eight while the
+// rounds shrink by less than 30 % a round), as one captured
 // HIP graph where allowed (timed, when profiling, by events around each
 // replay).  Each batch of rounds takes a group batch width from the size of
 // the last round seen, as the ratio r of the average group's derivations
@@ -1034,7 +1035,9 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
   const uint32_t widths[NW] = {WINDOW_ROUND_WIDE, WINDOW_ROUND_WIDE / 2, WINDOW_ROUND_WIDE / 4, 1};
   unsigned nbw[NW], nbmax = 0;
   for (int m = 0; m < NW; ++m) nbmax = std::max(nbmax, nbw[m] = window_round_grid(ng, widths[m]));
-  e.grow(e.wr_part, (size_t)BATCH_ROUNDS * nbmax * 2 * 4);
+  // a batch is BATCH_ROUNDS rounds, or twice that while the rounds shrink slowly
+  constexpr int LONG_ROUNDS = 2 * BATCH_ROUNDS;
+  e.grow(e.wr_part, (size_t)LONG_ROUNDS * nbmax * 2 * 4);
   // round 1's recent tuples (sorted) into window layout, through their CSR
   // over (sample, first column)
   const int ir = tw.steps[0].index;
@@ -1056,18 +1059,18 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
   // Every round writes its workgroups' counts to its own part of wr_part;
   // after a batch one small launch adds them up per round into the total
   // slots, which the host reads back with the others.
-  static_assert(S_PART + 2 * BATCH_ROUNDS <= 30, "batch totals overlap other slots");
-  auto enqueue_rounds = [&](int m) {
+  static_assert(S_PART + 2 * LONG_ROUNDS <= 30, "batch totals overlap other slots");
+  auto enqueue_rounds = [&](int m, int len) {
     ra.batch = widths[m];
-    for (int i = 0; i < BATCH_ROUNDS; ++i) {
+    for (int i = 0; i < len; ++i) {
       ra.cur = w[i & 1];
       ra.next = w[(i + 1) & 1];
       ra.part = e.wr_part.as<uint32_t>() + (size_t)i * nbw[m] * 2;
       window_round<K>(a, e.tag_kind, d, ra, e.stream);
     }
   };
-  auto enqueue_readback = [&](int m) {
-    sum_parts(e.wr_part.as<uint32_t>(), nbw[m], BATCH_ROUNDS, total_slot(e, S_PART), e.stream);
+  auto enqueue_readback = [&](int m, int len) {
+    sum_parts(e.wr_part.as<uint32_t>(), nbw[m], (unsigned)len, total_slot(e, S_PART), e.stream);
     DL_HIP(hipMemcpyAsync(e.host, e.dtotal.p, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, e.stream));
   };
   // The graph holds the rounds' launches only, so that two events around a
@@ -1076,14 +1079,16 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
   // capture and counted once per replay.  A graph is captured once per width
   // and kept in the engine for later runs while every argument of its
   // launches is the same.
-  static_assert(NW <= (int)(sizeof(e.fused_graph) / sizeof(e.fused_graph[0])), "a cached graph per width");
-  bool tried[NW] = {};
+  // graph gi = width m, plus NW for a long batch
+  static_assert(2 * NW <= (int)(sizeof(e.fused_graph) / sizeof(e.fused_graph[0])), "a cached graph per shape");
+  bool tried[2 * NW] = {};
   hipEvent_t span[2] = {nullptr, nullptr};
   if (g_prof) {
     span[0] = g_prof->get();
     span[1] = g_prof->get();
   }
-  auto graph_key = [&](int m) {
+  auto graph_key = [&](int gi) {
+    const int m = gi % NW, len = gi < NW ? BATCH_ROUNDS : LONG_ROUNDS;
     std::vector<unsigned char> k;
     auto put = [&](const void* p, size_t n) {
       const unsigned char* c = static_cast<const unsigned char*>(p);
@@ -1101,18 +1106,19 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     put(w, sizeof w);
     put(&part, sizeof part);
     put(&nbw[m], sizeof nbw[m]);
+    put(&len, sizeof len);
     put(&tk, sizeof tk);
     put(&e.stream, sizeof e.stream);
     return k;
   };
   auto release = [&] {
-    for (int m = 0; m < NW; ++m) e.drop_fused_graph(e.fused_graph[m]);
+    for (int gi = 0; gi < 2 * NW; ++gi) e.drop_fused_graph(e.fused_graph[gi]);
   };
-  auto capture = [&](int m) {  // the batch body of width m as a graph, once
-    tried[m] = true;
+  auto capture = [&](int gi) {  // the batch body of shape gi as a graph, once
+    tried[gi] = true;
     if (!e.cfg.graph) return;
-    Engine::FusedGraph& G = e.fused_graph[m];
-    std::vector<unsigned char> key = graph_key(m);
+    Engine::FusedGraph& G = e.fused_graph[gi];
+    std::vector<unsigned char> key = graph_key(gi);
     if (G.exec && G.key == key && (!g_prof || G.profiled)) {  // the last run's graph fits
       if (g_prof && G.defer_fam >= 0) g_prof->defer(G.defer_fam, G.defer_per);  // as its launchers did
       return;
@@ -1125,7 +1131,7 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     const size_t m0 = g_prof ? g_prof->recs.size() : 0;
     bool ok = true;
     try {
-      enqueue_rounds(m);
+      enqueue_rounds(gi % NW, gi < NW ? BATCH_ROUNDS : LONG_ROUNDS);
     } catch (...) {
       ok = false;
     }
@@ -1151,7 +1157,7 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
   // one width throughout
   const double per_group = (double)a.n / std::max<uint32_t>(ng, 1u);
   const double dense = ra.win_per_key == ~0u ? -1.0 : (double)rw.wkeys / std::max(ra.win_per_key, 1u);
-  uint64_t last = R.recent.n;
+  uint64_t last = R.recent.n, before = 0;  // the last two rounds' new or changed tuples
   int rounds = 0;
   bool done = false;
   while (!done) {
@@ -1162,25 +1168,29 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
       const double r = (double)last * per_group / ng / dense;
       m = r < 2.0 ? 0 : r < 4.0 ? 1 : r < 16.0 ? 2 : 3;
     }
-    if (!tried[m]) capture(m);
-    hipGraphExec_t exec = e.cfg.graph ? e.fused_graph[m].exec : nullptr;
+    // a long batch while the rounds shrink by less than 30 % a round (a long
+    // tail: fewer host synchronisations, and few rounds run past the end)
+    const bool lng = last < before && (double)last >= 0.7 * (double)before;
+    const int len = lng ? LONG_ROUNDS : BATCH_ROUNDS, gi = m + (lng ? NW : 0);
+    if (!tried[gi]) capture(gi);
+    hipGraphExec_t exec = e.cfg.graph ? e.fused_graph[gi].exec : nullptr;
     const bool timed = exec && span[0] && span[1];
     if (timed) DL_HIP(hipEventRecord(span[0], e.stream));
     if (exec) DL_HIP(hipGraphLaunch(exec, e.stream));
-    else enqueue_rounds(m);
+    else enqueue_rounds(m, len);
     if (timed) DL_HIP(hipEventRecord(span[1], e.stream));
-    enqueue_readback(m);
+    enqueue_readback(m, len);
     e.sync();
     if (timed) {
       float ms = 0.0f;
       DL_HIP(hipEventElapsedTime(&ms, span[0], span[1]));
-      Profiler::fold_span(e.fused_graph[m].recs, ms, e.kstats);
+      Profiler::fold_span(e.fused_graph[gi].recs, ms, e.kstats);
     }
     if (e.host[S_OVF]) {
       release();
       check_overflow(e);
     }
-    for (int i = 0; i < BATCH_ROUNDS; ++i) {
+    for (int i = 0; i < len; ++i) {
       const uint64_t U = e.host[S_PART + 2 * i], C = e.host[S_PART + 2 * i + 1];
       e.log_round(U, C, e.cur_stratum, DL_ROUND_FUSED);
       if (done) continue;  // launched after the last round: found nothing
@@ -1190,6 +1200,7 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
       e.stats.unique += U;
       e.fused_units += C;
       done = U == 0;
+      before = last;
       last = U;
     }
   }
