@@ -1035,8 +1035,11 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
   const uint32_t widths[NW] = {WINDOW_ROUND_WIDE, WINDOW_ROUND_WIDE / 2, WINDOW_ROUND_WIDE / 4, 1};
   unsigned nbw[NW], nbmax = 0;
   for (int m = 0; m < NW; ++m) nbmax = std::max(nbmax, nbw[m] = window_round_grid(ng, widths[m]));
-  // a batch is BATCH_ROUNDS rounds, or twice that while the rounds shrink slowly
+  // a batch is BATCH_ROUNDS rounds, or twice that while the rounds shrink
+  // slowly; both even, so that a batch ends with the recent tuples back in
+  // window set 0
   constexpr int LONG_ROUNDS = 2 * BATCH_ROUNDS;
+  static_assert(BATCH_ROUNDS % 2 == 0, "a batch ends in window set 0");
   e.grow(e.wr_part, (size_t)LONG_ROUNDS * nbmax * 2 * 4);
   // round 1's recent tuples (sorted) into window layout, through their CSR
   // over (sample, first column)
@@ -1076,10 +1079,9 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
   // The graph holds the rounds' launches only, so that two events around a
   // replay time exactly them when profiling (events recorded inside a graph
   // carry no time): the launches' records (family, bytes) are kept from the
-  // capture and counted once per replay.  A graph is captured once per width
-  // and kept in the engine for later runs while every argument of its
-  // launches is the same.
-  // graph gi = width m, plus NW for a long batch
+  // capture and counted once per replay.  A graph is captured once per batch
+  // shape (gi = width m, plus NW for a long batch) and kept in the engine for
+  // later runs while every argument of its launches is the same.
   static_assert(2 * NW <= (int)(sizeof(e.fused_graph) / sizeof(e.fused_graph[0])), "a cached graph per shape");
   bool tried[2 * NW] = {};
   hipEvent_t span[2] = {nullptr, nullptr};
