@@ -200,6 +200,7 @@ struct Engine {
     hipGraphExec_t exec = nullptr;
     std::vector<Profiler::Rec> recs;
     bool profiled = false;
+    uint32_t prof_mask = 0;  // the families timed when it was captured
     int defer_fam = -1;  // the launches' bytes per device-counted unit (Profiler::defer)
     double defer_per = 0.0;
   };

@@ -1121,7 +1121,10 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     if (!e.cfg.graph) return;
     Engine::FusedGraph& G = e.fused_graph[gi];
     std::vector<unsigned char> key = graph_key(gi);
-    if (G.exec && G.key == key && (!g_prof || G.profiled)) {  // the last run's graph fits
+    // the last run's graph fits: same arguments and, when timing, captured
+    // while timing the same families
+    const bool fits = G.exec && G.key == key && (!g_prof || (G.profiled && G.prof_mask == g_prof->mask));
+    if (fits) {
       if (g_prof && G.defer_fam >= 0) g_prof->defer(G.defer_fam, G.defer_per);  // as its launchers did
       return;
     }
@@ -1151,6 +1154,7 @@ int fused_rounds(Engine& e, const Stratum& st, const Plan& tw, const RowWindows&
     G.key = std::move(key);
     G.profiled = g_prof != nullptr;
     if (g_prof) {
+      G.prof_mask = g_prof->mask;
       G.defer_fam = g_prof->deferred_fam;
       G.defer_per = g_prof->deferred_per;
     }

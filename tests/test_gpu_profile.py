@@ -32,6 +32,10 @@ def test_profiled_graphs_match_direct_launches(synth, sr, fused):
         for fam in ("join_expand", "join_count"):
             assert ks2[fam]["launches"] == ks[fam]["launches"], fam
             assert ks2[fam]["bytes"] == pytest.approx(ks[fam]["bytes"], rel=1e-9), fam
+        # and a family no longer timed is not counted
+        e.profile(["join_count"])
+        e.run()
+        assert e.kernel_stats()["join_expand"]["launches"] == 0
     (g, kg), (d, kd) = runs[True], runs[False]
     assert np.array_equal(g["cols"], d["cols"])
     # fused rounds count the matches inside the join launch
