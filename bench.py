@@ -504,6 +504,7 @@ def main() -> int:
         ms += ks["ms"]
         nbytes += ks["bytes"]
     achieved = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    traffic = measured_traffic(dominant)
     stats = {sr: e.stats() for sr, e in zip(SEMIRINGS, engines)}
 
     line = {
@@ -537,7 +538,9 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dominant),
+            "traffic": traffic,
+            # the counted HBM bytes per launch over the same average launch time
+            "traffic_gbs": traffic / (ms * 1e-3 / launches) / 1e9 if traffic and launches and ms > 0 else None,
             "launches": int(launches),
             "avg_launch_us": ms * 1e3 / launches if launches else 0.0,
             "avg_launch_bytes": nbytes / launches if launches else 0.0,
