@@ -388,6 +388,7 @@ constexpr int RW_ROWS = 255;   // driver rows of a group staged in LDS (4 workgr
 constexpr int RW_BLOCK = 512;  // 8 waves: the window's LDS is shared by more waves
 constexpr int RW_WAVES = RW_BLOCK / WAVE;
 constexpr int SPARSE_ITEMS = 2;  // fused rounds: derivations per lane in flight in a sparse group
+static_assert(RW_KEYS / 32 <= RW_WAVES * WAVE, "a wave's share of a window's mark words fits its lanes");
 
 // FM >= 0 selects the specialised variant for the most common shape: 32-bit
 // keys, one sample, a binary head whose second column comes from the index
@@ -1842,10 +1843,13 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
       }
       __syncthreads();
       // the window's marked keys: per-wave word counts -> slots, emission
-      // by every wave over its 64 words, tags written back where changed
-      const uint32_t xw = threadIdx.x < NWD ? s_new[threadIdx.x] : 0u;
-      const uint32_t incl = wave_inclusive_scan((uint32_t)__popc(xw));
-      if (lane == WAVE - 1) s_ws[wv] = incl;
+      // by every wave over its share of the words (NWD / RW_WAVES, rounded
+      // up), tags written back where changed
+      const uint32_t per = (NWD + RW_WAVES - 1) / RW_WAVES;  // <= RW_KEYS / 32 / RW_WAVES <= WAVE
+      const uint32_t e0 = min(wv * per, NWD), e1 = min(e0 + per, NWD);
+      const uint32_t xw = e0 + lane < e1 ? s_new[e0 + lane] : 0u;
+      const uint32_t cw = wave_sum((uint32_t)__popc(xw));
+      if (lane == 0) s_ws[wv] = cw;
       __syncthreads();
       uint32_t before = 0, total = 0;
 #pragma unroll
@@ -1854,7 +1858,7 @@ __global__ __launch_bounds__(RW_BLOCK, 6) void k_window_round(JoinArgs a, DenseA
         before += (uint32_t)i < wv ? t : 0u;
         total += t;
       }
-      if (wv * WAVE < NWD) (void)emit(g, kb, s_new, wv * WAVE, min(wv * WAVE + WAVE, NWD), before, true);
+      if (e0 < e1) (void)emit(g, kb, s_new, e0, e1, before, true);
       if constexpr (TK == TAG_F32) {
         // write the window back four keys at a time where any changed (an
         // unchanged key gets the value it had: nothing else writes it);
