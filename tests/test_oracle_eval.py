@@ -5,7 +5,9 @@ forms computed here from the mathematics, not from the oracle:
 * Same Generation with its x != y selection on random out-trees: two distinct
   nodes at the same depth >= 1 are of the same generation, by exactly one
   derivation, whose tag is the product of the edges on the two paths up to
-  their lowest common ancestor (one edge pair per level).
+  their lowest common ancestor (one edge pair per level); on general graphs,
+  the union over k of (E^T)^k S0 E^k in the boolean and (max, min) matrix
+  algebras, with its first round.
 * Walks of an exact length with an arithmetic hop counter and a bound: the
   tag of walk(x, z, d) is entry (x, z) of the d-th semiring matrix power of
   the edge matrix (add-mult: clamped at 1 after every product, because every
@@ -101,6 +103,45 @@ def test_same_generation_on_trees(oracle, sr, seed):
     if sr != "bool":
         for k, v in want.items():
             assert got[k] == pytest.approx(v, rel=1e-12), k
+
+
+def mm_product(X, Y):
+    """(max, min) matrix product."""
+    return np.max(np.minimum(X[:, :, None], Y[None, :, :]), axis=1)
+
+
+@pytest.mark.parametrize("sr", ["bool", "maxmin"])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_same_generation_matrix_form(oracle, synth, sr, seed):
+    """Same Generation on general (cyclic) graphs in matrix form: with E the
+    edge matrix and S0 the pairs of distinct children of one parent, the
+    relation is the union over k >= 0 of (E^T)^k S0 E^k, products in the
+    semiring (boolean, or (max, min) with the value the best over k), and a
+    pair is first derived in round k + 1 for the smallest such k."""
+    n, m = 60, 150
+    src, dst, p = synth.er_graph(seed, n, m, weights=True)
+    E = np.zeros((n, n))
+    E[src, dst] = p.astype(np.float64) if sr == "maxmin" else 1.0
+    S0 = np.max(np.minimum(E[:, :, None], E[:, None, :]), axis=0)  # over the parent
+    np.fill_diagonal(S0, 0.0)
+    best, first = S0.copy(), np.where(S0 > 0, 1, 0)
+    X, k = S0, 0
+    while True:
+        k += 1
+        X = mm_product(mm_product(E.T, X), E)
+        first = np.where((first == 0) & (X > 0), k + 1, first)
+        if np.all(X <= best):  # then so is every later term: the products are monotone
+            break
+        best = np.maximum(best, X)
+    o = run(oracle, SG, sr, {"edge": ([src, dst], p)})
+    r = o.read("sg")
+    want = np.argwhere(best > 0)
+    assert want.shape[0] > 100
+    assert np.array_equal(r["cols"], want.astype(np.uint32))
+    if sr == "maxmin":
+        assert np.array_equal(r["value"], best[want[:, 0], want[:, 1]])
+    else:
+        assert np.array_equal(r["round"], first[want[:, 0], want[:, 1]].astype(np.int32))
 
 
 def semiring_power(P, present, d, sr):
