@@ -93,7 +93,9 @@ typedef struct {
                          3 = hash-set (Sec. 5): each round's candidates go into a hash set that
                              folds their tags, then only the distinct keys are sorted; f32 tags
                              or none, without recorded lineage (otherwise sort-based) */
-  int no_graphs;      /* 1: never replay round bodies as captured HIP graphs (0: replay where eligible) */
+  int no_graphs;      /* 1: never replay round bodies as captured HIP graphs (0: replay where eligible;
+                         the fused rounds' graphs stay in the engine from run to run while their
+                         launches' arguments are unchanged, and go with dl_free) */
   int no_fused;       /* 1: never run a round as one fused launch (0: where the stratum has one
                          static-driven join whose derivations fall into per-group windows) */
   int lineage;        /* DIFF_ADDMULT derivation lineage for dl_backward:
